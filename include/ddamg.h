@@ -1,0 +1,209 @@
+/*
+ * ddamg.h -- C-ABI of the MI355X DD-alpha-AMG solver for the clover-improved
+ * Wilson Dirac system D z = b on a periodic 4D lattice.
+ *
+ * Method: Frommer, Kahl, Krieg, Leder, Rottmann, "Adaptive aggregation based
+ * domain decomposition multigrid for the lattice Wilson Dirac operator"
+ * (arXiv:1303.1377).  The problem statement is eq. (discreteDirac) with D of
+ * eq. (lattice_WD) in the explicit site form of Sec. 2.2; the solver is FGMRES
+ * right-preconditioned by the V-cycle C^(nu) of Sec. 4.2 (eq. iterationmatrix)
+ * whose smoother is red-black SAP (Sec. 2.3) and whose coarse operator is
+ * D_c = P^H D P for the standard aggregation (Sec. 3.2); the hierarchy is built
+ * by the setup of Algorithm 2.  Default parameters are those of Table 1.
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers (HIP, e.g. torch tensors'
+ *     data_ptr()) unless stated otherwise.  Complex numbers are interleaved
+ *     (re, im) doubles (complex128).
+ *   - Lattice dims are {N0, N1, N2, N3}; x0 is time.  Canonical site index
+ *     ((x0*N1 + x1)*N2 + x2)*N3 + x3.  Boundary conditions are periodic.
+ *   - Fine spinor: [site][spin 0..3][colour 0..2] (colour fastest, Sec. 2.1).
+ *   - Gauge field: [site][mu 0..3][row][col], U_mu(x) on the link x -> x+mu.
+ *   - Coarse vectors of level l >= 1: [coarse site][2N] with index h*N + k,
+ *     h = 0 for the aggregate of spins {0,1} (Gamma5^c = +1), h = 1 for spins
+ *     {2,3}; coarse sites in canonical order of the coarse lattice.
+ *   - The caller keeps ownership of every pointer it passes; the context copies
+ *     what it needs.  A context is bound to the HIP stream given at creation and
+ *     is not thread-safe; distinct contexts are independent.
+ *   - Calls are synchronous with respect to the host: they return after the
+ *     work they enqueued on the context's stream has completed.
+ *   - On error the call returns a negative dd_status and dd_last_error() holds
+ *     a message; the context stays usable unless the status is DD_EDEVICE.
+ */
+#ifndef DDAMG_H
+#define DDAMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_MAXLEV 4
+
+typedef struct dd_ctx dd_ctx;
+
+typedef enum {
+    DD_OK = 0,
+    DD_EINVAL = -1,    /* invalid argument (dims, blocks, sizes, NULL pointer)      */
+    DD_ENOMEM = -2,    /* device allocation failed                                  */
+    DD_ENOCONV = -3,   /* iteration limit reached; x holds the last iterate         */
+    DD_EDEVICE = -4,   /* HIP runtime error                                         */
+    DD_ESTATE = -5,    /* call out of order (e.g. solve before setup)               */
+    DD_ENUMERIC = -6   /* NaN/Inf, singular block, rank-deficient aggregate         */
+} dd_status;
+
+/* Solver parameters (defaults: Table 1 of the paper; see dd_default_params). */
+typedef struct {
+    int levels;                  /* number of levels, 2 or 3                               */
+    int n_tv[DD_MAXLEV];         /* test vectors N of the transfer level l -> l+1          */
+    int agg[DD_MAXLEV][4];       /* aggregate lattice-block dims on level l (Def. standard
+                                    aggregation, Sec. 3.2)                                 */
+    int sap[DD_MAXLEV][4];       /* SAP lattice-block dims on level l (Sec. 2.3)           */
+    int mr_steps[DD_MAXLEV];     /* MR steps of the SAP block solver on level l (Sec. 5)   */
+    int nu;                      /* SAP post-smoothing iterations per V-cycle              */
+    int n_inv;                   /* setup iterations of Algorithm 2                        */
+    double coarse_tol;           /* coarsest-level relative residual (5e-2)                */
+    int coarse_restart;          /* restart length of the coarsest GMRES (30)              */
+    int coarse_maxit;            /* iteration cap of one coarsest solve                    */
+    int coarse_fixed;            /* >0: run exactly this many coarsest iterations          */
+    double mid_tol;              /* intermediate-level FGMRES relative residual (3 levels) */
+    int mid_restart;
+    int mid_maxit;
+    int mid_fixed;               /* >0: exactly this many intermediate iterations          */
+    int outer_restart;           /* FGMRES restart length n_kv                             */
+    int outer_maxit;             /* outer iteration cap                                    */
+    int precision;               /* 64: FP64 preconditioner; 32: FP32 preconditioner
+                                    (the outer FGMRES and its D are always FP64)          */
+    int given_vectors;           /* 1: the setup starts from vectors installed with
+                                    dd_set_test_vectors instead of drawing them            */
+    unsigned long long seed;     /* counter-based RNG key for the initial test vectors     */
+} dd_params;
+
+typedef struct {
+    int outer_iters;             /* FGMRES iterations (sum over restarts)                  */
+    int restarts;
+    long coarse_iters[DD_MAXLEV];/* summed iterations of the level-l solver               */
+    double true_relres;          /* ||b - D x|| / ||b|| in FP64 at exit                    */
+    double setup_s, solve_s;     /* wall time of the last dd_setup / dd_solve              */
+    int converged;
+} dd_stats;
+
+/* Fill *p with the Table 1 defaults (2 levels, N = 20, 4^4 aggregates and SAP
+ * blocks, 4 MR steps, nu = 2, n_inv = 6, coarse GMRES(30) to 5e-2,
+ * FGMRES(25), FP64). */
+void dd_default_params(dd_params *p);
+
+/* Create a solver context for D(U, m0, csw) (Sec. 2.2).
+ *   dims     lattice extents, each even and >= 2
+ *   gauge    device, complex128 [vol][4][3][3]; SU(3) links
+ *   clover   device, complex128 [vol][2][6][6] or NULL.  If given: the two
+ *            chiral 6x6 blocks of the clover term T(x) (without (m0+4)),
+ *            spins {0,1} then {2,3}, index spin*3 + colour within a block.
+ *            If NULL the term is computed on the device from the four-leaf
+ *            Q_{mu nu} of eq. (lattice_WD).
+ *   m0, csw  mass and Sheikholeslami-Wohlert coefficient
+ *   hip_stream  hipStream_t the context enqueues on (NULL: default stream)
+ * Errors: DD_EINVAL (dims, NULL gauge), DD_ENOMEM, DD_ENUMERIC (singular
+ * clover block), DD_EDEVICE. */
+dd_status dd_create(dd_ctx **out, const int dims[4], const double *gauge, const double *clover,
+                    double m0, double csw, void *hip_stream);
+
+/* Release every device buffer of the context.  NULL is ignored. */
+void dd_destroy(dd_ctx *ctx);
+
+/* Message of the last failing call on ctx (owned by ctx, valid until the next
+ * call).  With ctx == NULL: the last dd_create failure. */
+const char *dd_last_error(const dd_ctx *ctx);
+
+/* Adaptive setup, Algorithm 2 (DD-alpha-AMG-setup(n_inv, nu)) level by level.
+ *   n_tv, block, levels  override n_tv[0], agg[0] (= sap[0]) and levels of *p
+ *                        when > 0 / non-NULL
+ *   p                    parameters (NULL: defaults)
+ * Requirements: block dims divide the lattice dims; the number of blocks per
+ * dim is even or 1 (two colours, Sec. 2.3); every coarse lattice has even
+ * extents.  Errors: DD_EINVAL, DD_ENOMEM, DD_ENUMERIC (rank-deficient
+ * aggregate or singular coarse self block). */
+dd_status dd_setup(dd_ctx *ctx, int n_tv, const int block[4], int levels, const dd_params *p);
+
+/* Solve D x = b by FGMRES right-preconditioned by the V-cycle, x0 = 0, until
+ * ||b - D x|| <= tol ||b|| (true residual, FP64).
+ *   b, x  device complex128 fine spinors [vol][4][3]; x is output only
+ * Errors: DD_ESTATE before setup, DD_ENOCONV at outer_maxit (x = last iterate),
+ * DD_ENUMERIC on NaN/Inf in b or breakdown. */
+dd_status dd_solve(dd_ctx *ctx, const double *b, double *x, double tol, dd_stats *stats);
+
+/* k right-hand sides solved one after another on the resident setup.
+ *   b, x  device complex128 [k][vol][4][3]
+ *   stats array of k records or NULL */
+dd_status dd_solve_batch(dd_ctx *ctx, int k, const double *b, double *x, double tol, dd_stats *stats);
+
+/* Change m0 on a context that keeps its setup: A(x) -> A(x) + (m0' - m0) I and,
+ * because P^H P = I, D_c -> D_c + (m0' - m0) I on every coarse level
+ * (Sec. 6, mass scaling with one setup). */
+dd_status dd_set_mass(dd_ctx *ctx, double m0);
+
+/* ---------------------------------------------------------------------------
+ * Component access.  The calls below expose single steps of the method on
+ * the context's current hierarchy; they are used by the parity tests and by
+ * the benchmark's kernel measurements.  Arrays use the canonical layouts
+ * above and complex128.
+ * ------------------------------------------------------------------------- */
+
+/* Allocate the hierarchy geometry for parameters *p without running the
+ * setup (the operators of coarse levels are filled by dd_build_level). */
+dd_status dd_configure(dd_ctx *ctx, const dd_params *p);
+
+/* Install n test vectors of the transfer level -> level+1:
+ * v device complex128 [n][vol_level][nd_level], n = n_tv[level]. */
+dd_status dd_set_test_vectors(dd_ctx *ctx, int level, int n, const double *v);
+dd_status dd_get_test_vectors(dd_ctx *ctx, int level, double *v);
+
+/* Build P (local Gram-Schmidt of the test vectors per aggregate, eq.
+ * aggInterpolation) and D_c = P^H D P with its self-block inverses from the
+ * installed test vectors, without setup iterations. */
+dd_status dd_build_level(dd_ctx *ctx, int level);
+
+/* Mark a hierarchy assembled piecewise (dd_build_level) as complete. */
+dd_status dd_mark_setup(dd_ctx *ctx);
+
+/* Read back P of the transfer level -> level+1: [N][vol_level][nd_level]. */
+dd_status dd_get_P(dd_ctx *ctx, int level, double *out);
+
+/* Read back the coarse operator of level (>= 1): M [volc][9][nd][nd] with
+ * slot 0 the self block, slot 1+mu the coupling to x+mu, slot 5+mu the
+ * coupling to x-mu (row-major blocks), and Minv [volc][nd][nd] the inverses
+ * of the self blocks.  Either pointer may be NULL. */
+dd_status dd_get_coarse(dd_ctx *ctx, int level, double *M, double *Minv);
+
+/* Read back the clover blocks A(x) = (m0+4) I + T(x) and their inverses,
+ * [vol][2][6][6] each (full matrices).  Either pointer may be NULL. */
+dd_status dd_get_clover(dd_ctx *ctx, double *A, double *Ainv);
+
+typedef enum {
+    DD_OP_D = 0,            /* out = D in on `level` (level 0 in FP64)                 */
+    DD_OP_D_PREC = 1,       /* level-0 D in the preconditioner precision               */
+    DD_OP_SAP = 2,          /* out = M_SAP^(arg) in on `level` (zero initial guess)    */
+    DD_OP_VCYCLE = 3,       /* out = C^(nu) in on `level` (coarsest = levels-1)        */
+    DD_OP_RESTRICT = 4,     /* out (level+1) = P^H in (level)                          */
+    DD_OP_PROLONG = 5,      /* out (level) = P in (level+1)                            */
+    DD_OP_COARSE_SOLVE = 6, /* out = coarsest-level odd-even GMRES solution for in     */
+    DD_OP_SCHUR = 7,        /* out = S in, S = A_oo - D_oe A_ee^-1 D_eo on `level`;
+                               in and out are full vectors, zero on even sites        */
+    DD_OP_FGMRES = 8        /* intermediate-level FGMRES (3 levels) on `level`          */
+} dd_op;
+
+/* Apply one component.  in/out are device complex128 vectors of the level in
+ * the canonical layout (sizes given by dd_level_info).  `arg` is the number
+ * of SAP iterations for DD_OP_SAP and unused otherwise.  Returns the
+ * iteration count of solver components in *iters when iters != NULL. */
+dd_status dd_apply(dd_ctx *ctx, int op, int level, int arg, const double *in, double *out, long *iters);
+
+/* Lattice dims and unknowns per site of a level (level 0: the fine lattice). */
+dd_status dd_level_info(const dd_ctx *ctx, int level, int dims[4], int *nd);
+
+/* Device bytes currently allocated by the context. */
+long long dd_device_bytes(const dd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDAMG_H */

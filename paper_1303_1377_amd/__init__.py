@@ -1,0 +1,291 @@
+"""MI355X DD-alpha-AMG solver for the clover-improved Wilson Dirac system.
+
+Thin ctypes binding of libddamg.so (C-ABI in include/ddamg.h): argument
+marshalling only; every step of the method runs in the HIP kernels of the
+library.  PyTorch provides device memory (complex128 tensors on the HIP device)
+and the stream.  Importing the package never loads the library; the first use
+of a solver does, and raises if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+__all__ = ["Solver", "Params", "Stats", "default_params", "library", "DDError", "OPS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddamg.so")
+MAXLEV = 4
+
+OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8)
+STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
+          -6: "DD_ENUMERIC"}
+
+
+class DDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int),
+        ("n_tv", C.c_int * MAXLEV),
+        ("agg", (C.c_int * 4) * MAXLEV),
+        ("sap", (C.c_int * 4) * MAXLEV),
+        ("mr_steps", C.c_int * MAXLEV),
+        ("nu", C.c_int),
+        ("n_inv", C.c_int),
+        ("coarse_tol", C.c_double),
+        ("coarse_restart", C.c_int),
+        ("coarse_maxit", C.c_int),
+        ("coarse_fixed", C.c_int),
+        ("mid_tol", C.c_double),
+        ("mid_restart", C.c_int),
+        ("mid_maxit", C.c_int),
+        ("mid_fixed", C.c_int),
+        ("outer_restart", C.c_int),
+        ("outer_maxit", C.c_int),
+        ("precision", C.c_int),
+        ("given_vectors", C.c_int),
+        ("seed", C.c_ulonglong),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("outer_iters", C.c_int),
+        ("restarts", C.c_int),
+        ("coarse_iters", C.c_long * MAXLEV),
+        ("true_relres", C.c_double),
+        ("setup_s", C.c_double),
+        ("solve_s", C.c_double),
+        ("converged", C.c_int),
+    ]
+
+    def as_dict(self):
+        return dict(outer_iters=self.outer_iters, restarts=self.restarts, coarse_iters=list(self.coarse_iters),
+                    true_relres=self.true_relres, setup_s=self.setup_s, solve_s=self.solve_s,
+                    converged=bool(self.converged))
+
+
+_lib = None
+
+
+def library():
+    """Load libddamg.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libddamg.so not built: run paper_1303_1377_amd/build.py (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.c_double
+        L.dd_default_params.argtypes = [C.POINTER(Params)]
+        L.dd_last_error.restype = C.c_char_p
+        L.dd_last_error.argtypes = [vp]
+        L.dd_create.argtypes = [C.POINTER(vp), ip, vp, vp, dp, dp, vp]
+        L.dd_destroy.argtypes = [vp]
+        L.dd_setup.argtypes = [vp, C.c_int, ip, C.c_int, C.POINTER(Params)]
+        L.dd_solve.argtypes = [vp, vp, vp, dp, C.POINTER(Stats)]
+        L.dd_solve_batch.argtypes = [vp, C.c_int, vp, vp, dp, C.POINTER(Stats)]
+        L.dd_set_mass.argtypes = [vp, dp]
+        L.dd_configure.argtypes = [vp, C.POINTER(Params)]
+        L.dd_set_test_vectors.argtypes = [vp, C.c_int, C.c_int, vp]
+        L.dd_get_test_vectors.argtypes = [vp, C.c_int, vp]
+        L.dd_build_level.argtypes = [vp, C.c_int]
+        L.dd_mark_setup.argtypes = [vp]
+        L.dd_get_P.argtypes = [vp, C.c_int, vp]
+        L.dd_get_coarse.argtypes = [vp, C.c_int, vp, vp]
+        L.dd_get_clover.argtypes = [vp, vp, vp]
+        L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
+        L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
+        L.dd_device_bytes.restype = C.c_longlong
+        L.dd_device_bytes.argtypes = [vp]
+        for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
+                     "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
+                     "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_params(**kw) -> Params:
+    """Table 1 defaults, overridden by keyword (lists for per-level fields)."""
+    p = Params()
+    library().dd_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k in ("n_tv", "mr_steps"):
+            for l, x in enumerate(v):
+                getattr(p, k)[l] = int(x)
+        elif k in ("agg", "sap"):
+            for l, blk in enumerate(v):
+                for mu in range(4):
+                    getattr(p, k)[l][mu] = int(blk[mu])
+        elif k in ("coarse_tol", "mid_tol"):
+            setattr(p, k, float(v))
+        elif k == "seed":
+            p.seed = int(v)
+        else:
+            setattr(p, k, int(v))
+    return p
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dev(t):
+    """Device complex128 contiguous tensor for an array-like."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device="cuda", dtype=torch.complex128).contiguous()
+
+
+class Solver:
+    """One gauge field, one hierarchy (see include/ddamg.h for the semantics)."""
+
+    def __init__(self, dims, gauge, m0, csw, clover=None, stream=None):
+        torch = _torch()
+        L = library()
+        self.dims = tuple(int(v) for v in dims)
+        self.vol = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        g = _dev(gauge).reshape(self.vol, 4, 3, 3)
+        cl = None if clover is None else _dev(clover).reshape(self.vol, 2, 6, 6)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = L.dd_create(C.byref(h), (C.c_int * 4)(*self.dims), C.c_void_p(g.data_ptr()),
+                         None if cl is None else C.c_void_p(cl.data_ptr()), float(m0), float(csw),
+                         C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise DDError(rc, L.dd_last_error(None).decode())
+        self.h = h
+        self.m0, self.csw = float(m0), float(csw)
+        self.params = None
+
+    # ---- plumbing ----------------------------------------------------------
+    def _check(self, rc, ok=(0,)):
+        if rc not in ok:
+            raise DDError(rc, library().dd_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            library().dd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        d = (C.c_int * 4)()
+        nd = C.c_int()
+        self._check(library().dd_level_info(self.h, level, d, C.byref(nd)))
+        return tuple(d), nd.value
+
+    def level_size(self, level):
+        d, nd = self.level_info(level)
+        return d[0] * d[1] * d[2] * d[3], nd
+
+    def device_bytes(self):
+        return int(library().dd_device_bytes(self.h))
+
+    # ---- main API ----------------------------------------------------------
+    def setup(self, n_tv=0, block=None, levels=0, params=None, **kw):
+        p = params if params is not None else default_params(**kw)
+        blk = None if block is None else (C.c_int * 4)(*block)
+        self._check(library().dd_setup(self.h, int(n_tv), blk, int(levels), C.byref(p)))
+        self.params = p
+
+    def configure(self, params=None, **kw):
+        p = params if params is not None else default_params(**kw)
+        self._check(library().dd_configure(self.h, C.byref(p)))
+        self.params = p
+
+    def solve(self, b, tol=1e-10, allow_noconv=False):
+        torch = _torch()
+        bb = _dev(b).reshape(self.vol, 4, 3)
+        x = torch.empty_like(bb)
+        st = Stats()
+        rc = library().dd_solve(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), C.byref(st))
+        self._check(rc, ok=(0, -3) if allow_noconv else (0,))
+        return x, st.as_dict()
+
+    def solve_batch(self, b, tol=1e-10):
+        torch = _torch()
+        bb = _dev(b).reshape(-1, self.vol, 4, 3)
+        k = bb.shape[0]
+        x = torch.empty_like(bb)
+        st = (Stats * k)()
+        self._check(library().dd_solve_batch(self.h, k, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()),
+                                             float(tol), st))
+        return x, [s.as_dict() for s in st]
+
+    def set_mass(self, m0):
+        self._check(library().dd_set_mass(self.h, float(m0)))
+        self.m0 = float(m0)
+
+    # ---- components ----------------------------------------------------------
+    def set_test_vectors(self, level, v):
+        vv = _dev(v)
+        n = int(vv.shape[0])
+        self._check(library().dd_set_test_vectors(self.h, level, n, C.c_void_p(vv.data_ptr())))
+
+    def get_test_vectors(self, level):
+        torch = _torch()
+        vol, nd = self.level_size(level)
+        out = torch.empty((self.params.n_tv[level], vol, nd), dtype=torch.complex128, device="cuda")
+        self._check(library().dd_get_test_vectors(self.h, level, C.c_void_p(out.data_ptr())))
+        return out
+
+    def build_level(self, level):
+        self._check(library().dd_build_level(self.h, level))
+
+    def mark_setup(self):
+        self._check(library().dd_mark_setup(self.h))
+
+    def get_P(self, level):
+        torch = _torch()
+        vol, nd = self.level_size(level)
+        out = torch.empty((self.params.n_tv[level], vol, nd), dtype=torch.complex128, device="cuda")
+        self._check(library().dd_get_P(self.h, level, C.c_void_p(out.data_ptr())))
+        return out
+
+    def get_coarse(self, level):
+        torch = _torch()
+        vol, nd = self.level_size(level)
+        M = torch.empty((vol, 9, nd, nd), dtype=torch.complex128, device="cuda")
+        Mi = torch.empty((vol, nd, nd), dtype=torch.complex128, device="cuda")
+        self._check(library().dd_get_coarse(self.h, level, C.c_void_p(M.data_ptr()), C.c_void_p(Mi.data_ptr())))
+        return M, Mi
+
+    def get_clover(self):
+        torch = _torch()
+        A = torch.empty((self.vol, 2, 6, 6), dtype=torch.complex128, device="cuda")
+        Ai = torch.empty_like(A)
+        self._check(library().dd_get_clover(self.h, C.c_void_p(A.data_ptr()), C.c_void_p(Ai.data_ptr())))
+        return A, Ai
+
+    def apply(self, op, level, v, arg=0):
+        """One component on device vectors (op: name in OPS or its code)."""
+        torch = _torch()
+        code = OPS[op] if isinstance(op, str) else int(op)
+        vin = _dev(v)
+        if code == OPS["RESTRICT"]:
+            vol, nd = self.level_size(level + 1)
+            out = torch.empty((vol, nd), dtype=torch.complex128, device="cuda")
+        elif code == OPS["PROLONG"]:
+            vol, nd = self.level_size(level)
+            out = torch.empty((vol, nd), dtype=torch.complex128, device="cuda")
+        else:
+            out = torch.empty_like(vin)
+        its = C.c_long(0)
+        self._check(library().dd_apply(self.h, code, level, int(arg), C.c_void_p(vin.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), C.byref(its)))
+        return out, its.value

@@ -1,0 +1,632 @@
+// dd_coarse.hip -- kernels on coarse levels (nd = 2N unknowns per site).
+//
+//   coarse stencil D_c ............ nearest-neighbour blocks of P^H D P (Sec. 3.2)
+//   odd-even pieces ............... Schur complement A_oo - D_oe A_ee^{-1} D_eo (Sec. 5)
+//   self-block inverses ........... dense Gauss-Jordan in FP64
+//   coarse SAP, P^H, P, Gram-Schmidt, assembly of the next coarser operator
+//                                   (recursive application, Sec. 3 and 5)
+//
+// Vectors are [parity][layout index][nd] (a site's unknowns contiguous);
+// operator blocks are column-major so that the thread owning row r reads
+// consecutive addresses across the wavefront.
+#include "dd_kernels.h"
+
+namespace dd {
+
+static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// out(x) = [post Minv] ( self(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
+// workgroup = one site, thread = one row
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_coarse_apply(CoarseOp<T> op, int par, int self_mode, const cx<T>* __restrict__ in1, int hop_sign,
+                               const cx<T>* in2, int post_inv, cx<T>* out) {
+    extern __shared__ char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const Geom g = op.g;
+    const int nd = op.nd;
+    int p, i;
+    if (par < 0) { p = blockIdx.x >= g.vh; i = blockIdx.x - p * g.vh; }
+    else { p = par; i = blockIdx.x; }
+    const size_t gs = (size_t)p * g.vh + i;
+    const int r = threadIdx.x;
+    const size_t nn = (size_t)nd * nd;
+    cx<T> acc = czero<T>();
+    if (r < nd) {
+        if (self_mode == CS_IDENT) {
+            acc = in1[gs * nd + r];
+        } else if (self_mode == CS_SELF || self_mode == CS_SELFINV) {
+            const cx<T>* A = (self_mode == CS_SELF) ? op.M + gs * 9 * nn : op.Minv + gs * nn;
+            const cx<T>* v = in1 + gs * nd;
+            for (int c = 0; c < nd; c++) acc += A[(size_t)c * nd + r] * v[c];
+        }
+        if (hop_sign != 0) {
+            int x[4];
+            cb_coords(g, p, i, x);
+            cx<T> h = czero<T>();
+            for (int k = 0; k < 8; k++) {
+                int y[4];
+                nb_coords(g, x, k, y);
+                const size_t gy = (size_t)(1 - p) * g.vh + cb_index(g, y);
+                const cx<T>* A = op.M + (gs * 9 + 1 + k) * nn;
+                const cx<T>* v = in2 + gy * nd;
+                for (int c = 0; c < nd; c++) h += A[(size_t)c * nd + r] * v[c];
+            }
+            if (hop_sign > 0) acc += h;
+            else acc -= h;
+        }
+    }
+    if (post_inv) {
+        if (r < nd) buf[r] = acc;
+        __syncthreads();
+        if (r < nd) {
+            const cx<T>* A = op.Minv + gs * nn;
+            cx<T> s = czero<T>();
+            for (int c = 0; c < nd; c++) s += A[(size_t)c * nd + r] * buf[c];
+            acc = s;
+        }
+    }
+    if (r < nd) out[gs * nd + r] = acc;
+}
+
+template <class T>
+void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
+                  bool post_inv, cx<T>* out, hipStream_t s) {
+    int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
+    int nt = ((op.nd + 63) / 64) * 64;
+    k_coarse_apply<T><<<nsite, nt, sizeof(cx<T>) * op.nd, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out);
+}
+
+// ---------------------------------------------------------------------------
+// self-block inverse: Gauss-Jordan with partial pivoting on [A | I] in FP64
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_coarse_selfinv(Geom g, int nd, const cx<T>* __restrict__ M, cx<T>* __restrict__ Minv, int* bad) {
+    extern __shared__ char smem_raw[];
+    cx<double>* a = reinterpret_cast<cx<double>*>(smem_raw);  // row-major [nd][2nd]
+    __shared__ int piv;
+    __shared__ double pmax[1024 / 64];
+    __shared__ int pidx[1024 / 64];
+    const size_t gs = blockIdx.x;
+    const size_t nn = (size_t)nd * nd;
+    const int t = threadIdx.x, nt = blockDim.x, w2 = 2 * nd;
+    for (int e = t; e < nd * w2; e += nt) {
+        int r = e / w2, c = e % w2;
+        a[e] = (c < nd) ? ccast<double>(M[gs * 9 * nn + (size_t)c * nd + r]) : ((c - nd == r) ? cx<double>{1.0, 0.0} : czero<double>());
+    }
+    __syncthreads();
+    int singular = 0;
+    for (int c = 0; c < nd; c++) {
+        // pivot search over rows c..nd-1
+        double best = -1.0;
+        int bi = c;
+        for (int r = c + t; r < nd; r += nt) {
+            double v = norm2(a[r * w2 + c]);
+            if (v > best) { best = v; bi = r; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            double ob = __shfl_xor(best, o, 64);
+            int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if ((t & 63) == 0) { pmax[t >> 6] = best; pidx[t >> 6] = bi; }
+        __syncthreads();
+        if (t == 0) {
+            double b = pmax[0];
+            int bidx = pidx[0];
+            for (int q = 1; q < (nt + 63) / 64; q++)
+                if (pmax[q] > b || (pmax[q] == b && pidx[q] < bidx)) { b = pmax[q]; bidx = pidx[q]; }
+            piv = (b > 0.0) ? bidx : -1;
+        }
+        __syncthreads();
+        int pr = piv;
+        if (pr < 0) { singular = 1; break; }
+        if (pr != c)
+            for (int j = t; j < w2; j += nt) {
+                cx<double> tmp = a[c * w2 + j]; a[c * w2 + j] = a[pr * w2 + j]; a[pr * w2 + j] = tmp;
+            }
+        __syncthreads();
+        cx<double> pv = a[c * w2 + c];
+        double d = norm2(pv);
+        cx<double> ip = {pv.re / d, -pv.im / d};
+        __syncthreads();
+        for (int j = t; j < w2; j += nt) a[c * w2 + j] = a[c * w2 + j] * ip;
+        __syncthreads();
+        for (int e = t; e < nd * w2; e += nt) {
+            int r = e / w2, j = e % w2;
+            if (r == c) continue;
+            cx<double> f = a[r * w2 + c];
+            if (j == c) continue;
+            a[e] -= f * a[c * w2 + j];
+        }
+        __syncthreads();
+        for (int r = t; r < nd; r += nt)
+            if (r != c) a[r * w2 + c] = czero<double>();
+        __syncthreads();
+    }
+    if (singular) {
+        if (t == 0) atomicAdd(bad, 1);
+        return;
+    }
+    for (int e = t; e < (int)nn; e += nt) {
+        int c = e / nd, r = e % nd;  // column-major output
+        Minv[gs * nn + e] = ccast<T>(a[r * w2 + nd + c]);
+    }
+}
+
+template <class T>
+void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s) {
+    size_t lds = sizeof(cx<double>) * nd * 2 * nd;
+    k_coarse_selfinv<T><<<2 * g.vh, 256, lds, s>>>(g, nd, M, Minv, bad);
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion of coarse vectors and blocks
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_coarse_import(Geom g, int nd, int n, const double* __restrict__ canon, cx<T>* __restrict__ out) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (e >= vol * nd) return;
+    long s = e / nd;
+    int c = (int)(e % nd);
+    int x[4];
+    canon_coords(g.d, s, x);
+    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    const cx<double>* src = reinterpret_cast<const cx<double>*>(canon);
+    for (int v = 0; v < n; v++) out[(size_t)v * vol * nd + gs * nd + c] = ccast<T>(src[(size_t)v * vol * nd + s * nd + c]);
+}
+
+template <class T>
+__global__ void k_coarse_export(Geom g, int nd, int n, const cx<T>* __restrict__ in, double* __restrict__ canon) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (e >= vol * nd) return;
+    long s = e / nd;
+    int c = (int)(e % nd);
+    int x[4];
+    canon_coords(g.d, s, x);
+    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    cx<double>* dst = reinterpret_cast<cx<double>*>(canon);
+    for (int v = 0; v < n; v++) dst[(size_t)v * vol * nd + s * nd + c] = ccast<double>(in[(size_t)v * vol * nd + gs * nd + c]);
+}
+
+// blocks: layout [site][nslot][nd][nd] column-major -> canonical [site][nslot][nd][nd] row-major
+template <class T>
+__global__ void k_coarse_export_blocks(Geom g, int nd, int nslot, const cx<T>* __restrict__ in, double* __restrict__ canon) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    long nn = (long)nd * nd;
+    if (e >= vol * nslot * nn) return;
+    long s = e / (nslot * nn);
+    long rem = e % (nslot * nn);
+    int slot = (int)(rem / nn);
+    int q = (int)(rem % nn);
+    int r = q / nd, c = q % nd;
+    int x[4];
+    canon_coords(g.d, s, x);
+    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    cx<double>* dst = reinterpret_cast<cx<double>*>(canon);
+    dst[e] = ccast<double>(in[(gs * nslot + slot) * nn + (size_t)c * nd + r]);
+}
+
+template <class T>
+__global__ void k_coarse_shift(Geom g, int nd, double dm, cx<T>* M) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e >= 2L * g.vh * nd) return;
+    long s = e / nd;
+    int r = (int)(e % nd);
+    M[(s * 9) * nd * nd + (size_t)r * nd + r].re += T(dm);
+}
+
+template <class T>
+void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s) {
+    long tot = 2L * g.vh * nd;
+    k_coarse_import<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, n, canon, out);
+}
+template <class T>
+void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s) {
+    long tot = 2L * g.vh * nd;
+    k_coarse_export<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, n, in, canon);
+}
+template <class T>
+void coarse_export_blocks(const Geom& g, int nd, int nslot, const cx<T>* in, double* canon, hipStream_t s) {
+    long tot = 2L * g.vh * nslot * nd * nd;
+    k_coarse_export_blocks<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, nslot, in, canon);
+}
+template <class T>
+void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s) {
+    long tot = 2L * g.vh * nd;
+    k_coarse_shift<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, dm, M);
+}
+
+// ---------------------------------------------------------------------------
+// coarse SAP half sweep (same algebra as the fine kernel, dense site blocks):
+// workgroup = one block, thread = (local site l, row r) for both parities.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ cx<T> row_apply(const cx<T>* __restrict__ A, int nd, int r, const cx<T>* v) {
+    cx<T> s = czero<T>();
+    for (int c = 0; c < nd; c++) s += A[(size_t)c * nd + r] * v[c];
+    return s;
+}
+
+template <class T>
+__global__ void k_coarse_sap(CoarseOp<T> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+                             cx<T>* __restrict__ z, int mr_steps) {
+    extern __shared__ char smem_raw[];
+    const Geom g = op.g;
+    const int nd = op.nd, bvh = g.bvh;
+    const size_t nn = (size_t)nd * nd;
+    cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // [bvh][nd] odd-site field
+    cx<T>* se = so + bvh * nd;                        // even-site field
+    cx<T>* tm = se + bvh * nd;                        // temporary (even)
+    double* red = reinterpret_cast<double*>(tm + bvh * nd);
+    const int blk = blocks[blockIdx.x];
+    const int base = blk << g.lbvh;
+    const int t = threadIdx.x;
+    const bool act = t < bvh * nd;
+    const int l = act ? t / nd : 0, r = act ? t % nd : 0;
+    const int i = base + l;
+    int xe[4], xo[4], nbe[8], nbo[8];
+    cb_coords(g, 0, i, xe);
+    cb_coords(g, 1, i, xo);
+    for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, xe, k, y);
+        nbe[k] = cb_index(g, y);
+        nb_coords(g, xo, k, y);
+        nbo[k] = cb_index(g, y);
+    }
+    const size_t ge = i, go = (size_t)g.vh + i;
+    auto hop_glob = [&](size_t gs, int p, const int* nbj, const cx<T>* v) {
+        cx<T> h = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            size_t gy = (size_t)(1 - p) * g.vh + nbj[k];
+            h += row_apply(op.M + (gs * 9 + 1 + k) * nn, nd, r, v + gy * nd);
+        }
+        return h;
+    };
+    auto hop_int = [&](size_t gs, const int* nbj, const cx<T>* buf) {
+        cx<T> h = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            if ((nbj[k] >> g.lbvh) != blk) continue;
+            h += row_apply(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (nbj[k] - base) * nd);
+        }
+        return h;
+    };
+    // t0_e = Minv (b_e - H z) - z_e
+    cx<T> t0 = czero<T>(), rho = czero<T>(), eo = czero<T>(), sv = czero<T>();
+    if (act) tm[l * nd + r] = b[ge * nd + r] - hop_glob(ge, 0, nbe, z);
+    __syncthreads();
+    if (act) {
+        t0 = row_apply(op.Minv + ge * nn, nd, r, tm + l * nd) - z[ge * nd + r];
+        se[l * nd + r] = t0;
+        so[l * nd + r] = z[go * nd + r];
+    }
+    __syncthreads();
+    // f_o = b_o - M0 z_o - H z - H_int t0
+    if (act) rho = b[go * nd + r] - row_apply(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_glob(go, 1, nbo, z) - hop_int(go, nbo, se);
+    __syncthreads();
+    if (act) so[l * nd + r] = rho;
+    __syncthreads();
+    const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int it = 0; it < mr_steps; it++) {
+        if (act) tm[l * nd + r] = hop_int(ge, nbe, so);
+        __syncthreads();
+        cx<T> tv = czero<T>();
+        if (act) tv = row_apply(op.Minv + ge * nn, nd, r, tm + l * nd);
+        __syncthreads();
+        if (act) se[l * nd + r] = tv;
+        __syncthreads();
+        double sr = 0, si = 0, ss = 0;
+        if (act) {
+            sv = row_apply(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_int(go, nbo, se);
+            cx<T> d = cmulc(sv, rho);
+            sr = d.re; si = d.im; ss = norm2(sv);
+        }
+        sr = wave_sum(sr); si = wave_sum(si); ss = wave_sum(ss);
+        if (lane == 0) { red[3 * w] = sr; red[3 * w + 1] = si; red[3 * w + 2] = ss; }
+        __syncthreads();
+        sr = si = ss = 0;
+        for (int q = 0; q < nw; q++) { sr += red[3 * q]; si += red[3 * q + 1]; ss += red[3 * q + 2]; }
+        if (ss > 0 && act) {
+            cx<T> alpha = {T(sr / ss), T(si / ss)};
+            eo += alpha * rho;
+            rho -= alpha * sv;
+        }
+        __syncthreads();
+        if (act) so[l * nd + r] = (it + 1 < mr_steps) ? rho : eo;
+        __syncthreads();
+    }
+    if (mr_steps == 0) {
+        if (act) so[l * nd + r] = eo;
+        __syncthreads();
+    }
+    if (act) tm[l * nd + r] = hop_int(ge, nbe, so);
+    __syncthreads();
+    if (act) {
+        cx<T> ee = t0 - row_apply(op.Minv + ge * nn, nd, r, tm + l * nd);
+        z[ge * nd + r] += ee;
+        z[go * nd + r] += eo;
+    }
+}
+
+template <class T>
+void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+                     hipStream_t s) {
+    if (nblocks <= 0) return;
+    int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
+    size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
+    k_coarse_sap<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps);
+}
+
+// ---------------------------------------------------------------------------
+// transfer between two coarse levels.  P columns: [N][vol_f][ndf] (layout
+// order of the finer level); the coarser level has 2N unknowns per site.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void agg_site_c(const AggMap& m, const int xc[4], int s, int x[4]) {
+    int l3 = s % m.a[3]; s /= m.a[3];
+    int l2 = s % m.a[2]; s /= m.a[2];
+    int l1 = s % m.a[1];
+    int l0 = s / m.a[1];
+    x[0] = xc[0] * m.a[0] + l0;
+    x[1] = xc[1] * m.a[1] + l1;
+    x[2] = xc[2] * m.a[2] + l2;
+    x[3] = xc[3] * m.a[3] + l3;
+}
+
+// workgroup: coarser site; thread e < asz*ndf: (site s = e / ndf, row d = e % ndf)
+template <class T>
+__global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+                                  cx<T>* __restrict__ out) {
+    extern __shared__ char smem_raw[];
+    cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
+    const int gc = blockIdx.x;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const long volf = 2L * m.f.vh;
+    const int h0 = ndf / 2;
+    cx<double> acc[2];
+    for (int k = 0; k < N; k++) {
+        acc[0] = acc[1] = czero<double>();
+        for (int e = t; e < m.asz * ndf; e += blockDim.x) {
+            int s = e / ndf, d = e % ndf;
+            int x[4];
+            agg_site_c(m, xc, s, x);
+            size_t gf = (size_t)site_parity(x) * m.f.vh + cb_index(m.f, x);
+            acc[d / h0] += ccast<double>(cmulc(P[((size_t)k * volf + gf) * ndf + d], in[gf * ndf + d]));
+        }
+        for (int h = 0; h < 2; h++) {
+            acc[h].re = wave_sum(acc[h].re);
+            acc[h].im = wave_sum(acc[h].im);
+            if (lane == 0) red[w * 2 * N + h * N + k] = acc[h];
+        }
+    }
+    __syncthreads();
+    for (int q = t; q < 2 * N; q += blockDim.x) {
+        cx<double> s = czero<double>();
+        for (int ww = 0; ww < nw; ww++) s += red[ww * 2 * N + q];
+        out[(size_t)gc * 2 * N + q] = ccast<T>(s);
+    }
+}
+
+template <class T>
+__global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+                                 cx<T>* __restrict__ out) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long volf = 2L * m.f.vh;
+    if (e >= volf * ndf) return;
+    long gf = e / ndf;
+    int d = (int)(e % ndf);
+    int p = gf >= m.f.vh, i = (int)(gf - p * m.f.vh);
+    int x[4], xc[4];
+    cb_coords(m.f, p, i, x);
+    for (int mu = 0; mu < 4; mu++) xc[mu] = x[mu] / m.a[mu];
+    size_t gc = (size_t)site_parity(xc) * m.c.vh + cb_index(m.c, xc);
+    const int h = d / (ndf / 2);
+    cx<T> s = czero<T>();
+    for (int k = 0; k < N; k++) s += P[((size_t)k * volf + gf) * ndf + d] * in[gc * 2 * N + h * N + k];
+    out[gf * ndf + d] = s;
+}
+
+template <class T>
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    int nt = 256;
+    size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
+    k_coarse_restrict<T><<<2 * m.c.vh, nt, lds, s>>>(m, ndf, N, P, in, out);
+}
+template <class T>
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    long tot = 2L * m.f.vh * ndf;
+    k_coarse_prolong<T><<<nblk_of(tot, 256), 256, 0, s>>>(m, ndf, N, P, in, out);
+}
+
+// modified Gram-Schmidt per (coarser site, half): rows = aggregate sites x ndf/2
+template <class T>
+__global__ void k_coarse_gs(AggMap m, int ndf, int N, const cx<T>* __restrict__ tv, cx<T>* __restrict__ P, int* bad) {
+    __shared__ double red[2 * 16];
+    const int gc = blockIdx.x, h = blockIdx.y;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const int h0 = ndf / 2;
+    const int rows = m.asz * h0;
+    const bool act = t < rows;
+    const long volf = 2L * m.f.vh;
+    size_t off = 0;
+    if (act) {
+        int s = t / h0, d = h * h0 + t % h0;
+        int x[4];
+        agg_site_c(m, xc, s, x);
+        size_t gf = (size_t)site_parity(x) * m.f.vh + cb_index(m.f, x);
+        off = gf * ndf + d;
+    }
+    for (int k = 0; k < N; k++) {
+        cx<double> q = act ? ccast<double>(tv[(size_t)k * volf * ndf + off]) : czero<double>();
+        for (int j = 0; j < k; j++) {
+            cx<double> pj = act ? ccast<double>(P[(size_t)j * volf * ndf + off]) : czero<double>();
+            cx<double> d = cmulc(pj, q);
+            d.re = wave_sum(d.re);
+            d.im = wave_sum(d.im);
+            __syncthreads();
+            if (lane == 0) { red[2 * w] = d.re; red[2 * w + 1] = d.im; }
+            __syncthreads();
+            d = czero<double>();
+            for (int ww = 0; ww < nw; ww++) { d.re += red[2 * ww]; d.im += red[2 * ww + 1]; }
+            q -= d * pj;
+        }
+        double n2 = wave_sum(norm2(q));
+        __syncthreads();
+        if (lane == 0) red[2 * w] = n2;
+        __syncthreads();
+        n2 = 0;
+        for (int ww = 0; ww < nw; ww++) n2 += red[2 * ww];
+        double inv = 0;
+        if (n2 > 0) inv = 1.0 / sqrt(n2);
+        else if (t == 0) atomicAdd(bad, 1);
+        if (act) P[(size_t)k * volf * ndf + off] = ccast<T>(inv * q);
+    }
+}
+
+template <class T>
+void coarse_gram_schmidt(const AggMap& m, int ndf, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s) {
+    int nt = ((m.asz * (ndf / 2) + 63) / 64) * 64;
+    dim3 grid(2 * m.c.vh, 2);
+    k_coarse_gs<T><<<grid, nt, 0, s>>>(m, ndf, N, tv, P, bad);
+}
+
+// next coarser operator from a coarse one: workgroup (coarser site, column b)
+template <class T>
+__global__ void k_coarse_assemble(CoarseOp<T> op, AggMap m, int N, const cx<T>* __restrict__ P, cx<T>* __restrict__ Mc) {
+    extern __shared__ char smem_raw[];
+    const int ndf = op.nd;
+    const int h0 = ndf / 2;
+    const size_t nnf = (size_t)ndf * ndf;
+    cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);   // [nw][2N]
+    const int gc = blockIdx.x, bcol = blockIdx.y;
+    const int ndc = 2 * N, hb = bcol / N, kb = bcol % N;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool act = t < m.asz * ndf;
+    const long volf = 2L * m.f.vh;
+    int s = act ? t / ndf : 0, r = act ? t % ndf : 0;
+    int x[4];
+    agg_site_c(m, xc, s, x);
+    const int p = site_parity(x);
+    const size_t gf = (size_t)p * m.f.vh + cb_index(m.f, x);
+    // column b of P restricted to half hb, at site y
+    auto pcol = [&](size_t gy, int c) -> cx<T> {
+        return (c / h0 == hb) ? P[((size_t)kb * volf + gy) * ndf + c] : czero<T>();
+    };
+    for (int slot = 0; slot < 9; slot++) {
+        cx<T> wv = czero<T>();
+        if (act) {
+            if (slot == 0) {
+                for (int c = 0; c < ndf; c++) wv += op.M[(gf * 9) * nnf + (size_t)c * ndf + r] * pcol(gf, c);
+                for (int k = 0; k < 8; k++) {
+                    int y[4];
+                    nb_coords(op.g, x, k, y);
+                    if (y[0] / m.a[0] != xc[0] || y[1] / m.a[1] != xc[1] || y[2] / m.a[2] != xc[2] || y[3] / m.a[3] != xc[3]) continue;
+                    size_t gy = (size_t)(1 - p) * m.f.vh + cb_index(m.f, y);
+                    for (int c = 0; c < ndf; c++) wv += op.M[(gf * 9 + 1 + k) * nnf + (size_t)c * ndf + r] * pcol(gy, c);
+                }
+            } else {
+                int k = slot - 1;
+                int y[4];
+                nb_coords(op.g, x, k, y);
+                if (y[0] / m.a[0] != xc[0] || y[1] / m.a[1] != xc[1] || y[2] / m.a[2] != xc[2] || y[3] / m.a[3] != xc[3]) {
+                    size_t gy = (size_t)(1 - p) * m.f.vh + cb_index(m.f, y);
+                    for (int c = 0; c < ndf; c++) wv += op.M[(gf * 9 + 1 + k) * nnf + (size_t)c * ndf + r] * pcol(gy, c);
+                }
+            }
+        }
+        for (int a = 0; a < ndc; a++) {
+            const int ha = a / N, ka = a % N;
+            cx<double> d = czero<double>();
+            if (act && r / h0 == ha) d = cmulc(ccast<double>(P[((size_t)ka * volf + gf) * ndf + r]), ccast<double>(wv));
+            d.re = wave_sum(d.re);
+            d.im = wave_sum(d.im);
+            if (lane == 0) red[w * ndc + a] = d;
+        }
+        __syncthreads();
+        for (int a = t; a < ndc; a += blockDim.x) {
+            cx<double> sum = czero<double>();
+            for (int ww = 0; ww < nw; ww++) sum += red[ww * ndc + a];
+            Mc[(((size_t)gc * 9 + slot) * ndc + bcol) * ndc + a] = ccast<T>(sum);
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+void coarse_assemble(const CoarseOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* Mc, hipStream_t s) {
+    int nt = ((m.asz * op.nd + 63) / 64) * 64;
+    size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
+    dim3 grid(2 * m.c.vh, 2 * N);
+    k_coarse_assemble<T><<<grid, nt, lds, s>>>(op, m, N, P, Mc);
+}
+
+// counter-based normal numbers (Philox4x32-10 + Box-Muller), element index site*nd + c
+__device__ __forceinline__ void philox_c(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; r++) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1; c[3] = (uint32_t)p0; c[0] = n0; c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+template <class T>
+__global__ void k_coarse_random(Geom g, int nd, int n, unsigned long long seed, int sid, cx<T>* out) {
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (e >= vol * nd) return;
+    long s = e / nd;
+    int c = (int)(e % nd);
+    int x[4];
+    canon_coords(g.d, s, x);
+    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    for (int v = 0; v < n; v++) {
+        unsigned long long el = (unsigned long long)e;
+        uint32_t ctr[4] = {(uint32_t)el, (uint32_t)(el >> 32), (uint32_t)v, (uint32_t)sid};
+        philox_c(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+        double u1 = (ctr[0] + 0.5) * (1.0 / 4294967296.0);
+        double u2 = (ctr[1] + 0.5) * (1.0 / 4294967296.0);
+        double rr = sqrt(-2.0 * log(u1));
+        out[(size_t)v * vol * nd + gs * nd + c] = cx<T>{T(rr * cos(2.0 * M_PI * u2)), T(rr * sin(2.0 * M_PI * u2))};
+    }
+}
+
+template <class T>
+void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int sid, cx<T>* out, hipStream_t s) {
+    long tot = 2L * g.vh * nd;
+    k_coarse_random<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, n, seed, sid, out);
+}
+
+#define DD_COARSE_INST(T)                                                                                                \
+    template void coarse_apply<T>(const CoarseOp<T>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*, hipStream_t); \
+    template void coarse_self_inverse<T>(const Geom&, int, const cx<T>*, cx<T>*, int*, hipStream_t);                  \
+    template void coarse_import_vector<T>(const Geom&, int, int, const double*, cx<T>*, hipStream_t);                \
+    template void coarse_export_vector<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
+    template void coarse_export_blocks<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
+    template void coarse_shift_diag<T>(const Geom&, int, double, cx<T>*, hipStream_t);                                \
+    template void coarse_sap_half<T>(const CoarseOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t);    \
+    template void coarse_restrict<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);      \
+    template void coarse_prolong<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);       \
+    template void coarse_gram_schmidt<T>(const AggMap&, int, int, const cx<T>*, cx<T>*, int*, hipStream_t);          \
+    template void coarse_assemble<T>(const CoarseOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t);     \
+    template void coarse_random<T>(const Geom&, int, int, unsigned long long, int, cx<T>*, hipStream_t);
+
+DD_COARSE_INST(double)
+DD_COARSE_INST(float)
+
+}  // namespace dd

@@ -1,0 +1,963 @@
+// dd_fine.hip -- fine-level kernels of DD-alpha-AMG on gfx950.
+//
+//   clover-Wilson stencil ............ explicit site form of D (Sec. 2.2)
+//   clover term ...................... eq. (lattice_WD), four-leaf Q_{mu nu}
+//   SAP half sweep ................... Sec. 2.3 with the odd-even MR block solver of Sec. 5
+//   restriction / prolongation ....... eq. (aggInterpolation), standard aggregation (Sec. 3.2)
+//   local Gram-Schmidt ............... Sec. 3.1 (local orthonormalisation of the test vectors)
+//   coarse-operator assembly ......... D_c = P^H D P as a nearest-neighbour stencil (Sec. 3.2)
+//
+// Data layout: even-odd, block-major, structure of arrays (see dd_common.h).
+// A spinor field is [parity][12][vh] complex, the links [parity][mu][9][vh],
+// packed clover blocks [parity][72][vh] reals.  One thread owns one site, so
+// every load of a component is coalesced across the wavefront.
+#include "dd_kernels.h"
+
+#include <math.h>
+
+namespace dd {
+
+static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_import_gauge(Geom g, const double* __restrict__ canon, cx<T>* __restrict__ U) {
+    long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (s >= vol) return;
+    int x[4];
+    canon_coords(g.d, s, x);
+    int p = site_parity(x), i = cb_index(g, x);
+    const cx<double>* src = reinterpret_cast<const cx<double>*>(canon) + s * 36;
+    for (int mu = 0; mu < 4; mu++)
+        for (int e = 0; e < 9; e++) U[((size_t)(p * 4 + mu) * 9 + e) * g.vh + i] = ccast<T>(src[mu * 9 + e]);
+}
+
+template <class T>
+__global__ void k_import_vectors(Geom g, int n, const double* __restrict__ canon, cx<T>* __restrict__ out) {
+    long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (s >= vol) return;
+    int x[4];
+    canon_coords(g.d, s, x);
+    int p = site_parity(x), i = cb_index(g, x);
+    const cx<double>* src = reinterpret_cast<const cx<double>*>(canon);
+    for (int v = 0; v < n; v++)
+        for (int c = 0; c < 12; c++)
+            out[(size_t)v * 24 * g.vh + (size_t)(p * 12 + c) * g.vh + i] = ccast<T>(src[((size_t)v * vol + s) * 12 + c]);
+}
+
+template <class T>
+__global__ void k_export_vectors(Geom g, int n, const cx<T>* __restrict__ in, double* __restrict__ canon) {
+    long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (s >= vol) return;
+    int x[4];
+    canon_coords(g.d, s, x);
+    int p = site_parity(x), i = cb_index(g, x);
+    cx<double>* dst = reinterpret_cast<cx<double>*>(canon);
+    for (int v = 0; v < n; v++)
+        for (int c = 0; c < 12; c++)
+            dst[((size_t)v * vol + s) * 12 + c] = ccast<double>(in[(size_t)v * 24 * g.vh + (size_t)(p * 12 + c) * g.vh + i]);
+}
+
+template <class T>
+void fine_import_gauge(const Geom& g, const double* canon, cx<T>* U, hipStream_t s) {
+    long vol = 2L * g.vh;
+    k_import_gauge<T><<<nblk_of(vol, 256), 256, 0, s>>>(g, canon, U);
+}
+template <class T>
+void fine_import_spinor(const Geom& g, const double* canon, cx<T>* out, hipStream_t s) {
+    long vol = 2L * g.vh;
+    k_import_vectors<T><<<nblk_of(vol, 256), 256, 0, s>>>(g, 1, canon, out);
+}
+template <class T>
+void fine_export_spinor(const Geom& g, const cx<T>* in, double* canon, hipStream_t s) {
+    long vol = 2L * g.vh;
+    k_export_vectors<T><<<nblk_of(vol, 256), 256, 0, s>>>(g, 1, in, canon);
+}
+template <class T>
+void fine_import_vectors(const Geom& g, int n, const double* canon, cx<T>* out, hipStream_t s) {
+    long vol = 2L * g.vh;
+    k_import_vectors<T><<<nblk_of(vol, 256), 256, 0, s>>>(g, n, canon, out);
+}
+template <class T>
+void fine_export_vectors(const Geom& g, int n, const cx<T>* in, double* canon, hipStream_t s) {
+    long vol = 2L * g.vh;
+    k_export_vectors<T><<<nblk_of(vol, 256), 256, 0, s>>>(g, n, in, canon);
+}
+
+// ---------------------------------------------------------------------------
+// clover term
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cx<double> Bmat(int mu, int r, int c) {
+    // the off-diagonal spin blocks of the chiral gamma matrices (dd_common.h)
+    switch (mu) {
+        case 0: return (r != c) ? cx<double>{0.0, 1.0} : cx<double>{0.0, 0.0};
+        case 1: return (r == 0 && c == 1) ? cx<double>{-1.0, 0.0} : (r == 1 && c == 0) ? cx<double>{1.0, 0.0} : cx<double>{0.0, 0.0};
+        case 2: return (r != c) ? cx<double>{0.0, 0.0} : (r == 0 ? cx<double>{0.0, 1.0} : cx<double>{0.0, -1.0});
+        default: return (r == c) ? cx<double>{1.0, 0.0} : cx<double>{0.0, 0.0};
+    }
+}
+
+__device__ __forceinline__ void load_link64(const Geom& g, const cx<double>* U, const int y[4], int mu, cx<double> u[9]) {
+    int p = site_parity(y), i = cb_index(g, y);
+    for (int e = 0; e < 9; e++) u[e] = U[((size_t)(p * 4 + mu) * 9 + e) * g.vh + i];
+}
+
+__device__ __forceinline__ void m3mul(const cx<double> a[9], const cx<double> b[9], cx<double> c[9]) {
+    cx<double> t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = czero<double>();
+            for (int k = 0; k < 3; k++) s += a[i * 3 + k] * b[k * 3 + j];
+            t[i * 3 + j] = s;
+        }
+    for (int e = 0; e < 9; e++) c[e] = t[e];
+}
+// c = a b^H
+__device__ __forceinline__ void m3mul_nh(const cx<double> a[9], const cx<double> b[9], cx<double> c[9]) {
+    cx<double> t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = czero<double>();
+            for (int k = 0; k < 3; k++) s += a[i * 3 + k] * conj(b[j * 3 + k]);
+            t[i * 3 + j] = s;
+        }
+    for (int e = 0; e < 9; e++) c[e] = t[e];
+}
+// c = a^H b
+__device__ __forceinline__ void m3mul_hn(const cx<double> a[9], const cx<double> b[9], cx<double> c[9]) {
+    cx<double> t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = czero<double>();
+            for (int k = 0; k < 3; k++) s += cmulc(a[k * 3 + i], b[k * 3 + j]);
+            t[i * 3 + j] = s;
+        }
+    for (int e = 0; e < 9; e++) c[e] = t[e];
+}
+
+// Gauss-Jordan inverse of a 6x6 complex matrix (partial pivoting); returns 0 if singular
+__device__ int inv6(cx<double> a[36], cx<double> r[36]) {
+    for (int i = 0; i < 36; i++) r[i] = czero<double>();
+    for (int i = 0; i < 6; i++) r[i * 7] = cx<double>{1.0, 0.0};
+    for (int c = 0; c < 6; c++) {
+        int p = c;
+        double best = norm2(a[c * 6 + c]);
+        for (int q = c + 1; q < 6; q++)
+            if (norm2(a[q * 6 + c]) > best) { best = norm2(a[q * 6 + c]); p = q; }
+        if (best == 0.0) return 0;
+        if (p != c)
+            for (int j = 0; j < 6; j++) {
+                cx<double> t = a[c * 6 + j]; a[c * 6 + j] = a[p * 6 + j]; a[p * 6 + j] = t;
+                t = r[c * 6 + j]; r[c * 6 + j] = r[p * 6 + j]; r[p * 6 + j] = t;
+            }
+        cx<double> piv = a[c * 6 + c];
+        double d = norm2(piv);
+        cx<double> ip = {piv.re / d, -piv.im / d};
+        for (int j = 0; j < 6; j++) { a[c * 6 + j] = a[c * 6 + j] * ip; r[c * 6 + j] = r[c * 6 + j] * ip; }
+        for (int q = 0; q < 6; q++) {
+            if (q == c) continue;
+            cx<double> f = a[q * 6 + c];
+            for (int j = 0; j < 6; j++) {
+                a[q * 6 + j] -= f * a[c * 6 + j];
+                r[q * 6 + j] -= f * r[c * 6 + j];
+            }
+        }
+    }
+    return 1;
+}
+
+__device__ __forceinline__ void pack_herm(const cx<double> m[36], double* dst, int vh, int i) {
+    for (int r = 0; r < 6; r++) dst[(size_t)r * vh + i] = m[r * 7].re;
+    for (int r = 0; r < 6; r++)
+        for (int c = r + 1; c < 6; c++) {
+            int k = herm_off(r, c);
+            dst[(size_t)(6 + 2 * k) * vh + i] = m[r * 6 + c].re;
+            dst[(size_t)(7 + 2 * k) * vh + i] = m[r * 6 + c].im;
+        }
+}
+
+__device__ __forceinline__ void unpack_herm(const double* src, int vh, int i, cx<double> m[36]) {
+    for (int r = 0; r < 6; r++) m[r * 7] = cx<double>{src[(size_t)r * vh + i], 0.0};
+    for (int r = 0; r < 6; r++)
+        for (int c = r + 1; c < 6; c++) {
+            int k = herm_off(r, c);
+            cx<double> v = {src[(size_t)(6 + 2 * k) * vh + i], src[(size_t)(7 + 2 * k) * vh + i]};
+            m[r * 6 + c] = v;
+            m[c * 6 + r] = conj(v);
+        }
+}
+
+// finish one chiral block: pack A and its inverse
+__device__ __forceinline__ void finish_block(cx<double> a[36], double* clov, double* clovinv, int p, int h, int vh, int i,
+                                             int* bad) {
+    pack_herm(a, clov + (size_t)(p * 72 + h * 36) * vh, vh, i);
+    cx<double> r[36];
+    if (!inv6(a, r)) atomicAdd(bad, 1);
+    pack_herm(r, clovinv + (size_t)(p * 72 + h * 36) * vh, vh, i);
+}
+
+// T(x) = -(csw/32) sum_{mu,nu} gamma_mu gamma_nu (x) (Q_{mu nu} - Q_{nu mu})
+//      = -(csw/16) sum_{mu<nu} diag(B_mu B_nu^H, B_mu^H B_nu) (x) (Q_{mu nu} - Q_{mu nu}^H)
+__global__ void k_clover_links(Geom g, const cx<double>* __restrict__ U, double m0, double csw, double* clov,
+                               double* clovinv, int* bad) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.vh) return;
+    int p = gid >= g.vh, i = gid - p * g.vh;
+    int x[4];
+    cb_coords(g, p, i, x);
+    cx<double> Tb[2][36];
+    for (int h = 0; h < 2; h++)
+        for (int e = 0; e < 36; e++) Tb[h][e] = czero<double>();
+    for (int mu = 0; mu < 4; mu++)
+        for (int nu = mu + 1; nu < 4; nu++) {
+            int xpm[4], xpn[4], xmm[4], xmn[4], xmmpn[4], xmmmn[4], xmnpm[4];
+            nb_coords(g, x, mu, xpm);
+            nb_coords(g, x, nu, xpn);
+            nb_coords(g, x, 4 + mu, xmm);
+            nb_coords(g, x, 4 + nu, xmn);
+            nb_coords(g, xmm, nu, xmmpn);
+            nb_coords(g, xmm, 4 + nu, xmmmn);
+            nb_coords(g, xmn, mu, xmnpm);
+            cx<double> q[9], t[9], a[9], b[9];
+            // U_mu(x) U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H
+            load_link64(g, U, x, mu, a); load_link64(g, U, xpm, nu, b); m3mul(a, b, t);
+            load_link64(g, U, xpn, mu, a); m3mul_nh(t, a, t);
+            load_link64(g, U, x, nu, a); m3mul_nh(t, a, q);
+            // U_nu(x) U_mu(x-mu+nu)^H U_nu(x-mu)^H U_mu(x-mu)
+            load_link64(g, U, x, nu, a); load_link64(g, U, xmmpn, mu, b); m3mul_nh(a, b, t);
+            load_link64(g, U, xmm, nu, a); m3mul_nh(t, a, t);
+            load_link64(g, U, xmm, mu, a); m3mul(t, a, t);
+            for (int e = 0; e < 9; e++) q[e] += t[e];
+            // U_mu(x-mu)^H U_nu(x-mu-nu)^H U_mu(x-mu-nu) U_nu(x-nu)
+            load_link64(g, U, xmm, mu, a); load_link64(g, U, xmmmn, nu, b);
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) {  // t = a^H b^H = (b a)^H
+                    cx<double> s = czero<double>();
+                    for (int k = 0; k < 3; k++) s += b[r * 3 + k] * a[k * 3 + c];
+                    t[c * 3 + r] = conj(s);
+                }
+            load_link64(g, U, xmmmn, mu, a); m3mul(t, a, t);
+            load_link64(g, U, xmn, nu, a); m3mul(t, a, t);
+            for (int e = 0; e < 9; e++) q[e] += t[e];
+            // U_nu(x-nu)^H U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^H
+            load_link64(g, U, xmn, nu, a); load_link64(g, U, xmn, mu, b); m3mul_hn(a, b, t);
+            load_link64(g, U, xmnpm, nu, a); m3mul(t, a, t);
+            load_link64(g, U, x, mu, a); m3mul_nh(t, a, t);
+            for (int e = 0; e < 9; e++) q[e] += t[e];
+            // F = Q - Q^H
+            cx<double> F[9];
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) F[r * 3 + c] = q[r * 3 + c] - conj(q[c * 3 + r]);
+            for (int h = 0; h < 2; h++) {
+                // sigma = B_mu B_nu^H (h = 0) or B_mu^H B_nu (h = 1)
+                cx<double> sg[4];
+                for (int r = 0; r < 2; r++)
+                    for (int c = 0; c < 2; c++) {
+                        cx<double> s = czero<double>();
+                        for (int k = 0; k < 2; k++) {
+                            if (h == 0) s += Bmat(mu, r, k) * conj(Bmat(nu, c, k));
+                            else s += conj(Bmat(mu, k, r)) * Bmat(nu, k, c);
+                        }
+                        sg[r * 2 + c] = s;
+                    }
+                for (int sr = 0; sr < 2; sr++)
+                    for (int sc = 0; sc < 2; sc++)
+                        for (int a3 = 0; a3 < 3; a3++)
+                            for (int b3 = 0; b3 < 3; b3++)
+                                Tb[h][(sr * 3 + a3) * 6 + sc * 3 + b3] += (-csw / 16.0) * (sg[sr * 2 + sc] * F[a3 * 3 + b3]);
+            }
+        }
+    for (int h = 0; h < 2; h++) {
+        for (int e = 0; e < 6; e++) Tb[h][e * 7].re += m0 + 4.0;
+        finish_block(Tb[h], clov, clovinv, p, h, g.vh, i, bad);
+    }
+}
+
+// user-supplied T(x): canonical [vol][2][6][6] complex
+__global__ void k_clover_user(Geom g, const double* __restrict__ canonT, double m0, double* clov, double* clovinv,
+                              int* bad) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.vh) return;
+    int p = gid >= g.vh, i = gid - p * g.vh;
+    int x[4];
+    cb_coords(g, p, i, x);
+    long s = canon_index(g.d, x);
+    const cx<double>* src = reinterpret_cast<const cx<double>*>(canonT) + s * 72;
+    for (int h = 0; h < 2; h++) {
+        cx<double> a[36];
+        for (int e = 0; e < 36; e++) a[e] = src[h * 36 + e];
+        for (int e = 0; e < 6; e++) a[e * 7].re += m0 + 4.0;
+        finish_block(a, clov, clovinv, p, h, g.vh, i, bad);
+    }
+}
+
+__global__ void k_clover_shift(Geom g, double dm, double* clov, double* clovinv, int* bad) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.vh) return;
+    int p = gid >= g.vh, i = gid - p * g.vh;
+    for (int h = 0; h < 2; h++) {
+        cx<double> a[36];
+        unpack_herm(clov + (size_t)(p * 72 + h * 36) * g.vh, g.vh, i, a);
+        for (int e = 0; e < 6; e++) a[e * 7].re += dm;
+        finish_block(a, clov, clovinv, p, h, g.vh, i, bad);
+    }
+}
+
+__global__ void k_clover_export(Geom g, const double* __restrict__ packed, double* __restrict__ canon) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.vh) return;
+    int p = gid >= g.vh, i = gid - p * g.vh;
+    int x[4];
+    cb_coords(g, p, i, x);
+    long s = canon_index(g.d, x);
+    cx<double>* dst = reinterpret_cast<cx<double>*>(canon) + s * 72;
+    for (int h = 0; h < 2; h++) {
+        cx<double> a[36];
+        unpack_herm(packed + (size_t)(p * 72 + h * 36) * g.vh, g.vh, i, a);
+        for (int e = 0; e < 36; e++) dst[h * 36 + e] = a[e];
+    }
+}
+
+void fine_clover_from_links(const Geom& g, const cx<double>* U, double m0, double csw, double* clov, double* clovinv,
+                            int* bad, hipStream_t s) {
+    k_clover_links<<<nblk_of(2L * g.vh, 128), 128, 0, s>>>(g, U, m0, csw, clov, clovinv, bad);
+}
+void fine_clover_from_user(const Geom& g, const double* canonT, double m0, double* clov, double* clovinv, int* bad,
+                           hipStream_t s) {
+    k_clover_user<<<nblk_of(2L * g.vh, 128), 128, 0, s>>>(g, canonT, m0, clov, clovinv, bad);
+}
+void fine_clover_shift(const Geom& g, double dm, double* clov, double* clovinv, int* bad, hipStream_t s) {
+    k_clover_shift<<<nblk_of(2L * g.vh, 128), 128, 0, s>>>(g, dm, clov, clovinv, bad);
+}
+void fine_clover_export(const Geom& g, const double* packed, double* canon, hipStream_t s) {
+    k_clover_export<<<nblk_of(2L * g.vh, 256), 256, 0, s>>>(g, packed, canon);
+}
+
+// ---------------------------------------------------------------------------
+// stencil building blocks
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void load_link(const FineOp<T>& op, int p, int mu, int i, cx<T> u[9]) {
+    const cx<T>* base = op.U + (size_t)(p * 4 + mu) * 9 * op.g.vh + i;
+#pragma unroll
+    for (int e = 0; e < 9; e++) u[e] = base[(size_t)e * op.g.vh];
+}
+
+template <class T>
+__device__ __forceinline__ void load_spinor(const cx<T>* psi, int vh, int p, int i, cx<T> v[12]) {
+    const cx<T>* base = psi + (size_t)p * 12 * vh + i;
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = base[(size_t)c * vh];
+}
+
+template <class T>
+__device__ __forceinline__ void store_spinor(cx<T>* psi, int vh, int p, int i, const cx<T> v[12]) {
+    cx<T>* base = psi + (size_t)p * 12 * vh + i;
+#pragma unroll
+    for (int c = 0; c < 12; c++) base[(size_t)c * vh] = v[c];
+}
+
+// out = A v with the packed clover blocks at (p, i) of array `cl`
+template <class T>
+__device__ __forceinline__ void clover_apply(const T* __restrict__ cl, int vh, int p, int i, const cx<T> v[12], cx<T> out[12]) {
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        T m[36];
+        const T* base = cl + (size_t)(p * 72 + h * 36) * vh + i;
+#pragma unroll
+        for (int r = 0; r < 36; r++) m[r] = base[(size_t)r * vh];
+        herm6_apply(m, v + 6 * h, out + 6 * h);
+    }
+}
+
+// acc += (I -/+ gamma_mu) (x) U psi_y for hop k from a site of parity p:
+// forward (k < 4): link U_mu(x) at (p, i); backward: U_mu(y)^H at (1-p, j)
+template <class T>
+__device__ __forceinline__ void hop_accum(const FineOp<T>& op, int k, int p, int i, int j, const cx<T> v[12], cx<T> acc[12]) {
+    int mu = k & 3;
+    cx<T> h[6], gg[6], u[9];
+    if (k < 4) {
+        spin_project(mu, T(-1), v, h);
+        load_link(op, p, mu, i, u);
+        su3_two_spinor(u, false, h, gg);
+        spin_reconstruct(mu, T(-1), gg, acc);
+    } else {
+        spin_project(mu, T(1), v, h);
+        load_link(op, 1 - p, mu, j, u);
+        su3_two_spinor(u, true, h, gg);
+        spin_reconstruct(mu, T(1), gg, acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// D psi = A psi - 1/2 sum_mu [(I - g_mu) U_mu(x) psi(x+mu) + (I + g_mu) U_mu(x-mu)^H psi(x-mu)]
+// one thread per site, both parities in one grid
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out) {
+    const Geom g = op.g;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.vh) return;
+    int p = gid >= g.vh, i = gid - p * g.vh;
+    int x[4];
+    cb_coords(g, p, i, x);
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, x, k, y);
+        int j = cb_index(g, y);
+        cx<T> v[12];
+        load_spinor(in, g.vh, 1 - p, j, v);
+        hop_accum(op, k, p, i, j, v, acc);
+    }
+    cx<T> v[12], a[12];
+    load_spinor(in, g.vh, p, i, v);
+    clover_apply(op.clov, g.vh, p, i, v, a);
+#pragma unroll
+    for (int c = 0; c < 12; c++) a[c] -= T(0.5) * acc[c];
+    store_spinor(out, g.vh, p, i, a);
+}
+
+template <class T>
+void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    k_dirac<T><<<nblk_of(2L * op.g.vh, 256), 256, 0, s>>>(op, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// SAP half sweep: one workgroup per lattice block of the active colour.
+// Thread t owns the block's even site t and odd site t (local layout index).
+// With r = b - D z restricted to the block and H the hopping part of D:
+//   t0_e = A_e^{-1}(b_e - (H z)_e) - z_e               (= A_ee^{-1} r_e)
+//   f_o  = b_o - A_o z_o - (H z)_o - (H_int t0)_o        (= r_o - D_oe A_ee^{-1} r_e)
+//   MR on S = A_oo - D_oe A_ee^{-1} D_eo (block-internal hops) from e_o = 0
+//   e_e  = t0_e - A_e^{-1} (H_int e_o)_e
+//   z   += e on the block
+// Block-internal spinors are exchanged through LDS; the MR inner products are
+// wavefront shuffles plus one LDS step.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void lds_load(const cx<T>* buf, int bvh, int l, cx<T> v[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = buf[c * bvh + l];
+}
+template <class T>
+__device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T> v[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; c++) buf[c * bvh + l] = v[c];
+}
+
+// acc += sum over block-internal hops of the LDS field `buf` (opposite parity)
+template <class T>
+__device__ __forceinline__ void hop_internal(const FineOp<T>& op, int p, int i, const int nbj[8], int base, int lbvh,
+                                             const cx<T>* buf, int bvh, cx<T> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        int j = nbj[k];
+        if ((j >> lbvh) != (base >> lbvh)) continue;
+        cx<T> v[12];
+        lds_load(buf, bvh, j - base, v);
+        hop_accum(op, k, p, i, j, v, acc);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void hop_all(const FineOp<T>& op, int p, int i, const int nbj[8], const cx<T>* psi, cx<T> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        cx<T> v[12];
+        load_spinor(psi, op.g.vh, 1 - p, nbj[k], v);
+        hop_accum(op, k, p, i, nbj[k], v, acc);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __restrict__ blocks,
+                                                  const cx<T>* __restrict__ b, cx<T>* __restrict__ z, int mr_steps) {
+    extern __shared__ char smem_raw[];
+    const Geom g = op.g;
+    const int bvh = g.bvh;
+    cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // odd-site field [12][bvh]
+    cx<T>* se = so + 12 * bvh;                        // even-site field [12][bvh]
+    double* red = reinterpret_cast<double*>(se + 12 * bvh);
+    const int blk = blocks[blockIdx.x];
+    const int base = blk << g.lbvh;
+    const int t = threadIdx.x;
+    const bool act = t < bvh;
+    const int i = base + (act ? t : 0);
+    int xe[4], xo[4], nbe[8], nbo[8];
+    cb_coords(g, 0, i, xe);
+    cb_coords(g, 1, i, xo);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, xe, k, y);
+        nbe[k] = cb_index(g, y);
+        nb_coords(g, xo, k, y);
+        nbo[k] = cb_index(g, y);
+    }
+    cx<T> t0[12], rho[12], eo[12], s[12], acc[12], v[12];
+    // ---- t0_e = A_e^{-1}(b_e - H z) - z_e ----
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+        hop_all(op, 0, i, nbe, z, acc);
+        load_spinor(b, g.vh, 0, i, v);
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];
+        clover_apply(op.clovinv, g.vh, 0, i, v, t0);
+        load_spinor(z, g.vh, 0, i, v);
+#pragma unroll
+        for (int c = 0; c < 12; c++) t0[c] -= v[c];
+        lds_store(se, bvh, t, t0);
+    }
+    __syncthreads();
+    // ---- f_o = b_o - A z_o - H z - H_int t0 ----
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+        hop_all(op, 1, i, nbo, z, acc);
+        hop_internal(op, 1, i, nbo, base, g.lbvh, se, bvh, acc);
+        load_spinor(z, g.vh, 1, i, v);
+        clover_apply(op.clov, g.vh, 1, i, v, rho);
+        load_spinor(b, g.vh, 1, i, v);
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            rho[c] = v[c] - rho[c] + T(0.5) * acc[c];
+            eo[c] = czero<T>();
+        }
+        lds_store(so, bvh, t, rho);
+    }
+    __syncthreads();
+    for (int it = 0; it < mr_steps; it++) {
+        // even: t = A^{-1} (H_int rho) ;  H = -1/2 hopsum
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+            hop_internal(op, 0, i, nbe, base, g.lbvh, so, bvh, acc);
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
+            clover_apply(op.clovinv, g.vh, 0, i, acc, v);
+            lds_store(se, bvh, t, v);
+        }
+        __syncthreads();
+        // odd: s = A rho - H_int t
+        double sr = 0, si = 0, ss = 0;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+            hop_internal(op, 1, i, nbo, base, g.lbvh, se, bvh, acc);
+            clover_apply(op.clov, g.vh, 1, i, rho, s);
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                s[c] += T(0.5) * acc[c];
+                cx<T> d = cmulc(s[c], rho[c]);
+                sr += d.re;
+                si += d.im;
+                ss += norm2(s[c]);
+            }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        ss = wave_sum(ss);
+        const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+        if (lane == 0) { red[3 * w] = sr; red[3 * w + 1] = si; red[3 * w + 2] = ss; }
+        __syncthreads();
+        sr = si = ss = 0;
+        for (int q = 0; q < nw; q++) { sr += red[3 * q]; si += red[3 * q + 1]; ss += red[3 * q + 2]; }
+        if (ss > 0) {
+            cx<T> alpha = {T(sr / ss), T(si / ss)};
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    eo[c] += alpha * rho[c];
+                    rho[c] -= alpha * s[c];
+                }
+            }
+        }
+        __syncthreads();
+        if (act) lds_store(so, bvh, t, (it + 1 < mr_steps) ? rho : eo);
+        __syncthreads();
+    }
+    if (mr_steps == 0) {
+        if (act) lds_store(so, bvh, t, eo);
+        __syncthreads();
+    }
+    // ---- back-substitution and update ----
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+        hop_internal(op, 0, i, nbe, base, g.lbvh, so, bvh, acc);
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
+        clover_apply(op.clovinv, g.vh, 0, i, acc, v);
+        load_spinor(z, g.vh, 0, i, acc);
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] += t0[c] + v[c];
+        store_spinor(z, g.vh, 0, i, acc);
+        load_spinor(z, g.vh, 1, i, acc);
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] += eo[c];
+        store_spinor(z, g.vh, 1, i, acc);
+    }
+}
+
+template <class T>
+void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+                   hipStream_t s) {
+    if (nblocks <= 0) return;
+    int nt = ((op.g.bvh + 63) / 64) * 64;
+    size_t lds = 2 * 12 * (size_t)op.g.bvh * sizeof(cx<T>) + 3 * sizeof(double) * (nt / 64);
+    k_sap_fine<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps);
+}
+
+// ---------------------------------------------------------------------------
+// aggregation: coarse site gc (layout) owns the fine sites xc*a + l
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void agg_site(const AggMap& m, const int xc[4], int s, int x[4]) {
+    int l3 = s % m.a[3]; s /= m.a[3];
+    int l2 = s % m.a[2]; s /= m.a[2];
+    int l1 = s % m.a[1];
+    int l0 = s / m.a[1];
+    x[0] = xc[0] * m.a[0] + l0;
+    x[1] = xc[1] * m.a[1] + l1;
+    x[2] = xc[2] * m.a[2] + l2;
+    x[3] = xc[3] * m.a[3] + l3;
+}
+
+__device__ __forceinline__ void coarse_of(const AggMap& m, const int x[4], int xc[4]) {
+    for (int mu = 0; mu < 4; mu++) xc[mu] = x[mu] / m.a[mu];
+}
+
+// sum of per-wave partials: lane 0 of each wave stores; after a sync thread 0..n-1 adds them up
+// out[k] for k < n: P^H in, 2N unknowns per coarse site (index h*N + k)
+template <class T>
+__global__ void k_restrict_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+                                cx<T>* __restrict__ out) {
+    extern __shared__ char smem_raw[];
+    cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][2N]
+    const int gc = blockIdx.x;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool act = t < m.asz;
+    int p = 0, i = 0;
+    cx<T> v[12];
+    if (act) {
+        int x[4];
+        agg_site(m, xc, t, x);
+        p = site_parity(x);
+        i = cb_index(m.f, x);
+        load_spinor(in, m.f.vh, p, i, v);
+    }
+    const int vh = m.f.vh;
+    for (int k = 0; k < N; k++) {
+        cx<double> d0 = czero<double>(), d1 = czero<double>();
+        if (act) {
+            cx<T> q[12];
+            load_spinor(P + (size_t)k * 24 * vh, vh, p, i, q);
+#pragma unroll
+            for (int c = 0; c < 6; c++) d0 += ccast<double>(cmulc(q[c], v[c]));
+#pragma unroll
+            for (int c = 6; c < 12; c++) d1 += ccast<double>(cmulc(q[c], v[c]));
+        }
+        d0.re = wave_sum(d0.re); d0.im = wave_sum(d0.im);
+        d1.re = wave_sum(d1.re); d1.im = wave_sum(d1.im);
+        if (lane == 0) { red[w * 2 * N + k] = d0; red[w * 2 * N + N + k] = d1; }
+    }
+    __syncthreads();
+    for (int q = t; q < 2 * N; q += blockDim.x) {
+        cx<double> s = czero<double>();
+        for (int ww = 0; ww < nw; ww++) s += red[ww * 2 * N + q];
+        out[(size_t)gc * 2 * N + q] = ccast<T>(s);
+    }
+}
+
+template <class T>
+__global__ void k_prolong_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+                               cx<T>* __restrict__ out) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int vh = m.f.vh;
+    if (gid >= 2 * vh) return;
+    int p = gid >= vh, i = gid - p * vh;
+    int x[4], xc[4];
+    cb_coords(m.f, p, i, x);
+    coarse_of(m, x, xc);
+    int pc = site_parity(xc), ic = cb_index(m.c, xc);
+    const cx<T>* e = in + ((size_t)pc * m.c.vh + ic) * 2 * N;
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+    for (int k = 0; k < N; k++) {
+        cx<T> q[12];
+        load_spinor(P + (size_t)k * 24 * vh, vh, p, i, q);
+        cx<T> e0 = e[k], e1 = e[N + k];
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[c] += q[c] * e0;
+#pragma unroll
+        for (int c = 6; c < 12; c++) acc[c] += q[c] * e1;
+    }
+    store_spinor(out, vh, p, i, acc);
+}
+
+template <class T>
+void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    int nt = ((m.asz + 63) / 64) * 64;
+    size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
+    k_restrict_fine<T><<<2 * m.c.vh, nt, lds, s>>>(m, N, P, in, out);
+}
+template <class T>
+void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    k_prolong_fine<T><<<nblk_of(2L * m.f.vh, 256), 256, 0, s>>>(m, N, P, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// local orthonormalisation: modified Gram-Schmidt of v_1..v_N restricted to
+// one aggregate (coarse site gc, spin half h), in the order 1..N
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_gs_fine(AggMap m, int N, const cx<T>* __restrict__ tv, cx<T>* __restrict__ P, int* bad) {
+    __shared__ double red[2 * 16];
+    const int gc = blockIdx.x, h = blockIdx.y;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool act = t < m.asz;
+    const int vh = m.f.vh;
+    int p = 0, i = 0;
+    if (act) {
+        int x[4];
+        agg_site(m, xc, t, x);
+        p = site_parity(x);
+        i = cb_index(m.f, x);
+    }
+    for (int k = 0; k < N; k++) {
+        cx<double> q[6];
+        const size_t off_k = (size_t)k * 24 * vh + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+        for (int c = 0; c < 6; c++) q[c] = act ? ccast<double>(tv[off_k + (size_t)c * vh]) : czero<double>();
+        for (int j = 0; j < k; j++) {
+            const size_t off_j = (size_t)j * 24 * vh + (size_t)(p * 12 + 6 * h) * vh + i;
+            cx<T> pj[6];
+            cx<double> d = czero<double>();
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < 6; c++) {
+                    pj[c] = P[off_j + (size_t)c * vh];
+                    d += cmulc(ccast<double>(pj[c]), q[c]);
+                }
+            }
+            d.re = wave_sum(d.re);
+            d.im = wave_sum(d.im);
+            __syncthreads();
+            if (lane == 0) { red[2 * w] = d.re; red[2 * w + 1] = d.im; }
+            __syncthreads();
+            d = czero<double>();
+            for (int ww = 0; ww < nw; ww++) { d.re += red[2 * ww]; d.im += red[2 * ww + 1]; }
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < 6; c++) q[c] -= d * ccast<double>(pj[c]);
+            }
+        }
+        double n2 = 0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) n2 += norm2(q[c]);
+        n2 = wave_sum(n2);
+        __syncthreads();
+        if (lane == 0) red[2 * w] = n2;
+        __syncthreads();
+        n2 = 0;
+        for (int ww = 0; ww < nw; ww++) n2 += red[2 * ww];
+        double inv = 0;
+        if (n2 > 0) inv = 1.0 / sqrt(n2);
+        else if (t == 0) atomicAdd(bad, 1);
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) P[off_k + (size_t)c * vh] = ccast<T>(inv * q[c]);
+        }
+    }
+}
+
+template <class T>
+void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s) {
+    int nt = ((m.asz + 63) / 64) * 64;
+    dim3 grid(2 * m.c.vh, 2);
+    k_gs_fine<T><<<grid, nt, 0, s>>>(m, N, tv, P, bad);
+}
+
+// ---------------------------------------------------------------------------
+// D_c = P^H D P: workgroup (coarse site c, column b = hb*N + kb); slot 0
+// collects the self coupling and the hops that stay inside the aggregate's
+// lattice block, slot 1+k the hops k that leave it.  Accumulated in FP64.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __restrict__ P, cx<T>* __restrict__ M) {
+    extern __shared__ char smem_raw[];
+    cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][2N]
+    const int gc = blockIdx.x, bcol = blockIdx.y;
+    const int nd = 2 * N, hb = bcol / N, kb = bcol % N;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool act = t < m.asz;
+    const int vh = m.f.vh;
+    int x[4] = {0, 0, 0, 0}, p = 0, i = 0;
+    if (act) {
+        agg_site(m, xc, t, x);
+        p = site_parity(x);
+        i = cb_index(m.f, x);
+    }
+    const cx<T>* Pb = P + (size_t)kb * 24 * vh;
+    for (int slot = 0; slot < 9; slot++) {
+        cx<T> wv[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) wv[c] = czero<T>();
+        if (act) {
+            if (slot == 0) {
+                cx<T> v[12];
+                load_spinor(Pb, vh, p, i, v);
+#pragma unroll
+                for (int c = 0; c < 12; c++)
+                    if ((c / 6) != hb) v[c] = czero<T>();
+                clover_apply(op.clov, vh, p, i, v, wv);
+                cx<T> acc[12];
+#pragma unroll
+                for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+                for (int k = 0; k < 8; k++) {
+                    int y[4], yc[4];
+                    nb_coords(op.g, x, k, y);
+                    coarse_of(m, y, yc);
+                    if (yc[0] != xc[0] || yc[1] != xc[1] || yc[2] != xc[2] || yc[3] != xc[3]) continue;
+                    int j = cb_index(op.g, y);
+                    load_spinor(Pb, vh, 1 - p, j, v);
+#pragma unroll
+                    for (int c = 0; c < 12; c++)
+                        if ((c / 6) != hb) v[c] = czero<T>();
+                    hop_accum(op, k, p, i, j, v, acc);
+                }
+#pragma unroll
+                for (int c = 0; c < 12; c++) wv[c] -= T(0.5) * acc[c];
+            } else {
+                int k = slot - 1;
+                int y[4], yc[4];
+                nb_coords(op.g, x, k, y);
+                coarse_of(m, y, yc);
+                if (yc[0] != xc[0] || yc[1] != xc[1] || yc[2] != xc[2] || yc[3] != xc[3]) {
+                    int j = cb_index(op.g, y);
+                    cx<T> v[12], acc[12];
+                    load_spinor(Pb, vh, 1 - p, j, v);
+#pragma unroll
+                    for (int c = 0; c < 12; c++) {
+                        if ((c / 6) != hb) v[c] = czero<T>();
+                        acc[c] = czero<T>();
+                    }
+                    hop_accum(op, k, p, i, j, v, acc);
+#pragma unroll
+                    for (int c = 0; c < 12; c++) wv[c] = T(-0.5) * acc[c];
+                }
+            }
+        }
+        for (int a = 0; a < nd; a++) {
+            const int ha = a / N, ka = a % N;
+            cx<double> d = czero<double>();
+            if (act) {
+                const cx<T>* Pa = P + (size_t)ka * 24 * vh + (size_t)(p * 12 + 6 * ha) * vh + i;
+#pragma unroll
+                for (int c = 0; c < 6; c++) d += cmulc(ccast<double>(Pa[(size_t)c * vh]), ccast<double>(wv[6 * ha + c]));
+            }
+            d.re = wave_sum(d.re);
+            d.im = wave_sum(d.im);
+            if (lane == 0) red[w * nd + a] = d;
+        }
+        __syncthreads();
+        for (int a = t; a < nd; a += blockDim.x) {
+            cx<double> s = czero<double>();
+            for (int ww = 0; ww < nw; ww++) s += red[ww * nd + a];
+            M[(((size_t)gc * 9 + slot) * nd + bcol) * nd + a] = ccast<T>(s);  // column-major block
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+void fine_assemble(const FineOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* M, hipStream_t s) {
+    int nt = ((m.asz + 63) / 64) * 64;
+    size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
+    dim3 grid(2 * m.c.vh, 2 * N);
+    k_assemble_fine<T><<<grid, nt, lds, s>>>(op, m, N, P, M);
+}
+
+// ---------------------------------------------------------------------------
+// counter-based normal numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// SC'11) keyed by the seed, counter (element index, vector, stream), then the
+// Box-Muller transform.  Element e of vector v gets re + i im ~ N(0,1) each.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; r++) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ cx<double> gauss_pair(unsigned long long seed, unsigned long long e, int v, int sid) {
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)v, (uint32_t)sid};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    double u1 = (c[0] + 0.5) * (1.0 / 4294967296.0);
+    double u2 = (c[1] + 0.5) * (1.0 / 4294967296.0);
+    double r = sqrt(-2.0 * log(u1));
+    return {r * cos(2.0 * M_PI * u2), r * sin(2.0 * M_PI * u2)};
+}
+
+template <class T>
+__global__ void k_random_fine(Geom g, int n, unsigned long long seed, int sid, cx<T>* out) {
+    long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long vol = 2L * g.vh;
+    if (s >= vol) return;
+    int x[4];
+    canon_coords(g.d, s, x);
+    int p = site_parity(x), i = cb_index(g, x);
+    for (int v = 0; v < n; v++)
+        for (int c = 0; c < 12; c++)
+            out[(size_t)v * 24 * g.vh + (size_t)(p * 12 + c) * g.vh + i] = ccast<T>(gauss_pair(seed, s * 12 + c, v, sid));
+}
+
+template <class T>
+void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* out, hipStream_t s) {
+    k_random_fine<T><<<nblk_of(2L * g.vh, 256), 256, 0, s>>>(g, n, seed, sid, out);
+}
+
+// ---------------------------------------------------------------------------
+#define DD_FINE_INST(T)                                                                                      \
+    template void fine_import_gauge<T>(const Geom&, const double*, cx<T>*, hipStream_t);                     \
+    template void fine_import_spinor<T>(const Geom&, const double*, cx<T>*, hipStream_t);                    \
+    template void fine_export_spinor<T>(const Geom&, const cx<T>*, double*, hipStream_t);                    \
+    template void fine_import_vectors<T>(const Geom&, int, const double*, cx<T>*, hipStream_t);              \
+    template void fine_export_vectors<T>(const Geom&, int, const cx<T>*, double*, hipStream_t);              \
+    template void fine_dirac<T>(const FineOp<T>&, const cx<T>*, cx<T>*, hipStream_t);                        \
+    template void fine_sap_half<T>(const FineOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t); \
+    template void fine_restrict<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);     \
+    template void fine_prolong<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);      \
+    template void fine_gram_schmidt<T>(const AggMap&, int, const cx<T>*, cx<T>*, int*, hipStream_t);         \
+    template void fine_assemble<T>(const FineOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t); \
+    template void fine_random<T>(const Geom&, int, unsigned long long, int, cx<T>*, hipStream_t);
+
+DD_FINE_INST(double)
+DD_FINE_INST(float)
+
+}  // namespace dd

@@ -1,0 +1,120 @@
+// dd_kernels.h -- host-side launchers of the HIP kernels (one translation unit
+// per family: fine level, coarse levels, vector algebra).  All launchers are
+// asynchronous on the given stream.
+#pragma once
+#include "dd_common.h"
+
+namespace dd {
+
+// Fine clover-Wilson operator in one precision, even-odd block-major layout.
+//   U       [2][4][9][vh]  forward links of each site
+//   clov    [2][72][vh]    packed A(x) = (m0+4) I + T(x), two Hermitian 6x6 blocks
+//   clovinv [2][72][vh]    packed A(x)^{-1}
+template <class T>
+struct FineOp {
+    Geom g;
+    const cx<T>* U;
+    const T* clov;
+    const T* clovinv;
+};
+
+// Coarse stencil D_c on a level with nd unknowns per site.
+//   M    [vol][9][nd][nd]  column-major blocks: slot 0 self, 1+mu couples x+mu,
+//                          5+mu couples x-mu (layout site order)
+//   Minv [vol][nd][nd]     column-major inverse of the self block
+template <class T>
+struct CoarseOp {
+    Geom g;
+    int nd;
+    const cx<T>* M;
+    const cx<T>* Minv;
+};
+
+// aggregation of a fine (or finer coarse) level onto the next coarser level
+struct AggMap {
+    Geom f;        // finer level layout
+    Geom c;        // coarser level layout
+    int a[4];      // aggregate lattice-block extents
+    int asz;       // sites per aggregate
+};
+
+// ---- fine level (dd_fine.hip) ---------------------------------------------
+template <class T> void fine_import_gauge(const Geom& g, const double* canon, cx<T>* U, hipStream_t s);
+template <class T> void fine_import_spinor(const Geom& g, const double* canon, cx<T>* out, hipStream_t s);
+template <class T> void fine_export_spinor(const Geom& g, const cx<T>* in, double* canon, hipStream_t s);
+// clover from the FP64 layout links (four-leaf Q_{mu nu}), or from canonical
+// user blocks T(x); writes packed A and A^{-1} in FP64.  `bad` counts singular blocks.
+void fine_clover_from_links(const Geom& g, const cx<double>* U, double m0, double csw, double* clov,
+                            double* clovinv, int* bad, hipStream_t s);
+void fine_clover_from_user(const Geom& g, const double* canonT, double m0, double* clov, double* clovinv, int* bad,
+                           hipStream_t s);
+void fine_clover_shift(const Geom& g, double dm, double* clov, double* clovinv, int* bad, hipStream_t s);
+void fine_clover_export(const Geom& g, const double* packed, double* canon, hipStream_t s);
+template <class T> void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s);
+// one SAP half sweep: blocks listed in `blocks` (all of one colour)
+template <class T>
+void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+                   hipStream_t s);
+// P columns: [N][2][12][vh] (N fine spinors); coarse vectors: [cvol][2N] (layout order)
+template <class T>
+void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+template <class T>
+void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+template <class T>
+void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
+template <class T>
+void fine_assemble(const FineOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* M, hipStream_t s);
+template <class T> void fine_export_vectors(const Geom& g, int n, const cx<T>* in, double* canon, hipStream_t s);
+template <class T> void fine_import_vectors(const Geom& g, int n, const double* canon, cx<T>* out, hipStream_t s);
+// draw n complex N(0,1) fine spinors from the counter-based generator
+template <class T> void fine_random(const Geom& g, int n, unsigned long long seed, int stream_id, cx<T>* out, hipStream_t s);
+
+// ---- coarse levels (dd_coarse.hip) ----------------------------------------
+enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
+// out(x) = [post Minv] ( self_mode(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
+// for the sites of parity `par` (0, 1) or all sites (par < 0).
+template <class T>
+void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
+                  bool post_inv, cx<T>* out, hipStream_t s);
+template <class T> void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s);
+template <class T> void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s);
+template <class T> void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s);
+template <class T> void coarse_export_blocks(const Geom& g, int nd, int nslot, const cx<T>* in, double* canon, hipStream_t s);
+template <class T> void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s);
+template <class T>
+void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+                     hipStream_t s);
+template <class T>
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+template <class T>
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+template <class T>
+void coarse_gram_schmidt(const AggMap& m, int ndf, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
+template <class T>
+void coarse_assemble(const CoarseOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* Mc, hipStream_t s);
+template <class T> void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int stream_id, cx<T>* out, hipStream_t s);
+
+// ---- vector algebra (dd_blas.hip) -----------------------------------------
+// lengths are in complex entries
+template <class D, class S> void vec_convert(long n, const cx<S>* in, cx<D>* out, hipStream_t s);
+template <class T> void vec_axpy(long n, cx<double> a, const cx<T>* x, cx<T>* y, hipStream_t s);   // y += a x
+template <class T> void vec_xpay(long n, const cx<T>* x, cx<double> a, cx<T>* y, hipStream_t s);   // y = x + a y
+template <class T> void vec_scale(long n, cx<double> a, cx<T>* x, hipStream_t s);
+template <class T> void vec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, hipStream_t s); // out = a - b
+// out[i] = V_i^H w for i < m, V_i = V + i*ldv ; results in FP64 on the device.
+// `work` must hold reduce_work_size(m) bytes; `count` is an int zeroed once.
+size_t reduce_work_size(int m);
+template <class T>
+void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work, int* count,
+                  hipStream_t s);
+// w -= sum_i h_i V_i (h in FP64 on the device), then out[0].re = ||w||^2
+template <class T>
+void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
+                     void* work, int* count, hipStream_t s);
+// x += sum_i y_i Z_i (y in FP64 on the device)
+template <class T, class X>
+void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s);
+template <class T>
+void vec_finite_check(long n, const cx<T>* x, int* bad, hipStream_t s);
+
+}  // namespace dd

@@ -1,0 +1,1196 @@
+// dd_runtime.hip -- host runtime and C-ABI of the MI355X DD-alpha-AMG solver.
+//
+//   hierarchy ........ levels, standard aggregation, SAP block colouring (Sec. 2.3, 3.2)
+//   outer solver ..... FGMRES(n_kv) in FP64, right-preconditioned by one V-cycle (Sec. 4.2)
+//   V-cycle .......... C^(nu): restrict, coarse solve, prolong, nu SAP sweeps (eq. iterationmatrix)
+//   coarsest solver .. odd-even preconditioned restarted GMRES (Sec. 5)
+//   middle levels .... FGMRES preconditioned by the next V-cycle (recursive two-level method)
+//   setup ............ Algorithm 2, DD-alpha-AMG-setup(n_inv, nu), level by level
+//
+// Krylov vectors live on the device; the small Hessenberg least-squares
+// problem (Givens rotations) is solved on the host in FP64 from the inner
+// products the reduction kernels return, one transfer per Arnoldi step.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ddamg.h"
+#include "dd_kernels.h"
+
+using namespace dd;
+using zc = std::complex<double>;
+
+namespace {
+
+struct DdError {
+    dd_status code;
+    std::string msg;
+};
+
+#define HIPX(call)                                                                                    \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            throw DdError{e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EDEVICE,                          \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};                        \
+    } while (0)
+
+static void fail(dd_status c, const std::string& m) { throw DdError{c, m}; }
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// device allocation registry of one context
+struct Arena {
+    std::vector<void*> ptrs;
+    long long bytes = 0;
+    void* alloc(size_t n) {
+        void* p = nullptr;
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(DD_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        ptrs.push_back(p);
+        bytes += (long long)n;
+        return p;
+    }
+    template <class X> X* get(size_t count) { return reinterpret_cast<X*>(alloc(sizeof(X) * count)); }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+    ~Arena() { release(); }
+};
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static Geom make_geom(const int d[4], const int b[4]) {
+    Geom g;
+    long vol = 1, bvol = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        g.d[mu] = d[mu];
+        g.b[mu] = b[mu];
+        g.lb[mu] = ilog2(b[mu]);
+        g.nb[mu] = d[mu] / b[mu];
+        vol *= d[mu];
+        bvol *= b[mu];
+    }
+    g.bvh = (int)(bvol / 2);
+    g.lbvh = ilog2(g.bvh);
+    g.vh = (int)(vol / 2);
+    g.nblk = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
+    return g;
+}
+
+// layout/SAP block validity: powers of two, dividing, 2-colourable block grid
+static bool valid_layout(const int d[4], const int b[4], bool need_b3_even) {
+    for (int mu = 0; mu < 4; mu++) {
+        if (!is_pow2(b[mu]) || d[mu] % b[mu]) return false;
+        int n = d[mu] / b[mu];
+        if (n != 1 && (n & 1)) return false;
+        if (b[mu] < 2) return false;
+    }
+    (void)need_b3_even;
+    return true;
+}
+
+// Givens-rotation state of one (F)GMRES cycle (host, FP64)
+struct Hess {
+    int m;
+    std::vector<zc> H, cs, sn, g, y;
+    explicit Hess(int m_) : m(m_), H((m_ + 1) * m_), cs(m_), sn(m_), g(m_ + 1), y(m_) {}
+    void reset(double beta) {
+        std::fill(H.begin(), H.end(), zc(0));
+        std::fill(g.begin(), g.end(), zc(0));
+        g[0] = beta;
+    }
+    zc& h(int i, int j) { return H[i * m + j]; }
+    // column j holds h(0..j, j) and h(j+1, j); returns the new residual estimate
+    double rotate(int j) {
+        for (int i = 0; i < j; i++) {
+            zc a = h(i, j), b = h(i + 1, j);
+            h(i, j) = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
+            h(i + 1, j) = -sn[i] * a + cs[i] * b;
+        }
+        zc a = h(j, j), b = h(j + 1, j);
+        double den = std::sqrt(std::norm(a) + std::norm(b));
+        if (den == 0.0) { cs[j] = 1; sn[j] = 0; }
+        else { cs[j] = a / den; sn[j] = b / den; }
+        h(j, j) = std::conj(cs[j]) * a + std::conj(sn[j]) * b;
+        h(j + 1, j) = 0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = std::conj(cs[j]) * g[j];
+        return std::abs(g[j + 1]);
+    }
+    void solve(int k) {
+        for (int i = k - 1; i >= 0; i--) {
+            zc s = g[i];
+            for (int q = i + 1; q < k; q++) s -= h(i, q) * y[q];
+            y[i] = s / h(i, i);
+        }
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct HierBase {
+    virtual ~HierBase() {}
+};
+
+template <class T> struct Hier;
+
+struct dd_ctx {
+    hipStream_t s = nullptr;
+    int dims[4];
+    long vol = 0;
+    double m0 = 0, csw = 0;
+    std::string err;
+    Arena fields;        // gauge/clover (survive reconfiguration)
+    Arena levels;        // hierarchy buffers
+    double* gauge_canon = nullptr;
+    double* clover_canon = nullptr;
+    // FP64 fine operator (outer solver) in the current layout
+    Geom g0;
+    cx<double>* U64 = nullptr;
+    double* clov64 = nullptr;
+    double* clovinv64 = nullptr;
+    // FP32 copies for the preconditioner
+    cx<float>* U32 = nullptr;
+    float* clov32 = nullptr;
+    float* clovinv32 = nullptr;
+    int* dflags = nullptr;          // device ints: [0] bad, [1] reduction ticket, [2..] spare
+    cx<double>* dred = nullptr;     // device reduction results
+    void* dwork = nullptr;          // reduction partials
+    cx<double>* hred = nullptr;     // pinned host mirror of dred
+    dd_params p;
+    bool configured = false, have_setup = false;
+    std::unique_ptr<Hier<double>> H64;
+    std::unique_ptr<Hier<float>> H32;
+    double last_setup_s = 0;
+    // FP64 outer workspace
+    int outer_m = 0;
+    cx<double>* oV = nullptr;  // [m+1][n]
+    cx<double>* ob = nullptr;
+    cx<double>* ox = nullptr;
+    cx<double>* ot = nullptr;
+    ~dd_ctx();
+};
+
+static const int RED_SLOTS = 4 * 34;  // 2 x (32 + 2) results
+
+static void sync(dd_ctx* C) { HIPX(hipStreamSynchronize(C->s)); }
+
+static int read_flag(dd_ctx* C, int idx) {
+    int v = 0;
+    HIPX(hipMemcpyAsync(&v, C->dflags + idx, sizeof(int), hipMemcpyDeviceToHost, C->s));
+    sync(C);
+    return v;
+}
+static void clear_flag(dd_ctx* C, int idx) { HIPX(hipMemsetAsync(C->dflags + idx, 0, sizeof(int), C->s)); }
+
+// ---------------------------------------------------------------------------
+// level hierarchy in preconditioner precision T
+// ---------------------------------------------------------------------------
+template <class T>
+struct Hier : HierBase {
+    dd_ctx* C;
+    int nlev;
+    Geom g[DD_MAXLEV];
+    int nd[DD_MAXLEV];
+    FineOp<T> op0;
+    CoarseOp<T> cop[DD_MAXLEV];
+    int* blocks[DD_MAXLEV][2];
+    int nblocks[DD_MAXLEV][2];
+    AggMap amap[DD_MAXLEV];
+    int N[DD_MAXLEV];
+    cx<T>* tv[DD_MAXLEV];
+    cx<T>* P[DD_MAXLEV];
+    cx<T>* M[DD_MAXLEV];
+    cx<T>* Minv[DD_MAXLEV];
+    // per-level work vectors (full level vectors)
+    cx<T>* rc[DD_MAXLEV];   // restricted residual on level l (l >= 1)
+    cx<T>* ec[DD_MAXLEV];   // coarse correction on level l (l >= 1)
+    cx<T>* wa[DD_MAXLEV];   // scratch
+    cx<T>* wb[DD_MAXLEV];
+    cx<T>* wc[DD_MAXLEV];
+    // Krylov workspaces: coarsest GMRES and middle-level FGMRES
+    cx<T>* kV[DD_MAXLEV];
+    cx<T>* kZ[DD_MAXLEV];
+    long coarse_count[DD_MAXLEV];
+
+    long nlv(int l) const { return 2L * g[l].vh * nd[l]; }   // complex entries of a level vector
+
+    Hier(dd_ctx* c) : C(c) {
+        memset(blocks, 0, sizeof blocks);
+        memset(nblocks, 0, sizeof nblocks);
+        memset(tv, 0, sizeof tv);
+        memset(P, 0, sizeof P);
+        memset(M, 0, sizeof M);
+        memset(Minv, 0, sizeof Minv);
+        memset(coarse_count, 0, sizeof coarse_count);
+    }
+
+    void build_geometry();
+    void sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start);
+    void apply_D(int l, const cx<T>* in, cx<T>* out);
+    void restrict_(int l, const cx<T>* in, cx<T>* out);
+    void prolong(int l, const cx<T>* in, cx<T>* out);
+    void schur(int l, const cx<T>* v, cx<T>* out);
+    long gmres_oe(int l, const cx<T>* r, cx<T>* e);
+    long fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e);
+    void vcycle(int l, int bottom, const cx<T>* r, cx<T>* z);
+    void build(int l);
+    void setup_level(int l, bool given);
+    double norm(long n, const cx<T>* v);
+};
+
+dd_ctx::~dd_ctx() {
+    H64.reset();
+    H32.reset();
+    levels.release();
+    fields.release();
+    if (hred) (void)hipHostFree(hred);
+}
+
+// ---------------------------------------------------------------------------
+// fine fields: layout import, clover
+// ---------------------------------------------------------------------------
+static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, const double* clover_src) {
+    // gauge_src / clover_src are device canonical arrays that stay valid during the call
+    Arena fresh;
+    double* gcanon = fresh.get<double>((size_t)C->vol * 72);
+    HIPX(hipMemcpyAsync(gcanon, gauge_src, sizeof(double) * C->vol * 72, hipMemcpyDeviceToDevice, C->s));
+    double* ccanon = nullptr;
+    if (clover_src) {
+        ccanon = fresh.get<double>((size_t)C->vol * 144);
+        HIPX(hipMemcpyAsync(ccanon, clover_src, sizeof(double) * C->vol * 144, hipMemcpyDeviceToDevice, C->s));
+    }
+    Geom g = make_geom(C->dims, b);
+    cx<double>* U64 = fresh.get<cx<double>>((size_t)C->vol * 36);
+    double* clov = fresh.get<double>((size_t)C->vol * 72);
+    double* clovinv = fresh.get<double>((size_t)C->vol * 72);
+    cx<float>* U32 = fresh.get<cx<float>>((size_t)C->vol * 36);
+    float* clov32 = fresh.get<float>((size_t)C->vol * 72);
+    float* clovinv32 = fresh.get<float>((size_t)C->vol * 72);
+    int* flags = fresh.get<int>(16);
+    HIPX(hipMemsetAsync(flags, 0, sizeof(int) * 16, C->s));
+    fine_import_gauge<double>(g, gcanon, U64, C->s);
+    fine_import_gauge<float>(g, gcanon, U32, C->s);
+    if (ccanon) fine_clover_from_user(g, ccanon, C->m0, clov, clovinv, flags, C->s);
+    else fine_clover_from_links(g, U64, C->m0, C->csw, clov, clovinv, flags, C->s);
+    vec_convert<float, double>((long)C->vol * 36, reinterpret_cast<const cx<double>*>(clov),
+                               reinterpret_cast<cx<float>*>(clov32), C->s);
+    vec_convert<float, double>((long)C->vol * 36, reinterpret_cast<const cx<double>*>(clovinv),
+                               reinterpret_cast<cx<float>*>(clovinv32), C->s);
+    HIPX(hipGetLastError());
+    int bad = 0;
+    HIPX(hipMemcpyAsync(&bad, flags, sizeof(int), hipMemcpyDeviceToHost, C->s));
+    HIPX(hipStreamSynchronize(C->s));
+    // swap arenas
+    C->fields.release();
+    C->fields.ptrs.swap(fresh.ptrs);
+    C->fields.bytes = fresh.bytes;
+    fresh.bytes = 0;
+    C->gauge_canon = gcanon;
+    C->clover_canon = ccanon;
+    C->g0 = g;
+    C->U64 = U64; C->clov64 = clov; C->clovinv64 = clovinv;
+    C->U32 = U32; C->clov32 = clov32; C->clovinv32 = clovinv32;
+    C->dflags = flags;
+    C->dred = C->fields.get<cx<double>>(RED_SLOTS);
+    C->dwork = C->fields.alloc(reduce_work_size(34));
+    if (bad) fail(DD_ENUMERIC, "singular clover block on " + std::to_string(bad) + " sites");
+}
+
+template <class T> static FineOp<T> fine_op(dd_ctx* C);
+template <> FineOp<double> fine_op<double>(dd_ctx* C) { return FineOp<double>{C->g0, C->U64, C->clov64, C->clovinv64}; }
+template <> FineOp<float> fine_op<float>(dd_ctx* C) { return FineOp<float>{C->g0, C->U32, C->clov32, C->clovinv32}; }
+
+// ---------------------------------------------------------------------------
+// hierarchy geometry and buffers
+// ---------------------------------------------------------------------------
+template <class T>
+void Hier<T>::build_geometry() {
+    const dd_params& p = C->p;
+    nlev = p.levels;
+    Arena& A = C->levels;
+    g[0] = C->g0;
+    nd[0] = 12;
+    op0 = fine_op<T>(C);
+    int d[4];
+    memcpy(d, C->dims, sizeof d);
+    for (int l = 0; l < nlev; l++) {
+        if (l > 0) {
+            int b[4];
+            bool has_sap = (l < nlev - 1);
+            for (int mu = 0; mu < 4; mu++) b[mu] = has_sap ? p.sap[l][mu] : 2;
+            if (!valid_layout(d, b, false))
+                fail(DD_EINVAL, "level " + std::to_string(l) + ": lattice/blocks not supported (coarse extents must be even, "
+                                "SAP blocks powers of two with an even block count per dimension)");
+            g[l] = make_geom(d, b);
+            nd[l] = 2 * p.n_tv[l - 1];
+            M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
+            Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
+            cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l]};
+            rc[l] = A.get<cx<T>>(nlv(l));
+            ec[l] = A.get<cx<T>>(nlv(l));
+        }
+        wa[l] = A.get<cx<T>>(nlv(l));
+        wb[l] = A.get<cx<T>>(nlv(l));
+        wc[l] = A.get<cx<T>>(nlv(l));
+        if (l < nlev - 1) {
+            // SAP block lists by colour (red = even sum of block coordinates)
+            std::vector<int> lists[2];
+            const Geom& G = g[l];
+            for (int bi = 0; bi < G.nblk; bi++) {
+                int r = bi, bc3 = r % G.nb[3]; r /= G.nb[3];
+                int bc2 = r % G.nb[2]; r /= G.nb[2];
+                int bc1 = r % G.nb[1], bc0 = r / G.nb[1];
+                lists[(bc0 + bc1 + bc2 + bc3) & 1].push_back(bi);
+            }
+            for (int c = 0; c < 2; c++) {
+                nblocks[l][c] = (int)lists[c].size();
+                blocks[l][c] = A.get<int>(lists[c].size() + 1);
+                if (!lists[c].empty())
+                    HIPX(hipMemcpyAsync(blocks[l][c], lists[c].data(), sizeof(int) * lists[c].size(), hipMemcpyHostToDevice, C->s));
+            }
+            if (l > 0 && g[l].bvh * nd[l] > 1024) fail(DD_EINVAL, "coarse SAP block too large for one workgroup");
+            // aggregation onto level l+1
+            int a[4], dc[4];
+            for (int mu = 0; mu < 4; mu++) {
+                a[mu] = p.agg[l][mu];
+                if (a[mu] <= 0 || d[mu] % a[mu]) fail(DD_EINVAL, "aggregates do not divide level " + std::to_string(l));
+                dc[mu] = d[mu] / a[mu];
+                if (dc[mu] < 2 || (dc[mu] & 1)) fail(DD_EINVAL, "coarse lattice extents must be even (level " + std::to_string(l + 1) + ")");
+            }
+            N[l] = p.n_tv[l];
+            if (N[l] < 1 || N[l] > 32) fail(DD_EINVAL, "n_tv must be in 1..32");
+            int asz = a[0] * a[1] * a[2] * a[3];
+            if (asz > 1024 || (l > 0 && asz * nd[l] > 1024)) fail(DD_EINVAL, "aggregate too large for one workgroup");
+            amap[l].f = g[l];
+            amap[l].asz = asz;
+            memcpy(amap[l].a, a, sizeof a);
+            tv[l] = A.get<cx<T>>((size_t)N[l] * nlv(l));
+            P[l] = A.get<cx<T>>((size_t)N[l] * nlv(l));
+            memcpy(d, dc, sizeof d);
+        }
+    }
+    for (int l = 0; l + 1 < nlev; l++) amap[l].c = g[l + 1];
+    // Krylov workspaces
+    for (int l = 1; l < nlev; l++) {
+        int m = (l == nlev - 1) ? C->p.coarse_restart : C->p.mid_restart;
+        kV[l] = A.get<cx<T>>((size_t)(m + 1) * nlv(l));
+        kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)m * nlv(l)) : nullptr;
+    }
+    HIPX(hipStreamSynchronize(C->s));
+}
+
+// ---------------------------------------------------------------------------
+// elementary steps
+// ---------------------------------------------------------------------------
+template <class T>
+double Hier<T>::norm(long n, const cx<T>* v) {
+    vec_multidot<T>(n, 1, v, 0, v, C->dred, C->dwork, C->dflags + 1, C->s);
+    HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>), hipMemcpyDeviceToHost, C->s));
+    sync(C);
+    return std::sqrt(C->hred[0].re);
+}
+
+template <class T>
+void Hier<T>::apply_D(int l, const cx<T>* in, cx<T>* out) {
+    if (l == 0) fine_dirac<T>(op0, in, out, C->s);
+    else coarse_apply<T>(cop[l], -1, CS_SELF, in, 1, in, false, out, C->s);
+}
+
+// nsweeps SAP iterations on level l (red blocks, then black blocks)
+template <class T>
+void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start) {
+    if (zero_start) HIPX(hipMemsetAsync(z, 0, sizeof(cx<T>) * nlv(l), C->s));
+    for (int sw = 0; sw < nsweeps; sw++)
+        for (int c = 0; c < 2; c++) {
+            if (l == 0) fine_sap_half<T>(op0, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s);
+            else coarse_sap_half<T>(cop[l], blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s);
+        }
+}
+
+template <class T>
+void Hier<T>::restrict_(int l, const cx<T>* in, cx<T>* out) {
+    if (l == 0) fine_restrict<T>(amap[0], N[0], P[0], in, out, C->s);
+    else coarse_restrict<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
+}
+
+template <class T>
+void Hier<T>::prolong(int l, const cx<T>* in, cx<T>* out) {
+    if (l == 0) fine_prolong<T>(amap[0], N[0], P[0], in, out, C->s);
+    else coarse_prolong<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
+}
+
+// out_o = (A_oo - D_oe A_ee^{-1} D_eo) v_o ; even part of out = 0
+template <class T>
+void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out) {
+    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s);
+    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s);
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: odd-even GMRES(m) to relative residual coarse_tol (Sec. 5)
+// ---------------------------------------------------------------------------
+template <class T>
+long Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e) {
+    const dd_params& p = C->p;
+    const int m = p.coarse_restart;
+    const long nfull = nlv(l), nh = (long)g[l].vh * nd[l];
+    cx<T>* V = kV[l];
+    cx<T>* f = wa[l];
+    cx<T>* t = wb[l];
+    auto odd = [&](cx<T>* v) { return v + nh; };
+    // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
+    coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s);
+    coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s);
+    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull, C->s));
+    double fnorm = norm(nh, odd(f));
+    long its = 0;
+    const long fixed = p.coarse_fixed;
+    Hess hs(m);
+    if (fnorm > 0) {
+        // V_0 = residual of the Schur system
+        HIPX(hipMemcpyAsync(odd(V), odd(f), sizeof(cx<T>) * nh, hipMemcpyDeviceToDevice, C->s));
+        double beta = fnorm;
+        for (;;) {
+            hs.reset(beta);
+            vec_scale<T>(nh, cx<double>{1.0 / beta, 0.0}, odd(V), C->s);
+            int jend = 0;
+            bool stop = false;
+            for (int j = 0; j < m; j++) {
+                cx<T>* w = V + (size_t)(j + 1) * nfull;
+                schur(l, V + (size_t)j * nfull, w);
+                vec_multidot<T>(nh, j + 1, odd(V), nfull, odd(w), C->dred, C->dwork, C->dflags + 1, C->s);
+                vec_update_norm<T>(nh, j + 1, odd(V), nfull, C->dred, odd(w), C->dred + 33, C->dwork, C->dflags + 1, C->s);
+                HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 34, hipMemcpyDeviceToHost, C->s));
+                sync(C);
+                for (int i = 0; i <= j; i++) hs.h(i, j) = zc(C->hred[i].re, C->hred[i].im);
+                double hn = std::sqrt(C->hred[33].re);
+                hs.h(j + 1, j) = hn;
+                double res = hs.rotate(j);
+                its++;
+                jend = j + 1;
+                if (hn > 0) vec_scale<T>(nh, cx<double>{1.0 / hn, 0.0}, odd(w), C->s);
+                if (fixed > 0) { if (its >= fixed) { stop = true; break; } }
+                else if (res <= p.coarse_tol * fnorm || its >= p.coarse_maxit) { stop = true; break; }
+                if (hn == 0) { stop = true; break; }
+            }
+            hs.solve(jend);
+            std::vector<cx<double>> y(jend);
+            for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
+            HIPX(hipMemcpyAsync(C->dred + 64, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
+            vec_lincomb<T, T>(nh, jend, odd(V), nfull, C->dred + 64, odd(e), C->s);
+            sync(C);
+            if (stop) break;
+            // restart from the true Schur residual
+            schur(l, e, V);
+            vec_sub<T>(nh, odd(f), odd(V), odd(V), C->s);
+            beta = norm(nh, odd(V));
+            if (beta == 0) break;
+        }
+    }
+    // e_e = A_ee^{-1} (r_e - D_eo e_o)
+    coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s);
+    return its;
+}
+
+// ---------------------------------------------------------------------------
+// middle levels: FGMRES(m) on D_c preconditioned by the V-cycle of level l
+// ---------------------------------------------------------------------------
+template <class T>
+long Hier<T>::fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e) {
+    const dd_params& p = C->p;
+    const int m = p.mid_restart;
+    const long n = nlv(l);
+    cx<T>* V = kV[l];
+    cx<T>* Z = kZ[l];
+    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * n, C->s));
+    double bnorm = norm(n, r);
+    long its = 0;
+    if (bnorm == 0) return 0;
+    const long fixed = p.mid_fixed;
+    HIPX(hipMemcpyAsync(V, r, sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, C->s));
+    double beta = bnorm;
+    Hess hs(m);
+    for (;;) {
+        if (beta <= p.mid_tol * bnorm) break;
+        if (fixed > 0 ? its >= fixed : its >= p.mid_maxit) break;
+        hs.reset(beta);
+        vec_scale<T>(n, cx<double>{1.0 / beta, 0.0}, V, C->s);
+        int jend = 0;
+        for (int j = 0; j < m; j++) {
+            cx<T>* w = V + (size_t)(j + 1) * n;
+            vcycle(l, bottom, V + (size_t)j * n, Z + (size_t)j * n);
+            apply_D(l, Z + (size_t)j * n, w);
+            vec_multidot<T>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
+            vec_update_norm<T>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
+            vec_multidot<T>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
+            vec_update_norm<T>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+            HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
+            sync(C);
+            for (int i = 0; i <= j; i++)
+                hs.h(i, j) = zc(C->hred[i].re + C->hred[34 + i].re, C->hred[i].im + C->hred[34 + i].im);
+            double hn = std::sqrt(C->hred[67].re);
+            hs.h(j + 1, j) = hn;
+            double res = hs.rotate(j);
+            its++;
+            jend = j + 1;
+            if (hn > 0) vec_scale<T>(n, cx<double>{1.0 / hn, 0.0}, w, C->s);
+            if (fixed > 0) { if (its >= fixed) break; }
+            else if (res <= p.mid_tol * bnorm || its >= p.mid_maxit) break;
+            if (hn == 0) break;
+        }
+        hs.solve(jend);
+        std::vector<cx<double>> y(jend);
+        for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
+        HIPX(hipMemcpyAsync(C->dred + 70, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
+        vec_lincomb<T, T>(n, jend, Z, n, C->dred + 70, e, C->s);
+        // true residual for the restart decision
+        apply_D(l, e, V);
+        vec_sub<T>(n, r, V, V, C->s);
+        beta = norm(n, V);
+        if (fixed > 0 && its >= fixed) break;
+    }
+    return its;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle: z = P e_c with e_c ~ D_c^{-1} P^H r, then nu SAP iterations
+// ---------------------------------------------------------------------------
+template <class T>
+void Hier<T>::vcycle(int l, int bottom, const cx<T>* r, cx<T>* z) {
+    restrict_(l, r, rc[l + 1]);
+    long its;
+    if (l + 1 == bottom) its = gmres_oe(l + 1, rc[l + 1], ec[l + 1]);
+    else its = fgmres_mid(l + 1, bottom, rc[l + 1], ec[l + 1]);
+    coarse_count[l + 1] += its;
+    prolong(l, ec[l + 1], z);
+    sap(l, r, z, C->p.nu, false);
+}
+
+// ---------------------------------------------------------------------------
+// P, D_c and self-block inverses from the current test vectors of level l
+// ---------------------------------------------------------------------------
+template <class T>
+void Hier<T>::build(int l) {
+    clear_flag(C, 0);
+    if (l == 0) fine_gram_schmidt<T>(amap[0], N[0], tv[0], P[0], C->dflags, C->s);
+    else coarse_gram_schmidt<T>(amap[l], nd[l], N[l], tv[l], P[l], C->dflags, C->s);
+    HIPX(hipGetLastError());
+    if (read_flag(C, 0)) fail(DD_ENUMERIC, "rank-deficient aggregate on level " + std::to_string(l));
+    if (l == 0) fine_assemble<T>(op0, amap[0], N[0], P[0], M[1], C->s);
+    else coarse_assemble<T>(cop[l], amap[l], N[l], P[l], M[l + 1], C->s);
+    HIPX(hipGetLastError());
+    coarse_self_inverse<T>(g[l + 1], nd[l + 1], M[l + 1], Minv[l + 1], C->dflags, C->s);
+    HIPX(hipGetLastError());
+    if (read_flag(C, 0)) fail(DD_ENUMERIC, "singular coarse self block on level " + std::to_string(l + 1));
+}
+
+// Algorithm 2 on level l with level l+1 as the coarsest level of its V-cycles.
+// Readings: vectors normalised after each of the three initial SAP passes; P
+// and D_c rebuilt from the final vectors.
+template <class T>
+void Hier<T>::setup_level(int l, bool given) {
+    const long n = nlv(l);
+    if (!given) {
+        if (l == 0) fine_random<T>(g[0], N[0], C->p.seed, l, tv[0], C->s);
+        else coarse_random<T>(g[l], nd[l], N[l], C->p.seed, l, tv[l], C->s);
+    }
+    for (int eta = 1; eta <= 3; eta++)
+        for (int j = 0; j < N[l]; j++) {
+            cx<T>* v = tv[l] + (size_t)j * n;
+            sap(l, v, wa[l], eta, true);
+            double nv = norm(n, wa[l]);
+            if (!(nv > 0) || !std::isfinite(nv)) fail(DD_ENUMERIC, "setup: vanishing or non-finite test vector");
+            HIPX(hipMemcpyAsync(v, wa[l], sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, C->s));
+            vec_scale<T>(n, cx<double>{1.0 / nv, 0.0}, v, C->s);
+        }
+    for (int it = 0; it < C->p.n_inv; it++) {
+        build(l);
+        for (int j = 0; j < N[l]; j++) {
+            cx<T>* v = tv[l] + (size_t)j * n;
+            apply_D(l, v, wa[l]);
+            vec_sub<T>(n, v, wa[l], wa[l], C->s);
+            vcycle(l, l + 1, wa[l], wb[l]);
+            vec_axpy<T>(n, cx<double>{1.0, 0.0}, wb[l], v, C->s);
+            double nv = norm(n, v);
+            if (!(nv > 0) || !std::isfinite(nv)) fail(DD_ENUMERIC, "setup: vanishing or non-finite test vector");
+            vec_scale<T>(n, cx<double>{1.0 / nv, 0.0}, v, C->s);
+        }
+    }
+    build(l);
+}
+
+static double norm64(dd_ctx* C, long n, const cx<double>* v) {
+    vec_multidot<double>(n, 1, v, 0, v, C->dred, C->dwork, C->dflags + 1, C->s);
+    HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>), hipMemcpyDeviceToHost, C->s));
+    sync(C);
+    return std::sqrt(C->hred[0].re);
+}
+
+// ---------------------------------------------------------------------------
+// outer FGMRES in FP64 with the T-precision V-cycle as right preconditioner
+// ---------------------------------------------------------------------------
+template <class T>
+static dd_status outer_fgmres(dd_ctx* C, Hier<T>& H, const cx<double>* b, cx<double>* x, double tol, long fixed,
+                              dd_stats* st) {
+    const dd_params& p = C->p;
+    const int m = p.outer_restart;
+    const long n = 24L * C->g0.vh;
+    FineOp<double> op = fine_op<double>(C);
+    cx<double>* V = C->oV;
+    cx<T>* Z = reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * n);
+    cx<T>* vT = reinterpret_cast<cx<T>*>(C->ot);  // preconditioner-precision copy of v_j
+    cx<double>* t64 = C->ot + n;
+    memset(H.coarse_count, 0, sizeof H.coarse_count);
+    HIPX(hipMemsetAsync(x, 0, sizeof(cx<double>) * n, C->s));
+    clear_flag(C, 0);
+    vec_finite_check<double>(n, b, C->dflags, C->s);
+    if (read_flag(C, 0)) fail(DD_ENUMERIC, "NaN/Inf in the right-hand side");
+    double bnorm = norm64(C, n, b);
+    long its = 0;
+    int restarts = 0;
+    bool conv = false;
+    double relres = 1.0;
+    if (bnorm == 0) {
+        conv = true;
+        relres = 0;
+    } else {
+        HIPX(hipMemcpyAsync(V, b, sizeof(cx<double>) * n, hipMemcpyDeviceToDevice, C->s));
+        double beta = bnorm;
+        Hess hs(m);
+        for (;;) {
+            relres = beta / bnorm;
+            if (beta <= tol * bnorm) { conv = true; break; }
+            if (fixed > 0 ? its >= fixed : its >= p.outer_maxit) break;
+            hs.reset(beta);
+            vec_scale<double>(n, cx<double>{1.0 / beta, 0.0}, V, C->s);
+            int jend = 0;
+            for (int j = 0; j < m; j++) {
+                cx<double>* vj = V + (size_t)j * n;
+                cx<double>* w = V + (size_t)(j + 1) * n;
+                cx<T>* zj = Z + (size_t)j * n;
+                vec_convert<T, double>(n, vj, vT, C->s);
+                H.vcycle(0, H.nlev - 1, vT, zj);
+                vec_convert<double, T>(n, zj, t64, C->s);
+                fine_dirac<double>(op, t64, w, C->s);
+                vec_multidot<double>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
+                vec_update_norm<double>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
+                vec_multidot<double>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
+                vec_update_norm<double>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+                HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
+                sync(C);
+                for (int i = 0; i <= j; i++)
+                    hs.h(i, j) = zc(C->hred[i].re + C->hred[34 + i].re, C->hred[i].im + C->hred[34 + i].im);
+                double hn = std::sqrt(C->hred[67].re);
+                if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
+                hs.h(j + 1, j) = hn;
+                double res = hs.rotate(j);
+                its++;
+                jend = j + 1;
+                if (hn > 0) vec_scale<double>(n, cx<double>{1.0 / hn, 0.0}, w, C->s);
+                if (fixed > 0) { if (its >= fixed) break; }
+                else if (res <= tol * bnorm || its >= p.outer_maxit) break;
+                if (hn == 0) break;
+            }
+            hs.solve(jend);
+            std::vector<cx<double>> y(jend);
+            for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
+            HIPX(hipMemcpyAsync(C->dred + 70, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
+            vec_lincomb<T, double>(n, jend, Z, n, C->dred + 70, x, C->s);
+            // true residual in FP64 decides convergence; it is also the restart vector
+            fine_dirac<double>(op, x, t64, C->s);
+            vec_sub<double>(n, b, t64, V, C->s);
+            beta = norm64(C, n, V);
+            relres = beta / bnorm;
+            if (fixed > 0 && its >= fixed) { conv = beta <= tol * bnorm; break; }
+            restarts++;
+        }
+    }
+    if (st) {
+        st->outer_iters = (int)its;
+        st->restarts = restarts;
+        for (int l = 0; l < DD_MAXLEV; l++) st->coarse_iters[l] = H.coarse_count[l];
+        st->true_relres = relres;
+        st->converged = conv ? 1 : 0;
+    }
+    return conv ? DD_OK : DD_ENOCONV;
+}
+
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+static std::string g_create_error;
+
+#define ABI_TRY(ctx)                    \
+    if (!(ctx)) return DD_EINVAL;       \
+    try {
+#define ABI_END(ctx)                                  \
+    }                                                 \
+    catch (const DdError& e) {                        \
+        (ctx)->err = e.msg;                           \
+        return e.code;                                \
+    }                                                 \
+    catch (const std::exception& e) {                 \
+        (ctx)->err = e.what();                        \
+        return DD_EDEVICE;                            \
+    }
+
+// The public functions below were declared with C linkage in ddamg.h.
+
+void dd_default_params(dd_params* p) {
+    memset(p, 0, sizeof *p);
+    p->levels = 2;
+    for (int l = 0; l < DD_MAXLEV; l++) {
+        p->n_tv[l] = 20;
+        p->mr_steps[l] = 4;
+        for (int mu = 0; mu < 4; mu++) {
+            p->agg[l][mu] = (l == 0) ? 4 : 2;
+            p->sap[l][mu] = (l == 0) ? 4 : 2;
+        }
+    }
+    p->nu = 2;
+    p->n_inv = 6;
+    p->coarse_tol = 5e-2;
+    p->coarse_restart = 30;
+    p->coarse_maxit = 1000;
+    p->coarse_fixed = 0;
+    p->mid_tol = 5e-2;
+    p->mid_restart = 10;
+    p->mid_maxit = 50;
+    p->mid_fixed = 0;
+    p->outer_restart = 25;
+    p->outer_maxit = 2000;
+    p->precision = 64;
+    p->given_vectors = 0;
+    p->seed = 0x5eedULL;
+}
+
+const char* dd_last_error(const dd_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+dd_status dd_create(dd_ctx** out, const int dims[4], const double* gauge, const double* clover, double m0, double csw,
+                    void* hip_stream) {
+    if (!out || !dims || !gauge) {
+        g_create_error = "dd_create: NULL argument";
+        return DD_EINVAL;
+    }
+    *out = nullptr;
+    for (int mu = 0; mu < 4; mu++)
+        if (dims[mu] < 2 || (dims[mu] & 1)) {
+            g_create_error = "dd_create: lattice extents must be even and >= 2";
+            return DD_EINVAL;
+        }
+    dd_ctx* C = new dd_ctx();
+    try {
+        C->s = (hipStream_t)hip_stream;
+        memcpy(C->dims, dims, sizeof(int) * 4);
+        C->vol = (long)dims[0] * dims[1] * dims[2] * dims[3];
+        if (C->vol / 2 > 0x7fffffffL / 24) fail(DD_EINVAL, "lattice too large");
+        C->m0 = m0;
+        C->csw = csw;
+        HIPX(hipHostMalloc((void**)&C->hred, sizeof(cx<double>) * RED_SLOTS, hipHostMallocDefault));
+        int b[4];
+        bool four = true;
+        for (int mu = 0; mu < 4; mu++) { b[mu] = 4; if (dims[mu] % 4 || ((dims[mu] / 4) != 1 && ((dims[mu] / 4) & 1))) four = false; }
+        if (!four) for (int mu = 0; mu < 4; mu++) b[mu] = 2;
+        if (!valid_layout(dims, b, true)) fail(DD_EINVAL, "lattice extents admit no 2-colourable block layout");
+        layout_fields(C, b, gauge, clover);
+        dd_default_params(&C->p);
+    } catch (const DdError& e) {
+        g_create_error = e.msg;
+        delete C;
+        return e.code;
+    }
+    *out = C;
+    return DD_OK;
+}
+
+void dd_destroy(dd_ctx* ctx) { delete ctx; }
+
+static void configure_impl(dd_ctx* C, const dd_params* pin) {
+    dd_params p = *pin;
+    if (p.levels < 2 || p.levels > 3) fail(DD_EINVAL, "levels must be 2 or 3");
+    if (p.precision != 64 && p.precision != 32) fail(DD_EINVAL, "precision must be 64 or 32");
+    if (p.outer_restart < 1 || p.outer_restart > 32 || p.coarse_restart < 1 || p.coarse_restart > 32 || p.mid_restart < 1 ||
+        p.mid_restart > 32)
+        fail(DD_EINVAL, "restart lengths must be in 1..32");
+    if (p.nu < 0 || p.n_inv < 0) fail(DD_EINVAL, "nu and n_inv must be >= 0");
+    if (!valid_layout(C->dims, p.sap[0], true))
+        fail(DD_EINVAL, "SAP blocks must be powers of two dividing the lattice with an even block count (or 1) per dimension");
+    if (p.sap[0][0] * p.sap[0][1] * p.sap[0][2] * p.sap[0][3] > 256) fail(DD_EINVAL, "fine SAP blocks hold at most 256 sites");
+    C->H64.reset();
+    C->H32.reset();
+    C->levels.release();
+    C->configured = false;
+    C->have_setup = false;
+    C->p = p;
+    // re-layout the fine fields if the SAP blocks differ from the current layout
+    bool same = true;
+    for (int mu = 0; mu < 4; mu++) same = same && (C->g0.b[mu] == p.sap[0][mu]);
+    if (!same) layout_fields(C, p.sap[0], C->gauge_canon, C->clover_canon);
+    // FP64 outer workspace: V (m+1) + Z (m, in preconditioner precision) + 2 temporaries
+    const long n = 24L * C->g0.vh;
+    size_t zbytes = (p.precision == 64) ? sizeof(cx<double>) : sizeof(cx<float>);
+    size_t vbytes = sizeof(cx<double>) * (size_t)(p.outer_restart + 1) * n + zbytes * (size_t)p.outer_restart * n;
+    C->oV = reinterpret_cast<cx<double>*>(C->levels.alloc(vbytes));
+    C->ot = C->levels.get<cx<double>>(2 * (size_t)n);
+    C->ob = C->levels.get<cx<double>>((size_t)n);
+    C->ox = C->levels.get<cx<double>>((size_t)n);
+    C->outer_m = p.outer_restart;
+    if (p.precision == 64) {
+        C->H64.reset(new Hier<double>(C));
+        C->H64->build_geometry();
+    } else {
+        C->H32.reset(new Hier<float>(C));
+        C->H32->build_geometry();
+    }
+    C->configured = true;
+}
+
+dd_status dd_configure(dd_ctx* ctx, const dd_params* p) {
+    ABI_TRY(ctx)
+    dd_params d;
+    if (!p) { dd_default_params(&d); p = &d; }
+    configure_impl(ctx, p);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+template <class T>
+static void setup_all(dd_ctx* C, Hier<T>& H) {
+    for (int l = 0; l + 1 < H.nlev; l++) H.setup_level(l, C->p.given_vectors != 0);
+}
+
+dd_status dd_setup(dd_ctx* ctx, int n_tv, const int block[4], int levels, const dd_params* pin) {
+    ABI_TRY(ctx)
+    double t0 = now_s();
+    dd_params p;
+    if (pin) p = *pin;
+    else dd_default_params(&p);
+    if (n_tv > 0) p.n_tv[0] = n_tv;
+    if (levels > 0) p.levels = levels;
+    if (block)
+        for (int mu = 0; mu < 4; mu++) p.agg[0][mu] = p.sap[0][mu] = block[mu];
+    // given_vectors: the hierarchy was configured (dd_configure) and the initial
+    // test vectors installed (dd_set_test_vectors); its parameters are used as is
+    if (p.given_vectors) {
+        if (!ctx->configured) fail(DD_ESTATE, "given_vectors requires dd_configure + dd_set_test_vectors first");
+        ctx->p.given_vectors = 1;
+    } else {
+        configure_impl(ctx, &p);
+    }
+    if (ctx->H64) setup_all(ctx, *ctx->H64);
+    else setup_all(ctx, *ctx->H32);
+    sync(ctx);
+    ctx->have_setup = true;
+    ctx->last_setup_s = now_s() - t0;
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+template <class T>
+static dd_status solve_impl(dd_ctx* C, Hier<T>& H, const double* b, double* x, double tol, dd_stats* st) {
+    fine_import_spinor<double>(C->g0, b, C->ob, C->s);
+    dd_status rc = outer_fgmres<T>(C, H, C->ob, C->ox, tol, 0, st);
+    fine_export_spinor<double>(C->g0, C->ox, x, C->s);
+    sync(C);
+    return rc;
+}
+
+dd_status dd_solve(dd_ctx* ctx, const double* b, double* x, double tol, dd_stats* st) {
+    ABI_TRY(ctx)
+    if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve before dd_setup");
+    if (!b || !x) fail(DD_EINVAL, "NULL vector");
+    if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
+    double t0 = now_s();
+    dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, b, x, tol, st) : solve_impl(ctx, *ctx->H32, b, x, tol, st);
+    if (st) {
+        st->solve_s = now_s() - t0;
+        st->setup_s = ctx->last_setup_s;
+    }
+    if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit";
+    return rc;
+    ABI_END(ctx)
+}
+
+dd_status dd_solve_batch(dd_ctx* ctx, int k, const double* b, double* x, double tol, dd_stats* st) {
+    if (!ctx) return DD_EINVAL;
+    if (k < 0) { ctx->err = "k < 0"; return DD_EINVAL; }
+    dd_status worst = DD_OK;
+    for (int q = 0; q < k; q++) {
+        dd_status rc = dd_solve(ctx, b + (size_t)q * 24 * ctx->vol, x + (size_t)q * 24 * ctx->vol, tol, st ? st + q : nullptr);
+        if (rc != DD_OK && worst == DD_OK) worst = rc;
+        if (rc != DD_OK && rc != DD_ENOCONV) return rc;
+    }
+    return worst;
+}
+
+dd_status dd_set_mass(dd_ctx* ctx, double m0) {
+    ABI_TRY(ctx)
+    double dm = m0 - ctx->m0;
+    clear_flag(ctx, 0);
+    fine_clover_shift(ctx->g0, dm, ctx->clov64, ctx->clovinv64, ctx->dflags, ctx->s);
+    vec_convert<float, double>((long)ctx->vol * 36, reinterpret_cast<const cx<double>*>(ctx->clov64),
+                               reinterpret_cast<cx<float>*>(ctx->clov32), ctx->s);
+    vec_convert<float, double>((long)ctx->vol * 36, reinterpret_cast<const cx<double>*>(ctx->clovinv64),
+                               reinterpret_cast<cx<float>*>(ctx->clovinv32), ctx->s);
+    if (read_flag(ctx, 0)) fail(DD_ENUMERIC, "singular clover block after the mass shift");
+    ctx->m0 = m0;
+    auto shift = [&](auto& H) {
+        for (int l = 1; l < H.nlev; l++) {
+            coarse_shift_diag(H.g[l], H.nd[l], dm, H.M[l], ctx->s);
+            coarse_self_inverse(H.g[l], H.nd[l], H.M[l], H.Minv[l], ctx->dflags, ctx->s);
+        }
+    };
+    if (ctx->configured) {
+        if (ctx->H64) shift(*ctx->H64);
+        else shift(*ctx->H32);
+        if (read_flag(ctx, 0)) fail(DD_ENUMERIC, "singular coarse self block after the mass shift");
+    }
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+template <class T>
+static void set_vectors_impl(dd_ctx* C, Hier<T>& H, int l, int n, const double* v) {
+    if (l < 0 || l >= H.nlev - 1) fail(DD_EINVAL, "no transfer on this level");
+    if (n != H.N[l]) fail(DD_EINVAL, "vector count differs from n_tv of the level");
+    if (l == 0) fine_import_vectors<T>(H.g[0], n, v, H.tv[0], C->s);
+    else coarse_import_vector<T>(H.g[l], H.nd[l], n, v, H.tv[l], C->s);
+    sync(C);
+}
+
+dd_status dd_set_test_vectors(dd_ctx* ctx, int level, int n, const double* v) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
+    if (ctx->H64) set_vectors_impl(ctx, *ctx->H64, level, n, v);
+    else set_vectors_impl(ctx, *ctx->H32, level, n, v);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+template <class T>
+static void get_vectors_impl(dd_ctx* C, Hier<T>& H, int l, double* v, bool P) {
+    if (l < 0 || l >= H.nlev - 1) fail(DD_EINVAL, "no transfer on this level");
+    const cx<T>* src = P ? H.P[l] : H.tv[l];
+    if (l == 0) fine_export_vectors<T>(H.g[0], H.N[0], src, v, C->s);
+    else coarse_export_vector<T>(H.g[l], H.nd[l], H.N[l], src, v, C->s);
+    sync(C);
+}
+
+dd_status dd_get_test_vectors(dd_ctx* ctx, int level, double* v) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "not configured");
+    if (ctx->H64) get_vectors_impl(ctx, *ctx->H64, level, v, false);
+    else get_vectors_impl(ctx, *ctx->H32, level, v, false);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_get_P(dd_ctx* ctx, int level, double* out) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "not configured");
+    if (ctx->H64) get_vectors_impl(ctx, *ctx->H64, level, out, true);
+    else get_vectors_impl(ctx, *ctx->H32, level, out, true);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_build_level(dd_ctx* ctx, int level) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
+    auto go = [&](auto& H) {
+        if (level < 0 || level >= H.nlev - 1) fail(DD_EINVAL, "no transfer on this level");
+        H.build(level);
+    };
+    if (ctx->H64) go(*ctx->H64);
+    else go(*ctx->H32);
+    sync(ctx);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_mark_setup(dd_ctx* ctx) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
+    ctx->have_setup = true;
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_get_coarse(dd_ctx* ctx, int level, double* Mout, double* Minvout) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "not configured");
+    auto go = [&](auto& H) {
+        if (level < 1 || level >= H.nlev) fail(DD_EINVAL, "no coarse operator on this level");
+        if (Mout) coarse_export_blocks(H.g[level], H.nd[level], 9, H.M[level], Mout, ctx->s);
+        if (Minvout) coarse_export_blocks(H.g[level], H.nd[level], 1, H.Minv[level], Minvout, ctx->s);
+    };
+    if (ctx->H64) go(*ctx->H64);
+    else go(*ctx->H32);
+    sync(ctx);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_get_clover(dd_ctx* ctx, double* A, double* Ainv) {
+    ABI_TRY(ctx)
+    if (A) fine_clover_export(ctx->g0, ctx->clov64, A, ctx->s);
+    if (Ainv) fine_clover_export(ctx->g0, ctx->clovinv64, Ainv, ctx->s);
+    sync(ctx);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_level_info(const dd_ctx* ctx, int level, int dims[4], int* nd) {
+    if (!ctx) return DD_EINVAL;
+    if (level == 0) {
+        memcpy(dims, ctx->dims, sizeof(int) * 4);
+        *nd = 12;
+        return DD_OK;
+    }
+    const Geom* g = nullptr;
+    int n = 0;
+    if (ctx->H64 && level < ctx->H64->nlev) { g = &ctx->H64->g[level]; n = ctx->H64->nd[level]; }
+    if (ctx->H32 && level < ctx->H32->nlev) { g = &ctx->H32->g[level]; n = ctx->H32->nd[level]; }
+    if (!g) return DD_EINVAL;
+    memcpy(dims, g->d, sizeof(int) * 4);
+    *nd = n;
+    return DD_OK;
+}
+
+long long dd_device_bytes(const dd_ctx* ctx) { return ctx ? ctx->fields.bytes + ctx->levels.bytes : 0; }
+
+template <class T>
+static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const double* in, double* out, long* iters) {
+    if (l < 0 || l >= H.nlev) fail(DD_EINVAL, "level out of range");
+    long its = 0;
+    auto imp = [&](int lev, const double* src, cx<T>* dst) {
+        if (lev == 0) fine_import_spinor<T>(H.g[0], src, dst, C->s);
+        else coarse_import_vector<T>(H.g[lev], H.nd[lev], 1, src, dst, C->s);
+    };
+    auto exp_ = [&](int lev, const cx<T>* src, double* dst) {
+        if (lev == 0) fine_export_spinor<T>(H.g[0], src, dst, C->s);
+        else coarse_export_vector<T>(H.g[lev], H.nd[lev], 1, src, dst, C->s);
+    };
+    const int bottom = H.nlev - 1;
+    switch (op) {
+        case DD_OP_D:
+            if (l == 0) {
+                const long n = 24L * C->g0.vh;
+                cx<double>* a = C->ot;
+                cx<double>* b = C->ot + n;
+                fine_import_spinor<double>(C->g0, in, a, C->s);
+                fine_dirac<double>(fine_op<double>(C), a, b, C->s);
+                fine_export_spinor<double>(C->g0, b, out, C->s);
+                break;
+            }
+            imp(l, in, H.wa[l]);
+            H.apply_D(l, H.wa[l], H.wb[l]);
+            exp_(l, H.wb[l], out);
+            break;
+        case DD_OP_D_PREC:
+            imp(0, in, H.wa[0]);
+            H.apply_D(0, H.wa[0], H.wb[0]);
+            exp_(0, H.wb[0], out);
+            break;
+        case DD_OP_SAP:
+            if (l >= bottom) fail(DD_EINVAL, "no SAP on the coarsest level");
+            imp(l, in, H.wa[l]);
+            H.sap(l, H.wa[l], H.wb[l], arg, true);
+            exp_(l, H.wb[l], out);
+            break;
+        case DD_OP_VCYCLE:
+            if (l >= bottom) fail(DD_EINVAL, "no V-cycle on the coarsest level");
+            if (!C->have_setup) fail(DD_ESTATE, "hierarchy not built");
+            imp(l, in, H.wa[l]);
+            memset(H.coarse_count, 0, sizeof H.coarse_count);
+            H.vcycle(l, bottom, H.wa[l], H.wb[l]);
+            its = H.coarse_count[l + 1];
+            exp_(l, H.wb[l], out);
+            break;
+        case DD_OP_RESTRICT:
+            if (l >= bottom) fail(DD_EINVAL, "no restriction from the coarsest level");
+            imp(l, in, H.wa[l]);
+            H.restrict_(l, H.wa[l], H.wa[l + 1]);
+            exp_(l + 1, H.wa[l + 1], out);
+            break;
+        case DD_OP_PROLONG:
+            if (l >= bottom) fail(DD_EINVAL, "no prolongation to the coarsest level");
+            imp(l + 1, in, H.wa[l + 1]);
+            H.prolong(l, H.wa[l + 1], H.wa[l]);
+            exp_(l, H.wa[l], out);
+            break;
+        case DD_OP_COARSE_SOLVE:
+            if (l < 1) fail(DD_EINVAL, "coarse solve needs level >= 1");
+            imp(l, in, H.rc[l]);
+            its = H.gmres_oe(l, H.rc[l], H.ec[l]);
+            exp_(l, H.ec[l], out);
+            break;
+        case DD_OP_SCHUR:
+            if (l < 1) fail(DD_EINVAL, "Schur complement needs level >= 1");
+            imp(l, in, H.wa[l]);
+            H.schur(l, H.wa[l], H.wb[l]);
+            HIPX(hipMemsetAsync(H.wb[l], 0, sizeof(cx<T>) * (size_t)H.g[l].vh * H.nd[l], C->s));
+            exp_(l, H.wb[l], out);
+            break;
+        case DD_OP_FGMRES:
+            if (l < 1 || l >= bottom) fail(DD_EINVAL, "middle-level FGMRES needs 1 <= level < levels-1");
+            imp(l, in, H.rc[l]);
+            memset(H.coarse_count, 0, sizeof H.coarse_count);
+            its = H.fgmres_mid(l, bottom, H.rc[l], H.ec[l]);
+            exp_(l, H.ec[l], out);
+            break;
+        default:
+            fail(DD_EINVAL, "unknown op");
+    }
+    HIPX(hipGetLastError());
+    sync(C);
+    if (iters) *iters = its;
+}
+
+dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, double* out, long* iters) {
+    ABI_TRY(ctx)
+    if (!in || !out) fail(DD_EINVAL, "NULL vector");
+    if (!ctx->configured) {
+        if (op == DD_OP_D && level == 0) {
+            const long n = 24L * ctx->g0.vh;
+            Arena tmp;
+            cx<double>* a = tmp.get<cx<double>>(n);
+            cx<double>* b = tmp.get<cx<double>>(n);
+            fine_import_spinor<double>(ctx->g0, in, a, ctx->s);
+            fine_dirac<double>(fine_op<double>(ctx), a, b, ctx->s);
+            fine_export_spinor<double>(ctx->g0, b, out, ctx->s);
+            HIPX(hipGetLastError());
+            sync(ctx);
+            return DD_OK;
+        }
+        fail(DD_ESTATE, "dd_configure first");
+    }
+    if (ctx->H64) apply_impl(ctx, *ctx->H64, op, level, arg, in, out, iters);
+    else apply_impl(ctx, *ctx->H32, op, level, arg, in, out, iters);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+

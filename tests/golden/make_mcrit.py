@@ -1,0 +1,56 @@
+"""Write tests/golden/mcrit.json: the critical mass of the synthetic gauge
+fields used by the workloads, estimated by Arnoldi (ARPACK, which='SR') on the
+oracle's matrix-free D at m0 = 0:  m_crit = -Re(lambda_SR).
+
+Calls only the oracle and the seeded field generator.  Usage:
+    python tests/golden/make_mcrit.py [name ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.sparse.linalg as sla
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+from paper_1303_1377_amd import fields as F  # noqa: E402
+
+# lattice (T,X,Y,Z), link spread eps, APE steps (alpha 0.5), seed, csw
+FIELDS = {
+    "c2_16x4_seed0": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=0, csw=1.0),
+    "c2_16x4_seed1": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=1, csw=1.0),
+    "c1_4x4_seed0": dict(dims=(4, 4, 4, 4), eps=0.3, ape=0, seed=0, csw=1.0),
+    "t_8x4_seed0": dict(dims=(8, 8, 8, 8), eps=0.4, ape=2, seed=0, csw=1.0),
+}
+
+
+def mcrit(dims, eps, ape, seed, csw, k=8, tol=1e-6):
+    U = F.make_gauge(dims, eps, seed, ape_steps=ape, ape_alpha=0.5)
+    o = O.Oracle(dims, U, 0.0, csw)
+    n = int(np.prod(dims)) * 12
+    op = sla.LinearOperator((n, n), matvec=lambda v: o.apply(v.astype(np.complex128)), dtype=np.complex128)
+    ev = sla.eigs(op, k=k, which="SR", tol=tol, ncv=max(40, 3 * k), maxiter=100000,
+                  v0=np.ones(n, dtype=np.complex128), return_eigenvectors=False)
+    return float(-np.min(ev.real)), sorted(ev.real.tolist())[:4]
+
+
+def main(names):
+    path = os.path.join(HERE, "mcrit.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    for name in names or list(FIELDS):
+        cfg = FIELDS[name]
+        t = time.time()
+        m, low = mcrit(cfg["dims"], cfg["eps"], cfg["ape"], cfg["seed"], cfg["csw"])
+        data[name] = dict(cfg, dims=list(cfg["dims"]), m_crit=m, lowest_re=low,
+                          method="ARPACK eigs which=SR k=8 tol=1e-6 on the oracle D at m0=0",
+                          seconds=round(time.time() - t, 1))
+        print(name, m, "%.1fs" % (time.time() - t), flush=True)
+        json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,252 @@
+"""GPU parity: every component of the HIP path against the FP64 oracle on the
+same seeded inputs, element by element.  Bars: linear operator applies 1e-13
+(FP64) / 2e-6 (FP32); SAP/MR (non-linear through the MR step lengths) 1e-12
+(FP64); iterative components with a fixed iteration count 1e-10 (FP64)."""
+import numpy as np
+import pytest
+
+from paper_1303_1377_amd import fields as F
+from tests._gpu import Pair, rel, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+C1 = (4, 4, 4, 4)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    say("case: C1 pair 4^4 eps=0.3 seed=0 m0=-0.4")
+    return Pair(C1, eps=0.3, seed=0, m0=-0.4, csw=1.0)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 4), (4, 8, 2, 4), (2, 2, 2, 2), (8, 8, 4, 8)])
+def test_dirac_fp64(dims):
+    say("case: dirac fp64", dims)
+    p = Pair(dims, eps=0.4, seed=3, m0=-0.1, csw=1.3)
+    psi = F.gaussian_spinor(dims, 5)
+    out, _ = p.g.apply("D", 0, psi)
+    assert rel(to_np(out), p.o.apply(psi)) < 1e-13
+
+
+def test_dirac_fp32_and_clover(c1):
+    say("case: dirac fp32 + clover blocks")
+    c1.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)])
+    psi = F.gaussian_spinor(C1, 6)
+    out, _ = c1.g.apply("D_PREC", 0, psi)
+    assert rel(to_np(out), c1.o.apply(psi)) < 2e-6
+    A, Ai = c1.g.get_clover()
+    Ao, Aio = c1.o.clover()
+    assert rel(to_np(A), Ao) < 1e-14
+    assert rel(to_np(Ai), Aio) < 1e-12
+
+
+def test_user_clover_matches():
+    say("case: user-supplied clover term")
+    dims = (4, 4, 2, 2)
+    p0 = Pair(dims, eps=0.5, seed=2, m0=0.1, csw=1.0)
+    A, _ = p0.o.clover()
+    T = A - (0.1 + 4.0) * np.eye(6)[None, None]
+    p = Pair(dims, eps=0.5, seed=2, m0=0.1, csw=1.0, clover_T=T)
+    psi = F.gaussian_spinor(dims, 1)
+    out, _ = p.g.apply("D", 0, psi)
+    assert rel(to_np(out), p0.o.apply(psi)) < 1e-13
+
+
+@pytest.mark.parametrize("dims,blk,mr,nu", [((4, 4, 4, 4), (2, 2, 2, 2), 4, 1), ((4, 4, 4, 4), (2, 2, 2, 2), 4, 2),
+                                            ((8, 8, 8, 8), (4, 4, 4, 4), 3, 2), ((8, 4, 4, 4), (4, 4, 4, 4), 4, 1),
+                                            ((4, 4, 4, 4), (4, 4, 4, 4), 5, 1)])
+def test_sap_fp64(dims, blk, mr, nu):
+    say("case: sap fp64", dims, blk, mr, nu)
+    p = Pair(dims, eps=0.3, seed=1, m0=-0.2, csw=1.0)
+    agg = tuple(min(2, d) for d in dims)
+    p.configure(levels=2, n_tv=[4], agg=[agg], sap=[blk], mr_steps=[mr], nu=nu)
+    b = F.gaussian_spinor(dims, 2)
+    z, _ = p.g.apply("SAP", 0, b, arg=nu)
+    assert rel(to_np(z), p.o.sap(0, b, nu)) < 1e-12
+
+
+def test_sap_fp32(c1):
+    say("case: sap fp32")
+    c1.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4])
+    b = F.gaussian_spinor(C1, 2)
+    z, _ = c1.g.apply("SAP", 0, b, arg=2)
+    assert rel(to_np(z), c1.o.sap(0, b, 2)) < 1e-5
+
+
+def _built(p, n, agg, sap, seed=7, precision=64, **kw):
+    p.configure(precision=precision, levels=2, n_tv=[n], agg=[agg], sap=[sap], **kw)
+    tv = p.vectors(0, n, seed)
+    p.o.set_vectors(0, tv)
+    p.o.build(0)
+    p.g.set_test_vectors(0, tv)
+    p.g.build_level(0)
+    return tv
+
+
+@pytest.mark.parametrize("dims,agg,n", [((4, 4, 4, 4), (2, 2, 2, 2), 8), ((8, 8, 8, 8), (4, 4, 4, 4), 20),
+                                        ((8, 4, 4, 8), (2, 2, 2, 4), 6)])
+def test_build_P_and_coarse_operator(dims, agg, n):
+    say("case: P, D_c from injected vectors", dims, agg, n)
+    p = Pair(dims, eps=0.35, seed=4, m0=-0.25, csw=1.0)
+    _built(p, n, agg, agg)
+    assert rel(to_np(p.g.get_P(0)), p.o.get_P(0)) < 1e-12
+    M, Mi = p.g.get_coarse(1)
+    Mo, Mio = p.o.get_coarse(1)
+    assert rel(to_np(M), Mo) < 1e-12
+    assert rel(to_np(Mi), Mio) < 1e-10
+
+
+def test_transfer_and_coarse_ops(c1):
+    say("case: restrict/prolong/D_c/Schur")
+    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2))
+    v = F.gaussian_spinor(C1, 11)
+    rc, _ = c1.g.apply("RESTRICT", 0, v)
+    assert rel(to_np(rc), c1.o.restrict(0, v)) < 1e-13
+    vol_c, ndc = c1.o.level_size(1)
+    rng = np.random.default_rng(5)
+    vc = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
+    pr, _ = c1.g.apply("PROLONG", 0, vc)
+    assert rel(to_np(pr), c1.o.prolong(0, vc)) < 1e-13
+    dc, _ = c1.g.apply("D", 1, vc)
+    assert rel(to_np(dc), c1.o.apply(vc, level=1)) < 1e-13
+    sc, _ = c1.g.apply("SCHUR", 1, vc)
+    so = c1.o.schur(1, vc)
+    assert rel(to_np(sc), so) < 1e-13
+
+
+@pytest.mark.parametrize("fixed", [1, 5, 37])
+def test_coarse_solve_fixed_iterations(c1, fixed):
+    say("case: coarse GMRES fixed", fixed)
+    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=fixed)
+    vol_c, ndc = c1.o.level_size(1)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
+    e, its = c1.g.apply("COARSE_SOLVE", 1, r)
+    eo, itso = c1.o.coarse_solve(1, r)
+    assert its == itso == fixed
+    assert rel(to_np(e), eo) < 1e-10
+
+
+def test_coarse_solve_tolerance(c1):
+    say("case: coarse GMRES to 5e-2")
+    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2))
+    vol_c, ndc = c1.o.level_size(1)
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
+    e, its = c1.g.apply("COARSE_SOLVE", 1, r)
+    eo, itso = c1.o.coarse_solve(1, r)
+    assert abs(its - itso) <= 1
+    res = r - c1.o.apply(to_np(e), level=1)
+    assert np.linalg.norm(res) <= 5e-2 * np.linalg.norm(r) * 1.5
+
+
+def test_vcycle_fixed(c1):
+    say("case: V-cycle with fixed coarse iterations")
+    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=12, mr_steps=[4], nu=2)
+    c1.g.mark_setup()
+    c1.o.mark_setup()
+    r = F.gaussian_spinor(C1, 12)
+    z, _ = c1.g.apply("VCYCLE", 0, r)
+    assert rel(to_np(z), c1.o.vcycle(0, r)) < 1e-10
+
+
+@pytest.mark.parametrize("dims,agg,n,n_inv", [((4, 4, 4, 4), (2, 2, 2, 2), 8, 2), ((8, 8, 8, 8), (4, 4, 4, 4), 8, 1)])
+def test_setup_given_vectors(dims, agg, n, n_inv):
+    """Algorithm 2 in deterministic mode (fixed coarse iteration count) from the
+    same initial vectors: test vectors, P and D_c agree with the oracle."""
+    say("case: setup deterministic", dims, agg, n, n_inv)
+    import paper_1303_1377_amd as G
+
+    p = Pair(dims, eps=0.3, seed=0, m0=-0.3, csw=1.0)
+    kw = dict(levels=2, n_tv=[n], agg=[agg], sap=[agg], mr_steps=[3], n_inv=n_inv, coarse_fixed=10)
+    p.configure(**kw)
+    tv = p.vectors(0, n, 99)
+    p.g.set_test_vectors(0, tv)
+    p.g.setup(params=G.default_params(given_vectors=1, **kw))
+    p.o.setup([tv])
+    assert rel(to_np(p.g.get_test_vectors(0)), p.o.get_vectors(0)) < 1e-9
+    assert rel(to_np(p.g.get_coarse(1)[0]), p.o.get_coarse(1)[0]) < 1e-9
+
+
+def test_solve_c1_fp64(c1):
+    """Configuration 1: 4^4, 2 levels, 2^4 aggregates and SAP blocks, N = 8,
+    FGMRES(20) to 1e-10; both solutions meet the true residual and agree."""
+    say("case: C1 solve fp64")
+    import paper_1303_1377_amd as G
+
+    kw = dict(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4], n_inv=6, outer_restart=20)
+    c1.configure(**kw)
+    tv = c1.vectors(0, 8, 2024)
+    c1.g.set_test_vectors(0, tv)
+    c1.g.setup(params=G.default_params(given_vectors=1, **kw))
+    c1.o.setup([tv])
+    b = F.gaussian_spinor(C1, 1000)
+    x, st = c1.g.solve(b, 1e-10)
+    xo, sto = c1.o.solve(b, 1e-10)
+    xn = to_np(x)
+    r = b - c1.o.apply(xn)
+    relres = np.linalg.norm(r) / np.linalg.norm(b)
+    say("gpu its", st["outer_iters"], "oracle its", sto["outer_iters"], "relres", relres)
+    assert st["converged"] and relres <= 1e-10
+    assert np.linalg.norm(xn - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_solve_c1_fp32_preconditioner(c1):
+    say("case: C1 solve with fp32 preconditioner")
+    c1.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, precision=32, mr_steps=[4], outer_restart=20)
+    b = F.gaussian_spinor(C1, 1001)
+    x, st = c1.g.solve(b, 1e-10)
+    r = b - c1.o.apply(to_np(x))
+    assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
+def test_three_level_components():
+    """Three levels: SAP on the coarse operator, restriction between coarse
+    levels and the next coarse operator agree with the oracle."""
+    say("case: three-level components")
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=5, m0=-0.2, csw=1.0)
+    kw = dict(levels=3, n_tv=[6, 6], agg=[(2, 2, 2, 2), (2, 2, 2, 2)], sap=[(2, 2, 2, 2), (2, 2, 2, 2)],
+              mr_steps=[4, 4], coarse_fixed=8, mid_fixed=3)
+    p.configure(**kw)
+    tv0 = p.vectors(0, 6, 1)
+    for side in (p.o, p.g):
+        (side.set_vectors if side is p.o else side.set_test_vectors)(0, tv0)
+        side.build(0) if side is p.o else side.build_level(0)
+    tv1 = p.vectors(1, 6, 2)
+    p.o.set_vectors(1, tv1)
+    p.o.build(1)
+    p.g.set_test_vectors(1, tv1)
+    p.g.build_level(1)
+    p.g.mark_setup()
+    p.o.mark_setup()
+    assert rel(to_np(p.g.get_P(1)), p.o.get_P(1)) < 1e-12
+    assert rel(to_np(p.g.get_coarse(2)[0]), p.o.get_coarse(2)[0]) < 1e-12
+    vol1, nd1 = p.o.level_size(1)
+    rng = np.random.default_rng(3)
+    v1 = rng.standard_normal((vol1, nd1)) + 1j * rng.standard_normal((vol1, nd1))
+    z, _ = p.g.apply("SAP", 1, v1, arg=2)
+    assert rel(to_np(z), p.o.sap(1, v1, 2)) < 1e-12
+    rc, _ = p.g.apply("RESTRICT", 1, v1)
+    assert rel(to_np(rc), p.o.restrict(1, v1)) < 1e-13
+    e, its = p.g.apply("FGMRES", 1, v1)
+    # oracle: intermediate FGMRES = V-cycle of level 1 inside FGMRES; compare via the V-cycle
+    zv, _ = p.g.apply("VCYCLE", 1, v1)
+    assert rel(to_np(zv), p.o.vcycle(1, v1)) < 1e-10
+    r = F.gaussian_spinor(dims, 4)
+    zf, _ = p.g.apply("VCYCLE", 0, r)
+    assert rel(to_np(zf), p.o.vcycle(0, r)) < 1e-9
+
+
+def test_three_level_solve():
+    say("case: three-level solve 8^4")
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=5, m0=-0.2, csw=1.0)
+    p.g.setup(params=__import__("paper_1303_1377_amd").default_params(
+        levels=3, n_tv=[8, 8], agg=[(2, 2, 2, 2), (2, 2, 2, 2)], sap=[(2, 2, 2, 2), (2, 2, 2, 2)], n_inv=3,
+        outer_restart=20))
+    b = F.gaussian_spinor(dims, 7)
+    x, st = p.g.solve(b, 1e-10)
+    r = b - p.o.apply(to_np(x))
+    say("3-level its", st)
+    assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
