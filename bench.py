@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""DD-alpha-AMG time-to-solution on one MI355X.
+
+Workload (default): the 16^4 clover-Wilson system with links exp(i 0.4 H)
+reunitarised to SU(3) and smeared by two APE steps (alpha 0.5, seed 0),
+csw = 1, m0 = m_crit + 0.02 (m_crit of this field, estimated by Arnoldi on
+the CPU oracle and stored in tests/golden/mcrit.json); two levels, aggregates
+and SAP blocks 4^4, 3 MR steps, N = 20 test vectors, n_inv = 6, FP64
+throughout; one complex N(0,1) right-hand side per solve; FGMRES(25) to a
+true relative residual of 1e-10.
+
+One step = one complete solve on the resident setup (the setup time is
+reported separately).  Prints one JSON line with the time-to-solution, the
+roofline figure of the dominant kernel (algorithmic bytes / live HIP-event
+duration, accumulated by the library over the timed solves) and the CPU
+oracle's time on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-kernels]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_mcrit(name):
+    with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
+        return json.load(f)[name]
+
+
+def c2_problem():
+    from paper_1303_1377_amd import fields as F
+
+    info = load_mcrit("c2_16x4_seed0")
+    dims = tuple(info["dims"])
+    U = F.make_gauge(dims, info["eps"], info["seed"], ape_steps=info["ape"], ape_alpha=0.5)
+    m0 = info["m_crit"] + 0.02
+    return dims, U, m0, info["csw"], info
+
+
+def c2_params(G, **over):
+    kw = dict(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[3], nu=2, n_inv=6,
+              coarse_tol=5e-2, coarse_restart=30, outer_restart=25, precision=64)
+    kw.update(over)
+    return G.default_params(**kw), kw
+
+
+def cpu_baseline(dims, U, m0, csw, kw, gpu_stats, budget_s=30.0):
+    """Oracle (FP64 C, OpenMP) on a bounded sample of the same solve: P and
+    D_c built once from random test vectors (untimed), then V-cycles with the
+    GPU run's mean coarse-iteration count plus the outer D applies, timed and
+    scaled by the GPU's outer-iteration count to one solve."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1303_1377_amd import fields as F
+
+    vol = int(np.prod(dims))
+    o = O.Oracle(dims, U, m0, csw)
+    its = max(1, gpu_stats["outer_iters"])
+    cfix = max(1, int(round(gpu_stats["coarse_iters"][1] / its)))
+    okw = {k: v for k, v in kw.items() if k != "precision"}
+    okw["coarse_fixed"] = cfix
+    o.configure(**okw)
+    o.set_vectors(0, F.random_vectors(vol, 12, kw["n_tv"][0], 77))
+    o.build(0)
+    o.mark_setup()
+    r = F.gaussian_spinor(dims, 4242).reshape(-1)
+    t0 = time.time()
+    n = 0
+    while True:
+        z = o.vcycle(0, r)
+        o.apply(z)
+        n += 1
+        if time.time() - t0 > budget_s / 2 or n >= 3:
+            break
+    per_it = (time.time() - t0) / n
+    return dict(value=per_it * its, unit="s", cores=O.num_threads(), kind="oracle",
+                sample="%d V-cycle(s) (coarse GMRES fixed at %d its) + outer D apply on the 16^4 problem, "
+                       "P/D_c from random vectors; scaled by the GPU outer iteration count %d" % (n, cfix, its),
+                seconds_per_outer_iteration=per_it)
+
+
+def kernel_measurements(G, F):
+    """Standalone stencil and SAP timings at 32^3 x 64 (working set above the
+    256 MB last-level cache), FP64 and FP32."""
+    import numpy as np
+
+    dims = (64, 32, 32, 32)
+    vol = int(np.prod(dims))
+    t = time.time()
+    rng_seed = 0
+    U = F.make_gauge(dims, 0.4, rng_seed)
+    log("bench: 32^3x64 links generated in %.1fs" % (time.time() - t))
+    s = G.Solver(dims, U, -0.05, 1.0)
+    del U
+    out = {}
+    ms = s.time_kernel("dirac64", reps=20)
+    out["dirac_fp64_32c64"] = dict(ms=ms, GBs=vol * 192 * 8 / ms / 1e6, bytes_per_site=1536)
+    for prec in (32, 64):
+        s.configure(G.default_params(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4],
+                                     precision=prec))
+        sz = 4 if prec == 32 else 8
+        ms = s.time_kernel("dirac_prec", reps=20)
+        out["dirac_fp%d_32c64" % prec] = dict(ms=ms, GBs=vol * 192 * sz / ms / 1e6, bytes_per_site=192 * sz)
+        ms = s.time_kernel("sap", reps=5)
+        out["sap_sweep_fp%d_32c64" % prec] = dict(ms=ms, GBs=vol * 216 * sz / ms / 1e6, bytes_per_site=216 * sz,
+                                                   mr_steps=4)
+        log("bench: kernels fp%d done" % prec)
+    s.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1303_1377_amd as G
+    from paper_1303_1377_amd import fields as F
+
+    log("bench: generating the 16^4 field")
+    dims, U, m0, csw, info = c2_problem()
+    s = G.Solver(dims, U, m0, csw)
+    params, kw = c2_params(G)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    s.setup(params=params)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log("bench: setup %.3fs" % setup_s)
+    rhs = [torch.as_tensor(F.gaussian_spinor(dims, 1000 + i)).to("cuda") for i in range(args.warmup + args.steps)]
+    for i in range(args.warmup):
+        s.solve(rhs[i], 1e-10)
+    log("bench: warmup done")
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    stats = []
+    for i in range(args.steps):
+        x, st = s.solve(rhs[args.warmup + i], 1e-10)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    log("bench: timed %d solves in %.3fs" % (args.steps, elapsed))
+    tts = elapsed / args.steps
+    worst = max(st["true_relres"] for st in stats)
+    assert all(st["converged"] for st in stats) and worst <= 1e-10, stats
+
+    # dominant kernel class by time
+    dom = max(prof, key=lambda k: prof[k][1])
+    n_l, ms_l, by_l = prof[dom]
+    avg_ms = ms_l / max(n_l, 1)
+    achieved = (by_l / max(n_l, 1)) / (avg_ms * 1e-3) / 1e9 if n_l else 0.0
+    kernels = {k: dict(launches=v[0], total_ms=round(v[1], 3),
+                       GBs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None) for k, v in prof.items()}
+
+    out = dict(
+        metric="DD-alphaAMG time-to-solution @relres 1e-10",
+        value=tts,
+        unit="s",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=tts * 1e3,
+        higher_is_better=False,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64",
+        data="synthetic",
+        config=dict(workload="16^4 clover-Wilson, 2-level FP64 DD-alphaAMG (APE-smeared exp(i0.4H) links, "
+                             "m0=m_crit+0.02), 1 Gaussian RHS, FGMRES(25) to 1e-10",
+                    dims=list(dims), m0=m0, m_crit=info["m_crit"], csw=csw, n_tv=20, aggregates="4^4",
+                    sap_blocks="4^4", mr_steps=3, nu=2, n_inv=6, coarse="odd-even GMRES(30) to 5e-2"),
+        setup_s=setup_s,
+        solves_per_s=1.0 / tts,
+        outer_iters=[st["outer_iters"] for st in stats],
+        coarse_iters_per_solve=[st["coarse_iters"][1] for st in stats],
+        true_relres_max=worst,
+        roofline=dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=None, launches=n_l, avg_launch_ms=avg_ms),
+        kernel_classes=kernels,
+    )
+    if not args.no_kernels:
+        try:
+            out["kernels_32c64"] = kernel_measurements(G, F)
+        except Exception as e:  # measurement extras never hide the main line
+            out["kernels_32c64"] = dict(error=str(e))
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(dims, U, m0, csw, kw, stats[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

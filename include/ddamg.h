@@ -200,6 +200,39 @@ dd_status dd_apply(dd_ctx *ctx, int op, int level, int arg, const double *in, do
 /* Lattice dims and unknowns per site of a level (level 0: the fine lattice). */
 dd_status dd_level_info(const dd_ctx *ctx, int level, int dims[4], int *nd);
 
+/* ---------------------------------------------------------------------------
+ * Live kernel timing.  With profiling enabled every launch of the kernel
+ * classes below is bracketed by HIP events on the context stream; durations
+ * are accumulated per class when the host next synchronises.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    DD_K_DIRAC64 = 0,      /* fine stencil, FP64 (outer operator)              */
+    DD_K_DIRAC_PREC = 1,   /* fine stencil, preconditioner precision           */
+    DD_K_SAP = 2,          /* fine SAP half sweep (one colour)                 */
+    DD_K_RESTRICT = 3,     /* P^H (any level)                                  */
+    DD_K_PROLONG = 4,      /* P (any level)                                    */
+    DD_K_COARSE = 5,       /* coarse stencil / Schur pieces                     */
+    DD_K_COARSE_SAP = 6,   /* coarse-level SAP half sweep                       */
+    DD_K_REDUCE = 7,       /* multi-dot and update+norm reductions             */
+    DD_K_BLAS = 8,         /* other vector kernels (axpy, scale, conversions)  */
+    DD_K_NCLASS = 9
+} dd_kernel_class;
+
+/* enable != 0 starts (and resets) profiling; 0 stops it. */
+dd_status dd_profile(dd_ctx *ctx, int enable);
+
+/* Launch count, summed duration (ms) and summed algorithmic bytes (every
+ * datum a launch must read or write, counted once) of one kernel class since
+ * the last dd_profile(ctx, 1).  Any output pointer may be NULL. */
+dd_status dd_profile_read(dd_ctx *ctx, int kernel_class, long *launches, double *total_ms, double *total_bytes);
+
+/* Time `reps` back-to-back launches of one kernel class on the fine level
+ * (DD_K_DIRAC64, DD_K_DIRAC_PREC or DD_K_SAP = one full SAP sweep, both
+ * colours, preconditioner precision, mr_steps of level 0) on internal random
+ * data between two HIP events; *avg_ms = mean duration of one launch.  Needs
+ * dd_configure (for DD_K_DIRAC_PREC / DD_K_SAP). */
+dd_status dd_time_kernel(dd_ctx *ctx, int kernel_class, int reps, double *avg_ms);
+
 /* Device bytes currently allocated by the context. */
 long long dd_device_bytes(const dd_ctx *ctx);
 

@@ -11,12 +11,13 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-__all__ = ["Solver", "Params", "Stats", "default_params", "library", "DDError", "OPS"]
+__all__ = ["Solver", "Params", "Stats", "default_params", "library", "DDError", "OPS", "KERNEL_CLASSES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddamg.so")
 MAXLEV = 4
 
+KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse", "coarse_sap", "reduce", "blas"]
 OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8)
 STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
           -6: "DD_ENUMERIC"}
@@ -100,11 +101,15 @@ def library():
         L.dd_get_clover.argtypes = [vp, vp, vp]
         L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
+        L.dd_profile.argtypes = [vp, C.c_int]
+        L.dd_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_long), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.dd_time_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dd_device_bytes.restype = C.c_longlong
         L.dd_device_bytes.argtypes = [vp]
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
-                     "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info"):
+                     "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
+                     "dd_time_kernel"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -230,6 +235,25 @@ class Solver:
     def set_mass(self, m0):
         self._check(library().dd_set_mass(self.h, float(m0)))
         self.m0 = float(m0)
+
+    # ---- live kernel timing --------------------------------------------------
+    def profile(self, enable=True):
+        self._check(library().dd_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{class: (launches, total_ms, algorithmic_bytes)} since profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            n, ms, by = C.c_long(), C.c_double(), C.c_double()
+            self._check(library().dd_profile_read(self.h, k, C.byref(n), C.byref(ms), C.byref(by)))
+            out[name] = (n.value, ms.value, by.value)
+        return out
+
+    def time_kernel(self, name, reps=20):
+        """Mean duration (ms) of one standalone launch: dirac64, dirac_prec or sap (full sweep)."""
+        ms = C.c_double()
+        self._check(library().dd_time_kernel(self.h, KERNEL_CLASSES.index(name), int(reps), C.byref(ms)))
+        return ms.value
 
     # ---- components ----------------------------------------------------------
     def set_test_vectors(self, level, v):

@@ -17,65 +17,107 @@ static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // out(x) = [post Minv] ( self(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
-// workgroup = one site, thread = one row
+// One workgroup per site.  The (block, column) pairs of the site's dense
+// blocks are split evenly over the wavefronts; lane r accumulates row r, so
+// every load of a column-major block is coalesced.  Partial rows meet in LDS.
 // ---------------------------------------------------------------------------
+static constexpr int CA_WAVES = 8;
+
 template <class T>
-__global__ void k_coarse_apply(CoarseOp<T> op, int par, int self_mode, const cx<T>* __restrict__ in1, int hop_sign,
-                               const cx<T>* in2, int post_inv, cx<T>* out) {
-    extern __shared__ char smem_raw[];
-    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+__global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, int par, int self_mode,
+                                                                const cx<T>* __restrict__ in1, int hop_sign,
+                                                                const cx<T>* in2, int post_inv, cx<T>* out,
+                                                                const int* skip) {
+    if (skip && *skip) return;
+    __shared__ cx<T> part[CA_WAVES][64];
+    __shared__ cx<T> buf[64];
+    __shared__ const cx<T>* mat[9];
+    __shared__ const cx<T>* vin[9];
+    __shared__ int nslot_s;
     const Geom g = op.g;
     const int nd = op.nd;
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, r = threadIdx.x & 63;
     int p, i;
     if (par < 0) { p = blockIdx.x >= g.vh; i = blockIdx.x - p * g.vh; }
     else { p = par; i = blockIdx.x; }
     const size_t gs = (size_t)p * g.vh + i;
-    const int r = threadIdx.x;
     const size_t nn = (size_t)nd * nd;
-    cx<T> acc = czero<T>();
-    if (r < nd) {
-        if (self_mode == CS_IDENT) {
-            acc = in1[gs * nd + r];
-        } else if (self_mode == CS_SELF || self_mode == CS_SELFINV) {
-            const cx<T>* A = (self_mode == CS_SELF) ? op.M + gs * 9 * nn : op.Minv + gs * nn;
-            const cx<T>* v = in1 + gs * nd;
-            for (int c = 0; c < nd; c++) acc += A[(size_t)c * nd + r] * v[c];
-        }
+    if (threadIdx.x == 0) {
+        int ns = 0;
+        if (self_mode == CS_SELF) { mat[ns] = op.M + gs * 9 * nn; vin[ns] = in1 + gs * nd; ns++; }
+        else if (self_mode == CS_SELFINV) { mat[ns] = op.Minv + gs * nn; vin[ns] = in1 + gs * nd; ns++; }
         if (hop_sign != 0) {
             int x[4];
             cb_coords(g, p, i, x);
-            cx<T> h = czero<T>();
             for (int k = 0; k < 8; k++) {
                 int y[4];
                 nb_coords(g, x, k, y);
                 const size_t gy = (size_t)(1 - p) * g.vh + cb_index(g, y);
-                const cx<T>* A = op.M + (gs * 9 + 1 + k) * nn;
-                const cx<T>* v = in2 + gy * nd;
-                for (int c = 0; c < nd; c++) h += A[(size_t)c * nd + r] * v[c];
+                mat[ns] = op.M + (gs * 9 + 1 + k) * nn;
+                vin[ns] = in2 + gy * nd;
+                ns++;
             }
-            if (hop_sign > 0) acc += h;
-            else acc -= h;
+        }
+        nslot_s = ns;
+    }
+    __syncthreads();
+    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    const int Q = nslot_s * nd;
+    const int per = (Q + nw - 1) / nw;
+    const int q0 = w * per, q1 = min(Q, q0 + per);
+    cx<T> acc = czero<T>();
+    if (r < nd) {
+        int q = q0;
+        while (q < q1) {
+            const int sl = q / nd;
+            const int c0 = q - sl * nd;
+            const int c1 = min(nd, c0 + (q1 - q));
+            const cx<T>* A = mat[sl] + r;
+            const cx<T>* v = vin[sl];
+            cx<T> a2 = czero<T>();
+#pragma unroll 4
+            for (int c = c0; c < c1; c++) a2 += A[(size_t)c * nd] * v[c];
+            if (sl >= nself && hop_sign < 0) acc -= a2;
+            else acc += a2;
+            q += c1 - c0;
         }
     }
-    if (post_inv) {
-        if (r < nd) buf[r] = acc;
-        __syncthreads();
-        if (r < nd) {
-            const cx<T>* A = op.Minv + gs * nn;
-            cx<T> s = czero<T>();
-            for (int c = 0; c < nd; c++) s += A[(size_t)c * nd + r] * buf[c];
-            acc = s;
-        }
+    part[w][r] = acc;
+    __syncthreads();
+    cx<T> tot = czero<T>();
+    if (w == 0 && r < nd) {
+        tot = (self_mode == CS_IDENT) ? in1[gs * nd + r] : czero<T>();
+        for (int q = 0; q < nw; q++) tot += part[q][r];
     }
-    if (r < nd) out[gs * nd + r] = acc;
+    if (!post_inv) {
+        if (w == 0 && r < nd) out[gs * nd + r] = tot;
+        return;
+    }
+    if (w == 0) buf[r] = tot;
+    __syncthreads();
+    const int per2 = (nd + nw - 1) / nw;
+    const int c0 = w * per2, c1 = min(nd, c0 + per2);
+    cx<T> a3 = czero<T>();
+    if (r < nd) {
+        const cx<T>* A = op.Minv + gs * nn + r;
+        for (int c = c0; c < c1; c++) a3 += A[(size_t)c * nd] * buf[c];
+    }
+    part[w][r] = a3;
+    __syncthreads();
+    if (w == 0 && r < nd) {
+        cx<T> s2 = czero<T>();
+        for (int q = 0; q < nw; q++) s2 += part[q][r];
+        out[gs * nd + r] = s2;
+    }
 }
 
 template <class T>
 void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s) {
+                  bool post_inv, cx<T>* out, hipStream_t s, const int* skip) {
     int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
-    int nt = ((op.nd + 63) / 64) * 64;
-    k_coarse_apply<T><<<nsite, nt, sizeof(cx<T>) * op.nd, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out);
+    int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
+    int nw = nslot >= 8 ? CA_WAVES : (post_inv || nslot > 0 ? 4 : 1);
+    k_coarse_apply<T><<<nsite, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +655,8 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
 }
 
 #define DD_COARSE_INST(T)                                                                                                \
-    template void coarse_apply<T>(const CoarseOp<T>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*, hipStream_t); \
+    template void coarse_apply<T>(const CoarseOp<T>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*, hipStream_t, \
+                                  const int*);                                                                      \
     template void coarse_self_inverse<T>(const Geom&, int, const cx<T>*, cx<T>*, int*, hipStream_t);                  \
     template void coarse_import_vector<T>(const Geom&, int, int, const double*, cx<T>*, hipStream_t);                \
     template void coarse_export_vector<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \

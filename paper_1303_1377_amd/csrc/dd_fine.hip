@@ -432,16 +432,18 @@ void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// SAP half sweep: one workgroup per lattice block of the active colour.
-// Thread t owns the block's even site t and odd site t (local layout index).
-// With r = b - D z restricted to the block and H the hopping part of D:
+// SAP half sweep: one workgroup per lattice block of the active colour, one
+// thread per block site (threads [0, bvh) the even sites, [bvh, 2 bvh) the odd
+// sites, same local layout index).  With r = b - D z restricted to the block
+// and H the hopping part of D:
 //   t0_e = A_e^{-1}(b_e - (H z)_e) - z_e               (= A_ee^{-1} r_e)
 //   f_o  = b_o - A_o z_o - (H z)_o - (H_int t0)_o        (= r_o - D_oe A_ee^{-1} r_e)
 //   MR on S = A_oo - D_oe A_ee^{-1} D_eo (block-internal hops) from e_o = 0
 //   e_e  = t0_e - A_e^{-1} (H_int e_o)_e
 //   z   += e on the block
-// Block-internal spinors are exchanged through LDS; the MR inner products are
-// wavefront shuffles plus one LDS step.
+// Block fields live in LDS as [12][bvh] arrays: E (even field), O (odd field:
+// residual rho), T0 (t0), EO (e_o).  The MR inner products are wavefront
+// shuffles plus one LDS step.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ void lds_load(const cx<T>* buf, int bvh, int l, cx<T> v[12]) {
@@ -456,25 +458,32 @@ __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T
 
 // acc += sum over block-internal hops of the LDS field `buf` (opposite parity)
 template <class T>
-__device__ __forceinline__ void hop_internal(const FineOp<T>& op, int p, int i, const int nbj[8], int base, int lbvh,
-                                             const cx<T>* buf, int bvh, cx<T> acc[12]) {
-#pragma unroll
+__device__ __forceinline__ void hop_internal(const FineOp<T>& op, int p, int i, const int x[4], int blk, int base,
+                                             const cx<T>* buf, cx<T> acc[12]) {
+    const Geom& g = op.g;
+#pragma unroll 1
     for (int k = 0; k < 8; k++) {
-        int j = nbj[k];
-        if ((j >> lbvh) != (base >> lbvh)) continue;
+        int y[4];
+        nb_coords(g, x, k, y);
+        int j = cb_index(g, y);
+        if ((j >> g.lbvh) != blk) continue;
         cx<T> v[12];
-        lds_load(buf, bvh, j - base, v);
+        lds_load(buf, g.bvh, j - base, v);
         hop_accum(op, k, p, i, j, v, acc);
     }
 }
 
 template <class T>
-__device__ __forceinline__ void hop_all(const FineOp<T>& op, int p, int i, const int nbj[8], const cx<T>* psi, cx<T> acc[12]) {
-#pragma unroll
+__device__ __forceinline__ void hop_all(const FineOp<T>& op, int p, int i, const int x[4], const cx<T>* psi, cx<T> acc[12]) {
+    const Geom& g = op.g;
+#pragma unroll 1
     for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, x, k, y);
+        int j = cb_index(g, y);
         cx<T> v[12];
-        load_spinor(psi, op.g.vh, 1 - p, nbj[k], v);
-        hop_accum(op, k, p, i, nbj[k], v, acc);
+        load_spinor(psi, g.vh, 1 - p, j, v);
+        hop_accum(op, k, p, i, j, v, acc);
     }
 }
 
@@ -484,137 +493,148 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     extern __shared__ char smem_raw[];
     const Geom g = op.g;
     const int bvh = g.bvh;
-    cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // odd-site field [12][bvh]
-    cx<T>* se = so + 12 * bvh;                        // even-site field [12][bvh]
-    double* red = reinterpret_cast<double*>(se + 12 * bvh);
+    cx<T>* E = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* O = E + 12 * bvh;
+    cx<T>* T0 = O + 12 * bvh;
+    cx<T>* EO = T0 + 12 * bvh;
+    double* red = reinterpret_cast<double*>(EO + 12 * bvh);
     const int blk = blocks[blockIdx.x];
     const int base = blk << g.lbvh;
     const int t = threadIdx.x;
-    const bool act = t < bvh;
-    const int i = base + (act ? t : 0);
-    int xe[4], xo[4], nbe[8], nbo[8];
-    cb_coords(g, 0, i, xe);
-    cb_coords(g, 1, i, xo);
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        int y[4];
-        nb_coords(g, xe, k, y);
-        nbe[k] = cb_index(g, y);
-        nb_coords(g, xo, k, y);
-        nbo[k] = cb_index(g, y);
-    }
-    cx<T> t0[12], rho[12], eo[12], s[12], acc[12], v[12];
-    // ---- t0_e = A_e^{-1}(b_e - H z) - z_e ----
+    const bool act = t < 2 * bvh;
+    const int p = (t >= bvh) ? 1 : 0;
+    const int l = act ? t - p * bvh : 0;
+    const int i = base + l;
+    const bool ev = act && p == 0, od = act && p == 1;
+    int x[4];
+    cb_coords(g, p, i, x);
+    cx<T> acc[12], v[12], w[12];
+    // ---- residual on the block ----
     if (act) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_all(op, 0, i, nbe, z, acc);
-        load_spinor(b, g.vh, 0, i, v);
+        hop_all(op, p, i, x, z, acc);
+        load_spinor(b, g.vh, p, i, v);
 #pragma unroll
-        for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];
-        clover_apply(op.clovinv, g.vh, 0, i, v, t0);
-        load_spinor(z, g.vh, 0, i, v);
+        for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];  // b - H z
+        load_spinor(z, g.vh, p, i, acc);
+        if (ev) {
+            clover_apply(op.clovinv, g.vh, 0, i, v, w);
 #pragma unroll
-        for (int c = 0; c < 12; c++) t0[c] -= v[c];
-        lds_store(se, bvh, t, t0);
+            for (int c = 0; c < 12; c++) w[c] -= acc[c];
+            lds_store(E, bvh, l, w);
+            lds_store(T0, bvh, l, w);
+        } else {
+            clover_apply(op.clov, g.vh, 1, i, acc, w);
+#pragma unroll
+            for (int c = 0; c < 12; c++) w[c] = v[c] - w[c];
+            lds_store(O, bvh, l, w);
+        }
     }
     __syncthreads();
-    // ---- f_o = b_o - A z_o - H z - H_int t0 ----
-    if (act) {
+    if (od) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_all(op, 1, i, nbo, z, acc);
-        hop_internal(op, 1, i, nbo, base, g.lbvh, se, bvh, acc);
-        load_spinor(z, g.vh, 1, i, v);
-        clover_apply(op.clov, g.vh, 1, i, v, rho);
-        load_spinor(b, g.vh, 1, i, v);
+        hop_internal(op, 1, i, x, blk, base, E, acc);
+        lds_load(O, bvh, l, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) {
-            rho[c] = v[c] - rho[c] + T(0.5) * acc[c];
-            eo[c] = czero<T>();
+            v[c] += T(0.5) * acc[c];
+            w[c] = czero<T>();
         }
-        lds_store(so, bvh, t, rho);
+        lds_store(O, bvh, l, v);   // rho = f_o
+        lds_store(EO, bvh, l, w);  // e_o = 0
     }
     __syncthreads();
+    const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
     for (int it = 0; it < mr_steps; it++) {
-        // even: t = A^{-1} (H_int rho) ;  H = -1/2 hopsum
-        if (act) {
+        // even: t = A^{-1} (H_int rho), H = -1/2 hopsum
+        if (ev) {
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-            hop_internal(op, 0, i, nbe, base, g.lbvh, so, bvh, acc);
+            hop_internal(op, 0, i, x, blk, base, O, acc);
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
-            clover_apply(op.clovinv, g.vh, 0, i, acc, v);
-            lds_store(se, bvh, t, v);
+            clover_apply(op.clovinv, g.vh, 0, i, acc, w);
+            lds_store(E, bvh, l, w);
         }
         __syncthreads();
         // odd: s = A rho - H_int t
         double sr = 0, si = 0, ss = 0;
-        if (act) {
+        if (od) {
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-            hop_internal(op, 1, i, nbo, base, g.lbvh, se, bvh, acc);
-            clover_apply(op.clov, g.vh, 1, i, rho, s);
+            hop_internal(op, 1, i, x, blk, base, E, acc);
+            lds_load(O, bvh, l, v);
+            clover_apply(op.clov, g.vh, 1, i, v, w);
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                s[c] += T(0.5) * acc[c];
-                cx<T> d = cmulc(s[c], rho[c]);
+                w[c] += T(0.5) * acc[c];
+                cx<T> d = cmulc(w[c], v[c]);
                 sr += d.re;
                 si += d.im;
-                ss += norm2(s[c]);
+                ss += norm2(w[c]);
             }
         }
         sr = wave_sum(sr);
         si = wave_sum(si);
         ss = wave_sum(ss);
-        const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
-        if (lane == 0) { red[3 * w] = sr; red[3 * w + 1] = si; red[3 * w + 2] = ss; }
+        if (lane == 0) { red[3 * wv] = sr; red[3 * wv + 1] = si; red[3 * wv + 2] = ss; }
         __syncthreads();
         sr = si = ss = 0;
         for (int q = 0; q < nw; q++) { sr += red[3 * q]; si += red[3 * q + 1]; ss += red[3 * q + 2]; }
-        if (ss > 0) {
+        if (od && ss > 0) {
             cx<T> alpha = {T(sr / ss), T(si / ss)};
-            if (act) {
+            lds_load(EO, bvh, l, acc);
 #pragma unroll
-                for (int c = 0; c < 12; c++) {
-                    eo[c] += alpha * rho[c];
-                    rho[c] -= alpha * s[c];
-                }
+            for (int c = 0; c < 12; c++) {
+                acc[c] += alpha * v[c];
+                v[c] -= alpha * w[c];
             }
+            lds_store(EO, bvh, l, acc);
+            lds_store(O, bvh, l, v);
         }
-        __syncthreads();
-        if (act) lds_store(so, bvh, t, (it + 1 < mr_steps) ? rho : eo);
-        __syncthreads();
-    }
-    if (mr_steps == 0) {
-        if (act) lds_store(so, bvh, t, eo);
         __syncthreads();
     }
     // ---- back-substitution and update ----
-    if (act) {
+    if (ev) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_internal(op, 0, i, nbe, base, g.lbvh, so, bvh, acc);
+        hop_internal(op, 0, i, x, blk, base, EO, acc);
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
-        clover_apply(op.clovinv, g.vh, 0, i, acc, v);
+        clover_apply(op.clovinv, g.vh, 0, i, acc, w);
+        lds_load(T0, bvh, l, v);
         load_spinor(z, g.vh, 0, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += t0[c] + v[c];
+        for (int c = 0; c < 12; c++) acc[c] += v[c] + w[c];
         store_spinor(z, g.vh, 0, i, acc);
+    } else if (od) {
+        lds_load(EO, bvh, l, v);
         load_spinor(z, g.vh, 1, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += eo[c];
+        for (int c = 0; c < 12; c++) acc[c] += v[c];
         store_spinor(z, g.vh, 1, i, acc);
     }
+}
+
+template <class T>
+size_t sap_lds_bytes(int bvh) {
+    int nt = ((2 * bvh + 63) / 64) * 64;
+    return 4 * 12 * (size_t)bvh * sizeof(cx<T>) + 3 * sizeof(double) * (nt / 64);
 }
 
 template <class T>
 void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                    hipStream_t s) {
     if (nblocks <= 0) return;
-    int nt = ((op.g.bvh + 63) / 64) * 64;
-    size_t lds = 2 * 12 * (size_t)op.g.bvh * sizeof(cx<T>) + 3 * sizeof(double) * (nt / 64);
+    int nt = ((2 * op.g.bvh + 63) / 64) * 64;
+    size_t lds = sap_lds_bytes<T>(op.g.bvh);
+    static size_t configured = 0;
+    if (lds > 65536 && lds > configured) {
+        (void)hipFuncSetAttribute((const void*)k_sap_fine<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        configured = lds;
+    }
     k_sap_fine<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps);
 }
 

@@ -75,7 +75,7 @@ enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 // for the sites of parity `par` (0, 1) or all sites (par < 0).
 template <class T>
 void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s);
+                  bool post_inv, cx<T>* out, hipStream_t s, const int* skip = nullptr);
 template <class T> void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s);
 template <class T> void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s);
 template <class T> void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s);
@@ -116,5 +116,38 @@ template <class T, class X>
 void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s);
 template <class T>
 void vec_finite_check(long n, const cx<T>* x, int* bad, hipStream_t s);
+
+// ---- device-resident GMRES(m) bookkeeping (coarsest level) -----------------
+// The Hessenberg matrix, Givens rotations, residual estimate and stop flag of
+// one restarted GMRES live on the device, so the host can enqueue several
+// Arnoldi steps between synchronisations; every kernel of a step returns at
+// once when `stop` is set.
+struct GmDev {
+    cx<double> H[33 * 32];   // rotated Hessenberg, column j at H[j*33 + i]
+    cx<double> cs[32], sn[32], g[33], y[32];
+    double tol_abs;          // stop when |g_{j+1}| <= tol_abs
+    double scale;            // 1/||w|| for the basis vector just produced
+    int j;                   // columns completed in this cycle
+    int its;                 // iterations in total
+    int stop;                // converged, iteration cap or exact solution
+    int m, maxit, fixed;
+};
+// beta^2 from the norm reduction result; first cycle also fixes tol_abs
+void gm_start(GmDev* st, const cx<double>* beta2, double tol, int first, int m, int maxit, int fixed, hipStream_t s);
+// fold column j (inner products h, norm^2 of the new vector) into the state
+void gm_column(GmDev* st, int j, const cx<double>* h, const cx<double>* hn2, hipStream_t s);
+// y = R^{-1} g for the st->j columns of the cycle
+void gm_solve(GmDev* st, hipStream_t s);
+// x *= st->scale (skipped once st->stop)
+template <class T> void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop);
+// x += sum_{i < st->j} y_i V_i
+template <class T> void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s);
+// skip-aware reductions for the device-resident Arnoldi step
+template <class T>
+void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work,
+                       const int* skip, hipStream_t s);
+template <class T>
+void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
+                          void* work, const int* skip, hipStream_t s);
 
 }  // namespace dd

@@ -12,6 +12,7 @@
 // products the reduction kernels return, one transfer per Arnoldi step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -182,6 +183,14 @@ struct dd_ctx {
     std::unique_ptr<Hier<double>> H64;
     std::unique_ptr<Hier<float>> H32;
     double last_setup_s = 0;
+    // live kernel timing (dd_profile)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Rec { int cls; hipEvent_t a, b; double bytes; };
+    std::vector<Rec> pending;
+    long prof_n[DD_K_NCLASS] = {0};
+    double prof_ms[DD_K_NCLASS] = {0};
+    double prof_bytes[DD_K_NCLASS] = {0};
     // FP64 outer workspace
     int outer_m = 0;
     cx<double>* oV = nullptr;  // [m+1][n]
@@ -193,7 +202,59 @@ struct dd_ctx {
 
 static const int RED_SLOTS = 4 * 34;  // 2 x (32 + 2) results
 
-static void sync(dd_ctx* C) { HIPX(hipStreamSynchronize(C->s)); }
+static hipEvent_t ev_get(dd_ctx* C) {
+    if (C->ev_pool.empty()) {
+        hipEvent_t e;
+        HIPX(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = C->ev_pool.back();
+    C->ev_pool.pop_back();
+    return e;
+}
+
+// accumulate finished event pairs (the stream has been synchronised)
+static void harvest(dd_ctx* C) {
+    for (auto& r : C->pending) {
+        float ms = 0;
+        HIPX(hipEventElapsedTime(&ms, r.a, r.b));
+        C->prof_n[r.cls]++;
+        C->prof_ms[r.cls] += ms;
+        C->prof_bytes[r.cls] += r.bytes;
+        C->ev_pool.push_back(r.a);
+        C->ev_pool.push_back(r.b);
+    }
+    C->pending.clear();
+}
+
+static void sync(dd_ctx* C) {
+    HIPX(hipStreamSynchronize(C->s));
+    if (!C->pending.empty()) harvest(C);
+}
+
+// brackets the launches issued in its scope with events when profiling is on
+// `bytes`: algorithmic device-memory traffic of the bracketed launches
+// (every datum the step must read or write, counted once)
+struct Prof {
+    dd_ctx* C;
+    int cls;
+    double bytes;
+    hipEvent_t a = nullptr;
+    Prof(dd_ctx* c, int k, double by = 0) : C(c), cls(k), bytes(by) {
+        if (C->prof_on) {
+            a = ev_get(C);
+            HIPX(hipEventRecord(a, C->s));
+        }
+    }
+    ~Prof() noexcept(false) {
+        if (a) {
+            hipEvent_t b = ev_get(C);
+            HIPX(hipEventRecord(b, C->s));
+            C->pending.push_back(dd_ctx::Rec{cls, a, b, bytes});
+            if (C->pending.size() > 4096) sync(C);
+        }
+    }
+};
 
 static int read_flag(dd_ctx* C, int idx) {
     int v = 0;
@@ -231,9 +292,24 @@ struct Hier : HierBase {
     // Krylov workspaces: coarsest GMRES and middle-level FGMRES
     cx<T>* kV[DD_MAXLEV];
     cx<T>* kZ[DD_MAXLEV];
+    GmDev* gmst[DD_MAXLEV];
+    int last_its[DD_MAXLEV];
     long coarse_count[DD_MAXLEV];
 
     long nlv(int l) const { return 2L * g[l].vh * nd[l]; }   // complex entries of a level vector
+
+    // algorithmic bytes of one launch (model documented with the kernels)
+    double by_dirac() const { return 2.0 * g[0].vh * 192 * sizeof(T); }
+    double by_sap_half() const { return 1.0 * g[0].vh * 216 * sizeof(T); }
+    double by_coarse(int l, int nblk_per_site, int nvec_per_site, bool all_sites) const {
+        double sites = all_sites ? 2.0 * g[l].vh : 1.0 * g[l].vh;
+        return sites * ((double)nblk_per_site * nd[l] * nd[l] + (double)nvec_per_site * nd[l]) * 2 * sizeof(T);
+    }
+    double by_transfer(int l) const {
+        // P (N vectors) + fine vector + coarse vector
+        return (double)nlv(l) * (N[l] + 1) * 2 * sizeof(T) + (double)nlv(l + 1) * 2 * sizeof(T);
+    }
+    double by_reduce(long n, int m) const { return (double)n * (m + 1) * 2 * sizeof(T); }
 
     Hier(dd_ctx* c) : C(c) {
         memset(blocks, 0, sizeof blocks);
@@ -243,6 +319,8 @@ struct Hier : HierBase {
         memset(M, 0, sizeof M);
         memset(Minv, 0, sizeof Minv);
         memset(coarse_count, 0, sizeof coarse_count);
+        memset(gmst, 0, sizeof gmst);
+        for (int l = 0; l < DD_MAXLEV; l++) last_its[l] = 8;
     }
 
     void build_geometry();
@@ -250,7 +328,7 @@ struct Hier : HierBase {
     void apply_D(int l, const cx<T>* in, cx<T>* out);
     void restrict_(int l, const cx<T>* in, cx<T>* out);
     void prolong(int l, const cx<T>* in, cx<T>* out);
-    void schur(int l, const cx<T>* v, cx<T>* out);
+    void schur(int l, const cx<T>* v, cx<T>* out, const int* skip = nullptr);
     long gmres_oe(int l, const cx<T>* r, cx<T>* e);
     long fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e);
     void vcycle(int l, int bottom, const cx<T>* r, cx<T>* z);
@@ -260,6 +338,8 @@ struct Hier : HierBase {
 };
 
 dd_ctx::~dd_ctx() {
+    for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     H64.reset();
     H32.reset();
     levels.release();
@@ -396,6 +476,7 @@ void Hier<T>::build_geometry() {
         int m = (l == nlev - 1) ? C->p.coarse_restart : C->p.mid_restart;
         kV[l] = A.get<cx<T>>((size_t)(m + 1) * nlv(l));
         kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)m * nlv(l)) : nullptr;
+        gmst[l] = A.get<GmDev>(1);
     }
     HIPX(hipStreamSynchronize(C->s));
 }
@@ -413,6 +494,7 @@ double Hier<T>::norm(long n, const cx<T>* v) {
 
 template <class T>
 void Hier<T>::apply_D(int l, const cx<T>* in, cx<T>* out) {
+    Prof pr(C, l == 0 ? DD_K_DIRAC_PREC : DD_K_COARSE, l == 0 ? by_dirac() : by_coarse(l, 9, 2, true));
     if (l == 0) fine_dirac<T>(op0, in, out, C->s);
     else coarse_apply<T>(cop[l], -1, CS_SELF, in, 1, in, false, out, C->s);
 }
@@ -423,6 +505,7 @@ void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start)
     if (zero_start) HIPX(hipMemsetAsync(z, 0, sizeof(cx<T>) * nlv(l), C->s));
     for (int sw = 0; sw < nsweeps; sw++)
         for (int c = 0; c < 2; c++) {
+            Prof pr(C, l == 0 ? DD_K_SAP : DD_K_COARSE_SAP, l == 0 ? by_sap_half() : by_coarse(l, 9, 3, false));
             if (l == 0) fine_sap_half<T>(op0, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s);
             else coarse_sap_half<T>(cop[l], blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s);
         }
@@ -430,25 +513,33 @@ void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start)
 
 template <class T>
 void Hier<T>::restrict_(int l, const cx<T>* in, cx<T>* out) {
+    Prof pr(C, DD_K_RESTRICT, by_transfer(l));
     if (l == 0) fine_restrict<T>(amap[0], N[0], P[0], in, out, C->s);
     else coarse_restrict<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
 }
 
 template <class T>
 void Hier<T>::prolong(int l, const cx<T>* in, cx<T>* out) {
+    Prof pr(C, DD_K_PROLONG, by_transfer(l));
     if (l == 0) fine_prolong<T>(amap[0], N[0], P[0], in, out, C->s);
     else coarse_prolong<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
 }
 
 // out_o = (A_oo - D_oe A_ee^{-1} D_eo) v_o ; even part of out = 0
 template <class T>
-void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out) {
-    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s);
-    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s);
+void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out, const int* skip) {
+    // two launches, each over one parity: 8 hop blocks + (Minv | self) per site
+    Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false));
+    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s, skip);
+    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s, skip);
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level: odd-even GMRES(m) to relative residual coarse_tol (Sec. 5)
+// coarsest level: odd-even GMRES(m) to relative residual coarse_tol (Sec. 5).
+// The Arnoldi bookkeeping lives on the device (GmDev); the host enqueues a
+// chunk of Arnoldi steps, sized from the previous solve on this level, then
+// reads back the step count and stop flag.  Steps enqueued after the stop
+// return at once.
 // ---------------------------------------------------------------------------
 template <class T>
 long Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e) {
@@ -458,59 +549,66 @@ long Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e) {
     cx<T>* V = kV[l];
     cx<T>* f = wa[l];
     cx<T>* t = wb[l];
+    GmDev* st = gmst[l];
+    const int* skip = &st->stop;
     auto odd = [&](cx<T>* v) { return v + nh; };
     // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
-    coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s);
-    coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s);
+    {
+        Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false) + by_coarse(l, 8, 3, false));
+        coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s);
+        coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s);
+    }
     HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull, C->s));
-    double fnorm = norm(nh, odd(f));
-    long its = 0;
-    const long fixed = p.coarse_fixed;
-    Hess hs(m);
-    if (fnorm > 0) {
-        // V_0 = residual of the Schur system
-        HIPX(hipMemcpyAsync(odd(V), odd(f), sizeof(cx<T>) * nh, hipMemcpyDeviceToDevice, C->s));
-        double beta = fnorm;
-        for (;;) {
-            hs.reset(beta);
-            vec_scale<T>(nh, cx<double>{1.0 / beta, 0.0}, odd(V), C->s);
-            int jend = 0;
-            bool stop = false;
-            for (int j = 0; j < m; j++) {
+    HIPX(hipMemcpyAsync(odd(V), odd(f), sizeof(cx<T>) * nh, hipMemcpyDeviceToDevice, C->s));
+    vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, C->dflags + 1, C->s);
+    gm_start(st, C->dred, p.coarse_tol, 1, m, p.coarse_maxit, p.coarse_fixed, C->s);
+    vec_scale_dev<T>(nh, st, odd(V), C->s, true);
+    int hst[3] = {0, 0, 0};  // j, its, stop
+    auto read_state = [&]() {
+        HIPX(hipMemcpyAsync(C->hred, &st->j, 3 * sizeof(int), hipMemcpyDeviceToHost, C->s));
+        sync(C);
+        memcpy(hst, C->hred, sizeof hst);
+    };
+    int chunk = std::min(m, std::max(1, last_its[l] + 2));
+    for (;;) {
+        int j = 0;
+        bool stop = false;
+        while (j < m) {
+            const int jend = std::min(m, j + chunk);
+            for (; j < jend; j++) {
                 cx<T>* w = V + (size_t)(j + 1) * nfull;
-                schur(l, V + (size_t)j * nfull, w);
-                vec_multidot<T>(nh, j + 1, odd(V), nfull, odd(w), C->dred, C->dwork, C->dflags + 1, C->s);
-                vec_update_norm<T>(nh, j + 1, odd(V), nfull, C->dred, odd(w), C->dred + 33, C->dwork, C->dflags + 1, C->s);
-                HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 34, hipMemcpyDeviceToHost, C->s));
-                sync(C);
-                for (int i = 0; i <= j; i++) hs.h(i, j) = zc(C->hred[i].re, C->hred[i].im);
-                double hn = std::sqrt(C->hred[33].re);
-                hs.h(j + 1, j) = hn;
-                double res = hs.rotate(j);
-                its++;
-                jend = j + 1;
-                if (hn > 0) vec_scale<T>(nh, cx<double>{1.0 / hn, 0.0}, odd(w), C->s);
-                if (fixed > 0) { if (its >= fixed) { stop = true; break; } }
-                else if (res <= p.coarse_tol * fnorm || its >= p.coarse_maxit) { stop = true; break; }
-                if (hn == 0) { stop = true; break; }
+                schur(l, V + (size_t)j * nfull, w, skip);
+                Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1));
+                vec_multidot_skip<T>(nh, j + 1, odd(V), nfull, odd(w), nullptr, C->dwork, skip, C->s);
+                vec_update_norm_skip<T>(nh, j + 1, odd(V), nfull, C->dred, odd(w), C->dred + 33, C->dwork, skip, C->s);
+                gm_column(st, j, C->dred, C->dred + 33, C->s);
+                vec_scale_dev<T>(nh, st, odd(w), C->s, false);
             }
-            hs.solve(jend);
-            std::vector<cx<double>> y(jend);
-            for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
-            HIPX(hipMemcpyAsync(C->dred + 64, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
-            vec_lincomb<T, T>(nh, jend, odd(V), nfull, C->dred + 64, odd(e), C->s);
-            sync(C);
-            if (stop) break;
-            // restart from the true Schur residual
-            schur(l, e, V);
-            vec_sub<T>(nh, odd(f), odd(V), odd(V), C->s);
-            beta = norm(nh, odd(V));
-            if (beta == 0) break;
+            read_state();
+            if (hst[2]) { stop = true; break; }
+            j = hst[0];
+            chunk = 4;
         }
+        gm_solve(st, C->s);
+        vec_lincomb_dev<T>(nh, odd(V), nfull, st, odd(e), C->s);
+        if (stop) break;
+        // restart from the true Schur residual
+        schur(l, e, V);
+        vec_sub<T>(nh, odd(f), odd(V), odd(V), C->s);
+        vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, C->dflags + 1, C->s);
+        gm_start(st, C->dred, p.coarse_tol, 0, m, p.coarse_maxit, p.coarse_fixed, C->s);
+        vec_scale_dev<T>(nh, st, odd(V), C->s, true);
+        read_state();
+        if (hst[2]) break;
+        chunk = 4;
     }
     // e_e = A_ee^{-1} (r_e - D_eo e_o)
-    coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s);
-    return its;
+    {
+        Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false));
+        coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s);
+    }
+    last_its[l] = hst[1];
+    return hst[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -541,10 +639,13 @@ long Hier<T>::fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e) {
             cx<T>* w = V + (size_t)(j + 1) * n;
             vcycle(l, bottom, V + (size_t)j * n, Z + (size_t)j * n);
             apply_D(l, Z + (size_t)j * n, w);
-            vec_multidot<T>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
-            vec_update_norm<T>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
-            vec_multidot<T>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
-            vec_update_norm<T>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+            {
+                Prof pr(C, DD_K_REDUCE, 4 * by_reduce(n, j + 1));
+                vec_multidot<T>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
+                vec_update_norm<T>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
+                vec_multidot<T>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
+                vec_update_norm<T>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+            }
             HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
             sync(C);
             for (int i = 0; i <= j; i++)
@@ -689,14 +790,26 @@ static dd_status outer_fgmres(dd_ctx* C, Hier<T>& H, const cx<double>* b, cx<dou
                 cx<double>* vj = V + (size_t)j * n;
                 cx<double>* w = V + (size_t)(j + 1) * n;
                 cx<T>* zj = Z + (size_t)j * n;
-                vec_convert<T, double>(n, vj, vT, C->s);
+                {
+                    Prof pr(C, DD_K_BLAS, (double)n * (16 + 2 * sizeof(T)));
+                    vec_convert<T, double>(n, vj, vT, C->s);
+                }
                 H.vcycle(0, H.nlev - 1, vT, zj);
-                vec_convert<double, T>(n, zj, t64, C->s);
-                fine_dirac<double>(op, t64, w, C->s);
-                vec_multidot<double>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
-                vec_update_norm<double>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
-                vec_multidot<double>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
-                vec_update_norm<double>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+                {
+                    Prof pr(C, DD_K_BLAS, (double)n * (16 + 2 * sizeof(T)));
+                    vec_convert<double, T>(n, zj, t64, C->s);
+                }
+                {
+                    Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * 192 * 8);
+                    fine_dirac<double>(op, t64, w, C->s);
+                }
+                {
+                    Prof pr(C, DD_K_REDUCE, 4.0 * n * (j + 2) * 16);
+                    vec_multidot<double>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
+                    vec_update_norm<double>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
+                    vec_multidot<double>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
+                    vec_update_norm<double>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
+                }
                 HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
                 sync(C);
                 for (int i = 0; i <= j; i++)
@@ -1077,6 +1190,86 @@ dd_status dd_level_info(const dd_ctx* ctx, int level, int dims[4], int* nd) {
     memcpy(dims, g->d, sizeof(int) * 4);
     *nd = n;
     return DD_OK;
+}
+
+dd_status dd_profile(dd_ctx* ctx, int enable) {
+    ABI_TRY(ctx)
+    sync(ctx);
+    ctx->prof_on = enable != 0;
+    if (enable) {
+        for (int k = 0; k < DD_K_NCLASS; k++) { ctx->prof_n[k] = 0; ctx->prof_ms[k] = 0; ctx->prof_bytes[k] = 0; }
+    }
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_profile_read(dd_ctx* ctx, int cls, long* launches, double* total_ms, double* total_bytes) {
+    ABI_TRY(ctx)
+    if (cls < 0 || cls >= DD_K_NCLASS) fail(DD_EINVAL, "unknown kernel class");
+    sync(ctx);
+    if (launches) *launches = ctx->prof_n[cls];
+    if (total_ms) *total_ms = ctx->prof_ms[cls];
+    if (total_bytes) *total_bytes = ctx->prof_bytes[cls];
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+template <class T>
+static double time_prec(dd_ctx* C, Hier<T>& H, int cls, int reps) {
+    const long n = 24L * C->g0.vh;
+    fine_random<T>(H.g[0], 1, 12345ULL, 7, H.wa[0], C->s);
+    HIPX(hipMemsetAsync(H.wb[0], 0, sizeof(cx<T>) * n, C->s));
+    hipEvent_t a = ev_get(C), b = ev_get(C);
+    // one untimed launch first
+    if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
+    else H.sap(0, H.wa[0], H.wb[0], 1, false);
+    HIPX(hipEventRecord(a, C->s));
+    for (int r = 0; r < reps; r++) {
+        if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
+        else {
+            fine_sap_half<T>(H.op0, H.blocks[0][0], H.nblocks[0][0], H.wa[0], H.wb[0], C->p.mr_steps[0], C->s);
+            fine_sap_half<T>(H.op0, H.blocks[0][1], H.nblocks[0][1], H.wa[0], H.wb[0], C->p.mr_steps[0], C->s);
+        }
+    }
+    HIPX(hipEventRecord(b, C->s));
+    HIPX(hipGetLastError());
+    HIPX(hipEventSynchronize(b));
+    float ms = 0;
+    HIPX(hipEventElapsedTime(&ms, a, b));
+    C->ev_pool.push_back(a);
+    C->ev_pool.push_back(b);
+    return ms / reps;
+}
+
+dd_status dd_time_kernel(dd_ctx* ctx, int cls, int reps, double* avg_ms) {
+    ABI_TRY(ctx)
+    if (reps < 1 || !avg_ms) fail(DD_EINVAL, "reps >= 1 and avg_ms required");
+    if (cls == DD_K_DIRAC64) {
+        const long n = 24L * ctx->g0.vh;
+        Arena tmp;
+        cx<double>* a = tmp.get<cx<double>>(n);
+        cx<double>* b = tmp.get<cx<double>>(n);
+        fine_random<double>(ctx->g0, 1, 12345ULL, 7, a, ctx->s);
+        FineOp<double> op = fine_op<double>(ctx);
+        fine_dirac<double>(op, a, b, ctx->s);
+        hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
+        HIPX(hipEventRecord(e0, ctx->s));
+        for (int r = 0; r < reps; r++) fine_dirac<double>(op, a, b, ctx->s);
+        HIPX(hipEventRecord(e1, ctx->s));
+        HIPX(hipGetLastError());
+        HIPX(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPX(hipEventElapsedTime(&ms, e0, e1));
+        ctx->ev_pool.push_back(e0);
+        ctx->ev_pool.push_back(e1);
+        *avg_ms = ms / reps;
+        return DD_OK;
+    }
+    if (cls != DD_K_DIRAC_PREC && cls != DD_K_SAP) fail(DD_EINVAL, "kernel class not timed standalone");
+    if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
+    *avg_ms = ctx->H64 ? time_prec(ctx, *ctx->H64, cls, reps) : time_prec(ctx, *ctx->H32, cls, reps);
+    return DD_OK;
+    ABI_END(ctx)
 }
 
 long long dd_device_bytes(const dd_ctx* ctx) { return ctx ? ctx->fields.bytes + ctx->levels.bytes : 0; }

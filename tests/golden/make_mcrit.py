@@ -28,14 +28,22 @@ FIELDS = {
 }
 
 
-def mcrit(dims, eps, ape, seed, csw, k=8, tol=1e-6):
+def mcrit(dims, eps, ape, seed, csw, k=4, tol=1e-5, ncv=64):
     U = F.make_gauge(dims, eps, seed, ape_steps=ape, ape_alpha=0.5)
     o = O.Oracle(dims, U, 0.0, csw)
     n = int(np.prod(dims)) * 12
-    op = sla.LinearOperator((n, n), matvec=lambda v: o.apply(v.astype(np.complex128)), dtype=np.complex128)
-    ev = sla.eigs(op, k=k, which="SR", tol=tol, ncv=max(40, 3 * k), maxiter=100000,
+    count = [0]
+
+    def mv(v):
+        count[0] += 1
+        if count[0] % 500 == 0:
+            print("  matvecs", count[0], flush=True)
+        return o.apply(v.astype(np.complex128))
+
+    op = sla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
+    ev = sla.eigs(op, k=k, which="SR", tol=tol, ncv=ncv, maxiter=100000,
                   v0=np.ones(n, dtype=np.complex128), return_eigenvectors=False)
-    return float(-np.min(ev.real)), sorted(ev.real.tolist())[:4]
+    return float(-np.min(ev.real)), sorted(ev.real.tolist())[:4], count[0]
 
 
 def main(names):
@@ -44,9 +52,9 @@ def main(names):
     for name in names or list(FIELDS):
         cfg = FIELDS[name]
         t = time.time()
-        m, low = mcrit(cfg["dims"], cfg["eps"], cfg["ape"], cfg["seed"], cfg["csw"])
-        data[name] = dict(cfg, dims=list(cfg["dims"]), m_crit=m, lowest_re=low,
-                          method="ARPACK eigs which=SR k=8 tol=1e-6 on the oracle D at m0=0",
+        m, low, nmv = mcrit(cfg["dims"], cfg["eps"], cfg["ape"], cfg["seed"], cfg["csw"])
+        data[name] = dict(cfg, dims=list(cfg["dims"]), m_crit=m, lowest_re=low, matvecs=nmv,
+                          method="ARPACK eigs which=SR k=4 ncv=64 tol=1e-5 on the oracle D at m0=0",
                           seconds=round(time.time() - t, 1))
         print(name, m, "%.1fs" % (time.time() - t), flush=True)
         json.dump(data, open(path, "w"), indent=1, sort_keys=True)
