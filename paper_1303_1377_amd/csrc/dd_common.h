@@ -177,8 +177,10 @@ __host__ __device__ __forceinline__ int herm_off(int i, int j) { return i * 6 - 
 
 template <class T>
 __host__ __device__ __forceinline__ void herm6_apply(const T m[36], const cx<T>* in, cx<T>* out) {
+#pragma unroll
     for (int i = 0; i < 6; i++) {
         cx<T> acc = m[i] * in[i];
+#pragma unroll
         for (int j = 0; j < 6; j++) {
             if (j == i) continue;
             if (j > i) {

@@ -441,10 +441,52 @@ void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s)
 //   MR on S = A_oo - D_oe A_ee^{-1} D_eo (block-internal hops) from e_o = 0
 //   e_e  = t0_e - A_e^{-1} (H_int e_o)_e
 //   z   += e on the block
-// Block fields live in LDS as [12][bvh] arrays: E (even field), O (odd field:
-// residual rho), T0 (t0), EO (e_o).  The MR inner products are wavefront
-// shuffles plus one LDS step.
+// The block's operator stays on chip for the whole half sweep: the links
+// joining two sites of the block live in LDS as their first two rows (the
+// third row of an SU(3) matrix is conj(row0 x row1)), each thread keeps the
+// clover block of its site (A^{-1} on even, A on odd sites) in registers, and
+// the block fields E (even) and O (odd) are exchanged through LDS.  Every
+// link, clover entry and spinor is therefore read from memory once per half
+// sweep.  The MR inner products are wavefront shuffles plus one LDS step.
 // ---------------------------------------------------------------------------
+struct LinkMap {        // compact index of the block-internal links of direction mu
+    int ext[4][4];      // box extents per direction
+    int off[4];         // offset of direction mu
+    int total;
+};
+
+__host__ __device__ __forceinline__ void link_map(const Geom& g, LinkMap& m) {
+    int tot = 0;
+    for (int mu = 0; mu < 4; mu++) {
+        int cnt = 1;
+        for (int nu = 0; nu < 4; nu++) {
+            int e = g.b[nu];
+            if (nu == mu && g.nb[mu] != 1) e -= 1;
+            m.ext[mu][nu] = e;
+            cnt *= e;
+        }
+        m.off[mu] = tot;
+        tot += cnt;
+    }
+    m.total = tot;
+}
+
+__device__ __forceinline__ int link_idx(const LinkMap& m, int mu, const int lc[4]) {
+    return m.off[mu] + ((lc[0] * m.ext[mu][1] + lc[1]) * m.ext[mu][2] + lc[2]) * m.ext[mu][3] + lc[3];
+}
+
+// is the link (lc, mu) inside the block?  (a block spanning the lattice keeps its wrap link)
+__device__ __forceinline__ bool link_internal(const Geom& g, int mu, const int lc[4]) {
+    return g.nb[mu] == 1 || lc[mu] < g.b[mu] - 1;
+}
+
+template <class T>
+__device__ __forceinline__ void su3_rebuild(cx<T> u[9]) {
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
 template <class T>
 __device__ __forceinline__ void lds_load(const cx<T>* buf, int bvh, int l, cx<T> v[12]) {
 #pragma unroll
@@ -456,35 +498,63 @@ __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T
     for (int c = 0; c < 12; c++) buf[c * bvh + l] = v[c];
 }
 
-// acc += sum over block-internal hops of the LDS field `buf` (opposite parity)
-template <class T>
-__device__ __forceinline__ void hop_internal(const FineOp<T>& op, int p, int i, const int x[4], int blk, int base,
-                                             const cx<T>* buf, cx<T> acc[12]) {
-    const Geom& g = op.g;
-#pragma unroll 1
-    for (int k = 0; k < 8; k++) {
-        int y[4];
-        nb_coords(g, x, k, y);
-        int j = cb_index(g, y);
-        if ((j >> g.lbvh) != blk) continue;
-        cx<T> v[12];
-        lds_load(buf, g.bvh, j - base, v);
-        hop_accum(op, k, p, i, j, v, acc);
+// layout index of neighbour k of x, written with selects only (no dynamically
+// indexed private arrays, so rolled loops stay in registers)
+__device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k) {
+    const int mu = k & 3;
+    const bool fwd = k < 4;
+    int y[4];
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        const int c = x[nu], d = g.d[nu];
+        const int stepped = fwd ? ((c + 1 == d) ? 0 : c + 1) : ((c == 0) ? d - 1 : c - 1);
+        y[nu] = (nu == mu) ? stepped : c;
     }
+    return cb_index(g, y);
+}
+
+// hop k of the site (p, i) owned by thread t.  tab[k][t] packs, for a hop
+// inside the block, the LDS slot of the link (<< 8) and the neighbour's local
+// index; -1 marks a hop that leaves the block.  INTERNAL_ONLY: only internal
+// hops, neighbour field from the LDS array `buf`; otherwise all hops with the
+// neighbour field from global memory `psi`.
+template <class T, bool INTERNAL_ONLY>
+__device__ __forceinline__ void sap_hop(const FineOp<T>& op, int ltot, const cx<T>* __restrict__ L,
+                                        const int* __restrict__ tab, int ntab, int k, int t, int p, int i,
+                                        const int x[4], int base, const cx<T>* buf, const cx<T>* __restrict__ psi,
+                                        cx<T> acc[12]) {
+    const Geom& g = op.g;
+    const int code = tab[k * ntab + t];
+    if (INTERNAL_ONLY && code < 0) return;
+    const int mu = k & 3;
+    const bool fwd = k < 4;
+    const int j = (code >= 0) ? base + (code & 255) : nb_index_sel(g, x, k);
+    cx<T> v[12], u[9], h[6], gg[6];
+    if (INTERNAL_ONLY) lds_load(buf, g.bvh, j - base, v);
+    else load_spinor(psi, g.vh, 1 - p, j, v);
+    if (code >= 0) {
+        const int li = code >> 8;
+#pragma unroll
+        for (int e = 0; e < 6; e++) u[e] = L[e * ltot + li];
+        su3_rebuild(u);
+    } else {
+        load_link(op, fwd ? p : 1 - p, mu, fwd ? i : j, u);
+    }
+    const T sgn = fwd ? T(-1) : T(1);
+    spin_project(mu, sgn, v, h);
+    su3_two_spinor(u, !fwd, h, gg);
+    spin_reconstruct(mu, sgn, gg, acc);
 }
 
 template <class T>
-__device__ __forceinline__ void hop_all(const FineOp<T>& op, int p, int i, const int x[4], const cx<T>* psi, cx<T> acc[12]) {
-    const Geom& g = op.g;
-#pragma unroll 1
-    for (int k = 0; k < 8; k++) {
-        int y[4];
-        nb_coords(g, x, k, y);
-        int j = cb_index(g, y);
-        cx<T> v[12];
-        load_spinor(psi, g.vh, 1 - p, j, v);
-        hop_accum(op, k, p, i, j, v, acc);
-    }
+__device__ __forceinline__ void clover_regs(const T* __restrict__ cl, int vh, int p, int i, T m[72]) {
+#pragma unroll
+    for (int r = 0; r < 72; r++) m[r] = cl[(size_t)(p * 72 + r) * vh + i];
+}
+template <class T>
+__device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12], cx<T> out[12]) {
+    herm6_apply(m, v, out);
+    herm6_apply(m + 36, v + 6, out + 6);
 }
 
 template <class T>
@@ -493,11 +563,15 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     extern __shared__ char smem_raw[];
     const Geom g = op.g;
     const int bvh = g.bvh;
-    cx<T>* E = reinterpret_cast<cx<T>*>(smem_raw);
-    cx<T>* O = E + 12 * bvh;
-    cx<T>* T0 = O + 12 * bvh;
-    cx<T>* EO = T0 + 12 * bvh;
-    double* red = reinterpret_cast<double*>(EO + 12 * bvh);
+    const int ntab = 2 * bvh;
+    LinkMap lm;
+    link_map(g, lm);
+    const int ltot = lm.total;
+    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [6][ltot] first two rows of internal links
+    cx<T>* E = L + 6 * ltot;                         // even field [12][bvh]
+    cx<T>* O = E + 12 * bvh;                         // odd field [12][bvh]
+    int* tab = reinterpret_cast<int*>(O + 12 * bvh);  // [8][2 bvh] packed hop table
+    double* red = reinterpret_cast<double*>(tab + 8 * ntab);
     const int blk = blocks[blockIdx.x];
     const int base = blk << g.lbvh;
     const int t = threadIdx.x;
@@ -508,26 +582,55 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     const bool ev = act && p == 0, od = act && p == 1;
     int x[4];
     cb_coords(g, p, i, x);
-    cx<T> acc[12], v[12], w[12];
+    if (act) {
+        int lc[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) lc[mu] = x[mu] & (g.b[mu] - 1);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int mu = k & 3;
+            int y[4];
+            nb_coords(g, x, k, y);
+            const int j = cb_index(g, y);
+            int slot = -1;
+            if ((j >> g.lbvh) == blk) {  // link joins two sites of the block
+                int lo[4] = {lc[0], lc[1], lc[2], lc[3]};
+                if (k >= 4) lo[mu] = (lc[mu] == 0) ? g.b[mu] - 1 : lc[mu] - 1;
+                slot = link_idx(lm, mu, lo);
+            }
+            tab[k * ntab + t] = (slot >= 0) ? ((slot << 8) | (j - base)) : -1;
+            // own forward link inside the block -> LDS (two rows)
+            if (k < 4 && slot >= 0) {
+                const cx<T>* src = op.U + (size_t)(p * 4 + mu) * 9 * g.vh + i;
+#pragma unroll
+                for (int e = 0; e < 6; e++) L[e * ltot + slot] = src[(size_t)e * g.vh];
+            }
+        }
+    }
+    // clover block of the site: A^{-1} on even, A on odd sites
+    T m[72];
+    clover_regs(p == 0 ? op.clovinv : op.clov, g.vh, p, i, m);
+    __syncthreads();
+    cx<T> acc[12], v[12], w[12], pv[12];  // pv: t0 (even threads) or e_o (odd threads)
     // ---- residual on the block ----
     if (act) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_all(op, p, i, x, z, acc);
+#pragma unroll 1
+        for (int k = 0; k < 8; k++) sap_hop<T, false>(op, ltot, L, tab, ntab, k, t, p, i, x, base, nullptr, z, acc);
         load_spinor(b, g.vh, p, i, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];  // b - H z
         load_spinor(z, g.vh, p, i, acc);
         if (ev) {
-            clover_apply(op.clovinv, g.vh, 0, i, v, w);
+            clover_reg_apply(m, v, pv);
 #pragma unroll
-            for (int c = 0; c < 12; c++) w[c] -= acc[c];
-            lds_store(E, bvh, l, w);
-            lds_store(T0, bvh, l, w);
+            for (int c = 0; c < 12; c++) pv[c] -= acc[c];      // t0
+            lds_store(E, bvh, l, pv);
         } else {
-            clover_apply(op.clov, g.vh, 1, i, acc, w);
+            clover_reg_apply(m, acc, w);
 #pragma unroll
-            for (int c = 0; c < 12; c++) w[c] = v[c] - w[c];
+            for (int c = 0; c < 12; c++) w[c] = v[c] - w[c];   // r_o
             lds_store(O, bvh, l, w);
         }
     }
@@ -535,16 +638,17 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     if (od) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_internal(op, 1, i, x, blk, base, E, acc);
+#pragma unroll 1
+        for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
         lds_load(O, bvh, l, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) {
-            v[c] += T(0.5) * acc[c];
-            w[c] = czero<T>();
+            v[c] += T(0.5) * acc[c];  // rho = f_o
+            pv[c] = czero<T>();       // e_o = 0
         }
-        lds_store(O, bvh, l, v);   // rho = f_o
-        lds_store(EO, bvh, l, w);  // e_o = 0
     }
+    __syncthreads();
+    if (od) lds_store(O, bvh, l, v);
     __syncthreads();
     const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
     for (int it = 0; it < mr_steps; it++) {
@@ -552,21 +656,23 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
         if (ev) {
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-            hop_internal(op, 0, i, x, blk, base, O, acc);
+#pragma unroll 1
+            for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
-            clover_apply(op.clovinv, g.vh, 0, i, acc, w);
-            lds_store(E, bvh, l, w);
+            clover_reg_apply(m, acc, w);
         }
+        __syncthreads();
+        if (ev) lds_store(E, bvh, l, w);
         __syncthreads();
         // odd: s = A rho - H_int t
         double sr = 0, si = 0, ss = 0;
         if (od) {
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-            hop_internal(op, 1, i, x, blk, base, E, acc);
-            lds_load(O, bvh, l, v);
-            clover_apply(op.clov, g.vh, 1, i, v, w);
+#pragma unroll 1
+            for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
+            clover_reg_apply(m, v, w);
 #pragma unroll
             for (int c = 0; c < 12; c++) {
                 w[c] += T(0.5) * acc[c];
@@ -585,43 +691,47 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
         for (int q = 0; q < nw; q++) { sr += red[3 * q]; si += red[3 * q + 1]; ss += red[3 * q + 2]; }
         if (od && ss > 0) {
             cx<T> alpha = {T(sr / ss), T(si / ss)};
-            lds_load(EO, bvh, l, acc);
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                acc[c] += alpha * v[c];
+                pv[c] += alpha * v[c];
                 v[c] -= alpha * w[c];
             }
-            lds_store(EO, bvh, l, acc);
-            lds_store(O, bvh, l, v);
         }
+        if (od) lds_store(O, bvh, l, (it + 1 < mr_steps) ? v : pv);
+        __syncthreads();
+    }
+    if (mr_steps == 0) {
+        if (od) lds_store(O, bvh, l, pv);
         __syncthreads();
     }
     // ---- back-substitution and update ----
     if (ev) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-        hop_internal(op, 0, i, x, blk, base, EO, acc);
+#pragma unroll 1
+        for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
-        clover_apply(op.clovinv, g.vh, 0, i, acc, w);
-        lds_load(T0, bvh, l, v);
+        clover_reg_apply(m, acc, w);
         load_spinor(z, g.vh, 0, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += v[c] + w[c];
+        for (int c = 0; c < 12; c++) acc[c] += pv[c] + w[c];
         store_spinor(z, g.vh, 0, i, acc);
     } else if (od) {
-        lds_load(EO, bvh, l, v);
         load_spinor(z, g.vh, 1, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += v[c];
+        for (int c = 0; c < 12; c++) acc[c] += pv[c];
         store_spinor(z, g.vh, 1, i, acc);
     }
 }
 
 template <class T>
-size_t sap_lds_bytes(int bvh) {
-    int nt = ((2 * bvh + 63) / 64) * 64;
-    return 4 * 12 * (size_t)bvh * sizeof(cx<T>) + 3 * sizeof(double) * (nt / 64);
+size_t fine_sap_lds_bytes(const Geom& g) {
+    LinkMap lm;
+    link_map(g, lm);
+    int nt = ((2 * g.bvh + 63) / 64) * 64;
+    return (6 * (size_t)lm.total + 24 * (size_t)g.bvh) * sizeof(cx<T>) + 8 * 2 * (size_t)g.bvh * sizeof(int) +
+           3 * sizeof(double) * (nt / 64);
 }
 
 template <class T>
@@ -629,7 +739,7 @@ void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx
                    hipStream_t s) {
     if (nblocks <= 0) return;
     int nt = ((2 * op.g.bvh + 63) / 64) * 64;
-    size_t lds = sap_lds_bytes<T>(op.g.bvh);
+    size_t lds = fine_sap_lds_bytes<T>(op.g);
     static size_t configured = 0;
     if (lds > 65536 && lds > configured) {
         (void)hipFuncSetAttribute((const void*)k_sap_fine<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -975,7 +1085,8 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
     template void fine_prolong<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);      \
     template void fine_gram_schmidt<T>(const AggMap&, int, const cx<T>*, cx<T>*, int*, hipStream_t);         \
     template void fine_assemble<T>(const FineOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t); \
-    template void fine_random<T>(const Geom&, int, unsigned long long, int, cx<T>*, hipStream_t);
+    template void fine_random<T>(const Geom&, int, unsigned long long, int, cx<T>*, hipStream_t);            \
+    template size_t fine_sap_lds_bytes<T>(const Geom&);
 
 DD_FINE_INST(double)
 DD_FINE_INST(float)

@@ -55,6 +55,8 @@ template <class T> void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* 
 template <class T>
 void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                    hipStream_t s);
+// LDS bytes one SAP workgroup needs for the layout blocks of g
+template <class T> size_t fine_sap_lds_bytes(const Geom& g);
 // P columns: [N][2][12][vh] (N fine spinors); coarse vectors: [cvol][2N] (layout order)
 template <class T>
 void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);

@@ -961,6 +961,19 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
     bool same = true;
     for (int mu = 0; mu < 4; mu++) same = same && (C->g0.b[mu] == p.sap[0][mu]);
     if (!same) layout_fields(C, p.sap[0], C->gauge_canon, C->clover_canon);
+    {
+        int dev = 0, maxlds = 0, a = 0;
+        HIPX(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess) maxlds = std::max(maxlds, a);
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) maxlds = std::max(maxlds, a);
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+            maxlds = std::max(maxlds, a);
+        (void)hipGetLastError();
+        size_t need = (p.precision == 64) ? fine_sap_lds_bytes<double>(C->g0) : fine_sap_lds_bytes<float>(C->g0);
+        if (need > (size_t)maxlds)
+            fail(DD_EINVAL, "SAP blocks need " + std::to_string(need) + " bytes of LDS per workgroup at this precision; the "
+                            "device offers " + std::to_string(maxlds));
+    }
     // FP64 outer workspace: V (m+1) + Z (m, in preconditioner precision) + 2 temporaries
     const long n = 24L * C->g0.vh;
     size_t zbytes = (p.precision == 64) ? sizeof(cx<double>) : sizeof(cx<float>);
