@@ -76,6 +76,8 @@ typedef struct {
     int given_vectors;           /* 1: the setup starts from vectors installed with
                                     dd_set_test_vectors instead of drawing them            */
     unsigned long long seed;     /* counter-based RNG key for the initial test vectors     */
+    int max_rhs;                 /* right-hand sides one dd_solve_batch call can carry in
+                                    one batch (1..16); sizes the Krylov workspace          */
 } dd_params;
 
 typedef struct {
@@ -131,7 +133,12 @@ dd_status dd_setup(dd_ctx *ctx, int n_tv, const int block[4], int levels, const 
  * DD_ENUMERIC on NaN/Inf in b or breakdown. */
 dd_status dd_solve(dd_ctx *ctx, const double *b, double *x, double tol, dd_stats *stats);
 
-/* k right-hand sides solved one after another on the resident setup.
+/* k right-hand sides solved together on the resident setup: k independent
+ * FGMRES processes advance in lockstep and share every V-cycle launch (the SAP
+ * kernel loads each block operator once for all of them); a right-hand side
+ * leaves the batch when its own true residual reaches tol.  Batches larger
+ * than max_rhs are split.  The result of each right-hand side is the one a
+ * single solve computes, up to the summation order of the reductions.
  *   b, x  device complex128 [k][vol][4][3]
  *   stats array of k records or NULL */
 dd_status dd_solve_batch(dd_ctx *ctx, int k, const double *b, double *x, double tol, dd_stats *stats);

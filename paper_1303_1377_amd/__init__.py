@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("precision", C.c_int),
         ("given_vectors", C.c_int),
         ("seed", C.c_ulonglong),
+        ("max_rhs", C.c_int),
     ]
 
 
@@ -222,15 +223,16 @@ class Solver:
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, st.as_dict()
 
-    def solve_batch(self, b, tol=1e-10):
+    def solve_batch(self, b, tol=1e-10, allow_noconv=False):
+        """k right-hand sides [k][vol][4][3] in batches of at most max_rhs."""
         torch = _torch()
-        bb = _dev(b).reshape(-1, self.vol, 4, 3)
+        bb = _dev(b).reshape(-1, self.vol, 4, 3).contiguous()
         k = bb.shape[0]
         x = torch.empty_like(bb)
-        st = (Stats * k)()
-        self._check(library().dd_solve_batch(self.h, k, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()),
-                                             float(tol), st))
-        return x, [s.as_dict() for s in st]
+        st = (Stats * max(k, 1))()
+        rc = library().dd_solve_batch(self.h, k, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), st)
+        self._check(rc, ok=(0, -3) if allow_noconv else (0,))
+        return x, [s.as_dict() for s in st[:k]]
 
     def set_mass(self, m0):
         self._check(library().dd_set_mass(self.h, float(m0)))

@@ -3,6 +3,8 @@
 // The Arnoldi step needs the inner products V_i^H w of one new vector against
 // all basis vectors, then w -= V h and ||w||.  Accumulation is FP64 for every
 // storage precision; partial sums are combined in a fixed order.
+#include <algorithm>
+
 #include "dd_kernels.h"
 
 namespace dd {
@@ -11,7 +13,10 @@ static constexpr int MAXM = 32;        // basis vectors handled per launch
 static constexpr int RED_CHUNKS = 1024;  // chunks a reduced vector is cut into
 static constexpr int RED_NT = 256;
 
-size_t reduce_work_size(int m) { return sizeof(cx<double>) * (size_t)RED_CHUNKS * ((m < MAXM ? MAXM : m) + 1); }
+size_t reduce_work_size(int m, int nr) {
+    (void)m;
+    return sizeof(cx<double>) * (size_t)RED_CHUNKS * (MAXM + 1) * (size_t)(nr < 1 ? 1 : nr);
+}
 
 static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
 
@@ -47,6 +52,15 @@ static inline int grid_for(long n) {
     return (int)b;
 }
 
+static inline dim3 grid_b(long n, int nr) {
+    long b = (n + 255) / 256;
+    long cap = 4096 / (nr < 1 ? 1 : nr);
+    if (cap < 64) cap = 64;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b, (unsigned)(nr < 1 ? 1 : nr));
+}
+
 template <class D, class S>
 void vec_convert(long n, const cx<S>* in, cx<D>* out, hipStream_t s) {
     k_convert<D, S><<<grid_for(n), 256, 0, s>>>(n, in, out);
@@ -70,10 +84,10 @@ void vec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, hipStream_t s) 
 
 // ---- reductions ------------------------------------------------------------
 // The vector is cut into at most RED_CHUNKS chunks.  multidot runs one
-// workgroup per (chunk, basis vector) and writes the chunk's partial inner
-// product; update_norm runs one workgroup per chunk.  A one-workgroup kernel
-// then adds the partials in chunk order, so the result does not depend on
-// scheduling.
+// workgroup per (chunk, basis vector, right-hand side) and writes the chunk's
+// partial inner product; update_norm runs one workgroup per (chunk, RHS).  A
+// small kernel then adds the partials in chunk order, so the results do not
+// depend on scheduling.
 static inline int red_chunks(long n) {
     long c = (n + 255) / 256;
     if (c > RED_CHUNKS) c = RED_CHUNKS;
@@ -91,102 +105,149 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return s;
 }
 
+// part[(r*nc + c)*m + i] = chunk c of V_i^H w for RHS r
 template <class T>
-__global__ void __launch_bounds__(RED_NT) k_multidot(long n, long chunk, const cx<T>* __restrict__ V, long ldv,
-                                                     const cx<T>* __restrict__ w, cx<double>* __restrict__ part, int m) {
+__global__ void __launch_bounds__(RED_NT) k_multidot(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
+                                                     long ldv, const cx<T>* __restrict__ w, cx<double>* __restrict__ part,
+                                                     long ldr, long ldw, Mask mk) {
+    const int c = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
+    if (!mk.on(r)) return;
     __shared__ double sh[2][RED_NT / 64];
-    const int c = blockIdx.x, i = blockIdx.y;
     const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
-    const cx<T>* v = V + (size_t)i * ldv;
+    const cx<T>* v = V + r * ldr + (size_t)i * ldv;
+    const cx<T>* ww = w + r * ldw;
     double re = 0, im = 0;
     for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
-        cx<T> a = v[e], b = w[e];
+        cx<T> a = v[e], b = ww[e];
         re += (double)a.re * b.re + (double)a.im * b.im;
         im += (double)a.re * b.im - (double)a.im * b.re;
     }
     re = block_sum256(re, sh[0]);
     im = block_sum256(im, sh[1]);
-    if (threadIdx.x == 0) part[(size_t)c * m + i] = cx<double>{re, im};
+    if (threadIdx.x == 0) part[((size_t)r * nc + c) * m + i] = cx<double>{re, im};
 }
 
-// one workgroup per output: strided partial sums, then a fixed-shape tree
-__global__ void __launch_bounds__(RED_NT) k_final_sum(int nchunk, int m, const cx<double>* __restrict__ part,
-                                                      cx<double>* __restrict__ out) {
+// out[r*ostride + i] = sum_c part[(r*nc + c)*m + i]; one workgroup per (i, r)
+__global__ void __launch_bounds__(RED_NT) k_final_sum(int nc, int m, const cx<double>* __restrict__ part,
+                                                      cx<double>* __restrict__ out, int ostride, Mask mk) {
+    const int i = blockIdx.x, r = blockIdx.y;
+    if (!mk.on(r)) return;
     __shared__ double sh[2][RED_NT / 64];
-    const int i = blockIdx.x;
     double re = 0, im = 0;
-    for (int c = threadIdx.x; c < nchunk; c += RED_NT) {
-        cx<double> v = part[(size_t)c * m + i];
+    for (int c = threadIdx.x; c < nc; c += RED_NT) {
+        cx<double> v = part[((size_t)r * nc + c) * m + i];
         re += v.re;
         im += v.im;
     }
     re = block_sum256(re, sh[0]);
     im = block_sum256(im, sh[1]);
-    if (threadIdx.x == 0) out[i] = cx<double>{re, im};
+    if (threadIdx.x == 0) out[(size_t)r * ostride + i] = cx<double>{re, im};
 }
 
+// w -= sum_i h_i V_i ; npart[r*nc + c] = chunk c of ||w||^2.  With hpart != 0
+// the inner products are first summed from the multidot partials.
 template <class T>
-__global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int m, const cx<T>* __restrict__ V, long ldv,
-                                                        const cx<double>* __restrict__ h, cx<T>* __restrict__ w,
-                                                        cx<double>* __restrict__ part) {
+__global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
+                                                        long ldv, const cx<double>* __restrict__ h, int hstride,
+                                                        const cx<double>* __restrict__ hpart, cx<double>* hout,
+                                                        cx<T>* __restrict__ w, cx<double>* __restrict__ npart, long ldr,
+                                                        long ldw, Mask mk) {
+    const int c = blockIdx.x, r = blockIdx.y;
+    if (!mk.on(r)) return;
     __shared__ double sh[RED_NT / 64];
     __shared__ cx<T> hh[MAXM];
-    if (threadIdx.x < m) hh[threadIdx.x] = ccast<T>(h[threadIdx.x]);
+    if (threadIdx.x < m) {
+        cx<double> hv;
+        if (hpart) {
+            hv = czero<double>();
+            for (int q = 0; q < nc; q++) hv += hpart[((size_t)r * nc + q) * m + threadIdx.x];
+            if (c == 0) hout[(size_t)r * hstride + threadIdx.x] = hv;
+        } else {
+            hv = h[(size_t)r * hstride + threadIdx.x];
+        }
+        hh[threadIdx.x] = ccast<T>(hv);
+    }
     __syncthreads();
-    const int c = blockIdx.x;
+    const cx<T>* Vr = V + r * ldr;
+    cx<T>* wr = w + r * ldw;
     const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
     double acc = 0;
     for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
-        cx<T> we = w[e];
-        for (int i = 0; i < m; i++) we -= hh[i] * V[(size_t)i * ldv + e];
-        w[e] = we;
+        cx<T> we = wr[e];
+#pragma unroll 4
+        for (int i = 0; i < m; i++) we -= hh[i] * Vr[(size_t)i * ldv + e];
+        wr[e] = we;
         acc += (double)norm2(we);
     }
     acc = block_sum256(acc, sh);
-    if (threadIdx.x == 0) part[c] = cx<double>{acc, 0.0};
+    if (threadIdx.x == 0) npart[(size_t)r * nc + c] = cx<double>{acc, 0.0};
+}
+
+static inline cx<double>* hpart_of(void* work) { return (cx<double>*)work; }
+static inline cx<double>* npart_of(void* work, int nr) {
+    return (cx<double>*)work + (size_t)RED_CHUNKS * MAXM * (nr < 1 ? 1 : nr);
 }
 
 template <class T>
 void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work, int* count,
-                  hipStream_t s) {
+                  hipStream_t s, RedBatch rb) {
     (void)count;
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
     for (int i0 = 0; i0 < m; i0 += MAXM) {
         int mm = (m - i0 < MAXM) ? m - i0 : MAXM;
-        dim3 grid(nc, mm);
-        k_multidot<T><<<grid, RED_NT, 0, s>>>(n, chunk, V + (size_t)i0 * ldv, ldv, w, (cx<double>*)work, mm);
-        k_final_sum<<<mm, RED_NT, 0, s>>>(nc, mm, (const cx<double>*)work, out + i0);
+        dim3 grid(nc, mm, rb.nr);
+        k_multidot<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, mm, V + (size_t)i0 * ldv, ldv, w, hpart_of(work), rb.ldr,
+                                              rb.ldw, rb.mk);
+        dim3 g2(mm, rb.nr);
+        k_final_sum<<<g2, RED_NT, 0, s>>>(nc, mm, hpart_of(work), out + i0, rb.ostride, rb.mk);
     }
 }
 
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                     void* work, int* count, hipStream_t s) {
+                     void* work, int* count, hipStream_t s, RedBatch rb) {
     (void)count;
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
     int i0 = 0;
     do {
         int mm = (m - i0 < MAXM) ? m - i0 : MAXM;
-        k_update_norm<T><<<nc, RED_NT, 0, s>>>(n, chunk, mm, V + (size_t)i0 * ldv, ldv, h + i0, w, (cx<double>*)work);
+        dim3 grid(nc, rb.nr);
+        k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, mm, V + (size_t)i0 * ldv, ldv, h + i0, rb.ostride, nullptr,
+                                                 nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
         i0 += mm;
     } while (i0 < m);
-    k_final_sum<<<1, RED_NT, 0, s>>>(nc, 1, (const cx<double>*)work, out);
+    dim3 g2(1, rb.nr);
+    k_final_sum<<<g2, RED_NT, 0, s>>>(nc, 1, npart_of(work, rb.nr), out, rb.ostride, rb.mk);
 }
 
-// ---- device-resident GMRES bookkeeping ------------------------------------
-__global__ void k_gm_start(GmDev* st, const cx<double>* beta2, double tol, int first, int m, int maxit, int fixed) {
+// ---- device-resident GMRES bookkeeping (one state per right-hand side) -----
+__global__ void k_gm_start(GmDev* st0, const cx<double>* res, int rstride, double tol, int first, int m, int maxit,
+                           int fixed, Mask mk) {
     if (threadIdx.x != 0) return;
-    double beta = sqrt(beta2->re);
+    GmDev* st = st0 + blockIdx.x;
     if (first) {
-        st->tol_abs = tol * beta;
         st->its = 0;
-        st->stop = (beta == 0.0) ? 1 : 0;
+        st->stop = 0;
         st->m = m;
         st->maxit = maxit;
         st->fixed = fixed;
     }
+    // a right-hand side outside the batch's mask, or one that stopped in an
+    // earlier cycle, contributes nothing to this cycle (j = 0)
+    if (!mk.on(blockIdx.x)) {
+        st->stop = 1;
+        st->j = 0;
+        st->scale = 0.0;
+        return;
+    }
+    if (!first && st->stop) {
+        st->j = 0;
+        return;
+    }
+    const double beta = sqrt(res[(size_t)blockIdx.x * rstride].re);
+    if (first) st->tol_abs = tol * beta;
     for (int i = 0; i < 33; i++) st->g[i] = czero<double>();
     for (int i = 0; i < 33 * 32; i++) st->H[i] = czero<double>();
     st->g[0] = cx<double>{beta, 0.0};
@@ -200,11 +261,13 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
     return cx<double>{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-__global__ void k_gm_column(GmDev* st, int j, const cx<double>* __restrict__ h, const cx<double>* __restrict__ hn2) {
+__global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
+    GmDev* st = st0 + blockIdx.x;
     if (threadIdx.x != 0 || st->stop) return;
+    const cx<double>* h = res + (size_t)blockIdx.x * rstride;
     cx<double>* col = st->H + (size_t)j * 33;
     for (int i = 0; i <= j; i++) col[i] = h[i];
-    double hn = sqrt(hn2->re);
+    double hn = sqrt(h[33].re);
     col[j + 1] = cx<double>{hn, 0.0};
     for (int i = 0; i < j; i++) {  // previous rotations
         cx<double> a = col[i], b = col[i + 1];
@@ -221,17 +284,18 @@ __global__ void k_gm_column(GmDev* st, int j, const cx<double>* __restrict__ h, 
     st->g[j] = conj(st->cs[j]) * st->g[j];
     st->its += 1;
     st->j = j + 1;
-    double res = sqrt(norm2(st->g[j + 1]));
+    double resid = sqrt(norm2(st->g[j + 1]));
     int stop = 0;
     if (st->fixed > 0) stop = st->its >= st->fixed;
-    else stop = (res <= st->tol_abs) || (st->its >= st->maxit);
+    else stop = (resid <= st->tol_abs) || (st->its >= st->maxit);
     if (hn == 0.0) stop = 1;
     st->stop = stop;
     st->scale = (hn > 0) ? 1.0 / hn : 0.0;
 }
 
-__global__ void k_gm_solve(GmDev* st) {
+__global__ void k_gm_solve(GmDev* st0) {
     if (threadIdx.x != 0) return;
+    GmDev* st = st0 + blockIdx.x;
     int k = st->j;
     for (int i = k - 1; i >= 0; i--) {
         cx<double> sacc = st->g[i];
@@ -240,28 +304,46 @@ __global__ void k_gm_solve(GmDev* st) {
     }
 }
 
-void gm_start(GmDev* st, const cx<double>* beta2, double tol, int first, int m, int maxit, int fixed, hipStream_t s) {
-    k_gm_start<<<1, 64, 0, s>>>(st, beta2, tol, first, m, maxit, fixed);
+void gm_start(GmDev* st, const cx<double>* res, int rstride, double tol, int first, int m, int maxit, int fixed,
+              int nr, hipStream_t s, Mask mk) {
+    k_gm_start<<<nr, 64, 0, s>>>(st, res, rstride, tol, first, m, maxit, fixed, mk);
 }
-void gm_column(GmDev* st, int j, const cx<double>* h, const cx<double>* hn2, hipStream_t s) {
-    k_gm_column<<<1, 64, 0, s>>>(st, j, h, hn2);
+
+__global__ void k_gm_gather(const GmDev* st, int nr, int* out) {
+    const int r = threadIdx.x;
+    if (r < nr) {
+        out[3 * r] = st[r].j;
+        out[3 * r + 1] = st[r].its;
+        out[3 * r + 2] = st[r].stop;
+    }
 }
-void gm_solve(GmDev* st, hipStream_t s) { k_gm_solve<<<1, 64, 0, s>>>(st); }
+void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s) { k_gm_gather<<<1, 64, 0, s>>>(st, nr, out); }
+void gm_column(GmDev* st, int j, const cx<double>* res, int rstride, int nr, hipStream_t s) {
+    k_gm_column<<<nr, 64, 0, s>>>(st, j, res, rstride);
+}
+void gm_solve(GmDev* st, int nr, hipStream_t s) { k_gm_solve<<<nr, 64, 0, s>>>(st); }
 
 template <class T>
-__global__ void k_scale_dev(long n, const GmDev* st, cx<T>* __restrict__ x, int ignore_stop) {
+__global__ void k_scale_dev(long n, const GmDev* st0, cx<T>* __restrict__ x, int ignore_stop, long ld) {
+    const GmDev* st = st0 + blockIdx.y;
     if (!ignore_stop && st->stop) return;
+    x += blockIdx.y * ld;
     const T sc = T(st->scale);
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) x[e] = sc * x[e];
 }
 template <class T>
-void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop) {
-    k_scale_dev<T><<<grid_for(n), 256, 0, s>>>(n, st, x, ignore_stop ? 1 : 0);
+void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr, long ld) {
+    dim3 grid(grid_for(n), nr);
+    k_scale_dev<T><<<grid, 256, 0, s>>>(n, st, x, ignore_stop ? 1 : 0, ld);
 }
 
 template <class T>
-__global__ void k_lincomb_dev(long n, const cx<T>* __restrict__ V, long ldv, const GmDev* st, cx<T>* __restrict__ x) {
+__global__ void k_lincomb_dev(long n, const cx<T>* __restrict__ V, long ldv, const GmDev* st0, cx<T>* __restrict__ x,
+                              long ldr, long ldx) {
+    const GmDev* st = st0 + blockIdx.y;
     const int m = st->j;
+    V += blockIdx.y * ldr;
+    x += blockIdx.y * ldx;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         cx<double> sacc = ccast<double>(x[e]);
         for (int i = 0; i < m; i++) sacc += st->y[i] * ccast<double>(V[(size_t)i * ldv + e]);
@@ -269,105 +351,55 @@ __global__ void k_lincomb_dev(long n, const cx<T>* __restrict__ V, long ldv, con
     }
 }
 template <class T>
-void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s) {
-    k_lincomb_dev<T><<<grid_for(n), 256, 0, s>>>(n, V, ldv, st, x);
-}
-
-// skip-aware Arnoldi reductions: the multidot partials are summed by every
-// workgroup of the update kernel itself (fixed order), saving a launch
-template <class T>
-__global__ void __launch_bounds__(RED_NT) k_multidot_skip(long n, long chunk, const cx<T>* __restrict__ V, long ldv,
-                                                          const cx<T>* __restrict__ w, cx<double>* __restrict__ part,
-                                                          int m, const int* skip) {
-    if (*skip) return;
-    __shared__ double sh[2][RED_NT / 64];
-    const int c = blockIdx.x, i = blockIdx.y;
-    const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
-    const cx<T>* v = V + (size_t)i * ldv;
-    double re = 0, im = 0;
-    for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
-        cx<T> a = v[e], b = w[e];
-        re += (double)a.re * b.re + (double)a.im * b.im;
-        im += (double)a.re * b.im - (double)a.im * b.re;
-    }
-    re = block_sum256(re, sh[0]);
-    im = block_sum256(im, sh[1]);
-    if (threadIdx.x == 0) part[(size_t)c * m + i] = cx<double>{re, im};
+void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s, int nr, long ldr,
+                     long ldx) {
+    dim3 grid(grid_for(n), nr);
+    k_lincomb_dev<T><<<grid, 256, 0, s>>>(n, V, ldv, st, x, ldr, ldx);
 }
 
 template <class T>
-__global__ void __launch_bounds__(RED_NT) k_update_norm_skip(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
-                                                             long ldv, const cx<double>* __restrict__ hpart,
-                                                             cx<T>* __restrict__ w, cx<double>* __restrict__ hout,
-                                                             cx<double>* __restrict__ npart, const int* skip) {
-    if (*skip) return;
-    __shared__ double sh[RED_NT / 64];
-    __shared__ cx<T> hh[MAXM];
-    if (threadIdx.x < m) {
-        cx<double> sacc = czero<double>();
-        for (int c = 0; c < nc; c++) sacc += hpart[(size_t)c * m + threadIdx.x];
-        hh[threadIdx.x] = ccast<T>(sacc);
-        if (blockIdx.x == 0) hout[threadIdx.x] = sacc;
-    }
-    __syncthreads();
-    const int c = blockIdx.x;
-    const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
-    double acc = 0;
-    for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
-        cx<T> we = w[e];
-        for (int i = 0; i < m; i++) we -= hh[i] * V[(size_t)i * ldv + e];
-        w[e] = we;
-        acc += (double)norm2(we);
-    }
-    acc = block_sum256(acc, sh);
-    if (threadIdx.x == 0) npart[c] = cx<double>{acc, 0.0};
-}
-
-__global__ void k_final_norm_skip(int nchunk, const cx<double>* __restrict__ part, cx<double>* __restrict__ out,
-                                  const int* skip) {
-    if (*skip) return;
-    __shared__ double sh[RED_NT / 64];
-    double re = 0;
-    for (int c = threadIdx.x; c < nchunk; c += RED_NT) re += part[c].re;
-    re = block_sum256(re, sh);
-    if (threadIdx.x == 0) out[0] = cx<double>{re, 0.0};
-}
-
-// `out` receives h (m entries); `work` holds the multidot partials, followed
-// by RED_CHUNKS norm partials
-template <class T>
-void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work,
-                       const int* skip, hipStream_t s) {
-    (void)out;
+void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, void* work, hipStream_t s,
+                       RedBatch rb) {
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
-    dim3 grid(nc, m);
-    k_multidot_skip<T><<<grid, RED_NT, 0, s>>>(n, chunk, V, ldv, w, (cx<double>*)work, m, skip);
+    dim3 grid(nc, m, rb.nr);
+    k_multidot<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, w, hpart_of(work), rb.ldr, rb.ldw, rb.mk);
 }
+
+// h (summed from the multidot partials) goes to res + r*ostride, ||w||^2 to res + r*ostride + 33
 template <class T>
-void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                          void* work, const int* skip, hipStream_t s) {
+void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
+                          hipStream_t s, RedBatch rb) {
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
-    cx<double>* hpart = (cx<double>*)work;
-    cx<double>* npart = hpart + (size_t)RED_CHUNKS * MAXM;
-    k_update_norm_skip<T><<<nc, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, hpart, w, const_cast<cx<double>*>(h), npart, skip);
-    k_final_norm_skip<<<1, RED_NT, 0, s>>>(nc, npart, out, skip);
+    dim3 grid(nc, rb.nr);
+    k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
+                                             npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
+    dim3 g2(1, rb.nr);
+    k_final_sum<<<g2, RED_NT, 0, s>>>(nc, 1, npart_of(work, rb.nr), res + 33, rb.ostride, rb.mk);
 }
 
 template <class T, class X>
-__global__ void k_lincomb(long n, int m, const cx<T>* __restrict__ Z, long ldz, const cx<double>* __restrict__ y,
-                          cx<X>* __restrict__ x) {
+__global__ void k_lincomb(long n, Counts mc, const cx<T>* __restrict__ Z, long ldz, const cx<double>* __restrict__ y,
+                          cx<X>* __restrict__ x, long ldzr, int ystride, long ldx, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    const int m = mc.v[blockIdx.y];
+    Z += blockIdx.y * ldzr;
+    y += (size_t)blockIdx.y * ystride;
+    x += blockIdx.y * ldx;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        cx<double> s = ccast<double>(x[e]);
-        for (int i = 0; i < m; i++) s += y[i] * ccast<double>(Z[(size_t)i * ldz + e]);
-        x[e] = ccast<X>(s);
+        cx<double> sacc = ccast<double>(x[e]);
+        for (int i = 0; i < m; i++) sacc += y[i] * ccast<double>(Z[(size_t)i * ldz + e]);
+        x[e] = ccast<X>(sacc);
     }
 }
 
 template <class T, class X>
-void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s) {
-    k_lincomb<T, X><<<grid_for(n), 256, 0, s>>>(n, m, Z, ldz, y, x);
+void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s, int nr,
+                 long ldzr, int ystride, long ldx, Mask mk, const Counts* per) {
+    Counts mc;
+    for (int r = 0; r < MAX_RHS; r++) mc.v[r] = (per && r < nr) ? std::min(per->v[r], m) : m;
+    k_lincomb<T, X><<<grid_b(n, nr), 256, 0, s>>>(n, mc, Z, ldz, y, x, ldzr, ystride, ldx, mk);
 }
 
 template <class T>
@@ -382,21 +414,67 @@ void vec_finite_check(long n, const cx<T>* x, int* bad, hipStream_t s) {
     k_finite<T><<<grid_for(n), 256, 0, s>>>(n, x, bad);
 }
 
+
+// ---- batched element-wise operations (RHS r at base + r*ld, grid.y = RHS) --
+template <class D, class S>
+__global__ void k_convert_b(long n, const cx<S>* __restrict__ in, cx<D>* __restrict__ out, long ld, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ld;
+    out += blockIdx.y * ld;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        out[e] = ccast<D>(in[e]);
+}
+template <class T>
+__global__ void k_sub_b(long n, const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, cx<T>* __restrict__ out,
+                        long ld, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    const long o = blockIdx.y * ld;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        out[o + e] = a[o + e] - b[o + e];
+}
+template <class T>
+__global__ void k_scale_b(long n, Coefs c, cx<T>* __restrict__ x, long ld, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    x += blockIdx.y * ld;
+    const T f = T(c.v[blockIdx.y]);
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) x[e] = f * x[e];
+}
+__global__ void k_set_flags(int* d, unsigned bits, int n) {
+    if ((int)threadIdx.x < n) d[threadIdx.x] = (bits >> threadIdx.x) & 1u;
+}
+
+
+template <class D, class S>
+void bvec_convert(long n, const cx<S>* in, cx<D>* out, long ld, int nr, Mask mk, hipStream_t s) {
+    k_convert_b<D, S><<<grid_b(n, nr), 256, 0, s>>>(n, in, out, ld, mk);
+}
+template <class T>
+void bvec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, long ld, int nr, Mask mk, hipStream_t s) {
+    k_sub_b<T><<<grid_b(n, nr), 256, 0, s>>>(n, a, b, out, ld, mk);
+}
+template <class T>
+void bvec_scale(long n, const Coefs& c, cx<T>* x, long ld, int nr, Mask mk, hipStream_t s) {
+    k_scale_b<T><<<grid_b(n, nr), 256, 0, s>>>(n, c, x, ld, mk);
+}
+void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 64, 0, s>>>(d, bits, n); }
+
 #define DD_BLAS_INST(T)                                                                                            \
     template void vec_axpy<T>(long, cx<double>, const cx<T>*, cx<T>*, hipStream_t);                                \
     template void vec_xpay<T>(long, const cx<T>*, cx<double>, cx<T>*, hipStream_t);                                \
     template void vec_scale<T>(long, cx<double>, cx<T>*, hipStream_t);                                             \
     template void vec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);                               \
-    template void vec_multidot<T>(long, int, const cx<T>*, long, const cx<T>*, cx<double>*, void*, int*, hipStream_t); \
+    template void vec_multidot<T>(long, int, const cx<T>*, long, const cx<T>*, cx<double>*, void*, int*, hipStream_t, \
+                                  RedBatch);                                                                       \
     template void vec_update_norm<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*, int*, \
-                                     hipStream_t);                                                                 \
+                                     hipStream_t, RedBatch);                                                       \
     template void vec_finite_check<T>(long, const cx<T>*, int*, hipStream_t);                                     \
-    template void vec_scale_dev<T>(long, const GmDev*, cx<T>*, hipStream_t, bool);                                 \
-    template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t);                 \
-    template void vec_multidot_skip<T>(long, int, const cx<T>*, long, const cx<T>*, cx<double>*, void*, const int*, \
-                                       hipStream_t);                                                              \
-    template void vec_update_norm_skip<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*, \
-                                          const int*, hipStream_t);
+    template void bvec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, long, int, Mask, hipStream_t);            \
+    template void bvec_scale<T>(long, const Coefs&, cx<T>*, long, int, Mask, hipStream_t);                         \
+    template void vec_scale_dev<T>(long, const GmDev*, cx<T>*, hipStream_t, bool, int, long);                      \
+    template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t, int, long, long); \
+    template void vec_multidot_skip<T>(long, int, const cx<T>*, long, const cx<T>*, void*, hipStream_t, RedBatch);  \
+    template void vec_update_norm_skip<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t,  \
+                                          RedBatch);
 
 DD_BLAS_INST(double)
 DD_BLAS_INST(float)
@@ -404,8 +482,14 @@ template void vec_convert<double, float>(long, const cx<float>*, cx<double>*, hi
 template void vec_convert<float, double>(long, const cx<double>*, cx<float>*, hipStream_t);
 template void vec_convert<double, double>(long, const cx<double>*, cx<double>*, hipStream_t);
 template void vec_convert<float, float>(long, const cx<float>*, cx<float>*, hipStream_t);
-template void vec_lincomb<double, double>(long, int, const cx<double>*, long, const cx<double>*, cx<double>*, hipStream_t);
-template void vec_lincomb<float, double>(long, int, const cx<float>*, long, const cx<double>*, cx<double>*, hipStream_t);
-template void vec_lincomb<float, float>(long, int, const cx<float>*, long, const cx<double>*, cx<float>*, hipStream_t);
+template void bvec_convert<double, float>(long, const cx<float>*, cx<double>*, long, int, Mask, hipStream_t);
+template void bvec_convert<float, double>(long, const cx<double>*, cx<float>*, long, int, Mask, hipStream_t);
+template void bvec_convert<double, double>(long, const cx<double>*, cx<double>*, long, int, Mask, hipStream_t);
+#define DD_LINCOMB_INST(T, X) \
+    template void vec_lincomb<T, X>(long, int, const cx<T>*, long, const cx<double>*, cx<X>*, hipStream_t, int, long, int, long, Mask, \
+                                    const Counts*);
+DD_LINCOMB_INST(double, double)
+DD_LINCOMB_INST(float, double)
+DD_LINCOMB_INST(float, float)
 
 }  // namespace dd

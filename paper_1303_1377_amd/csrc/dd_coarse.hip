@@ -27,8 +27,14 @@ template <class T>
 __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, int par, int self_mode,
                                                                 const cx<T>* __restrict__ in1, int hop_sign,
                                                                 const cx<T>* in2, int post_inv, cx<T>* out,
-                                                                const int* skip) {
-    if (skip && *skip) return;
+                                                                Mask mk, long ld) {
+    if (!mk.on(blockIdx.y)) return;
+    {
+        const long off = blockIdx.y * ld;
+        if (in1) in1 += off;
+        if (in2) in2 += off;
+        out += off;
+    }
     __shared__ cx<T> part[CA_WAVES][64];
     __shared__ cx<T> buf[64];
     __shared__ const cx<T>* mat[9];
@@ -113,11 +119,12 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, 
 
 template <class T>
 void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s, const int* skip) {
+                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
     int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
     int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
     int nw = nslot >= 8 ? CA_WAVES : (post_inv || nslot > 0 ? 4 : 1);
-    k_coarse_apply<T><<<nsite, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, skip);
+    dim3 grid(nsite, nr);
+    k_coarse_apply<T><<<grid, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,7 +303,10 @@ __device__ __forceinline__ cx<T> row_apply(const cx<T>* __restrict__ A, int nd, 
 
 template <class T>
 __global__ void k_coarse_sap(CoarseOp<T> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
-                             cx<T>* __restrict__ z, int mr_steps) {
+                             cx<T>* __restrict__ z, int mr_steps, long ld, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    b += blockIdx.y * ld;
+    z += blockIdx.y * ld;
     extern __shared__ char smem_raw[];
     const Geom g = op.g;
     const int nd = op.nd, bvh = g.bvh;
@@ -397,11 +407,12 @@ __global__ void k_coarse_sap(CoarseOp<T> op, const int* __restrict__ blocks, con
 
 template <class T>
 void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                     hipStream_t s) {
+                     hipStream_t s, int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
     int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
     size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
-    k_coarse_sap<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps);
+    dim3 grid(nblocks, nr);
+    k_coarse_sap<T><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +433,10 @@ __device__ __forceinline__ void agg_site_c(const AggMap& m, const int xc[4], int
 // workgroup: coarser site; thread e < asz*ndf: (site s = e / ndf, row d = e % ndf)
 template <class T>
 __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
-                                  cx<T>* __restrict__ out) {
+                                  cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ldi;
+    out += blockIdx.y * ldo;
     extern __shared__ char smem_raw[];
     cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
     const int gc = blockIdx.x;
@@ -458,10 +472,12 @@ __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restr
 
 template <class T>
 __global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
-                                 cx<T>* __restrict__ out) {
+                                 cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long volf = 2L * m.f.vh;
-    if (e >= volf * ndf) return;
+    if (e >= volf * ndf || !mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ldi;
+    out += blockIdx.y * ldo;
     long gf = e / ndf;
     int d = (int)(e % ndf);
     int p = gf >= m.f.vh, i = (int)(gf - p * m.f.vh);
@@ -476,15 +492,19 @@ __global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<T>* __restri
 }
 
 template <class T>
-void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+                     int nr, long ldi, long ldo, Mask mk) {
     int nt = 256;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
-    k_coarse_restrict<T><<<2 * m.c.vh, nt, lds, s>>>(m, ndf, N, P, in, out);
+    dim3 grid(2 * m.c.vh, nr);
+    k_coarse_restrict<T><<<grid, nt, lds, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
 }
 template <class T>
-void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+                    int nr, long ldi, long ldo, Mask mk) {
     long tot = 2L * m.f.vh * ndf;
-    k_coarse_prolong<T><<<nblk_of(tot, 256), 256, 0, s>>>(m, ndf, N, P, in, out);
+    dim3 grid(nblk_of(tot, 256), nr);
+    k_coarse_prolong<T><<<grid, 256, 0, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
 }
 
 // modified Gram-Schmidt per (coarser site, half): rows = aggregate sites x ndf/2
@@ -656,15 +676,18 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
 
 #define DD_COARSE_INST(T)                                                                                                \
     template void coarse_apply<T>(const CoarseOp<T>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*, hipStream_t, \
-                                  const int*);                                                                      \
+                                  Mask, int, long);                                                                 \
     template void coarse_self_inverse<T>(const Geom&, int, const cx<T>*, cx<T>*, int*, hipStream_t);                  \
     template void coarse_import_vector<T>(const Geom&, int, int, const double*, cx<T>*, hipStream_t);                \
     template void coarse_export_vector<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
     template void coarse_export_blocks<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
     template void coarse_shift_diag<T>(const Geom&, int, double, cx<T>*, hipStream_t);                                \
-    template void coarse_sap_half<T>(const CoarseOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t);    \
-    template void coarse_restrict<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);      \
-    template void coarse_prolong<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);       \
+    template void coarse_sap_half<T>(const CoarseOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, int, \
+                                     long, Mask);                                                                   \
+    template void coarse_restrict<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long, \
+                                     long, Mask);                                                                   \
+    template void coarse_prolong<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long,  \
+                                    long, Mask);                                                                    \
     template void coarse_gram_schmidt<T>(const AggMap&, int, int, const cx<T>*, cx<T>*, int*, hipStream_t);          \
     template void coarse_assemble<T>(const CoarseOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t);     \
     template void coarse_random<T>(const Geom&, int, int, unsigned long long, int, cx<T>*, hipStream_t);

@@ -399,10 +399,13 @@ __device__ __forceinline__ void hop_accum(const FineOp<T>& op, int k, int p, int
 // one thread per site, both parities in one grid
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                               long ld, Mask mk) {
     const Geom g = op.g;
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= 2 * g.vh) return;
+    if (gid >= 2 * g.vh || !mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ld;
+    out += blockIdx.y * ld;
     int p = gid >= g.vh, i = gid - p * g.vh;
     int x[4];
     cb_coords(g, p, i, x);
@@ -427,8 +430,9 @@ __global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __rest
 }
 
 template <class T>
-void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s) {
-    k_dirac<T><<<nblk_of(2L * op.g.vh, 256), 256, 0, s>>>(op, in, out);
+void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
+    dim3 grid(nblk_of(2L * op.g.vh, 256), nr);
+    k_dirac<T><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,7 +563,8 @@ __device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12
 
 template <class T>
 __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __restrict__ blocks,
-                                                  const cx<T>* __restrict__ b, cx<T>* __restrict__ z, int mr_steps) {
+                                                  const cx<T>* __restrict__ b0, cx<T>* __restrict__ z0, int mr_steps,
+                                                  int nr, long ld, Mask mk) {
     extern __shared__ char smem_raw[];
     const Geom g = op.g;
     const int bvh = g.bvh;
@@ -611,6 +616,11 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     T m[72];
     clover_regs(p == 0 ? op.clovinv : op.clov, g.vh, p, i, m);
     __syncthreads();
+    const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int rhs = 0; rhs < nr; rhs++) {
+    if (!mk.on(rhs)) continue;
+    const cx<T>* __restrict__ b = b0 + rhs * ld;
+    cx<T>* __restrict__ z = z0 + rhs * ld;
     cx<T> acc[12], v[12], w[12], pv[12];  // pv: t0 (even threads) or e_o (odd threads)
     // ---- residual on the block ----
     if (act) {
@@ -650,7 +660,6 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     __syncthreads();
     if (od) lds_store(O, bvh, l, v);
     __syncthreads();
-    const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
     for (int it = 0; it < mr_steps; it++) {
         // even: t = A^{-1} (H_int rho), H = -1/2 hopsum
         if (ev) {
@@ -723,6 +732,8 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
         for (int c = 0; c < 12; c++) acc[c] += pv[c];
         store_spinor(z, g.vh, 1, i, acc);
     }
+    __syncthreads();  // the block fields are reused by the next right-hand side
+    }
 }
 
 template <class T>
@@ -736,7 +747,7 @@ size_t fine_sap_lds_bytes(const Geom& g) {
 
 template <class T>
 void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                   hipStream_t s) {
+                   hipStream_t s, int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
     int nt = ((2 * op.g.bvh + 63) / 64) * 64;
     size_t lds = fine_sap_lds_bytes<T>(op.g);
@@ -745,7 +756,7 @@ void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx
         (void)hipFuncSetAttribute((const void*)k_sap_fine<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         configured = lds;
     }
-    k_sap_fine<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps);
+    k_sap_fine<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -770,7 +781,10 @@ __device__ __forceinline__ void coarse_of(const AggMap& m, const int x[4], int x
 // out[k] for k < n: P^H in, 2N unknowns per coarse site (index h*N + k)
 template <class T>
 __global__ void k_restrict_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
-                                cx<T>* __restrict__ out) {
+                                cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ldi;
+    out += blockIdx.y * ldo;
     extern __shared__ char smem_raw[];
     cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][2N]
     const int gc = blockIdx.x;
@@ -813,10 +827,12 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<T>* __restrict__ P, co
 
 template <class T>
 __global__ void k_prolong_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
-                               cx<T>* __restrict__ out) {
+                               cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int vh = m.f.vh;
-    if (gid >= 2 * vh) return;
+    if (gid >= 2 * vh || !mk.on(blockIdx.y)) return;
+    in += blockIdx.y * ldi;
+    out += blockIdx.y * ldo;
     int p = gid >= vh, i = gid - p * vh;
     int x[4], xc[4];
     cb_coords(m.f, p, i, x);
@@ -839,14 +855,18 @@ __global__ void k_prolong_fine(AggMap m, int N, const cx<T>* __restrict__ P, con
 }
 
 template <class T>
-void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
+void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+                   long ldi, long ldo, Mask mk) {
     int nt = ((m.asz + 63) / 64) * 64;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
-    k_restrict_fine<T><<<2 * m.c.vh, nt, lds, s>>>(m, N, P, in, out);
+    dim3 grid(2 * m.c.vh, nr);
+    k_restrict_fine<T><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
 template <class T>
-void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s) {
-    k_prolong_fine<T><<<nblk_of(2L * m.f.vh, 256), 256, 0, s>>>(m, N, P, in, out);
+void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+                  long ldi, long ldo, Mask mk) {
+    dim3 grid(nblk_of(2L * m.f.vh, 256), nr);
+    k_prolong_fine<T><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,10 +1099,13 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
     template void fine_export_spinor<T>(const Geom&, const cx<T>*, double*, hipStream_t);                    \
     template void fine_import_vectors<T>(const Geom&, int, const double*, cx<T>*, hipStream_t);              \
     template void fine_export_vectors<T>(const Geom&, int, const cx<T>*, double*, hipStream_t);              \
-    template void fine_dirac<T>(const FineOp<T>&, const cx<T>*, cx<T>*, hipStream_t);                        \
-    template void fine_sap_half<T>(const FineOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t); \
-    template void fine_restrict<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);     \
-    template void fine_prolong<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);      \
+    template void fine_dirac<T>(const FineOp<T>&, const cx<T>*, cx<T>*, hipStream_t, int, long, Mask);      \
+    template void fine_sap_half<T>(const FineOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, int, \
+                                   long, Mask);                                                               \
+    template void fine_restrict<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long, \
+                                   long, Mask);                                                               \
+    template void fine_prolong<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long,  \
+                                  long, Mask);                                                                \
     template void fine_gram_schmidt<T>(const AggMap&, int, const cx<T>*, cx<T>*, int*, hipStream_t);         \
     template void fine_assemble<T>(const FineOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t); \
     template void fine_random<T>(const Geom&, int, unsigned long long, int, cx<T>*, hipStream_t);            \

@@ -30,6 +30,27 @@ struct CoarseOp {
     const cx<T>* Minv;
 };
 
+// which right-hand sides of a batch a launch works on: flag r at p[r*stride];
+// with invert = 1 a nonzero flag means "inactive" (e.g. a GMRES stop flag)
+struct Mask {
+    const int* p;
+    int stride;
+    int invert;
+    __host__ __device__ __forceinline__ bool on(int r) const {
+        return p == nullptr || ((p[(size_t)r * stride] != 0) != (invert != 0));
+    }
+};
+static inline Mask all_rhs() { return Mask{nullptr, 1, 0}; }
+
+// largest batch of right-hand sides, and per-RHS values passed by value
+static constexpr int MAX_RHS = 16;
+struct Coefs {
+    double v[MAX_RHS];   // one real factor per right-hand side
+};
+struct Counts {
+    int v[MAX_RHS];      // one count per right-hand side
+};
+
 // aggregation of a fine (or finer coarse) level onto the next coarser level
 struct AggMap {
     Geom f;        // finer level layout
@@ -50,18 +71,25 @@ void fine_clover_from_user(const Geom& g, const double* canonT, double m0, doubl
                            hipStream_t s);
 void fine_clover_shift(const Geom& g, double dm, double* clov, double* clovinv, int* bad, hipStream_t s);
 void fine_clover_export(const Geom& g, const double* packed, double* canon, hipStream_t s);
-template <class T> void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s);
-// one SAP half sweep: blocks listed in `blocks` (all of one colour)
+// Batched launches: nr right-hand sides, vector r at base + r*ld (complex
+// entries); RHS switched off by the mask are left untouched.
+template <class T>
+void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1, long ld = 0,
+                Mask mk = all_rhs());
+// one SAP half sweep: blocks listed in `blocks` (all of one colour); the block
+// operator is loaded once and applied to every right-hand side of the batch
 template <class T>
 void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                   hipStream_t s);
+                   hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs());
 // LDS bytes one SAP workgroup needs for the layout blocks of g
 template <class T> size_t fine_sap_lds_bytes(const Geom& g);
 // P columns: [N][2][12][vh] (N fine spinors); coarse vectors: [cvol][2N] (layout order)
 template <class T>
-void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
+                   long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
-void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
+                  long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
 void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
 template <class T>
@@ -77,7 +105,7 @@ enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 // for the sites of parity `par` (0, 1) or all sites (par < 0).
 template <class T>
 void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s, const int* skip = nullptr);
+                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
 template <class T> void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s);
 template <class T> void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s);
 template <class T> void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s);
@@ -85,11 +113,13 @@ template <class T> void coarse_export_blocks(const Geom& g, int nd, int nslot, c
 template <class T> void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s);
 template <class T>
 void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                     hipStream_t s);
+                     hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs());
 template <class T>
-void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+                     int nr = 1, long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
-void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s);
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+                    int nr = 1, long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
 void coarse_gram_schmidt(const AggMap& m, int ndf, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
 template <class T>
@@ -105,26 +135,48 @@ template <class T> void vec_scale(long n, cx<double> a, cx<T>* x, hipStream_t s)
 template <class T> void vec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, hipStream_t s); // out = a - b
 // out[i] = V_i^H w for i < m, V_i = V + i*ldv ; results in FP64 on the device.
 // `work` must hold reduce_work_size(m) bytes; `count` is an int zeroed once.
-size_t reduce_work_size(int m);
+size_t reduce_work_size(int m, int nr);
+// Batch layout of the reductions: RHS r uses basis V + r*ldr, vector w + r*ldw
+// and writes its results at out + r*ostride.
+struct RedBatch {
+    int nr;
+    long ldr, ldw;
+    int ostride;
+    Mask mk;
+};
+static inline RedBatch single_rhs() { return RedBatch{1, 0, 0, 0, all_rhs()}; }
 template <class T>
 void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work, int* count,
-                  hipStream_t s);
-// w -= sum_i h_i V_i (h in FP64 on the device), then out[0].re = ||w||^2
+                  hipStream_t s, RedBatch rb = single_rhs());
+// w -= sum_i h_i V_i (h in FP64 on the device, RHS r at h + r*ostride), then
+// out[0].re = ||w||^2
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                     void* work, int* count, hipStream_t s);
-// x += sum_i y_i Z_i (y in FP64 on the device)
+                     void* work, int* count, hipStream_t s, RedBatch rb = single_rhs());
+// x += sum_i y_i Z_i (y in FP64 on the device; RHS r: Z + r*ldzr, y + r*ystride, x + r*ldx)
+// over i < m, or i < per->v[r] when per-RHS counts are given
 template <class T, class X>
-void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s);
+void vec_lincomb(long n, int m, const cx<T>* Z, long ldz, const cx<double>* y, cx<X>* x, hipStream_t s, int nr = 1,
+                 long ldzr = 0, int ystride = 0, long ldx = 0, Mask mk = all_rhs(), const Counts* per = nullptr);
 template <class T>
 void vec_finite_check(long n, const cx<T>* x, int* bad, hipStream_t s);
+
+// batched element-wise operations: RHS r at base + r*ld, switched off by the mask
+template <class D, class S>
+void bvec_convert(long n, const cx<S>* in, cx<D>* out, long ld, int nr, Mask mk, hipStream_t s);
+template <class T>
+void bvec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, long ld, int nr, Mask mk, hipStream_t s);
+template <class T>
+void bvec_scale(long n, const Coefs& c, cx<T>* x, long ld, int nr, Mask mk, hipStream_t s);
+// d[r] = bit r of `bits` for r < n (device mask words written in stream order)
+void set_flags(int* d, unsigned bits, int n, hipStream_t s);
 
 // ---- device-resident GMRES(m) bookkeeping (coarsest level) -----------------
 // The Hessenberg matrix, Givens rotations, residual estimate and stop flag of
 // one restarted GMRES live on the device, so the host can enqueue several
 // Arnoldi steps between synchronisations; every kernel of a step returns at
 // once when `stop` is set.
-struct GmDev {
+struct alignas(16) GmDev {
     cx<double> H[33 * 32];   // rotated Hessenberg, column j at H[j*33 + i]
     cx<double> cs[32], sn[32], g[33], y[32];
     double tol_abs;          // stop when |g_{j+1}| <= tol_abs
@@ -134,22 +186,31 @@ struct GmDev {
     int stop;                // converged, iteration cap or exact solution
     int m, maxit, fixed;
 };
-// beta^2 from the norm reduction result; first cycle also fixes tol_abs
-void gm_start(GmDev* st, const cx<double>* beta2, double tol, int first, int m, int maxit, int fixed, hipStream_t s);
-// fold column j (inner products h, norm^2 of the new vector) into the state
-void gm_column(GmDev* st, int j, const cx<double>* h, const cx<double>* hn2, hipStream_t s);
+// One state per right-hand side: st[r]; reduction results of RHS r at
+// res + r*rstride.  beta^2 from the norm reduction; first cycle also fixes tol_abs.
+// A right-hand side the mask switches off is marked stopped with no columns;
+// on a restart (first = 0) a stopped one keeps its iteration count and gets j = 0.
+void gm_start(GmDev* st, const cx<double>* res, int rstride, double tol, int first, int m, int maxit, int fixed,
+              int nr, hipStream_t s, Mask mk = all_rhs());
+// out[3r..3r+2] = {j, its, stop} of st[r] (one small transfer reads a batch)
+void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s);
+// fold column j (inner products h at res, norm^2 at res + 33) into the state
+void gm_column(GmDev* st, int j, const cx<double>* res, int rstride, int nr, hipStream_t s);
 // y = R^{-1} g for the st->j columns of the cycle
-void gm_solve(GmDev* st, hipStream_t s);
-// x *= st->scale (skipped once st->stop)
-template <class T> void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop);
-// x += sum_{i < st->j} y_i V_i
-template <class T> void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s);
-// skip-aware reductions for the device-resident Arnoldi step
+void gm_solve(GmDev* st, int nr, hipStream_t s);
+// x_r *= st[r].scale (skipped once st[r].stop unless ignore_stop)
 template <class T>
-void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work,
-                       const int* skip, hipStream_t s);
+void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr = 1, long ld = 0);
+// x_r += sum_{i < st[r].j} y_i V_i
 template <class T>
-void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                          void* work, const int* skip, hipStream_t s);
+void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s, int nr = 1,
+                     long ldr = 0, long ldx = 0);
+// Arnoldi reductions of the device-resident GMRES (RHS with st[r].stop skip)
+template <class T>
+void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, void* work, hipStream_t s,
+                       RedBatch rb);
+template <class T>
+void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
+                          hipStream_t s, RedBatch rb);
 
 }  // namespace dd

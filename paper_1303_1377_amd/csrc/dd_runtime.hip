@@ -149,11 +149,17 @@ struct Hess {
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
-struct HierBase {
-    virtual ~HierBase() {}
-};
-
 template <class T> struct Hier;
+
+// layout of the context's device int words (dflags)
+static const int DI_BAD = 0;        // error counter of the last checked step
+static const int DI_ONES = 16;      // MAX_RHS words that stay 1: "every RHS active"
+static const int DI_GATHER = 32;    // {j, its, stop} of each coarsest-GMRES state
+static const int DI_MASK = 128;     // per level: [cycle mask][current mask], MAX_RHS each
+static const int DI_WORDS = DI_MASK + 2 * MAX_RHS * DD_MAXLEV;
+// reduction results per right-hand side: pass-1 h (0..32), ||w||^2 (33),
+// pass-2 h (34..66), ||w||^2 (67)
+static const int RS = 136;
 
 struct dd_ctx {
     hipStream_t s = nullptr;
@@ -174,10 +180,13 @@ struct dd_ctx {
     cx<float>* U32 = nullptr;
     float* clov32 = nullptr;
     float* clovinv32 = nullptr;
-    int* dflags = nullptr;          // device ints: [0] bad, [1] reduction ticket, [2..] spare
-    cx<double>* dred = nullptr;     // device reduction results
+    int* dflags = nullptr;          // DI_WORDS device ints
+    cx<double>* dred = nullptr;     // MAX_RHS * RS reduction results
+    cx<double>* dy = nullptr;       // MAX_RHS * 32 least-squares solutions
     void* dwork = nullptr;          // reduction partials
-    cx<double>* hred = nullptr;     // pinned host mirror of dred
+    cx<double>* hred = nullptr;     // pinned mirror of dred
+    cx<double>* hy = nullptr;       // pinned staging of dy
+    int* hint = nullptr;            // pinned mirror of dflags
     dd_params p;
     bool configured = false, have_setup = false;
     std::unique_ptr<Hier<double>> H64;
@@ -191,16 +200,25 @@ struct dd_ctx {
     long prof_n[DD_K_NCLASS] = {0};
     double prof_ms[DD_K_NCLASS] = {0};
     double prof_bytes[DD_K_NCLASS] = {0};
-    // FP64 outer workspace
-    int outer_m = 0;
-    cx<double>* oV = nullptr;  // [m+1][n]
-    cx<double>* ob = nullptr;
-    cx<double>* ox = nullptr;
-    cx<double>* ot = nullptr;
+    // FP64 outer workspace for max_rhs right-hand sides
+    int R = 1;                 // slots of every batched vector set
+    cx<double>* oV = nullptr;  // basis: V_i of RHS r at oV + (i*R + r)*n
+    cx<double>* ob = nullptr;  // R right-hand sides
+    cx<double>* ox = nullptr;  // R solutions
+    cx<double>* ot = nullptr;  // 2R temporaries
     ~dd_ctx();
 };
 
-static const int RED_SLOTS = 4 * 34;  // 2 x (32 + 2) results
+// The right-hand sides one launch sequence works on: slots 0..nr-1 of every
+// vector set, active ones flagged on the device (d[r] = 1) and on the host.
+struct Batch {
+    int nr;
+    int* d;
+    unsigned h;
+    Mask mask() const { return Mask{d, 1, 0}; }
+    int count() const { return __builtin_popcount(h); }
+    bool on(int r) const { return (h >> r) & 1u; }
+};
 
 static hipEvent_t ev_get(dd_ctx* C) {
     if (C->ev_pool.empty()) {
@@ -257,20 +275,37 @@ struct Prof {
 };
 
 static int read_flag(dd_ctx* C, int idx) {
-    int v = 0;
-    HIPX(hipMemcpyAsync(&v, C->dflags + idx, sizeof(int), hipMemcpyDeviceToHost, C->s));
+    HIPX(hipMemcpyAsync(C->hint + idx, C->dflags + idx, sizeof(int), hipMemcpyDeviceToHost, C->s));
     sync(C);
-    return v;
+    return C->hint[idx];
 }
 static void clear_flag(dd_ctx* C, int idx) { HIPX(hipMemsetAsync(C->dflags + idx, 0, sizeof(int), C->s)); }
 
+// copy the reduction results of nr right-hand sides (first `cnt` slots each)
+static void read_red(dd_ctx* C, int nr, int cnt) {
+    HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * ((size_t)(nr - 1) * RS + cnt), hipMemcpyDeviceToHost, C->s));
+    sync(C);
+}
+
+static Batch single(dd_ctx* C) { return Batch{1, C->dflags + DI_ONES, 1u}; }
+
+// device mask words of `b` at dflags + DI_MASK + word, with host bits h
+static Batch with_mask(dd_ctx* C, const Batch& b, int word, unsigned h) {
+    Batch o{b.nr, C->dflags + DI_MASK + word, h};
+    set_flags(o.d, h, b.nr, C->s);
+    return o;
+}
+
 // ---------------------------------------------------------------------------
-// level hierarchy in preconditioner precision T
+// level hierarchy in preconditioner precision T.  Every level-l vector set has
+// R slots (RHS r at base + r*nlv(l)); a Krylov basis stores V_i of RHS r at
+// base + (i*R + r)*nlv(l), so basis vector i of a batch is again a vector set.
 // ---------------------------------------------------------------------------
 template <class T>
-struct Hier : HierBase {
+struct Hier {
     dd_ctx* C;
     int nlev;
+    int R;
     Geom g[DD_MAXLEV];
     int nd[DD_MAXLEV];
     FineOp<T> op0;
@@ -283,33 +318,32 @@ struct Hier : HierBase {
     cx<T>* P[DD_MAXLEV];
     cx<T>* M[DD_MAXLEV];
     cx<T>* Minv[DD_MAXLEV];
-    // per-level work vectors (full level vectors)
-    cx<T>* rc[DD_MAXLEV];   // restricted residual on level l (l >= 1)
-    cx<T>* ec[DD_MAXLEV];   // coarse correction on level l (l >= 1)
-    cx<T>* wa[DD_MAXLEV];   // scratch
+    cx<T>* rc[DD_MAXLEV];   // restricted residuals on level l (l >= 1)
+    cx<T>* ec[DD_MAXLEV];   // coarse corrections on level l (l >= 1)
+    cx<T>* wa[DD_MAXLEV];   // scratch sets
     cx<T>* wb[DD_MAXLEV];
     cx<T>* wc[DD_MAXLEV];
-    // Krylov workspaces: coarsest GMRES and middle-level FGMRES
-    cx<T>* kV[DD_MAXLEV];
-    cx<T>* kZ[DD_MAXLEV];
-    GmDev* gmst[DD_MAXLEV];
+    cx<T>* kV[DD_MAXLEV];   // Krylov bases (coarsest GMRES, middle FGMRES)
+    cx<T>* kZ[DD_MAXLEV];   // middle FGMRES preconditioned vectors
+    GmDev* gmst[DD_MAXLEV]; // R device GMRES states of the coarsest level
     int last_its[DD_MAXLEV];
-    long coarse_count[DD_MAXLEV];
+    long coarse_count[DD_MAXLEV][MAX_RHS];
 
     long nlv(int l) const { return 2L * g[l].vh * nd[l]; }   // complex entries of a level vector
 
-    // algorithmic bytes of one launch (model documented with the kernels)
-    double by_dirac() const { return 2.0 * g[0].vh * 192 * sizeof(T); }
-    double by_sap_half() const { return 1.0 * g[0].vh * 216 * sizeof(T); }
-    double by_coarse(int l, int nblk_per_site, int nvec_per_site, bool all_sites) const {
+    // algorithmic bytes of one launch for k right-hand sides (model documented
+    // with the kernels): operator data once, vector data once per RHS
+    double by_dirac(int k) const { return 2.0 * g[0].vh * (144 + 48.0 * k) * sizeof(T); }
+    double by_sap_half(int k) const { return 1.0 * g[0].vh * (144 + 72.0 * k) * sizeof(T); }
+    double by_coarse(int l, int nblk_per_site, int nvec_per_site, bool all_sites, int k) const {
         double sites = all_sites ? 2.0 * g[l].vh : 1.0 * g[l].vh;
-        return sites * ((double)nblk_per_site * nd[l] * nd[l] + (double)nvec_per_site * nd[l]) * 2 * sizeof(T);
+        return sites * ((double)nblk_per_site * nd[l] * nd[l] + (double)k * nvec_per_site * nd[l]) * 2 * sizeof(T);
     }
-    double by_transfer(int l) const {
-        // P (N vectors) + fine vector + coarse vector
-        return (double)nlv(l) * (N[l] + 1) * 2 * sizeof(T) + (double)nlv(l + 1) * 2 * sizeof(T);
+    double by_transfer(int l, int k) const {
+        // P (N vectors) + fine vector + coarse vector per RHS
+        return (double)nlv(l) * (N[l] + k) * 2 * sizeof(T) + (double)k * nlv(l + 1) * 2 * sizeof(T);
     }
-    double by_reduce(long n, int m) const { return (double)n * (m + 1) * 2 * sizeof(T); }
+    double by_reduce(long n, int m, int k) const { return (double)k * n * (m + 1) * 2 * sizeof(T); }
 
     Hier(dd_ctx* c) : C(c) {
         memset(blocks, 0, sizeof blocks);
@@ -324,17 +358,18 @@ struct Hier : HierBase {
     }
 
     void build_geometry();
-    void sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start);
-    void apply_D(int l, const cx<T>* in, cx<T>* out);
-    void restrict_(int l, const cx<T>* in, cx<T>* out);
-    void prolong(int l, const cx<T>* in, cx<T>* out);
-    void schur(int l, const cx<T>* v, cx<T>* out, const int* skip = nullptr);
-    long gmres_oe(int l, const cx<T>* r, cx<T>* e);
-    long fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e);
-    void vcycle(int l, int bottom, const cx<T>* r, cx<T>* z);
+    std::vector<double> norms(long n, const cx<T>* v, long ld, const Batch& b);
+    void sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start, const Batch& bt);
+    void apply_D(int l, const cx<T>* in, cx<T>* out, const Batch& bt);
+    void restrict_(int l, const cx<T>* in, cx<T>* out, const Batch& bt);
+    void prolong(int l, const cx<T>* in, cx<T>* out, const Batch& bt);
+    void schur(int l, const cx<T>* v, cx<T>* out, Mask mk, int nr, int k);
+    void gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt);
+    void fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e, const Batch& bt);
+    void vcycle(int l, int bottom, const cx<T>* r, cx<T>* z, const Batch& bt);
     void build(int l);
     void setup_level(int l, bool given);
-    double norm(long n, const cx<T>* v);
+    double norm1(long n, const cx<T>* v) { return norms(n, v, 0, single(C))[0]; }
 };
 
 dd_ctx::~dd_ctx() {
@@ -345,6 +380,8 @@ dd_ctx::~dd_ctx() {
     levels.release();
     fields.release();
     if (hred) (void)hipHostFree(hred);
+    if (hy) (void)hipHostFree(hy);
+    if (hint) (void)hipHostFree(hint);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,8 +404,9 @@ static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, co
     cx<float>* U32 = fresh.get<cx<float>>((size_t)C->vol * 36);
     float* clov32 = fresh.get<float>((size_t)C->vol * 72);
     float* clovinv32 = fresh.get<float>((size_t)C->vol * 72);
-    int* flags = fresh.get<int>(16);
-    HIPX(hipMemsetAsync(flags, 0, sizeof(int) * 16, C->s));
+    int* flags = fresh.get<int>(DI_WORDS);
+    HIPX(hipMemsetAsync(flags, 0, sizeof(int) * DI_WORDS, C->s));
+    set_flags(flags + DI_ONES, (1u << MAX_RHS) - 1, MAX_RHS, C->s);
     fine_import_gauge<double>(g, gcanon, U64, C->s);
     fine_import_gauge<float>(g, gcanon, U32, C->s);
     if (ccanon) fine_clover_from_user(g, ccanon, C->m0, clov, clovinv, flags, C->s);
@@ -378,9 +416,9 @@ static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, co
     vec_convert<float, double>((long)C->vol * 36, reinterpret_cast<const cx<double>*>(clovinv),
                                reinterpret_cast<cx<float>*>(clovinv32), C->s);
     HIPX(hipGetLastError());
-    int bad = 0;
-    HIPX(hipMemcpyAsync(&bad, flags, sizeof(int), hipMemcpyDeviceToHost, C->s));
+    HIPX(hipMemcpyAsync(C->hint, flags, sizeof(int), hipMemcpyDeviceToHost, C->s));
     HIPX(hipStreamSynchronize(C->s));
+    const int bad = C->hint[0];
     // swap arenas
     C->fields.release();
     C->fields.ptrs.swap(fresh.ptrs);
@@ -392,8 +430,9 @@ static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, co
     C->U64 = U64; C->clov64 = clov; C->clovinv64 = clovinv;
     C->U32 = U32; C->clov32 = clov32; C->clovinv32 = clovinv32;
     C->dflags = flags;
-    C->dred = C->fields.get<cx<double>>(RED_SLOTS);
-    C->dwork = C->fields.alloc(reduce_work_size(34));
+    C->dred = C->fields.get<cx<double>>((size_t)MAX_RHS * RS);
+    C->dy = C->fields.get<cx<double>>((size_t)MAX_RHS * 32);
+    C->dwork = C->fields.alloc(reduce_work_size(34, MAX_RHS));
     if (bad) fail(DD_ENUMERIC, "singular clover block on " + std::to_string(bad) + " sites");
 }
 
@@ -408,6 +447,7 @@ template <class T>
 void Hier<T>::build_geometry() {
     const dd_params& p = C->p;
     nlev = p.levels;
+    R = C->R;
     Arena& A = C->levels;
     g[0] = C->g0;
     nd[0] = 12;
@@ -427,12 +467,12 @@ void Hier<T>::build_geometry() {
             M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
             Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
             cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l]};
-            rc[l] = A.get<cx<T>>(nlv(l));
-            ec[l] = A.get<cx<T>>(nlv(l));
+            rc[l] = A.get<cx<T>>((size_t)R * nlv(l));
+            ec[l] = A.get<cx<T>>((size_t)R * nlv(l));
         }
-        wa[l] = A.get<cx<T>>(nlv(l));
-        wb[l] = A.get<cx<T>>(nlv(l));
-        wc[l] = A.get<cx<T>>(nlv(l));
+        wa[l] = A.get<cx<T>>((size_t)R * nlv(l));
+        wb[l] = A.get<cx<T>>((size_t)R * nlv(l));
+        wc[l] = A.get<cx<T>>((size_t)R * nlv(l));
         if (l < nlev - 1) {
             // SAP block lists by colour (red = even sum of block coordinates)
             std::vector<int> lists[2];
@@ -474,218 +514,325 @@ void Hier<T>::build_geometry() {
     // Krylov workspaces
     for (int l = 1; l < nlev; l++) {
         int m = (l == nlev - 1) ? C->p.coarse_restart : C->p.mid_restart;
-        kV[l] = A.get<cx<T>>((size_t)(m + 1) * nlv(l));
-        kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)m * nlv(l)) : nullptr;
-        gmst[l] = A.get<GmDev>(1);
+        kV[l] = A.get<cx<T>>((size_t)(m + 1) * R * nlv(l));
+        kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)m * R * nlv(l)) : nullptr;
+        gmst[l] = A.get<GmDev>(R);
     }
     HIPX(hipStreamSynchronize(C->s));
 }
 
 // ---------------------------------------------------------------------------
-// elementary steps
+// elementary steps (every one over the active right-hand sides of a batch)
 // ---------------------------------------------------------------------------
 template <class T>
-double Hier<T>::norm(long n, const cx<T>* v) {
-    vec_multidot<T>(n, 1, v, 0, v, C->dred, C->dwork, C->dflags + 1, C->s);
-    HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>), hipMemcpyDeviceToHost, C->s));
-    sync(C);
-    return std::sqrt(C->hred[0].re);
+std::vector<double> Hier<T>::norms(long n, const cx<T>* v, long ld, const Batch& b) {
+    RedBatch rb{b.nr, ld, ld, RS, b.mask()};
+    vec_multidot<T>(n, 1, v, 0, v, C->dred, C->dwork, nullptr, C->s, rb);
+    read_red(C, b.nr, 1);
+    std::vector<double> out(b.nr, 0.0);
+    for (int r = 0; r < b.nr; r++)
+        if (b.on(r)) out[r] = std::sqrt(C->hred[(size_t)r * RS].re);
+    return out;
 }
 
 template <class T>
-void Hier<T>::apply_D(int l, const cx<T>* in, cx<T>* out) {
-    Prof pr(C, l == 0 ? DD_K_DIRAC_PREC : DD_K_COARSE, l == 0 ? by_dirac() : by_coarse(l, 9, 2, true));
-    if (l == 0) fine_dirac<T>(op0, in, out, C->s);
-    else coarse_apply<T>(cop[l], -1, CS_SELF, in, 1, in, false, out, C->s);
+void Hier<T>::apply_D(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
+    Prof pr(C, l == 0 ? DD_K_DIRAC_PREC : DD_K_COARSE, l == 0 ? by_dirac(bt.count()) : by_coarse(l, 9, 2, true, bt.count()));
+    if (l == 0) fine_dirac<T>(op0, in, out, C->s, bt.nr, nlv(0), bt.mask());
+    else coarse_apply<T>(cop[l], -1, CS_SELF, in, 1, in, false, out, C->s, bt.mask(), bt.nr, nlv(l));
 }
 
 // nsweeps SAP iterations on level l (red blocks, then black blocks)
 template <class T>
-void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start) {
-    if (zero_start) HIPX(hipMemsetAsync(z, 0, sizeof(cx<T>) * nlv(l), C->s));
+void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start, const Batch& bt) {
+    if (zero_start) HIPX(hipMemsetAsync(z, 0, sizeof(cx<T>) * nlv(l) * bt.nr, C->s));
     for (int sw = 0; sw < nsweeps; sw++)
         for (int c = 0; c < 2; c++) {
-            Prof pr(C, l == 0 ? DD_K_SAP : DD_K_COARSE_SAP, l == 0 ? by_sap_half() : by_coarse(l, 9, 3, false));
-            if (l == 0) fine_sap_half<T>(op0, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s);
-            else coarse_sap_half<T>(cop[l], blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s);
+            Prof pr(C, l == 0 ? DD_K_SAP : DD_K_COARSE_SAP,
+                    l == 0 ? by_sap_half(bt.count()) : by_coarse(l, 9, 3, false, bt.count()));
+            if (l == 0)
+                fine_sap_half<T>(op0, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s, bt.nr, nlv(0), bt.mask());
+            else
+                coarse_sap_half<T>(cop[l], blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s, bt.nr, nlv(l), bt.mask());
         }
 }
 
 template <class T>
-void Hier<T>::restrict_(int l, const cx<T>* in, cx<T>* out) {
-    Prof pr(C, DD_K_RESTRICT, by_transfer(l));
-    if (l == 0) fine_restrict<T>(amap[0], N[0], P[0], in, out, C->s);
-    else coarse_restrict<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
+void Hier<T>::restrict_(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
+    Prof pr(C, DD_K_RESTRICT, by_transfer(l, bt.count()));
+    if (l == 0) fine_restrict<T>(amap[0], N[0], P[0], in, out, C->s, bt.nr, nlv(0), nlv(1), bt.mask());
+    else coarse_restrict<T>(amap[l], nd[l], N[l], P[l], in, out, C->s, bt.nr, nlv(l), nlv(l + 1), bt.mask());
 }
 
 template <class T>
-void Hier<T>::prolong(int l, const cx<T>* in, cx<T>* out) {
-    Prof pr(C, DD_K_PROLONG, by_transfer(l));
-    if (l == 0) fine_prolong<T>(amap[0], N[0], P[0], in, out, C->s);
-    else coarse_prolong<T>(amap[l], nd[l], N[l], P[l], in, out, C->s);
+void Hier<T>::prolong(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
+    Prof pr(C, DD_K_PROLONG, by_transfer(l, bt.count()));
+    if (l == 0) fine_prolong<T>(amap[0], N[0], P[0], in, out, C->s, bt.nr, nlv(1), nlv(0), bt.mask());
+    else coarse_prolong<T>(amap[l], nd[l], N[l], P[l], in, out, C->s, bt.nr, nlv(l + 1), nlv(l), bt.mask());
 }
 
-// out_o = (A_oo - D_oe A_ee^{-1} D_eo) v_o ; even part of out = 0
+// out_o = (A_oo - D_oe A_ee^{-1} D_eo) v_o ; the even part of out is not written
 template <class T>
-void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out, const int* skip) {
+void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out, Mask mk, int nr, int k) {
     // two launches, each over one parity: 8 hop blocks + (Minv | self) per site
-    Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false));
-    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s, skip);
-    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s, skip);
+    Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
+    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s, mk, nr, nlv(l));
+    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s, mk, nr, nlv(l));
 }
 
 // ---------------------------------------------------------------------------
 // coarsest level: odd-even GMRES(m) to relative residual coarse_tol (Sec. 5).
-// The Arnoldi bookkeeping lives on the device (GmDev); the host enqueues a
-// chunk of Arnoldi steps, sized from the previous solve on this level, then
-// reads back the step count and stop flag.  Steps enqueued after the stop
-// return at once.
+// The Arnoldi bookkeeping lives on the device, one GmDev per right-hand side,
+// so the host can enqueue a chunk of Arnoldi steps (sized from the previous
+// solve on this level) before it reads back the step counts and stop flags.
+// Every kernel of a step skips the right-hand sides whose flag is set, so the
+// RHS of a batch advance in lockstep and each one stops on its own residual.
 // ---------------------------------------------------------------------------
 template <class T>
-long Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e) {
+void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     const dd_params& p = C->p;
-    const int m = p.coarse_restart;
+    const int m = p.coarse_restart, nr = bt.nr, k = bt.count();
     const long nfull = nlv(l), nh = (long)g[l].vh * nd[l];
+    const long ldv = (long)R * nfull;   // basis stride
     cx<T>* V = kV[l];
     cx<T>* f = wa[l];
     cx<T>* t = wb[l];
     GmDev* st = gmst[l];
-    const int* skip = &st->stop;
+    const Mask live{&st->stop, (int)(sizeof(GmDev) / sizeof(int)), 1};
+    const Mask in = bt.mask();
     auto odd = [&](cx<T>* v) { return v + nh; };
     // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
     {
-        Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false) + by_coarse(l, 8, 3, false));
-        coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s);
-        coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s);
+        Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false, k) + by_coarse(l, 8, 3, false, k));
+        coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s, in, nr, nfull);
+        coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s, in, nr, nfull);
     }
-    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull, C->s));
-    HIPX(hipMemcpyAsync(odd(V), odd(f), sizeof(cx<T>) * nh, hipMemcpyDeviceToDevice, C->s));
-    vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, C->dflags + 1, C->s);
-    gm_start(st, C->dred, p.coarse_tol, 1, m, p.coarse_maxit, p.coarse_fixed, C->s);
-    vec_scale_dev<T>(nh, st, odd(V), C->s, true);
-    int hst[3] = {0, 0, 0};  // j, its, stop
+    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull * nr, C->s));
+    HIPX(hipMemcpyAsync(V, f, sizeof(cx<T>) * nfull * nr, hipMemcpyDeviceToDevice, C->s));
+    RedBatch rb0{nr, nfull, nfull, RS, in};
+    vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, nullptr, C->s, rb0);
+    gm_start(st, C->dred, RS, p.coarse_tol, 1, m, p.coarse_maxit, p.coarse_fixed, nr, C->s, in);
+    vec_scale_dev<T>(nh, st, odd(V), C->s, true, nr, nfull);
+    int* hs = C->hint + DI_GATHER;
     auto read_state = [&]() {
-        HIPX(hipMemcpyAsync(C->hred, &st->j, 3 * sizeof(int), hipMemcpyDeviceToHost, C->s));
+        gm_gather(st, nr, C->dflags + DI_GATHER, C->s);
+        HIPX(hipMemcpyAsync(hs, C->dflags + DI_GATHER, 3 * sizeof(int) * nr, hipMemcpyDeviceToHost, C->s));
         sync(C);
-        memcpy(hst, C->hred, sizeof hst);
+        for (int q = 0; q < nr; q++)
+            if (!hs[3 * q + 2]) return false;
+        return true;
     };
+    const RedBatch rb{nr, nfull, nfull, RS, live};
     int chunk = std::min(m, std::max(1, last_its[l] + 2));
     for (;;) {
         int j = 0;
-        bool stop = false;
+        bool all_stop = false;
         while (j < m) {
             const int jend = std::min(m, j + chunk);
             for (; j < jend; j++) {
-                cx<T>* w = V + (size_t)(j + 1) * nfull;
-                schur(l, V + (size_t)j * nfull, w, skip);
-                Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1));
-                vec_multidot_skip<T>(nh, j + 1, odd(V), nfull, odd(w), nullptr, C->dwork, skip, C->s);
-                vec_update_norm_skip<T>(nh, j + 1, odd(V), nfull, C->dred, odd(w), C->dred + 33, C->dwork, skip, C->s);
-                gm_column(st, j, C->dred, C->dred + 33, C->s);
-                vec_scale_dev<T>(nh, st, odd(w), C->s, false);
+                cx<T>* vj = V + (size_t)j * ldv;
+                cx<T>* w = V + (size_t)(j + 1) * ldv;
+                schur(l, vj, w, live, nr, k);
+                Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
+                vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, C->s, rb);
+                vec_update_norm_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, C->s, rb);
+                gm_column(st, j, C->dred, RS, nr, C->s);
+                vec_scale_dev<T>(nh, st, odd(w), C->s, false, nr, nfull);
             }
-            read_state();
-            if (hst[2]) { stop = true; break; }
-            j = hst[0];
+            if (read_state()) { all_stop = true; break; }
             chunk = 4;
         }
-        gm_solve(st, C->s);
-        vec_lincomb_dev<T>(nh, odd(V), nfull, st, odd(e), C->s);
-        if (stop) break;
-        // restart from the true Schur residual
-        schur(l, e, V);
-        vec_sub<T>(nh, odd(f), odd(V), odd(V), C->s);
-        vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, C->dflags + 1, C->s);
-        gm_start(st, C->dred, p.coarse_tol, 0, m, p.coarse_maxit, p.coarse_fixed, C->s);
-        vec_scale_dev<T>(nh, st, odd(V), C->s, true);
-        read_state();
-        if (hst[2]) break;
+        gm_solve(st, nr, C->s);
+        vec_lincomb_dev<T>(nh, odd(V), ldv, st, odd(e), C->s, nr, nfull, nfull);
+        if (all_stop) break;
+        // restart the running RHS from their true Schur residual
+        schur(l, e, V, live, nr, k);
+        bvec_sub<T>(nh, odd(f), odd(V), odd(V), nfull, nr, live, C->s);
+        vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, nullptr, C->s, rb);
+        gm_start(st, C->dred, RS, p.coarse_tol, 0, m, p.coarse_maxit, p.coarse_fixed, nr, C->s);
+        vec_scale_dev<T>(nh, st, odd(V), C->s, false, nr, nfull);
+        if (read_state()) break;
         chunk = 4;
     }
     // e_e = A_ee^{-1} (r_e - D_eo e_o)
     {
-        Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false));
-        coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s);
+        Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false, k));
+        coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s, in, nr, nfull);
     }
-    last_its[l] = hst[1];
-    return hst[1];
+    int mx = 0;
+    for (int q = 0; q < nr; q++) {
+        coarse_count[l][q] += hs[3 * q + 1];
+        mx = std::max(mx, hs[3 * q + 1]);
+    }
+    last_its[l] = mx;
 }
 
 // ---------------------------------------------------------------------------
-// middle levels: FGMRES(m) on D_c preconditioned by the V-cycle of level l
+// FGMRES(m) shared by the outer solver (FP64, level 0) and the middle levels
+// (precision T): k independent right-preconditioned Krylov processes in
+// lockstep with host-side Givens rotations, classical Gram-Schmidt with one
+// reorthogonalisation pass, and a true-residual restart.
 // ---------------------------------------------------------------------------
-template <class T>
-long Hier<T>::fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e) {
-    const dd_params& p = C->p;
-    const int m = p.mid_restart;
-    const long n = nlv(l);
-    cx<T>* V = kV[l];
-    cx<T>* Z = kZ[l];
-    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * n, C->s));
-    double bnorm = norm(n, r);
-    long its = 0;
-    if (bnorm == 0) return 0;
-    const long fixed = p.mid_fixed;
-    HIPX(hipMemcpyAsync(V, r, sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, C->s));
-    double beta = bnorm;
-    Hess hs(m);
-    for (;;) {
-        if (beta <= p.mid_tol * bnorm) break;
-        if (fixed > 0 ? its >= fixed : its >= p.mid_maxit) break;
-        hs.reset(beta);
-        vec_scale<T>(n, cx<double>{1.0 / beta, 0.0}, V, C->s);
-        int jend = 0;
-        for (int j = 0; j < m; j++) {
-            cx<T>* w = V + (size_t)(j + 1) * n;
-            vcycle(l, bottom, V + (size_t)j * n, Z + (size_t)j * n);
-            apply_D(l, Z + (size_t)j * n, w);
-            {
-                Prof pr(C, DD_K_REDUCE, 4 * by_reduce(n, j + 1));
-                vec_multidot<T>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
-                vec_update_norm<T>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
-                vec_multidot<T>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
-                vec_update_norm<T>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
-            }
-            HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
-            sync(C);
-            for (int i = 0; i <= j; i++)
-                hs.h(i, j) = zc(C->hred[i].re + C->hred[34 + i].re, C->hred[i].im + C->hred[34 + i].im);
-            double hn = std::sqrt(C->hred[67].re);
-            hs.h(j + 1, j) = hn;
-            double res = hs.rotate(j);
-            its++;
-            jend = j + 1;
-            if (hn > 0) vec_scale<T>(n, cx<double>{1.0 / hn, 0.0}, w, C->s);
-            if (fixed > 0) { if (its >= fixed) break; }
-            else if (res <= p.mid_tol * bnorm || its >= p.mid_maxit) break;
-            if (hn == 0) break;
-        }
-        hs.solve(jend);
-        std::vector<cx<double>> y(jend);
-        for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
-        HIPX(hipMemcpyAsync(C->dred + 70, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
-        vec_lincomb<T, T>(n, jend, Z, n, C->dred + 70, e, C->s);
-        // true residual for the restart decision
-        apply_D(l, e, V);
-        vec_sub<T>(n, r, V, V, C->s);
-        beta = norm(n, V);
-        if (fixed > 0 && its >= fixed) break;
+struct KrylovResult {
+    long its[MAX_RHS];
+    int restarts[MAX_RHS];
+    double relres[MAX_RHS];
+    bool conv[MAX_RHS];
+};
+
+// Ops supplies, for a batch: precond(j, V_j, Z_j, batch), matvec(Z_j -> w),
+// residual(x -> V_0 := r - A x over the batch) and the vector sets.
+template <class VS, class ZS, class Ops>
+static void fgmres_batch(dd_ctx* C, Ops& ops, long n, long ldv, int m, double tol, int maxit, long fixed,
+                         const Batch& in, int word, const std::vector<double>& bnorm, KrylovResult& out) {
+    const int nr = in.nr;
+    cx<VS>* V = ops.V();
+    cx<ZS>* Z = ops.Z();
+    std::vector<Hess> hs(nr, Hess(m));
+    std::vector<double> beta(bnorm);
+    unsigned alive = 0;
+    for (int r = 0; r < nr; r++) {
+        out.its[r] = 0;
+        out.restarts[r] = 0;
+        out.relres[r] = (in.on(r) && bnorm[r] > 0) ? 1.0 : 0.0;
+        out.conv[r] = !in.on(r) || bnorm[r] == 0;
+        if (in.on(r) && bnorm[r] > 0) alive |= 1u << r;
     }
-    return its;
+    for (;;) {
+        // which RHS run another cycle
+        unsigned cyc = 0;
+        for (int r = 0; r < nr; r++) {
+            if (!((alive >> r) & 1u)) continue;
+            out.relres[r] = beta[r] / bnorm[r];
+            if (beta[r] <= tol * bnorm[r]) { out.conv[r] = true; continue; }
+            if (fixed > 0 ? out.its[r] >= fixed : out.its[r] >= maxit) continue;
+            cyc |= 1u << r;
+        }
+        alive = cyc;
+        if (!cyc) break;
+        Batch bc = with_mask(C, in, word, cyc);
+        Coefs sc{};
+        for (int r = 0; r < nr; r++)
+            if ((cyc >> r) & 1u) { hs[r].reset(beta[r]); sc.v[r] = 1.0 / beta[r]; }
+        bvec_scale<VS>(n, sc, V, n, nr, bc.mask(), C->s);
+        Batch cur = with_mask(C, in, word + MAX_RHS, cyc);
+        int jend[MAX_RHS] = {0};
+        int jmax = 0;
+        for (int j = 0; j < m && cur.h; j++) {
+            cx<VS>* vj = V + (size_t)j * ldv;
+            cx<VS>* w = V + (size_t)(j + 1) * ldv;
+            cx<ZS>* zj = Z + (size_t)j * ldv;
+            ops.precond(vj, zj, cur);
+            ops.matvec(zj, w, cur);
+            {
+                RedBatch rb{nr, n, n, RS, cur.mask()};
+                Prof pr(C, DD_K_REDUCE, 4.0 * cur.count() * n * (j + 2) * sizeof(cx<VS>));
+                vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred, C->dwork, nullptr, C->s, rb);
+                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
+                vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
+                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb);
+            }
+            read_red(C, nr, 68);
+            unsigned next = cur.h;
+            Coefs wn{};
+            for (int r = 0; r < nr; r++) {
+                if (!cur.on(r)) continue;
+                const cx<double>* h = C->hred + (size_t)r * RS;
+                Hess& H = hs[r];
+                for (int i = 0; i <= j; i++) H.h(i, j) = zc(h[i].re + h[34 + i].re, h[i].im + h[34 + i].im);
+                double hn = std::sqrt(h[67].re);
+                if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
+                H.h(j + 1, j) = hn;
+                double res = H.rotate(j);
+                out.its[r]++;
+                jend[r] = j + 1;
+                jmax = std::max(jmax, j + 1);
+                bool stop;
+                if (fixed > 0) stop = out.its[r] >= fixed;
+                else stop = res <= tol * bnorm[r] || out.its[r] >= maxit;
+                if (hn == 0) stop = true;
+                if (stop) next &= ~(1u << r);
+                else wn.v[r] = 1.0 / hn;
+            }
+            if (next != cur.h) cur = with_mask(C, in, word + MAX_RHS, next);
+            if (next) bvec_scale<VS>(n, wn, w, n, nr, cur.mask(), C->s);
+        }
+        // x += Z y per RHS over the columns of its own cycle
+        for (int r = 0; r < nr; r++) {
+            cx<double>* y = C->hy + (size_t)r * 32;
+            if (!bc.on(r)) continue;
+            hs[r].solve(jend[r]);
+            for (int i = 0; i < jend[r]; i++) y[i] = cx<double>{hs[r].y[i].real(), hs[r].y[i].imag()};
+        }
+        HIPX(hipMemcpyAsync(C->dy, C->hy, sizeof(cx<double>) * 32 * nr, hipMemcpyHostToDevice, C->s));
+        Counts jc{};
+        for (int r = 0; r < nr; r++) jc.v[r] = jend[r];
+        ops.update(jmax, Z, ldv, C->dy, bc, jc);
+        // true residual of the cycle's RHS: restart vector and convergence test
+        ops.residual(bc);
+        std::vector<double> nb = ops.norms(V, bc);
+        for (int r = 0; r < nr; r++) {
+            if (!bc.on(r)) continue;
+            beta[r] = nb[r];
+            out.relres[r] = beta[r] / bnorm[r];
+            if (!std::isfinite(beta[r])) fail(DD_ENUMERIC, "non-finite residual");
+            if (fixed > 0 && out.its[r] >= fixed) {
+                out.conv[r] = beta[r] <= tol * bnorm[r];
+                alive &= ~(1u << r);
+            } else if (beta[r] > tol * bnorm[r]) {
+                out.restarts[r]++;
+            }
+        }
+    }
+}
+
+// middle levels: FGMRES(m) on D_c preconditioned by the V-cycle of level l
+template <class T>
+struct MidOps {
+    Hier<T>* H;
+    int l, bottom;
+    const cx<T>* r;
+    cx<T>* e;
+    cx<T>* V() { return H->kV[l]; }
+    cx<T>* Z() { return H->kZ[l]; }
+    void precond(const cx<T>* v, cx<T>* z, const Batch& b) { H->vcycle(l, bottom, v, z, b); }
+    void matvec(const cx<T>* z, cx<T>* w, const Batch& b) { H->apply_D(l, z, w, b); }
+    void update(int m, const cx<T>* Z, long ldz, const cx<double>* y, const Batch& b, const Counts& jc) {
+        const long n = H->nlv(l);
+        vec_lincomb<T, T>(n, m, Z, ldz, y, e, H->C->s, b.nr, n, 32, n, b.mask(), &jc);
+    }
+    void residual(const Batch& b) {
+        const long n = H->nlv(l);
+        H->apply_D(l, e, H->kV[l], b);
+        bvec_sub<T>(n, r, H->kV[l], H->kV[l], n, b.nr, b.mask(), H->C->s);
+    }
+    std::vector<double> norms(const cx<T>* v, const Batch& b) { return H->norms(H->nlv(l), v, H->nlv(l), b); }
+};
+
+template <class T>
+void Hier<T>::fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e, const Batch& bt) {
+    const dd_params& p = C->p;
+    const long n = nlv(l);
+    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * n * bt.nr, C->s));
+    std::vector<double> bn = norms(n, r, n, bt);
+    HIPX(hipMemcpyAsync(kV[l], r, sizeof(cx<T>) * n * bt.nr, hipMemcpyDeviceToDevice, C->s));
+    MidOps<T> ops{this, l, bottom, r, e};
+    KrylovResult res;
+    fgmres_batch<T, T>(C, ops, n, (long)R * n, p.mid_restart, p.mid_tol, p.mid_maxit, p.mid_fixed, bt,
+                               2 * MAX_RHS * l, bn, res);
+    for (int q = 0; q < bt.nr; q++) coarse_count[l][q] += res.its[q];
 }
 
 // ---------------------------------------------------------------------------
 // V-cycle: z = P e_c with e_c ~ D_c^{-1} P^H r, then nu SAP iterations
 // ---------------------------------------------------------------------------
 template <class T>
-void Hier<T>::vcycle(int l, int bottom, const cx<T>* r, cx<T>* z) {
-    restrict_(l, r, rc[l + 1]);
-    long its;
-    if (l + 1 == bottom) its = gmres_oe(l + 1, rc[l + 1], ec[l + 1]);
-    else its = fgmres_mid(l + 1, bottom, rc[l + 1], ec[l + 1]);
-    coarse_count[l + 1] += its;
-    prolong(l, ec[l + 1], z);
-    sap(l, r, z, C->p.nu, false);
+void Hier<T>::vcycle(int l, int bottom, const cx<T>* r, cx<T>* z, const Batch& bt) {
+    restrict_(l, r, rc[l + 1], bt);
+    if (l + 1 == bottom) gmres_oe(l + 1, rc[l + 1], ec[l + 1], bt);
+    else fgmres_mid(l + 1, bottom, rc[l + 1], ec[l + 1], bt);
+    prolong(l, ec[l + 1], z, bt);
+    sap(l, r, z, C->p.nu, false, bt);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,17 +840,17 @@ void Hier<T>::vcycle(int l, int bottom, const cx<T>* r, cx<T>* z) {
 // ---------------------------------------------------------------------------
 template <class T>
 void Hier<T>::build(int l) {
-    clear_flag(C, 0);
-    if (l == 0) fine_gram_schmidt<T>(amap[0], N[0], tv[0], P[0], C->dflags, C->s);
-    else coarse_gram_schmidt<T>(amap[l], nd[l], N[l], tv[l], P[l], C->dflags, C->s);
+    clear_flag(C, DI_BAD);
+    if (l == 0) fine_gram_schmidt<T>(amap[0], N[0], tv[0], P[0], C->dflags + DI_BAD, C->s);
+    else coarse_gram_schmidt<T>(amap[l], nd[l], N[l], tv[l], P[l], C->dflags + DI_BAD, C->s);
     HIPX(hipGetLastError());
-    if (read_flag(C, 0)) fail(DD_ENUMERIC, "rank-deficient aggregate on level " + std::to_string(l));
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "rank-deficient aggregate on level " + std::to_string(l));
     if (l == 0) fine_assemble<T>(op0, amap[0], N[0], P[0], M[1], C->s);
     else coarse_assemble<T>(cop[l], amap[l], N[l], P[l], M[l + 1], C->s);
     HIPX(hipGetLastError());
-    coarse_self_inverse<T>(g[l + 1], nd[l + 1], M[l + 1], Minv[l + 1], C->dflags, C->s);
+    coarse_self_inverse<T>(g[l + 1], nd[l + 1], M[l + 1], Minv[l + 1], C->dflags + DI_BAD, C->s);
     HIPX(hipGetLastError());
-    if (read_flag(C, 0)) fail(DD_ENUMERIC, "singular coarse self block on level " + std::to_string(l + 1));
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "singular coarse self block on level " + std::to_string(l + 1));
 }
 
 // Algorithm 2 on level l with level l+1 as the coarsest level of its V-cycles.
@@ -712,6 +859,7 @@ void Hier<T>::build(int l) {
 template <class T>
 void Hier<T>::setup_level(int l, bool given) {
     const long n = nlv(l);
+    const Batch one = single(C);
     if (!given) {
         if (l == 0) fine_random<T>(g[0], N[0], C->p.seed, l, tv[0], C->s);
         else coarse_random<T>(g[l], nd[l], N[l], C->p.seed, l, tv[l], C->s);
@@ -719,8 +867,8 @@ void Hier<T>::setup_level(int l, bool given) {
     for (int eta = 1; eta <= 3; eta++)
         for (int j = 0; j < N[l]; j++) {
             cx<T>* v = tv[l] + (size_t)j * n;
-            sap(l, v, wa[l], eta, true);
-            double nv = norm(n, wa[l]);
+            sap(l, v, wa[l], eta, true, one);
+            double nv = norm1(n, wa[l]);
             if (!(nv > 0) || !std::isfinite(nv)) fail(DD_ENUMERIC, "setup: vanishing or non-finite test vector");
             HIPX(hipMemcpyAsync(v, wa[l], sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, C->s));
             vec_scale<T>(n, cx<double>{1.0 / nv, 0.0}, v, C->s);
@@ -729,11 +877,11 @@ void Hier<T>::setup_level(int l, bool given) {
         build(l);
         for (int j = 0; j < N[l]; j++) {
             cx<T>* v = tv[l] + (size_t)j * n;
-            apply_D(l, v, wa[l]);
+            apply_D(l, v, wa[l], one);
             vec_sub<T>(n, v, wa[l], wa[l], C->s);
-            vcycle(l, l + 1, wa[l], wb[l]);
+            vcycle(l, l + 1, wa[l], wb[l], one);
             vec_axpy<T>(n, cx<double>{1.0, 0.0}, wb[l], v, C->s);
-            double nv = norm(n, v);
+            double nv = norm1(n, v);
             if (!(nv > 0) || !std::isfinite(nv)) fail(DD_ENUMERIC, "setup: vanishing or non-finite test vector");
             vec_scale<T>(n, cx<double>{1.0 / nv, 0.0}, v, C->s);
         }
@@ -741,112 +889,82 @@ void Hier<T>::setup_level(int l, bool given) {
     build(l);
 }
 
-static double norm64(dd_ctx* C, long n, const cx<double>* v) {
-    vec_multidot<double>(n, 1, v, 0, v, C->dred, C->dwork, C->dflags + 1, C->s);
-    HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>), hipMemcpyDeviceToHost, C->s));
-    sync(C);
-    return std::sqrt(C->hred[0].re);
-}
-
 // ---------------------------------------------------------------------------
 // outer FGMRES in FP64 with the T-precision V-cycle as right preconditioner
 // ---------------------------------------------------------------------------
 template <class T>
-static dd_status outer_fgmres(dd_ctx* C, Hier<T>& H, const cx<double>* b, cx<double>* x, double tol, long fixed,
-                              dd_stats* st) {
+struct OuterOps {
+    dd_ctx* C;
+    Hier<T>* H;
+    const cx<double>* b;
+    cx<double>* x;
+    long n;
+    cx<T>* Zb;
+    cx<double>* V() { return C->oV; }
+    cx<T>* Z() { return Zb; }
+    cx<T>* vT() { return reinterpret_cast<cx<T>*>(C->ot); }    // preconditioner-precision copies of v_j
+    cx<double>* t64() { return C->ot + (size_t)C->R * n; }
+    void precond(const cx<double>* v, cx<T>* z, const Batch& bt) {
+        {
+            Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * sizeof(T)));
+            bvec_convert<T, double>(n, v, vT(), n, bt.nr, bt.mask(), C->s);
+        }
+        H->vcycle(0, H->nlev - 1, vT(), z, bt);
+    }
+    void matvec(const cx<T>* z, cx<double>* w, const Batch& bt) {
+        {
+            Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * sizeof(T)));
+            bvec_convert<double, T>(n, z, t64(), n, bt.nr, bt.mask(), C->s);
+        }
+        Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
+        fine_dirac<double>(fine_op<double>(C), t64(), w, C->s, bt.nr, n, bt.mask());
+    }
+    void update(int m, const cx<T>* Z, long ldz, const cx<double>* y, const Batch& bt, const Counts& jc) {
+        vec_lincomb<T, double>(n, m, Z, ldz, y, x, C->s, bt.nr, n, 32, n, bt.mask(), &jc);
+    }
+    void residual(const Batch& bt) {
+        fine_dirac<double>(fine_op<double>(C), x, t64(), C->s, bt.nr, n, bt.mask());
+        bvec_sub<double>(n, b, t64(), C->oV, n, bt.nr, bt.mask(), C->s);
+    }
+    std::vector<double> norms(const cx<double>* v, const Batch& bt) { return norms64(C, n, v, bt); }
+    static std::vector<double> norms64(dd_ctx* C, long n, const cx<double>* v, const Batch& bt) {
+        RedBatch rb{bt.nr, n, n, RS, bt.mask()};
+        vec_multidot<double>(n, 1, v, 0, v, C->dred, C->dwork, nullptr, C->s, rb);
+        read_red(C, bt.nr, 1);
+        std::vector<double> out(bt.nr, 0.0);
+        for (int r = 0; r < bt.nr; r++)
+            if (bt.on(r)) out[r] = std::sqrt(C->hred[(size_t)r * RS].re);
+        return out;
+    }
+};
+
+// Solve the nr right-hand sides at C->ob into C->ox.
+template <class T>
+static void outer_fgmres(dd_ctx* C, Hier<T>& H, int nr, double tol, long fixed, dd_stats* st, dd_status* rc) {
     const dd_params& p = C->p;
     const int m = p.outer_restart;
     const long n = 24L * C->g0.vh;
-    FineOp<double> op = fine_op<double>(C);
-    cx<double>* V = C->oV;
-    cx<T>* Z = reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * n);
-    cx<T>* vT = reinterpret_cast<cx<T>*>(C->ot);  // preconditioner-precision copy of v_j
-    cx<double>* t64 = C->ot + n;
+    const long ldv = (long)C->R * n;
     memset(H.coarse_count, 0, sizeof H.coarse_count);
-    HIPX(hipMemsetAsync(x, 0, sizeof(cx<double>) * n, C->s));
-    clear_flag(C, 0);
-    vec_finite_check<double>(n, b, C->dflags, C->s);
-    if (read_flag(C, 0)) fail(DD_ENUMERIC, "NaN/Inf in the right-hand side");
-    double bnorm = norm64(C, n, b);
-    long its = 0;
-    int restarts = 0;
-    bool conv = false;
-    double relres = 1.0;
-    if (bnorm == 0) {
-        conv = true;
-        relres = 0;
-    } else {
-        HIPX(hipMemcpyAsync(V, b, sizeof(cx<double>) * n, hipMemcpyDeviceToDevice, C->s));
-        double beta = bnorm;
-        Hess hs(m);
-        for (;;) {
-            relres = beta / bnorm;
-            if (beta <= tol * bnorm) { conv = true; break; }
-            if (fixed > 0 ? its >= fixed : its >= p.outer_maxit) break;
-            hs.reset(beta);
-            vec_scale<double>(n, cx<double>{1.0 / beta, 0.0}, V, C->s);
-            int jend = 0;
-            for (int j = 0; j < m; j++) {
-                cx<double>* vj = V + (size_t)j * n;
-                cx<double>* w = V + (size_t)(j + 1) * n;
-                cx<T>* zj = Z + (size_t)j * n;
-                {
-                    Prof pr(C, DD_K_BLAS, (double)n * (16 + 2 * sizeof(T)));
-                    vec_convert<T, double>(n, vj, vT, C->s);
-                }
-                H.vcycle(0, H.nlev - 1, vT, zj);
-                {
-                    Prof pr(C, DD_K_BLAS, (double)n * (16 + 2 * sizeof(T)));
-                    vec_convert<double, T>(n, zj, t64, C->s);
-                }
-                {
-                    Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * 192 * 8);
-                    fine_dirac<double>(op, t64, w, C->s);
-                }
-                {
-                    Prof pr(C, DD_K_REDUCE, 4.0 * n * (j + 2) * 16);
-                    vec_multidot<double>(n, j + 1, V, n, w, C->dred, C->dwork, C->dflags + 1, C->s);
-                    vec_update_norm<double>(n, j + 1, V, n, C->dred, w, C->dred + 33, C->dwork, C->dflags + 1, C->s);
-                    vec_multidot<double>(n, j + 1, V, n, w, C->dred + 34, C->dwork, C->dflags + 1, C->s);
-                    vec_update_norm<double>(n, j + 1, V, n, C->dred + 34, w, C->dred + 67, C->dwork, C->dflags + 1, C->s);
-                }
-                HIPX(hipMemcpyAsync(C->hred, C->dred, sizeof(cx<double>) * 68, hipMemcpyDeviceToHost, C->s));
-                sync(C);
-                for (int i = 0; i <= j; i++)
-                    hs.h(i, j) = zc(C->hred[i].re + C->hred[34 + i].re, C->hred[i].im + C->hred[34 + i].im);
-                double hn = std::sqrt(C->hred[67].re);
-                if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
-                hs.h(j + 1, j) = hn;
-                double res = hs.rotate(j);
-                its++;
-                jend = j + 1;
-                if (hn > 0) vec_scale<double>(n, cx<double>{1.0 / hn, 0.0}, w, C->s);
-                if (fixed > 0) { if (its >= fixed) break; }
-                else if (res <= tol * bnorm || its >= p.outer_maxit) break;
-                if (hn == 0) break;
-            }
-            hs.solve(jend);
-            std::vector<cx<double>> y(jend);
-            for (int i = 0; i < jend; i++) y[i] = cx<double>{hs.y[i].real(), hs.y[i].imag()};
-            HIPX(hipMemcpyAsync(C->dred + 70, y.data(), sizeof(cx<double>) * jend, hipMemcpyHostToDevice, C->s));
-            vec_lincomb<T, double>(n, jend, Z, n, C->dred + 70, x, C->s);
-            // true residual in FP64 decides convergence; it is also the restart vector
-            fine_dirac<double>(op, x, t64, C->s);
-            vec_sub<double>(n, b, t64, V, C->s);
-            beta = norm64(C, n, V);
-            relres = beta / bnorm;
-            if (fixed > 0 && its >= fixed) { conv = beta <= tol * bnorm; break; }
-            restarts++;
-        }
+    HIPX(hipMemsetAsync(C->ox, 0, sizeof(cx<double>) * n * nr, C->s));
+    clear_flag(C, DI_BAD);
+    vec_finite_check<double>(n * nr, C->ob, C->dflags + DI_BAD, C->s);
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "NaN/Inf in a right-hand side");
+    Batch all{nr, C->dflags + DI_ONES, (nr >= 32) ? ~0u : ((1u << nr) - 1)};
+    std::vector<double> bn = OuterOps<T>::norms64(C, n, C->ob, all);
+    HIPX(hipMemcpyAsync(C->oV, C->ob, sizeof(cx<double>) * n * nr, hipMemcpyDeviceToDevice, C->s));
+    OuterOps<T> ops{C, &H, C->ob, C->ox, n, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
+    KrylovResult res;
+    fgmres_batch<double, T>(C, ops, n, ldv, m, tol, p.outer_maxit, fixed, all, 0, bn, res);
+    for (int r = 0; r < nr; r++) {
+        rc[r] = res.conv[r] ? DD_OK : DD_ENOCONV;
+        if (!st) continue;
+        st[r].outer_iters = (int)res.its[r];
+        st[r].restarts = res.restarts[r];
+        for (int l = 0; l < DD_MAXLEV; l++) st[r].coarse_iters[l] = H.coarse_count[l][r];
+        st[r].true_relres = res.relres[r];
+        st[r].converged = res.conv[r] ? 1 : 0;
     }
-    if (st) {
-        st->outer_iters = (int)its;
-        st->restarts = restarts;
-        for (int l = 0; l < DD_MAXLEV; l++) st->coarse_iters[l] = H.coarse_count[l];
-        st->true_relres = relres;
-        st->converged = conv ? 1 : 0;
-    }
-    return conv ? DD_OK : DD_ENOCONV;
 }
 
 
@@ -897,6 +1015,7 @@ void dd_default_params(dd_params* p) {
     p->precision = 64;
     p->given_vectors = 0;
     p->seed = 0x5eedULL;
+    p->max_rhs = 1;
 }
 
 const char* dd_last_error(const dd_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
@@ -921,7 +1040,9 @@ dd_status dd_create(dd_ctx** out, const int dims[4], const double* gauge, const 
         if (C->vol / 2 > 0x7fffffffL / 24) fail(DD_EINVAL, "lattice too large");
         C->m0 = m0;
         C->csw = csw;
-        HIPX(hipHostMalloc((void**)&C->hred, sizeof(cx<double>) * RED_SLOTS, hipHostMallocDefault));
+        HIPX(hipHostMalloc((void**)&C->hred, sizeof(cx<double>) * MAX_RHS * RS, hipHostMallocDefault));
+        HIPX(hipHostMalloc((void**)&C->hy, sizeof(cx<double>) * MAX_RHS * 32, hipHostMallocDefault));
+        HIPX(hipHostMalloc((void**)&C->hint, sizeof(int) * DI_WORDS, hipHostMallocDefault));
         int b[4];
         bool four = true;
         for (int mu = 0; mu < 4; mu++) { b[mu] = 4; if (dims[mu] % 4 || ((dims[mu] / 4) != 1 && ((dims[mu] / 4) & 1))) four = false; }
@@ -948,6 +1069,7 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
         p.mid_restart > 32)
         fail(DD_EINVAL, "restart lengths must be in 1..32");
     if (p.nu < 0 || p.n_inv < 0) fail(DD_EINVAL, "nu and n_inv must be >= 0");
+    if (p.max_rhs < 1 || p.max_rhs > MAX_RHS) fail(DD_EINVAL, "max_rhs must be in 1.." + std::to_string(MAX_RHS));
     if (!valid_layout(C->dims, p.sap[0], true))
         fail(DD_EINVAL, "SAP blocks must be powers of two dividing the lattice with an even block count (or 1) per dimension");
     if (p.sap[0][0] * p.sap[0][1] * p.sap[0][2] * p.sap[0][3] > 256) fail(DD_EINVAL, "fine SAP blocks hold at most 256 sites");
@@ -974,15 +1096,16 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
             fail(DD_EINVAL, "SAP blocks need " + std::to_string(need) + " bytes of LDS per workgroup at this precision; the "
                             "device offers " + std::to_string(maxlds));
     }
-    // FP64 outer workspace: V (m+1) + Z (m, in preconditioner precision) + 2 temporaries
-    const long n = 24L * C->g0.vh;
+    // FP64 outer workspace for R = max_rhs right-hand sides: V (m+1 sets),
+    // Z (m sets, preconditioner precision), b, x and two temporary sets
+    C->R = p.max_rhs;
+    const size_t nR = (size_t)24 * C->g0.vh * C->R;
     size_t zbytes = (p.precision == 64) ? sizeof(cx<double>) : sizeof(cx<float>);
-    size_t vbytes = sizeof(cx<double>) * (size_t)(p.outer_restart + 1) * n + zbytes * (size_t)p.outer_restart * n;
+    size_t vbytes = sizeof(cx<double>) * (size_t)(p.outer_restart + 1) * nR + zbytes * (size_t)p.outer_restart * nR;
     C->oV = reinterpret_cast<cx<double>*>(C->levels.alloc(vbytes));
-    C->ot = C->levels.get<cx<double>>(2 * (size_t)n);
-    C->ob = C->levels.get<cx<double>>((size_t)n);
-    C->ox = C->levels.get<cx<double>>((size_t)n);
-    C->outer_m = p.outer_restart;
+    C->ot = C->levels.get<cx<double>>(2 * nR);
+    C->ob = C->levels.get<cx<double>>(nR);
+    C->ox = C->levels.get<cx<double>>(nR);
     if (p.precision == 64) {
         C->H64.reset(new Hier<double>(C));
         C->H64->build_geometry();
@@ -1034,13 +1157,33 @@ dd_status dd_setup(dd_ctx* ctx, int n_tv, const int block[4], int levels, const 
     ABI_END(ctx)
 }
 
+// k right-hand sides (device, canonical layout) solved in batches of at most R
 template <class T>
-static dd_status solve_impl(dd_ctx* C, Hier<T>& H, const double* b, double* x, double tol, dd_stats* st) {
-    fine_import_spinor<double>(C->g0, b, C->ob, C->s);
-    dd_status rc = outer_fgmres<T>(C, H, C->ob, C->ox, tol, 0, st);
-    fine_export_spinor<double>(C->g0, C->ox, x, C->s);
-    sync(C);
-    return rc;
+static dd_status solve_impl(dd_ctx* C, Hier<T>& H, int k, const double* b, double* x, double tol, dd_stats* st) {
+    const long n = 24L * C->g0.vh;
+    const size_t canon = (size_t)24 * C->vol;
+    dd_status worst = DD_OK;
+    for (int q0 = 0; q0 < k; q0 += C->R) {
+        const int nr = std::min(C->R, k - q0);
+        const double t0 = now_s();
+        fine_import_vectors<double>(C->g0, nr, b + q0 * canon, C->ob, C->s);
+        dd_status rc[MAX_RHS];
+        dd_stats sb[MAX_RHS];
+        memset(sb, 0, sizeof sb);
+        outer_fgmres<T>(C, H, nr, tol, 0, sb, rc);
+        fine_export_vectors<double>(C->g0, nr, C->ox, x + q0 * canon, C->s);
+        HIPX(hipGetLastError());
+        sync(C);
+        const double dt = now_s() - t0;
+        (void)n;
+        for (int r = 0; r < nr; r++) {
+            sb[r].solve_s = dt;
+            sb[r].setup_s = C->last_setup_s;
+            if (st) st[q0 + r] = sb[r];
+            if (rc[r] != DD_OK && worst == DD_OK) worst = rc[r];
+        }
+    }
+    return worst;
 }
 
 dd_status dd_solve(dd_ctx* ctx, const double* b, double* x, double tol, dd_stats* st) {
@@ -1048,50 +1191,46 @@ dd_status dd_solve(dd_ctx* ctx, const double* b, double* x, double tol, dd_stats
     if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve before dd_setup");
     if (!b || !x) fail(DD_EINVAL, "NULL vector");
     if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
-    double t0 = now_s();
-    dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, b, x, tol, st) : solve_impl(ctx, *ctx->H32, b, x, tol, st);
-    if (st) {
-        st->solve_s = now_s() - t0;
-        st->setup_s = ctx->last_setup_s;
-    }
+    dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, 1, b, x, tol, st) : solve_impl(ctx, *ctx->H32, 1, b, x, tol, st);
     if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit";
     return rc;
     ABI_END(ctx)
 }
 
 dd_status dd_solve_batch(dd_ctx* ctx, int k, const double* b, double* x, double tol, dd_stats* st) {
-    if (!ctx) return DD_EINVAL;
-    if (k < 0) { ctx->err = "k < 0"; return DD_EINVAL; }
-    dd_status worst = DD_OK;
-    for (int q = 0; q < k; q++) {
-        dd_status rc = dd_solve(ctx, b + (size_t)q * 24 * ctx->vol, x + (size_t)q * 24 * ctx->vol, tol, st ? st + q : nullptr);
-        if (rc != DD_OK && worst == DD_OK) worst = rc;
-        if (rc != DD_OK && rc != DD_ENOCONV) return rc;
-    }
-    return worst;
+    ABI_TRY(ctx)
+    if (k < 0) fail(DD_EINVAL, "k < 0");
+    if (k == 0) return DD_OK;
+    if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve_batch before dd_setup");
+    if (!b || !x) fail(DD_EINVAL, "NULL vector");
+    if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
+    dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, k, b, x, tol, st) : solve_impl(ctx, *ctx->H32, k, b, x, tol, st);
+    if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit for at least one right-hand side";
+    return rc;
+    ABI_END(ctx)
 }
 
 dd_status dd_set_mass(dd_ctx* ctx, double m0) {
     ABI_TRY(ctx)
     double dm = m0 - ctx->m0;
-    clear_flag(ctx, 0);
-    fine_clover_shift(ctx->g0, dm, ctx->clov64, ctx->clovinv64, ctx->dflags, ctx->s);
+    clear_flag(ctx, DI_BAD);
+    fine_clover_shift(ctx->g0, dm, ctx->clov64, ctx->clovinv64, ctx->dflags + DI_BAD, ctx->s);
     vec_convert<float, double>((long)ctx->vol * 36, reinterpret_cast<const cx<double>*>(ctx->clov64),
                                reinterpret_cast<cx<float>*>(ctx->clov32), ctx->s);
     vec_convert<float, double>((long)ctx->vol * 36, reinterpret_cast<const cx<double>*>(ctx->clovinv64),
                                reinterpret_cast<cx<float>*>(ctx->clovinv32), ctx->s);
-    if (read_flag(ctx, 0)) fail(DD_ENUMERIC, "singular clover block after the mass shift");
+    if (read_flag(ctx, DI_BAD)) fail(DD_ENUMERIC, "singular clover block after the mass shift");
     ctx->m0 = m0;
     auto shift = [&](auto& H) {
         for (int l = 1; l < H.nlev; l++) {
             coarse_shift_diag(H.g[l], H.nd[l], dm, H.M[l], ctx->s);
-            coarse_self_inverse(H.g[l], H.nd[l], H.M[l], H.Minv[l], ctx->dflags, ctx->s);
+            coarse_self_inverse(H.g[l], H.nd[l], H.M[l], H.Minv[l], ctx->dflags + DI_BAD, ctx->s);
         }
     };
     if (ctx->configured) {
         if (ctx->H64) shift(*ctx->H64);
         else shift(*ctx->H32);
-        if (read_flag(ctx, 0)) fail(DD_ENUMERIC, "singular coarse self block after the mass shift");
+        if (read_flag(ctx, DI_BAD)) fail(DD_ENUMERIC, "singular coarse self block after the mass shift");
     }
     return DD_OK;
     ABI_END(ctx)
@@ -1235,7 +1374,7 @@ static double time_prec(dd_ctx* C, Hier<T>& H, int cls, int reps) {
     hipEvent_t a = ev_get(C), b = ev_get(C);
     // one untimed launch first
     if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
-    else H.sap(0, H.wa[0], H.wb[0], 1, false);
+    else H.sap(0, H.wa[0], H.wb[0], 1, false, single(C));
     HIPX(hipEventRecord(a, C->s));
     for (int r = 0; r < reps; r++) {
         if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
@@ -1300,6 +1439,7 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
         else coarse_export_vector<T>(H.g[lev], H.nd[lev], 1, src, dst, C->s);
     };
     const int bottom = H.nlev - 1;
+    const Batch one = single(C);
     switch (op) {
         case DD_OP_D:
             if (l == 0) {
@@ -1312,18 +1452,18 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
                 break;
             }
             imp(l, in, H.wa[l]);
-            H.apply_D(l, H.wa[l], H.wb[l]);
+            H.apply_D(l, H.wa[l], H.wb[l], one);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_D_PREC:
             imp(0, in, H.wa[0]);
-            H.apply_D(0, H.wa[0], H.wb[0]);
+            H.apply_D(0, H.wa[0], H.wb[0], one);
             exp_(0, H.wb[0], out);
             break;
         case DD_OP_SAP:
             if (l >= bottom) fail(DD_EINVAL, "no SAP on the coarsest level");
             imp(l, in, H.wa[l]);
-            H.sap(l, H.wa[l], H.wb[l], arg, true);
+            H.sap(l, H.wa[l], H.wb[l], arg, true, one);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_VCYCLE:
@@ -1331,32 +1471,34 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
             if (!C->have_setup) fail(DD_ESTATE, "hierarchy not built");
             imp(l, in, H.wa[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            H.vcycle(l, bottom, H.wa[l], H.wb[l]);
-            its = H.coarse_count[l + 1];
+            H.vcycle(l, bottom, H.wa[l], H.wb[l], one);
+            its = H.coarse_count[l + 1][0];
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_RESTRICT:
             if (l >= bottom) fail(DD_EINVAL, "no restriction from the coarsest level");
             imp(l, in, H.wa[l]);
-            H.restrict_(l, H.wa[l], H.wa[l + 1]);
+            H.restrict_(l, H.wa[l], H.wa[l + 1], one);
             exp_(l + 1, H.wa[l + 1], out);
             break;
         case DD_OP_PROLONG:
             if (l >= bottom) fail(DD_EINVAL, "no prolongation to the coarsest level");
             imp(l + 1, in, H.wa[l + 1]);
-            H.prolong(l, H.wa[l + 1], H.wa[l]);
+            H.prolong(l, H.wa[l + 1], H.wa[l], one);
             exp_(l, H.wa[l], out);
             break;
         case DD_OP_COARSE_SOLVE:
             if (l < 1) fail(DD_EINVAL, "coarse solve needs level >= 1");
             imp(l, in, H.rc[l]);
-            its = H.gmres_oe(l, H.rc[l], H.ec[l]);
+            memset(H.coarse_count, 0, sizeof H.coarse_count);
+            H.gmres_oe(l, H.rc[l], H.ec[l], one);
+            its = H.coarse_count[l][0];
             exp_(l, H.ec[l], out);
             break;
         case DD_OP_SCHUR:
             if (l < 1) fail(DD_EINVAL, "Schur complement needs level >= 1");
             imp(l, in, H.wa[l]);
-            H.schur(l, H.wa[l], H.wb[l]);
+            H.schur(l, H.wa[l], H.wb[l], one.mask(), 1, 1);
             HIPX(hipMemsetAsync(H.wb[l], 0, sizeof(cx<T>) * (size_t)H.g[l].vh * H.nd[l], C->s));
             exp_(l, H.wb[l], out);
             break;
@@ -1364,7 +1506,8 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
             if (l < 1 || l >= bottom) fail(DD_EINVAL, "middle-level FGMRES needs 1 <= level < levels-1");
             imp(l, in, H.rc[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            its = H.fgmres_mid(l, bottom, H.rc[l], H.ec[l]);
+            H.fgmres_mid(l, bottom, H.rc[l], H.ec[l], one);
+            its = H.coarse_count[l][0];
             exp_(l, H.ec[l], out);
             break;
         default:

@@ -25,7 +25,10 @@ FIELDS = {
     "c2_16x4_seed1": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=1, csw=1.0),
     "c1_4x4_seed0": dict(dims=(4, 4, 4, 4), eps=0.3, ape=0, seed=0, csw=1.0),
     "t_8x4_seed0": dict(dims=(8, 8, 8, 8), eps=0.4, ape=2, seed=0, csw=1.0),
+    "c3_32c64_seed0": dict(dims=(64, 32, 32, 32), eps=0.4, ape=2, seed=0, csw=1.0),
 }
+# Krylov space size per field (memory: ncv vectors of 12*volume complex numbers)
+NCV = {"c3_32c64_seed0": 32}
 
 
 def mcrit(dims, eps, ape, seed, csw, k=4, tol=1e-5, ncv=64):
@@ -52,9 +55,9 @@ def main(names):
     for name in names or list(FIELDS):
         cfg = FIELDS[name]
         t = time.time()
-        m, low, nmv = mcrit(cfg["dims"], cfg["eps"], cfg["ape"], cfg["seed"], cfg["csw"])
+        m, low, nmv = mcrit(cfg["dims"], cfg["eps"], cfg["ape"], cfg["seed"], cfg["csw"], ncv=NCV.get(name, 64))
         data[name] = dict(cfg, dims=list(cfg["dims"]), m_crit=m, lowest_re=low, matvecs=nmv,
-                          method="ARPACK eigs which=SR k=4 ncv=64 tol=1e-5 on the oracle D at m0=0",
+                          method="ARPACK eigs which=SR k=4 ncv=%d tol=1e-5 on the oracle D at m0=0" % NCV.get(name, 64),
                           seconds=round(time.time() - t, 1))
         print(name, m, "%.1fs" % (time.time() - t), flush=True)
         json.dump(data, open(path, "w"), indent=1, sort_keys=True)

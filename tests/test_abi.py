@@ -36,6 +36,7 @@ def test_default_params_are_table1():
     assert list(p.agg[0]) == [4, 4, 4, 4] and list(p.sap[0]) == [4, 4, 4, 4]
     assert p.mr_steps[0] == 4 and p.coarse_restart == 30 and abs(p.coarse_tol - 5e-2) < 1e-15
     assert p.outer_restart == 25
+    assert p.max_rhs == 1
 
 
 def test_package_import_does_not_need_the_device():
