@@ -236,12 +236,40 @@ dd_status dd_profile_read(dd_ctx *ctx, int kernel_class, long *launches, double 
 /* Time `reps` back-to-back launches of one kernel class on the fine level
  * (DD_K_DIRAC64, DD_K_DIRAC_PREC or DD_K_SAP = one full SAP sweep, both
  * colours, preconditioner precision, mr_steps of level 0) on internal random
- * data between two HIP events; *avg_ms = mean duration of one launch.  Needs
- * dd_configure (for DD_K_DIRAC_PREC / DD_K_SAP). */
+ * data between two HIP events; *avg_ms = mean duration of one launch.
+ * DD_K_BLAS times a plain copy kernel of one FP64 fine spinor (16 bytes read
+ * and 16 written per complex entry): the reference for achievable bandwidth
+ * and for scaling memory counters.  Needs dd_configure (for DD_K_DIRAC_PREC /
+ * DD_K_SAP). */
 dd_status dd_time_kernel(dd_ctx *ctx, int kernel_class, int reps, double *avg_ms);
 
 /* Device bytes currently allocated by the context. */
 long long dd_device_bytes(const dd_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Launch schedules and autotuning.  The fine stencil and SAP kernels have
+ * schedule variants that compute identical results:
+ *   DD_SCHED_FUSED  a stencil workgroup covers both parities of its layout
+ *                   blocks (links and spinors reused on chip)
+ *   DD_SCHED_XCD    workgroups renumbered so that each of the eight XCDs
+ *                   (separate L2 caches) works on a contiguous lattice region
+ *   DD_SCHED_LDS    stencil: one workgroup per layout block with its spinors
+ *                   staged in LDS and each internal link applied twice per
+ *                   load (needs 32..128 sites per block and parity; other
+ *                   layouts fall back to the FUSED schedule's kernel)
+ * ------------------------------------------------------------------------- */
+enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4 };
+
+/* Select a schedule (a combination of DD_SCHED_* flags). DD_EINVAL otherwise. */
+dd_status dd_set_schedule(dd_ctx *ctx, int sched);
+/* Current schedule, -1 for ctx == NULL. */
+int dd_get_schedule(const dd_ctx *ctx);
+
+/* Time every schedule on the context's own fields (the FP64 stencil plus nu
+ * SAP sweeps once configured, each the mean of `reps` launches) and keep the
+ * fastest.  chosen (may be NULL) receives it; times_ms (may be NULL) holds 8
+ * doubles, the cost of each schedule (flag set 0..7) in ms. */
+dd_status dd_autotune(dd_ctx *ctx, int reps, int *chosen, double *times_ms);
 
 #ifdef __cplusplus
 }

@@ -107,10 +107,14 @@ def library():
         L.dd_time_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dd_device_bytes.restype = C.c_longlong
         L.dd_device_bytes.argtypes = [vp]
+        L.dd_set_schedule.argtypes = [vp, C.c_int]
+        L.dd_get_schedule.argtypes = [vp]
+        L.dd_get_schedule.restype = C.c_int
+        L.dd_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
-                     "dd_time_kernel"):
+                     "dd_time_kernel", "dd_set_schedule", "dd_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -250,6 +254,20 @@ class Solver:
             self._check(library().dd_profile_read(self.h, k, C.byref(n), C.byref(ms), C.byref(by)))
             out[name] = (n.value, ms.value, by.value)
         return out
+
+    # ---- launch schedules / autotuner -------------------------------------------
+    def set_schedule(self, sched):
+        self._check(library().dd_set_schedule(self.h, int(sched)))
+
+    def get_schedule(self):
+        return int(library().dd_get_schedule(self.h))
+
+    def autotune(self, reps=10):
+        """Time every fine-kernel schedule, keep the fastest; returns (chosen, [ms per schedule])."""
+        ch = C.c_int()
+        t = (C.c_double * 8)()
+        self._check(library().dd_autotune(self.h, int(reps), C.byref(ch), t))
+        return ch.value, list(t)
 
     def time_kernel(self, name, reps=20):
         """Mean duration (ms) of one standalone launch: dirac64, dirac_prec or sap (full sweep)."""

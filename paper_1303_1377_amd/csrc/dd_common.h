@@ -196,6 +196,20 @@ __host__ __device__ __forceinline__ void herm6_apply(const T m[36], const cx<T>*
 }
 
 // ---------------------------------------------------------------------------
+// workgroup scheduling.  Consecutive workgroups of a grid are dealt round
+// robin to the eight XCDs, each with its own L2.  xcd_swizzle maps the
+// hardware index w to a logical one so that XCD x works on the contiguous
+// range [x n/8, (x+1) n/8) of logical workgroups, which keeps lattice
+// neighbours (halo reuse) in one L2.  Grids whose size is not a multiple of 8
+// keep the identity.
+// ---------------------------------------------------------------------------
+static constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_swizzle(int w, int n) {
+    if (n % NUM_XCD) return w;
+    return (w % NUM_XCD) * (n / NUM_XCD) + w / NUM_XCD;
+}
+
+// ---------------------------------------------------------------------------
 // reductions (wave64 shuffles, then one LDS step across the waves)
 // ---------------------------------------------------------------------------
 template <class T>

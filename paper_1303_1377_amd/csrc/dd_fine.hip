@@ -396,24 +396,40 @@ __device__ __forceinline__ void hop_accum(const FineOp<T>& op, int k, int p, int
 
 // ---------------------------------------------------------------------------
 // D psi = A psi - 1/2 sum_mu [(I - g_mu) U_mu(x) psi(x+mu) + (I + g_mu) U_mu(x-mu)^H psi(x-mu)]
-// one thread per site, both parities in one grid
+// one thread per site, both parities in one grid.  With SCHED_FUSED a
+// workgroup takes the even and the odd sites of the same layout blocks, so the
+// forward links its even sites read are the backward links of its odd sites
+// (and the spinors one parity gathers were loaded by the other): every link
+// and spinor is fetched from HBM about once.  Without it the grid runs all
+// even sites, then all odd ones, and each link is fetched twice.
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                long ld, Mask mk) {
     const Geom g = op.g;
-    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int gid = w * blockDim.x + threadIdx.x;
     if (gid >= 2 * g.vh || !mk.on(blockIdx.y)) return;
     in += blockIdx.y * ld;
     out += blockIdx.y * ld;
-    int p = gid >= g.vh, i = gid - p * g.vh;
+    int p, i;
+    if (op.sched & (SCHED_FUSED | SCHED_LDS)) {
+        p = (gid >> g.lbvh) & 1;
+        i = ((gid >> (g.lbvh + 1)) << g.lbvh) | (gid & (g.bvh - 1));
+    } else {
+        p = gid >= g.vh;
+        i = gid - p * g.vh;
+    }
     int x[4];
     cb_coords(g, p, i, x);
     cx<T> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+    // hops in the order +0, -0, +1, -1, ... (the order of the LDS schedule, so
+    // that every schedule produces the same bits)
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
+    for (int kk = 0; kk < 8; kk++) {
+        const int k = (kk >> 1) + ((kk & 1) << 2);
         int y[4];
         nb_coords(g, x, k, y);
         int j = cb_index(g, y);
@@ -429,8 +445,150 @@ __global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __rest
     store_spinor(out, g.vh, p, i, a);
 }
 
+// layout index of neighbour k of x, written with selects only (no dynamically
+// indexed private arrays, so rolled loops stay in registers)
+__device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k) {
+    const int mu = k & 3;
+    const bool fwd = k < 4;
+    int y[4];
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        const int c = x[nu], d = g.d[nu];
+        const int stepped = fwd ? ((c + 1 == d) ? 0 : c + 1) : ((c == 0) ? d - 1 : c - 1);
+        y[nu] = (nu == mu) ? stepped : c;
+    }
+    return cb_index(g, y);
+}
+
+// ---------------------------------------------------------------------------
+// Stencil with the layout block staged in LDS (SCHED_LDS).  One workgroup per
+// layout block, one thread per site (threads [0, bvh) even, [bvh, 2 bvh) odd).
+//   1. every thread copies its spinor into S (coalesced; each spinor is read
+//      from memory once by its own block);
+//   2. per direction mu, with U = U_mu(x) loaded once by the owner x:
+//      forward hop  acc(x)    += (I - g_mu) U psi(x+mu)      psi from S if x+mu is in the block
+//      backward hop acc(x+mu) += (I + g_mu) U^H psi(x)       computed by x, handed to
+//                                                            x+mu through HB as the colour-
+//                                                            rotated two-spinor
+//      so each internal link is loaded once and applied twice; hops that
+//      leave the block gather the link and spinor of the neighbour block;
+//   3. out = A psi - acc / 2.
+// LDS: S [2][12][bvh] + HB [2][6][bvh] complex entries.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                   long ld, Mask mk) {
+    extern __shared__ char smem_raw[];
+    if (!mk.on(blockIdx.y)) return;
+    const Geom g = op.g;
+    const int bvh = g.bvh;
+    cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);   // [2][12][bvh]
+    cx<T>* HB = S + 24 * bvh;                         // [2][6][bvh]
+    in += blockIdx.y * ld;
+    out += blockIdx.y * ld;
+    const int blk = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int t = threadIdx.x;
+    const int p = t >= bvh;
+    const int l = t - p * bvh;
+    const int base = blk << g.lbvh;
+    const int i = base + l;
+    {
+        cx<T> v[12];
+        load_spinor(in, g.vh, p, i, v);
+#pragma unroll
+        for (int c = 0; c < 12; c++) S[(p * 12 + c) * bvh + l] = v[c];
+    }
+    int x[4];
+    cb_coords(g, p, i, x);
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+    __syncthreads();
+    const int q = 1 - p;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++) {
+        const int jf = nb_index_sel(g, x, mu);
+        const int jb = nb_index_sel(g, x, 4 + mu);
+        const bool inf = (jf >> g.lbvh) == blk, inb = (jb >> g.lbvh) == blk;
+        cx<T> u[9], h[6], gg[6];
+        load_link(op, p, mu, i, u);
+        {
+            // forward hop of x
+            cx<T> v[12];
+            if (inf) {
+                const int lf = jf & (bvh - 1);
+#pragma unroll
+                for (int c = 0; c < 12; c++) v[c] = S[(q * 12 + c) * bvh + lf];
+            } else {
+                load_spinor(in, g.vh, q, jf, v);
+            }
+            spin_project(mu, T(-1), v, h);
+            su3_two_spinor(u, false, h, gg);
+            spin_reconstruct(mu, T(-1), gg, acc);
+        }
+        if (inf) {
+            // backward hop of x+mu, with the link just loaded
+            cx<T> v[12];
+#pragma unroll
+            for (int c = 0; c < 12; c++) v[c] = S[(p * 12 + c) * bvh + l];
+            spin_project(mu, T(1), v, h);
+            su3_two_spinor(u, true, h, gg);
+            const int lf = jf & (bvh - 1);
+#pragma unroll
+            for (int c = 0; c < 6; c++) HB[(q * 6 + c) * bvh + lf] = gg[c];
+        }
+        __syncthreads();
+        if (inb) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) gg[c] = HB[(p * 6 + c) * bvh + l];
+        } else {
+            cx<T> v[12];
+            load_spinor(in, g.vh, q, jb, v);
+            load_link(op, q, mu, jb, u);
+            spin_project(mu, T(1), v, h);
+            su3_two_spinor(u, true, h, gg);
+        }
+        spin_reconstruct(mu, T(1), gg, acc);
+        __syncthreads();
+    }
+    cx<T> v[12], a[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = S[(p * 12 + c) * bvh + l];
+    clover_apply(op.clov, g.vh, p, i, v, a);
+#pragma unroll
+    for (int c = 0; c < 12; c++) a[c] -= T(0.5) * acc[c];
+    store_spinor(out, g.vh, p, i, a);
+}
+
+template <class T>
+size_t fine_dirac_lds_bytes(const Geom& g) {
+    return sizeof(cx<T>) * 36 * (size_t)g.bvh;
+}
+
+// the LDS stencil needs whole waves and at most 256 threads per layout block
+static inline bool dirac_lds_fits(const Geom& g) { return 2 * g.bvh >= 64 && 2 * g.bvh <= 256; }
+
 template <class T>
 void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
+    if ((op.sched & SCHED_LDS) && dirac_lds_fits(op.g)) {
+        const size_t lds = fine_dirac_lds_bytes<T>(op.g);
+        static size_t configured = 65536;
+        static bool refused = false;
+        if (lds > configured && !refused) {
+            if (hipFuncSetAttribute((const void*)k_dirac_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+                hipSuccess)
+                configured = lds;
+            else {
+                (void)hipGetLastError();
+                refused = true;
+            }
+        }
+        if (lds <= configured) {
+            dim3 grid(op.g.nblk, nr);
+            k_dirac_lds<T><<<grid, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk);
+            return;
+        }
+    }
     dim3 grid(nblk_of(2L * op.g.vh, 256), nr);
     k_dirac<T><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
 }
@@ -502,21 +660,6 @@ __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T
     for (int c = 0; c < 12; c++) buf[c * bvh + l] = v[c];
 }
 
-// layout index of neighbour k of x, written with selects only (no dynamically
-// indexed private arrays, so rolled loops stay in registers)
-__device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k) {
-    const int mu = k & 3;
-    const bool fwd = k < 4;
-    int y[4];
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        const int c = x[nu], d = g.d[nu];
-        const int stepped = fwd ? ((c + 1 == d) ? 0 : c + 1) : ((c == 0) ? d - 1 : c - 1);
-        y[nu] = (nu == mu) ? stepped : c;
-    }
-    return cb_index(g, y);
-}
-
 // hop k of the site (p, i) owned by thread t.  tab[k][t] packs, for a hop
 // inside the block, the LDS slot of the link (<< 8) and the neighbour's local
 // index; -1 marks a hop that leaves the block.  INTERNAL_ONLY: only internal
@@ -577,7 +720,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
     cx<T>* O = E + 12 * bvh;                         // odd field [12][bvh]
     int* tab = reinterpret_cast<int*>(O + 12 * bvh);  // [8][2 bvh] packed hop table
     double* red = reinterpret_cast<double*>(tab + 8 * ntab);
-    const int blk = blocks[blockIdx.x];
+    const int blk = blocks[(op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x];
     const int base = blk << g.lbvh;
     const int t = threadIdx.x;
     const bool act = t < 2 * bvh;

@@ -10,12 +10,20 @@ namespace dd {
 //   U       [2][4][9][vh]  forward links of each site
 //   clov    [2][72][vh]    packed A(x) = (m0+4) I + T(x), two Hermitian 6x6 blocks
 //   clovinv [2][72][vh]    packed A(x)^{-1}
+//   sched   SCHED_* flags: launch schedule of the stencil and SAP kernels
+//           (results are identical for every choice; the autotuner picks one)
+enum FineSched {
+    SCHED_FUSED = 1,   // stencil: one workgroup covers both parities of its layout blocks
+    SCHED_XCD = 2,     // stencil and SAP: XCD-contiguous workgroup order
+    SCHED_LDS = 4,     // stencil: one workgroup per layout block staged in LDS
+};
 template <class T>
 struct FineOp {
     Geom g;
     const cx<T>* U;
     const T* clov;
     const T* clovinv;
+    int sched = SCHED_LDS | SCHED_XCD;
 };
 
 // Coarse stencil D_c on a level with nd unknowns per site.

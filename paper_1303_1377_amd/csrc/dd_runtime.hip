@@ -206,6 +206,7 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
+    int sched = SCHED_LDS | SCHED_XCD;     // launch schedule of the fine stencil / SAP
     ~dd_ctx();
 };
 
@@ -437,8 +438,12 @@ static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, co
 }
 
 template <class T> static FineOp<T> fine_op(dd_ctx* C);
-template <> FineOp<double> fine_op<double>(dd_ctx* C) { return FineOp<double>{C->g0, C->U64, C->clov64, C->clovinv64}; }
-template <> FineOp<float> fine_op<float>(dd_ctx* C) { return FineOp<float>{C->g0, C->U32, C->clov32, C->clovinv32}; }
+template <> FineOp<double> fine_op<double>(dd_ctx* C) {
+    return FineOp<double>{C->g0, C->U64, C->clov64, C->clovinv64, C->sched};
+}
+template <> FineOp<float> fine_op<float>(dd_ctx* C) {
+    return FineOp<float>{C->g0, C->U32, C->clov32, C->clovinv32, C->sched};
+}
 
 // ---------------------------------------------------------------------------
 // hierarchy geometry and buffers
@@ -1396,17 +1401,21 @@ static double time_prec(dd_ctx* C, Hier<T>& H, int cls, int reps) {
 dd_status dd_time_kernel(dd_ctx* ctx, int cls, int reps, double* avg_ms) {
     ABI_TRY(ctx)
     if (reps < 1 || !avg_ms) fail(DD_EINVAL, "reps >= 1 and avg_ms required");
-    if (cls == DD_K_DIRAC64) {
+    if (cls == DD_K_DIRAC64 || cls == DD_K_BLAS) {
         const long n = 24L * ctx->g0.vh;
         Arena tmp;
         cx<double>* a = tmp.get<cx<double>>(n);
         cx<double>* b = tmp.get<cx<double>>(n);
         fine_random<double>(ctx->g0, 1, 12345ULL, 7, a, ctx->s);
         FineOp<double> op = fine_op<double>(ctx);
-        fine_dirac<double>(op, a, b, ctx->s);
+        auto launch = [&]() {
+            if (cls == DD_K_BLAS) vec_convert<double, double>(n, a, b, ctx->s);
+            else fine_dirac<double>(op, a, b, ctx->s);
+        };
+        launch();
         hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
         HIPX(hipEventRecord(e0, ctx->s));
-        for (int r = 0; r < reps; r++) fine_dirac<double>(op, a, b, ctx->s);
+        for (int r = 0; r < reps; r++) launch();
         HIPX(hipEventRecord(e1, ctx->s));
         HIPX(hipGetLastError());
         HIPX(hipEventSynchronize(e1));
@@ -1543,3 +1552,46 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
 }
 
 
+
+static void set_sched(dd_ctx* C, int sched) {
+    C->sched = sched;
+    if (C->H64) C->H64->op0.sched = sched;
+    if (C->H32) C->H32->op0.sched = sched;
+}
+
+dd_status dd_set_schedule(dd_ctx* ctx, int sched) {
+    ABI_TRY(ctx)
+    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS)) fail(DD_EINVAL, "unknown schedule flags");
+    set_sched(ctx, sched);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+int dd_get_schedule(const dd_ctx* ctx) { return ctx ? ctx->sched : -1; }
+
+// Autotuner: every schedule is timed on the context's own fields (FP64
+// stencil, plus nu SAP sweeps in preconditioner precision once configured,
+// the fine-level work of one outer iteration); the fastest one is kept.
+dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
+    ABI_TRY(ctx)
+    if (reps < 1) fail(DD_EINVAL, "reps >= 1");
+    const int nsched = (SCHED_FUSED | SCHED_XCD | SCHED_LDS) + 1;
+    double best = 0;
+    int pick = ctx->sched;
+    for (int sc = 0; sc < nsched; sc++) {
+        set_sched(ctx, sc);
+        double ms = 0, t = 0;
+        if (dd_time_kernel(ctx, DD_K_DIRAC64, reps, &t) != DD_OK) return DD_EDEVICE;
+        ms += t;
+        if (ctx->configured) {
+            if (dd_time_kernel(ctx, DD_K_SAP, reps, &t) != DD_OK) return DD_EDEVICE;
+            ms += std::max(ctx->p.nu, 1) * t;
+        }
+        if (times_ms) times_ms[sc] = ms;
+        if (sc == 0 || ms < best) { best = ms; pick = sc; }
+    }
+    set_sched(ctx, pick);
+    if (chosen) *chosen = pick;
+    return DD_OK;
+    ABI_END(ctx)
+}

@@ -333,3 +333,31 @@ def test_batch_argument_errors(c1):
     c1.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, mr_steps=[4], outer_restart=20, max_rhs=2)
     X, st = c1.g.solve_batch(np.zeros((0, int(np.prod(C1)), 4, 3), dtype=np.complex128))
     assert X.shape[0] == 0 and st == []
+
+
+def test_schedules_give_identical_results():
+    """Every launch schedule gives the same SAP bits (only the block order
+    differs) and the same stencil up to rounding (the LDS schedule is a
+    different kernel, so the compiler's contractions may differ); the
+    autotuner keeps one of them."""
+    say("case: schedules 8^4")
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=2, m0=-0.3, csw=1.0)
+    import paper_1303_1377_amd as G
+
+    p.g.configure(G.default_params(levels=2, n_tv=[6], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4]))
+    v = F.gaussian_spinor(dims, 11)
+    ref_d = ref_s = None
+    for sc in range(8):
+        p.g.set_schedule(sc)
+        d, _ = p.g.apply("D", 0, v)
+        z, _ = p.g.apply("SAP", 0, v, arg=2)
+        d, z = to_np(d), to_np(z)
+        if ref_d is None:
+            ref_d, ref_s = d, z
+        say("schedule", sc, "D vs schedule 0", rel(d, ref_d))
+        assert rel(d, p.o.apply(v)) < 1e-13 and rel(d, ref_d) < 1e-14
+        assert np.array_equal(z, ref_s)
+    chosen, times = p.g.autotune(reps=2)
+    say("autotune", chosen, times)
+    assert chosen in range(8) and p.g.get_schedule() == chosen and all(t > 0 for t in times)
