@@ -71,8 +71,10 @@ typedef struct {
     int mid_fixed;               /* >0: exactly this many intermediate iterations          */
     int outer_restart;           /* FGMRES restart length n_kv                             */
     int outer_maxit;             /* outer iteration cap                                    */
-    int precision;               /* 64: FP64 preconditioner; 32: FP32 preconditioner
-                                    (the outer FGMRES and its D are always FP64)          */
+    int precision;               /* 64: FP64 preconditioner; 32: FP32 preconditioner;
+                                    16: FP32 arithmetic on FP16-stored operators (links,
+                                    clover blocks, P, D_c, self-block inverses; vectors
+                                    FP32).  The outer FGMRES and its D are always FP64.  */
     int given_vectors;           /* 1: the setup starts from vectors installed with
                                     dd_set_test_vectors instead of drawing them            */
     unsigned long long seed;     /* counter-based RNG key for the initial test vectors     */

@@ -482,6 +482,7 @@ template void vec_convert<double, float>(long, const cx<float>*, cx<double>*, hi
 template void vec_convert<float, double>(long, const cx<double>*, cx<float>*, hipStream_t);
 template void vec_convert<double, double>(long, const cx<double>*, cx<double>*, hipStream_t);
 template void vec_convert<float, float>(long, const cx<float>*, cx<float>*, hipStream_t);
+template void vec_convert<_Float16, float>(long, const cx<float>*, cx<_Float16>*, hipStream_t);
 template void bvec_convert<double, float>(long, const cx<float>*, cx<double>*, long, int, Mask, hipStream_t);
 template void bvec_convert<float, double>(long, const cx<double>*, cx<float>*, long, int, Mask, hipStream_t);
 template void bvec_convert<double, double>(long, const cx<double>*, cx<double>*, long, int, Mask, hipStream_t);

@@ -23,8 +23,8 @@ static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
 // ---------------------------------------------------------------------------
 static constexpr int CA_WAVES = 8;
 
-template <class T>
-__global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, int par, int self_mode,
+template <class T, class S>
+__global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> op, int par, int self_mode,
                                                                 const cx<T>* __restrict__ in1, int hop_sign,
                                                                 const cx<T>* in2, int post_inv, cx<T>* out,
                                                                 Mask mk, long ld) {
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, 
     }
     __shared__ cx<T> part[CA_WAVES][64];
     __shared__ cx<T> buf[64];
-    __shared__ const cx<T>* mat[9];
+    __shared__ const cx<S>* mat[9];
     __shared__ const cx<T>* vin[9];
     __shared__ int nslot_s;
     const Geom g = op.g;
@@ -78,11 +78,11 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, 
             const int sl = q / nd;
             const int c0 = q - sl * nd;
             const int c1 = min(nd, c0 + (q1 - q));
-            const cx<T>* A = mat[sl] + r;
+            const cx<S>* A = mat[sl] + r;
             const cx<T>* v = vin[sl];
             cx<T> a2 = czero<T>();
 #pragma unroll 4
-            for (int c = c0; c < c1; c++) a2 += A[(size_t)c * nd] * v[c];
+            for (int c = c0; c < c1; c++) a2 += ccast<T>(A[(size_t)c * nd]) * v[c];
             if (sl >= nself && hop_sign < 0) acc -= a2;
             else acc += a2;
             q += c1 - c0;
@@ -105,8 +105,8 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, 
     const int c0 = w * per2, c1 = min(nd, c0 + per2);
     cx<T> a3 = czero<T>();
     if (r < nd) {
-        const cx<T>* A = op.Minv + gs * nn + r;
-        for (int c = c0; c < c1; c++) a3 += A[(size_t)c * nd] * buf[c];
+        const cx<S>* A = op.Minv + gs * nn + r;
+        for (int c = c0; c < c1; c++) a3 += ccast<T>(A[(size_t)c * nd]) * buf[c];
     }
     part[w][r] = a3;
     __syncthreads();
@@ -117,14 +117,14 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T> op, 
     }
 }
 
-template <class T>
-void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
+template <class T, class S>
+void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
     int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
     int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
     int nw = nslot >= 8 ? CA_WAVES : (post_inv || nslot > 0 ? 4 : 1);
     dim3 grid(nsite, nr);
-    k_coarse_apply<T><<<grid, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld);
+    k_coarse_apply<T, S><<<grid, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,15 +294,15 @@ void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s
 // coarse SAP half sweep (same algebra as the fine kernel, dense site blocks):
 // workgroup = one block, thread = (local site l, row r) for both parities.
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ cx<T> row_apply(const cx<T>* __restrict__ A, int nd, int r, const cx<T>* v) {
+template <class T, class S>
+__device__ __forceinline__ cx<T> row_apply(const cx<S>* __restrict__ A, int nd, int r, const cx<T>* v) {
     cx<T> s = czero<T>();
-    for (int c = 0; c < nd; c++) s += A[(size_t)c * nd + r] * v[c];
+    for (int c = 0; c < nd; c++) s += ccast<T>(A[(size_t)c * nd + r]) * v[c];
     return s;
 }
 
-template <class T>
-__global__ void k_coarse_sap(CoarseOp<T> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+template <class T, class S>
+__global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
                              cx<T>* __restrict__ z, int mr_steps, long ld, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     b += blockIdx.y * ld;
@@ -405,14 +405,14 @@ __global__ void k_coarse_sap(CoarseOp<T> op, const int* __restrict__ blocks, con
     }
 }
 
-template <class T>
-void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+template <class T, class S>
+void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                      hipStream_t s, int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
     int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
     size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
     dim3 grid(nblocks, nr);
-    k_coarse_sap<T><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+    k_coarse_sap<T, S><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,8 +431,8 @@ __device__ __forceinline__ void agg_site_c(const AggMap& m, const int xc[4], int
 }
 
 // workgroup: coarser site; thread e < asz*ndf: (site s = e / ndf, row d = e % ndf)
-template <class T>
-__global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+template <class T, class S>
+__global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
                                   cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     in += blockIdx.y * ldi;
@@ -454,7 +454,7 @@ __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restr
             int x[4];
             agg_site_c(m, xc, s, x);
             size_t gf = (size_t)site_parity(x) * m.f.vh + cb_index(m.f, x);
-            acc[d / h0] += ccast<double>(cmulc(P[((size_t)k * volf + gf) * ndf + d], in[gf * ndf + d]));
+            acc[d / h0] += ccast<double>(cmulc(ccast<T>(P[((size_t)k * volf + gf) * ndf + d]), in[gf * ndf + d]));
         }
         for (int h = 0; h < 2; h++) {
             acc[h].re = wave_sum(acc[h].re);
@@ -470,8 +470,8 @@ __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<T>* __restr
     }
 }
 
-template <class T>
-__global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+template <class T, class S>
+__global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
                                  cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long volf = 2L * m.f.vh;
@@ -487,24 +487,24 @@ __global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<T>* __restri
     size_t gc = (size_t)site_parity(xc) * m.c.vh + cb_index(m.c, xc);
     const int h = d / (ndf / 2);
     cx<T> s = czero<T>();
-    for (int k = 0; k < N; k++) s += P[((size_t)k * volf + gf) * ndf + d] * in[gc * 2 * N + h * N + k];
+    for (int k = 0; k < N; k++) s += ccast<T>(P[((size_t)k * volf + gf) * ndf + d]) * in[gc * 2 * N + h * N + k];
     out[gf * ndf + d] = s;
 }
 
-template <class T>
-void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+template <class T, class S>
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
                      int nr, long ldi, long ldo, Mask mk) {
     int nt = 256;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
     dim3 grid(2 * m.c.vh, nr);
-    k_coarse_restrict<T><<<grid, nt, lds, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
+    k_coarse_restrict<T, S><<<grid, nt, lds, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
 }
-template <class T>
-void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+template <class T, class S>
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
                     int nr, long ldi, long ldo, Mask mk) {
     long tot = 2L * m.f.vh * ndf;
     dim3 grid(nblk_of(tot, 256), nr);
-    k_coarse_prolong<T><<<grid, 256, 0, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
+    k_coarse_prolong<T, S><<<grid, 256, 0, s>>>(m, ndf, N, P, in, out, ldi, ldo, mk);
 }
 
 // modified Gram-Schmidt per (coarser site, half): rows = aggregate sites x ndf/2
@@ -674,25 +674,30 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
     k_coarse_random<T><<<nblk_of(tot, 256), 256, 0, s>>>(g, nd, n, seed, sid, out);
 }
 
+// operator kernels for compute type T and storage type S
+#define DD_COARSE_OP_INST(T, S)                                                                                      \
+    template void coarse_apply<T, S>(const CoarseOp<T, S>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*,   \
+                                     hipStream_t, Mask, int, long);                                                 \
+    template void coarse_sap_half<T, S>(const CoarseOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
+                                        int, long, Mask);                                                           \
+    template void coarse_restrict<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int, \
+                                        long, long, Mask);                                                          \
+    template void coarse_prolong<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int,  \
+                                       long, long, Mask);
+
 #define DD_COARSE_INST(T)                                                                                                \
-    template void coarse_apply<T>(const CoarseOp<T>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*, hipStream_t, \
-                                  Mask, int, long);                                                                 \
+    DD_COARSE_OP_INST(T, T)                                                                                          \
     template void coarse_self_inverse<T>(const Geom&, int, const cx<T>*, cx<T>*, int*, hipStream_t);                  \
     template void coarse_import_vector<T>(const Geom&, int, int, const double*, cx<T>*, hipStream_t);                \
     template void coarse_export_vector<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
     template void coarse_export_blocks<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
     template void coarse_shift_diag<T>(const Geom&, int, double, cx<T>*, hipStream_t);                                \
-    template void coarse_sap_half<T>(const CoarseOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, int, \
-                                     long, Mask);                                                                   \
-    template void coarse_restrict<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long, \
-                                     long, Mask);                                                                   \
-    template void coarse_prolong<T>(const AggMap&, int, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long,  \
-                                    long, Mask);                                                                    \
     template void coarse_gram_schmidt<T>(const AggMap&, int, int, const cx<T>*, cx<T>*, int*, hipStream_t);          \
     template void coarse_assemble<T>(const CoarseOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t);     \
     template void coarse_random<T>(const Geom&, int, int, unsigned long long, int, cx<T>*, hipStream_t);
 
 DD_COARSE_INST(double)
 DD_COARSE_INST(float)
+DD_COARSE_OP_INST(float, _Float16)
 
 }  // namespace dd

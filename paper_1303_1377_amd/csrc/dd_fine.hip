@@ -341,18 +341,18 @@ void fine_clover_export(const Geom& g, const double* packed, double* canon, hipS
 // ---------------------------------------------------------------------------
 // stencil building blocks
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void load_link(const FineOp<T>& op, int p, int mu, int i, cx<T> u[9]) {
-    const cx<T>* base = op.U + (size_t)(p * 4 + mu) * 9 * op.g.vh + i;
+template <class T, class S>
+__device__ __forceinline__ void load_link(const FineOp<T, S>& op, int p, int mu, int i, cx<T> u[9]) {
+    const cx<S>* base = op.U + (size_t)(p * 4 + mu) * 9 * op.g.vh + i;
 #pragma unroll
-    for (int e = 0; e < 9; e++) u[e] = base[(size_t)e * op.g.vh];
+    for (int e = 0; e < 9; e++) u[e] = ccast<T>(base[(size_t)e * op.g.vh]);
 }
 
-template <class T>
-__device__ __forceinline__ void load_spinor(const cx<T>* psi, int vh, int p, int i, cx<T> v[12]) {
-    const cx<T>* base = psi + (size_t)p * 12 * vh + i;
+template <class T, class S>
+__device__ __forceinline__ void load_spinor(const cx<S>* psi, int vh, int p, int i, cx<T> v[12]) {
+    const cx<S>* base = psi + (size_t)p * 12 * vh + i;
 #pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = base[(size_t)c * vh];
+    for (int c = 0; c < 12; c++) v[c] = ccast<T>(base[(size_t)c * vh]);
 }
 
 template <class T>
@@ -363,22 +363,22 @@ __device__ __forceinline__ void store_spinor(cx<T>* psi, int vh, int p, int i, c
 }
 
 // out = A v with the packed clover blocks at (p, i) of array `cl`
-template <class T>
-__device__ __forceinline__ void clover_apply(const T* __restrict__ cl, int vh, int p, int i, const cx<T> v[12], cx<T> out[12]) {
+template <class T, class S>
+__device__ __forceinline__ void clover_apply(const S* __restrict__ cl, int vh, int p, int i, const cx<T> v[12], cx<T> out[12]) {
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         T m[36];
-        const T* base = cl + (size_t)(p * 72 + h * 36) * vh + i;
+        const S* base = cl + (size_t)(p * 72 + h * 36) * vh + i;
 #pragma unroll
-        for (int r = 0; r < 36; r++) m[r] = base[(size_t)r * vh];
+        for (int r = 0; r < 36; r++) m[r] = T(base[(size_t)r * vh]);
         herm6_apply(m, v + 6 * h, out + 6 * h);
     }
 }
 
 // acc += (I -/+ gamma_mu) (x) U psi_y for hop k from a site of parity p:
 // forward (k < 4): link U_mu(x) at (p, i); backward: U_mu(y)^H at (1-p, j)
-template <class T>
-__device__ __forceinline__ void hop_accum(const FineOp<T>& op, int k, int p, int i, int j, const cx<T> v[12], cx<T> acc[12]) {
+template <class T, class S>
+__device__ __forceinline__ void hop_accum(const FineOp<T, S>& op, int k, int p, int i, int j, const cx<T> v[12], cx<T> acc[12]) {
     int mu = k & 3;
     cx<T> h[6], gg[6], u[9];
     if (k < 4) {
@@ -403,8 +403,8 @@ __device__ __forceinline__ void hop_accum(const FineOp<T>& op, int k, int p, int
 // and spinor is fetched from HBM about once.  Without it the grid runs all
 // even sites, then all odd ones, and each link is fetched twice.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256) k_dirac(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+template <class T, class S>
+__global__ void __launch_bounds__(256) k_dirac(FineOp<T, S> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                long ld, Mask mk) {
     const Geom g = op.g;
     const int w = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -463,27 +463,27 @@ __device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k
 // ---------------------------------------------------------------------------
 // Stencil with the layout block staged in LDS (SCHED_LDS).  One workgroup per
 // layout block, one thread per site (threads [0, bvh) even, [bvh, 2 bvh) odd).
-//   1. every thread copies its spinor into S (coalesced; each spinor is read
+//   1. every thread copies its spinor into SP (coalesced; each spinor is read
 //      from memory once by its own block);
 //   2. per direction mu, with U = U_mu(x) loaded once by the owner x:
-//      forward hop  acc(x)    += (I - g_mu) U psi(x+mu)      psi from S if x+mu is in the block
+//      forward hop  acc(x)    += (I - g_mu) U psi(x+mu)      psi from SP if x+mu is in the block
 //      backward hop acc(x+mu) += (I + g_mu) U^H psi(x)       computed by x, handed to
 //                                                            x+mu through HB as the colour-
 //                                                            rotated two-spinor
 //      so each internal link is loaded once and applied twice; hops that
 //      leave the block gather the link and spinor of the neighbour block;
 //   3. out = A psi - acc / 2.
-// LDS: S [2][12][bvh] + HB [2][6][bvh] complex entries.
+// LDS: SP [2][12][bvh] + HB [2][6][bvh] complex entries.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+template <class T, class S>
+__global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T, S> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                    long ld, Mask mk) {
     extern __shared__ char smem_raw[];
     if (!mk.on(blockIdx.y)) return;
     const Geom g = op.g;
     const int bvh = g.bvh;
-    cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);   // [2][12][bvh]
-    cx<T>* HB = S + 24 * bvh;                         // [2][6][bvh]
+    cx<T>* SP = reinterpret_cast<cx<T>*>(smem_raw);  // [2][12][bvh]
+    cx<T>* HB = SP + 24 * bvh;                         // [2][6][bvh]
     in += blockIdx.y * ld;
     out += blockIdx.y * ld;
     const int blk = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __
         cx<T> v[12];
         load_spinor(in, g.vh, p, i, v);
 #pragma unroll
-        for (int c = 0; c < 12; c++) S[(p * 12 + c) * bvh + l] = v[c];
+        for (int c = 0; c < 12; c++) SP[(p * 12 + c) * bvh + l] = v[c];
     }
     int x[4];
     cb_coords(g, p, i, x);
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __
             if (inf) {
                 const int lf = jf & (bvh - 1);
 #pragma unroll
-                for (int c = 0; c < 12; c++) v[c] = S[(q * 12 + c) * bvh + lf];
+                for (int c = 0; c < 12; c++) v[c] = SP[(q * 12 + c) * bvh + lf];
             } else {
                 load_spinor(in, g.vh, q, jf, v);
             }
@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __
             // backward hop of x+mu, with the link just loaded
             cx<T> v[12];
 #pragma unroll
-            for (int c = 0; c < 12; c++) v[c] = S[(p * 12 + c) * bvh + l];
+            for (int c = 0; c < 12; c++) v[c] = SP[(p * 12 + c) * bvh + l];
             spin_project(mu, T(1), v, h);
             su3_two_spinor(u, true, h, gg);
             const int lf = jf & (bvh - 1);
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T> op, const cx<T>* __
     }
     cx<T> v[12], a[12];
 #pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = S[(p * 12 + c) * bvh + l];
+    for (int c = 0; c < 12; c++) v[c] = SP[(p * 12 + c) * bvh + l];
     clover_apply(op.clov, g.vh, p, i, v, a);
 #pragma unroll
     for (int c = 0; c < 12; c++) a[c] -= T(0.5) * acc[c];
@@ -568,14 +568,14 @@ size_t fine_dirac_lds_bytes(const Geom& g) {
 // the LDS stencil needs whole waves and at most 256 threads per layout block
 static inline bool dirac_lds_fits(const Geom& g) { return 2 * g.bvh >= 64 && 2 * g.bvh <= 256; }
 
-template <class T>
-void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
+template <class T, class S>
+void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
     if ((op.sched & SCHED_LDS) && dirac_lds_fits(op.g)) {
         const size_t lds = fine_dirac_lds_bytes<T>(op.g);
         static size_t configured = 65536;
         static bool refused = false;
         if (lds > configured && !refused) {
-            if (hipFuncSetAttribute((const void*)k_dirac_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+            if (hipFuncSetAttribute((const void*)k_dirac_lds<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
                 hipSuccess)
                 configured = lds;
             else {
@@ -585,12 +585,12 @@ void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s,
         }
         if (lds <= configured) {
             dim3 grid(op.g.nblk, nr);
-            k_dirac_lds<T><<<grid, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk);
+            k_dirac_lds<T, S><<<grid, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk);
             return;
         }
     }
     dim3 grid(nblk_of(2L * op.g.vh, 256), nr);
-    k_dirac<T><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
+    k_dirac<T, S><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,8 +665,8 @@ __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T
 // index; -1 marks a hop that leaves the block.  INTERNAL_ONLY: only internal
 // hops, neighbour field from the LDS array `buf`; otherwise all hops with the
 // neighbour field from global memory `psi`.
-template <class T, bool INTERNAL_ONLY>
-__device__ __forceinline__ void sap_hop(const FineOp<T>& op, int ltot, const cx<T>* __restrict__ L,
+template <class T, class S, bool INTERNAL_ONLY>
+__device__ __forceinline__ void sap_hop(const FineOp<T, S>& op, int ltot, const cx<T>* __restrict__ L,
                                         const int* __restrict__ tab, int ntab, int k, int t, int p, int i,
                                         const int x[4], int base, const cx<T>* buf, const cx<T>* __restrict__ psi,
                                         cx<T> acc[12]) {
@@ -693,10 +693,10 @@ __device__ __forceinline__ void sap_hop(const FineOp<T>& op, int ltot, const cx<
     spin_reconstruct(mu, sgn, gg, acc);
 }
 
-template <class T>
-__device__ __forceinline__ void clover_regs(const T* __restrict__ cl, int vh, int p, int i, T m[72]) {
+template <class T, class S>
+__device__ __forceinline__ void clover_regs(const S* __restrict__ cl, int vh, int p, int i, T m[72]) {
 #pragma unroll
-    for (int r = 0; r < 72; r++) m[r] = cl[(size_t)(p * 72 + r) * vh + i];
+    for (int r = 0; r < 72; r++) m[r] = T(cl[(size_t)(p * 72 + r) * vh + i]);
 }
 template <class T>
 __device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12], cx<T> out[12]) {
@@ -704,8 +704,8 @@ __device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12
     herm6_apply(m + 36, v + 6, out + 6);
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __restrict__ blocks,
+template <class T, class S>
+__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __restrict__ blocks,
                                                   const cx<T>* __restrict__ b0, cx<T>* __restrict__ z0, int mr_steps,
                                                   int nr, long ld, Mask mk) {
     extern __shared__ char smem_raw[];
@@ -749,9 +749,9 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
             tab[k * ntab + t] = (slot >= 0) ? ((slot << 8) | (j - base)) : -1;
             // own forward link inside the block -> LDS (two rows)
             if (k < 4 && slot >= 0) {
-                const cx<T>* src = op.U + (size_t)(p * 4 + mu) * 9 * g.vh + i;
+                const cx<S>* src = op.U + (size_t)(p * 4 + mu) * 9 * g.vh + i;
 #pragma unroll
-                for (int e = 0; e < 6; e++) L[e * ltot + slot] = src[(size_t)e * g.vh];
+                for (int e = 0; e < 6; e++) L[e * ltot + slot] = ccast<T>(src[(size_t)e * g.vh]);
             }
         }
     }
@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, false>(op, ltot, L, tab, ntab, k, t, p, i, x, base, nullptr, z, acc);
+        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, t, p, i, x, base, nullptr, z, acc);
         load_spinor(b, g.vh, p, i, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];  // b - H z
@@ -792,7 +792,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
+        for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
         lds_load(O, bvh, l, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) {
@@ -809,7 +809,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-            for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
+            for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
             clover_reg_apply(m, acc, w);
@@ -823,7 +823,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-            for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
+            for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
             clover_reg_apply(m, v, w);
 #pragma unroll
             for (int c = 0; c < 12; c++) {
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const int* __res
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
+        for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
         clover_reg_apply(m, acc, w);
@@ -888,18 +888,18 @@ size_t fine_sap_lds_bytes(const Geom& g) {
            3 * sizeof(double) * (nt / 64);
 }
 
-template <class T>
-void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+template <class T, class S>
+void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                    hipStream_t s, int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
     int nt = ((2 * op.g.bvh + 63) / 64) * 64;
     size_t lds = fine_sap_lds_bytes<T>(op.g);
     static size_t configured = 0;
     if (lds > 65536 && lds > configured) {
-        (void)hipFuncSetAttribute((const void*)k_sap_fine<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void*)k_sap_fine<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         configured = lds;
     }
-    k_sap_fine<T><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
+    k_sap_fine<T, S><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -922,8 +922,8 @@ __device__ __forceinline__ void coarse_of(const AggMap& m, const int x[4], int x
 
 // sum of per-wave partials: lane 0 of each wave stores; after a sync thread 0..n-1 adds them up
 // out[k] for k < n: P^H in, 2N unknowns per coarse site (index h*N + k)
-template <class T>
-__global__ void k_restrict_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+template <class T, class S>
+__global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
                                 cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     in += blockIdx.y * ldi;
@@ -968,8 +968,8 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<T>* __restrict__ P, co
     }
 }
 
-template <class T>
-__global__ void k_prolong_fine(AggMap m, int N, const cx<T>* __restrict__ P, const cx<T>* __restrict__ in,
+template <class T, class S>
+__global__ void k_prolong_fine(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
                                cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int vh = m.f.vh;
@@ -997,19 +997,19 @@ __global__ void k_prolong_fine(AggMap m, int N, const cx<T>* __restrict__ P, con
     store_spinor(out, vh, p, i, acc);
 }
 
-template <class T>
-void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+template <class T, class S>
+void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
                    long ldi, long ldo, Mask mk) {
     int nt = ((m.asz + 63) / 64) * 64;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
     dim3 grid(2 * m.c.vh, nr);
-    k_restrict_fine<T><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    k_restrict_fine<T, S><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
-template <class T>
-void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+template <class T, class S>
+void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
                   long ldi, long ldo, Mask mk) {
     dim3 grid(nblk_of(2L * m.f.vh, 256), nr);
-    k_prolong_fine<T><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    k_prolong_fine<T, S><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1236,19 +1236,23 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
 }
 
 // ---------------------------------------------------------------------------
+// operator kernels for compute type T and storage type S
+#define DD_FINE_OP_INST(T, S)                                                                                 \
+    template void fine_dirac<T, S>(const FineOp<T, S>&, const cx<T>*, cx<T>*, hipStream_t, int, long, Mask);  \
+    template void fine_sap_half<T, S>(const FineOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
+                                      int, long, Mask);                                                       \
+    template void fine_restrict<T, S>(const AggMap&, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int,   \
+                                      long, long, Mask);                                                      \
+    template void fine_prolong<T, S>(const AggMap&, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int,    \
+                                     long, long, Mask);
+
 #define DD_FINE_INST(T)                                                                                      \
     template void fine_import_gauge<T>(const Geom&, const double*, cx<T>*, hipStream_t);                     \
     template void fine_import_spinor<T>(const Geom&, const double*, cx<T>*, hipStream_t);                    \
     template void fine_export_spinor<T>(const Geom&, const cx<T>*, double*, hipStream_t);                    \
     template void fine_import_vectors<T>(const Geom&, int, const double*, cx<T>*, hipStream_t);              \
     template void fine_export_vectors<T>(const Geom&, int, const cx<T>*, double*, hipStream_t);              \
-    template void fine_dirac<T>(const FineOp<T>&, const cx<T>*, cx<T>*, hipStream_t, int, long, Mask);      \
-    template void fine_sap_half<T>(const FineOp<T>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, int, \
-                                   long, Mask);                                                               \
-    template void fine_restrict<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long, \
-                                   long, Mask);                                                               \
-    template void fine_prolong<T>(const AggMap&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t, int, long,  \
-                                  long, Mask);                                                                \
+    DD_FINE_OP_INST(T, T)                                                                                    \
     template void fine_gram_schmidt<T>(const AggMap&, int, const cx<T>*, cx<T>*, int*, hipStream_t);         \
     template void fine_assemble<T>(const FineOp<T>&, const AggMap&, int, const cx<T>*, cx<T>*, hipStream_t); \
     template void fine_random<T>(const Geom&, int, unsigned long long, int, cx<T>*, hipStream_t);            \
@@ -1256,5 +1260,6 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
 
 DD_FINE_INST(double)
 DD_FINE_INST(float)
+DD_FINE_OP_INST(float, _Float16)
 
 }  // namespace dd

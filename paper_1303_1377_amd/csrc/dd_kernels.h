@@ -17,12 +17,14 @@ enum FineSched {
     SCHED_XCD = 2,     // stencil and SAP: XCD-contiguous workgroup order
     SCHED_LDS = 4,     // stencil: one workgroup per layout block staged in LDS
 };
-template <class T>
+// Fields are stored in S (T, or _Float16 for the FP16-storage preconditioner)
+// and computed on in T.
+template <class T, class S = T>
 struct FineOp {
     Geom g;
-    const cx<T>* U;
-    const T* clov;
-    const T* clovinv;
+    const cx<S>* U;
+    const S* clov;
+    const S* clovinv;
     int sched = SCHED_LDS | SCHED_XCD;
 };
 
@@ -30,12 +32,12 @@ struct FineOp {
 //   M    [vol][9][nd][nd]  column-major blocks: slot 0 self, 1+mu couples x+mu,
 //                          5+mu couples x-mu (layout site order)
 //   Minv [vol][nd][nd]     column-major inverse of the self block
-template <class T>
+template <class T, class S = T>
 struct CoarseOp {
     Geom g;
     int nd;
-    const cx<T>* M;
-    const cx<T>* Minv;
+    const cx<S>* M;
+    const cx<S>* Minv;
 };
 
 // which right-hand sides of a batch a launch works on: flag r at p[r*stride];
@@ -81,22 +83,22 @@ void fine_clover_shift(const Geom& g, double dm, double* clov, double* clovinv, 
 void fine_clover_export(const Geom& g, const double* packed, double* canon, hipStream_t s);
 // Batched launches: nr right-hand sides, vector r at base + r*ld (complex
 // entries); RHS switched off by the mask are left untouched.
-template <class T>
-void fine_dirac(const FineOp<T>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1, long ld = 0,
+template <class T, class S>
+void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1, long ld = 0,
                 Mask mk = all_rhs());
 // one SAP half sweep: blocks listed in `blocks` (all of one colour); the block
 // operator is loaded once and applied to every right-hand side of the batch
-template <class T>
-void fine_sap_half(const FineOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+template <class T, class S>
+void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                    hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs());
 // LDS bytes one SAP workgroup needs for the layout blocks of g
 template <class T> size_t fine_sap_lds_bytes(const Geom& g);
 // P columns: [N][2][12][vh] (N fine spinors); coarse vectors: [cvol][2N] (layout order)
-template <class T>
-void fine_restrict(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
+template <class T, class S>
+void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
                    long ldi = 0, long ldo = 0, Mask mk = all_rhs());
-template <class T>
-void fine_prolong(const AggMap& m, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
+template <class T, class S>
+void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
                   long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
 void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
@@ -111,22 +113,22 @@ template <class T> void fine_random(const Geom& g, int n, unsigned long long see
 enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 // out(x) = [post Minv] ( self_mode(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
 // for the sites of parity `par` (0, 1) or all sites (par < 0).
-template <class T>
-void coarse_apply(const CoarseOp<T>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
+template <class T, class S>
+void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
 template <class T> void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s);
 template <class T> void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s);
 template <class T> void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s);
 template <class T> void coarse_export_blocks(const Geom& g, int nd, int nslot, const cx<T>* in, double* canon, hipStream_t s);
 template <class T> void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s);
-template <class T>
-void coarse_sap_half(const CoarseOp<T>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+template <class T, class S>
+void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                      hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs());
-template <class T>
-void coarse_restrict(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+template <class T, class S>
+void coarse_restrict(const AggMap& m, int ndf, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
                      int nr = 1, long ldi = 0, long ldo = 0, Mask mk = all_rhs());
-template <class T>
-void coarse_prolong(const AggMap& m, int ndf, int N, const cx<T>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
+template <class T, class S>
+void coarse_prolong(const AggMap& m, int ndf, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
                     int nr = 1, long ldi = 0, long ldo = 0, Mask mk = all_rhs());
 template <class T>
 void coarse_gram_schmidt(const AggMap& m, int ndf, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);

@@ -21,6 +21,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ddamg.h"
@@ -180,6 +181,10 @@ struct dd_ctx {
     cx<float>* U32 = nullptr;
     float* clov32 = nullptr;
     float* clovinv32 = nullptr;
+    // FP16 storage copies (precision 16), in the levels arena
+    cx<_Float16>* U16 = nullptr;
+    _Float16* clov16 = nullptr;
+    _Float16* clovinv16 = nullptr;
     int* dflags = nullptr;          // DI_WORDS device ints
     cx<double>* dred = nullptr;     // MAX_RHS * RS reduction results
     cx<double>* dy = nullptr;       // MAX_RHS * 32 least-squares solutions
@@ -311,6 +316,32 @@ struct Hier {
     int nd[DD_MAXLEV];
     FineOp<T> op0;
     CoarseOp<T> cop[DD_MAXLEV];
+    // FP16 storage of the operators the V-cycle applies (precision 16): the
+    // fine links and clover blocks, P, D_c and its self-block inverses; the
+    // setup builds P and D_c in T and refreshes these copies after each build
+    bool half = false;
+    FineOp<T, _Float16> op0h;
+    CoarseOp<T, _Float16> coph[DD_MAXLEV];
+    cx<_Float16>* Ph[DD_MAXLEV];
+    cx<_Float16>* Mh[DD_MAXLEV];
+    cx<_Float16>* Minvh[DD_MAXLEV];
+    // run f with the fine operator / coarse operator / P of the storage in use
+    template <class F> void with_fine(F&& f) {
+        if constexpr (std::is_same<T, float>::value)
+            if (half) { f(op0h); return; }
+        f(op0);
+    }
+    template <class F> void with_coarse(int l, F&& f) {
+        if constexpr (std::is_same<T, float>::value)
+            if (half) { f(coph[l]); return; }
+        f(cop[l]);
+    }
+    template <class F> void with_P(int l, F&& f) {
+        if constexpr (std::is_same<T, float>::value)
+            if (half) { f((const cx<_Float16>*)Ph[l]); return; }
+        f((const cx<T>*)P[l]);
+    }
+    void refresh_half(int l);
     int* blocks[DD_MAXLEV][2];
     int nblocks[DD_MAXLEV][2];
     AggMap amap[DD_MAXLEV];
@@ -355,6 +386,9 @@ struct Hier {
         memset(Minv, 0, sizeof Minv);
         memset(coarse_count, 0, sizeof coarse_count);
         memset(gmst, 0, sizeof gmst);
+        memset(Ph, 0, sizeof Ph);
+        memset(Mh, 0, sizeof Mh);
+        memset(Minvh, 0, sizeof Minvh);
         for (int l = 0; l < DD_MAXLEV; l++) last_its[l] = 8;
     }
 
@@ -457,6 +491,19 @@ void Hier<T>::build_geometry() {
     g[0] = C->g0;
     nd[0] = 12;
     op0 = fine_op<T>(C);
+    half = (p.precision == 16);
+    if (half) {
+        const long vol = 2L * g[0].vh;
+        C->U16 = A.get<cx<_Float16>>((size_t)vol * 36);
+        C->clov16 = reinterpret_cast<_Float16*>(A.get<cx<_Float16>>((size_t)vol * 36));
+        C->clovinv16 = reinterpret_cast<_Float16*>(A.get<cx<_Float16>>((size_t)vol * 36));
+        vec_convert<_Float16, float>(vol * 36, C->U32, C->U16, C->s);
+        vec_convert<_Float16, float>(vol * 36, reinterpret_cast<const cx<float>*>(C->clov32),
+                                     reinterpret_cast<cx<_Float16>*>(C->clov16), C->s);
+        vec_convert<_Float16, float>(vol * 36, reinterpret_cast<const cx<float>*>(C->clovinv32),
+                                     reinterpret_cast<cx<_Float16>*>(C->clovinv16), C->s);
+        op0h = FineOp<T, _Float16>{g[0], C->U16, C->clov16, C->clovinv16, C->sched};
+    }
     int d[4];
     memcpy(d, C->dims, sizeof d);
     for (int l = 0; l < nlev; l++) {
@@ -472,6 +519,11 @@ void Hier<T>::build_geometry() {
             M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
             Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
             cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l]};
+            if (half) {
+                Mh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
+                Minvh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
+                coph[l] = CoarseOp<T, _Float16>{g[l], nd[l], Mh[l], Minvh[l]};
+            }
             rc[l] = A.get<cx<T>>((size_t)R * nlv(l));
             ec[l] = A.get<cx<T>>((size_t)R * nlv(l));
         }
@@ -512,6 +564,7 @@ void Hier<T>::build_geometry() {
             memcpy(amap[l].a, a, sizeof a);
             tv[l] = A.get<cx<T>>((size_t)N[l] * nlv(l));
             P[l] = A.get<cx<T>>((size_t)N[l] * nlv(l));
+            if (half) Ph[l] = A.get<cx<_Float16>>((size_t)N[l] * nlv(l));
             memcpy(d, dc, sizeof d);
         }
     }
@@ -543,8 +596,8 @@ std::vector<double> Hier<T>::norms(long n, const cx<T>* v, long ld, const Batch&
 template <class T>
 void Hier<T>::apply_D(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
     Prof pr(C, l == 0 ? DD_K_DIRAC_PREC : DD_K_COARSE, l == 0 ? by_dirac(bt.count()) : by_coarse(l, 9, 2, true, bt.count()));
-    if (l == 0) fine_dirac<T>(op0, in, out, C->s, bt.nr, nlv(0), bt.mask());
-    else coarse_apply<T>(cop[l], -1, CS_SELF, in, 1, in, false, out, C->s, bt.mask(), bt.nr, nlv(l));
+    if (l == 0) with_fine([&](auto& op) { fine_dirac(op, in, out, C->s, bt.nr, nlv(0), bt.mask()); });
+    else with_coarse(l, [&](auto& op) { coarse_apply(op, -1, CS_SELF, in, 1, in, false, out, C->s, bt.mask(), bt.nr, nlv(l)); });
 }
 
 // nsweeps SAP iterations on level l (red blocks, then black blocks)
@@ -556,24 +609,32 @@ void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start,
             Prof pr(C, l == 0 ? DD_K_SAP : DD_K_COARSE_SAP,
                     l == 0 ? by_sap_half(bt.count()) : by_coarse(l, 9, 3, false, bt.count()));
             if (l == 0)
-                fine_sap_half<T>(op0, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s, bt.nr, nlv(0), bt.mask());
+                with_fine([&](auto& op) {
+                    fine_sap_half(op, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s, bt.nr, nlv(0), bt.mask());
+                });
             else
-                coarse_sap_half<T>(cop[l], blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s, bt.nr, nlv(l), bt.mask());
+                with_coarse(l, [&](auto& op) {
+                    coarse_sap_half(op, blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s, bt.nr, nlv(l), bt.mask());
+                });
         }
 }
 
 template <class T>
 void Hier<T>::restrict_(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
     Prof pr(C, DD_K_RESTRICT, by_transfer(l, bt.count()));
-    if (l == 0) fine_restrict<T>(amap[0], N[0], P[0], in, out, C->s, bt.nr, nlv(0), nlv(1), bt.mask());
-    else coarse_restrict<T>(amap[l], nd[l], N[l], P[l], in, out, C->s, bt.nr, nlv(l), nlv(l + 1), bt.mask());
+    with_P(l, [&](auto* Pl) {
+        if (l == 0) fine_restrict(amap[0], N[0], Pl, in, out, C->s, bt.nr, nlv(0), nlv(1), bt.mask());
+        else coarse_restrict(amap[l], nd[l], N[l], Pl, in, out, C->s, bt.nr, nlv(l), nlv(l + 1), bt.mask());
+    });
 }
 
 template <class T>
 void Hier<T>::prolong(int l, const cx<T>* in, cx<T>* out, const Batch& bt) {
     Prof pr(C, DD_K_PROLONG, by_transfer(l, bt.count()));
-    if (l == 0) fine_prolong<T>(amap[0], N[0], P[0], in, out, C->s, bt.nr, nlv(1), nlv(0), bt.mask());
-    else coarse_prolong<T>(amap[l], nd[l], N[l], P[l], in, out, C->s, bt.nr, nlv(l + 1), nlv(l), bt.mask());
+    with_P(l, [&](auto* Pl) {
+        if (l == 0) fine_prolong(amap[0], N[0], Pl, in, out, C->s, bt.nr, nlv(1), nlv(0), bt.mask());
+        else coarse_prolong(amap[l], nd[l], N[l], Pl, in, out, C->s, bt.nr, nlv(l + 1), nlv(l), bt.mask());
+    });
 }
 
 // out_o = (A_oo - D_oe A_ee^{-1} D_eo) v_o ; the even part of out is not written
@@ -581,8 +642,10 @@ template <class T>
 void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out, Mask mk, int nr, int k) {
     // two launches, each over one parity: 8 hop blocks + (Minv | self) per site
     Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
-    coarse_apply<T>(cop[l], 0, CS_NONE, nullptr, 1, v, true, wc[l], C->s, mk, nr, nlv(l));
-    coarse_apply<T>(cop[l], 1, CS_SELF, v, -1, wc[l], false, out, C->s, mk, nr, nlv(l));
+    with_coarse(l, [&](auto& op) {
+        coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, v, true, wc[l], C->s, mk, nr, nlv(l));
+        coarse_apply(op, 1, CS_SELF, v, -1, wc[l], false, out, C->s, mk, nr, nlv(l));
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -609,8 +672,10 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
     {
         Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false, k) + by_coarse(l, 8, 3, false, k));
-        coarse_apply<T>(cop[l], 0, CS_SELFINV, r, 0, nullptr, false, t, C->s, in, nr, nfull);
-        coarse_apply<T>(cop[l], 1, CS_IDENT, r, -1, t, false, f, C->s, in, nr, nfull);
+        with_coarse(l, [&](auto& op) {
+            coarse_apply(op, 0, CS_SELFINV, r, 0, (const cx<T>*)nullptr, false, t, C->s, in, nr, nfull);
+            coarse_apply(op, 1, CS_IDENT, r, -1, t, false, f, C->s, in, nr, nfull);
+        });
     }
     HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull * nr, C->s));
     HIPX(hipMemcpyAsync(V, f, sizeof(cx<T>) * nfull * nr, hipMemcpyDeviceToDevice, C->s));
@@ -662,7 +727,7 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     // e_e = A_ee^{-1} (r_e - D_eo e_o)
     {
         Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false, k));
-        coarse_apply<T>(cop[l], 0, CS_IDENT, r, -1, e, true, e, C->s, in, nr, nfull);
+        with_coarse(l, [&](auto& op) { coarse_apply(op, 0, CS_IDENT, r, -1, e, true, e, C->s, in, nr, nfull); });
     }
     int mx = 0;
     for (int q = 0; q < nr; q++) {
@@ -856,6 +921,20 @@ void Hier<T>::build(int l) {
     coarse_self_inverse<T>(g[l + 1], nd[l + 1], M[l + 1], Minv[l + 1], C->dflags + DI_BAD, C->s);
     HIPX(hipGetLastError());
     if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "singular coarse self block on level " + std::to_string(l + 1));
+    refresh_half(l);
+}
+
+// FP16 copies of P of level l and of the operator of level l+1
+template <class T>
+void Hier<T>::refresh_half(int l) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (!half) return;
+        const size_t nn = (size_t)nd[l + 1] * nd[l + 1], vc = 2L * g[l + 1].vh;
+        if (Ph[l]) vec_convert<_Float16, float>((long)N[l] * nlv(l), P[l], Ph[l], C->s);
+        vec_convert<_Float16, float>((long)(vc * 9 * nn), M[l + 1], Mh[l + 1], C->s);
+        vec_convert<_Float16, float>((long)(vc * nn), Minv[l + 1], Minvh[l + 1], C->s);
+    }
+    (void)l;
 }
 
 // Algorithm 2 on level l with level l+1 as the coarsest level of its V-cycles.
@@ -1069,7 +1148,7 @@ void dd_destroy(dd_ctx* ctx) { delete ctx; }
 static void configure_impl(dd_ctx* C, const dd_params* pin) {
     dd_params p = *pin;
     if (p.levels < 2 || p.levels > 3) fail(DD_EINVAL, "levels must be 2 or 3");
-    if (p.precision != 64 && p.precision != 32) fail(DD_EINVAL, "precision must be 64 or 32");
+    if (p.precision != 64 && p.precision != 32 && p.precision != 16) fail(DD_EINVAL, "precision must be 64, 32 or 16");
     if (p.outer_restart < 1 || p.outer_restart > 32 || p.coarse_restart < 1 || p.coarse_restart > 32 || p.mid_restart < 1 ||
         p.mid_restart > 32)
         fail(DD_EINVAL, "restart lengths must be in 1..32");
@@ -1230,6 +1309,14 @@ dd_status dd_set_mass(dd_ctx* ctx, double m0) {
         for (int l = 1; l < H.nlev; l++) {
             coarse_shift_diag(H.g[l], H.nd[l], dm, H.M[l], ctx->s);
             coarse_self_inverse(H.g[l], H.nd[l], H.M[l], H.Minv[l], ctx->dflags + DI_BAD, ctx->s);
+            H.refresh_half(l - 1);
+        }
+        if (H.half) {
+            const long vol = 2L * H.g[0].vh;
+            vec_convert<_Float16, float>(vol * 36, reinterpret_cast<const cx<float>*>(ctx->clov32),
+                                         reinterpret_cast<cx<_Float16>*>(ctx->clov16), ctx->s);
+            vec_convert<_Float16, float>(vol * 36, reinterpret_cast<const cx<float>*>(ctx->clovinv32),
+                                         reinterpret_cast<cx<_Float16>*>(ctx->clovinv16), ctx->s);
         }
     };
     if (ctx->configured) {
@@ -1378,15 +1465,12 @@ static double time_prec(dd_ctx* C, Hier<T>& H, int cls, int reps) {
     HIPX(hipMemsetAsync(H.wb[0], 0, sizeof(cx<T>) * n, C->s));
     hipEvent_t a = ev_get(C), b = ev_get(C);
     // one untimed launch first
-    if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
+    if (cls == DD_K_DIRAC_PREC) H.apply_D(0, H.wa[0], H.wb[0], single(C));
     else H.sap(0, H.wa[0], H.wb[0], 1, false, single(C));
     HIPX(hipEventRecord(a, C->s));
     for (int r = 0; r < reps; r++) {
-        if (cls == DD_K_DIRAC_PREC) fine_dirac<T>(H.op0, H.wa[0], H.wb[0], C->s);
-        else {
-            fine_sap_half<T>(H.op0, H.blocks[0][0], H.nblocks[0][0], H.wa[0], H.wb[0], C->p.mr_steps[0], C->s);
-            fine_sap_half<T>(H.op0, H.blocks[0][1], H.nblocks[0][1], H.wa[0], H.wb[0], C->p.mr_steps[0], C->s);
-        }
+        if (cls == DD_K_DIRAC_PREC) H.apply_D(0, H.wa[0], H.wb[0], single(C));
+        else H.sap(0, H.wa[0], H.wb[0], 1, false, single(C));
     }
     HIPX(hipEventRecord(b, C->s));
     HIPX(hipGetLastError());
@@ -1556,7 +1640,7 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
 static void set_sched(dd_ctx* C, int sched) {
     C->sched = sched;
     if (C->H64) C->H64->op0.sched = sched;
-    if (C->H32) C->H32->op0.sched = sched;
+    if (C->H32) C->H32->op0.sched = C->H32->op0h.sched = sched;
 }
 
 dd_status dd_set_schedule(dd_ctx* ctx, int sched) {

@@ -361,3 +361,57 @@ def test_schedules_give_identical_results():
     chosen, times = p.g.autotune(reps=2)
     say("autotune", chosen, times)
     assert chosen in range(8) and p.g.get_schedule() == chosen and all(t > 0 for t in times)
+
+
+def test_fp16_storage_operators():
+    """precision 16: operators stored in FP16, arithmetic in FP32.  Each
+    apply agrees with the FP64 oracle to the FP16 rounding bound (unit
+    roundoff 2^-11 on every stored entry, summed over the 9 terms of a site:
+    4e-3 of the largest entry) and is visibly less accurate than FP32 (so
+    the FP16 copies are the ones in use)."""
+    say("case: FP16 storage components 8^4")
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=6, m0=-0.25, csw=1.0)
+    _built(p, 8, (4, 4, 4, 4), (4, 4, 4, 4), precision=16)
+    v = F.gaussian_spinor(dims, 21)
+    errs = {}
+    d, _ = p.g.apply("D_PREC", 0, v)
+    errs["D"] = rel(to_np(d), p.o.apply(v))
+    rc, _ = p.g.apply("RESTRICT", 0, v)
+    errs["restrict"] = rel(to_np(rc), p.o.restrict(0, v))
+    vol_c, ndc = p.o.level_size(1)
+    rng = np.random.default_rng(9)
+    vc = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
+    pr, _ = p.g.apply("PROLONG", 0, vc)
+    errs["prolong"] = rel(to_np(pr), p.o.prolong(0, vc))
+    dc, _ = p.g.apply("D", 1, vc)
+    errs["D_c"] = rel(to_np(dc), p.o.apply(vc, level=1))
+    sc, _ = p.g.apply("SCHUR", 1, vc)
+    errs["schur"] = rel(to_np(sc), p.o.schur(1, vc))
+    z, _ = p.g.apply("SAP", 0, v, arg=1)
+    errs["sap"] = rel(to_np(z), p.o.sap(0, v, 1))
+    say("fp16 errors", errs)
+    for k, e in errs.items():
+        assert 1e-5 < e < (1e-2 if k == "sap" else 4e-3), (k, e)
+
+
+def test_fp16_preconditioner_solve():
+    """The FP64 outer FGMRES recovers full accuracy from the FP16-storage
+    preconditioner: true residual 1e-10, solution close to the FP64-preconditioned one."""
+    say("case: FP16-storage preconditioned solve 8^4")
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=3, m0=-0.25, csw=1.0)
+    kw = dict(levels=2, n_tv=[8], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4], n_inv=3, outer_restart=20)
+    b = F.gaussian_spinor(dims, 77)
+    xs = {}
+    for prec in (64, 16):
+        p.g.setup(params=G.default_params(precision=prec, **kw))
+        x, st = p.g.solve(b, 1e-10)
+        x = to_np(x)
+        r = b - p.o.apply(x)
+        say("precision", prec, "its", st["outer_iters"], "relres", np.linalg.norm(r) / np.linalg.norm(b))
+        assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+        xs[prec] = x
+    assert np.linalg.norm(xs[16] - xs[64]) <= 1e-8 * np.linalg.norm(xs[64])
