@@ -206,6 +206,13 @@ typedef enum {
  * iteration count of solver components in *iters when iters != NULL. */
 dd_status dd_apply(dd_ctx *ctx, int op, int level, int arg, const double *in, double *out, long *iters);
 
+/* dd_apply on k vectors at once (1 <= k <= max_rhs), run as one batch: the
+ * batched kernels of the level (for the coarse stencil with k >= 2 in FP32
+ * arithmetic, the matrix-core form).  in/out: device complex128
+ * [k][vol_level][nd_level]; iters: NULL or k counts. */
+dd_status dd_apply_batch(dd_ctx *ctx, int op, int level, int arg, int k, const double *in, double *out,
+                         long *iters);
+
 /* Lattice dims and unknowns per site of a level (level 0: the fine lattice). */
 dd_status dd_level_info(const dd_ctx *ctx, int level, int dims[4], int *nd);
 
@@ -259,16 +266,22 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   staged in LDS and each internal link applied twice per
  *                   load (needs 32..128 sites per block and parity; other
  *                   layouts fall back to the FUSED schedule's kernel)
+ *   DD_SCHED_NO_MFMA  the coarse stencil with 2..16 right-hand sides in FP32
+ *                   arithmetic runs on the vector units (one workgroup per
+ *                   site and RHS) instead of the matrix cores (one workgroup
+ *                   per site for all RHS); results agree to rounding
+ * The default is DD_SCHED_LDS | DD_SCHED_XCD with the matrix cores on.
  * ------------------------------------------------------------------------- */
-enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4 };
+enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8 };
 
 /* Select a schedule (a combination of DD_SCHED_* flags). DD_EINVAL otherwise. */
 dd_status dd_set_schedule(dd_ctx *ctx, int sched);
 /* Current schedule, -1 for ctx == NULL. */
 int dd_get_schedule(const dd_ctx *ctx);
 
-/* Time every schedule on the context's own fields (the FP64 stencil plus nu
- * SAP sweeps once configured, each the mean of `reps` launches) and keep the
+/* Time every schedule of the fine kernels (flag sets 0..7; the NO_MFMA bit is
+ * kept as set) on the context's own fields (the FP64 stencil plus nu SAP
+ * sweeps once configured, each the mean of `reps` launches) and keep the
  * fastest.  chosen (may be NULL) receives it; times_ms (may be NULL) holds 8
  * doubles, the cost of each schedule (flag set 0..7) in ms. */
 dd_status dd_autotune(dd_ctx *ctx, int reps, int *chosen, double *times_ms);

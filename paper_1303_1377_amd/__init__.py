@@ -101,6 +101,7 @@ def library():
         L.dd_get_coarse.argtypes = [vp, C.c_int, vp, vp]
         L.dd_get_clover.argtypes = [vp, vp, vp]
         L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
+        L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
         L.dd_profile.argtypes = [vp, C.c_int]
         L.dd_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_long), C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -114,7 +115,7 @@ def library():
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
-                     "dd_time_kernel", "dd_set_schedule", "dd_autotune"):
+                     "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -333,3 +334,24 @@ class Solver:
         self._check(library().dd_apply(self.h, code, level, int(arg), C.c_void_p(vin.data_ptr()),
                                        C.c_void_p(out.data_ptr()), C.byref(its)))
         return out, its.value
+
+    def apply_batch(self, op, level, vs, arg=0):
+        """One component on k vectors at once ([k][vol_level][nd_level]); returns (out, [iters])."""
+        torch = _torch()
+        code = OPS[op] if isinstance(op, str) else int(op)
+        vin = _dev(vs)
+        k = vin.shape[0]
+        vin = vin.reshape(k, -1).contiguous()
+        if code == OPS["RESTRICT"]:
+            vol, nd = self.level_size(level + 1)
+            out = torch.empty((k, vol, nd), dtype=torch.complex128, device="cuda")
+        elif code == OPS["PROLONG"]:
+            vol, nd = self.level_size(level)
+            out = torch.empty((k, vol, nd), dtype=torch.complex128, device="cuda")
+        else:
+            vol, nd = self.level_size(level)
+            out = torch.empty((k, vol, nd), dtype=torch.complex128, device="cuda")
+        its = (C.c_long * k)()
+        self._check(library().dd_apply_batch(self.h, code, level, int(arg), int(k), C.c_void_p(vin.data_ptr()),
+                                             C.c_void_p(out.data_ptr()), its))
+        return out, list(its)

@@ -9,6 +9,8 @@
 // Vectors are [parity][layout index][nd] (a site's unknowns contiguous);
 // operator blocks are column-major so that the thread owning row r reads
 // consecutive addresses across the wavefront.
+#include <type_traits>
+
 #include "dd_kernels.h"
 
 namespace dd {
@@ -117,10 +119,228 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-RHS coarse stencil on the matrix cores.  For one site and k <= 16
+// right-hand sides the apply is a sum of complex products
+//     C (nd x k) += M_s (nd x nd) X_s (nd x k),   s = self + 8 hops,
+// which runs as real MFMA tiles on the split real / imaginary parts:
+//     C_re += M_re X_re - M_im X_im,   C_im += M_re X_im + M_im X_re.
+// Workgroup = one site; wave w owns rows [16w, 16w+16) of C (nd <= 64).  The
+// k right-hand-side columns of every X_s are staged once in LDS (one coalesced
+// pass per RHS), so each block entry is read once for all right-hand sides.
+// The FP32 form uses v_mfma_f32_16x16x4_f32 on FP32 blocks; the FP16-storage
+// form uses v_mfma_f32_16x16x16_f16 with the blocks as stored and X rounded to
+// FP16 (FP32 accumulation in both).
+//   16x16xK tile layout (lane l = 16 q + j):  A row j, k-slice q;  B column j,
+//   k-slice q;  D column j, rows 4q .. 4q+3 in the four result registers.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+template <class S> struct MfmaK;
+template <> struct MfmaK<float> { static constexpr int K = 4; };       // k per instruction, FP32 inputs
+template <> struct MfmaK<_Float16> { static constexpr int K = 16; };   // k per instruction, FP16 inputs
+
+__device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma(f16x4 a, f16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// A fragment of a column-major nd x nd block: row r, columns c0 .. c0+K/4-1
+// of this lane's k-slice; zero outside the block.
+template <class S>
+__device__ __forceinline__ void a_frag(const cx<S>* __restrict__ A, int nd, int r, int c0, float sgn,
+                                       typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& re,
+                                       typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& im) {
+    if constexpr (std::is_same<S, float>::value) {
+        cx<float> a = (r < nd && c0 < nd) ? A[(size_t)c0 * nd + r] : czero<float>();
+        re = sgn * a.re;
+        im = sgn * a.im;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int c = c0 + q;
+            cx<_Float16> a = (r < nd && c < nd) ? A[(size_t)c * nd + r] : cx<_Float16>{_Float16(0), _Float16(0)};
+            re[q] = sgn > 0 ? a.re : _Float16(-a.re);
+            im[q] = sgn > 0 ? a.im : _Float16(-a.im);
+        }
+    }
+}
+
+// B fragment from the staged X [ndk][16] (split re / im planes of type S)
+template <class S>
+__device__ __forceinline__ void b_frag(const S* __restrict__ Xre, const S* __restrict__ Xim, int c0, int j,
+                                       typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& re,
+                                       typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& im) {
+    if constexpr (std::is_same<S, float>::value) {
+        re = Xre[c0 * 16 + j];
+        im = Xim[c0 * 16 + j];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            re[q] = Xre[(c0 + q) * 16 + j];
+            im[q] = Xim[(c0 + q) * 16 + j];
+        }
+    }
+}
+
+// C += A X over the ndk rows of X for one 16-row tile
+template <class S>
+__device__ __forceinline__ void tile_mma(const cx<S>* __restrict__ A, int nd, int ndk, int r, int lane, float sgn,
+                                         const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
+    constexpr int K = MfmaK<S>::K;
+    constexpr int KL = K / 4;   // k entries per lane
+    const int q = lane >> 4, j = lane & 15;
+    for (int k0 = 0; k0 < ndk; k0 += K) {
+        const int c0 = k0 + q * KL;
+        typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type are, aim, bre, bim, naim;
+        a_frag<S>(A, nd, r, c0, sgn, are, aim);
+        b_frag<S>(Xre, Xim, c0, j, bre, bim);
+        naim = -aim;
+        cre = mma(are, bre, cre);
+        cre = mma(naim, bim, cre);
+        cim = mma(are, bim, cim);
+        cim = mma(aim, bre, cim);
+    }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op, int par, int self_mode,
+                                                           const cx<float>* __restrict__ in1, int hop_sign,
+                                                           const cx<float>* in2, int post_inv, cx<float>* out, Mask mk,
+                                                           long ld, int nr) {
+    constexpr int K = MfmaK<S>::K;
+    extern __shared__ char smem_raw[];
+    __shared__ const cx<S>* mat[9];
+    __shared__ const cx<float>* vin[9];
+    __shared__ int nslot_s;
+    const Geom g = op.g;
+    const int nd = op.nd;
+    const int ndk = (nd + K - 1) / K * K;          // k extent padded to the instruction
+    S* Xre = reinterpret_cast<S*>(smem_raw);        // [9][ndk][16]
+    S* Xim = Xre + 9 * ndk * 16;
+    int p, i;
+    if (par < 0) { p = blockIdx.x >= g.vh; i = blockIdx.x - p * g.vh; }
+    else { p = par; i = blockIdx.x; }
+    const size_t gs = (size_t)p * g.vh + i;
+    const size_t nn = (size_t)nd * nd;
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) {
+        int ns = 0;
+        if (self_mode == CS_SELF) { mat[ns] = op.M + gs * 9 * nn; vin[ns] = in1 + gs * nd; ns++; }
+        else if (self_mode == CS_SELFINV) { mat[ns] = op.Minv + gs * nn; vin[ns] = in1 + gs * nd; ns++; }
+        if (hop_sign != 0) {
+            int x[4];
+            cb_coords(g, p, i, x);
+            for (int k = 0; k < 8; k++) {
+                int y[4];
+                nb_coords(g, x, k, y);
+                mat[ns] = op.M + (gs * 9 + 1 + k) * nn;
+                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
+                ns++;
+            }
+        }
+        nslot_s = ns;
+    }
+    __syncthreads();
+    const int ns = nslot_s;
+    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    // stage X_s: entry (s, c, j), c fastest so each RHS column is read contiguously
+    for (int e = t; e < ns * 16 * ndk; e += nt) {
+        const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+        const int j = rem / ndk, c = rem - j * ndk;
+        cx<float> v = czero<float>();
+        if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
+        Xre[(sl * ndk + c) * 16 + j] = S(v.re);
+        Xim[(sl * ndk + c) * 16 + j] = S(v.im);
+    }
+    __syncthreads();
+    const int w = t >> 6, lane = t & 63;
+    const int ntile = (nd + 15) / 16;
+    const int r = 16 * w + (lane & 15);
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    if (w < ntile) {
+        for (int sl = 0; sl < ns; sl++) {
+            const float sgn = (sl >= nself && hop_sign < 0) ? -1.f : 1.f;
+            tile_mma<S>(mat[sl], nd, ndk, r, lane, sgn, Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
+        }
+    }
+    // result rows 16w + 4q + v, column j
+    const int q = lane >> 4, j = lane & 15;
+    const bool jon = j < nr && mk.on(j);
+    if (self_mode == CS_IDENT && w < ntile && jon) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int row = 16 * w + 4 * q + v;
+            if (row < nd) {
+                cx<float> a = in1[(size_t)j * ld + gs * nd + row];
+                cre[v] += a.re;
+                cim[v] += a.im;
+            }
+        }
+    }
+    if (!post_inv) {
+        if (w < ntile && jon) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = 16 * w + 4 * q + v;
+                if (row < nd) out[(size_t)j * ld + gs * nd + row] = cx<float>{cre[v], cim[v]};
+            }
+        }
+        return;
+    }
+    // post multiplication by the self-block inverse: stage the result as a new X
+    __syncthreads();
+    for (int e = t; e < ndk * 16; e += nt) {   // clear (padding rows stay zero)
+        Xre[e] = S(0.f);
+        Xim[e] = S(0.f);
+    }
+    __syncthreads();
+    if (w < ntile) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int row = 16 * w + 4 * q + v;
+            if (row < nd) {
+                Xre[row * 16 + j] = S(cre[v]);
+                Xim[row * 16 + j] = S(cim[v]);
+            }
+        }
+    }
+    __syncthreads();
+    if (w < ntile) {
+        f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+        tile_mma<S>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, dre, dim);
+        if (jon) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = 16 * w + 4 * q + v;
+                if (row < nd) out[(size_t)j * ld + gs * nd + row] = cx<float>{dre[v], dim[v]};
+            }
+        }
+    }
+}
+
+template <class S>
+static size_t mfma_lds_bytes(int nd) {
+    const int K = MfmaK<S>::K;
+    const int ndk = (nd + K - 1) / K * K;
+    return 2 * sizeof(S) * 9 * (size_t)ndk * 16;
+}
+
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
     int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
+    if constexpr (std::is_same<T, float>::value) {
+        // the matrix-core form serves FP32 arithmetic with 2..16 right-hand sides and nd <= 64
+        if (op.mfma && nr >= 2 && nr <= 16 && op.nd <= 64) {
+            k_coarse_apply_mfma<S><<<nsite, 64 * ((op.nd + 15) / 16), mfma_lds_bytes<S>(op.nd), s>>>(
+                op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
+            return;
+        }
+    }
     int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
     int nw = nslot >= 8 ? CA_WAVES : (post_inv || nslot > 0 ? 4 : 1);
     dim3 grid(nsite, nr);

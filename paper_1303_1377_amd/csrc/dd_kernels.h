@@ -16,6 +16,7 @@ enum FineSched {
     SCHED_FUSED = 1,   // stencil: one workgroup covers both parities of its layout blocks
     SCHED_XCD = 2,     // stencil and SAP: XCD-contiguous workgroup order
     SCHED_LDS = 4,     // stencil: one workgroup per layout block staged in LDS
+    SCHED_NO_MFMA = 8, // multi-RHS coarse stencil on the vector units instead of the matrix cores
 };
 // Fields are stored in S (T, or _Float16 for the FP16-storage preconditioner)
 // and computed on in T.
@@ -32,12 +33,16 @@ struct FineOp {
 //   M    [vol][9][nd][nd]  column-major blocks: slot 0 self, 1+mu couples x+mu,
 //                          5+mu couples x-mu (layout site order)
 //   Minv [vol][nd][nd]     column-major inverse of the self block
+//   mfma  with 2..16 right-hand sides and FP32 arithmetic the apply runs on
+//         the matrix cores (one launch for all RHS, each block entry read
+//         once); 0: one workgroup per (site, RHS) on the vector units
 template <class T, class S = T>
 struct CoarseOp {
     Geom g;
     int nd;
     const cx<S>* M;
     const cx<S>* Minv;
+    int mfma = 1;
 };
 
 // which right-hand sides of a batch a launch works on: flag r at p[r*stride];

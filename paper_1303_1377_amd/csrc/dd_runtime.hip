@@ -518,11 +518,11 @@ void Hier<T>::build_geometry() {
             nd[l] = 2 * p.n_tv[l - 1];
             M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
             Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
-            cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l]};
+            cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1};
             if (half) {
                 Mh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
                 Minvh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
-                coph[l] = CoarseOp<T, _Float16>{g[l], nd[l], Mh[l], Minvh[l]};
+                coph[l] = CoarseOp<T, _Float16>{g[l], nd[l], Mh[l], Minvh[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1};
             }
             rc[l] = A.get<cx<T>>((size_t)R * nlv(l));
             ec[l] = A.get<cx<T>>((size_t)R * nlv(l));
@@ -1519,44 +1519,50 @@ dd_status dd_time_kernel(dd_ctx* ctx, int cls, int reps, double* avg_ms) {
 
 long long dd_device_bytes(const dd_ctx* ctx) { return ctx ? ctx->fields.bytes + ctx->levels.bytes : 0; }
 
+// op on k vectors (canonical [k][vol][nd] in and out) as one batch
 template <class T>
-static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const double* in, double* out, long* iters) {
+static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, const double* in, double* out,
+                       long* iters) {
     if (l < 0 || l >= H.nlev) fail(DD_EINVAL, "level out of range");
-    long its = 0;
+    if (k < 1 || k > C->R) fail(DD_EINVAL, "batch of " + std::to_string(k) + " vectors; max_rhs is " + std::to_string(C->R));
+    long its[MAX_RHS] = {0};
     auto imp = [&](int lev, const double* src, cx<T>* dst) {
-        if (lev == 0) fine_import_spinor<T>(H.g[0], src, dst, C->s);
-        else coarse_import_vector<T>(H.g[lev], H.nd[lev], 1, src, dst, C->s);
+        if (lev == 0) fine_import_vectors<T>(H.g[0], k, src, dst, C->s);
+        else coarse_import_vector<T>(H.g[lev], H.nd[lev], k, src, dst, C->s);
     };
     auto exp_ = [&](int lev, const cx<T>* src, double* dst) {
-        if (lev == 0) fine_export_spinor<T>(H.g[0], src, dst, C->s);
-        else coarse_export_vector<T>(H.g[lev], H.nd[lev], 1, src, dst, C->s);
+        if (lev == 0) fine_export_vectors<T>(H.g[0], k, src, dst, C->s);
+        else coarse_export_vector<T>(H.g[lev], H.nd[lev], k, src, dst, C->s);
+    };
+    auto counts = [&](int lev) {
+        for (int r = 0; r < k; r++) its[r] = H.coarse_count[lev][r];
     };
     const int bottom = H.nlev - 1;
-    const Batch one = single(C);
+    const Batch bt{k, C->dflags + DI_ONES, (1u << k) - 1};
     switch (op) {
         case DD_OP_D:
             if (l == 0) {
                 const long n = 24L * C->g0.vh;
                 cx<double>* a = C->ot;
-                cx<double>* b = C->ot + n;
-                fine_import_spinor<double>(C->g0, in, a, C->s);
-                fine_dirac<double>(fine_op<double>(C), a, b, C->s);
-                fine_export_spinor<double>(C->g0, b, out, C->s);
+                cx<double>* b = C->ot + (size_t)C->R * n;
+                fine_import_vectors<double>(C->g0, k, in, a, C->s);
+                fine_dirac<double>(fine_op<double>(C), a, b, C->s, k, n, bt.mask());
+                fine_export_vectors<double>(C->g0, k, b, out, C->s);
                 break;
             }
             imp(l, in, H.wa[l]);
-            H.apply_D(l, H.wa[l], H.wb[l], one);
+            H.apply_D(l, H.wa[l], H.wb[l], bt);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_D_PREC:
             imp(0, in, H.wa[0]);
-            H.apply_D(0, H.wa[0], H.wb[0], one);
+            H.apply_D(0, H.wa[0], H.wb[0], bt);
             exp_(0, H.wb[0], out);
             break;
         case DD_OP_SAP:
             if (l >= bottom) fail(DD_EINVAL, "no SAP on the coarsest level");
             imp(l, in, H.wa[l]);
-            H.sap(l, H.wa[l], H.wb[l], arg, true, one);
+            H.sap(l, H.wa[l], H.wb[l], arg, true, bt);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_VCYCLE:
@@ -1564,43 +1570,44 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
             if (!C->have_setup) fail(DD_ESTATE, "hierarchy not built");
             imp(l, in, H.wa[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            H.vcycle(l, bottom, H.wa[l], H.wb[l], one);
-            its = H.coarse_count[l + 1][0];
+            H.vcycle(l, bottom, H.wa[l], H.wb[l], bt);
+            counts(l + 1);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_RESTRICT:
             if (l >= bottom) fail(DD_EINVAL, "no restriction from the coarsest level");
             imp(l, in, H.wa[l]);
-            H.restrict_(l, H.wa[l], H.wa[l + 1], one);
+            H.restrict_(l, H.wa[l], H.wa[l + 1], bt);
             exp_(l + 1, H.wa[l + 1], out);
             break;
         case DD_OP_PROLONG:
             if (l >= bottom) fail(DD_EINVAL, "no prolongation to the coarsest level");
             imp(l + 1, in, H.wa[l + 1]);
-            H.prolong(l, H.wa[l + 1], H.wa[l], one);
+            H.prolong(l, H.wa[l + 1], H.wa[l], bt);
             exp_(l, H.wa[l], out);
             break;
         case DD_OP_COARSE_SOLVE:
             if (l < 1) fail(DD_EINVAL, "coarse solve needs level >= 1");
             imp(l, in, H.rc[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            H.gmres_oe(l, H.rc[l], H.ec[l], one);
-            its = H.coarse_count[l][0];
+            H.gmres_oe(l, H.rc[l], H.ec[l], bt);
+            counts(l);
             exp_(l, H.ec[l], out);
             break;
         case DD_OP_SCHUR:
             if (l < 1) fail(DD_EINVAL, "Schur complement needs level >= 1");
             imp(l, in, H.wa[l]);
-            H.schur(l, H.wa[l], H.wb[l], one.mask(), 1, 1);
-            HIPX(hipMemsetAsync(H.wb[l], 0, sizeof(cx<T>) * (size_t)H.g[l].vh * H.nd[l], C->s));
+            H.schur(l, H.wa[l], H.wb[l], bt.mask(), k, k);
+            for (int r = 0; r < k; r++)
+                HIPX(hipMemsetAsync(H.wb[l] + (size_t)r * H.nlv(l), 0, sizeof(cx<T>) * (size_t)H.g[l].vh * H.nd[l], C->s));
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_FGMRES:
             if (l < 1 || l >= bottom) fail(DD_EINVAL, "middle-level FGMRES needs 1 <= level < levels-1");
             imp(l, in, H.rc[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            H.fgmres_mid(l, bottom, H.rc[l], H.ec[l], one);
-            its = H.coarse_count[l][0];
+            H.fgmres_mid(l, bottom, H.rc[l], H.ec[l], bt);
+            counts(l);
             exp_(l, H.ec[l], out);
             break;
         default:
@@ -1608,7 +1615,18 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, const doub
     }
     HIPX(hipGetLastError());
     sync(C);
-    if (iters) *iters = its;
+    if (iters)
+        for (int r = 0; r < k; r++) iters[r] = its[r];
+}
+
+dd_status dd_apply_batch(dd_ctx* ctx, int op, int level, int arg, int k, const double* in, double* out, long* iters) {
+    ABI_TRY(ctx)
+    if (!in || !out) fail(DD_EINVAL, "NULL vector");
+    if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
+    if (ctx->H64) apply_impl(ctx, *ctx->H64, op, level, arg, k, in, out, iters);
+    else apply_impl(ctx, *ctx->H32, op, level, arg, k, in, out, iters);
+    return DD_OK;
+    ABI_END(ctx)
 }
 
 dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, double* out, long* iters) {
@@ -1629,8 +1647,8 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
         }
         fail(DD_ESTATE, "dd_configure first");
     }
-    if (ctx->H64) apply_impl(ctx, *ctx->H64, op, level, arg, in, out, iters);
-    else apply_impl(ctx, *ctx->H32, op, level, arg, in, out, iters);
+    if (ctx->H64) apply_impl(ctx, *ctx->H64, op, level, arg, 1, in, out, iters);
+    else apply_impl(ctx, *ctx->H32, op, level, arg, 1, in, out, iters);
     return DD_OK;
     ABI_END(ctx)
 }
@@ -1639,13 +1657,20 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
 
 static void set_sched(dd_ctx* C, int sched) {
     C->sched = sched;
-    if (C->H64) C->H64->op0.sched = sched;
-    if (C->H32) C->H32->op0.sched = C->H32->op0h.sched = sched;
+    const int mf = (sched & SCHED_NO_MFMA) ? 0 : 1;
+    if (C->H64) {
+        C->H64->op0.sched = sched;
+        for (int l = 0; l < DD_MAXLEV; l++) C->H64->cop[l].mfma = mf;
+    }
+    if (C->H32) {
+        C->H32->op0.sched = C->H32->op0h.sched = sched;
+        for (int l = 0; l < DD_MAXLEV; l++) C->H32->cop[l].mfma = C->H32->coph[l].mfma = mf;
+    }
 }
 
 dd_status dd_set_schedule(dd_ctx* ctx, int sched) {
     ABI_TRY(ctx)
-    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS)) fail(DD_EINVAL, "unknown schedule flags");
+    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA)) fail(DD_EINVAL, "unknown schedule flags");
     set_sched(ctx, sched);
     return DD_OK;
     ABI_END(ctx)
@@ -1660,10 +1685,11 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     ABI_TRY(ctx)
     if (reps < 1) fail(DD_EINVAL, "reps >= 1");
     const int nsched = (SCHED_FUSED | SCHED_XCD | SCHED_LDS) + 1;
+    const int keep = ctx->sched & SCHED_NO_MFMA;
     double best = 0;
     int pick = ctx->sched;
     for (int sc = 0; sc < nsched; sc++) {
-        set_sched(ctx, sc);
+        set_sched(ctx, sc | keep);
         double ms = 0, t = 0;
         if (dd_time_kernel(ctx, DD_K_DIRAC64, reps, &t) != DD_OK) return DD_EDEVICE;
         ms += t;
@@ -1672,7 +1698,7 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
             ms += std::max(ctx->p.nu, 1) * t;
         }
         if (times_ms) times_ms[sc] = ms;
-        if (sc == 0 || ms < best) { best = ms; pick = sc; }
+        if (sc == 0 || ms < best) { best = ms; pick = sc | keep; }
     }
     set_sched(ctx, pick);
     if (chosen) *chosen = pick;

@@ -415,3 +415,70 @@ def test_fp16_preconditioner_solve():
         assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
         xs[prec] = x
     assert np.linalg.norm(xs[16] - xs[64]) <= 1e-8 * np.linalg.norm(xs[64])
+
+
+def _built_batch(precision, k, sched=None):
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=8, m0=-0.25, csw=1.0)
+    kw = dict(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4], coarse_fixed=6)
+    p.o.configure(**kw)
+    p.g.configure(G.default_params(precision=precision, max_rhs=k, **kw))
+    if sched is not None:
+        p.g.set_schedule(sched)
+    tv = p.vectors(0, 20, 12)
+    p.o.set_vectors(0, tv)
+    p.o.build(0)
+    p.g.set_test_vectors(0, tv)
+    p.g.build_level(0)
+    p.g.mark_setup()
+    p.o.mark_setup()
+    vol_c, ndc = p.o.level_size(1)
+    rng = np.random.default_rng(31)
+    V = rng.standard_normal((k, vol_c, ndc)) + 1j * rng.standard_normal((k, vol_c, ndc))
+    return p, V
+
+
+@pytest.mark.parametrize("precision,bound", [(32, 2e-6), (16, 4e-3)])
+def test_multi_rhs_coarse_stencil(precision, bound):
+    """Twelve coarse vectors (nd = 40, the production shape) through the
+    batched coarse stencil on the matrix cores: D_c and the Schur complement
+    per vector against the FP64 oracle, at the FP32 bar or the FP16-storage
+    bound; the vector-unit form gives the same within rounding."""
+    say("case: multi-RHS coarse stencil precision", precision)
+    k = 12
+    p, V = _built_batch(precision, k)
+    D, _ = p.g.apply_batch("D", 1, V)
+    S, _ = p.g.apply_batch("SCHUR", 1, V)
+    D, S = to_np(D), to_np(S)
+    for q in range(k):
+        ed = rel(D[q], p.o.apply(V[q], level=1))
+        es = rel(S[q], p.o.schur(1, V[q]))
+        assert ed < bound and es < bound, (q, ed, es)
+    p.g.set_schedule(p.g.get_schedule() | 8)
+    D2, _ = p.g.apply_batch("D", 1, V)
+    e2 = rel(D, to_np(D2))
+    say("mfma vs vector units", e2)
+    # each form is within the bar of the exact result, so they differ by at most twice it
+    assert e2 < 2 * bound, e2
+
+
+def test_multi_rhs_coarse_solve_and_vcycle():
+    """A batch of 12 coarse solves (fixed 6 GMRES iterations) and 12 V-cycles
+    equal the one-at-a-time results of the same FP32 path within FP32 rounding."""
+    say("case: multi-RHS coarse solve / V-cycle")
+    k = 12
+    p, V = _built_batch(32, k)
+    E, its = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    E = to_np(E)
+    assert its == [6] * k
+    for q in range(k):
+        e1, it1 = p.g.apply("COARSE_SOLVE", 1, V[q])
+        assert it1 == 6 and rel(E[q], to_np(e1)) < 1e-4
+        assert rel(E[q], p.o.coarse_solve(1, V[q])[0]) < 1e-4
+    R = np.stack([F.gaussian_spinor((8, 8, 8, 8), 500 + q) for q in range(k)])
+    Z, _ = p.g.apply_batch("VCYCLE", 0, R)
+    Z = to_np(Z)
+    for q in (0, 5, 11):
+        assert rel(Z[q].reshape(-1), p.o.vcycle(0, R[q]).reshape(-1)) < 1e-4
