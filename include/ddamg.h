@@ -248,7 +248,8 @@ dd_status dd_profile_read(dd_ctx *ctx, int kernel_class, long *launches, double 
  * data between two HIP events; *avg_ms = mean duration of one launch.
  * DD_K_BLAS times a plain copy kernel of one FP64 fine spinor (16 bytes read
  * and 16 written per complex entry): the reference for achievable bandwidth
- * and for scaling memory counters.  Needs dd_configure (for DD_K_DIRAC_PREC /
+ * and for scaling memory counters.  DD_K_COARSE (after dd_setup) times D_c of
+ * level 1 applied to max_rhs random vectors as one batch.  Needs dd_configure (for DD_K_DIRAC_PREC /
  * DD_K_SAP). */
 dd_status dd_time_kernel(dd_ctx *ctx, int kernel_class, int reps, double *avg_ms);
 

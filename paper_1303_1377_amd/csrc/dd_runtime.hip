@@ -1510,6 +1510,30 @@ dd_status dd_time_kernel(dd_ctx* ctx, int cls, int reps, double* avg_ms) {
         *avg_ms = ms / reps;
         return DD_OK;
     }
+    if (cls == DD_K_COARSE) {
+        // D_c on level 1 applied to max_rhs random vectors at once
+        if (!ctx->have_setup) fail(DD_ESTATE, "the coarse stencil is timed after dd_setup");
+        auto go = [&](auto& H) {
+            const int k = ctx->R;
+            coarse_random(H.g[1], H.nd[1], k, 4242ULL, 9, H.wa[1], ctx->s);
+            const Batch bt{k, ctx->dflags + DI_ONES, (1u << k) - 1};
+            H.apply_D(1, H.wa[1], H.wb[1], bt);
+            hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
+            HIPX(hipEventRecord(e0, ctx->s));
+            for (int r = 0; r < reps; r++) H.apply_D(1, H.wa[1], H.wb[1], bt);
+            HIPX(hipEventRecord(e1, ctx->s));
+            HIPX(hipGetLastError());
+            HIPX(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPX(hipEventElapsedTime(&ms, e0, e1));
+            ctx->ev_pool.push_back(e0);
+            ctx->ev_pool.push_back(e1);
+            *avg_ms = ms / reps;
+        };
+        if (ctx->H64) go(*ctx->H64);
+        else go(*ctx->H32);
+        return DD_OK;
+    }
     if (cls != DD_K_DIRAC_PREC && cls != DD_K_SAP) fail(DD_EINVAL, "kernel class not timed standalone");
     if (!ctx->configured) fail(DD_ESTATE, "dd_configure first");
     *avg_ms = ctx->H64 ? time_prec(ctx, *ctx->H64, cls, reps) : time_prec(ctx, *ctx->H32, cls, reps);

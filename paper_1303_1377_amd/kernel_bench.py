@@ -14,6 +14,9 @@ Byte model per lattice site (reals of the storage precision):
   stencil   192 = links 72 + clover 72 + spinor in 24 + spinor out 24
   SAP sweep 432 = 2 half sweeps x (links 72 + clover 72 + b 24 + z 24 + z 24) / 2
   copy      one FP64 spinor read and written: 2 x 24 reals of 8 bytes
+  coarse    per coarse site: 9 blocks of nd x nd complex (storage precision)
+            + k input and k output vectors of nd complex FP32; flops 9 nd^2 k x 8
+            (kernel names coarse<precision>x<k>, e.g. coarse32x12, coarse16x12)
 """
 from __future__ import annotations
 
@@ -45,6 +48,25 @@ def run(dims=(64, 32, 32, 32), kernels=("copy", "dirac64", "dirac32", "sap32", "
     for k, sc in [(k, sc) for k in kernels for sc in (scheds if k != "copy" else (None,))]:
         if sc is not None:
             s.set_schedule(sc)
+        if k.startswith("coarse"):
+            # coarse<prec>x<k>: D_c of level 1 (aggregates 4^4, N = 20) on k RHS at once
+            prec_s, kk = k[len("coarse"):].split("x")
+            prec, kk = int(prec_s), int(kk)
+            if configured != ("coarse", prec, kk, sc):
+                s.setup(params=G.default_params(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)],
+                                                mr_steps=[mr], precision=prec, n_inv=0, max_rhs=kk))
+                if sc is not None:
+                    s.set_schedule(sc)
+                configured = ("coarse", prec, kk, sc)
+            ms = s.time_kernel("coarse", reps=reps)
+            vol_c, nd = s.level_size(1)
+            sz = 8 if prec != 16 else 4
+            by = vol_c * (9 * nd * nd * sz + 2 * kk * nd * 8)
+            fl = vol_c * 9 * nd * nd * kk * 8
+            key = k if sc is None or len(scheds) == 1 else "%s_sched%d" % (k, sc)
+            out[key] = dict(ms=ms, GBs=by / (ms * 1e-3) / 1e9, bytes=by, TFLOPs=fl / (ms * 1e-3) / 1e12, sched=sc)
+            _log("kernel_bench: %s %.4f ms %.0f GB/s %.1f TFLOP/s" % (key, ms, out[key]["GBs"], out[key]["TFLOPs"]))
+            continue
         if k in ("copy", "dirac64"):
             ms = s.time_kernel("blas" if k == "copy" else "dirac64", reps=reps)
             by = vol * (2 * 24 * 8 if k == "copy" else 192 * 8)
