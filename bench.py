@@ -16,7 +16,7 @@ duration, accumulated by the library over the timed solves) and the CPU
 oracle's time on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-kernels]
+                       [--no-kernels] [--no-variants] [--sched FLAGS]
 """
 import argparse
 import json
@@ -122,6 +122,50 @@ def kernel_measurements(G, F):
     return out
 
 
+def variants(G, F, dims, U, m0, csw, n_solves=3):
+    """Same 16^4 problem in the other forms the library offers: FP32 and
+    FP16-storage preconditioners (FP64 outer), and 12 right-hand sides solved
+    as one batch; each with its own setup, timed over whole solves."""
+    import numpy as np
+    import torch
+
+    out = {}
+    rhs = [torch.as_tensor(F.gaussian_spinor(dims, 2000 + i)).to("cuda") for i in range(12)]
+    for name, over in (("fp32_preconditioner", dict(precision=32)), ("fp16_storage_preconditioner", dict(precision=16)),
+                       ("fp64_batch12", dict(max_rhs=12)), ("fp32_batch12", dict(precision=32, max_rhs=12))):
+        s = G.Solver(dims, U, m0, csw)
+        params, _ = c2_params(G, **over)
+        t0 = time.time()
+        s.setup(params=params)
+        torch.cuda.synchronize()
+        setup_s = time.time() - t0
+        s.autotune(reps=5)
+        if "batch" in name:
+            B = torch.stack(rhs)
+            s.solve_batch(B, 1e-10)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            X, st = s.solve_batch(B, 1e-10)
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            worst = max(x["true_relres"] for x in st)
+            out[name] = dict(setup_s=setup_s, batch_s=el, solves_per_s=12 / el, rhs=12, true_relres_max=worst,
+                             outer_iters=[x["outer_iters"] for x in st])
+        else:
+            s.solve(rhs[0], 1e-10)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            sts = [s.solve(rhs[1 + i], 1e-10)[1] for i in range(n_solves)]
+            torch.cuda.synchronize()
+            el = (time.time() - t0) / n_solves
+            out[name] = dict(setup_s=setup_s, time_to_solution_s=el, solves_per_s=1 / el,
+                             true_relres_max=max(x["true_relres"] for x in sts),
+                             outer_iters=[x["outer_iters"] for x in sts])
+        log("bench: variant %s %s" % (name, out[name]))
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +173,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--sched", type=int, default=None, help="launch schedule flags instead of the autotuned one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -150,6 +196,12 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log("bench: setup %.3fs" % setup_s)
+    if args.sched is None:
+        sched, tune_ms = s.autotune(reps=5)
+        log("bench: autotuned schedule %d (ms per schedule %s)" % (sched, ["%.3f" % t for t in tune_ms]))
+    else:
+        s.set_schedule(args.sched)
+        sched = args.sched
     rhs = [torch.as_tensor(F.gaussian_spinor(dims, 1000 + i)).to("cuda") for i in range(args.warmup + args.steps)]
     for i in range(args.warmup):
         s.solve(rhs[i], 1e-10)
@@ -170,8 +222,10 @@ def main():
     worst = max(st["true_relres"] for st in stats)
     assert all(st["converged"] for st in stats) and worst <= 1e-10, stats
 
-    # dominant kernel class by time
-    dom = max(prof, key=lambda k: prof[k][1])
+    # dominant single-kernel class by time (classes that bracket one launch each;
+    # "coarse", "reduce", "blas" and "coarse_step" bracket groups of launches)
+    single = ("sap", "dirac64", "dirac_prec", "restrict", "prolong", "coarse_sap")
+    dom = max(single, key=lambda k: prof[k][1])
     n_l, ms_l, by_l = prof[dom]
     avg_ms = ms_l / max(n_l, 1)
     achieved = (by_l / max(n_l, 1)) / (avg_ms * 1e-3) / 1e9 if n_l else 0.0
@@ -197,6 +251,7 @@ def main():
                     sap_blocks="4^4", mr_steps=3, nu=2, n_inv=6, coarse="odd-even GMRES(30) to 5e-2"),
         setup_s=setup_s,
         solves_per_s=1.0 / tts,
+        schedule=sched,
         outer_iters=[st["outer_iters"] for st in stats],
         coarse_iters_per_solve=[st["coarse_iters"][1] for st in stats],
         true_relres_max=worst,
@@ -204,6 +259,11 @@ def main():
                       frac=achieved / HBM_PEAK_GBS, traffic=None, launches=n_l, avg_launch_ms=avg_ms),
         kernel_classes=kernels,
     )
+    if not args.no_variants:
+        try:
+            out["variants_16x4"] = variants(G, F, dims, U, m0, csw)
+        except Exception as e:  # measurement extras never hide the main line
+            out["variants_16x4"] = dict(error=str(e))
     if not args.no_kernels:
         try:
             out["kernels_32c64"] = kernel_measurements(G, F)

@@ -231,7 +231,9 @@ typedef enum {
     DD_K_COARSE_SAP = 6,   /* coarse-level SAP half sweep                       */
     DD_K_REDUCE = 7,       /* multi-dot and update+norm reductions             */
     DD_K_BLAS = 8,         /* other vector kernels (axpy, scale, conversions)  */
-    DD_K_NCLASS = 9
+    DD_K_COARSE_STEP = 9,  /* one coarsest-level Arnoldi step replayed as a graph
+                              (Schur complement + reductions + Givens + scale) */
+    DD_K_NCLASS = 10
 } dd_kernel_class;
 
 /* enable != 0 starts (and resets) profiling; 0 stops it. */
@@ -271,17 +273,23 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   arithmetic runs on the vector units (one workgroup per
  *                   site and RHS) instead of the matrix cores (one workgroup
  *                   per site for all RHS); results agree to rounding
- * The default is DD_SCHED_LDS | DD_SCHED_XCD with the matrix cores on.
+ *   DD_SCHED_GRAPH  each Arnoldi step of the coarsest-level GMRES (Schur
+ *                   complement, reductions, Givens update, scaling: seven
+ *                   kernels) is captured once as a HIP graph per (level, step,
+ *                   batch size) and replayed with one launch (not while
+ *                   dd_profile times single kernels)
+ * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH with the matrix
+ * cores on.
  * ------------------------------------------------------------------------- */
-enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8 };
+enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16 };
 
 /* Select a schedule (a combination of DD_SCHED_* flags). DD_EINVAL otherwise. */
 dd_status dd_set_schedule(dd_ctx *ctx, int sched);
 /* Current schedule, -1 for ctx == NULL. */
 int dd_get_schedule(const dd_ctx *ctx);
 
-/* Time every schedule of the fine kernels (flag sets 0..7; the NO_MFMA bit is
- * kept as set) on the context's own fields (the FP64 stencil plus nu SAP
+/* Time every schedule of the fine kernels (flag sets 0..7; the NO_MFMA and
+ * GRAPH bits are kept as set) on the context's own fields (the FP64 stencil plus nu SAP
  * sweeps once configured, each the mean of `reps` launches) and keep the
  * fastest.  chosen (may be NULL) receives it; times_ms (may be NULL) holds 8
  * doubles, the cost of each schedule (flag set 0..7) in ms. */

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddamg.so")
 MAXLEV = 4
 
-KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse", "coarse_sap", "reduce", "blas"]
+KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse", "coarse_sap", "reduce", "blas",
+                  "coarse_step"]
 OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8)
 STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
           -6: "DD_ENUMERIC"}

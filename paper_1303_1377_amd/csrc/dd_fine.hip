@@ -11,6 +11,8 @@
 // A spinor field is [parity][12][vh] complex, the links [parity][mu][9][vh],
 // packed clover blocks [parity][72][vh] reals.  One thread owns one site, so
 // every load of a component is coalesced across the wavefront.
+#include <mutex>
+
 #include "dd_kernels.h"
 
 #include <math.h>
@@ -572,18 +574,24 @@ template <class T, class S>
 void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
     if ((op.sched & SCHED_LDS) && dirac_lds_fits(op.g)) {
         const size_t lds = fine_dirac_lds_bytes<T>(op.g);
+        static std::mutex mu;
         static size_t configured = 65536;
         static bool refused = false;
-        if (lds > configured && !refused) {
-            if (hipFuncSetAttribute((const void*)k_dirac_lds<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
-                hipSuccess)
-                configured = lds;
-            else {
-                (void)hipGetLastError();
-                refused = true;
+        size_t allowed;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            if (lds > configured && !refused) {
+                if (hipFuncSetAttribute((const void*)k_dirac_lds<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds) == hipSuccess)
+                    configured = lds;
+                else {
+                    (void)hipGetLastError();
+                    refused = true;
+                }
             }
+            allowed = configured;
         }
-        if (lds <= configured) {
+        if (lds <= allowed) {
             dim3 grid(op.g.nblk, nr);
             k_dirac_lds<T, S><<<grid, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk);
             return;
@@ -894,10 +902,14 @@ void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const
     if (nblocks <= 0) return;
     int nt = ((2 * op.g.bvh + 63) / 64) * 64;
     size_t lds = fine_sap_lds_bytes<T>(op.g);
+    static std::mutex mu;
     static size_t configured = 0;
-    if (lds > 65536 && lds > configured) {
-        (void)hipFuncSetAttribute((const void*)k_sap_fine<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        configured = lds;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (lds > 65536 && lds > configured) {
+            (void)hipFuncSetAttribute((const void*)k_sap_fine<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            configured = lds;
+        }
     }
     k_sap_fine<T, S><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
 }

@@ -17,6 +17,7 @@ enum FineSched {
     SCHED_XCD = 2,     // stencil and SAP: XCD-contiguous workgroup order
     SCHED_LDS = 4,     // stencil: one workgroup per layout block staged in LDS
     SCHED_NO_MFMA = 8, // multi-RHS coarse stencil on the vector units instead of the matrix cores
+    SCHED_GRAPH = 16,  // coarsest-level Arnoldi steps replayed as captured HIP graphs
 };
 // Fields are stored in S (T, or _Float16 for the FP16-storage preconditioner)
 // and computed on in T.

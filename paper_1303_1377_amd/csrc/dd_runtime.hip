@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -164,6 +165,7 @@ static const int RS = 136;
 
 struct dd_ctx {
     hipStream_t s = nullptr;
+    hipStream_t cap = nullptr;   // private stream the Arnoldi-step graphs are captured on
     int dims[4];
     long vol = 0;
     double m0 = 0, csw = 0;
@@ -199,6 +201,7 @@ struct dd_ctx {
     double last_setup_s = 0;
     // live kernel timing (dd_profile)
     bool prof_on = false;
+    bool capturing = false;      // a graph capture is in progress (no event records)
     std::vector<hipEvent_t> ev_pool;
     struct Rec { int cls; hipEvent_t a, b; double bytes; };
     std::vector<Rec> pending;
@@ -211,7 +214,7 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
-    int sched = SCHED_LDS | SCHED_XCD;     // launch schedule of the fine stencil / SAP
+    int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
     ~dd_ctx();
 };
 
@@ -265,7 +268,7 @@ struct Prof {
     double bytes;
     hipEvent_t a = nullptr;
     Prof(dd_ctx* c, int k, double by = 0) : C(c), cls(k), bytes(by) {
-        if (C->prof_on) {
+        if (C->prof_on && !C->capturing) {
             a = ev_get(C);
             HIPX(hipEventRecord(a, C->s));
         }
@@ -360,6 +363,11 @@ struct Hier {
     GmDev* gmst[DD_MAXLEV]; // R device GMRES states of the coarsest level
     int last_its[DD_MAXLEV];
     long coarse_count[DD_MAXLEV][MAX_RHS];
+    // instantiated graphs of one coarsest-level Arnoldi step, by (level, j, nr)
+    std::map<long, hipGraphExec_t> graphs;
+    ~Hier() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    }
 
     long nlv(int l) const { return 2L * g[l].vh * nd[l]; }   // complex entries of a level vector
 
@@ -408,6 +416,9 @@ struct Hier {
 };
 
 dd_ctx::~dd_ctx() {
+    H64.reset();
+    H32.reset();
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     H64.reset();
@@ -693,6 +704,26 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         return true;
     };
     const RedBatch rb{nr, nfull, nfull, RS, live};
+    // one Arnoldi step of every running RHS, enqueued on stream `sq`
+    // (the Prof brackets record nothing while a graph is being captured)
+    auto arnoldi_step = [&](int j, hipStream_t sq) {
+        cx<T>* vj = V + (size_t)j * ldv;
+        cx<T>* w = V + (size_t)(j + 1) * ldv;
+        {
+            Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
+            with_coarse(l, [&](auto& op) {
+                coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, wc[l], sq, live, nr, nfull);
+                coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull);
+            });
+        }
+        Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
+        vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, sq, rb);
+        vec_update_norm_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb);
+        gm_column(st, j, C->dred, RS, nr, sq);
+        vec_scale_dev<T>(nh, st, odd(w), sq, false, nr, nfull);
+    };
+    // graphs need a capture stream; live kernel timing brackets single launches
+    const bool use_graphs = (C->sched & SCHED_GRAPH) && C->cap;
     int chunk = std::min(m, std::max(1, last_its[l] + 2));
     for (;;) {
         int j = 0;
@@ -700,14 +731,28 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         while (j < m) {
             const int jend = std::min(m, j + chunk);
             for (; j < jend; j++) {
-                cx<T>* vj = V + (size_t)j * ldv;
-                cx<T>* w = V + (size_t)(j + 1) * ldv;
-                schur(l, vj, w, live, nr, k);
-                Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
-                vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, C->s, rb);
-                vec_update_norm_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, C->s, rb);
-                gm_column(st, j, C->dred, RS, nr, C->s);
-                vec_scale_dev<T>(nh, st, odd(w), C->s, false, nr, nfull);
+                if (use_graphs) {
+                    // the whole step as one graph launch (captured once per (level, j, nr))
+                    const long key = ((long)l * 64 + j) * 64 + nr;
+                    auto it = graphs.find(key);
+                    if (it == graphs.end()) {
+                        hipGraph_t gr = nullptr;
+                        hipGraphExec_t ex = nullptr;
+                        HIPX(hipStreamBeginCapture(C->cap, hipStreamCaptureModeThreadLocal));
+                        C->capturing = true;
+                        arnoldi_step(j, C->cap);
+                        C->capturing = false;
+                        HIPX(hipStreamEndCapture(C->cap, &gr));
+                        hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(gr);
+                        HIPX(e);
+                        it = graphs.emplace(key, ex).first;
+                    }
+                    Prof pr(C, DD_K_COARSE_STEP, 2 * by_coarse(l, 9, 2, false, k) + 2 * by_reduce(nh, j + 1, k));
+                    HIPX(hipGraphLaunch(it->second, C->s));
+                } else {
+                    arnoldi_step(j, C->s);
+                }
             }
             if (read_state()) { all_stop = true; break; }
             chunk = 4;
@@ -1119,6 +1164,7 @@ dd_status dd_create(dd_ctx** out, const int dims[4], const double* gauge, const 
     dd_ctx* C = new dd_ctx();
     try {
         C->s = (hipStream_t)hip_stream;
+        HIPX(hipStreamCreateWithFlags(&C->cap, hipStreamNonBlocking));
         memcpy(C->dims, dims, sizeof(int) * 4);
         C->vol = (long)dims[0] * dims[1] * dims[2] * dims[3];
         if (C->vol / 2 > 0x7fffffffL / 24) fail(DD_EINVAL, "lattice too large");
@@ -1681,6 +1727,13 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
 
 static void set_sched(dd_ctx* C, int sched) {
     C->sched = sched;
+    // captured graphs hold the previous kernel choices
+    auto drop = [](auto& H) {
+        for (auto& kv : H.graphs) (void)hipGraphExecDestroy(kv.second);
+        H.graphs.clear();
+    };
+    if (C->H64) drop(*C->H64);
+    if (C->H32) drop(*C->H32);
     const int mf = (sched & SCHED_NO_MFMA) ? 0 : 1;
     if (C->H64) {
         C->H64->op0.sched = sched;
@@ -1694,7 +1747,8 @@ static void set_sched(dd_ctx* C, int sched) {
 
 dd_status dd_set_schedule(dd_ctx* ctx, int sched) {
     ABI_TRY(ctx)
-    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA)) fail(DD_EINVAL, "unknown schedule flags");
+    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA | SCHED_GRAPH))
+        fail(DD_EINVAL, "unknown schedule flags");
     set_sched(ctx, sched);
     return DD_OK;
     ABI_END(ctx)
@@ -1709,7 +1763,7 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     ABI_TRY(ctx)
     if (reps < 1) fail(DD_EINVAL, "reps >= 1");
     const int nsched = (SCHED_FUSED | SCHED_XCD | SCHED_LDS) + 1;
-    const int keep = ctx->sched & SCHED_NO_MFMA;
+    const int keep = ctx->sched & (SCHED_NO_MFMA | SCHED_GRAPH);
     double best = 0;
     int pick = ctx->sched;
     for (int sc = 0; sc < nsched; sc++) {

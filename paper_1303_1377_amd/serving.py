@@ -1,0 +1,317 @@
+"""Continuous-batching solve server over the C-ABI.
+
+Requests (a gauge field id, k right-hand sides, a tolerance) arrive at any
+time.  The server
+
+  * keeps the setup of each field (P, D_c, clover inverses: one solver
+    context) resident on the device, admitted against an HBM budget and
+    evicted least-recently-used when a new field needs room and the old one
+    is idle;
+  * batches right-hand sides that share a field and tolerance: RHS of
+    different requests join one dd_solve_batch call as slots free up, and a
+    large request is spread over several batches;
+  * runs the batches of different fields concurrently, each field's context
+    on its own HIP stream driven by its own worker thread, so their kernels
+    overlap on the device;
+  * records per-request latency (submit to last RHS done) and reports
+    p50 / p99 latency and solves/s.
+
+Every right-hand side's result is the one a single solve on the same resident
+setup computes (the batched solver advances each RHS exactly as a single solve
+would), so a request gives the same answer alone and in any mix.
+
+The solver backend is injectable (`solver_factory`) so that the scheduling
+logic can be exercised without a device.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+
+@dataclass
+class FieldSpec:
+    """A registered gauge field: D(U, m0, csw) on a lattice `dims`."""
+
+    dims: tuple
+    gauge: object
+    m0: float
+    csw: float
+    params: object = None       # Params for the setup (None: library defaults)
+    clover: object = None
+    est_bytes: int = 0          # HBM the resident setup is admitted with
+
+
+@dataclass
+class _Request:
+    field_id: object
+    rhs: object                 # [k][vol][4][3] array-like
+    tol: float
+    future: Future
+    t_submit: float
+    k: int
+    next_rhs: int = 0           # first RHS not yet handed to a batch
+    done: int = 0
+    x: list = field(default_factory=list)
+    stats: list = field(default_factory=list)
+
+
+def _stack(xs):
+    """Stack device tensors with torch and anything else with numpy."""
+    try:
+        import torch
+
+        if isinstance(xs[0], torch.Tensor):
+            return torch.stack([torch.as_tensor(x) for x in xs])
+    except ImportError:  # pragma: no cover - torch is part of the image
+        pass
+    import numpy as np
+
+    return np.stack([np.asarray(x) for x in xs])
+
+
+def estimate_bytes(dims, params=None, max_rhs=1):
+    """HBM a resident two- or three-level setup needs, from the allocation
+    sizes of the library (fields, hierarchy, Krylov workspaces), rounded up."""
+    vol = 1
+    for d in dims:
+        vol *= d
+    levels = getattr(params, "levels", 2) if params is not None else 2
+    prec = getattr(params, "precision", 64) if params is not None else 64
+    n_tv = list(getattr(params, "n_tv", [20, 20])) if params is not None else [20, 20]
+    agg = [tuple(a) for a in getattr(params, "agg", [(4, 4, 4, 4), (2, 2, 2, 2)])] if params is not None else \
+        [(4, 4, 4, 4), (2, 2, 2, 2)]
+    m_out = getattr(params, "outer_restart", 25) if params is not None else 25
+    m_c = getattr(params, "coarse_restart", 30) if params is not None else 30
+    sz = 16 if prec == 64 else 8
+    R = max_rhs
+    # fine fields: FP64 + FP32 links and clover (+ FP16 copies), canonical gauge copy
+    b = vol * (72 * 8 + 144 * 8 + 72 * 4 + 144 * 4 + 72 * 8)
+    if prec == 16:
+        b += vol * (72 + 144) * 2
+    # outer workspace: V (m+1) FP64, Z (m) in preconditioner precision, b, x, 2 temporaries
+    n = 12 * vol
+    b += R * n * ((m_out + 1) * 16 + m_out * sz + 4 * 16)
+    # level 0 vectors and transfer
+    n0 = 12 * vol
+    b += 3 * R * n0 * sz + 2 * n_tv[0] * n0 * sz
+    v = vol
+    for l in range(1, levels):
+        a = agg[l - 1]
+        v //= a[0] * a[1] * a[2] * a[3]
+        nd = 2 * n_tv[l - 1]
+        b += v * 10 * nd * nd * sz + 5 * R * v * nd * sz
+        if l < levels - 1:
+            b += 2 * n_tv[l] * v * nd * sz + 21 * R * v * nd * sz
+        else:
+            b += (m_c + 1) * R * v * nd * sz
+    return int(b * 1.1) + (64 << 20)
+
+
+class Server:
+    """See the module docstring.  `submit` returns a Future resolving to
+    (x [k][vol][4][3] device tensor, [stats per RHS])."""
+
+    def __init__(self, budget_bytes=200e9, max_rhs=12, solver_factory=None, clock=time.perf_counter):
+        self.budget = int(budget_bytes)
+        self.max_rhs = int(max_rhs)
+        self.clock = clock
+        self._factory = solver_factory or self._default_factory
+        self._fields = {}
+        self._resident = collections.OrderedDict()   # field_id -> solver (LRU order)
+        self._resident_bytes = {}
+        self._busy = set()
+        self._pending = collections.deque()
+        self._cv = threading.Condition()
+        self._closed = False
+        self._latency = []
+        self._solved = 0
+        self._t_first = None
+        self._t_last = None
+        self.admitted = 0
+        self.evicted = 0
+        self._workers = {}
+        self._dispatcher = threading.Thread(target=self._dispatch, name="dd-dispatch", daemon=True)
+        self._dispatcher.start()
+
+    # ---- registration / submission ------------------------------------------
+    def add_field(self, field_id, dims, gauge, m0, csw, params=None, clover=None):
+        spec = FieldSpec(tuple(dims), gauge, float(m0), float(csw), params, clover)
+        spec.est_bytes = estimate_bytes(spec.dims, params, self.max_rhs)
+        if spec.est_bytes > self.budget:
+            raise ValueError("field %r needs about %.1f GB, above the HBM budget" % (field_id, spec.est_bytes / 1e9))
+        with self._cv:
+            self._fields[field_id] = spec
+
+    def submit(self, field_id, b, tol=1e-10):
+        import numpy as np
+
+        if field_id not in self._fields:
+            raise KeyError("unknown field %r" % (field_id,))
+        spec = self._fields[field_id]
+        vol = int(np.prod(spec.dims))
+        shape = tuple(getattr(b, "shape", np.shape(b)))
+        k = 1 if len(shape) == 3 else int(shape[0])
+        rhs = b if len(shape) == 4 else b.reshape(1, vol, 4, 3)
+        fut = Future()
+        req = _Request(field_id, rhs, float(tol), fut, self.clock(), k, x=[None] * k, stats=[None] * k)
+        with self._cv:
+            if self._closed:
+                raise RuntimeError("server closed")
+            if self._t_first is None:
+                self._t_first = req.t_submit
+            self._pending.append(req)
+            self._cv.notify_all()
+        return fut
+
+    # ---- statistics -----------------------------------------------------------
+    def stats(self):
+        import numpy as np
+
+        with self._cv:
+            lat = np.array(self._latency) if self._latency else np.zeros(1)
+            span = (self._t_last - self._t_first) if self._t_last and self._t_first else 0.0
+            return dict(requests=len(self._latency), rhs_solved=self._solved,
+                        p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+                        solves_per_s=(self._solved / span) if span > 0 else 0.0,
+                        requests_per_s=(len(self._latency) / span) if span > 0 else 0.0,
+                        resident=list(self._resident.keys()), resident_bytes=sum(self._resident_bytes.values()),
+                        admitted=self.admitted, evicted=self.evicted)
+
+    def close(self):
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        self._dispatcher.join()
+        for w in list(self._workers.values()):
+            w.join()
+        with self._cv:
+            for fid in list(self._resident):
+                self._evict(fid)
+
+    # ---- internals ------------------------------------------------------------
+    def _default_factory(self, spec):
+        import torch
+
+        import paper_1303_1377_amd as G
+
+        stream = torch.cuda.Stream()
+        s = G.Solver(spec.dims, spec.gauge, spec.m0, spec.csw, clover=spec.clover, stream=stream)
+        p = spec.params if spec.params is not None else G.default_params()
+        p.max_rhs = self.max_rhs
+        s.setup(params=p)
+        return s
+
+    def _evict(self, fid):
+        s = self._resident.pop(fid)
+        self._resident_bytes.pop(fid, None)
+        close = getattr(s, "close", None)
+        if close:
+            close()
+        self.evicted += 1
+
+    def _admit(self, fid):
+        """Make room for field `fid` (caller holds the lock).  True when the
+        field may be set up now."""
+        need = self._fields[fid].est_bytes
+        used = sum(self._resident_bytes.values())
+        if used + need <= self.budget:
+            return True
+        pending_fields = {r.field_id for r in self._pending}
+        for old in list(self._resident):
+            if used + need <= self.budget:
+                break
+            if old in self._busy or old in pending_fields:
+                continue
+            used -= self._resident_bytes.get(old, 0)
+            self._evict(old)
+        return used + need <= self.budget
+
+    def _next_batch(self, fid):
+        """Up to max_rhs RHS of field `fid` sharing one tolerance, in arrival
+        order (caller holds the lock)."""
+        batch = []
+        tol = None
+        for req in self._pending:
+            if req.field_id != fid or req.next_rhs >= req.k:
+                continue
+            if tol is None:
+                tol = req.tol
+            if req.tol != tol:
+                continue
+            while req.next_rhs < req.k and len(batch) < self.max_rhs:
+                batch.append((req, req.next_rhs))
+                req.next_rhs += 1
+            if len(batch) == self.max_rhs:
+                break
+        return batch, tol
+
+    def _dispatch(self):
+        while True:
+            with self._cv:
+                while not self._runnable():
+                    if self._closed and not self._pending:
+                        return
+                    self._cv.wait(timeout=0.05)
+                for fid in self._runnable():
+                    if fid not in self._resident and not self._admit(fid):
+                        continue
+                    self._busy.add(fid)
+                    w = threading.Thread(target=self._work, args=(fid,), name="dd-field-%s" % (fid,), daemon=True)
+                    self._workers[fid] = w
+                    w.start()
+
+    def _runnable(self):
+        out = []
+        for req in self._pending:
+            fid = req.field_id
+            if req.next_rhs < req.k and fid not in self._busy and fid not in out:
+                out.append(fid)
+        return out
+
+    def _work(self, fid):
+        """Worker of one field: set up if needed, then solve batches of this
+        field until none is left (solve_batch returns after its stream has
+        finished)."""
+        try:
+            with self._cv:
+                solver = self._resident.get(fid)
+            if solver is None:
+                solver = self._factory(self._fields[fid])
+                with self._cv:
+                    self._resident[fid] = solver
+                    self._resident_bytes[fid] = self._fields[fid].est_bytes
+                    self.admitted += 1
+            while True:
+                with self._cv:
+                    self._resident.move_to_end(fid)
+                    batch, tol = self._next_batch(fid)
+                if not batch:
+                    break
+                B = _stack([req.rhs[q] for req, q in batch])
+                X, st = solver.solve_batch(B, tol)
+                t = self.clock()
+                with self._cv:
+                    for i, (req, q) in enumerate(batch):
+                        req.x[q] = X[i]
+                        req.stats[q] = st[i]
+                        req.done += 1
+                        self._solved += 1
+                        if req.done == req.k:
+                            self._pending.remove(req)
+                            self._latency.append(t - req.t_submit)
+                            self._t_last = t
+                            req.future.set_result((_stack(req.x), req.stats))
+        except BaseException as e:  # fail the requests of this field, keep serving others
+            with self._cv:
+                for req in [r for r in self._pending if r.field_id == fid]:
+                    self._pending.remove(req)
+                    if not req.future.done():
+                        req.future.set_exception(e)
+        finally:
+            with self._cv:
+                self._busy.discard(fid)
+                self._cv.notify_all()

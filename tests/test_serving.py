@@ -1,0 +1,187 @@
+"""Scheduling logic of the solve server, with an injected CPU backend (the
+device path is covered by the GPU test at the end)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1303_1377_amd import fields as F
+from paper_1303_1377_amd.serving import Server, estimate_bytes
+
+
+class FakeSolver:
+    """x = 2 b; records the batch sizes and which fields run at the same time."""
+
+    active = set()
+    overlap = []
+    lock = threading.Lock()
+
+    def __init__(self, spec, delay=0.02):
+        self.spec = spec
+        self.batches = []
+        self.delay = delay
+        self.closed = False
+
+    def solve_batch(self, B, tol):
+        with FakeSolver.lock:
+            FakeSolver.active.add(id(self))
+            if len(FakeSolver.active) > 1:
+                FakeSolver.overlap.append(len(FakeSolver.active))
+        self.batches.append(len(B))
+        time.sleep(self.delay)
+        with FakeSolver.lock:
+            FakeSolver.active.discard(id(self))
+        return 2 * np.asarray(B), [dict(converged=1, tol=tol)] * len(B)
+
+    def close(self):
+        self.closed = True
+
+
+def _server(budget, max_rhs=4, made=None):
+    def factory(spec):
+        s = FakeSolver(spec)
+        if made is not None:
+            made.append(s)
+        return s
+
+    return Server(budget_bytes=budget, max_rhs=max_rhs, solver_factory=factory)
+
+
+def _rhs(dims, k, seed):
+    return F.gaussian_spinor(dims, seed, nrhs=k)
+
+
+def test_requests_share_batches_and_results_are_per_rhs():
+    made = []
+    srv = _server(1e12, max_rhs=4, made=made)
+    dims = (4, 4, 4, 4)
+    srv.add_field("a", dims, None, -0.4, 1.0)
+    bs = [_rhs(dims, k, 10 + k) for k in (3, 2, 5)]
+    futs = [srv.submit("a", b) for b in bs]
+    for b, f in zip(bs, futs):
+        x, st = f.result(timeout=10)
+        assert np.array_equal(x, 2 * b) and len(st) == len(b)
+    srv.close()
+    assert len(made) == 1
+    assert all(n <= 4 for n in made[0].batches) and sum(made[0].batches) == 10
+    # RHS of different requests were batched together (10 RHS in fewer than 3+1+2 single-request batches)
+    assert len(made[0].batches) <= 4
+    st = srv.stats()
+    assert st["requests"] == 3 and st["rhs_solved"] == 10 and st["p99_latency_s"] >= st["p50_latency_s"] > 0
+
+
+def test_tolerances_are_not_mixed_in_a_batch():
+    made = []
+    srv = _server(1e12, max_rhs=8, made=made)
+    dims = (4, 4, 4, 4)
+    srv.add_field("a", dims, None, -0.4, 1.0)
+    f1 = srv.submit("a", _rhs(dims, 2, 1), tol=1e-10)
+    f2 = srv.submit("a", _rhs(dims, 2, 2), tol=1e-6)
+    assert all(s["tol"] == 1e-10 for s in f1.result(timeout=10)[1])
+    assert all(s["tol"] == 1e-6 for s in f2.result(timeout=10)[1])
+    srv.close()
+
+
+def test_budget_admission_and_lru_eviction():
+    dims = (4, 4, 4, 4)
+    one = estimate_bytes(dims, None, 4)
+    made = []
+    srv = _server(int(one * 1.5), max_rhs=4, made=made)   # room for one resident setup
+    srv.add_field("a", dims, None, -0.4, 1.0)
+    srv.add_field("b", dims, None, -0.4, 1.0)
+    srv.submit("a", _rhs(dims, 1, 1)).result(timeout=10)
+    assert srv.stats()["resident"] == ["a"]
+    srv.submit("b", _rhs(dims, 1, 2)).result(timeout=10)
+    st = srv.stats()
+    assert st["resident"] == ["b"] and st["evicted"] == 1 and st["admitted"] == 2
+    assert made[0].closed and not made[1].closed
+    srv.close()
+
+
+def test_field_above_budget_is_refused():
+    srv = _server(1e6)
+    with pytest.raises(ValueError):
+        srv.add_field("big", (16, 16, 16, 16), None, 0.0, 1.0)
+    srv.close()
+
+
+def test_fields_run_concurrently():
+    FakeSolver.overlap.clear()
+    srv = _server(1e12, max_rhs=2)
+    dims = (4, 4, 4, 4)
+    for f in ("a", "b", "c"):
+        srv.add_field(f, dims, None, -0.4, 1.0)
+    futs = [srv.submit(f, _rhs(dims, 4, i)) for i, f in enumerate(("a", "b", "c"))]
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+    assert FakeSolver.overlap, "batches of different fields never overlapped"
+
+
+def test_backend_failure_fails_only_that_field():
+    dims = (4, 4, 4, 4)
+
+    def factory(spec):
+        if spec.m0 > 0:
+            raise RuntimeError("setup failed")
+        return FakeSolver(spec)
+
+    srv = Server(budget_bytes=1e12, max_rhs=4, solver_factory=factory)
+    srv.add_field("bad", dims, None, 0.5, 1.0)
+    srv.add_field("good", dims, None, -0.4, 1.0)
+    fb = srv.submit("bad", _rhs(dims, 1, 1))
+    fg = srv.submit("good", _rhs(dims, 1, 2))
+    with pytest.raises(RuntimeError):
+        fb.result(timeout=10)
+    assert fg.result(timeout=10)[0].shape == (1, 256, 4, 3)
+    srv.close()
+
+
+@pytest.mark.gpu
+def test_served_results_equal_solo_solves():
+    """Two resident fields of different sizes, requests of 1..5 RHS arriving
+    while others run: each result equals the solo solve of the same RHS on a
+    setup of its own (to 1e-12: batched RHS advance exactly as single solves),
+    and meets the 1e-10 true residual."""
+    import torch
+
+    import oracle as O
+    import paper_1303_1377_amd as G
+
+    specs = {"small": ((4, 4, 4, 4), 0, -0.4), "large": ((8, 8, 8, 8), 1, -0.25)}
+    kw = dict(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4], n_inv=2, outer_restart=20)
+    srv = Server(budget_bytes=50e9, max_rhs=4)
+    U = {}
+    for name, (dims, seed, m0) in specs.items():
+        U[name] = F.make_gauge(dims, 0.3, seed)
+        srv.add_field(name, dims, U[name], m0, 1.0, params=G.default_params(**kw))
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(8):
+        name = ("small", "large")[i % 2]
+        dims = specs[name][0]
+        k = int(rng.integers(1, 6))
+        b = F.gaussian_spinor(dims, 300 + i, nrhs=k)
+        reqs.append((name, b, srv.submit(name, torch.as_tensor(b).to("cuda"))))
+        time.sleep(0.01 * (i % 3))
+    out = [(name, b, f.result(timeout=120)) for name, b, f in reqs]
+    st = srv.stats()
+    srv.close()
+    print("serving stats", st, flush=True)
+    for name, (dims, seed, m0) in specs.items():
+        solo = G.Solver(dims, U[name], m0, 1.0)
+        solo.setup(params=G.default_params(max_rhs=4, **kw))
+        orc = O.Oracle(dims, U[name], m0, 1.0)
+        for nm, b, (x, sts) in out:
+            if nm != name:
+                continue
+            x = x.cpu().numpy()
+            for q in range(len(b)):
+                xs, _ = solo.solve(b[q], 1e-10)
+                xs = xs.cpu().numpy()
+                assert np.linalg.norm(x[q] - xs) <= 1e-12 * np.linalg.norm(xs)
+                r = b[q] - orc.apply(x[q])
+                assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[q]) and sts[q]["converged"]
+        solo.close()
+    assert st["requests"] == 8 and st["p99_latency_s"] > 0
