@@ -360,6 +360,7 @@ struct Hier {
     cx<T>* wc[DD_MAXLEV];
     cx<T>* kV[DD_MAXLEV];   // Krylov bases (coarsest GMRES, middle FGMRES)
     cx<T>* kZ[DD_MAXLEV];   // middle FGMRES preconditioned vectors
+    int kv_cap[DD_MAXLEV];  // basis vectors kV[l] holds per RHS
     GmDev* gmst[DD_MAXLEV]; // R device GMRES states of the coarsest level
     int last_its[DD_MAXLEV];
     long coarse_count[DD_MAXLEV][MAX_RHS];
@@ -394,6 +395,7 @@ struct Hier {
         memset(Minv, 0, sizeof Minv);
         memset(coarse_count, 0, sizeof coarse_count);
         memset(gmst, 0, sizeof gmst);
+        memset(kv_cap, 0, sizeof kv_cap);
         memset(Ph, 0, sizeof Ph);
         memset(Mh, 0, sizeof Mh);
         memset(Minvh, 0, sizeof Minvh);
@@ -580,11 +582,14 @@ void Hier<T>::build_geometry() {
         }
     }
     for (int l = 0; l + 1 < nlev; l++) amap[l].c = g[l + 1];
-    // Krylov workspaces
+    // Krylov workspaces.  A middle level runs FGMRES(mid_restart) in solves,
+    // but during the setup of the level above it is the coarsest level of
+    // the V-cycle and runs GMRES(coarse_restart): its basis holds the larger.
     for (int l = 1; l < nlev; l++) {
-        int m = (l == nlev - 1) ? C->p.coarse_restart : C->p.mid_restart;
-        kV[l] = A.get<cx<T>>((size_t)(m + 1) * R * nlv(l));
-        kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)m * R * nlv(l)) : nullptr;
+        const int mv = (l == nlev - 1) ? C->p.coarse_restart : std::max(C->p.mid_restart, C->p.coarse_restart);
+        kV[l] = A.get<cx<T>>((size_t)(mv + 1) * R * nlv(l));
+        kv_cap[l] = mv + 1;
+        kZ[l] = (l < nlev - 1) ? A.get<cx<T>>((size_t)C->p.mid_restart * R * nlv(l)) : nullptr;
         gmst[l] = A.get<GmDev>(R);
     }
     HIPX(hipStreamSynchronize(C->s));
@@ -671,6 +676,7 @@ template <class T>
 void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     const dd_params& p = C->p;
     const int m = p.coarse_restart, nr = bt.nr, k = bt.count();
+    if (m + 1 > kv_cap[l] || !gmst[l] || nr > R) fail(DD_EINVAL, "GMRES workspace of level " + std::to_string(l) + " too small");
     const long nfull = nlv(l), nh = (long)g[l].vh * nd[l];
     const long ldv = (long)R * nfull;   // basis stride
     cx<T>* V = kV[l];
@@ -928,6 +934,8 @@ template <class T>
 void Hier<T>::fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e, const Batch& bt) {
     const dd_params& p = C->p;
     const long n = nlv(l);
+    if (p.mid_restart + 1 > kv_cap[l] || !kZ[l] || bt.nr > R)
+        fail(DD_EINVAL, "FGMRES workspace of level " + std::to_string(l) + " too small");
     HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * n * bt.nr, C->s));
     std::vector<double> bn = norms(n, r, n, bt);
     HIPX(hipMemcpyAsync(kV[l], r, sizeof(cx<T>) * n * bt.nr, hipMemcpyDeviceToDevice, C->s));

@@ -510,3 +510,23 @@ def test_graph_replay_matches_eager():
             assert np.array_equal(to_np(x), eager[q]), (rep, q)
         xb = to_np(p.g.solve_batch(np.stack(B), 1e-10)[0])
         assert np.array_equal(xb, eager_b), rep
+
+
+def test_three_level_setup_long_coarse_solve():
+    """Regression: during the setup of level 0 the middle level is the
+    coarsest level of the V-cycle and runs GMRES(coarse_restart); with a
+    tight coarse tolerance it takes more steps than the middle FGMRES(2)
+    basis would hold.  Setup and solve complete and converge."""
+    say("case: three-level setup with a long level-1 coarse solve")
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=5, m0=-0.2, csw=1.0)
+    p.g.setup(params=G.default_params(
+        levels=3, n_tv=[8, 8], agg=[(2, 2, 2, 2), (2, 2, 2, 2)], sap=[(2, 2, 2, 2), (2, 2, 2, 2)], n_inv=2,
+        mid_restart=2, coarse_tol=1e-4, coarse_restart=30, outer_restart=20))
+    b = F.gaussian_spinor(dims, 8)
+    x, st = p.g.solve(b, 1e-10)
+    r = b - p.o.apply(to_np(x))
+    say("stats", st)
+    assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
