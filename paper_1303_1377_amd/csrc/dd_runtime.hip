@@ -97,15 +97,16 @@ static Geom make_geom(const int d[4], const int b[4]) {
     return g;
 }
 
-// layout/SAP block validity: powers of two, dividing, 2-colourable block grid
-static bool valid_layout(const int d[4], const int b[4], bool need_b3_even) {
+// layout block validity: powers of two >= 2 dividing the extents; blocks
+// that carry SAP must also form a 2-colourable grid (an even count, or one
+// block, per dimension).  The coarsest level has no SAP, so any count is fine.
+static bool valid_layout(const int d[4], const int b[4], bool need_colouring) {
     for (int mu = 0; mu < 4; mu++) {
         if (!is_pow2(b[mu]) || d[mu] % b[mu]) return false;
         int n = d[mu] / b[mu];
-        if (n != 1 && (n & 1)) return false;
+        if (need_colouring && n != 1 && (n & 1)) return false;
         if (b[mu] < 2) return false;
     }
-    (void)need_b3_even;
     return true;
 }
 
@@ -524,7 +525,7 @@ void Hier<T>::build_geometry() {
             int b[4];
             bool has_sap = (l < nlev - 1);
             for (int mu = 0; mu < 4; mu++) b[mu] = has_sap ? p.sap[l][mu] : 2;
-            if (!valid_layout(d, b, false))
+            if (!valid_layout(d, b, has_sap))
                 fail(DD_EINVAL, "level " + std::to_string(l) + ": lattice/blocks not supported (coarse extents must be even, "
                                 "SAP blocks powers of two with an even block count per dimension)");
             g[l] = make_geom(d, b);

@@ -530,3 +530,22 @@ def test_three_level_setup_long_coarse_solve():
     r = b - p.o.apply(to_np(x))
     say("stats", st)
     assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
+def test_coarsest_level_with_odd_block_count():
+    """A coarsest lattice whose extent/2 is odd (6 x 2^3 from 24 x 8^3 with
+    4^4 aggregates): no SAP runs there, so no colouring is needed; D_c
+    matches the oracle and the solve converges."""
+    say("case: coarsest level 6x2x2x2")
+    import paper_1303_1377_amd as G
+
+    dims = (24, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=2, m0=-0.25, csw=1.0)
+    _built(p, 6, (4, 4, 4, 4), (4, 4, 4, 4))
+    assert rel(to_np(p.g.get_coarse(1)[0]), p.o.get_coarse(1)[0]) < 1e-12
+    p.g.setup(params=G.default_params(levels=2, n_tv=[8], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], n_inv=2,
+                                      outer_restart=20))
+    b = F.gaussian_spinor(dims, 3)
+    x, st = p.g.solve(b, 1e-10)
+    r = b - p.o.apply(to_np(x))
+    assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
