@@ -34,6 +34,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest(path):
+    import hashlib
+
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counter_traffic(kernel_class):
+    """HBM bytes per launch of the kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record of this workload, scaled by the plain-copy
+    factors stored with it; None when no record exists or the kernel's source
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters_16x4_fp64_solve.json")
+    if not os.path.exists(path):
+        return None, "no counter record"
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel_class)
+    if not k:
+        return None, "no counters for this kernel"
+    if kernel_source_digest(k["source"]) != k["source_sha256"]:
+        return None, "kernel changed since the counters were taken"
+    by = (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
+    return by, "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, mean over %d dispatches" % k["dispatches"]
+
+
 def load_mcrit(name):
     with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
         return json.load(f)[name]
@@ -229,6 +255,7 @@ def main():
     n_l, ms_l, by_l = prof[dom]
     avg_ms = ms_l / max(n_l, 1)
     achieved = (by_l / max(n_l, 1)) / (avg_ms * 1e-3) / 1e9 if n_l else 0.0
+    traffic, traffic_src = counter_traffic(dom)
     kernels = {k: dict(launches=v[0], total_ms=round(v[1], 3),
                        GBs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None) for k, v in prof.items()}
 
@@ -256,7 +283,8 @@ def main():
         coarse_iters_per_solve=[st["coarse_iters"][1] for st in stats],
         true_relres_max=worst,
         roofline=dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None, launches=n_l, avg_launch_ms=avg_ms),
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_source=traffic_src,
+                      algorithmic_bytes_per_launch=(by_l / max(n_l, 1)), launches=n_l, avg_launch_ms=avg_ms),
         kernel_classes=kernels,
     )
     if not args.no_variants:
