@@ -12,7 +12,8 @@ kernel trace and the memory counters of exactly these launches.
 
 Byte model per lattice site (reals of the storage precision):
   stencil   192 = links 72 + clover 72 + spinor in 24 + spinor out 24
-  SAP sweep 432 = 2 half sweeps x (links 72 + clover 72 + b 24 + z 24 + z 24) / 2
+  SAP sweep 216 = links 72 + clover 72 + b 24 + z read 24 + z write 24 (each
+            site is solved once per sweep, in the half sweep of its colour)
   copy      one FP64 spinor read and written: 2 x 24 reals of 8 bytes
   coarse    per coarse site: 9 blocks of nd x nd complex (storage precision)
             + k input and k output vectors of nd complex FP32; flops 9 nd^2 k x 8
@@ -82,7 +83,7 @@ def run(dims=(64, 32, 32, 32), kernels=("copy", "dirac64", "dirac32", "sap32", "
                 by = vol * 192 * sz
             else:
                 ms = s.time_kernel("sap", reps=reps)
-                by = vol * 432 * sz
+                by = vol * 216 * sz
         key = k if sc is None or len(scheds) == 1 else "%s_sched%d" % (k, sc)
         out[key] = dict(ms=ms, GBs=by / (ms * 1e-3) / 1e9, bytes=by, sched=sc)
         _log("kernel_bench: %s %.4f ms %.0f GB/s" % (key, ms, out[key]["GBs"]))
