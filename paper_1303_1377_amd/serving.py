@@ -113,10 +113,15 @@ def estimate_bytes(dims, params=None, max_rhs=1):
 
 class Server:
     """See the module docstring.  `submit` returns a Future resolving to
-    (x [k][vol][4][3] device tensor, [stats per RHS])."""
+    (x [k][vol][4][3], [stats per RHS]); x is a device tensor, or a host
+    tensor with results_on_host.  Right-hand sides may be host arrays: they
+    stay on the host while queued and are copied to the device per batch, so
+    queued requests hold no device memory."""
 
-    def __init__(self, budget_bytes=200e9, max_rhs=12, solver_factory=None, clock=time.perf_counter):
+    def __init__(self, budget_bytes=200e9, max_rhs=12, solver_factory=None, clock=time.perf_counter,
+                 results_on_host=False):
         self.budget = int(budget_bytes)
+        self.results_on_host = bool(results_on_host)
         self.max_rhs = int(max_rhs)
         self.clock = clock
         self._factory = solver_factory or self._default_factory
@@ -281,9 +286,12 @@ class Server:
                 solver = self._resident.get(fid)
             if solver is None:
                 solver = self._factory(self._fields[fid])
+                # account what the setup really holds once it is known
+                used = getattr(solver, "device_bytes", None)
+                held = max(self._fields[fid].est_bytes, int(used()) if callable(used) else 0)
                 with self._cv:
                     self._resident[fid] = solver
-                    self._resident_bytes[fid] = self._fields[fid].est_bytes
+                    self._resident_bytes[fid] = held
                     self.admitted += 1
             while True:
                 with self._cv:
@@ -296,7 +304,7 @@ class Server:
                 t = self.clock()
                 with self._cv:
                     for i, (req, q) in enumerate(batch):
-                        req.x[q] = X[i]
+                        req.x[q] = X[i].cpu() if (self.results_on_host and hasattr(X[i], "cpu")) else X[i]
                         req.stats[q] = st[i]
                         req.done += 1
                         self._solved += 1
@@ -304,7 +312,9 @@ class Server:
                             self._pending.remove(req)
                             self._latency.append(t - req.t_submit)
                             self._t_last = t
-                            req.future.set_result((_stack(req.x), req.stats))
+                            x, req.x = _stack(req.x), None
+                            req.rhs = None
+                            req.future.set_result((x, req.stats))
         except BaseException as e:  # fail the requests of this field, keep serving others
             with self._cv:
                 for req in [r for r in self._pending if r.field_id == fid]:
