@@ -278,18 +278,24 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   kernels) is captured once as a HIP graph per (level, step,
  *                   batch size) and replayed with one launch (not while
  *                   dd_profile times single kernels)
- * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH with the matrix
- * cores on.
+ *   DD_SCHED_COOP   each restart cycle of the coarsest-level GMRES runs as one
+ *                   persistent cooperative launch (workgroups meet at grid
+ *                   barriers between the phases of an Arnoldi step); falls
+ *                   back to DD_SCHED_GRAPH / single launches when the device
+ *                   does not admit the grid.  Results agree to rounding.
+ * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH | DD_SCHED_COOP
+ * with the matrix cores on.
  * ------------------------------------------------------------------------- */
-enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16 };
+enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16,
+       DD_SCHED_COOP = 32 };
 
 /* Select a schedule (a combination of DD_SCHED_* flags). DD_EINVAL otherwise. */
 dd_status dd_set_schedule(dd_ctx *ctx, int sched);
 /* Current schedule, -1 for ctx == NULL. */
 int dd_get_schedule(const dd_ctx *ctx);
 
-/* Time every schedule of the fine kernels (flag sets 0..7; the NO_MFMA and
- * GRAPH bits are kept as set) on the context's own fields (the FP64 stencil plus nu SAP
+/* Time every schedule of the fine kernels (flag sets 0..7; the NO_MFMA, GRAPH
+ * and COOP bits are kept as set) on the context's own fields (the FP64 stencil plus nu SAP
  * sweeps once configured, each the mean of `reps` launches) and keep the
  * fastest.  chosen (may be NULL) receives it; times_ms (may be NULL) holds 8
  * doubles, the cost of each schedule (flag set 0..7) in ms. */

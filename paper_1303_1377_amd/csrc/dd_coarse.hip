@@ -348,6 +348,322 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
 }
 
 // ---------------------------------------------------------------------------
+// Persistent coarsest-level GMRES cycle (one cooperative launch).
+//
+// On small coarse lattices every Arnoldi step of the odd-even GMRES is a
+// handful of tiny launches whose latency dominates.  This kernel runs all the
+// steps of one restart cycle, for every RHS of the batch, inside one launch of
+// G co-resident workgroups that meet at grid barriers:
+//   A  t_e = A_ee^{-1} D_eo v_j          (even sites, spread over workgroups)
+//   B  w   = A_oo v_j - D_oe t_e          (odd sites)
+//   C  partial inner products V_i^H w    (odd entries cut into G chunks)
+//   D  h = sum of the partials (fixed order, in every workgroup), w -= V h,
+//      partial ||w||^2
+//   E  ||w||, Givens update of the Hessenberg column (identical arithmetic
+//      in every workgroup; workgroup 0 writes the GmDev state), w /= ||w||
+// Each step is five barriers; the stop test is the device GMRES's own.  The
+// barrier is a counter/generation pair updated with device-scope atomics; a
+// wait that exceeds its spin limit raises `abort` and every workgroup leaves,
+// so the kernel always drains.
+// ---------------------------------------------------------------------------
+static constexpr int COOP_NT = 256;
+static constexpr int COOP_MAXR = 16;
+
+__device__ __forceinline__ bool coop_barrier(unsigned* bar, int* abort_flag, unsigned nblk) {
+    __syncthreads();
+    __shared__ int ok_s;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const unsigned g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblk - 1) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bar + 1, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+                if (++spins > (1L << 24)) {   // about a second: give up rather than hang
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        __threadfence();
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+// out(site) = [post Minv] ( self(x) in1 + hop_sign sum_k M_k in2(x_k) ) for one
+// site with the workgroup's 4 wavefronts (lane r owns row r; nd <= 64)
+template <class T, class S>
+__device__ __forceinline__ void coop_site_apply(const CoarseOp<T, S>& op, int p, int i, int self_mode,
+                                                const cx<T>* in1, int hop_sign, const cx<T>* in2, bool post_inv,
+                                                cx<T>* out, cx<T> (*part)[64], cx<T>* buf, const cx<S>** mat,
+                                                const cx<T>** vin) {
+    const Geom& g = op.g;
+    const int nd = op.nd;
+    const int t = threadIdx.x, w = t >> 6, r = t & 63;
+    const size_t gs = (size_t)p * g.vh + i;
+    const size_t nn = (size_t)nd * nd;
+    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    const int ns = nself + (hop_sign != 0 ? 8 : 0);
+    if (t < ns) {
+        if (t < nself) {
+            mat[0] = (self_mode == CS_SELF) ? op.M + gs * 9 * nn : op.Minv + gs * nn;
+            vin[0] = in1 + gs * nd;
+        } else {
+            const int k = t - nself;
+            int x[4], y[4];
+            cb_coords(g, p, i, x);
+            nb_coords(g, x, k, y);
+            mat[t] = op.M + (gs * 9 + 1 + k) * nn;
+            vin[t] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
+        }
+    }
+    __syncthreads();
+    const int Q = ns * nd, per = (Q + 3) / 4;
+    const int q0 = w * per, q1 = min(Q, q0 + per);
+    cx<T> acc = czero<T>();
+    if (r < nd) {
+        int q = q0;
+        while (q < q1) {
+            const int sl = q / nd, c0 = q - sl * nd, c1 = min(nd, c0 + (q1 - q));
+            const cx<S>* A = mat[sl] + r;
+            const cx<T>* v = vin[sl];
+            cx<T> a2 = czero<T>();
+            for (int c = c0; c < c1; c++) a2 += ccast<T>(A[(size_t)c * nd]) * v[c];
+            if (sl >= nself && hop_sign < 0) acc -= a2;
+            else acc += a2;
+            q += c1 - c0;
+        }
+    }
+    part[w][r] = acc;
+    __syncthreads();
+    cx<T> tot = czero<T>();
+    if (w == 0 && r < nd) {
+        tot = (self_mode == CS_IDENT) ? in1[gs * nd + r] : czero<T>();
+        for (int q = 0; q < 4; q++) tot += part[q][r];
+    }
+    if (!post_inv) {
+        if (w == 0 && r < nd) out[gs * nd + r] = tot;
+        __syncthreads();
+        return;
+    }
+    if (w == 0) buf[r] = tot;
+    __syncthreads();
+    const int per2 = (nd + 3) / 4, c0 = w * per2, c1 = min(nd, c0 + per2);
+    cx<T> a3 = czero<T>();
+    if (r < nd) {
+        const cx<S>* A = op.Minv + gs * nn + r;
+        for (int c = c0; c < c1; c++) a3 += ccast<T>(A[(size_t)c * nd]) * buf[c];
+    }
+    part[w][r] = a3;
+    __syncthreads();
+    if (w == 0 && r < nd) {
+        cx<T> s2 = czero<T>();
+        for (int q = 0; q < 4; q++) s2 += part[q][r];
+        out[gs * nd + r] = s2;
+    }
+    __syncthreads();
+}
+
+// sum of v over the workgroup (COOP_NT threads), returned to every thread
+__device__ __forceinline__ double coop_sum(double v, double* sh) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    for (int q = 0; q < COOP_NT / 64; q++) s += sh[q];
+    return s;
+}
+
+__device__ __forceinline__ cx<double> cdivd(cx<double> a, cx<double> b) {
+    double d = norm2(b);
+    return cx<double>{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+template <class T, class S>
+__global__ void __launch_bounds__(COOP_NT) k_gmres_coop(CoarseOp<T, S> op, cx<T>* __restrict__ V, long ldv, long nfull,
+                                                        cx<T>* tmp, GmDev* st, int nr, int m, cx<double>* part,
+                                                        unsigned* bar, int* abort_flag) {
+    __shared__ cx<T> ap_part[4][64];
+    __shared__ cx<T> ap_buf[64];
+    __shared__ const cx<S>* ap_mat[9];
+    __shared__ const cx<T>* ap_vin[9];
+    __shared__ double sh[COOP_NT / 64];
+    __shared__ cx<double> cs_s[COOP_MAXR][32], sn_s[COOP_MAXR][32], g_s[COOP_MAXR][33], h_s[COOP_MAXR][33];
+    __shared__ cx<double> col_s[COOP_MAXR][34];
+    __shared__ int stop_s[COOP_MAXR], its_s[COOP_MAXR], fixed_s[COOP_MAXR], maxit_s[COOP_MAXR];
+    __shared__ double tol_s[COOP_MAXR], hn_s[COOP_MAXR];
+    const unsigned G = gridDim.x;
+    const int wg = blockIdx.x, t = threadIdx.x;
+    const int vh = op.g.vh;
+    const long nh = (long)vh * op.nd;
+    // private copy of the rotation state (every workgroup updates it identically)
+    int j0 = 0;
+    for (int r = 0; r < nr; r++) {
+        const GmDev* sr = st + r;
+        if (t < 32) { cs_s[r][t] = sr->cs[t]; sn_s[r][t] = sr->sn[t]; }
+        if (t < 33) g_s[r][t] = sr->g[t];
+        if (t == 0) {
+            stop_s[r] = sr->stop;
+            its_s[r] = sr->its;
+            fixed_s[r] = sr->fixed;
+            maxit_s[r] = sr->maxit;
+            tol_s[r] = sr->tol_abs;
+        }
+        if (!sr->stop) j0 = sr->j;   // the running RHS share j
+    }
+    __syncthreads();
+    const long chunk = (nh + G - 1) / G;
+    const long e0 = min(nh, (long)wg * chunk), e1 = min(nh, e0 + chunk);
+    for (int j = j0; j < m; j++) {
+        int live = 0;
+        for (int r = 0; r < nr; r++) live += !stop_s[r];
+        if (!live) break;
+        // A: t_e = A_ee^{-1} D_eo v_j (odd part of v_j)
+        for (int s = wg; s < vh; s += G)
+            for (int r = 0; r < nr; r++) {
+                if (stop_s[r]) continue;
+                const cx<T>* vj = V + (size_t)j * ldv + (size_t)r * nfull;
+                coop_site_apply(op, 0, s, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, tmp + (size_t)r * nfull,
+                                ap_part, ap_buf, ap_mat, ap_vin);
+            }
+        if (!coop_barrier(bar, abort_flag, G)) return;
+        // B: w = A_oo v_j - D_oe t_e, written as v_{j+1}
+        for (int s = wg; s < vh; s += G)
+            for (int r = 0; r < nr; r++) {
+                if (stop_s[r]) continue;
+                const cx<T>* vj = V + (size_t)j * ldv + (size_t)r * nfull;
+                coop_site_apply(op, 1, s, CS_SELF, vj, -1, tmp + (size_t)r * nfull, false,
+                                V + (size_t)(j + 1) * ldv + (size_t)r * nfull, ap_part, ap_buf, ap_mat, ap_vin);
+            }
+        if (!coop_barrier(bar, abort_flag, G)) return;
+        // C: partial inner products over this workgroup's chunk of the odd entries
+        for (int r = 0; r < nr; r++) {
+            if (stop_s[r]) continue;
+            const cx<T>* Vr = V + (size_t)r * nfull + nh;
+            const cx<T>* w = Vr + (size_t)(j + 1) * ldv;
+            for (int i = 0; i <= j; i++) {
+                double re = 0, im = 0;
+                for (long e = e0 + t; e < e1; e += COOP_NT) {
+                    cx<T> a = Vr[(size_t)i * ldv + e], b = w[e];
+                    re += (double)a.re * b.re + (double)a.im * b.im;
+                    im += (double)a.re * b.im - (double)a.im * b.re;
+                }
+                re = coop_sum(re, sh);
+                im = coop_sum(im, sh);
+                if (t == 0) part[((size_t)r * 34 + i) * G + wg] = cx<double>{re, im};
+            }
+        }
+        if (!coop_barrier(bar, abort_flag, G)) return;
+        // D: h (fixed-order sum of the partials), w -= V h, partial ||w||^2
+        for (int r = 0; r < nr; r++) {
+            if (stop_s[r]) continue;
+            for (int i = t; i <= j; i += COOP_NT) {
+                cx<double> hsum = czero<double>();
+                for (unsigned q = 0; q < G; q++) hsum += part[((size_t)r * 34 + i) * G + q];
+                h_s[r][i] = hsum;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < nr; r++) {
+            if (stop_s[r]) continue;
+            const cx<T>* Vr = V + (size_t)r * nfull + nh;
+            cx<T>* w = V + (size_t)(j + 1) * ldv + (size_t)r * nfull + nh;
+            double acc = 0;
+            for (long e = e0 + t; e < e1; e += COOP_NT) {
+                cx<T> we = w[e];
+                for (int i = 0; i <= j; i++) we -= ccast<T>(h_s[r][i]) * Vr[(size_t)i * ldv + e];
+                w[e] = we;
+                acc += (double)norm2(we);
+            }
+            acc = coop_sum(acc, sh);
+            if (t == 0) part[((size_t)r * 34 + 33) * G + wg] = cx<double>{acc, 0.0};
+        }
+        if (!coop_barrier(bar, abort_flag, G)) return;
+        // E: ||w||, Givens update (same arithmetic as the step-by-step kernels), scale
+        if (t < nr && !stop_s[t]) {
+            const int r = t;
+            double n2 = 0;
+            for (unsigned q = 0; q < G; q++) n2 += part[((size_t)r * 34 + 33) * G + q].re;
+            const double hn = sqrt(n2);
+            cx<double>* col = col_s[r];
+            for (int i = 0; i <= j; i++) col[i] = h_s[r][i];
+            col[j + 1] = cx<double>{hn, 0.0};
+            for (int i = 0; i < j; i++) {
+                cx<double> a = col[i], b = col[i + 1];
+                col[i] = conj(cs_s[r][i]) * a + conj(sn_s[r][i]) * b;
+                col[i + 1] = -(sn_s[r][i] * a) + cs_s[r][i] * b;
+            }
+            cx<double> a = col[j], b = col[j + 1];
+            const double den = sqrt(norm2(a) + norm2(b));
+            if (den == 0.0) { cs_s[r][j] = cx<double>{1.0, 0.0}; sn_s[r][j] = czero<double>(); }
+            else { cs_s[r][j] = cx<double>{a.re / den, a.im / den}; sn_s[r][j] = cx<double>{b.re / den, b.im / den}; }
+            col[j] = conj(cs_s[r][j]) * a + conj(sn_s[r][j]) * b;
+            col[j + 1] = czero<double>();
+            g_s[r][j + 1] = -(sn_s[r][j] * g_s[r][j]);
+            g_s[r][j] = conj(cs_s[r][j]) * g_s[r][j];
+            its_s[r] += 1;
+            const double resid = sqrt(norm2(g_s[r][j + 1]));
+            int stop = (fixed_s[r] > 0) ? (its_s[r] >= fixed_s[r]) : ((resid <= tol_s[r]) || (its_s[r] >= maxit_s[r]));
+            if (hn == 0.0) stop = 1;
+            hn_s[r] = hn;
+            if (wg == 0) {
+                GmDev* sr = st + r;
+                for (int i = 0; i <= j + 1; i++) sr->H[(size_t)j * 33 + i] = col[i];
+                sr->cs[j] = cs_s[r][j];
+                sr->sn[j] = sn_s[r][j];
+                sr->g[j] = g_s[r][j];
+                sr->g[j + 1] = g_s[r][j + 1];
+                sr->its = its_s[r];
+                sr->j = j + 1;
+                sr->stop = stop;
+                sr->scale = (hn > 0) ? 1.0 / hn : 0.0;
+            }
+            stop_s[r] = stop;
+        }
+        __syncthreads();
+        for (int r = 0; r < nr; r++) {
+            if (stop_s[r]) continue;   // (a RHS that stopped in this step is not scaled, as before)
+            cx<T>* w = V + (size_t)(j + 1) * ldv + (size_t)r * nfull + nh;
+            const T sc = T(1.0 / hn_s[r]);
+            for (long e = e0 + t; e < e1; e += COOP_NT) w[e] = sc * w[e];
+        }
+        if (!coop_barrier(bar, abort_flag, G)) return;
+    }
+}
+
+// Largest grid the cooperative launch admits (0 when not supported)
+template <class T, class S>
+int coarse_gmres_coop_max_grid() {
+    int dev = 0, ncu = 0, per = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_gmres_coop<T, S>, COOP_NT, 0) != hipSuccess)
+        return 0;
+    return per * ncu;
+}
+
+template <class T, class S>
+hipError_t coarse_gmres_coop(const CoarseOp<T, S>& op, cx<T>* V, long ldv, long nfull, cx<T>* tmp, GmDev* st, int nr,
+                             int m, cx<double>* part, unsigned* bar, int* abort_flag, int grid, hipStream_t s) {
+    if (nr > COOP_MAXR || op.nd > 64 || m > 32 || grid < 1) return hipErrorInvalidValue;
+    CoarseOp<T, S> a0 = op;
+    void* args[] = {&a0, &V, &ldv, &nfull, &tmp, &st, &nr, &m, &part, &bar, &abort_flag};
+    return hipLaunchCooperativeKernel((const void*)k_gmres_coop<T, S>, dim3(grid), dim3(COOP_NT), args, 0, s);
+}
+
+// ---------------------------------------------------------------------------
 // self-block inverse: Gauss-Jordan with partial pivoting on [A | I] in FP64
 // ---------------------------------------------------------------------------
 template <class T>
@@ -896,6 +1212,9 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
 
 // operator kernels for compute type T and storage type S
 #define DD_COARSE_OP_INST(T, S)                                                                                      \
+    template int coarse_gmres_coop_max_grid<T, S>();                                                                 \
+    template hipError_t coarse_gmres_coop<T, S>(const CoarseOp<T, S>&, cx<T>*, long, long, cx<T>*, GmDev*, int, int, \
+                                                cx<double>*, unsigned*, int*, int, hipStream_t);                      \
     template void coarse_apply<T, S>(const CoarseOp<T, S>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*,   \
                                      hipStream_t, Mask, int, long);                                                 \
     template void coarse_sap_half<T, S>(const CoarseOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \

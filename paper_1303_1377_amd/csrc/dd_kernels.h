@@ -18,6 +18,7 @@ enum FineSched {
     SCHED_LDS = 4,     // stencil: one workgroup per layout block staged in LDS
     SCHED_NO_MFMA = 8, // multi-RHS coarse stencil on the vector units instead of the matrix cores
     SCHED_GRAPH = 16,  // coarsest-level Arnoldi steps replayed as captured HIP graphs
+    SCHED_COOP = 32,   // coarsest-level GMRES cycle as one persistent cooperative launch
 };
 // Fields are stored in S (T, or _Float16 for the FP16-storage preconditioner)
 // and computed on in T.
@@ -122,6 +123,16 @@ enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
+// One restart cycle of the coarsest odd-even GMRES for nr <= 16 RHS in one
+// cooperative launch of `grid` workgroups (see dd_coarse.hip); the GmDev states
+// must have been started (gm_start) and v_0 normalised.  part: nr*34*grid
+// complex doubles of scratch; bar: two zeroed words kept across launches;
+// abort_flag: raised if a grid barrier wait exceeds its spin limit.
+struct GmDev;
+template <class T, class S> int coarse_gmres_coop_max_grid();
+template <class T, class S>
+hipError_t coarse_gmres_coop(const CoarseOp<T, S>& op, cx<T>* V, long ldv, long nfull, cx<T>* tmp, GmDev* st, int nr,
+                             int m, cx<double>* part, unsigned* bar, int* abort_flag, int grid, hipStream_t s);
 template <class T> void coarse_self_inverse(const Geom& g, int nd, const cx<T>* M, cx<T>* Minv, int* bad, hipStream_t s);
 template <class T> void coarse_import_vector(const Geom& g, int nd, int n, const double* canon, cx<T>* out, hipStream_t s);
 template <class T> void coarse_export_vector(const Geom& g, int nd, int n, const cx<T>* in, double* canon, hipStream_t s);

@@ -158,6 +158,7 @@ template <class T> struct Hier;
 static const int DI_BAD = 0;        // error counter of the last checked step
 static const int DI_ONES = 16;      // MAX_RHS words that stay 1: "every RHS active"
 static const int DI_GATHER = 32;    // {j, its, stop} of each coarsest-GMRES state
+static const int DI_BAR = 120;      // cooperative GMRES: barrier count, generation, abort flag
 static const int DI_MASK = 128;     // per level: [cycle mask][current mask], MAX_RHS each
 static const int DI_WORDS = DI_MASK + 2 * MAX_RHS * DD_MAXLEV;
 // reduction results per right-hand side: pass-1 h (0..32), ||w||^2 (33),
@@ -215,7 +216,7 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
-    int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
+    int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH | SCHED_COOP;   // launch schedule (SCHED_* flags)
     ~dd_ctx();
 };
 
@@ -306,6 +307,20 @@ static Batch with_mask(dd_ctx* C, const Batch& b, int word, unsigned h) {
     return o;
 }
 
+// largest cooperative grid of the persistent coarse GMRES for an operator type
+template <class Op> struct CoopTypes;
+template <class T, class S> struct CoopTypes<CoarseOp<T, S>> {
+    static int max_grid() { return coarse_gmres_coop_max_grid<T, S>(); }
+};
+template <class Op> static int coop_max_grid() {
+    static int cached = -1;
+    if (cached < 0) {
+        cached = CoopTypes<Op>::max_grid();
+        (void)hipGetLastError();
+    }
+    return cached;
+}
+
 // ---------------------------------------------------------------------------
 // level hierarchy in preconditioner precision T.  Every level-l vector set has
 // R slots (RHS r at base + r*nlv(l)); a Krylov basis stores V_i of RHS r at
@@ -365,6 +380,7 @@ struct Hier {
     GmDev* gmst[DD_MAXLEV]; // R device GMRES states of the coarsest level
     int last_its[DD_MAXLEV];
     long coarse_count[DD_MAXLEV][MAX_RHS];
+    bool coop_off = false;   // the cooperative coarse GMRES failed once on this hierarchy
     // instantiated graphs of one coarsest-level Arnoldi step, by (level, j, nr)
     std::map<long, hipGraphExec_t> graphs;
     ~Hier() {
@@ -731,10 +747,46 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     };
     // graphs need a capture stream; live kernel timing brackets single launches
     const bool use_graphs = (C->sched & SCHED_GRAPH) && C->cap;
+    // one cooperative launch per restart cycle when the device admits the grid
+    int coop_grid = 0;
+    if ((C->sched & SCHED_COOP) && !coop_off && nd[l] <= 64 && nr <= 16 && m <= 32) {
+        int mx = 0;
+        with_coarse(l, [&](auto& op) {
+            using OpT = typename std::remove_reference<decltype(op)>::type;
+            mx = coop_max_grid<OpT>();
+        });
+        coop_grid = std::min({mx, std::max(1, g[l].vh), 512});
+    }
     int chunk = std::min(m, std::max(1, last_its[l] + 2));
     for (;;) {
         int j = 0;
         bool all_stop = false;
+        if (coop_grid > 0) {
+            unsigned* bar = reinterpret_cast<unsigned*>(C->dflags + DI_BAR);
+            HIPX(hipMemsetAsync(C->dflags + DI_BAR, 0, 3 * sizeof(int), C->s));
+            hipError_t herr = hipSuccess;
+            {
+                Prof pr(C, DD_K_COARSE_STEP, 0.0);
+                with_coarse(l, [&](auto& op) {
+                    herr = coarse_gmres_coop(op, V, ldv, nfull, wc[l], st, nr, m, reinterpret_cast<cx<double>*>(C->dwork),
+                                             bar, C->dflags + DI_BAR + 2, coop_grid, C->s);
+                });
+            }
+            if (herr == hipSuccess) {
+                all_stop = read_state();
+                if (read_flag(C, DI_BAR + 2)) {
+                    // a barrier wait gave up (workgroups not co-resident): redo this
+                    // coarse solve with single launches and keep them from now on
+                    coop_off = true;
+                    gmres_oe(l, r, e, bt);
+                    return;
+                }
+                j = m;
+            } else {
+                (void)hipGetLastError();   // not admitted: step-by-step launches from here on
+                coop_grid = 0;
+            }
+        }
         while (j < m) {
             const int jend = std::min(m, j + chunk);
             for (; j < jend; j++) {
@@ -1756,7 +1808,7 @@ static void set_sched(dd_ctx* C, int sched) {
 
 dd_status dd_set_schedule(dd_ctx* ctx, int sched) {
     ABI_TRY(ctx)
-    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA | SCHED_GRAPH))
+    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP))
         fail(DD_EINVAL, "unknown schedule flags");
     set_sched(ctx, sched);
     return DD_OK;
@@ -1772,7 +1824,7 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     ABI_TRY(ctx)
     if (reps < 1) fail(DD_EINVAL, "reps >= 1");
     const int nsched = (SCHED_FUSED | SCHED_XCD | SCHED_LDS) + 1;
-    const int keep = ctx->sched & (SCHED_NO_MFMA | SCHED_GRAPH);
+    const int keep = ctx->sched & (SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP);
     double best = 0;
     int pick = ctx->sched;
     for (int sc = 0; sc < nsched; sc++) {

@@ -549,3 +549,41 @@ def test_coarsest_level_with_odd_block_count():
     x, st = p.g.solve(b, 1e-10)
     r = b - p.o.apply(to_np(x))
     assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_cooperative_coarse_gmres_matches_step_launches(precision):
+    """The coarsest GMRES cycle as one cooperative launch (default schedule)
+    against the step-by-step launches: coarse solves with a fixed iteration
+    count and to tolerance, single and batched, agree to rounding; the FP64
+    fixed-count solve also matches the oracle."""
+    say("case: cooperative coarse GMRES precision", precision)
+    k = 3
+    p, V = _built_batch(precision, k)
+    base = p.g.get_schedule()
+    assert base & 32, "the cooperative coarse GMRES is part of the default schedule"
+    E1, it1 = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    e1, j1 = p.g.apply("COARSE_SOLVE", 1, V[0])
+    p.g.set_schedule(base & ~32)
+    E2, it2 = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    e2, j2 = p.g.apply("COARSE_SOLVE", 1, V[0])
+    p.g.set_schedule(base)
+    bar = 1e-11 if precision == 64 else 1e-5
+    assert it1 == it2 == [6] * k and j1 == j2 == 6
+    assert rel(to_np(E1), to_np(E2)) < bar and rel(to_np(e1), to_np(e2)) < bar
+    if precision == 64:
+        for q in range(k):
+            assert rel(to_np(E1)[q], p.o.coarse_solve(1, V[q])[0]) < 1e-10
+    # to tolerance (no fixed count): same iteration counts, same solution to rounding
+    p.g.configure(__import__("paper_1303_1377_amd").default_params(
+        levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4], coarse_tol=1e-8, coarse_restart=2,
+        precision=precision, max_rhs=k))
+    p.g.set_test_vectors(0, p.vectors(0, 20, 12))
+    p.g.build_level(0)
+    p.g.mark_setup()
+    Ec, itc = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    p.g.set_schedule(base & ~32)
+    Es, its_ = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    say("coop its", itc, "step its", its_)
+    assert itc == its_ and all(i > 2 for i in itc)   # several restart cycles
+    assert rel(to_np(Ec), to_np(Es)) < (1e-9 if precision == 64 else 1e-4)
