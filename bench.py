@@ -222,9 +222,15 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log("bench: setup %.3fs" % setup_s)
+    coarse_tune = None
     if args.sched is None:
         sched, tune_ms = s.autotune(reps=5)
         log("bench: autotuned schedule %d (ms per schedule %s)" % (sched, ["%.3f" % t for t in tune_ms]))
+        grid, ctimes = s.autotune_coarse(reps=3)
+        sched = s.get_schedule()
+        coarse_tune = dict(chosen_grid=grid, ms_step_launches=ctimes[0],
+                           ms_cooperative={str(g): t for g, t in zip((16, 32, 64, 128), ctimes[1:])})
+        log("bench: coarse solver %s" % coarse_tune)
     else:
         s.set_schedule(args.sched)
         sched = args.sched
@@ -279,6 +285,7 @@ def main():
         setup_s=setup_s,
         solves_per_s=1.0 / tts,
         schedule=sched,
+        coarse_solver_tuning=coarse_tune,
         outer_iters=[st["outer_iters"] for st in stats],
         coarse_iters_per_solve=[st["coarse_iters"][1] for st in stats],
         true_relres_max=worst,

@@ -283,8 +283,8 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   barriers between the phases of an Arnoldi step); falls
  *                   back to DD_SCHED_GRAPH / single launches when the device
  *                   does not admit the grid.  Results agree to rounding.
- * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH | DD_SCHED_COOP
- * with the matrix cores on.
+ * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH with the matrix
+ * cores on; dd_autotune_coarse decides about DD_SCHED_COOP and its grid.
  * ------------------------------------------------------------------------- */
 enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16,
        DD_SCHED_COOP = 32 };
@@ -300,6 +300,13 @@ int dd_get_schedule(const dd_ctx *ctx);
  * fastest.  chosen (may be NULL) receives it; times_ms (may be NULL) holds 8
  * doubles, the cost of each schedule (flag set 0..7) in ms. */
 dd_status dd_autotune(dd_ctx *ctx, int reps, int *chosen, double *times_ms);
+
+/* Coarse-solver autotuner (after dd_setup): times `reps` coarsest-level solves
+ * of a fixed random right-hand side with step-by-step launches and with the
+ * cooperative cycle (DD_SCHED_COOP) at 16, 32, 64 and 128 workgroups, and keeps
+ * the fastest.  chosen_grid (may be NULL): 0 for step-by-step launches, else
+ * the workgroup count; times_ms (may be NULL): 5 doubles, ms per solve. */
+dd_status dd_autotune_coarse(dd_ctx *ctx, int reps, int *chosen_grid, double *times_ms);
 
 #ifdef __cplusplus
 }

@@ -113,10 +113,11 @@ def library():
         L.dd_get_schedule.argtypes = [vp]
         L.dd_get_schedule.restype = C.c_int
         L.dd_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.dd_autotune_coarse.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
-                     "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch"):
+                     "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -269,6 +270,13 @@ class Solver:
         ch = C.c_int()
         t = (C.c_double * 8)()
         self._check(library().dd_autotune(self.h, int(reps), C.byref(ch), t))
+        return ch.value, list(t)
+
+    def autotune_coarse(self, reps=3):
+        """Step-by-step vs cooperative coarse GMRES (16..128 workgroups); returns (grid or 0, [ms x 5])."""
+        ch = C.c_int()
+        t = (C.c_double * 5)()
+        self._check(library().dd_autotune_coarse(self.h, int(reps), C.byref(ch), t))
         return ch.value, list(t)
 
     def time_kernel(self, name, reps=20):

@@ -216,7 +216,8 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
-    int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH | SCHED_COOP;   // launch schedule (SCHED_* flags)
+    int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
+    int coop_cap = 32;           // workgroups of the cooperative coarse GMRES (autotuned)
     ~dd_ctx();
 };
 
@@ -755,7 +756,7 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
             using OpT = typename std::remove_reference<decltype(op)>::type;
             mx = coop_max_grid<OpT>();
         });
-        coop_grid = std::min({mx, std::max(1, g[l].vh), 512});
+        coop_grid = std::min({mx, std::max(1, g[l].vh), C->coop_cap});
     }
     int chunk = std::min(m, std::max(1, last_its[l] + 2));
     for (;;) {
@@ -1841,6 +1842,47 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     }
     set_sched(ctx, pick);
     if (chosen) *chosen = pick;
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+// Coarse-solver autotuner: one coarsest-level solve on a fixed random RHS with
+// the step-by-step graph launches and with the cooperative cycle at 16, 32, 64
+// and 128 workgroups; the fastest is kept.
+template <class T>
+static void tune_coarse(dd_ctx* C, Hier<T>& H, int reps, int* chosen, double* times) {
+    const int l = H.nlev - 1;
+    coarse_random(H.g[l], H.nd[l], 1, 777ULL, 11, H.rc[l], C->s);
+    const Batch one = single(C);
+    const int caps[5] = {0, 16, 32, 64, 128};
+    const int saved = C->sched, saved_cap = C->coop_cap;
+    double best = 0;
+    int pick = 0;
+    for (int v = 0; v < 5; v++) {
+        C->sched = caps[v] ? (saved | SCHED_COOP) : (saved & ~SCHED_COOP);
+        C->coop_cap = caps[v] ? caps[v] : saved_cap;
+        H.coop_off = false;
+        H.gmres_oe(l, H.rc[l], H.ec[l], one);   // warm-up (graph capture)
+        sync(C);
+        const double t0 = now_s();
+        for (int r = 0; r < reps; r++) H.gmres_oe(l, H.rc[l], H.ec[l], one);
+        sync(C);
+        const double ms = (now_s() - t0) * 1e3 / reps;
+        if (times) times[v] = ms;
+        if (v == 0 || ms < best) { best = ms; pick = v; }
+    }
+    C->sched = caps[pick] ? (saved | SCHED_COOP) : (saved & ~SCHED_COOP);
+    C->coop_cap = caps[pick] ? caps[pick] : saved_cap;
+    memset(H.coarse_count, 0, sizeof H.coarse_count);
+    if (chosen) *chosen = caps[pick];
+}
+
+dd_status dd_autotune_coarse(dd_ctx* ctx, int reps, int* chosen_grid, double* times_ms) {
+    ABI_TRY(ctx)
+    if (reps < 1) fail(DD_EINVAL, "reps >= 1");
+    if (!ctx->have_setup) fail(DD_ESTATE, "the coarse solver is tuned after dd_setup");
+    if (ctx->H64) tune_coarse(ctx, *ctx->H64, reps, chosen_grid, times_ms);
+    else tune_coarse(ctx, *ctx->H32, reps, chosen_grid, times_ms);
     return DD_OK;
     ABI_END(ctx)
 }

@@ -553,15 +553,15 @@ def test_coarsest_level_with_odd_block_count():
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_cooperative_coarse_gmres_matches_step_launches(precision):
-    """The coarsest GMRES cycle as one cooperative launch (default schedule)
-    against the step-by-step launches: coarse solves with a fixed iteration
+    """The coarsest GMRES cycle as one cooperative launch against the
+    step-by-step launches: coarse solves with a fixed iteration
     count and to tolerance, single and batched, agree to rounding; the FP64
     fixed-count solve also matches the oracle."""
     say("case: cooperative coarse GMRES precision", precision)
     k = 3
     p, V = _built_batch(precision, k)
-    base = p.g.get_schedule()
-    assert base & 32, "the cooperative coarse GMRES is part of the default schedule"
+    base = p.g.get_schedule() | 32
+    p.g.set_schedule(base)
     E1, it1 = p.g.apply_batch("COARSE_SOLVE", 1, V)
     e1, j1 = p.g.apply("COARSE_SOLVE", 1, V[0])
     p.g.set_schedule(base & ~32)
@@ -581,9 +581,28 @@ def test_cooperative_coarse_gmres_matches_step_launches(precision):
     p.g.set_test_vectors(0, p.vectors(0, 20, 12))
     p.g.build_level(0)
     p.g.mark_setup()
+    p.g.set_schedule(base)
     Ec, itc = p.g.apply_batch("COARSE_SOLVE", 1, V)
     p.g.set_schedule(base & ~32)
     Es, its_ = p.g.apply_batch("COARSE_SOLVE", 1, V)
     say("coop its", itc, "step its", its_)
     assert itc == its_ and all(i > 2 for i in itc)   # several restart cycles
     assert rel(to_np(Ec), to_np(Es)) < (1e-9 if precision == 64 else 1e-4)
+
+
+def test_coarse_autotuner_keeps_results():
+    """dd_autotune_coarse picks a coarse-solver form; solves before and after agree to rounding."""
+    say("case: coarse autotuner")
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=3, m0=-0.25, csw=1.0)
+    p.g.setup(params=G.default_params(levels=2, n_tv=[8], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], n_inv=2,
+                                      outer_restart=20))
+    b = F.gaussian_spinor(dims, 5)
+    x0, st0 = p.g.solve(b, 1e-10)
+    grid, times = p.g.autotune_coarse(reps=2)
+    say("coarse autotune", grid, times)
+    assert grid in (0, 16, 32, 64, 128) and all(t > 0 for t in times)
+    x1, st1 = p.g.solve(b, 1e-10)
+    assert st1["converged"] and rel(to_np(x1), to_np(x0)) < 1e-9
