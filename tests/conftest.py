@@ -4,6 +4,10 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the oracle's OpenMP threads and the BLAS threads of the dense reference
+# solves share the cores: idle threads sleep instead of spinning, which keeps
+# the suite's time sane when the machine is busy
+os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
