@@ -261,13 +261,11 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
     return cx<double>{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-__global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
-    GmDev* st = st0 + blockIdx.x;
-    if (threadIdx.x != 0 || st->stop) return;
-    const cx<double>* h = res + (size_t)blockIdx.x * rstride;
+// fold column j (inner products h[0..j], ||w||^2 = hn2) into the state (one thread)
+__device__ void gm_column_dev(GmDev* st, int j, const cx<double>* h, double hn2) {
     cx<double>* col = st->H + (size_t)j * 33;
     for (int i = 0; i <= j; i++) col[i] = h[i];
-    double hn = sqrt(h[33].re);
+    double hn = sqrt(hn2);
     col[j + 1] = cx<double>{hn, 0.0};
     for (int i = 0; i < j; i++) {  // previous rotations
         cx<double> a = col[i], b = col[i + 1];
@@ -291,6 +289,31 @@ __global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ re
     if (hn == 0.0) stop = 1;
     st->stop = stop;
     st->scale = (hn > 0) ? 1.0 / hn : 0.0;
+}
+
+__global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
+    GmDev* st = st0 + blockIdx.x;
+    if (threadIdx.x != 0 || st->stop) return;
+    const cx<double>* h = res + (size_t)blockIdx.x * rstride;
+    gm_column_dev(st, j, h, h[33].re);
+}
+
+// ||w||^2 from the chunk partials (fixed order) and the Givens update of
+// column j, one workgroup per RHS: the last two kernels of an Arnoldi step in one
+__global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>* __restrict__ npart, cx<double>* res,
+                                                        int rstride, GmDev* st0, int j) {
+    const int r = blockIdx.x;
+    GmDev* st = st0 + r;
+    if (st->stop) return;
+    __shared__ double sh[RED_NT / 64];
+    double acc = 0;
+    for (int c = threadIdx.x; c < nc; c += RED_NT) acc += npart[(size_t)r * nc + c].re;
+    acc = block_sum256(acc, sh);
+    if (threadIdx.x == 0) {
+        cx<double>* h = res + (size_t)r * rstride;
+        h[33] = cx<double>{acc, 0.0};
+        gm_column_dev(st, j, h, acc);
+    }
 }
 
 __global__ void k_gm_solve(GmDev* st0) {
@@ -377,6 +400,17 @@ void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<
                                              npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
     dim3 g2(1, rb.nr);
     k_final_sum<<<g2, RED_NT, 0, s>>>(nc, 1, npart_of(work, rb.nr), res + 33, rb.ostride, rb.mk);
+}
+
+template <class T>
+void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
+                            hipStream_t s, RedBatch rb, GmDev* st, int j) {
+    const int nc = red_chunks(n);
+    const long chunk = (n + nc - 1) / nc;
+    dim3 grid(nc, rb.nr);
+    k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
+                                             npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
+    k_norm_givens<<<rb.nr, RED_NT, 0, s>>>(nc, npart_of(work, rb.nr), res, rb.ostride, st, j);
 }
 
 template <class T, class X>
@@ -474,7 +508,9 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t, int, long, long); \
     template void vec_multidot_skip<T>(long, int, const cx<T>*, long, const cx<T>*, void*, hipStream_t, RedBatch);  \
     template void vec_update_norm_skip<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t,  \
-                                          RedBatch);
+                                          RedBatch);                                                               \
+    template void vec_update_norm_givens<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t, \
+                                            RedBatch, GmDev*, int);
 
 DD_BLAS_INST(double)
 DD_BLAS_INST(float)
