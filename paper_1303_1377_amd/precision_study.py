@@ -68,6 +68,12 @@ def run(dims, m0, precisions=(64, 32, 16), solves=2, tol=1e-10, seed=0, ape=2, n
             times.append(time.time() - t0)
             xs.append(x)
             sts.append(st)
+        # time per kernel class over one more solve (live HIP events)
+        s.profile(True)
+        s.solve(B[0], tol)
+        prof = s.profile_read()
+        s.profile(False)
+        classes = {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in prof.items() if v[0]}
         if ref is None and prec == 64:
             ref = xs
         dev = None
@@ -77,7 +83,7 @@ def run(dims, m0, precisions=(64, 32, 16), solves=2, tol=1e-10, seed=0, ape=2, n
             precision=prec, setup_s=setup_s, time_to_solution_s=float(np.median(times)), solve_s=times,
             outer_iters=[st["outer_iters"] for st in sts], coarse_iters=[list(st["coarse_iters"][:3]) for st in sts],
             true_relres=[st["true_relres"] for st in sts], rel_diff_vs_fp64_form=dev, device_bytes=s.device_bytes(),
-            schedule=s.get_schedule())
+            schedule=s.get_schedule(), kernel_classes_ms=classes)
         _log("precision_study:", prec, res["fp%d" % prec if prec != 16 else "fp16_storage"])
         s.close()
     return res

@@ -74,41 +74,48 @@ def _stack(xs):
 
 
 def estimate_bytes(dims, params=None, max_rhs=1):
-    """HBM a resident two- or three-level setup needs, from the allocation
-    sizes of the library (fields, hierarchy, Krylov workspaces), rounded up."""
+    """Device bytes a resident setup holds, following the library's
+    allocations: fine fields (FP64 and FP32 copies), the outer FGMRES
+    workspace for max_rhs right-hand sides, and per level the vector sets,
+    test vectors, P, D_c, its self-block inverses and the Krylov bases
+    (FP16 copies for precision 16)."""
+    def get(name, default):
+        return getattr(params, name, default) if params is not None else default
+
     vol = 1
     for d in dims:
         vol *= d
-    levels = getattr(params, "levels", 2) if params is not None else 2
-    prec = getattr(params, "precision", 64) if params is not None else 64
-    n_tv = list(getattr(params, "n_tv", [20, 20])) if params is not None else [20, 20]
-    agg = [tuple(a) for a in getattr(params, "agg", [(4, 4, 4, 4), (2, 2, 2, 2)])] if params is not None else \
-        [(4, 4, 4, 4), (2, 2, 2, 2)]
-    m_out = getattr(params, "outer_restart", 25) if params is not None else 25
-    m_c = getattr(params, "coarse_restart", 30) if params is not None else 30
-    sz = 16 if prec == 64 else 8
+    levels = get("levels", 2)
+    prec = get("precision", 64)
+    n_tv = list(get("n_tv", [20, 20, 20, 20]))
+    agg = [tuple(a) for a in get("agg", [(4, 4, 4, 4)] + [(2, 2, 2, 2)] * 3)]
+    m_out = get("outer_restart", 25)
+    m_c = get("coarse_restart", 30)
+    m_mid = get("mid_restart", 10)
     R = max_rhs
-    # fine fields: FP64 + FP32 links and clover (+ FP16 copies), canonical gauge copy
-    b = vol * (72 * 8 + 144 * 8 + 72 * 4 + 144 * 4 + 72 * 8)
+    sz = 16 if prec == 64 else 8            # complex entry of the preconditioner
+    zb = 16 if prec == 64 else 8
+    b = vol * 3168 + (9 << 20)              # links, clover, inverses (FP64 + FP32), canonical gauge
+    nR = 12 * vol * R
+    b += (m_out + 1) * nR * 16 + m_out * nR * zb + 4 * nR * 16
     if prec == 16:
-        b += vol * (72 + 144) * 2
-    # outer workspace: V (m+1) FP64, Z (m) in preconditioner precision, b, x, 2 temporaries
-    n = 12 * vol
-    b += R * n * ((m_out + 1) * 16 + m_out * sz + 4 * 16)
-    # level 0 vectors and transfer
+        b += vol * 432                      # FP16 links and clover blocks
     n0 = 12 * vol
-    b += 3 * R * n0 * sz + 2 * n_tv[0] * n0 * sz
+    b += 3 * R * n0 * sz + 2 * n_tv[0] * n0 * sz + (n_tv[0] * n0 * 4 if prec == 16 else 0)
     v = vol
     for l in range(1, levels):
         a = agg[l - 1]
         v //= a[0] * a[1] * a[2] * a[3]
         nd = 2 * n_tv[l - 1]
-        b += v * 10 * nd * nd * sz + 5 * R * v * nd * sz
+        nl = v * nd
+        b += v * 10 * nd * nd * sz + (v * 10 * nd * nd * 4 if prec == 16 else 0)
+        b += 5 * R * nl * sz + R * 17 * 1024
         if l < levels - 1:
-            b += 2 * n_tv[l] * v * nd * sz + 21 * R * v * nd * sz
+            b += 2 * n_tv[l] * nl * sz + (n_tv[l] * nl * 4 if prec == 16 else 0)
+            b += (max(m_mid, m_c) + 1) * R * nl * sz + m_mid * R * nl * sz
         else:
-            b += (m_c + 1) * R * v * nd * sz
-    return int(b * 1.1) + (64 << 20)
+            b += (m_c + 1) * R * nl * sz
+    return int(b * 1.02) + (32 << 20)
 
 
 class Server:
@@ -235,6 +242,17 @@ class Server:
             self._evict(old)
         return used + need <= self.budget
 
+    def _trim(self, keep):
+        """Evict idle setups (least recently used first) while the resident
+        bytes exceed the budget (caller holds the lock)."""
+        pending_fields = {r.field_id for r in self._pending}
+        for old in list(self._resident):
+            if sum(self._resident_bytes.values()) <= self.budget:
+                break
+            if old == keep or old in self._busy or old in pending_fields:
+                continue
+            self._evict(old)
+
     def _next_batch(self, fid):
         """Up to max_rhs RHS of field `fid` sharing one tolerance, in arrival
         order (caller holds the lock)."""
@@ -293,6 +311,7 @@ class Server:
                     self._resident[fid] = solver
                     self._resident_bytes[fid] = held
                     self.admitted += 1
+                    self._trim(keep=fid)
             while True:
                 with self._cv:
                     self._resident.move_to_end(fid)
