@@ -21,6 +21,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -314,11 +315,12 @@ template <class T, class S> struct CoopTypes<CoarseOp<T, S>> {
     static int max_grid() { return coarse_gmres_coop_max_grid<T, S>(); }
 };
 template <class Op> static int coop_max_grid() {
-    static int cached = -1;
-    if (cached < 0) {
+    static std::once_flag once;
+    static int cached = 0;
+    std::call_once(once, [] {
         cached = CoopTypes<Op>::max_grid();
         (void)hipGetLastError();
-    }
+    });
     return cached;
 }
 
