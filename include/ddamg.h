@@ -231,13 +231,21 @@ typedef enum {
     DD_K_COARSE_SAP = 6,   /* coarse-level SAP half sweep                       */
     DD_K_REDUCE = 7,       /* multi-dot and update+norm reductions             */
     DD_K_BLAS = 8,         /* other vector kernels (axpy, scale, conversions)  */
-    DD_K_COARSE_STEP = 9,  /* one coarsest-level Arnoldi step replayed as a graph
+    DD_K_COARSE_STEP = 9,  /* coarsest-level Arnoldi steps: one graph launch of a
+                              chunk of steps, or one cooperative restart cycle
                               (Schur complement + reductions + Givens + scale) */
     DD_K_NCLASS = 10
 } dd_kernel_class;
 
-/* enable != 0 starts (and resets) profiling; 0 stops it. */
+/* enable != 0 starts (and resets) profiling of every kernel class; 0 stops
+ * it.  Each timed launch (or launch group) is bracketed by two HIP events
+ * on the context's stream. */
 dd_status dd_profile(dd_ctx *ctx, int enable);
+
+/* As dd_profile, but only the classes whose bit (1u << class) is set in
+ * class_mask are timed; the others run without events.  class_mask = 0 stops
+ * profiling.  DD_EINVAL for a bit at or above DD_K_NCLASS. */
+dd_status dd_profile_classes(dd_ctx *ctx, unsigned class_mask);
 
 /* Launch count, summed duration (ms) and summed algorithmic bytes (every
  * datum a launch must read or write, counted once) of one kernel class since
@@ -273,11 +281,12 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   arithmetic runs on the vector units (one workgroup per
  *                   site and RHS) instead of the matrix cores (one workgroup
  *                   per site for all RHS); results agree to rounding
- *   DD_SCHED_GRAPH  each Arnoldi step of the coarsest-level GMRES (Schur
- *                   complement, reductions, Givens update, scaling: seven
- *                   kernels) is captured once as a HIP graph per (level, step,
- *                   batch size) and replayed with one launch (not while
- *                   dd_profile times single kernels)
+ *   DD_SCHED_GRAPH  the Arnoldi steps of the coarsest-level GMRES (Schur
+ *                   complement, reductions, Givens update, scaling: six
+ *                   kernels per step) that the host enqueues between two
+ *                   reads of the stop flags are captured once as one HIP
+ *                   graph per (level, first step, step count, batch size)
+ *                   and replayed with one launch
  *   DD_SCHED_COOP   each restart cycle of the coarsest-level GMRES runs as one
  *                   persistent cooperative launch (workgroups meet at grid
  *                   barriers between the phases of an Arnoldi step); falls

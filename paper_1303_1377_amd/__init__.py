@@ -105,6 +105,7 @@ def library():
         L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
         L.dd_profile.argtypes = [vp, C.c_int]
+        L.dd_profile_classes.argtypes = [vp, C.c_uint]
         L.dd_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_long), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.dd_time_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dd_device_bytes.restype = C.c_longlong
@@ -117,6 +118,7 @@ def library():
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
+                     "dd_profile_classes",
                      "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -246,8 +248,16 @@ class Solver:
         self.m0 = float(m0)
 
     # ---- live kernel timing --------------------------------------------------
-    def profile(self, enable=True):
-        self._check(library().dd_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, classes=None):
+        """Start (reset) or stop live timing; `classes` limits it to the named
+        kernel classes (the others run without events)."""
+        if classes is None or not enable:
+            self._check(library().dd_profile(self.h, 1 if enable else 0))
+        else:
+            mask = 0
+            for name in classes:
+                mask |= 1 << KERNEL_CLASSES.index(name)
+            self._check(library().dd_profile_classes(self.h, mask))
 
     def profile_read(self):
         """{class: (launches, total_ms, algorithmic_bytes)} since profile(True)."""

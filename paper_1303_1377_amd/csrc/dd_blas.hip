@@ -12,6 +12,7 @@ namespace dd {
 static constexpr int MAXM = 32;        // basis vectors handled per launch
 static constexpr int RED_CHUNKS = 1024;  // chunks a reduced vector is cut into
 static constexpr int RED_NT = 256;
+static constexpr int UN_BATCH = 16;    // basis vectors loaded together in k_update_norm
 
 size_t reduce_work_size(int m, int nr) {
     (void)m;
@@ -174,8 +175,16 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
     double acc = 0;
     for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
         cx<T> we = wr[e];
-#pragma unroll 4
-        for (int i = 0; i < m; i++) we -= hh[i] * Vr[(size_t)i * ldv + e];
+        // basis entries are loaded in batches so that many loads are in flight
+        // (short coarse vectors leave one element per thread: latency bound)
+        for (int i0 = 0; i0 < m; i0 += UN_BATCH) {
+            cx<T> vv[UN_BATCH];
+#pragma unroll
+            for (int u = 0; u < UN_BATCH; u++) vv[u] = (i0 + u < m) ? Vr[(size_t)(i0 + u) * ldv + e] : czero<T>();
+#pragma unroll
+            for (int u = 0; u < UN_BATCH; u++)
+                if (i0 + u < m) we -= hh[i0 + u] * vv[u];
+        }
         wr[e] = we;
         acc += (double)norm2(we);
     }
@@ -261,28 +270,44 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
     return cx<double>{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-// fold column j (inner products h[0..j], ||w||^2 = hn2) into the state (one thread)
-__device__ void gm_column_dev(GmDev* st, int j, const cx<double>* h, double hn2) {
-    cx<double>* col = st->H + (size_t)j * 33;
-    for (int i = 0; i <= j; i++) col[i] = h[i];
-    double hn = sqrt(hn2);
-    col[j + 1] = cx<double>{hn, 0.0};
-    for (int i = 0; i < j; i++) {  // previous rotations
-        cx<double> a = col[i], b = col[i + 1];
-        col[i] = conj(st->cs[i]) * a + conj(st->sn[i]) * b;
-        col[i + 1] = -(st->sn[i] * a) + st->cs[i] * b;
+// fold column j (inner products h[0..j], ||w||^2 = hn2) into the state of
+// one RHS, by a whole workgroup (at least 32 threads): the inner
+// products and the previous rotations are first staged in LDS by many
+// threads at once, then one thread runs the rotation chain with the running
+// entry in registers (the global-memory form waits on one load per rotation)
+__device__ void gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2) {
+    __shared__ cx<double> hs[33], css[32], sns[32];
+    const int t = threadIdx.x;
+    if (t <= j) hs[t] = h[t];
+    if (t < j) {
+        css[t] = st->cs[t];
+        sns[t] = st->sn[t];
     }
-    cx<double> a = col[j], b = col[j + 1];
-    double den = sqrt(norm2(a) + norm2(b));
-    if (den == 0.0) { st->cs[j] = cx<double>{1.0, 0.0}; st->sn[j] = czero<double>(); }
-    else { st->cs[j] = cx<double>{a.re / den, a.im / den}; st->sn[j] = cx<double>{b.re / den, b.im / den}; }
-    col[j] = conj(st->cs[j]) * a + conj(st->sn[j]) * b;
+    __syncthreads();
+    if (t != 0) return;
+    cx<double>* col = st->H + (size_t)j * 33;
+    const double hn = sqrt(hn2);
+    cx<double> a = hs[0];
+    for (int i = 0; i < j; i++) {  // previous rotations; col[i] is final after rotation i
+        const cx<double> b = hs[i + 1];
+        col[i] = conj(css[i]) * a + conj(sns[i]) * b;
+        a = -(sns[i] * a) + css[i] * b;
+    }
+    const cx<double> b = cx<double>{hn, 0.0};
+    const double den = sqrt(norm2(a) + norm2(b));
+    cx<double> c, s;
+    if (den == 0.0) { c = cx<double>{1.0, 0.0}; s = czero<double>(); }
+    else { c = cx<double>{a.re / den, a.im / den}; s = cx<double>{b.re / den, b.im / den}; }
+    st->cs[j] = c;
+    st->sn[j] = s;
+    col[j] = conj(c) * a + conj(s) * b;
     col[j + 1] = czero<double>();
-    st->g[j + 1] = -(st->sn[j] * st->g[j]);
-    st->g[j] = conj(st->cs[j]) * st->g[j];
+    const cx<double> gj = st->g[j];
+    st->g[j + 1] = -(s * gj);
+    st->g[j] = conj(c) * gj;
     st->its += 1;
     st->j = j + 1;
-    double resid = sqrt(norm2(st->g[j + 1]));
+    const double resid = sqrt(norm2(st->g[j + 1]));
     int stop = 0;
     if (st->fixed > 0) stop = st->its >= st->fixed;
     else stop = (resid <= st->tol_abs) || (st->its >= st->maxit);
@@ -293,9 +318,9 @@ __device__ void gm_column_dev(GmDev* st, int j, const cx<double>* h, double hn2)
 
 __global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
     GmDev* st = st0 + blockIdx.x;
-    if (threadIdx.x != 0 || st->stop) return;
+    if (st->stop) return;
     const cx<double>* h = res + (size_t)blockIdx.x * rstride;
-    gm_column_dev(st, j, h, h[33].re);
+    gm_column_wg(st, j, h, h[33].re);
 }
 
 // ||w||^2 from the chunk partials (fixed order) and the Givens update of
@@ -309,11 +334,9 @@ __global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>
     double acc = 0;
     for (int c = threadIdx.x; c < nc; c += RED_NT) acc += npart[(size_t)r * nc + c].re;
     acc = block_sum256(acc, sh);
-    if (threadIdx.x == 0) {
-        cx<double>* h = res + (size_t)r * rstride;
-        h[33] = cx<double>{acc, 0.0};
-        gm_column_dev(st, j, h, acc);
-    }
+    cx<double>* h = res + (size_t)r * rstride;
+    if (threadIdx.x == 0) h[33] = cx<double>{acc, 0.0};
+    gm_column_wg(st, j, h, acc);
 }
 
 __global__ void k_gm_solve(GmDev* st0) {

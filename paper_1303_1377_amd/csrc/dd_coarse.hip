@@ -19,11 +19,17 @@ static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // out(x) = [post Minv] ( self(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
-// One workgroup per site.  The (block, column) pairs of the site's dense
-// blocks are split evenly over the wavefronts; lane r accumulates row r, so
-// every load of a column-major block is coalesced.  Partial rows meet in LDS.
+// One workgroup per site.  The site's input vectors (self and 8 neighbours,
+// hop sign folded in) are staged in LDS; the (block, column) pairs of its dense
+// blocks are then split evenly over the wavefronts and lane r accumulates row
+// r, so every load of a column-major block is coalesced.  Each wavefront
+// issues its block loads in batches of CA_BATCH before using them, which keeps
+// that many loads in flight per lane: on small coarse lattices (a few hundred
+// sites) the kernel is bound by memory latency, not bandwidth.  Partial rows
+// meet in LDS.
 // ---------------------------------------------------------------------------
-static constexpr int CA_WAVES = 8;
+static constexpr int CA_WAVES = 16;
+static constexpr int CA_BATCH = 12;
 
 template <class T, class S>
 __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> op, int par, int self_mode,
@@ -38,8 +44,8 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
         out += off;
     }
     __shared__ cx<T> part[CA_WAVES][64];
-    __shared__ cx<T> buf[64];
-    __shared__ const cx<S>* mat[9];
+    __shared__ cx<T> X[9 * 64];            // staged inputs [slot][nd] (nd <= 64)
+    __shared__ const cx<S>* mat[10];       // one spare entry for the batched loop's overrun
     __shared__ const cx<T>* vin[9];
     __shared__ int nslot_s;
     const Geom g = op.g;
@@ -50,6 +56,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     else { p = par; i = blockIdx.x; }
     const size_t gs = (size_t)p * g.vh + i;
     const size_t nn = (size_t)nd * nd;
+    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
     if (threadIdx.x == 0) {
         int ns = 0;
         if (self_mode == CS_SELF) { mat[ns] = op.M + gs * 9 * nn; vin[ns] = in1 + gs * nd; ns++; }
@@ -66,28 +73,33 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
                 ns++;
             }
         }
+        mat[ns] = mat[0];
         nslot_s = ns;
     }
     __syncthreads();
-    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
-    const int Q = nslot_s * nd;
+    const int ns = nslot_s;
+    const int Q = ns * nd;
+    for (int e = threadIdx.x; e < Q; e += blockDim.x) {
+        const int sl = e / nd;
+        const cx<T> v = vin[sl][e - sl * nd];
+        X[e] = (sl >= nself && hop_sign < 0) ? -v : v;
+    }
+    __syncthreads();
     const int per = (Q + nw - 1) / nw;
     const int q0 = w * per, q1 = min(Q, q0 + per);
     cx<T> acc = czero<T>();
-    if (r < nd) {
-        int q = q0;
-        while (q < q1) {
-            const int sl = q / nd;
-            const int c0 = q - sl * nd;
-            const int c1 = min(nd, c0 + (q1 - q));
-            const cx<S>* A = mat[sl] + r;
-            const cx<T>* v = vin[sl];
-            cx<T> a2 = czero<T>();
-#pragma unroll 4
-            for (int c = c0; c < c1; c++) a2 += ccast<T>(A[(size_t)c * nd]) * v[c];
-            if (sl >= nself && hop_sign < 0) acc -= a2;
-            else acc += a2;
-            q += c1 - c0;
+    if (r < nd && q0 < q1) {
+        int sl = q0 / nd, c = q0 - sl * nd;   // (slot, column) of pair q, advanced incrementally
+        for (int qb = q0; qb < q1; qb += CA_BATCH) {
+            cx<S> a[CA_BATCH];
+#pragma unroll
+            for (int u = 0; u < CA_BATCH; u++) {
+                a[u] = (qb + u < q1) ? mat[min(sl, 9)][(size_t)c * nd + r] : cx<S>{S(0), S(0)};
+                if (++c == nd) { c = 0; sl++; }
+            }
+#pragma unroll
+            for (int u = 0; u < CA_BATCH; u++)
+                if (qb + u < q1) acc += ccast<T>(a[u]) * X[qb + u];
         }
     }
     part[w][r] = acc;
@@ -101,14 +113,21 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
         if (w == 0 && r < nd) out[gs * nd + r] = tot;
         return;
     }
-    if (w == 0) buf[r] = tot;
+    if (w == 0) X[r] = tot;
     __syncthreads();
     const int per2 = (nd + nw - 1) / nw;
     const int c0 = w * per2, c1 = min(nd, c0 + per2);
     cx<T> a3 = czero<T>();
-    if (r < nd) {
+    if (r < nd && c0 < c1) {
         const cx<S>* A = op.Minv + gs * nn + r;
-        for (int c = c0; c < c1; c++) a3 += ccast<T>(A[(size_t)c * nd]) * buf[c];
+        cx<S> a[CA_BATCH];
+        for (int cb = c0; cb < c1; cb += CA_BATCH) {
+#pragma unroll
+            for (int u = 0; u < CA_BATCH; u++) a[u] = (cb + u < c1) ? A[(size_t)(cb + u) * nd] : cx<S>{S(0), S(0)};
+#pragma unroll
+            for (int u = 0; u < CA_BATCH; u++)
+                if (cb + u < c1) a3 += ccast<T>(a[u]) * X[cb + u];
+        }
     }
     part[w][r] = a3;
     __syncthreads();
@@ -342,7 +361,9 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
         }
     }
     int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
-    int nw = nslot >= 8 ? CA_WAVES : (post_inv || nslot > 0 ? 4 : 1);
+    // about two batches of (block, column) pairs per wavefront
+    int nw = std::max(1, std::min(CA_WAVES, (nslot * op.nd + CA_BATCH * 2 - 1) / (CA_BATCH * 2)));
+    if (post_inv) nw = std::max(nw, 4);
     dim3 grid(nsite, nr);
     k_coarse_apply<T, S><<<grid, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld);
 }
@@ -830,15 +851,31 @@ void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s
 // coarse SAP half sweep (same algebra as the fine kernel, dense site blocks):
 // workgroup = one block, thread = (local site l, row r) for both parities.
 // ---------------------------------------------------------------------------
-template <class T, class S>
+// row r of a column-major block times v; block entries and v are loaded in
+// batches of RA_BATCH (many loads in flight, the sum still in column order)
+template <class T, class S, int RA_BATCH>
 __device__ __forceinline__ cx<T> row_apply(const cx<S>* __restrict__ A, int nd, int r, const cx<T>* v) {
     cx<T> s = czero<T>();
-    for (int c = 0; c < nd; c++) s += ccast<T>(A[(size_t)c * nd + r]) * v[c];
+    for (int c0 = 0; c0 < nd; c0 += RA_BATCH) {
+        cx<S> a[RA_BATCH];
+        cx<T> x[RA_BATCH];
+#pragma unroll
+        for (int u = 0; u < RA_BATCH; u++) {
+            const bool in = c0 + u < nd;
+            a[u] = in ? A[(size_t)(c0 + u) * nd + r] : cx<S>{S(0), S(0)};
+            x[u] = in ? v[c0 + u] : czero<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < RA_BATCH; u++)
+            if (c0 + u < nd) s += ccast<T>(a[u]) * x[u];
+    }
     return s;
 }
 
-template <class T, class S>
-__global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+// NTMAX: the workgroup size the kernel is compiled for (wider batches of
+// loads where fewer threads leave more registers per thread)
+template <class T, class S, int NTMAX>
+__global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
                              cx<T>* __restrict__ z, int mr_steps, long ld, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     b += blockIdx.y * ld;
@@ -847,6 +884,7 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
     const Geom g = op.g;
     const int nd = op.nd, bvh = g.bvh;
     const size_t nn = (size_t)nd * nd;
+    constexpr int RB = NTMAX <= 512 ? 20 : 8;
     cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // [bvh][nd] odd-site field
     cx<T>* se = so + bvh * nd;                        // even-site field
     cx<T>* tm = se + bvh * nd;                        // temporary (even)
@@ -872,7 +910,7 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
         cx<T> h = czero<T>();
         for (int k = 0; k < 8; k++) {
             size_t gy = (size_t)(1 - p) * g.vh + nbj[k];
-            h += row_apply(op.M + (gs * 9 + 1 + k) * nn, nd, r, v + gy * nd);
+            h += row_apply<T, S, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, v + gy * nd);
         }
         return h;
     };
@@ -880,7 +918,7 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
         cx<T> h = czero<T>();
         for (int k = 0; k < 8; k++) {
             if ((nbj[k] >> g.lbvh) != blk) continue;
-            h += row_apply(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (nbj[k] - base) * nd);
+            h += row_apply<T, S, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (nbj[k] - base) * nd);
         }
         return h;
     };
@@ -889,13 +927,13 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
     if (act) tm[l * nd + r] = b[ge * nd + r] - hop_glob(ge, 0, nbe, z);
     __syncthreads();
     if (act) {
-        t0 = row_apply(op.Minv + ge * nn, nd, r, tm + l * nd) - z[ge * nd + r];
+        t0 = row_apply<T, S, RB>(op.Minv + ge * nn, nd, r, tm + l * nd) - z[ge * nd + r];
         se[l * nd + r] = t0;
         so[l * nd + r] = z[go * nd + r];
     }
     __syncthreads();
     // f_o = b_o - M0 z_o - H z - H_int t0
-    if (act) rho = b[go * nd + r] - row_apply(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_glob(go, 1, nbo, z) - hop_int(go, nbo, se);
+    if (act) rho = b[go * nd + r] - row_apply<T, S, RB>(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_glob(go, 1, nbo, z) - hop_int(go, nbo, se);
     __syncthreads();
     if (act) so[l * nd + r] = rho;
     __syncthreads();
@@ -904,13 +942,13 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
         if (act) tm[l * nd + r] = hop_int(ge, nbe, so);
         __syncthreads();
         cx<T> tv = czero<T>();
-        if (act) tv = row_apply(op.Minv + ge * nn, nd, r, tm + l * nd);
+        if (act) tv = row_apply<T, S, RB>(op.Minv + ge * nn, nd, r, tm + l * nd);
         __syncthreads();
         if (act) se[l * nd + r] = tv;
         __syncthreads();
         double sr = 0, si = 0, ss = 0;
         if (act) {
-            sv = row_apply(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_int(go, nbo, se);
+            sv = row_apply<T, S, RB>(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_int(go, nbo, se);
             cx<T> d = cmulc(sv, rho);
             sr = d.re; si = d.im; ss = norm2(sv);
         }
@@ -935,7 +973,7 @@ __global__ void k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, 
     if (act) tm[l * nd + r] = hop_int(ge, nbe, so);
     __syncthreads();
     if (act) {
-        cx<T> ee = t0 - row_apply(op.Minv + ge * nn, nd, r, tm + l * nd);
+        cx<T> ee = t0 - row_apply<T, S, RB>(op.Minv + ge * nn, nd, r, tm + l * nd);
         z[ge * nd + r] += ee;
         z[go * nd + r] += eo;
     }
@@ -948,7 +986,8 @@ void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, c
     int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
     size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
     dim3 grid(nblocks, nr);
-    k_coarse_sap<T, S><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+    if (nt <= 512) k_coarse_sap<T, S, 512><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+    else k_coarse_sap<T, S, 1024><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
 }
 
 // ---------------------------------------------------------------------------

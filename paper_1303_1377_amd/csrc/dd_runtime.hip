@@ -204,6 +204,7 @@ struct dd_ctx {
     double last_setup_s = 0;
     // live kernel timing (dd_profile)
     bool prof_on = false;
+    unsigned prof_mask = 0;   // classes timed while prof_on (bit c: class c)
     bool capturing = false;      // a graph capture is in progress (no event records)
     std::vector<hipEvent_t> ev_pool;
     struct Rec { int cls; hipEvent_t a, b; double bytes; };
@@ -272,7 +273,7 @@ struct Prof {
     double bytes;
     hipEvent_t a = nullptr;
     Prof(dd_ctx* c, int k, double by = 0) : C(c), cls(k), bytes(by) {
-        if (C->prof_on && !C->capturing) {
+        if (C->prof_on && !C->capturing && ((C->prof_mask >> cls) & 1u)) {
             a = ev_get(C);
             HIPX(hipEventRecord(a, C->s));
         }
@@ -791,29 +792,32 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         }
         while (j < m) {
             const int jend = std::min(m, j + chunk);
-            for (; j < jend; j++) {
-                if (use_graphs) {
-                    // the whole step as one graph launch (captured once per (level, j, nr))
-                    const long key = ((long)l * 64 + j) * 64 + nr;
-                    auto it = graphs.find(key);
-                    if (it == graphs.end()) {
-                        hipGraph_t gr = nullptr;
-                        hipGraphExec_t ex = nullptr;
-                        HIPX(hipStreamBeginCapture(C->cap, hipStreamCaptureModeThreadLocal));
-                        C->capturing = true;
-                        arnoldi_step(j, C->cap);
-                        C->capturing = false;
-                        HIPX(hipStreamEndCapture(C->cap, &gr));
-                        hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-                        (void)hipGraphDestroy(gr);
-                        HIPX(e);
-                        it = graphs.emplace(key, ex).first;
-                    }
-                    Prof pr(C, DD_K_COARSE_STEP, 2 * by_coarse(l, 9, 2, false, k) + 2 * by_reduce(nh, j + 1, k));
-                    HIPX(hipGraphLaunch(it->second, C->s));
-                } else {
-                    arnoldi_step(j, C->s);
+            if (use_graphs) {
+                // the chunk of steps as one graph launch (captured once per
+                // (level, first step, step count, batch size)); steps past a
+                // right-hand side's convergence are no-ops on the device
+                const long key = (((long)l * 64 + j) * 64 + (jend - j)) * 64 + nr;
+                auto it = graphs.find(key);
+                if (it == graphs.end()) {
+                    hipGraph_t gr = nullptr;
+                    hipGraphExec_t ex = nullptr;
+                    HIPX(hipStreamBeginCapture(C->cap, hipStreamCaptureModeThreadLocal));
+                    C->capturing = true;
+                    for (int q = j; q < jend; q++) arnoldi_step(q, C->cap);
+                    C->capturing = false;
+                    HIPX(hipStreamEndCapture(C->cap, &gr));
+                    hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    HIPX(e);
+                    it = graphs.emplace(key, ex).first;
                 }
+                double by = 0;
+                for (int q = j; q < jend; q++) by += 2 * by_coarse(l, 9, 2, false, k) + 2 * by_reduce(nh, q + 1, k);
+                Prof pr(C, DD_K_COARSE_STEP, by);
+                HIPX(hipGraphLaunch(it->second, C->s));
+                j = jend;
+            } else {
+                for (; j < jend; j++) arnoldi_step(j, C->s);
             }
             if (read_state()) { all_stop = true; break; }
             chunk = 4;
@@ -1545,15 +1549,21 @@ dd_status dd_level_info(const dd_ctx* ctx, int level, int dims[4], int* nd) {
     return DD_OK;
 }
 
-dd_status dd_profile(dd_ctx* ctx, int enable) {
+dd_status dd_profile_classes(dd_ctx* ctx, unsigned class_mask) {
     ABI_TRY(ctx)
+    if (class_mask >> DD_K_NCLASS) fail(DD_EINVAL, "class mask names an unknown kernel class");
     sync(ctx);
-    ctx->prof_on = enable != 0;
-    if (enable) {
+    ctx->prof_mask = class_mask;
+    ctx->prof_on = class_mask != 0;
+    if (class_mask) {
         for (int k = 0; k < DD_K_NCLASS; k++) { ctx->prof_n[k] = 0; ctx->prof_ms[k] = 0; ctx->prof_bytes[k] = 0; }
     }
     return DD_OK;
     ABI_END(ctx)
+}
+
+dd_status dd_profile(dd_ctx* ctx, int enable) {
+    return dd_profile_classes(ctx, enable ? (1u << DD_K_NCLASS) - 1u : 0u);
 }
 
 dd_status dd_profile_read(dd_ctx* ctx, int cls, long* launches, double* total_ms, double* total_bytes) {
