@@ -13,6 +13,7 @@ static constexpr int MAXM = 32;        // basis vectors handled per launch
 static constexpr int RED_CHUNKS = 1024;  // chunks a reduced vector is cut into
 static constexpr int RED_NT = 256;
 static constexpr int UN_BATCH = 16;    // basis vectors loaded together in k_update_norm
+static_assert(RED_NT % MAXM == 0, "k_update_norm splits its threads into groups of MAXM");
 
 size_t reduce_work_size(int m, int nr) {
     (void)m;
@@ -157,16 +158,26 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
     if (!mk.on(r)) return;
     __shared__ double sh[RED_NT / 64];
     __shared__ cx<T> hh[MAXM];
-    if (threadIdx.x < m) {
-        cx<double> hv;
-        if (hpart) {
-            hv = czero<double>();
-            for (int q = 0; q < nc; q++) hv += hpart[((size_t)r * nc + q) * m + threadIdx.x];
-            if (c == 0) hout[(size_t)r * hstride + threadIdx.x] = hv;
-        } else {
-            hv = h[(size_t)r * hstride + threadIdx.x];
+    if (hpart) {
+        // inner product i = sum over the chunk partials: thread (g, i) adds the
+        // chunks c = g mod HG, then thread i adds the HG group sums (fixed order)
+        constexpr int HG = RED_NT / MAXM;
+        __shared__ cx<double> hg[HG][MAXM];
+        const int i = threadIdx.x % MAXM, gq = threadIdx.x / MAXM;
+        if (i < m) {
+            cx<double> hv = czero<double>();
+            for (int q = gq; q < nc; q += HG) hv += hpart[((size_t)r * nc + q) * m + i];
+            hg[gq][i] = hv;
         }
-        hh[threadIdx.x] = ccast<T>(hv);
+        __syncthreads();
+        if (threadIdx.x < m) {
+            cx<double> hv = hg[0][threadIdx.x];
+            for (int q = 1; q < HG; q++) hv += hg[q][threadIdx.x];
+            if (c == 0) hout[(size_t)r * hstride + threadIdx.x] = hv;
+            hh[threadIdx.x] = ccast<T>(hv);
+        }
+    } else if (threadIdx.x < m) {
+        hh[threadIdx.x] = ccast<T>(h[(size_t)r * hstride + threadIdx.x]);
     }
     __syncthreads();
     const cx<T>* Vr = V + r * ldr;
@@ -275,8 +286,11 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
 // products and the previous rotations are first staged in LDS by many
 // threads at once, then one thread runs the rotation chain with the running
 // entry in registers (the global-memory form waits on one load per rotation)
-__device__ void gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2) {
+// Returns, in every thread, the factor that normalises the new basis vector
+// (0 when this RHS stopped at this step: the vector is then left as it is).
+__device__ double gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2) {
     __shared__ cx<double> hs[33], css[32], sns[32];
+    __shared__ double sc_s;
     const int t = threadIdx.x;
     if (t <= j) hs[t] = h[t];
     if (t < j) {
@@ -284,36 +298,40 @@ __device__ void gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2) 
         sns[t] = st->sn[t];
     }
     __syncthreads();
-    if (t != 0) return;
-    cx<double>* col = st->H + (size_t)j * 33;
-    const double hn = sqrt(hn2);
-    cx<double> a = hs[0];
-    for (int i = 0; i < j; i++) {  // previous rotations; col[i] is final after rotation i
-        const cx<double> b = hs[i + 1];
-        col[i] = conj(css[i]) * a + conj(sns[i]) * b;
-        a = -(sns[i] * a) + css[i] * b;
+    if (t == 0) {
+        cx<double>* col = st->H + (size_t)j * 33;
+        const double hn = sqrt(hn2);
+        cx<double> a = hs[0];
+        for (int i = 0; i < j; i++) {  // previous rotations; col[i] is final after rotation i
+            const cx<double> b = hs[i + 1];
+            col[i] = conj(css[i]) * a + conj(sns[i]) * b;
+            a = -(sns[i] * a) + css[i] * b;
+        }
+        const cx<double> b = cx<double>{hn, 0.0};
+        const double den = sqrt(norm2(a) + norm2(b));
+        cx<double> c, s;
+        if (den == 0.0) { c = cx<double>{1.0, 0.0}; s = czero<double>(); }
+        else { c = cx<double>{a.re / den, a.im / den}; s = cx<double>{b.re / den, b.im / den}; }
+        st->cs[j] = c;
+        st->sn[j] = s;
+        col[j] = conj(c) * a + conj(s) * b;
+        col[j + 1] = czero<double>();
+        const cx<double> gj = st->g[j];
+        st->g[j + 1] = -(s * gj);
+        st->g[j] = conj(c) * gj;
+        st->its += 1;
+        st->j = j + 1;
+        const double resid = sqrt(norm2(st->g[j + 1]));
+        int stop = 0;
+        if (st->fixed > 0) stop = st->its >= st->fixed;
+        else stop = (resid <= st->tol_abs) || (st->its >= st->maxit);
+        if (hn == 0.0) stop = 1;
+        st->stop = stop;
+        st->scale = (hn > 0) ? 1.0 / hn : 0.0;
+        sc_s = stop ? 0.0 : st->scale;
     }
-    const cx<double> b = cx<double>{hn, 0.0};
-    const double den = sqrt(norm2(a) + norm2(b));
-    cx<double> c, s;
-    if (den == 0.0) { c = cx<double>{1.0, 0.0}; s = czero<double>(); }
-    else { c = cx<double>{a.re / den, a.im / den}; s = cx<double>{b.re / den, b.im / den}; }
-    st->cs[j] = c;
-    st->sn[j] = s;
-    col[j] = conj(c) * a + conj(s) * b;
-    col[j + 1] = czero<double>();
-    const cx<double> gj = st->g[j];
-    st->g[j + 1] = -(s * gj);
-    st->g[j] = conj(c) * gj;
-    st->its += 1;
-    st->j = j + 1;
-    const double resid = sqrt(norm2(st->g[j + 1]));
-    int stop = 0;
-    if (st->fixed > 0) stop = st->its >= st->fixed;
-    else stop = (resid <= st->tol_abs) || (st->its >= st->maxit);
-    if (hn == 0.0) stop = 1;
-    st->stop = stop;
-    st->scale = (hn > 0) ? 1.0 / hn : 0.0;
+    __syncthreads();
+    return sc_s;
 }
 
 __global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
@@ -324,9 +342,15 @@ __global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ re
 }
 
 // ||w||^2 from the chunk partials (fixed order) and the Givens update of
-// column j, one workgroup per RHS: the last two kernels of an Arnoldi step in one
+// column j, one workgroup per RHS: the last kernels of an Arnoldi step in one.
+// With nscale > 0 the workgroup also normalises w (its first nscale entries):
+// short coarse vectors, where a separate launch would cost more than the work.
+static constexpr long FUSE_SCALE_MAX = 16384;
+
+template <class T>
 __global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>* __restrict__ npart, cx<double>* res,
-                                                        int rstride, GmDev* st0, int j) {
+                                                        int rstride, GmDev* st0, int j, cx<T>* __restrict__ w,
+                                                        long ldw, long nscale) {
     const int r = blockIdx.x;
     GmDev* st = st0 + r;
     if (st->stop) return;
@@ -336,7 +360,25 @@ __global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>
     acc = block_sum256(acc, sh);
     cx<double>* h = res + (size_t)r * rstride;
     if (threadIdx.x == 0) h[33] = cx<double>{acc, 0.0};
-    gm_column_wg(st, j, h, acc);
+    const double sc = gm_column_wg(st, j, h, acc);
+    if (nscale > 0 && sc != 0.0) {
+        cx<T>* wr = w + r * ldw;
+        const T f = T(sc);
+        constexpr int B = 8;   // entries per thread in flight
+        for (long e0 = threadIdx.x; e0 < nscale; e0 += (long)B * RED_NT) {
+            cx<T> v[B];
+#pragma unroll
+            for (int u = 0; u < B; u++) {
+                const long e = e0 + (long)u * RED_NT;
+                v[u] = (e < nscale) ? wr[e] : czero<T>();
+            }
+#pragma unroll
+            for (int u = 0; u < B; u++) {
+                const long e = e0 + (long)u * RED_NT;
+                if (e < nscale) wr[e] = f * v[u];
+            }
+        }
+    }
 }
 
 __global__ void k_gm_solve(GmDev* st0) {
@@ -433,7 +475,10 @@ void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, c
     dim3 grid(nc, rb.nr);
     k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
                                              npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
-    k_norm_givens<<<rb.nr, RED_NT, 0, s>>>(nc, npart_of(work, rb.nr), res, rb.ostride, st, j);
+    const bool fuse = n <= FUSE_SCALE_MAX;
+    k_norm_givens<T><<<rb.nr, RED_NT, 0, s>>>(nc, npart_of(work, rb.nr), res, rb.ostride, st, j, w, rb.ldw,
+                                              fuse ? n : 0);
+    if (!fuse) vec_scale_dev<T>(n, st, w, s, false, rb.nr, rb.ldw);
 }
 
 template <class T, class X>

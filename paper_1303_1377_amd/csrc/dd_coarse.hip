@@ -9,6 +9,7 @@
 // Vectors are [parity][layout index][nd] (a site's unknowns contiguous);
 // operator blocks are column-major so that the thread owning row r reads
 // consecutive addresses across the wavefront.
+#include <stdexcept>
 #include <type_traits>
 
 #include "dd_kernels.h"
@@ -19,17 +20,23 @@ static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // out(x) = [post Minv] ( self(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
-// One workgroup per site.  The site's input vectors (self and 8 neighbours,
-// hop sign folded in) are staged in LDS; the (block, column) pairs of its dense
-// blocks are then split evenly over the wavefronts and lane r accumulates row
-// r, so every load of a column-major block is coalesced.  Each wavefront
-// issues its block loads in batches of CA_BATCH before using them, which keeps
-// that many loads in flight per lane: on small coarse lattices (a few hundred
-// sites) the kernel is bound by memory latency, not bandwidth.  Partial rows
-// meet in LDS.
+// One workgroup per site.  The site's blocks used here lie back to back in
+// memory (self, then the 8 hops, each column-major), so (block, column) pair
+// q is column q of one nd-row panel.  The pairs are split evenly over the
+// wavefronts and lane r accumulates row r: every load is coalesced.  On small
+// coarse lattices (a few hundred sites) the kernel is bound by memory latency,
+// not bandwidth, so each lane issues the loads of its first pairs (and of its
+// columns of the self-block inverse) before the site's input vectors
+// (hop sign folded in) are staged in LDS: block entries and inputs are in
+// flight together.  Partial rows meet in LDS.
 // ---------------------------------------------------------------------------
-static constexpr int CA_WAVES = 16;
-static constexpr int CA_BATCH = 12;
+static constexpr int CA_WAVES = 12;
+// block entries and inverse-block columns a lane loads at once (fewer in
+// FP64, where they take twice the registers)
+template <class S> struct CaPre {
+    static constexpr int N = sizeof(S) > 4 ? 24 : 30;
+    static constexpr int INV = sizeof(S) > 4 ? 4 : 8;
+};
 
 template <class T, class S>
 __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> op, int par, int self_mode,
@@ -45,9 +52,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     }
     __shared__ cx<T> part[CA_WAVES][64];
     __shared__ cx<T> X[9 * 64];            // staged inputs [slot][nd] (nd <= 64)
-    __shared__ const cx<S>* mat[10];       // one spare entry for the batched loop's overrun
     __shared__ const cx<T>* vin[9];
-    __shared__ int nslot_s;
     const Geom g = op.g;
     const int nd = op.nd;
     const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, r = threadIdx.x & 63;
@@ -57,81 +62,84 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     const size_t gs = (size_t)p * g.vh + i;
     const size_t nn = (size_t)nd * nd;
     const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    // first block of the panel: the self block, its inverse, or the first hop
+    const cx<S>* panel = (self_mode == CS_SELFINV) ? op.Minv + gs * nn : op.M + (gs * 9 + 1 - nself) * nn;
     if (threadIdx.x == 0) {
         int ns = 0;
-        if (self_mode == CS_SELF) { mat[ns] = op.M + gs * 9 * nn; vin[ns] = in1 + gs * nd; ns++; }
-        else if (self_mode == CS_SELFINV) { mat[ns] = op.Minv + gs * nn; vin[ns] = in1 + gs * nd; ns++; }
+        if (nself) { vin[ns] = in1 + gs * nd; ns++; }
         if (hop_sign != 0) {
             int x[4];
             cb_coords(g, p, i, x);
             for (int k = 0; k < 8; k++) {
                 int y[4];
                 nb_coords(g, x, k, y);
-                const size_t gy = (size_t)(1 - p) * g.vh + cb_index(g, y);
-                mat[ns] = op.M + (gs * 9 + 1 + k) * nn;
-                vin[ns] = in2 + gy * nd;
+                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
                 ns++;
             }
         }
-        mat[ns] = mat[0];
-        nslot_s = ns;
     }
-    __syncthreads();
-    const int ns = nslot_s;
+    const int ns = nself + (hop_sign != 0 ? 8 : 0);
     const int Q = ns * nd;
-    for (int e = threadIdx.x; e < Q; e += blockDim.x) {
-        const int sl = e / nd;
-        const cx<T> v = vin[sl][e - sl * nd];
-        X[e] = (sl >= nself && hop_sign < 0) ? -v : v;
-    }
-    __syncthreads();
     const int per = (Q + nw - 1) / nw;
     const int q0 = w * per, q1 = min(Q, q0 + per);
+    const bool row = r < nd;
+    const cx<S>* A = panel + r;
+    constexpr int CA_PRE = CaPre<S>::N;
+    cx<S> a[CA_PRE];
+    auto load_pairs = [&](int qb) {
+#pragma unroll
+        for (int u = 0; u < CA_PRE; u++)
+            a[u] = (row && qb + u < q1) ? A[(size_t)(qb + u) * nd] : cx<S>{S(0), S(0)};
+    };
+    load_pairs(q0);
+    const int per2 = (nd + nw - 1) / nw;
+    const int c0 = w * per2, c1 = min(nd, c0 + per2);
+    const cx<S>* Ainv = op.Minv + gs * nn + r;
+    constexpr int CA_INV = CaPre<S>::INV;
+    cx<S> b[CA_INV];
+    auto load_inv = [&](int cb) {
+#pragma unroll
+        for (int u = 0; u < CA_INV; u++)
+            b[u] = (row && cb + u < c1) ? Ainv[(size_t)(cb + u) * nd] : cx<S>{S(0), S(0)};
+    };
+    if (post_inv) load_inv(c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < Q; e += blockDim.x) {
+        const int s2 = e / nd;
+        const cx<T> v = vin[s2][e - s2 * nd];
+        X[e] = (s2 >= nself && hop_sign < 0) ? -v : v;
+    }
+    __syncthreads();
     cx<T> acc = czero<T>();
-    if (r < nd && q0 < q1) {
-        int sl = q0 / nd, c = q0 - sl * nd;   // (slot, column) of pair q, advanced incrementally
-        for (int qb = q0; qb < q1; qb += CA_BATCH) {
-            cx<S> a[CA_BATCH];
+    for (int qb = q0; qb < q1; qb += CA_PRE) {
+        if (qb != q0) load_pairs(qb);
 #pragma unroll
-            for (int u = 0; u < CA_BATCH; u++) {
-                a[u] = (qb + u < q1) ? mat[min(sl, 9)][(size_t)c * nd + r] : cx<S>{S(0), S(0)};
-                if (++c == nd) { c = 0; sl++; }
-            }
-#pragma unroll
-            for (int u = 0; u < CA_BATCH; u++)
-                if (qb + u < q1) acc += ccast<T>(a[u]) * X[qb + u];
-        }
+        for (int u = 0; u < CA_PRE; u++)
+            if (qb + u < q1) acc += ccast<T>(a[u]) * X[qb + u];
     }
     part[w][r] = acc;
     __syncthreads();
     cx<T> tot = czero<T>();
-    if (w == 0 && r < nd) {
+    if (w == 0 && row) {
         tot = (self_mode == CS_IDENT) ? in1[gs * nd + r] : czero<T>();
         for (int q = 0; q < nw; q++) tot += part[q][r];
     }
     if (!post_inv) {
-        if (w == 0 && r < nd) out[gs * nd + r] = tot;
+        if (w == 0 && row) out[gs * nd + r] = tot;
         return;
     }
     if (w == 0) X[r] = tot;
     __syncthreads();
-    const int per2 = (nd + nw - 1) / nw;
-    const int c0 = w * per2, c1 = min(nd, c0 + per2);
     cx<T> a3 = czero<T>();
-    if (r < nd && c0 < c1) {
-        const cx<S>* A = op.Minv + gs * nn + r;
-        cx<S> a[CA_BATCH];
-        for (int cb = c0; cb < c1; cb += CA_BATCH) {
+    for (int cb = c0; cb < c1; cb += CA_INV) {
+        if (cb != c0) load_inv(cb);
 #pragma unroll
-            for (int u = 0; u < CA_BATCH; u++) a[u] = (cb + u < c1) ? A[(size_t)(cb + u) * nd] : cx<S>{S(0), S(0)};
-#pragma unroll
-            for (int u = 0; u < CA_BATCH; u++)
-                if (cb + u < c1) a3 += ccast<T>(a[u]) * X[cb + u];
-        }
+        for (int u = 0; u < CA_INV; u++)
+            if (cb + u < c1) a3 += ccast<T>(b[u]) * X[cb + u];
     }
     part[w][r] = a3;
     __syncthreads();
-    if (w == 0 && r < nd) {
+    if (w == 0 && row) {
         cx<T> s2 = czero<T>();
         for (int q = 0; q < nw; q++) s2 += part[q][r];
         out[gs * nd + r] = s2;
@@ -360,10 +368,15 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
             return;
         }
     }
+    // the vector-unit kernel reads the site's blocks as one panel: the self
+    // inverse is not stored next to the hop blocks
+    if (self_mode == CS_SELFINV && hop_sign != 0)
+        throw std::invalid_argument("coarse_apply: the self-block inverse combines with no hop term");
     int nslot = ((self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0) + (hop_sign != 0 ? 8 : 0);
-    // about two batches of (block, column) pairs per wavefront
-    int nw = std::max(1, std::min(CA_WAVES, (nslot * op.nd + CA_BATCH * 2 - 1) / (CA_BATCH * 2)));
-    if (post_inv) nw = std::max(nw, 4);
+    // at most one prefetch batch of (block, column) pairs per wavefront where the
+    // workgroup size allows
+    int nw = std::max(1, std::min(CA_WAVES, (nslot * op.nd + CaPre<S>::N - 1) / CaPre<S>::N));
+    if (post_inv) nw = std::max(nw, std::min(CA_WAVES, (op.nd + CaPre<S>::INV - 1) / CaPre<S>::INV));
     dim3 grid(nsite, nr);
     k_coarse_apply<T, S><<<grid, 64 * nw, 0, s>>>(op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld);
 }

@@ -240,7 +240,8 @@ template <class T>
 void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
                           hipStream_t s, RedBatch rb);
 // the same update and norm, then the Givens update of column j in the same
-// kernel as the final norm sum (what gm_column does), skipping stopped RHS
+// kernel as the final norm sum (what gm_column does), skipping stopped RHS,
+// and w scaled to the next basis vector (what vec_scale_dev does)
 template <class T>
 void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
                             hipStream_t s, RedBatch rb, GmDev* st, int j);

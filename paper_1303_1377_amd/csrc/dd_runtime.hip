@@ -746,7 +746,6 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
         vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, sq, rb);
         vec_update_norm_givens<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb, st, j);
-        vec_scale_dev<T>(nh, st, odd(w), sq, false, nr, nfull);
     };
     // graphs need a capture stream; live kernel timing brackets single launches
     const bool use_graphs = (C->sched & SCHED_GRAPH) && C->cap;
