@@ -857,7 +857,12 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
                 v[c] -= alpha * w[c];
             }
         }
-        if (od) lds_store(O, bvh, l, (it + 1 < mr_steps) ? v : pv);
+        // (two calls, not a pointer select: selecting between the arrays would
+        // force both out of registers)
+        if (od) {
+            if (it + 1 < mr_steps) lds_store(O, bvh, l, v);
+            else lds_store(O, bvh, l, pv);
+        }
         __syncthreads();
     }
     if (mr_steps == 0) {
@@ -958,7 +963,11 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, co
         load_spinor(in, m.f.vh, p, i, v);
     }
     const int vh = m.f.vh;
-    for (int k = 0; k < N; k++) {
+    // this workgroup's test vectors: [k0, k1) (the grid's z index splits them
+    // when there are few coarse sites, so that enough workgroups stream P)
+    const int kper = (N + gridDim.z - 1) / gridDim.z;
+    const int k0 = blockIdx.z * kper, k1 = min(N, k0 + kper);
+    for (int k = k0; k < k1; k++) {
         cx<double> d0 = czero<double>(), d1 = czero<double>();
         if (act) {
             cx<T> q[12];
@@ -973,7 +982,9 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, co
         if (lane == 0) { red[w * 2 * N + k] = d0; red[w * 2 * N + N + k] = d1; }
     }
     __syncthreads();
-    for (int q = t; q < 2 * N; q += blockDim.x) {
+    const int kn = max(0, k1 - k0);
+    for (int e = t; e < 2 * kn; e += blockDim.x) {
+        const int q = (e < kn) ? k0 + e : N + k0 + (e - kn);
         cx<double> s = czero<double>();
         for (int ww = 0; ww < nw; ww++) s += red[ww * 2 * N + q];
         out[(size_t)gc * 2 * N + q] = ccast<T>(s);
@@ -1014,7 +1025,9 @@ void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T
                    long ldi, long ldo, Mask mk) {
     int nt = ((m.asz + 63) / 64) * 64;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
-    dim3 grid(2 * m.c.vh, nr);
+    // split the test vectors over workgroups until about 1024 stream P
+    const int ks = std::max(1, std::min(N, (1024 + 2 * m.c.vh - 1) / (2 * m.c.vh)));
+    dim3 grid(2 * m.c.vh, nr, ks);
     k_restrict_fine<T, S><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
 template <class T, class S>
