@@ -712,8 +712,21 @@ __device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12
     herm6_apply(m + 36, v + 6, out + 6);
 }
 
-template <class T, class S>
-__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __restrict__ blocks,
+// value of the partner lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
+__device__ __forceinline__ float pair_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// MINW: waves per SIMD the register allocation must allow (2 for FP32 fields,
+// so that two workgroups share a CU; FP64 needs the whole register file)
+template <class T, class S, int MINW = (sizeof(T) > 4 ? 1 : 2)>
+__global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const int* __restrict__ blocks,
                                                   const cx<T>* __restrict__ b0, cx<T>* __restrict__ z0, int mr_steps,
                                                   int nr, long ld, Mask mk) {
     extern __shared__ char smem_raw[];
@@ -726,15 +739,20 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
     cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw);  // [6][ltot] first two rows of internal links
     cx<T>* E = L + 6 * ltot;                         // even field [12][bvh]
     cx<T>* O = E + 12 * bvh;                         // odd field [12][bvh]
-    int* tab = reinterpret_cast<int*>(O + 12 * bvh);  // [8][2 bvh] packed hop table
+    int* tab = reinterpret_cast<int*>(O + 12 * bvh);  // [8][2 bvh] packed hop table, column p bvh + l
     double* red = reinterpret_cast<double*>(tab + 8 * ntab);
     const int blk = blocks[(op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x];
     const int base = blk << g.lbvh;
+    // lanes 2l (even site l) and 2l + 1 (odd site l) are partners: when only one
+    // parity's sites are updated, each of the two computes half of the hops of
+    // that parity's site l (lane p: hops 4p .. 4p+3) and the halves meet
+    // through one lane swap, so no lane idles in the hopping parts
     const int t = threadIdx.x;
     const bool act = t < 2 * bvh;
-    const int p = (t >= bvh) ? 1 : 0;
-    const int l = act ? t - p * bvh : 0;
+    const int p = t & 1;
+    const int l = act ? t >> 1 : 0;
     const int i = base + l;
+    const int sidx = p * bvh + l;
     const bool ev = act && p == 0, od = act && p == 1;
     int x[4];
     cb_coords(g, p, i, x);
@@ -754,7 +772,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
                 if (k >= 4) lo[mu] = (lc[mu] == 0) ? g.b[mu] - 1 : lc[mu] - 1;
                 slot = link_idx(lm, mu, lo);
             }
-            tab[k * ntab + t] = (slot >= 0) ? ((slot << 8) | (j - base)) : -1;
+            tab[k * ntab + sidx] = (slot >= 0) ? ((slot << 8) | (j - base)) : -1;
             // own forward link inside the block -> LDS (two rows)
             if (k < 4 && slot >= 0) {
                 const cx<S>* src = op.U + (size_t)(p * 4 + mu) * 9 * g.vh + i;
@@ -768,17 +786,31 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
     clover_regs(p == 0 ? op.clovinv : op.clov, g.vh, p, i, m);
     __syncthreads();
     const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
+    // hopping sum of the block-internal hops of site (P, l) over the field buf,
+    // in both partner lanes
+    auto pair_hops = [&](int P, const cx<T>* buf, cx<T> a[12]) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) a[c] = czero<T>();
+#pragma unroll 1
+        for (int k = 4 * p; k < 4 * p + 4; k++)
+            sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, P * bvh + l, P, i, x, base, buf, nullptr, a);
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            a[c].re += pair_swap(a[c].re);
+            a[c].im += pair_swap(a[c].im);
+        }
+    };
     for (int rhs = 0; rhs < nr; rhs++) {
     if (!mk.on(rhs)) continue;
     const cx<T>* __restrict__ b = b0 + rhs * ld;
     cx<T>* __restrict__ z = z0 + rhs * ld;
-    cx<T> acc[12], v[12], w[12], pv[12];  // pv: t0 (even threads) or e_o (odd threads)
-    // ---- residual on the block ----
+    cx<T> acc[12], v[12], w[12], pv[12];  // pv: t0 (even lanes) or e_o (odd lanes)
+    // ---- residual on the block: every lane its own site, all 8 hops ----
     if (act) {
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, t, p, i, x, base, nullptr, z, acc);
+        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, sidx, p, i, x, base, nullptr, z, acc);
         load_spinor(b, g.vh, p, i, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];  // b - H z
@@ -796,16 +828,15 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
         }
     }
     __syncthreads();
-    if (od) {
+    if (act) {
+        pair_hops(1, E, acc);
+        if (od) {
+            lds_load(O, bvh, l, v);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-#pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
-        lds_load(O, bvh, l, v);
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-            v[c] += T(0.5) * acc[c];  // rho = f_o
-            pv[c] = czero<T>();       // e_o = 0
+            for (int c = 0; c < 12; c++) {
+                v[c] += T(0.5) * acc[c];  // rho = f_o
+                pv[c] = czero<T>();       // e_o = 0
+            }
         }
     }
     __syncthreads();
@@ -813,33 +844,31 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
     __syncthreads();
     for (int it = 0; it < mr_steps; it++) {
         // even: t = A^{-1} (H_int rho), H = -1/2 hopsum
-        if (ev) {
+        if (act) {
+            pair_hops(0, O, acc);
+            if (ev) {
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-#pragma unroll 1
-            for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
-#pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
-            clover_reg_apply(m, acc, w);
+                for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
+                clover_reg_apply(m, acc, w);
+            }
         }
         __syncthreads();
         if (ev) lds_store(E, bvh, l, w);
         __syncthreads();
         // odd: s = A rho - H_int t
         double sr = 0, si = 0, ss = 0;
-        if (od) {
+        if (act) {
+            pair_hops(1, E, acc);
+            if (od) {
+                clover_reg_apply(m, v, w);
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-#pragma unroll 1
-            for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 1, i, x, base, E, nullptr, acc);
-            clover_reg_apply(m, v, w);
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                w[c] += T(0.5) * acc[c];
-                cx<T> d = cmulc(w[c], v[c]);
-                sr += d.re;
-                si += d.im;
-                ss += norm2(w[c]);
+                for (int c = 0; c < 12; c++) {
+                    w[c] += T(0.5) * acc[c];
+                    cx<T> d = cmulc(w[c], v[c]);
+                    sr += d.re;
+                    si += d.im;
+                    ss += norm2(w[c]);
+                }
             }
         }
         sr = wave_sum(sr);
@@ -870,23 +899,22 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T, S> op, const int* __
         __syncthreads();
     }
     // ---- back-substitution and update ----
-    if (ev) {
+    if (act) {
+        pair_hops(0, O, acc);
+        if (ev) {
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] = czero<T>();
-#pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, t, 0, i, x, base, O, nullptr, acc);
+            for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
+            clover_reg_apply(m, acc, w);
+            load_spinor(z, g.vh, 0, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
-        clover_reg_apply(m, acc, w);
-        load_spinor(z, g.vh, 0, i, acc);
+            for (int c = 0; c < 12; c++) acc[c] += pv[c] + w[c];
+            store_spinor(z, g.vh, 0, i, acc);
+        } else {
+            load_spinor(z, g.vh, 1, i, acc);
 #pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += pv[c] + w[c];
-        store_spinor(z, g.vh, 0, i, acc);
-    } else if (od) {
-        load_spinor(z, g.vh, 1, i, acc);
-#pragma unroll
-        for (int c = 0; c < 12; c++) acc[c] += pv[c];
-        store_spinor(z, g.vh, 1, i, acc);
+            for (int c = 0; c < 12; c++) acc[c] += pv[c];
+            store_spinor(z, g.vh, 1, i, acc);
+        }
     }
     __syncthreads();  // the block fields are reused by the next right-hand side
     }
