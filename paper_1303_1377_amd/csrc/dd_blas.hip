@@ -245,35 +245,41 @@ void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* 
 // ---- device-resident GMRES bookkeeping (one state per right-hand side) -----
 __global__ void k_gm_start(GmDev* st0, const cx<double>* res, int rstride, double tol, int first, int m, int maxit,
                            int fixed, Mask mk) {
-    if (threadIdx.x != 0) return;
     GmDev* st = st0 + blockIdx.x;
-    if (first) {
-        st->its = 0;
-        st->stop = 0;
-        st->m = m;
-        st->maxit = maxit;
-        st->fixed = fixed;
+    __shared__ int reset_s;
+    __shared__ double beta_s;
+    if (threadIdx.x == 0) {
+        reset_s = 0;
+        if (first) {
+            st->its = 0;
+            st->stop = 0;
+            st->m = m;
+            st->maxit = maxit;
+            st->fixed = fixed;
+        }
+        // a right-hand side outside the batch's mask, or one that stopped in an
+        // earlier cycle, contributes nothing to this cycle (j = 0)
+        if (!mk.on(blockIdx.x)) {
+            st->stop = 1;
+            st->j = 0;
+            st->scale = 0.0;
+        } else if (!first && st->stop) {
+            st->j = 0;
+        } else {
+            const double beta = sqrt(res[(size_t)blockIdx.x * rstride].re);
+            if (first) st->tol_abs = tol * beta;
+            st->j = 0;
+            st->scale = (beta > 0) ? 1.0 / beta : 0.0;
+            if (beta == 0.0) st->stop = 1;
+            beta_s = beta;
+            reset_s = 1;
+        }
     }
-    // a right-hand side outside the batch's mask, or one that stopped in an
-    // earlier cycle, contributes nothing to this cycle (j = 0)
-    if (!mk.on(blockIdx.x)) {
-        st->stop = 1;
-        st->j = 0;
-        st->scale = 0.0;
-        return;
-    }
-    if (!first && st->stop) {
-        st->j = 0;
-        return;
-    }
-    const double beta = sqrt(res[(size_t)blockIdx.x * rstride].re);
-    if (first) st->tol_abs = tol * beta;
-    for (int i = 0; i < 33; i++) st->g[i] = czero<double>();
-    for (int i = 0; i < 33 * 32; i++) st->H[i] = czero<double>();
-    st->g[0] = cx<double>{beta, 0.0};
-    st->j = 0;
-    st->scale = (beta > 0) ? 1.0 / beta : 0.0;
-    if (beta == 0.0) st->stop = 1;
+    __syncthreads();
+    if (!reset_s) return;
+    // cleared by the whole workgroup (one thread would wait on a thousand stores)
+    for (int e = threadIdx.x; e < 33 * 32; e += blockDim.x) st->H[e] = czero<double>();
+    for (int e = threadIdx.x; e < 33; e += blockDim.x) st->g[e] = (e == 0) ? cx<double>{beta_s, 0.0} : czero<double>();
 }
 
 __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
@@ -381,15 +387,23 @@ __global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>
     }
 }
 
+// back substitution R y = g with the rotated Hessenberg R (k x k upper
+// triangle), by columns: once y_i is known every thread r < i removes
+// R_ri y_i from its g_r.  R and g are staged in LDS first (at least 32 threads).
 __global__ void k_gm_solve(GmDev* st0) {
-    if (threadIdx.x != 0) return;
     GmDev* st = st0 + blockIdx.x;
-    int k = st->j;
+    __shared__ cx<double> Rs[32 * 33], gsh[33], ys[32];
+    const int k = st->j, t = threadIdx.x;
+    for (int e = t; e < k * 33; e += blockDim.x) Rs[e] = st->H[e];
+    for (int e = t; e < k; e += blockDim.x) gsh[e] = st->g[e];
+    __syncthreads();
     for (int i = k - 1; i >= 0; i--) {
-        cx<double> sacc = st->g[i];
-        for (int q = i + 1; q < k; q++) sacc -= st->H[(size_t)q * 33 + i] * st->y[q];
-        st->y[i] = cdiv(sacc, st->H[(size_t)i * 33 + i]);
+        if (t == 0) ys[i] = cdiv(gsh[i], Rs[i * 33 + i]);
+        __syncthreads();
+        if (t < i) gsh[t] -= Rs[i * 33 + t] * ys[i];
+        __syncthreads();
     }
+    for (int e = t; e < k; e += blockDim.x) st->y[e] = ys[e];
 }
 
 void gm_start(GmDev* st, const cx<double>* res, int rstride, double tol, int first, int m, int maxit, int fixed,

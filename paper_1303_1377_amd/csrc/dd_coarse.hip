@@ -356,6 +356,148 @@ static size_t mfma_lds_bytes(int nd) {
     return 2 * sizeof(S) * 9 * (size_t)ndk * 16;
 }
 
+// ---------------------------------------------------------------------------
+// The same stencil split by rows: workgroup = (site, chunk of RC rows) with RC
+// rows of a block column making one 128-byte line, so a small coarse lattice
+// still spreads over every CU.  Lane (rl, cg) of a wavefront accumulates row
+// rl of the chunk over the columns q = cg, cg + CG, ... of the site's panel
+// (self block, then the 8 hop blocks, or the 8 folded blocks B_k); the column
+// groups meet through lane shuffles and the wavefronts in LDS.  No post
+// multiplication: the folded blocks carry the self inverse where it is needed.
+// ---------------------------------------------------------------------------
+template <class T, class S, int RC>
+__global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par, int self_mode,
+                                                     const cx<T>* __restrict__ in1, int hop_sign, int fold,
+                                                     const cx<T>* in2, cx<T>* out, Mask mk, long ld) {
+    constexpr int CG = 64 / RC;          // column groups per wavefront
+    constexpr int PF = (CG >= 4) ? 12 * (8 / CG) : 24;   // block entries a lane loads at once
+    if (!mk.on(blockIdx.y)) return;
+    {
+        const long off = blockIdx.y * ld;
+        if (in1) in1 += off;
+        if (in2) in2 += off;
+        out += off;
+    }
+    __shared__ cx<T> X[9 * 64];          // staged inputs [slot][nd] (nd <= 64), hop sign folded in
+    __shared__ cx<T> part[4][RC];
+    __shared__ const cx<T>* vin[9];
+    const Geom g = op.g;
+    const int nd = op.nd;
+    const int nrc = (nd + RC - 1) / RC;
+    const int site = blockIdx.x / nrc, rc = blockIdx.x - site * nrc;
+    int p, i;
+    if (par < 0) { p = site >= g.vh; i = site - p * g.vh; }
+    else { p = par; i = site; }
+    const size_t gs = (size_t)p * g.vh + i;
+    const size_t nn = (size_t)nd * nd;
+    const int nself = (self_mode == CS_SELF) ? 1 : 0;
+    const cx<S>* panel = fold ? op.B + (size_t)i * 8 * nn : op.M + (gs * 9 + 1 - nself) * nn;
+    if (threadIdx.x == 0) {
+        int ns = 0;
+        if (nself) { vin[ns] = in1 + gs * nd; ns++; }
+        if (hop_sign != 0) {
+            int x[4];
+            cb_coords(g, p, i, x);
+            for (int k = 0; k < 8; k++) {
+                int y[4];
+                nb_coords(g, x, k, y);
+                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
+                ns++;
+            }
+        }
+    }
+    const int ns = nself + (hop_sign != 0 ? 8 : 0);
+    const int Q = ns * nd;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    const int rl = lane % RC, cg = lane / RC;
+    const int row = rc * RC + rl;
+    const bool rok = row < nd;
+    const int qs = w * CG + cg, qstep = nw * CG;
+    const cx<S>* A = panel + (rok ? row : 0);
+    cx<S> a[PF];
+    auto load = [&](int qb) {
+#pragma unroll
+        for (int u = 0; u < PF; u++) {
+            const int q = qb + u * qstep;
+            a[u] = (rok && q < Q) ? A[(size_t)q * nd] : cx<S>{S(0), S(0)};
+        }
+    };
+    load(qs);   // in flight while the inputs are staged
+    __syncthreads();
+    for (int e = t; e < Q; e += blockDim.x) {
+        const int s2 = e / nd;
+        const cx<T> v = vin[s2][e - s2 * nd];
+        X[e] = (s2 >= nself && hop_sign < 0) ? -v : v;
+    }
+    __syncthreads();
+    cx<T> acc = czero<T>();
+    for (int qb = qs; qb < Q; qb += PF * qstep) {
+        if (qb != qs) load(qb);
+#pragma unroll
+        for (int u = 0; u < PF; u++) {
+            const int q = qb + u * qstep;
+            if (q < Q) acc += ccast<T>(a[u]) * X[q];
+        }
+    }
+#pragma unroll
+    for (int o = RC; o < 64; o <<= 1) {
+        acc.re += __shfl_xor(acc.re, o, 64);
+        acc.im += __shfl_xor(acc.im, o, 64);
+    }
+    if (cg == 0) part[w][rl] = acc;
+    __syncthreads();
+    if (w == 0 && cg == 0 && rok) {
+        cx<T> tot = (self_mode == CS_IDENT) ? in1[gs * nd + row] : czero<T>();
+        for (int q = 0; q < nw; q++) tot += part[q][rl];
+        out[gs * nd + row] = tot;
+    }
+}
+
+template <class T, class S>
+static void launch_rows(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, int fold,
+                        const cx<T>* in2, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
+    constexpr int RC = 128 / (int)sizeof(cx<S>);   // rows per 128-byte line
+    const int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
+    const int nrc = (op.nd + RC - 1) / RC;
+    dim3 grid(nsite * nrc, nr);
+    k_coarse_rows<T, S, RC><<<grid, 256, 0, s>>>(op, par, self_mode, in1, hop_sign, fold, in2, out, mk, ld);
+}
+
+// B_k(x) = Minv(x) M_{1+k}(x): workgroup (even site i, hop k), FP64 sums
+template <class T>
+__global__ void k_coarse_fold(int nd, const cx<T>* __restrict__ M, const cx<T>* __restrict__ Minv,
+                              cx<T>* __restrict__ B) {
+    const int i = blockIdx.x, k = blockIdx.y;
+    const size_t nn = (size_t)nd * nd;
+    const cx<T>* Mi = Minv + (size_t)i * nn;
+    const cx<T>* Mk = M + ((size_t)i * 9 + 1 + k) * nn;
+    cx<T>* Bk = B + ((size_t)i * 8 + k) * nn;
+    for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) {
+        const int c = e / nd, r = e - c * nd;   // column-major entry (r, c)
+        cx<double> s = czero<double>();
+        for (int q = 0; q < nd; q++) s += ccast<double>(Mi[(size_t)q * nd + r]) * ccast<double>(Mk[(size_t)c * nd + q]);
+        Bk[e] = ccast<T>(s);
+    }
+}
+
+template <class T>
+void coarse_fold_inverse(const Geom& g, int nd, const cx<T>* M, const cx<T>* Minv, cx<T>* B, hipStream_t s) {
+    dim3 grid(g.vh, 8);
+    k_coarse_fold<T><<<grid, 256, 0, s>>>(nd, M, Minv, B);
+}
+
+template <class T, class S>
+bool coarse_uses_mfma(const CoarseOp<T, S>& op, int nr) {
+    return std::is_same<T, float>::value && op.mfma && nr >= 2 && nr <= 16 && op.nd <= 64;
+}
+
+template <class T, class S>
+void coarse_apply_folded(const CoarseOp<T, S>& op, const cx<T>* in1, int hop_sign, const cx<T>* in2, cx<T>* out,
+                         hipStream_t s, Mask mk, int nr, long ld) {
+    if (!op.B || op.nd > 64) throw std::invalid_argument("coarse_apply_folded: no folded blocks on this level");
+    launch_rows(op, 0, in1 ? CS_IDENT : CS_NONE, in1, hop_sign, 1, in2, out, s, mk, nr, ld);
+}
+
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
@@ -367,6 +509,11 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
                 op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
             return;
         }
+    }
+    // without the post multiplication by the inverse the row-split form applies
+    if (!post_inv && self_mode != CS_SELFINV && op.nd <= 64) {
+        launch_rows(op, par, self_mode, in1, hop_sign, 0, in2, out, s, mk, nr, ld);
+        return;
     }
     // the vector-unit kernel reads the site's blocks as one panel: the self
     // inverse is not stored next to the hop blocks
@@ -1269,6 +1416,9 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
                                                 cx<double>*, unsigned*, int*, int, hipStream_t);                      \
     template void coarse_apply<T, S>(const CoarseOp<T, S>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*,   \
                                      hipStream_t, Mask, int, long);                                                 \
+    template bool coarse_uses_mfma<T, S>(const CoarseOp<T, S>&, int);                                                \
+    template void coarse_apply_folded<T, S>(const CoarseOp<T, S>&, const cx<T>*, int, const cx<T>*, cx<T>*,           \
+                                            hipStream_t, Mask, int, long);                                          \
     template void coarse_sap_half<T, S>(const CoarseOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
                                         int, long, Mask);                                                           \
     template void coarse_restrict<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int, \
@@ -1279,6 +1429,7 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
 #define DD_COARSE_INST(T)                                                                                                \
     DD_COARSE_OP_INST(T, T)                                                                                          \
     template void coarse_self_inverse<T>(const Geom&, int, const cx<T>*, cx<T>*, int*, hipStream_t);                  \
+    template void coarse_fold_inverse<T>(const Geom&, int, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);          \
     template void coarse_import_vector<T>(const Geom&, int, int, const double*, cx<T>*, hipStream_t);                \
     template void coarse_export_vector<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \
     template void coarse_export_blocks<T>(const Geom&, int, int, const cx<T>*, double*, hipStream_t);                \

@@ -38,6 +38,9 @@ struct FineOp {
 //   mfma  with 2..16 right-hand sides and FP32 arithmetic the apply runs on
 //         the matrix cores (one launch for all RHS, each block entry read
 //         once); 0: one workgroup per (site, RHS) on the vector units
+//   B    [vh][8][nd][nd]   (coarsest level only, else null) the even sites' hop
+//         blocks with the self inverse folded in, B_k(x) = Minv(x) M_{1+k}(x),
+//         so that A_ee^{-1} D_eo needs no second pass over the site's result
 template <class T, class S = T>
 struct CoarseOp {
     Geom g;
@@ -45,6 +48,7 @@ struct CoarseOp {
     const cx<S>* M;
     const cx<S>* Minv;
     int mfma = 1;
+    const cx<S>* B = nullptr;
 };
 
 // which right-hand sides of a batch a launch works on: flag r at p[r*stride];
@@ -123,6 +127,18 @@ enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
                   bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
+// whether coarse_apply takes the matrix-core form for nr right-hand sides
+template <class T, class S>
+bool coarse_uses_mfma(const CoarseOp<T, S>& op, int nr);
+// out(x) = [in1(x)] + hop_sign * sum_k B_k(x) in2(x_k) on the even sites (op.B
+// must be set; in1 may be null): A_ee^{-1} D_eo in one pass.  Not the
+// matrix-core form: callers check coarse_uses_mfma first.
+template <class T, class S>
+void coarse_apply_folded(const CoarseOp<T, S>& op, const cx<T>* in1, int hop_sign, const cx<T>* in2, cx<T>* out,
+                         hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
+// B_k(x) = Minv(x) M_{1+k}(x) for the even sites x (FP64 accumulation)
+template <class T>
+void coarse_fold_inverse(const Geom& g, int nd, const cx<T>* M, const cx<T>* Minv, cx<T>* B, hipStream_t s);
 // One restart cycle of the coarsest odd-even GMRES for nr <= 16 RHS in one
 // cooperative launch of `grid` workgroups (see dd_coarse.hip); the GmDev states
 // must have been started (gm_start) and v_0 normalised.  part: nr*34*grid

@@ -348,6 +348,7 @@ struct Hier {
     cx<_Float16>* Ph[DD_MAXLEV];
     cx<_Float16>* Mh[DD_MAXLEV];
     cx<_Float16>* Minvh[DD_MAXLEV];
+    cx<_Float16>* Bh[DD_MAXLEV];
     // run f with the fine operator / coarse operator / P of the storage in use
     template <class F> void with_fine(F&& f) {
         if constexpr (std::is_same<T, float>::value)
@@ -365,6 +366,7 @@ struct Hier {
         f((const cx<T>*)P[l]);
     }
     void refresh_half(int l);
+    void fold(int l);
     int* blocks[DD_MAXLEV][2];
     int nblocks[DD_MAXLEV][2];
     AggMap amap[DD_MAXLEV];
@@ -373,6 +375,7 @@ struct Hier {
     cx<T>* P[DD_MAXLEV];
     cx<T>* M[DD_MAXLEV];
     cx<T>* Minv[DD_MAXLEV];
+    cx<T>* B[DD_MAXLEV];    // coarsest level: even-site hop blocks with the self inverse folded in
     cx<T>* rc[DD_MAXLEV];   // restricted residuals on level l (l >= 1)
     cx<T>* ec[DD_MAXLEV];   // coarse corrections on level l (l >= 1)
     cx<T>* wa[DD_MAXLEV];   // scratch sets
@@ -414,6 +417,8 @@ struct Hier {
         memset(P, 0, sizeof P);
         memset(M, 0, sizeof M);
         memset(Minv, 0, sizeof Minv);
+        memset(B, 0, sizeof B);
+        memset(Bh, 0, sizeof Bh);
         memset(coarse_count, 0, sizeof coarse_count);
         memset(gmst, 0, sizeof gmst);
         memset(kv_cap, 0, sizeof kv_cap);
@@ -552,11 +557,14 @@ void Hier<T>::build_geometry() {
             nd[l] = 2 * p.n_tv[l - 1];
             M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
             Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
-            cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1};
+            const bool coarsest = (l == nlev - 1) && nd[l] <= 64;
+            if (coarsest) B[l] = A.get<cx<T>>((size_t)g[l].vh * 8 * nd[l] * nd[l]);
+            cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1, B[l]};
             if (half) {
                 Mh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
                 Minvh[l] = A.get<cx<_Float16>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
-                coph[l] = CoarseOp<T, _Float16>{g[l], nd[l], Mh[l], Minvh[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1};
+                if (coarsest) Bh[l] = A.get<cx<_Float16>>((size_t)g[l].vh * 8 * nd[l] * nd[l]);
+                coph[l] = CoarseOp<T, _Float16>{g[l], nd[l], Mh[l], Minvh[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1, Bh[l]};
             }
             rc[l] = A.get<cx<T>>((size_t)R * nlv(l));
             ec[l] = A.get<cx<T>>((size_t)R * nlv(l));
@@ -680,7 +688,8 @@ void Hier<T>::schur(int l, const cx<T>* v, cx<T>* out, Mask mk, int nr, int k) {
     // two launches, each over one parity: 8 hop blocks + (Minv | self) per site
     Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
     with_coarse(l, [&](auto& op) {
-        coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, v, true, wc[l], C->s, mk, nr, nlv(l));
+        if (op.B && !coarse_uses_mfma(op, nr)) coarse_apply_folded(op, (const cx<T>*)nullptr, 1, v, wc[l], C->s, mk, nr, nlv(l));
+        else coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, v, true, wc[l], C->s, mk, nr, nlv(l));
         coarse_apply(op, 1, CS_SELF, v, -1, wc[l], false, out, C->s, mk, nr, nlv(l));
     });
 }
@@ -707,6 +716,9 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     const Mask live{&st->stop, (int)(sizeof(GmDev) / sizeof(int)), 1};
     const Mask in = bt.mask();
     auto odd = [&](cx<T>* v) { return v + nh; };
+    // A_ee^{-1} D_eo in one pass with the folded blocks (vector-unit forms)
+    bool folded = false;
+    with_coarse(l, [&](auto& op) { folded = op.B && !coarse_uses_mfma(op, nr); });
     // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
     {
         Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false, k) + by_coarse(l, 8, 3, false, k));
@@ -739,7 +751,8 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         {
             Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
             with_coarse(l, [&](auto& op) {
-                coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, wc[l], sq, live, nr, nfull);
+                if (folded) coarse_apply_folded(op, (const cx<T>*)nullptr, 1, vj, wc[l], sq, live, nr, nfull);
+                else coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, wc[l], sq, live, nr, nfull);
                 coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull);
             });
         }
@@ -833,10 +846,13 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         if (read_state()) break;
         chunk = 4;
     }
-    // e_e = A_ee^{-1} (r_e - D_eo e_o)
+    // e_e = A_ee^{-1} (r_e - D_eo e_o)  (= t_e - B e_o with the folded blocks)
     {
         Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false, k));
-        with_coarse(l, [&](auto& op) { coarse_apply(op, 0, CS_IDENT, r, -1, e, true, e, C->s, in, nr, nfull); });
+        with_coarse(l, [&](auto& op) {
+            if (folded) coarse_apply_folded(op, (const cx<T>*)t, -1, e, e, C->s, in, nr, nfull);
+            else coarse_apply(op, 0, CS_IDENT, r, -1, e, true, e, C->s, in, nr, nfull);
+        });
     }
     int mx = 0;
     for (int q = 0; q < nr; q++) {
@@ -1032,7 +1048,16 @@ void Hier<T>::build(int l) {
     coarse_self_inverse<T>(g[l + 1], nd[l + 1], M[l + 1], Minv[l + 1], C->dflags + DI_BAD, C->s);
     HIPX(hipGetLastError());
     if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "singular coarse self block on level " + std::to_string(l + 1));
+    fold(l + 1);
     refresh_half(l);
+}
+
+// the folded even-site blocks B_k = Minv M_{1+k} of level l (if it keeps them)
+template <class T>
+void Hier<T>::fold(int l) {
+    if (!B[l]) return;
+    coarse_fold_inverse<T>(g[l], nd[l], M[l], Minv[l], B[l], C->s);
+    HIPX(hipGetLastError());
 }
 
 // FP16 copies of P of level l and of the operator of level l+1
@@ -1044,6 +1069,7 @@ void Hier<T>::refresh_half(int l) {
         if (Ph[l]) vec_convert<_Float16, float>((long)N[l] * nlv(l), P[l], Ph[l], C->s);
         vec_convert<_Float16, float>((long)(vc * 9 * nn), M[l + 1], Mh[l + 1], C->s);
         vec_convert<_Float16, float>((long)(vc * nn), Minv[l + 1], Minvh[l + 1], C->s);
+        if (Bh[l + 1]) vec_convert<_Float16, float>((long)(g[l + 1].vh * 8 * nn), B[l + 1], Bh[l + 1], C->s);
     }
     (void)l;
 }
@@ -1421,6 +1447,7 @@ dd_status dd_set_mass(dd_ctx* ctx, double m0) {
         for (int l = 1; l < H.nlev; l++) {
             coarse_shift_diag(H.g[l], H.nd[l], dm, H.M[l], ctx->s);
             coarse_self_inverse(H.g[l], H.nd[l], H.M[l], H.Minv[l], ctx->dflags + DI_BAD, ctx->s);
+            H.fold(l);
             H.refresh_half(l - 1);
         }
         if (H.half) {

@@ -77,8 +77,9 @@ def estimate_bytes(dims, params=None, max_rhs=1):
     """Device bytes a resident setup holds, following the library's
     allocations: fine fields (FP64 and FP32 copies), the outer FGMRES
     workspace for max_rhs right-hand sides, and per level the vector sets,
-    test vectors, P, D_c, its self-block inverses and the Krylov bases
-    (FP16 copies for precision 16)."""
+    test vectors, P, D_c, its self-block inverses (and on the coarsest level
+    the folded even-site blocks) and the Krylov bases (FP16 copies for
+    precision 16)."""
     def get(name, default):
         return getattr(params, name, default) if params is not None else default
 
@@ -109,6 +110,8 @@ def estimate_bytes(dims, params=None, max_rhs=1):
         nd = 2 * n_tv[l - 1]
         nl = v * nd
         b += v * 10 * nd * nd * sz + (v * 10 * nd * nd * 4 if prec == 16 else 0)
+        if l == levels - 1 and nd <= 64:   # even-site hop blocks with the self inverse folded in
+            b += (v // 2) * 8 * nd * nd * (sz + (4 if prec == 16 else 0))
         b += 5 * R * nl * sz + R * 17 * 1024
         if l < levels - 1:
             b += 2 * n_tv[l] * nl * sz + (n_tv[l] * nl * 4 if prec == 16 else 0)
