@@ -148,14 +148,30 @@ __global__ void __launch_bounds__(RED_NT) k_final_sum(int nc, int m, const cx<do
 
 // w -= sum_i h_i V_i ; npart[r*nc + c] = chunk c of ||w||^2.  With hpart != 0
 // the inner products are first summed from the multidot partials.
+//
+// With ga.st (the coarsest GMRES) the stored basis vectors may carry factors
+// sc_i (V_i = sc_i * stored): the partial sums are of the stored vectors, so
+// h_i = sc_i * sum and w -= sum_i (h_i sc_i) stored_i.  The last workgroup of
+// each RHS to finish (atomic count in ga.done, reset by it) then adds the norm
+// partials and folds the column into the state (and scales w when
+// ga.normalize): the norm sum and the Givens update need no launch of their own.
+struct GivensArgs {
+    GmDev* st = nullptr;
+    int j = 0;
+    int* done = nullptr;
+    int normalize = 0;
+};
+__device__ double gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2, bool normalize);
+
 template <class T>
 __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
                                                         long ldv, const cx<double>* __restrict__ h, int hstride,
                                                         const cx<double>* __restrict__ hpart, cx<double>* hout,
                                                         cx<T>* __restrict__ w, cx<double>* __restrict__ npart, long ldr,
-                                                        long ldw, Mask mk) {
+                                                        long ldw, Mask mk, GivensArgs ga) {
     const int c = blockIdx.x, r = blockIdx.y;
     if (!mk.on(r)) return;
+    const double* scv = ga.st ? ga.st[r].sc : nullptr;
     __shared__ double sh[RED_NT / 64];
     __shared__ cx<T> hh[MAXM];
     if (hpart) {
@@ -173,8 +189,10 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
         if (threadIdx.x < m) {
             cx<double> hv = hg[0][threadIdx.x];
             for (int q = 1; q < HG; q++) hv += hg[q][threadIdx.x];
+            const double f = scv ? scv[threadIdx.x] : 1.0;
+            hv = f * hv;
             if (c == 0) hout[(size_t)r * hstride + threadIdx.x] = hv;
-            hh[threadIdx.x] = ccast<T>(hv);
+            hh[threadIdx.x] = ccast<T>(f * hv);
         }
     } else if (threadIdx.x < m) {
         hh[threadIdx.x] = ccast<T>(h[(size_t)r * hstride + threadIdx.x]);
@@ -201,6 +219,41 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
     }
     acc = block_sum256(acc, sh);
     if (threadIdx.x == 0) npart[(size_t)r * nc + c] = cx<double>{acc, 0.0};
+    if (!ga.st) return;
+    // ---- last workgroup of this RHS: norm, Givens update, next basis vector ----
+    __shared__ int last_s;
+    __threadfence();   // this workgroup's w entries, h (chunk 0) and norm partial
+    if (threadIdx.x == 0) last_s = (atomicAdd(ga.done + r, 1) == nc - 1);
+    __syncthreads();
+    if (!last_s) return;
+    __threadfence();
+    double n2 = 0;
+    for (int q = threadIdx.x; q < nc; q += RED_NT) n2 += npart[(size_t)r * nc + q].re;
+    __syncthreads();   // sh is reused
+    n2 = block_sum256(n2, sh);
+    cx<double>* hr = hout + (size_t)r * hstride;
+    if (threadIdx.x == 0) {
+        hr[33] = cx<double>{n2, 0.0};
+        ga.done[r] = 0;
+    }
+    const double f = gm_column_wg(ga.st + r, ga.j, hr, n2, ga.normalize != 0);
+    if (ga.normalize && f != 0.0) {
+        const T ft = T(f);
+        constexpr int B = 8;   // entries per thread in flight
+        for (long q0 = threadIdx.x; q0 < n; q0 += (long)B * RED_NT) {
+            cx<T> v[B];
+#pragma unroll
+            for (int u = 0; u < B; u++) {
+                const long q = q0 + (long)u * RED_NT;
+                v[u] = (q < n) ? wr[q] : czero<T>();
+            }
+#pragma unroll
+            for (int u = 0; u < B; u++) {
+                const long q = q0 + (long)u * RED_NT;
+                if (q < n) wr[q] = ft * v[u];
+            }
+        }
+    }
 }
 
 static inline cx<double>* hpart_of(void* work) { return (cx<double>*)work; }
@@ -235,7 +288,7 @@ void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* 
         int mm = (m - i0 < MAXM) ? m - i0 : MAXM;
         dim3 grid(nc, rb.nr);
         k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, mm, V + (size_t)i0 * ldv, ldv, h + i0, rb.ostride, nullptr,
-                                                 nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
+                                                 nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk, GivensArgs{});
         i0 += mm;
     } while (i0 < m);
     dim3 g2(1, rb.nr);
@@ -277,9 +330,13 @@ __global__ void k_gm_start(GmDev* st0, const cx<double>* res, int rstride, doubl
     }
     __syncthreads();
     if (!reset_s) return;
-    // cleared by the whole workgroup (one thread would wait on a thousand stores)
+    // cleared by the whole workgroup (one thread would wait on a thousand stores);
+    // v_0 is normalised explicitly (sc[0] = 1)
     for (int e = threadIdx.x; e < 33 * 32; e += blockDim.x) st->H[e] = czero<double>();
-    for (int e = threadIdx.x; e < 33; e += blockDim.x) st->g[e] = (e == 0) ? cx<double>{beta_s, 0.0} : czero<double>();
+    for (int e = threadIdx.x; e < 33; e += blockDim.x) {
+        st->g[e] = (e == 0) ? cx<double>{beta_s, 0.0} : czero<double>();
+        st->sc[e] = 1.0;
+    }
 }
 
 __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
@@ -294,7 +351,7 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
 // entry in registers (the global-memory form waits on one load per rotation)
 // Returns, in every thread, the factor that normalises the new basis vector
 // (0 when this RHS stopped at this step: the vector is then left as it is).
-__device__ double gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2) {
+__device__ double gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2, bool normalize) {
     __shared__ cx<double> hs[33], css[32], sns[32];
     __shared__ double sc_s;
     const int t = threadIdx.x;
@@ -334,57 +391,13 @@ __device__ double gm_column_wg(GmDev* st, int j, const cx<double>* h, double hn2
         if (hn == 0.0) stop = 1;
         st->stop = stop;
         st->scale = (hn > 0) ? 1.0 / hn : 0.0;
+        // the new basis vector: w scaled by the caller (normalize), or w kept
+        // with its factor
+        st->sc[j + 1] = normalize ? 1.0 : st->scale;
         sc_s = stop ? 0.0 : st->scale;
     }
     __syncthreads();
     return sc_s;
-}
-
-__global__ void k_gm_column(GmDev* st0, int j, const cx<double>* __restrict__ res, int rstride) {
-    GmDev* st = st0 + blockIdx.x;
-    if (st->stop) return;
-    const cx<double>* h = res + (size_t)blockIdx.x * rstride;
-    gm_column_wg(st, j, h, h[33].re);
-}
-
-// ||w||^2 from the chunk partials (fixed order) and the Givens update of
-// column j, one workgroup per RHS: the last kernels of an Arnoldi step in one.
-// With nscale > 0 the workgroup also normalises w (its first nscale entries):
-// short coarse vectors, where a separate launch would cost more than the work.
-static constexpr long FUSE_SCALE_MAX = 16384;
-
-template <class T>
-__global__ void __launch_bounds__(RED_NT) k_norm_givens(int nc, const cx<double>* __restrict__ npart, cx<double>* res,
-                                                        int rstride, GmDev* st0, int j, cx<T>* __restrict__ w,
-                                                        long ldw, long nscale) {
-    const int r = blockIdx.x;
-    GmDev* st = st0 + r;
-    if (st->stop) return;
-    __shared__ double sh[RED_NT / 64];
-    double acc = 0;
-    for (int c = threadIdx.x; c < nc; c += RED_NT) acc += npart[(size_t)r * nc + c].re;
-    acc = block_sum256(acc, sh);
-    cx<double>* h = res + (size_t)r * rstride;
-    if (threadIdx.x == 0) h[33] = cx<double>{acc, 0.0};
-    const double sc = gm_column_wg(st, j, h, acc);
-    if (nscale > 0 && sc != 0.0) {
-        cx<T>* wr = w + r * ldw;
-        const T f = T(sc);
-        constexpr int B = 8;   // entries per thread in flight
-        for (long e0 = threadIdx.x; e0 < nscale; e0 += (long)B * RED_NT) {
-            cx<T> v[B];
-#pragma unroll
-            for (int u = 0; u < B; u++) {
-                const long e = e0 + (long)u * RED_NT;
-                v[u] = (e < nscale) ? wr[e] : czero<T>();
-            }
-#pragma unroll
-            for (int u = 0; u < B; u++) {
-                const long e = e0 + (long)u * RED_NT;
-                if (e < nscale) wr[e] = f * v[u];
-            }
-        }
-    }
 }
 
 // back substitution R y = g with the rotated Hessenberg R (k x k upper
@@ -420,9 +433,6 @@ __global__ void k_gm_gather(const GmDev* st, int nr, int* out) {
     }
 }
 void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s) { k_gm_gather<<<1, 64, 0, s>>>(st, nr, out); }
-void gm_column(GmDev* st, int j, const cx<double>* res, int rstride, int nr, hipStream_t s) {
-    k_gm_column<<<nr, 64, 0, s>>>(st, j, res, rstride);
-}
 void gm_solve(GmDev* st, int nr, hipStream_t s) { k_gm_solve<<<nr, 64, 0, s>>>(st); }
 
 template <class T>
@@ -448,7 +458,7 @@ __global__ void k_lincomb_dev(long n, const cx<T>* __restrict__ V, long ldv, con
     x += blockIdx.y * ldx;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         cx<double> sacc = ccast<double>(x[e]);
-        for (int i = 0; i < m; i++) sacc += st->y[i] * ccast<double>(V[(size_t)i * ldv + e]);
+        for (int i = 0; i < m; i++) sacc += st->y[i] * (st->sc[i] * ccast<double>(V[(size_t)i * ldv + e]));
         x[e] = ccast<T>(sacc);
     }
 }
@@ -468,31 +478,15 @@ void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, 
     k_multidot<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, w, hpart_of(work), rb.ldr, rb.ldw, rb.mk);
 }
 
-// h (summed from the multidot partials) goes to res + r*ostride, ||w||^2 to res + r*ostride + 33
-template <class T>
-void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
-                          hipStream_t s, RedBatch rb) {
-    const int nc = red_chunks(n);
-    const long chunk = (n + nc - 1) / nc;
-    dim3 grid(nc, rb.nr);
-    k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
-                                             npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
-    dim3 g2(1, rb.nr);
-    k_final_sum<<<g2, RED_NT, 0, s>>>(nc, 1, npart_of(work, rb.nr), res + 33, rb.ostride, rb.mk);
-}
-
 template <class T>
 void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
-                            hipStream_t s, RedBatch rb, GmDev* st, int j) {
+                            hipStream_t s, RedBatch rb, GmDev* st, int j, int* done, bool normalize) {
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
     dim3 grid(nc, rb.nr);
     k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
-                                             npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
-    const bool fuse = n <= FUSE_SCALE_MAX;
-    k_norm_givens<T><<<rb.nr, RED_NT, 0, s>>>(nc, npart_of(work, rb.nr), res, rb.ostride, st, j, w, rb.ldw,
-                                              fuse ? n : 0);
-    if (!fuse) vec_scale_dev<T>(n, st, w, s, false, rb.nr, rb.ldw);
+                                             npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk,
+                                             GivensArgs{st, j, done, normalize ? 1 : 0});
 }
 
 template <class T, class X>
@@ -589,10 +583,8 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template void vec_scale_dev<T>(long, const GmDev*, cx<T>*, hipStream_t, bool, int, long);                      \
     template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t, int, long, long); \
     template void vec_multidot_skip<T>(long, int, const cx<T>*, long, const cx<T>*, void*, hipStream_t, RedBatch);  \
-    template void vec_update_norm_skip<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t,  \
-                                          RedBatch);                                                               \
     template void vec_update_norm_givens<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t, \
-                                            RedBatch, GmDev*, int);
+                                            RedBatch, GmDev*, int, int*, bool);
 
 DD_BLAS_INST(double)
 DD_BLAS_INST(float)

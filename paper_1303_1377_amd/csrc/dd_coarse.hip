@@ -368,7 +368,7 @@ static size_t mfma_lds_bytes(int nd) {
 template <class T, class S, int RC>
 __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par, int self_mode,
                                                      const cx<T>* __restrict__ in1, int hop_sign, int fold,
-                                                     const cx<T>* in2, cx<T>* out, Mask mk, long ld) {
+                                                     const cx<T>* in2, cx<T>* out, Mask mk, long ld, InScale isc) {
     constexpr int CG = 64 / RC;          // column groups per wavefront
     constexpr int PF = (CG >= 4) ? 12 * (8 / CG) : 24;   // block entries a lane loads at once
     if (!mk.on(blockIdx.y)) return;
@@ -423,11 +423,19 @@ __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par,
         }
     };
     load(qs);   // in flight while the inputs are staged
+    // factors of the two inputs (stored GMRES basis vectors carry theirs in the state)
+    T f1 = T(1), f2 = T(1);
+    if (isc.st) {
+        const T f = T(isc.st[blockIdx.y].sc[isc.j]);
+        if (isc.which & 1) f1 = f;
+        if (isc.which & 2) f2 = f;
+    }
+    if (hop_sign < 0) f2 = -f2;
     __syncthreads();
     for (int e = t; e < Q; e += blockDim.x) {
         const int s2 = e / nd;
         const cx<T> v = vin[s2][e - s2 * nd];
-        X[e] = (s2 >= nself && hop_sign < 0) ? -v : v;
+        X[e] = ((s2 >= nself) ? f2 : f1) * v;
     }
     __syncthreads();
     cx<T> acc = czero<T>();
@@ -447,7 +455,7 @@ __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par,
     if (cg == 0) part[w][rl] = acc;
     __syncthreads();
     if (w == 0 && cg == 0 && rok) {
-        cx<T> tot = (self_mode == CS_IDENT) ? in1[gs * nd + row] : czero<T>();
+        cx<T> tot = (self_mode == CS_IDENT) ? f1 * in1[gs * nd + row] : czero<T>();
         for (int q = 0; q < nw; q++) tot += part[q][rl];
         out[gs * nd + row] = tot;
     }
@@ -455,12 +463,12 @@ __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par,
 
 template <class T, class S>
 static void launch_rows(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, int fold,
-                        const cx<T>* in2, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
+                        const cx<T>* in2, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld, InScale isc) {
     constexpr int RC = 128 / (int)sizeof(cx<S>);   // rows per 128-byte line
     const int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
     const int nrc = (op.nd + RC - 1) / RC;
     dim3 grid(nsite * nrc, nr);
-    k_coarse_rows<T, S, RC><<<grid, 256, 0, s>>>(op, par, self_mode, in1, hop_sign, fold, in2, out, mk, ld);
+    k_coarse_rows<T, S, RC><<<grid, 256, 0, s>>>(op, par, self_mode, in1, hop_sign, fold, in2, out, mk, ld, isc);
 }
 
 // B_k(x) = Minv(x) M_{1+k}(x): workgroup (even site i, hop k), FP64 sums
@@ -493,14 +501,17 @@ bool coarse_uses_mfma(const CoarseOp<T, S>& op, int nr) {
 
 template <class T, class S>
 void coarse_apply_folded(const CoarseOp<T, S>& op, const cx<T>* in1, int hop_sign, const cx<T>* in2, cx<T>* out,
-                         hipStream_t s, Mask mk, int nr, long ld) {
+                         hipStream_t s, Mask mk, int nr, long ld, InScale isc) {
     if (!op.B || op.nd > 64) throw std::invalid_argument("coarse_apply_folded: no folded blocks on this level");
-    launch_rows(op, 0, in1 ? CS_IDENT : CS_NONE, in1, hop_sign, 1, in2, out, s, mk, nr, ld);
+    launch_rows(op, 0, in1 ? CS_IDENT : CS_NONE, in1, hop_sign, 1, in2, out, s, mk, nr, ld, isc);
 }
 
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld) {
+                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk, int nr, long ld, InScale isc) {
+    const bool rows = !post_inv && self_mode != CS_SELFINV && op.nd <= 64;
+    if (isc.st && (coarse_uses_mfma(op, nr) || !rows))
+        throw std::invalid_argument("coarse_apply: scaled inputs need the row-split vector-unit form");
     int nsite = (par < 0) ? 2 * op.g.vh : op.g.vh;
     if constexpr (std::is_same<T, float>::value) {
         // the matrix-core form serves FP32 arithmetic with 2..16 right-hand sides and nd <= 64
@@ -511,8 +522,8 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
         }
     }
     // without the post multiplication by the inverse the row-split form applies
-    if (!post_inv && self_mode != CS_SELFINV && op.nd <= 64) {
-        launch_rows(op, par, self_mode, in1, hop_sign, 0, in2, out, s, mk, nr, ld);
+    if (rows) {
+        launch_rows(op, par, self_mode, in1, hop_sign, 0, in2, out, s, mk, nr, ld, isc);
         return;
     }
     // the vector-unit kernel reads the site's blocks as one panel: the self
@@ -809,6 +820,7 @@ __global__ void __launch_bounds__(COOP_NT) k_gmres_coop(CoarseOp<T, S> op, cx<T>
                 sr->j = j + 1;
                 sr->stop = stop;
                 sr->scale = (hn > 0) ? 1.0 / hn : 0.0;
+                sr->sc[j + 1] = 1.0;   // this kernel stores its basis vectors normalised
             }
             stop_s[r] = stop;
         }
@@ -1415,10 +1427,10 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
     template hipError_t coarse_gmres_coop<T, S>(const CoarseOp<T, S>&, cx<T>*, long, long, cx<T>*, GmDev*, int, int, \
                                                 cx<double>*, unsigned*, int*, int, hipStream_t);                      \
     template void coarse_apply<T, S>(const CoarseOp<T, S>&, int, int, const cx<T>*, int, const cx<T>*, bool, cx<T>*,   \
-                                     hipStream_t, Mask, int, long);                                                 \
+                                     hipStream_t, Mask, int, long, InScale);                                        \
     template bool coarse_uses_mfma<T, S>(const CoarseOp<T, S>&, int);                                                \
     template void coarse_apply_folded<T, S>(const CoarseOp<T, S>&, const cx<T>*, int, const cx<T>*, cx<T>*,           \
-                                            hipStream_t, Mask, int, long);                                          \
+                                            hipStream_t, Mask, int, long, InScale);                                 \
     template void coarse_sap_half<T, S>(const CoarseOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
                                         int, long, Mask);                                                           \
     template void coarse_restrict<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int, \

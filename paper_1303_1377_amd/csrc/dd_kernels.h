@@ -124,9 +124,19 @@ template <class T> void fine_random(const Geom& g, int n, unsigned long long see
 enum CoarseSelf { CS_NONE = 0, CS_IDENT = 1, CS_SELF = 2, CS_SELFINV = 3 };
 // out(x) = [post Minv] ( self_mode(x) in1(x) + hop_sign * sum_k M_{1+k}(x) in2(x_k) )
 // for the sites of parity `par` (0, 1) or all sites (par < 0).
+// input scaling of the coarse stencil: the inputs flagged in `which` (1: in1,
+// 2: in2) of right-hand side r are multiplied by st[r].sc[j] (GMRES basis
+// vectors stored without their normalisation); vector-unit forms only
+struct GmDev;
+struct InScale {
+    const GmDev* st = nullptr;
+    int j = 0;
+    int which = 0;
+};
 template <class T, class S>
 void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>* in1, int hop_sign, const cx<T>* in2,
-                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
+                  bool post_inv, cx<T>* out, hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0,
+                  InScale isc = InScale{});
 // whether coarse_apply takes the matrix-core form for nr right-hand sides
 template <class T, class S>
 bool coarse_uses_mfma(const CoarseOp<T, S>& op, int nr);
@@ -135,7 +145,7 @@ bool coarse_uses_mfma(const CoarseOp<T, S>& op, int nr);
 // matrix-core form: callers check coarse_uses_mfma first.
 template <class T, class S>
 void coarse_apply_folded(const CoarseOp<T, S>& op, const cx<T>* in1, int hop_sign, const cx<T>* in2, cx<T>* out,
-                         hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0);
+                         hipStream_t s, Mask mk = all_rhs(), int nr = 1, long ld = 0, InScale isc = InScale{});
 // B_k(x) = Minv(x) M_{1+k}(x) for the even sites x (FP64 accumulation)
 template <class T>
 void coarse_fold_inverse(const Geom& g, int nd, const cx<T>* M, const cx<T>* Minv, cx<T>* B, hipStream_t s);
@@ -222,6 +232,8 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s);
 struct alignas(16) GmDev {
     cx<double> H[33 * 32];   // rotated Hessenberg, column j at H[j*33 + i]
     cx<double> cs[32], sn[32], g[33], y[32];
+    double sc[33];           // basis vector i = sc[i] * the stored vector i (stored
+                             // vectors may be left unnormalised; 1 when normalised)
     double tol_abs;          // stop when |g_{j+1}| <= tol_abs
     double scale;            // 1/||w|| for the basis vector just produced
     int j;                   // columns completed in this cycle
@@ -237,14 +249,12 @@ void gm_start(GmDev* st, const cx<double>* res, int rstride, double tol, int fir
               int nr, hipStream_t s, Mask mk = all_rhs());
 // out[3r..3r+2] = {j, its, stop} of st[r] (one small transfer reads a batch)
 void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s);
-// fold column j (inner products h at res, norm^2 at res + 33) into the state
-void gm_column(GmDev* st, int j, const cx<double>* res, int rstride, int nr, hipStream_t s);
 // y = R^{-1} g for the st->j columns of the cycle
 void gm_solve(GmDev* st, int nr, hipStream_t s);
 // x_r *= st[r].scale (skipped once st[r].stop unless ignore_stop)
 template <class T>
 void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr = 1, long ld = 0);
-// x_r += sum_{i < st[r].j} y_i V_i
+// x_r += sum_{i < st[r].j} y_i sc_i V_i
 template <class T>
 void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s, int nr = 1,
                      long ldr = 0, long ldx = 0);
@@ -252,14 +262,14 @@ void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x
 template <class T>
 void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, void* work, hipStream_t s,
                        RedBatch rb);
-template <class T>
-void vec_update_norm_skip(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
-                          hipStream_t s, RedBatch rb);
-// the same update and norm, then the Givens update of column j in the same
-// kernel as the final norm sum (what gm_column does), skipping stopped RHS,
-// and w scaled to the next basis vector (what vec_scale_dev does)
+// w -= sum_i h_i V_i with h_i = sc_i (stored V_i)^H w summed from the multidot
+// partials (written to res + r*ostride), ||w||^2, and then, in the last
+// workgroup of each RHS to finish (counter done[r], left at 0), the Givens
+// update of column j; w becomes the next basis vector: scaled by the last
+// workgroup when `normalize`, else stored as is with sc[j+1] = 1/||w||.
+// Stopped RHS are skipped.
 template <class T>
 void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, cx<double>* res, void* work,
-                            hipStream_t s, RedBatch rb, GmDev* st, int j);
+                            hipStream_t s, RedBatch rb, GmDev* st, int j, int* done, bool normalize);
 
 }  // namespace dd

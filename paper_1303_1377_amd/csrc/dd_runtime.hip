@@ -161,7 +161,9 @@ static const int DI_ONES = 16;      // MAX_RHS words that stay 1: "every RHS act
 static const int DI_GATHER = 32;    // {j, its, stop} of each coarsest-GMRES state
 static const int DI_BAR = 120;      // cooperative GMRES: barrier count, generation, abort flag
 static const int DI_MASK = 128;     // per level: [cycle mask][current mask], MAX_RHS each
-static const int DI_WORDS = DI_MASK + 2 * MAX_RHS * DD_MAXLEV;
+static const int DI_DONE = DI_MASK + 2 * MAX_RHS * DD_MAXLEV;   // coarsest GMRES: finished-workgroup
+                                                                 // counts, one per RHS (kept at 0)
+static const int DI_WORDS = DI_DONE + MAX_RHS;
 // reduction results per right-hand side: pass-1 h (0..32), ||w||^2 (33),
 // pass-2 h (34..66), ||w||^2 (67)
 static const int RS = 136;
@@ -751,14 +753,21 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         {
             Prof pr(C, DD_K_COARSE, 2 * by_coarse(l, 9, 2, false, k));
             with_coarse(l, [&](auto& op) {
-                if (folded) coarse_apply_folded(op, (const cx<T>*)nullptr, 1, vj, wc[l], sq, live, nr, nfull);
-                else coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, wc[l], sq, live, nr, nfull);
-                coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull);
+                // vector-unit forms: basis vectors stay unnormalised, their factors
+                // scale the stencil's inputs (no pass over w to normalise it)
+                if (folded) {
+                    coarse_apply_folded(op, (const cx<T>*)nullptr, 1, vj, wc[l], sq, live, nr, nfull, InScale{st, j, 2});
+                    coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull, InScale{st, j, 1});
+                } else {
+                    coarse_apply(op, 0, CS_NONE, (const cx<T>*)nullptr, 1, vj, true, wc[l], sq, live, nr, nfull);
+                    coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull);
+                }
             });
         }
         Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
         vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, sq, rb);
-        vec_update_norm_givens<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb, st, j);
+        vec_update_norm_givens<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb, st, j, C->dflags + DI_DONE,
+                                  !folded);
     };
     // graphs need a capture stream; live kernel timing brackets single launches
     const bool use_graphs = (C->sched & SCHED_GRAPH) && C->cap;
