@@ -31,6 +31,7 @@ __all__ = [
     "random_vectors",
     "random_gauge_transform",
     "unit_gauge",
+    "make_gauge_device",
 ]
 
 
@@ -156,3 +157,129 @@ def random_vectors(n_sites: int, nd: int, count: int, seed: int) -> np.ndarray:
     """Initial test vectors for the adaptive setup: [count][n_sites][nd], complex N(0,1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.ascontiguousarray(_cgauss(rng, (count, n_sites, nd)))
+
+
+# ---------------------------------------------------------------------------
+# The same link recipe drawn on the GPU, for lattices whose host generation
+# would take too long (tens of millions of links).  The random stream is
+# torch's Philox generator on the device, so the field is a different draw
+# from make_gauge with the same seed; the distribution and the steps are the
+# same: exp(i eps H) (Taylor series with scaling and squaring), reunitarised,
+# then APE steps with the polar projection (Newton iteration
+# X <- (X + X^-H)/2, then det phase and reunitarisation).  3x3 products are written out element-wise (no batched
+# BLAS calls).  Returns a [site][mu][3][3] complex128 tensor on the device.
+# ---------------------------------------------------------------------------
+def _t_mm(a, b):
+    return (a.unsqueeze(-1) * b.unsqueeze(-3)).sum(-2)
+
+
+def _t_dag(a):
+    return a.transpose(-1, -2).conj()
+
+
+def _t_det(a):
+    return (a[..., 0, 0] * (a[..., 1, 1] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 1])
+            - a[..., 0, 1] * (a[..., 1, 0] * a[..., 2, 2] - a[..., 1, 2] * a[..., 2, 0])
+            + a[..., 0, 2] * (a[..., 1, 0] * a[..., 2, 1] - a[..., 1, 1] * a[..., 2, 0]))
+
+
+def _t_inv(a):
+    import torch
+
+    c = torch.empty_like(a)
+    for i in range(3):
+        for j in range(3):
+            r = [q for q in range(3) if q != j]
+            s = [q for q in range(3) if q != i]
+            m = a[..., r[0], s[0]] * a[..., r[1], s[1]] - a[..., r[0], s[1]] * a[..., r[1], s[0]]
+            c[..., i, j] = m if (i + j) % 2 == 0 else -m
+    return c / _t_det(a)[..., None, None]
+
+
+def _t_reunitarise(u):
+    import torch
+
+    r0 = u[..., 0, :]
+    r0 = r0 / torch.linalg.vector_norm(r0, dim=-1, keepdim=True)
+    r1 = u[..., 1, :]
+    r1 = r1 - (r0.conj() * r1).sum(-1, keepdim=True) * r0
+    r1 = r1 / torch.linalg.vector_norm(r1, dim=-1, keepdim=True)
+    r2 = torch.stack([r0[..., 1] * r1[..., 2] - r0[..., 2] * r1[..., 1],
+                      r0[..., 2] * r1[..., 0] - r0[..., 0] * r1[..., 2],
+                      r0[..., 0] * r1[..., 1] - r0[..., 1] * r1[..., 0]], dim=-1).conj()
+    return torch.stack([r0, r1, r2], dim=-2)
+
+
+def _t_project(w, iters=12):
+    import torch
+
+    x = w
+    for _ in range(iters):
+        x = 0.5 * (x + _t_dag(_t_inv(x)))
+    ph = torch.exp(-1j * torch.angle(_t_det(x)) / 3.0)
+    return _t_reunitarise(x * ph[..., None, None])
+
+
+def _t_random_su3(n, eps, gen, device):
+    import torch
+
+    re = torch.randn((n, 3, 3), generator=gen, device=device, dtype=torch.float64)
+    im = torch.randn((n, 3, 3), generator=gen, device=device, dtype=torch.float64)
+    a = torch.complex(re, im)
+    del re, im
+    h = 0.5 * (a + _t_dag(a))
+    tr = (h[..., 0, 0] + h[..., 1, 1] + h[..., 2, 2]).real / 3.0
+    for q in range(3):
+        h[..., q, q] -= tr
+    # exp(i eps H): Taylor series of degree 14 on A / 2^5, then 5 squarings
+    a = (1j * eps / 32.0) * h
+    u = torch.zeros_like(a)
+    term = torch.zeros_like(a)
+    for q in range(3):
+        u[..., q, q] = 1.0
+        term[..., q, q] = 1.0
+    for k in range(1, 15):
+        term = _t_mm(term, a) / k
+        u = u + term
+    for _ in range(5):
+        u = _t_mm(u, u)
+    return _t_reunitarise(u)
+
+
+def make_gauge_device(dims, eps: float, seed: int, ape_steps: int = 0, ape_alpha: float = 0.5, device="cuda",
+                      chunk: int = 1 << 21, log=None):
+    """The make_gauge recipe on the GPU (see above): [site][mu][3][3] complex128."""
+    import torch
+
+    d = tuple(int(v) for v in dims)
+    vol = lattice_volume(d)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    u = torch.empty((vol * 4, 3, 3), dtype=torch.complex128, device=device)
+    for s in range(0, vol * 4, chunk):
+        e = min(vol * 4, s + chunk)
+        u[s:e] = _t_random_su3(e - s, eps, gen, device)
+    u = u.reshape(d + (4, 3, 3))
+    if log:
+        log("make_gauge_device: SU(3) links drawn")
+    for step in range(ape_steps):
+        out = torch.empty_like(u)
+        for mu in range(4):
+            umu = u[..., mu, :, :]
+            staple = torch.zeros_like(umu)
+            for nu in range(4):
+                if nu == mu:
+                    continue
+                unu = u[..., nu, :, :]
+                # U_nu(x) U_mu(x+nu) U_nu(x+mu)^H
+                staple += _t_mm(_t_mm(unu, torch.roll(umu, -1, nu)), _t_dag(torch.roll(unu, -1, mu)))
+                # U_nu(x-nu)^H U_mu(x-nu) U_nu(x-nu+mu)
+                unu_m = torch.roll(unu, 1, nu)
+                staple += _t_mm(_t_mm(_t_dag(unu_m), torch.roll(umu, 1, nu)), torch.roll(unu_m, -1, mu))
+                del unu_m
+            out[..., mu, :, :] = _t_project((1.0 - ape_alpha) * umu + (ape_alpha / 6.0) * staple)
+            del staple
+        u = out
+        if log:
+            log("make_gauge_device: APE step %d done" % (step + 1))
+    return u.reshape(vol, 4, 3, 3)
