@@ -1025,21 +1025,29 @@ void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s
 // ---------------------------------------------------------------------------
 // row r of a column-major block times v; block entries and v are loaded in
 // batches of RA_BATCH (many loads in flight, the sum still in column order)
+// (a 4-byte complex -- FP16 storage -- is loaded as one 32-bit word and
+// converted after the batch: converting each half as it arrives would make the
+// compiler wait for every load in turn)
+template <class S>
+using cx_word = typename std::conditional<sizeof(cx<S>) == 4, unsigned int, cx<S>>::type;
+
 template <class T, class S, int RA_BATCH>
 __device__ __forceinline__ cx<T> row_apply(const cx<S>* __restrict__ A, int nd, int r, const cx<T>* v) {
+    using W = cx_word<S>;
+    const W* Aw = reinterpret_cast<const W*>(A);
     cx<T> s = czero<T>();
     for (int c0 = 0; c0 < nd; c0 += RA_BATCH) {
-        cx<S> a[RA_BATCH];
+        W a[RA_BATCH];
         cx<T> x[RA_BATCH];
 #pragma unroll
         for (int u = 0; u < RA_BATCH; u++) {
             const bool in = c0 + u < nd;
-            a[u] = in ? A[(size_t)(c0 + u) * nd + r] : cx<S>{S(0), S(0)};
+            a[u] = in ? Aw[(size_t)(c0 + u) * nd + r] : W{};
             x[u] = in ? v[c0 + u] : czero<T>();
         }
 #pragma unroll
         for (int u = 0; u < RA_BATCH; u++)
-            if (c0 + u < nd) s += ccast<T>(a[u]) * x[u];
+            if (c0 + u < nd) s += ccast<T>(__builtin_bit_cast(cx<S>, a[u])) * x[u];
     }
     return s;
 }

@@ -10,7 +10,8 @@ Fields (links exp(i 0.4 H) reunitarised to SU(3), two APE steps, csw 1):
   seeds 4, 5   64 x 32^3      three levels, aggregates 4^4 then 2^4, N 20 / 20
 m0 = m_crit + 0.02 (16^4) or + 0.01 (larger lattices), m_crit from
 tests/golden/mcrit.json (the 16^4 seed-0 value where no other is stored).
-Preconditioner FP32 (mixed precision), FP64 outer FGMRES, tolerance 1e-10.
+Preconditioner FP32 (mixed precision) or FP16 storage, FP64 outer FGMRES(10),
+tolerance 1e-10.
 
 Requests: arrival times from a Poisson process (rate = load x the measured
 capacity of the batched server), field uniform over the six, 1..12 Gaussian
@@ -57,11 +58,16 @@ def field_table(small=False):
 
 
 def field_params(G, f, precision, max_rhs):
+    # outer FGMRES(10): the FP64 Krylov basis of max_rhs RHS is the largest
+    # part of a setup (with FGMRES(25) the six fields need about 250 GB at four
+    # RHS slots, above the 200 GB budget, and the server would evict setups in
+    # the middle of the capacity run)
     if f["levels"] == 3:
         return G.default_params(levels=3, n_tv=[20, 20], agg=[(4, 4, 4, 4), (2, 2, 2, 2)],
-                                sap=[(4, 4, 4, 4), (2, 2, 2, 2)], mr_steps=[4, 4], precision=precision, max_rhs=max_rhs)
+                                sap=[(4, 4, 4, 4), (2, 2, 2, 2)], mr_steps=[4, 4], precision=precision, max_rhs=max_rhs,
+                                outer_restart=10)
     return G.default_params(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[3],
-                            precision=precision, max_rhs=max_rhs)
+                            precision=precision, max_rhs=max_rhs, outer_restart=10)
 
 
 def main():

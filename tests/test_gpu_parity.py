@@ -238,6 +238,43 @@ def test_three_level_components():
     assert rel(to_np(zf), p.o.vcycle(0, r)) < 1e-9
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_multi_rhs_coarse_sap_matches_single(precision):
+    """SAP on the intermediate level for a batch of 6 RHS (one workgroup per
+    block and RHS) equals the one-at-a-time sweeps and matches the oracle."""
+    say("case: multi-RHS coarse SAP, precision", precision)
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    k = 6
+    p = Pair(dims, eps=0.3, seed=5, m0=-0.2, csw=1.0)
+    kw = dict(levels=3, n_tv=[6, 6], agg=[(2, 2, 2, 2), (2, 2, 2, 2)], sap=[(2, 2, 2, 2), (2, 2, 2, 2)],
+              mr_steps=[4, 4])
+    p.o.configure(**kw)
+    p.g.configure(G.default_params(precision=precision, max_rhs=k, **kw))
+    tv0 = p.vectors(0, 6, 1)
+    p.o.set_vectors(0, tv0)
+    p.o.build(0)
+    p.g.set_test_vectors(0, tv0)
+    p.g.build_level(0)
+    tv1 = p.vectors(1, 6, 2)
+    p.o.set_vectors(1, tv1)
+    p.o.build(1)
+    p.g.set_test_vectors(1, tv1)
+    p.g.build_level(1)
+    p.g.mark_setup()
+    p.o.mark_setup()
+    vol1, nd1 = p.o.level_size(1)
+    rng = np.random.default_rng(31)
+    V = rng.standard_normal((k, vol1, nd1)) + 1j * rng.standard_normal((k, vol1, nd1))
+    Z, _ = p.g.apply_batch("SAP", 1, V, arg=2)
+    Z = to_np(Z)
+    for q in range(k):
+        z1, _ = p.g.apply("SAP", 1, V[q], arg=2)
+        assert rel(Z[q].reshape(-1), to_np(z1).reshape(-1)) < (1e-14 if precision == 64 else 1e-6)
+        assert rel(Z[q].reshape(-1), p.o.sap(1, V[q], 2).reshape(-1)) < (1e-12 if precision == 64 else 1e-5)
+
+
 def test_three_level_solve():
     say("case: three-level solve 8^4")
     dims = (8, 8, 8, 8)
