@@ -45,7 +45,7 @@ class FieldSpec:
     est_bytes: int = 0          # HBM the resident setup is admitted with
 
 
-@dataclass
+@dataclass(eq=False)   # requests compare by identity (queue removal)
 class _Request:
     field_id: object
     rhs: object                 # [k][vol][4][3] array-like
@@ -53,6 +53,7 @@ class _Request:
     future: Future
     t_submit: float
     k: int
+    m0: float = None            # mass of this request (None: the field's own)
     next_rhs: int = 0           # first RHS not yet handed to a batch
     done: int = 0
     x: list = field(default_factory=list)
@@ -161,7 +162,11 @@ class Server:
         with self._cv:
             self._fields[field_id] = spec
 
-    def submit(self, field_id, b, tol=1e-10):
+    def submit(self, field_id, b, tol=1e-10, m0=None):
+        """Queue the solves of b (one RHS [vol][4][3] or k of them) on field
+        `field_id`; with m0 the Dirac operator of that mass: the resident setup
+        is moved to it (dd_set_mass: a diagonal shift, no new setup) for the
+        batch, which only holds RHS of one mass."""
         import numpy as np
 
         if field_id not in self._fields:
@@ -172,7 +177,8 @@ class Server:
         k = 1 if len(shape) == 3 else int(shape[0])
         rhs = b if len(shape) == 4 else b.reshape(1, vol, 4, 3)
         fut = Future()
-        req = _Request(field_id, rhs, float(tol), fut, self.clock(), k, x=[None] * k, stats=[None] * k)
+        m = spec.m0 if m0 is None else float(m0)
+        req = _Request(field_id, rhs, float(tol), fut, self.clock(), k, m0=m, x=[None] * k, stats=[None] * k)
         with self._cv:
             if self._closed:
                 raise RuntimeError("server closed")
@@ -257,23 +263,23 @@ class Server:
             self._evict(old)
 
     def _next_batch(self, fid):
-        """Up to max_rhs RHS of field `fid` sharing one tolerance, in arrival
-        order (caller holds the lock)."""
+        """Up to max_rhs RHS of field `fid` sharing one tolerance and one mass,
+        in arrival order (caller holds the lock)."""
         batch = []
-        tol = None
+        tol = m0 = None
         for req in self._pending:
             if req.field_id != fid or req.next_rhs >= req.k:
                 continue
             if tol is None:
-                tol = req.tol
-            if req.tol != tol:
+                tol, m0 = req.tol, req.m0
+            if req.tol != tol or req.m0 != m0:
                 continue
             while req.next_rhs < req.k and len(batch) < self.max_rhs:
                 batch.append((req, req.next_rhs))
                 req.next_rhs += 1
             if len(batch) == self.max_rhs:
                 break
-        return batch, tol
+        return batch, tol, m0
 
     def _dispatch(self):
         while True:
@@ -318,9 +324,11 @@ class Server:
             while True:
                 with self._cv:
                     self._resident.move_to_end(fid)
-                    batch, tol = self._next_batch(fid)
+                    batch, tol, m0 = self._next_batch(fid)
                 if not batch:
                     break
+                if m0 is not None and getattr(solver, "m0", m0) != m0:
+                    solver.set_mass(m0)
                 B = _stack([req.rhs[q] for req, q in batch])
                 X, st = solver.solve_batch(B, tol)
                 t = self.clock()

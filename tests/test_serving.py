@@ -138,6 +138,46 @@ def test_backend_failure_fails_only_that_field():
     srv.close()
 
 
+def test_masses_are_not_mixed_in_a_batch():
+    """Requests at two masses on one field: every batch holds one mass, the
+    resident setup is moved (set_mass) only when the mass changes, and no
+    second setup is made."""
+    masses = []
+
+    class MassSolver(FakeSolver):
+        def __init__(self, spec):
+            super().__init__(spec)
+            self.m0 = spec.m0
+            self.calls = []
+
+        def set_mass(self, m0):
+            self.m0 = m0
+            self.calls.append(m0)
+
+        def solve_batch(self, B, tol):
+            masses.append((self.m0, len(B)))
+            return super().solve_batch(B, tol)
+
+    made = []
+
+    def factory(spec):
+        s = MassSolver(spec)
+        made.append(s)
+        return s
+
+    srv = Server(budget_bytes=1e12, max_rhs=4, solver_factory=factory)
+    srv.add_field("f", (4, 4, 4, 4), None, -0.4, 1.0)
+    futs = [srv.submit("f", np.ones((2, 256, 4, 3)), m0=(-0.4 if i % 2 == 0 else -0.3)) for i in range(6)]
+    res = [f.result(timeout=10) for f in futs]
+    srv.close()
+    assert len(made) == 1
+    assert all(np.allclose(x, 2.0) for x, _ in res)
+    # three requests of 2 RHS per mass: batches of at most 4, never mixed
+    assert sum(k for m, k in masses if m == -0.4) == 6 and sum(k for m, k in masses if m == -0.3) == 6
+    assert all(k <= 4 for _, k in masses)
+    assert len(made[0].calls) <= len(masses)
+
+
 @pytest.mark.gpu
 def test_served_results_equal_solo_solves():
     """Two resident fields of different sizes, requests of 1..5 RHS arriving
@@ -185,3 +225,42 @@ def test_served_results_equal_solo_solves():
                 assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[q]) and sts[q]["converged"]
         solo.close()
     assert st["requests"] == 8 and st["p99_latency_s"] > 0
+
+
+@pytest.mark.gpu
+def test_served_masses_meet_their_residuals():
+    """Requests at two masses on one resident 8^4 setup: each result meets
+    the 1e-10 true residual of the operator at its own mass (the setup is
+    shifted, not rebuilt), and equals the solve of a setup moved to that mass
+    with dd_set_mass directly."""
+    import torch
+
+    import oracle as O
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    U = F.make_gauge(dims, 0.3, 2)
+    kw = dict(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4], n_inv=2, outer_restart=20)
+    masses = (-0.25, -0.2)
+    srv = Server(budget_bytes=50e9, max_rhs=4)
+    srv.add_field("f", dims, U, masses[0], 1.0, params=G.default_params(**kw))
+    reqs = []
+    for i in range(6):
+        m = masses[i % 2]
+        b = F.gaussian_spinor(dims, 600 + i, nrhs=2)
+        reqs.append((m, b, srv.submit("f", torch.as_tensor(b).to("cuda"), m0=m)))
+    out = [(m, b, f.result(timeout=120)) for m, b, f in reqs]
+    srv.close()
+    orc = {m: O.Oracle(dims, U, m, 1.0) for m in masses}
+    solo = G.Solver(dims, U, masses[0], 1.0)
+    solo.setup(params=G.default_params(max_rhs=4, **kw))
+    for m, b, (x, sts) in out:
+        x = x.cpu().numpy()
+        solo.set_mass(m)
+        for q in range(len(b)):
+            r = b[q] - orc[m].apply(x[q])
+            assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[q]) and sts[q]["converged"]
+            xs, _ = solo.solve(b[q], 1e-10)
+            xs = xs.cpu().numpy()
+            assert np.linalg.norm(x[q] - xs) <= 1e-12 * np.linalg.norm(xs)
+    solo.close()
