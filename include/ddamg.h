@@ -53,7 +53,7 @@ typedef enum {
 
 /* Solver parameters (defaults: Table 1 of the paper; see dd_default_params). */
 typedef struct {
-    int levels;                  /* number of levels, 2 or 3                               */
+    int levels;                  /* number of levels, 2 .. DD_MAXLEV                       */
     int n_tv[DD_MAXLEV];         /* test vectors N of the transfer level l -> l+1          */
     int agg[DD_MAXLEV][4];       /* aggregate lattice-block dims on level l (Def. standard
                                     aggregation, Sec. 3.2)                                 */
@@ -65,7 +65,7 @@ typedef struct {
     int coarse_restart;          /* restart length of the coarsest GMRES (30)              */
     int coarse_maxit;            /* iteration cap of one coarsest solve                    */
     int coarse_fixed;            /* >0: run exactly this many coarsest iterations          */
-    double mid_tol;              /* intermediate-level FGMRES relative residual (3 levels) */
+    double mid_tol;              /* intermediate-level FGMRES relative residual (3+ levels)*/
     int mid_restart;
     int mid_maxit;
     int mid_fixed;               /* >0: exactly this many intermediate iterations          */
@@ -197,7 +197,7 @@ typedef enum {
     DD_OP_COARSE_SOLVE = 6, /* out = coarsest-level odd-even GMRES solution for in     */
     DD_OP_SCHUR = 7,        /* out = S in, S = A_oo - D_oe A_ee^-1 D_eo on `level`;
                                in and out are full vectors, zero on even sites        */
-    DD_OP_FGMRES = 8        /* intermediate-level FGMRES (3 levels) on `level`          */
+    DD_OP_FGMRES = 8        /* intermediate-level FGMRES (3+ levels) on `level`         */
 } dd_op;
 
 /* Apply one component.  in/out are device complex128 vectors of the level in

@@ -1294,7 +1294,7 @@ void dd_destroy(dd_ctx* ctx) { delete ctx; }
 
 static void configure_impl(dd_ctx* C, const dd_params* pin) {
     dd_params p = *pin;
-    if (p.levels < 2 || p.levels > 3) fail(DD_EINVAL, "levels must be 2 or 3");
+    if (p.levels < 2 || p.levels > DD_MAXLEV) fail(DD_EINVAL, "levels must be 2 .. " + std::to_string(DD_MAXLEV));
     if (p.precision != 64 && p.precision != 32 && p.precision != 16) fail(DD_EINVAL, "precision must be 64, 32 or 16");
     if (p.outer_restart < 1 || p.outer_restart > 32 || p.coarse_restart < 1 || p.coarse_restart > 32 || p.mid_restart < 1 ||
         p.mid_restart > 32)
