@@ -68,7 +68,7 @@ def load_mcrit(name):
 def c2_problem():
     from paper_1303_1377_amd import fields as F
 
-    info = load_mcrit("c2_16x4_seed0")
+    info = load_mcrit("lat16x4_ape2_seed0")
     dims = tuple(info["dims"])
     U = F.make_gauge(dims, info["eps"], info["seed"], ape_steps=info["ape"], ape_alpha=0.5)
     m0 = info["m_crit"] + 0.02

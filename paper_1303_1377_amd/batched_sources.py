@@ -68,7 +68,7 @@ def main():
     from paper_1303_1377_amd.serving import estimate_bytes
 
     with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
-        m_crit = json.load(f)["c2_16x4_seed0"]["m_crit"]
+        m_crit = json.load(f)["lat16x4_ape2_seed0"]["m_crit"]
     m0 = m_crit + a.shift
     vol = dims[0] * dims[1] * dims[2] * dims[3]
     t0 = time.time()

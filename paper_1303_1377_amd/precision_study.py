@@ -5,7 +5,7 @@ true relative residual and the distance of the solution from the
 FP64-preconditioned one.
 
     python -m paper_1303_1377_amd.precision_study [--dims 64,32,32,32]
-        [--m0 M] [--mcrit-key c3_32c64_seed0] [--precisions 64,32,16]
+        [--m0 M] [--mcrit-key lat64x32c3_ape2_seed0] [--precisions 64,32,16]
         [--solves 2] [--tol 1e-10] [--levels 3]
 
 The field is the 32^3 x 64 workload: links exp(i 0.4 H) reunitarised to
@@ -97,7 +97,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dims", default="64,32,32,32")
     ap.add_argument("--m0", type=float, default=None)
-    ap.add_argument("--mcrit-key", default="c3_32c64_seed0")
+    ap.add_argument("--mcrit-key", default="lat64x32c3_ape2_seed0")
     ap.add_argument("--shift", type=float, default=0.01)
     ap.add_argument("--precisions", default="64,32,16")
     ap.add_argument("--solves", type=int, default=2)

@@ -65,7 +65,7 @@ def main():
     from paper_1303_1377_amd import fields as F
 
     with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
-        m_crit = json.load(f)["c2_16x4_seed0"]["m_crit"]
+        m_crit = json.load(f)["lat16x4_ape2_seed0"]["m_crit"]
     U = F.make_gauge(dims, 0.4, 0, ape_steps=2, ape_alpha=0.5)
     B = [torch.as_tensor(F.gaussian_spinor(dims, 3000 + i)).to("cuda") for i in range(a.solves)]
     out = dict(dims=list(dims), m_crit=m_crit, solves=a.solves)

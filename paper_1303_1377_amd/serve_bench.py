@@ -43,8 +43,8 @@ def _log(*a):
 def field_table(small=False):
     with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
         mc = json.load(f)
-    base = mc["c2_16x4_seed0"]["m_crit"]
-    c3 = mc.get("c3_32c64_seed0", {}).get("m_crit", base)
+    base = mc["lat16x4_ape2_seed0"]["m_crit"]
+    c3 = mc.get("lat64x32c3_ape2_seed0", {}).get("m_crit", base)
     if small:
         return [dict(seed=s, dims=d, m0=base + 0.02, levels=2) for s, d in
                 ((0, (8, 8, 8, 8)), (1, (8, 8, 8, 8)), (2, (16, 8, 8, 8)), (3, (16, 8, 8, 8)), (4, (8, 8, 8, 16)),

@@ -21,14 +21,14 @@ from paper_1303_1377_amd import fields as F  # noqa: E402
 
 # lattice (T,X,Y,Z), link spread eps, APE steps (alpha 0.5), seed, csw
 FIELDS = {
-    "c2_16x4_seed0": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=0, csw=1.0),
-    "c2_16x4_seed1": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=1, csw=1.0),
-    "c1_4x4_seed0": dict(dims=(4, 4, 4, 4), eps=0.3, ape=0, seed=0, csw=1.0),
+    "lat16x4_ape2_seed0": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=0, csw=1.0),
+    "lat16x4_ape2_seed1": dict(dims=(16, 16, 16, 16), eps=0.4, ape=2, seed=1, csw=1.0),
+    "lat4x4_seed0": dict(dims=(4, 4, 4, 4), eps=0.3, ape=0, seed=0, csw=1.0),
     "t_8x4_seed0": dict(dims=(8, 8, 8, 8), eps=0.4, ape=2, seed=0, csw=1.0),
-    "c3_32c64_seed0": dict(dims=(64, 32, 32, 32), eps=0.4, ape=2, seed=0, csw=1.0),
+    "lat64x32c3_ape2_seed0": dict(dims=(64, 32, 32, 32), eps=0.4, ape=2, seed=0, csw=1.0),
 }
 # Krylov space size per field (memory: ncv vectors of 12*volume complex numbers)
-NCV = {"c3_32c64_seed0": 32}
+NCV = {"lat64x32c3_ape2_seed0": 32}
 
 
 def mcrit(dims, eps, ape, seed, csw, k=4, tol=1e-5, ncv=64):

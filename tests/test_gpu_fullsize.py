@@ -29,7 +29,7 @@ class Full:
         import paper_1303_1377_amd as G
 
         with open(os.path.join(ROOT, "tests", "golden", "mcrit.json")) as f:
-            info = json.load(f)["c2_16x4_seed0"]
+            info = json.load(f)["lat16x4_ape2_seed0"]
         self.dims = tuple(info["dims"])
         self.m0 = info["m_crit"] + 0.02
         self.csw = info["csw"]
@@ -57,7 +57,7 @@ class Full:
 
 @pytest.fixture(scope="module")
 def full():
-    say("case: full size 16^4, C2 field and parameters")
+    say("case: full size 16^4, the benchmarked field and parameters")
     return Full()
 
 

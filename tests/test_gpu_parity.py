@@ -10,13 +10,13 @@ from tests._gpu import Pair, rel, say, to_np
 
 pytestmark = pytest.mark.gpu
 
-C1 = (4, 4, 4, 4)
+L4 = (4, 4, 4, 4)
 
 
 @pytest.fixture(scope="module")
-def c1():
-    say("case: C1 pair 4^4 eps=0.3 seed=0 m0=-0.4")
-    return Pair(C1, eps=0.3, seed=0, m0=-0.4, csw=1.0)
+def p4():
+    say("case: pair 4^4 eps=0.3 seed=0 m0=-0.4")
+    return Pair(L4, eps=0.3, seed=0, m0=-0.4, csw=1.0)
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 4), (4, 8, 2, 4), (2, 2, 2, 2), (8, 8, 4, 8)])
@@ -28,14 +28,14 @@ def test_dirac_fp64(dims):
     assert rel(to_np(out), p.o.apply(psi)) < 1e-13
 
 
-def test_dirac_fp32_and_clover(c1):
+def test_dirac_fp32_and_clover(p4):
     say("case: dirac fp32 + clover blocks")
-    c1.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)])
-    psi = F.gaussian_spinor(C1, 6)
-    out, _ = c1.g.apply("D_PREC", 0, psi)
-    assert rel(to_np(out), c1.o.apply(psi)) < 2e-6
-    A, Ai = c1.g.get_clover()
-    Ao, Aio = c1.o.clover()
+    p4.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)])
+    psi = F.gaussian_spinor(L4, 6)
+    out, _ = p4.g.apply("D_PREC", 0, psi)
+    assert rel(to_np(out), p4.o.apply(psi)) < 2e-6
+    A, Ai = p4.g.get_clover()
+    Ao, Aio = p4.o.clover()
     assert rel(to_np(A), Ao) < 1e-14
     assert rel(to_np(Ai), Aio) < 1e-12
 
@@ -65,12 +65,12 @@ def test_sap_fp64(dims, blk, mr, nu):
     assert rel(to_np(z), p.o.sap(0, b, nu)) < 1e-12
 
 
-def test_sap_fp32(c1):
+def test_sap_fp32(p4):
     say("case: sap fp32")
-    c1.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4])
-    b = F.gaussian_spinor(C1, 2)
-    z, _ = c1.g.apply("SAP", 0, b, arg=2)
-    assert rel(to_np(z), c1.o.sap(0, b, 2)) < 1e-5
+    p4.configure(precision=32, levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4])
+    b = F.gaussian_spinor(L4, 2)
+    z, _ = p4.g.apply("SAP", 0, b, arg=2)
+    assert rel(to_np(z), p4.o.sap(0, b, 2)) < 1e-5
 
 
 def _built(p, n, agg, sap, seed=7, precision=64, **kw):
@@ -96,58 +96,58 @@ def test_build_P_and_coarse_operator(dims, agg, n):
     assert rel(to_np(Mi), Mio) < 1e-10
 
 
-def test_transfer_and_coarse_ops(c1):
+def test_transfer_and_coarse_ops(p4):
     say("case: restrict/prolong/D_c/Schur")
-    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2))
-    v = F.gaussian_spinor(C1, 11)
-    rc, _ = c1.g.apply("RESTRICT", 0, v)
-    assert rel(to_np(rc), c1.o.restrict(0, v)) < 1e-13
-    vol_c, ndc = c1.o.level_size(1)
+    _built(p4, 8, (2, 2, 2, 2), (2, 2, 2, 2))
+    v = F.gaussian_spinor(L4, 11)
+    rc, _ = p4.g.apply("RESTRICT", 0, v)
+    assert rel(to_np(rc), p4.o.restrict(0, v)) < 1e-13
+    vol_c, ndc = p4.o.level_size(1)
     rng = np.random.default_rng(5)
     vc = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
-    pr, _ = c1.g.apply("PROLONG", 0, vc)
-    assert rel(to_np(pr), c1.o.prolong(0, vc)) < 1e-13
-    dc, _ = c1.g.apply("D", 1, vc)
-    assert rel(to_np(dc), c1.o.apply(vc, level=1)) < 1e-13
-    sc, _ = c1.g.apply("SCHUR", 1, vc)
-    so = c1.o.schur(1, vc)
+    pr, _ = p4.g.apply("PROLONG", 0, vc)
+    assert rel(to_np(pr), p4.o.prolong(0, vc)) < 1e-13
+    dc, _ = p4.g.apply("D", 1, vc)
+    assert rel(to_np(dc), p4.o.apply(vc, level=1)) < 1e-13
+    sc, _ = p4.g.apply("SCHUR", 1, vc)
+    so = p4.o.schur(1, vc)
     assert rel(to_np(sc), so) < 1e-13
 
 
 @pytest.mark.parametrize("fixed", [1, 5, 37])
-def test_coarse_solve_fixed_iterations(c1, fixed):
+def test_coarse_solve_fixed_iterations(p4, fixed):
     say("case: coarse GMRES fixed", fixed)
-    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=fixed)
-    vol_c, ndc = c1.o.level_size(1)
+    _built(p4, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=fixed)
+    vol_c, ndc = p4.o.level_size(1)
     rng = np.random.default_rng(8)
     r = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
-    e, its = c1.g.apply("COARSE_SOLVE", 1, r)
-    eo, itso = c1.o.coarse_solve(1, r)
+    e, its = p4.g.apply("COARSE_SOLVE", 1, r)
+    eo, itso = p4.o.coarse_solve(1, r)
     assert its == itso == fixed
     assert rel(to_np(e), eo) < 1e-10
 
 
-def test_coarse_solve_tolerance(c1):
+def test_coarse_solve_tolerance(p4):
     say("case: coarse GMRES to 5e-2")
-    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2))
-    vol_c, ndc = c1.o.level_size(1)
+    _built(p4, 8, (2, 2, 2, 2), (2, 2, 2, 2))
+    vol_c, ndc = p4.o.level_size(1)
     rng = np.random.default_rng(9)
     r = rng.standard_normal((vol_c, ndc)) + 1j * rng.standard_normal((vol_c, ndc))
-    e, its = c1.g.apply("COARSE_SOLVE", 1, r)
-    eo, itso = c1.o.coarse_solve(1, r)
+    e, its = p4.g.apply("COARSE_SOLVE", 1, r)
+    eo, itso = p4.o.coarse_solve(1, r)
     assert abs(its - itso) <= 1
-    res = r - c1.o.apply(to_np(e), level=1)
+    res = r - p4.o.apply(to_np(e), level=1)
     assert np.linalg.norm(res) <= 5e-2 * np.linalg.norm(r) * 1.5
 
 
-def test_vcycle_fixed(c1):
+def test_vcycle_fixed(p4):
     say("case: V-cycle with fixed coarse iterations")
-    _built(c1, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=12, mr_steps=[4], nu=2)
-    c1.g.mark_setup()
-    c1.o.mark_setup()
-    r = F.gaussian_spinor(C1, 12)
-    z, _ = c1.g.apply("VCYCLE", 0, r)
-    assert rel(to_np(z), c1.o.vcycle(0, r)) < 1e-10
+    _built(p4, 8, (2, 2, 2, 2), (2, 2, 2, 2), coarse_fixed=12, mr_steps=[4], nu=2)
+    p4.g.mark_setup()
+    p4.o.mark_setup()
+    r = F.gaussian_spinor(L4, 12)
+    z, _ = p4.g.apply("VCYCLE", 0, r)
+    assert rel(to_np(z), p4.o.vcycle(0, r)) < 1e-10
 
 
 @pytest.mark.parametrize("dims,agg,n,n_inv", [((4, 4, 4, 4), (2, 2, 2, 2), 8, 2), ((8, 8, 8, 8), (4, 4, 4, 4), 8, 1)])
@@ -168,35 +168,35 @@ def test_setup_given_vectors(dims, agg, n, n_inv):
     assert rel(to_np(p.g.get_coarse(1)[0]), p.o.get_coarse(1)[0]) < 1e-9
 
 
-def test_solve_c1_fp64(c1):
+def test_solve_4x4_fp64(p4):
     """Configuration 1: 4^4, 2 levels, 2^4 aggregates and SAP blocks, N = 8,
     FGMRES(20) to 1e-10; both solutions meet the true residual and agree."""
-    say("case: C1 solve fp64")
+    say("case: 4^4 solve fp64")
     import paper_1303_1377_amd as G
 
     kw = dict(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4], n_inv=6, outer_restart=20)
-    c1.configure(**kw)
-    tv = c1.vectors(0, 8, 2024)
-    c1.g.set_test_vectors(0, tv)
-    c1.g.setup(params=G.default_params(given_vectors=1, **kw))
-    c1.o.setup([tv])
-    b = F.gaussian_spinor(C1, 1000)
-    x, st = c1.g.solve(b, 1e-10)
-    xo, sto = c1.o.solve(b, 1e-10)
+    p4.configure(**kw)
+    tv = p4.vectors(0, 8, 2024)
+    p4.g.set_test_vectors(0, tv)
+    p4.g.setup(params=G.default_params(given_vectors=1, **kw))
+    p4.o.setup([tv])
+    b = F.gaussian_spinor(L4, 1000)
+    x, st = p4.g.solve(b, 1e-10)
+    xo, sto = p4.o.solve(b, 1e-10)
     xn = to_np(x)
-    r = b - c1.o.apply(xn)
+    r = b - p4.o.apply(xn)
     relres = np.linalg.norm(r) / np.linalg.norm(b)
     say("gpu its", st["outer_iters"], "oracle its", sto["outer_iters"], "relres", relres)
     assert st["converged"] and relres <= 1e-10
     assert np.linalg.norm(xn - xo) / np.linalg.norm(xo) <= 1e-8
 
 
-def test_solve_c1_fp32_preconditioner(c1):
-    say("case: C1 solve with fp32 preconditioner")
-    c1.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, precision=32, mr_steps=[4], outer_restart=20)
-    b = F.gaussian_spinor(C1, 1001)
-    x, st = c1.g.solve(b, 1e-10)
-    r = b - c1.o.apply(to_np(x))
+def test_solve_4x4_fp32_preconditioner(p4):
+    say("case: 4^4 solve with fp32 preconditioner")
+    p4.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, precision=32, mr_steps=[4], outer_restart=20)
+    b = F.gaussian_spinor(L4, 1001)
+    x, st = p4.g.solve(b, 1e-10)
+    r = b - p4.o.apply(to_np(x))
     assert st["converged"] and np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
 
 
@@ -426,14 +426,14 @@ def test_solve_batch_three_levels():
         assert np.linalg.norm(X[q] - to_np(x1)) <= 1e-12 * np.linalg.norm(to_np(x1))
 
 
-def test_batch_argument_errors(c1):
+def test_batch_argument_errors(p4):
     """max_rhs outside 1..16 is rejected; k = 0 is a no-op."""
     import paper_1303_1377_amd as G
 
     with pytest.raises(RuntimeError):
-        c1.g.configure(G.default_params(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], max_rhs=17))
-    c1.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, mr_steps=[4], outer_restart=20, max_rhs=2)
-    X, st = c1.g.solve_batch(np.zeros((0, int(np.prod(C1)), 4, 3), dtype=np.complex128))
+        p4.g.configure(G.default_params(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], max_rhs=17))
+    p4.g.setup(n_tv=8, block=(2, 2, 2, 2), levels=2, params=None, mr_steps=[4], outer_restart=20, max_rhs=2)
+    X, st = p4.g.solve_batch(np.zeros((0, int(np.prod(L4)), 4, 3), dtype=np.complex128))
     assert X.shape[0] == 0 and st == []
 
 
