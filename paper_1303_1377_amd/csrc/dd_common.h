@@ -36,6 +36,22 @@ template <class T> __host__ __device__ __forceinline__ cx<T> times_mi(cx<T> a) {
 template <class T> __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 template <class T> __host__ __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
 template <class D, class S> __host__ __device__ __forceinline__ cx<D> ccast(cx<S> a) { return {D(a.re), D(a.im)}; }
+// fused multiply-add; acc += a b and acc += conj(a) b as four of them (written
+// out: the compiler does not contract a sum of products into an accumulator)
+__host__ __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <class T> __host__ __device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.re = fmadd(a.re, b.re, acc.re);
+    acc.re = fmadd(-a.im, b.im, acc.re);
+    acc.im = fmadd(a.re, b.im, acc.im);
+    acc.im = fmadd(a.im, b.re, acc.im);
+}
+template <class T> __host__ __device__ __forceinline__ void cmacc(cx<T>& acc, cx<T> a, cx<T> b) {
+    acc.re = fmadd(a.re, b.re, acc.re);
+    acc.re = fmadd(a.im, b.im, acc.re);
+    acc.im = fmadd(a.re, b.im, acc.im);
+    acc.im = fmadd(-a.im, b.re, acc.im);
+}
 
 // ---------------------------------------------------------------------------
 // lattice layout
@@ -160,10 +176,10 @@ template <class T>
 __host__ __device__ __forceinline__ void su3_two_spinor(const cx<T> u[9], bool dag, const cx<T> h[6], cx<T> g[6]) {
     for (int s = 0; s < 2; s++)
         for (int a = 0; a < 3; a++) {
-            cx<T> acc = czero<T>();
-            for (int b = 0; b < 3; b++) {
-                if (dag) acc += cmulc(u[b * 3 + a], h[s * 3 + b]);
-                else acc += u[a * 3 + b] * h[s * 3 + b];
+            cx<T> acc = dag ? cmulc(u[a], h[s * 3]) : u[a * 3] * h[s * 3];
+            for (int b = 1; b < 3; b++) {
+                if (dag) cmacc(acc, u[b * 3 + a], h[s * 3 + b]);
+                else cmac(acc, u[a * 3 + b], h[s * 3 + b]);
             }
             g[s * 3 + a] = acc;
         }
@@ -185,10 +201,10 @@ __host__ __device__ __forceinline__ void herm6_apply(const T m[36], const cx<T>*
             if (j == i) continue;
             if (j > i) {
                 int k = herm_off(i, j);
-                acc += cx<T>{m[6 + 2 * k], m[7 + 2 * k]} * in[j];
+                cmac(acc, cx<T>{m[6 + 2 * k], m[7 + 2 * k]}, in[j]);
             } else {
                 int k = herm_off(j, i);
-                acc += cmulc(cx<T>{m[6 + 2 * k], m[7 + 2 * k]}, in[j]);
+                cmacc(acc, cx<T>{m[6 + 2 * k], m[7 + 2 * k]}, in[j]);
             }
         }
         out[i] = acc;

@@ -602,10 +602,10 @@ void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// SAP half sweep: one workgroup per lattice block of the active colour, one
-// thread per block site (threads [0, bvh) the even sites, [bvh, 2 bvh) the odd
-// sites, same local layout index).  With r = b - D z restricted to the block
-// and H the hopping part of D:
+// SAP half sweep: one workgroup per lattice block of the active colour, two
+// lanes per pair of block sites (the even and the odd site of one local layout
+// index), each lane holding one chirality half of both.  With r = b - D z
+// restricted to the block and H the hopping part of D:
 //   t0_e = A_e^{-1}(b_e - (H z)_e) - z_e               (= A_ee^{-1} r_e)
 //   f_o  = b_o - A_o z_o - (H z)_o - (H_int t0)_o        (= r_o - D_oe A_ee^{-1} r_e)
 //   MR on S = A_oo - D_oe A_ee^{-1} D_eo (block-internal hops) from e_o = 0
@@ -613,9 +613,10 @@ void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t
 //   z   += e on the block
 // The block's operator stays on chip for the whole half sweep: the links
 // joining two sites of the block live in LDS as their first two rows (the
-// third row of an SU(3) matrix is conj(row0 x row1)), each thread keeps the
-// clover block of its site (A^{-1} on even, A on odd sites) in registers, and
-// the block fields E (even) and O (odd) are exchanged through LDS.  Every
+// third row of an SU(3) matrix is conj(row0 x row1)), each lane keeps its
+// chirality half of the clover blocks (A^{-1} at the even, A at the odd site)
+// in registers, and the block fields E (even) and O (odd) are exchanged
+// through LDS.  Every
 // link, clover entry and spinor is therefore read from memory once per half
 // sweep.  The MR inner products are wavefront shuffles plus one LDS step.
 // ---------------------------------------------------------------------------
@@ -652,9 +653,15 @@ __device__ __forceinline__ bool link_internal(const Geom& g, int mu, const int l
 
 template <class T>
 __device__ __forceinline__ void su3_rebuild(cx<T> u[9]) {
-    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    // conj(a b - c d) as products and fused multiply-adds
+    auto cross = [](cx<T> a, cx<T> b, cx<T> c, cx<T> d) {
+        cx<T> r = -(c * d);
+        cmac(r, a, b);
+        return conj(r);
+    };
+    u[6] = cross(u[1], u[5], u[2], u[4]);
+    u[7] = cross(u[2], u[3], u[0], u[5]);
+    u[8] = cross(u[0], u[4], u[1], u[3]);
 }
 
 template <class T>
@@ -701,17 +708,6 @@ __device__ __forceinline__ void sap_hop(const FineOp<T, S>& op, int ltot, const 
     spin_reconstruct(mu, sgn, gg, acc);
 }
 
-template <class T, class S>
-__device__ __forceinline__ void clover_regs(const S* __restrict__ cl, int vh, int p, int i, T m[72]) {
-#pragma unroll
-    for (int r = 0; r < 72; r++) m[r] = T(cl[(size_t)(p * 72 + r) * vh + i]);
-}
-template <class T>
-__device__ __forceinline__ void clover_reg_apply(const T m[72], const cx<T> v[12], cx<T> out[12]) {
-    herm6_apply(m, v, out);
-    herm6_apply(m + 36, v + 6, out + 6);
-}
-
 // value of the partner lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
 __device__ __forceinline__ float pair_swap(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
@@ -721,6 +717,93 @@ __device__ __forceinline__ double pair_swap(double v) {
     const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// chirality half h (spins 2h, 2h + 1) of a spinor: global memory and the LDS block fields
+template <class T>
+__device__ __forceinline__ void half_load(const cx<T>* psi, int vh, int p, int h, int i, cx<T> v[6]) {
+    const cx<T>* base = psi + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+    for (int c = 0; c < 6; c++) v[c] = base[(size_t)c * vh];
+}
+template <class T>
+__device__ __forceinline__ void half_store(cx<T>* psi, int vh, int p, int h, int i, const cx<T> v[6]) {
+    cx<T>* base = psi + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+    for (int c = 0; c < 6; c++) base[(size_t)c * vh] = v[c];
+}
+template <class T>
+__device__ __forceinline__ void lds_load6(const cx<T>* buf, int bvh, int h, int l, cx<T> v[6]) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) v[c] = buf[(6 * h + c) * bvh + l];
+}
+template <class T>
+__device__ __forceinline__ void lds_store6(cx<T>* buf, int bvh, int h, int l, const cx<T> v[6]) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) buf[(6 * h + c) * bvh + l] = v[c];
+}
+template <class T, class S>
+__device__ __forceinline__ void clover_half_regs(const S* __restrict__ cl, int vh, int p, int h, int i, T m[36]) {
+    const S* base = cl + (size_t)(p * 72 + h * 36) * vh + i;
+#pragma unroll
+    for (int r = 0; r < 36; r++) m[r] = T(base[(size_t)r * vh]);
+}
+
+// One block-internal hop of a site for the pair lane of chirality half h, in
+// direction mu = 2h + Q, forward (FWD: neighbour x + mu, link U_mu(x), factor
+// I - gamma_mu) or backward (x - mu, U_mu(x - mu)^H, I + gamma_mu).  With the
+// chiral gamma matrices of dd_common.h the projection is h = psi_up + s B_mu
+// psi_lo and the result (g, s B_mu^H g), g = U h, s = -1 forward, +1 backward.
+// For the two directions of one lane the lower spin that feeds h_0 is the same
+// (lo_1 on lane 0: mu = 0, 1; lo_0 on lane 1: mu = 2, 3), read at LDS offset
+// oa (the other one at ob), and the remaining differences between B_0 / B_2
+// and B_1 / B_3 are one sign, tau = +1 on lane 0 and -1 on lane 1:
+//   Q = 0:  h_0 = u_0 + s i La,       h_1 = u_1 + s tau i Lb,
+//           X  += s (-i) g_0,         Y  += s tau (-i) g_1,
+//   Q = 1:  h_0 = u_0 - s tau La,     h_1 = u_1 + s Lb,
+//           X  += -s tau g_0,         Y  += s g_1,
+// where X is the lower spin fed by g_0 (lo_1 on lane 0, lo_0 on lane 1) and Y
+// the one fed by g_1; up collects g itself.  code: the hop-table entry (LDS
+// slot of the link << 8 | neighbour's local index), -1 for a hop that leaves
+// the block.
+template <class T, int Q, bool FWD>
+__device__ __forceinline__ void pair_hop(const cx<T>* __restrict__ L, int ltot, int code, const cx<T>* buf, int bvh,
+                                         int oa, int ob, T tau, cx<T> up[6], cx<T> X[3], cx<T> Y[3]) {
+    if (code < 0) return;
+    const int j = code & 255, li = code >> 8;
+    cx<T> u[9];
+#pragma unroll
+    for (int e = 0; e < 6; e++) u[e] = L[e * ltot + li];
+    su3_rebuild(u);
+    const T s = FWD ? T(-1) : T(1);
+    const T st = s * tau;
+    cx<T> hv[6];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<T> u0 = buf[c * bvh + j], u1 = buf[(3 + c) * bvh + j];
+        const cx<T> la = buf[oa + c * bvh + j], lb = buf[ob + c * bvh + j];
+        if (Q == 0) {
+            hv[c] = {u0.re - s * la.im, u0.im + s * la.re};
+            hv[3 + c] = {u1.re - st * lb.im, u1.im + st * lb.re};
+        } else {
+            hv[c] = {u0.re - st * la.re, u0.im - st * la.im};
+            hv[3 + c] = {u1.re + s * lb.re, u1.im + s * lb.im};
+        }
+    }
+    cx<T> gv[6];
+    su3_two_spinor(u, !FWD, hv, gv);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        up[c] += gv[c];
+        up[3 + c] += gv[3 + c];
+        if (Q == 0) {
+            X[c] += cx<T>{s * gv[c].im, -s * gv[c].re};
+            Y[c] += cx<T>{st * gv[3 + c].im, -st * gv[3 + c].re};
+        } else {
+            X[c] -= st * gv[c];
+            Y[c] += s * gv[3 + c];
+        }
+    }
 }
 
 // MINW: waves per SIMD the register allocation must allow (2 for FP32 fields,
@@ -743,19 +826,21 @@ __global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const i
     double* red = reinterpret_cast<double*>(tab + 8 * ntab);
     const int blk = blocks[(op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x];
     const int base = blk << g.lbvh;
-    // lanes 2l (even site l) and 2l + 1 (odd site l) are partners: when only one
-    // parity's sites are updated, each of the two computes half of the hops of
-    // that parity's site l (lane p: hops 4p .. 4p+3) and the halves meet
-    // through one lane swap, so no lane idles in the hopping parts
+    // Lanes 2l and 2l + 1 form a pair that owns the even site l and the odd
+    // site l of the block.  Lane h holds chirality half h (spins 2h, 2h + 1) of
+    // both sites' block vectors and of both clover blocks, so every clover
+    // product and MR update is local to the lane; a hopping sum is split over
+    // the pair by direction (lane h: mu = 2h, 2h + 1) and the halves meet
+    // through one lane swap.  Only the residual, with its hops to other blocks,
+    // is computed per site (lane h: the site of parity h).
     const int t = threadIdx.x;
     const bool act = t < 2 * bvh;
-    const int p = t & 1;
+    const int h = t & 1;
     const int l = act ? t >> 1 : 0;
     const int i = base + l;
-    const int sidx = p * bvh + l;
-    const bool ev = act && p == 0, od = act && p == 1;
+    const int sidx = h * bvh + l;
     int x[4];
-    cb_coords(g, p, i, x);
+    cb_coords(g, h, i, x);
     if (act) {
         int lc[4];
 #pragma unroll
@@ -775,100 +860,124 @@ __global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const i
             tab[k * ntab + sidx] = (slot >= 0) ? ((slot << 8) | (j - base)) : -1;
             // own forward link inside the block -> LDS (two rows)
             if (k < 4 && slot >= 0) {
-                const cx<S>* src = op.U + (size_t)(p * 4 + mu) * 9 * g.vh + i;
+                const cx<S>* src = op.U + (size_t)(h * 4 + mu) * 9 * g.vh + i;
 #pragma unroll
                 for (int e = 0; e < 6; e++) L[e * ltot + slot] = ccast<T>(src[(size_t)e * g.vh]);
             }
         }
     }
-    // clover block of the site: A^{-1} on even, A on odd sites
-    T m[72];
-    clover_regs(p == 0 ? op.clovinv : op.clov, g.vh, p, i, m);
+    // chirality half h of the clover blocks: A^{-1} at the even site, A at the odd site
+    T me[36], mo[36];
+    clover_half_regs(op.clovinv, g.vh, 0, h, i, me);
+    clover_half_regs(op.clov, g.vh, 1, h, i, mo);
     __syncthreads();
     const int lane = t & 63, wv = t >> 6, nw = (blockDim.x + 63) >> 6;
-    // hopping sum of the block-internal hops of site (P, l) over the field buf,
-    // in both partner lanes
-    auto pair_hops = [&](int P, const cx<T>* buf, cx<T> a[12]) {
+    const T tau = h ? T(-1) : T(1);
+    const int oa = (h ? 6 : 9) * bvh, ob = (h ? 9 : 6) * bvh;
+    // chirality half h of the block-internal hopping sum at the site (P, l)
+    // over the field buf (the neighbours' parity)
+    auto pair_hops = [&](int P, const cx<T>* buf, cx<T> R[6]) {
+        cx<T> up[6], X[3], Y[3];
 #pragma unroll
-        for (int c = 0; c < 12; c++) a[c] = czero<T>();
-#pragma unroll 1
-        for (int k = 4 * p; k < 4 * p + 4; k++)
-            sap_hop<T, S, true>(op, ltot, L, tab, ntab, k, P * bvh + l, P, i, x, base, buf, nullptr, a);
+        for (int c = 0; c < 6; c++) up[c] = czero<T>();
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            a[c].re += pair_swap(a[c].re);
-            a[c].im += pair_swap(a[c].im);
+        for (int c = 0; c < 3; c++) X[c] = Y[c] = czero<T>();
+        const int* tp = tab + P * bvh + l;
+        const int d0 = 2 * h;
+        pair_hop<T, 0, true>(L, ltot, tp[d0 * ntab], buf, bvh, oa, ob, tau, up, X, Y);
+        pair_hop<T, 0, false>(L, ltot, tp[(4 + d0) * ntab], buf, bvh, oa, ob, tau, up, X, Y);
+        pair_hop<T, 1, true>(L, ltot, tp[(1 + d0) * ntab], buf, bvh, oa, ob, tau, up, X, Y);
+        pair_hop<T, 1, false>(L, ltot, tp[(5 + d0) * ntab], buf, bvh, oa, ob, tau, up, X, Y);
+        // lane 0 keeps the upper spins and sends its lower-spin parts in the
+        // order (lo_0, lo_1) = (Y, X); lane 1 keeps (lo_0, lo_1) = (X, Y) and
+        // sends its upper spins
+        cx<T> snd[6];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            snd[c] = h ? up[c] : Y[c];
+            snd[3 + c] = h ? up[3 + c] : X[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            const cx<T> keep = h ? (c < 3 ? X[c] : Y[c - 3]) : up[c];
+            R[c] = {keep.re + pair_swap(snd[c].re), keep.im + pair_swap(snd[c].im)};
         }
     };
     for (int rhs = 0; rhs < nr; rhs++) {
     if (!mk.on(rhs)) continue;
     const cx<T>* __restrict__ b = b0 + rhs * ld;
     cx<T>* __restrict__ z = z0 + rhs * ld;
-    cx<T> acc[12], v[12], w[12], pv[12];  // pv: t0 (even lanes) or e_o (odd lanes)
-    // ---- residual on the block: every lane its own site, all 8 hops ----
+    // half h of: e_o, rho (the odd MR residual), w, R
+    cx<T> eo[6], rho[6], w[6], R[6];
+    // ---- residual on the block, b - H z with all 8 hops of the lane's own site ----
     if (act) {
+        cx<T> acc[12], v[12];
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, sidx, p, i, x, base, nullptr, z, acc);
-        load_spinor(b, g.vh, p, i, v);
+        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, sidx, h, i, x, base, nullptr, z, acc);
+        load_spinor(b, g.vh, h, i, v);
 #pragma unroll
-        for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];  // b - H z
-        load_spinor(z, g.vh, p, i, acc);
-        if (ev) {
-            clover_reg_apply(m, v, pv);
-#pragma unroll
-            for (int c = 0; c < 12; c++) pv[c] -= acc[c];      // t0
-            lds_store(E, bvh, l, pv);
-        } else {
-            clover_reg_apply(m, acc, w);
-#pragma unroll
-            for (int c = 0; c < 12; c++) w[c] = v[c] - w[c];   // r_o
-            lds_store(O, bvh, l, w);
-        }
+        for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];
+        lds_store(h ? O : E, bvh, l, v);
     }
     __syncthreads();
     if (act) {
-        pair_hops(1, E, acc);
-        if (od) {
-            lds_load(O, bvh, l, v);
+        cx<T> vh6[6], zh[6], t0[6];
+        // t0_e = A_e^{-1} (b - H z)_e - z_e
+        lds_load6(E, bvh, h, l, vh6);
+        half_load(z, g.vh, 0, h, i, zh);
+        herm6_apply(me, vh6, t0);
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                v[c] += T(0.5) * acc[c];  // rho = f_o
-                pv[c] = czero<T>();       // e_o = 0
-            }
+        for (int c = 0; c < 6; c++) {
+            t0[c] -= zh[c];
+            zh[c] += t0[c];
         }
+        // z_e + t0 now (the block's z has been read by all its lanes), the
+        // rest of e_e after the MR steps: t0 need not stay in registers
+        half_store(z, g.vh, 0, h, i, zh);
+        // r_o = (b - H z)_o - A_o z_o
+        lds_load6(O, bvh, h, l, vh6);
+        half_load(z, g.vh, 1, h, i, zh);
+        herm6_apply(mo, zh, w);
+#pragma unroll
+        for (int c = 0; c < 6; c++) rho[c] = vh6[c] - w[c];
+        lds_store6(E, bvh, h, l, t0);  // each lane overwrites only the half it read
     }
     __syncthreads();
-    if (od) lds_store(O, bvh, l, v);
+    if (act) {
+        // rho = f_o = r_o - D_oe t0, e_o = 0
+        pair_hops(1, E, R);
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            rho[c] += T(0.5) * R[c];
+            eo[c] = czero<T>();
+        }
+        lds_store6(O, bvh, h, l, rho);
+    }
     __syncthreads();
     for (int it = 0; it < mr_steps; it++) {
-        // even: t = A^{-1} (H_int rho), H = -1/2 hopsum
+        // even: w_e = A_e^{-1} (H_int rho), H = -1/2 hopsum
         if (act) {
-            pair_hops(0, O, acc);
-            if (ev) {
+            pair_hops(0, O, R);
 #pragma unroll
-                for (int c = 0; c < 12; c++) acc[c] = T(-0.5) * acc[c];
-                clover_reg_apply(m, acc, w);
-            }
+            for (int c = 0; c < 6; c++) R[c] = T(-0.5) * R[c];
+            herm6_apply(me, R, w);
+            lds_store6(E, bvh, h, l, w);
         }
         __syncthreads();
-        if (ev) lds_store(E, bvh, l, w);
-        __syncthreads();
-        // odd: s = A rho - H_int t
+        // odd: w_o = A_o rho - H_int w_e
         double sr = 0, si = 0, ss = 0;
         if (act) {
-            pair_hops(1, E, acc);
-            if (od) {
-                clover_reg_apply(m, v, w);
+            pair_hops(1, E, R);
+            herm6_apply(mo, rho, w);
 #pragma unroll
-                for (int c = 0; c < 12; c++) {
-                    w[c] += T(0.5) * acc[c];
-                    cx<T> d = cmulc(w[c], v[c]);
-                    sr += d.re;
-                    si += d.im;
-                    ss += norm2(w[c]);
-                }
+            for (int c = 0; c < 6; c++) {
+                w[c] += T(0.5) * R[c];
+                cx<T> d = cmulc(w[c], rho[c]);
+                sr += d.re;
+                si += d.im;
+                ss += norm2(w[c]);
             }
         }
         sr = wave_sum(sr);
@@ -878,43 +987,41 @@ __global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const i
         __syncthreads();
         sr = si = ss = 0;
         for (int q = 0; q < nw; q++) { sr += red[3 * q]; si += red[3 * q + 1]; ss += red[3 * q + 2]; }
-        if (od && ss > 0) {
+        if (act && ss > 0) {
             cx<T> alpha = {T(sr / ss), T(si / ss)};
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                pv[c] += alpha * v[c];
-                v[c] -= alpha * w[c];
+            for (int c = 0; c < 6; c++) {
+                eo[c] += alpha * rho[c];
+                rho[c] -= alpha * w[c];
             }
         }
         // (two calls, not a pointer select: selecting between the arrays would
         // force both out of registers)
-        if (od) {
-            if (it + 1 < mr_steps) lds_store(O, bvh, l, v);
-            else lds_store(O, bvh, l, pv);
+        if (act) {
+            if (it + 1 < mr_steps) lds_store6(O, bvh, h, l, rho);
+            else lds_store6(O, bvh, h, l, eo);
         }
         __syncthreads();
     }
     if (mr_steps == 0) {
-        if (od) lds_store(O, bvh, l, pv);
+        if (act) lds_store6(O, bvh, h, l, eo);
         __syncthreads();
     }
-    // ---- back-substitution and update ----
+    // ---- back-substitution and update: e_e = t0 - A_e^{-1} (H_int e_o)_e, t0 already in z ----
     if (act) {
-        pair_hops(0, O, acc);
-        if (ev) {
+        pair_hops(0, O, R);
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] = T(0.5) * acc[c];
-            clover_reg_apply(m, acc, w);
-            load_spinor(z, g.vh, 0, i, acc);
+        for (int c = 0; c < 6; c++) R[c] = T(0.5) * R[c];
+        herm6_apply(me, R, w);
+        cx<T> zh[6];
+        half_load(z, g.vh, 0, h, i, zh);
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] += pv[c] + w[c];
-            store_spinor(z, g.vh, 0, i, acc);
-        } else {
-            load_spinor(z, g.vh, 1, i, acc);
+        for (int c = 0; c < 6; c++) zh[c] += w[c];
+        half_store(z, g.vh, 0, h, i, zh);
+        half_load(z, g.vh, 1, h, i, zh);
 #pragma unroll
-            for (int c = 0; c < 12; c++) acc[c] += pv[c];
-            store_spinor(z, g.vh, 1, i, acc);
-        }
+        for (int c = 0; c < 6; c++) zh[c] += eo[c];
+        half_store(z, g.vh, 1, h, i, zh);
     }
     __syncthreads();  // the block fields are reused by the next right-hand side
     }
