@@ -228,8 +228,10 @@ def main():
         log("bench: autotuned schedule %d (ms per schedule %s)" % (sched, ["%.3f" % t for t in tune_ms]))
         grid, ctimes = s.autotune_coarse(reps=3)
         sched = s.get_schedule()
-        coarse_tune = dict(chosen_grid=grid, ms_step_launches=ctimes[0],
-                           ms_cooperative={str(g): t for g, t in zip((16, 32, 64, 128), ctimes[1:])})
+        coarse_tune = dict(chosen_grid=grid, graph_replay=bool(sched & 16), ms_single_launches=ctimes[0],
+                           ms_graph_replay=ctimes[1],
+                           ms_cooperative={str(g): t for g, t in zip((16, 32, 64, 128), ctimes[2:6])},
+                           ms_outer_solve={"single_launches": ctimes[6], "graph_replay": ctimes[7]})
         log("bench: coarse solver %s" % coarse_tune)
     else:
         s.set_schedule(args.sched)

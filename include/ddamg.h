@@ -293,7 +293,8 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   back to DD_SCHED_GRAPH / single launches when the device
  *                   does not admit the grid.  Results agree to rounding.
  * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH with the matrix
- * cores on; dd_autotune_coarse decides about DD_SCHED_COOP and its grid.
+ * cores on; dd_autotune_coarse decides about DD_SCHED_GRAPH, DD_SCHED_COOP and
+ * the cooperative grid.
  * ------------------------------------------------------------------------- */
 enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16,
        DD_SCHED_COOP = 32 };
@@ -311,10 +312,16 @@ int dd_get_schedule(const dd_ctx *ctx);
 dd_status dd_autotune(dd_ctx *ctx, int reps, int *chosen, double *times_ms);
 
 /* Coarse-solver autotuner (after dd_setup): times `reps` coarsest-level solves
- * of a fixed random right-hand side with step-by-step launches and with the
- * cooperative cycle (DD_SCHED_COOP) at 16, 32, 64 and 128 workgroups, and keeps
- * the fastest.  chosen_grid (may be NULL): 0 for step-by-step launches, else
- * the workgroup count; times_ms (may be NULL): 5 doubles, ms per solve. */
+ * of a fixed random right-hand side with step-by-step single launches, with
+ * graph replay (DD_SCHED_GRAPH) and with the cooperative cycle (DD_SCHED_COOP)
+ * at 16, 32, 64 and 128 workgroups.  When a step-by-step form is the fastest,
+ * single launches and graph replay are compared again by `reps` whole outer
+ * solves (random right-hand side, tolerance 1e-10).  The winner is kept (the
+ * call sets or clears DD_SCHED_GRAPH and DD_SCHED_COOP).  chosen_grid (may be
+ * NULL): 0 for step-by-step launches, else the workgroup count; times_ms (may
+ * be NULL): 8 doubles, ms per coarsest-level solve in the order above, then ms
+ * per outer solve with single launches and with graph replay (0 when a
+ * cooperative form won). */
 dd_status dd_autotune_coarse(dd_ctx *ctx, int reps, int *chosen_grid, double *times_ms);
 
 #ifdef __cplusplus

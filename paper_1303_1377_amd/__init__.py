@@ -283,9 +283,11 @@ class Solver:
         return ch.value, list(t)
 
     def autotune_coarse(self, reps=3):
-        """Step-by-step vs cooperative coarse GMRES (16..128 workgroups); returns (grid or 0, [ms x 5])."""
+        """Step-by-step (single launches, graph replay) vs cooperative coarse GMRES (16..128
+        workgroups), then single launches vs graph replay by whole solves; returns
+        (grid or 0, [ms x 8])."""
         ch = C.c_int()
-        t = (C.c_double * 5)()
+        t = (C.c_double * 8)()
         self._check(library().dd_autotune_coarse(self.h, int(reps), C.byref(ch), t))
         return ch.value, list(t)
 

@@ -64,19 +64,12 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
     // first block of the panel: the self block, its inverse, or the first hop
     const cx<S>* panel = (self_mode == CS_SELFINV) ? op.Minv + gs * nn : op.M + (gs * 9 + 1 - nself) * nn;
-    if (threadIdx.x == 0) {
-        int ns = 0;
-        if (nself) { vin[ns] = in1 + gs * nd; ns++; }
-        if (hop_sign != 0) {
-            int x[4];
-            cb_coords(g, p, i, x);
-            for (int k = 0; k < 8; k++) {
-                int y[4];
-                nb_coords(g, x, k, y);
-                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
-                ns++;
-            }
-        }
+    // input vectors of the panel's column slots: thread k < 8 finds neighbour k
+    if (threadIdx.x == 0 && nself) vin[0] = in1 + gs * nd;
+    if (hop_sign != 0 && threadIdx.x < 8) {
+        int x[4];
+        cb_coords(g, p, i, x);
+        vin[nself + threadIdx.x] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, threadIdx.x)) * nd;
     }
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
     const int Q = ns * nd;
@@ -242,7 +235,6 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     extern __shared__ char smem_raw[];
     __shared__ const cx<S>* mat[9];
     __shared__ const cx<float>* vin[9];
-    __shared__ int nslot_s;
     const Geom g = op.g;
     const int nd = op.nd;
     const int ndk = (nd + K - 1) / K * K;          // k extent padded to the instruction
@@ -254,26 +246,20 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     const size_t gs = (size_t)p * g.vh + i;
     const size_t nn = (size_t)nd * nd;
     const int t = threadIdx.x, nt = blockDim.x;
-    if (t == 0) {
-        int ns = 0;
-        if (self_mode == CS_SELF) { mat[ns] = op.M + gs * 9 * nn; vin[ns] = in1 + gs * nd; ns++; }
-        else if (self_mode == CS_SELFINV) { mat[ns] = op.Minv + gs * nn; vin[ns] = in1 + gs * nd; ns++; }
-        if (hop_sign != 0) {
-            int x[4];
-            cb_coords(g, p, i, x);
-            for (int k = 0; k < 8; k++) {
-                int y[4];
-                nb_coords(g, x, k, y);
-                mat[ns] = op.M + (gs * 9 + 1 + k) * nn;
-                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
-                ns++;
-            }
-        }
-        nslot_s = ns;
+    // block and input of every slot: thread k < 8 finds neighbour k
+    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    if (t == 0 && nself) {
+        mat[0] = (self_mode == CS_SELF) ? op.M + gs * 9 * nn : op.Minv + gs * nn;
+        vin[0] = in1 + gs * nd;
+    }
+    if (hop_sign != 0 && t < 8) {
+        int x[4];
+        cb_coords(g, p, i, x);
+        mat[nself + t] = op.M + (gs * 9 + 1 + t) * nn;
+        vin[nself + t] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, t)) * nd;
     }
     __syncthreads();
-    const int ns = nslot_s;
-    const int nself = (self_mode == CS_SELF || self_mode == CS_SELFINV) ? 1 : 0;
+    const int ns = nself + (hop_sign != 0 ? 8 : 0);
     // stage X_s: entry (s, c, j), c fastest so each RHS column is read contiguously
     for (int e = t; e < ns * 16 * ndk; e += nt) {
         const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
@@ -392,19 +378,12 @@ __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par,
     const size_t nn = (size_t)nd * nd;
     const int nself = (self_mode == CS_SELF) ? 1 : 0;
     const cx<S>* panel = fold ? op.B + (size_t)i * 8 * nn : op.M + (gs * 9 + 1 - nself) * nn;
-    if (threadIdx.x == 0) {
-        int ns = 0;
-        if (nself) { vin[ns] = in1 + gs * nd; ns++; }
-        if (hop_sign != 0) {
-            int x[4];
-            cb_coords(g, p, i, x);
-            for (int k = 0; k < 8; k++) {
-                int y[4];
-                nb_coords(g, x, k, y);
-                vin[ns] = in2 + ((size_t)(1 - p) * g.vh + cb_index(g, y)) * nd;
-                ns++;
-            }
-        }
+    // input vectors of the panel's column slots: thread k < 8 finds neighbour k
+    if (threadIdx.x == 0 && nself) vin[0] = in1 + gs * nd;
+    if (hop_sign != 0 && threadIdx.x < 8) {
+        int x[4];
+        cb_coords(g, p, i, x);
+        vin[nself + threadIdx.x] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, threadIdx.x)) * nd;
     }
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
     const int Q = ns * nd;

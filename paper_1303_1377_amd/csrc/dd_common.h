@@ -129,6 +129,21 @@ __host__ __device__ __forceinline__ void nb_coords(const Geom& g, const int x[4]
     else y[mu] = (x[mu] == 0) ? g.d[mu] - 1 : x[mu] - 1;
 }
 
+// layout index of neighbour k of x, written with selects only (no dynamically
+// indexed private arrays, so rolled loops stay in registers)
+__device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k) {
+    const int mu = k & 3;
+    const bool fwd = k < 4;
+    int y[4];
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        const int c = x[nu], d = g.d[nu];
+        const int stepped = fwd ? ((c + 1 == d) ? 0 : c + 1) : ((c == 0) ? d - 1 : c - 1);
+        y[nu] = (nu == mu) ? stepped : c;
+    }
+    return cb_index(g, y);
+}
+
 // ---------------------------------------------------------------------------
 // spin structure.  In the chiral representation every gamma_mu is
 // [[0, B_mu], [B_mu^H, 0]] in the spin halves {0,1} / {2,3} with

@@ -447,21 +447,6 @@ __global__ void __launch_bounds__(256) k_dirac(FineOp<T, S> op, const cx<T>* __r
     store_spinor(out, g.vh, p, i, a);
 }
 
-// layout index of neighbour k of x, written with selects only (no dynamically
-// indexed private arrays, so rolled loops stay in registers)
-__device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k) {
-    const int mu = k & 3;
-    const bool fwd = k < 4;
-    int y[4];
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-        const int c = x[nu], d = g.d[nu];
-        const int stepped = fwd ? ((c + 1 == d) ? 0 : c + 1) : ((c == 0) ? d - 1 : c - 1);
-        y[nu] = (nu == mu) ? stepped : c;
-    }
-    return cb_index(g, y);
-}
-
 // ---------------------------------------------------------------------------
 // Stencil with the layout block staged in LDS (SCHED_LDS).  One workgroup per
 // layout block, one thread per site (threads [0, bvh) even, [bvh, 2 bvh) odd).

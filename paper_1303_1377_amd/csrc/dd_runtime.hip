@@ -1893,19 +1893,24 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
 }
 
 // Coarse-solver autotuner: one coarsest-level solve on a fixed random RHS with
-// the step-by-step graph launches and with the cooperative cycle at 16, 32, 64
-// and 128 workgroups; the fastest is kept.
+// step-by-step launches (single kernel launches, then chunks of steps replayed
+// as graphs) and with the cooperative cycle at 16, 32, 64 and 128 workgroups;
+// the fastest is kept.
 template <class T>
 static void tune_coarse(dd_ctx* C, Hier<T>& H, int reps, int* chosen, double* times) {
     const int l = H.nlev - 1;
     coarse_random(H.g[l], H.nd[l], 1, 777ULL, 11, H.rc[l], C->s);
     const Batch one = single(C);
-    const int caps[5] = {0, 16, 32, 64, 128};
-    const int saved = C->sched, saved_cap = C->coop_cap;
+    constexpr int NV = 6;
+    const int caps[NV] = {0, 0, 16, 32, 64, 128};
+    const int saved = C->sched & ~(SCHED_COOP | SCHED_GRAPH), saved_cap = C->coop_cap;
+    auto flags = [&](int v) {
+        return v == 0 ? saved : v == 1 ? (saved | SCHED_GRAPH) : (saved | SCHED_GRAPH | SCHED_COOP);
+    };
     double best = 0;
     int pick = 0;
-    for (int v = 0; v < 5; v++) {
-        C->sched = caps[v] ? (saved | SCHED_COOP) : (saved & ~SCHED_COOP);
+    for (int v = 0; v < NV; v++) {
+        C->sched = flags(v);
         C->coop_cap = caps[v] ? caps[v] : saved_cap;
         H.coop_off = false;
         H.gmres_oe(l, H.rc[l], H.ec[l], one);   // warm-up (graph capture)
@@ -1917,7 +1922,30 @@ static void tune_coarse(dd_ctx* C, Hier<T>& H, int reps, int* chosen, double* ti
         if (times) times[v] = ms;
         if (v == 0 || ms < best) { best = ms; pick = v; }
     }
-    C->sched = caps[pick] ? (saved | SCHED_COOP) : (saved & ~SCHED_COOP);
+    // single launches and graph replay compare in context, by whole outer
+    // solves of a random right-hand side: the graph's launch latency and how
+    // far the host's enqueueing runs ahead both depend on the work around the
+    // coarse solves
+    if (times) times[NV] = times[NV + 1] = 0.0;
+    if (caps[pick] == 0) {
+        fine_random<double>(C->g0, 1, 778ULL, 12, C->ob, C->s);
+        double ts[2];
+        for (int v = 0; v < 2; v++) {
+            C->sched = flags(v);
+            C->coop_cap = saved_cap;
+            dd_stats sb[MAX_RHS];
+            dd_status rc[MAX_RHS];
+            outer_fgmres<T>(C, H, 1, 1e-10, 0, sb, rc);   // warm-up (graph capture)
+            sync(C);
+            const double t0 = now_s();
+            for (int r = 0; r < reps; r++) outer_fgmres<T>(C, H, 1, 1e-10, 0, sb, rc);
+            sync(C);
+            ts[v] = (now_s() - t0) * 1e3 / reps;
+            if (times) times[NV + v] = ts[v];
+        }
+        pick = (ts[1] < ts[0]) ? 1 : 0;
+    }
+    C->sched = flags(pick);
     C->coop_cap = caps[pick] ? caps[pick] : saved_cap;
     memset(H.coarse_count, 0, sizeof H.coarse_count);
     if (chosen) *chosen = caps[pick];
