@@ -1237,12 +1237,19 @@ void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* b
 // collects the self coupling and the hops that stay inside the aggregate's
 // lattice block, slot 1+k the hops k that leave it.  Accumulated in FP64.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __restrict__ P, cx<T>* __restrict__ M) {
+// NT: the largest workgroup (one thread per aggregate site) the build allows;
+// the 256-thread form has the register file to keep its state without scratch
+template <class T, int NT>
+__global__ void __launch_bounds__(NT) k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __restrict__ P,
+                                                      cx<T>* __restrict__ M) {
     extern __shared__ char smem_raw[];
     cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][2N]
-    const int gc = blockIdx.x, bcol = blockIdx.y;
-    const int nd = 2 * N, hb = bcol / N, kb = bcol % N;
+    // workgroup (coarse site gc, column bcol); the 2N workgroups of one coarse
+    // site run back to back on one XCD, sharing its L2 for the aggregate's P
+    const int nd = 2 * N;
+    const int lw = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int gc = lw / nd, bcol = lw - gc * nd;
+    const int hb = bcol / N, kb = bcol % N;
     const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
     int xc[4];
     cb_coords(m.c, pc, ic, xc);
@@ -1277,6 +1284,10 @@ __global__ void k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __re
                     coarse_of(m, y, yc);
                     if (yc[0] != xc[0] || yc[1] != xc[1] || yc[2] != xc[2] || yc[3] != xc[3]) continue;
                     int j = cb_index(op.g, y);
+                    // opaque per iteration: keeps the compiler from hoisting the
+                    // neighbour's addresses out of the slot loop (they would not
+                    // fit in registers)
+                    asm volatile("" : "+v"(j));
                     load_spinor(Pb, vh, 1 - p, j, v);
 #pragma unroll
                     for (int c = 0; c < 12; c++)
@@ -1292,6 +1303,10 @@ __global__ void k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __re
                 coarse_of(m, y, yc);
                 if (yc[0] != xc[0] || yc[1] != xc[1] || yc[2] != xc[2] || yc[3] != xc[3]) {
                     int j = cb_index(op.g, y);
+                    // opaque per iteration: keeps the compiler from hoisting the
+                    // neighbour's addresses out of the slot loop (they would not
+                    // fit in registers)
+                    asm volatile("" : "+v"(j));
                     cx<T> v[12], acc[12];
                     load_spinor(Pb, vh, 1 - p, j, v);
 #pragma unroll
@@ -1305,17 +1320,36 @@ __global__ void k_assemble_fine(FineOp<T> op, AggMap m, int N, const cx<T>* __re
                 }
             }
         }
-        for (int a = 0; a < nd; a++) {
-            const int ha = a / N, ka = a % N;
-            cx<double> d = czero<double>();
-            if (act) {
+        // projections onto the aggregate's columns a, AB at a time so that
+        // their loads and reductions overlap
+        constexpr int AB = 4;
+        for (int a0 = 0; a0 < nd; a0 += AB) {
+            cx<T> pa[AB][6];
+#pragma unroll
+            for (int u = 0; u < AB; u++) {
+                const int a = a0 + u, ha = a / N, ka = a % N;
                 const cx<T>* Pa = P + (size_t)ka * 24 * vh + (size_t)(p * 12 + 6 * ha) * vh + i;
 #pragma unroll
-                for (int c = 0; c < 6; c++) d += cmulc(ccast<double>(Pa[(size_t)c * vh]), ccast<double>(wv[6 * ha + c]));
+                for (int c = 0; c < 6; c++) pa[u][c] = (act && a < nd) ? Pa[(size_t)c * vh] : czero<T>();
             }
-            d.re = wave_sum(d.re);
-            d.im = wave_sum(d.im);
-            if (lane == 0) red[w * nd + a] = d;
+            cx<double> d[AB];
+#pragma unroll
+            for (int u = 0; u < AB; u++) {
+                const int ha = ((a0 + u) / N) & 1;
+                d[u] = czero<double>();
+#pragma unroll
+                for (int c = 0; c < 6; c++) d[u] += cmulc(ccast<double>(pa[u][c]), ccast<double>(wv[6 * ha + c]));
+            }
+#pragma unroll
+            for (int u = 0; u < AB; u++) {
+                d[u].re = wave_sum(d[u].re);
+                d[u].im = wave_sum(d[u].im);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < AB; u++)
+                    if (a0 + u < nd) red[w * nd + a0 + u] = d[u];
+            }
         }
         __syncthreads();
         for (int a = t; a < nd; a += blockDim.x) {
@@ -1331,8 +1365,9 @@ template <class T>
 void fine_assemble(const FineOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* M, hipStream_t s) {
     int nt = ((m.asz + 63) / 64) * 64;
     size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
-    dim3 grid(2 * m.c.vh, 2 * N);
-    k_assemble_fine<T><<<grid, nt, lds, s>>>(op, m, N, P, M);
+    const int nwg = 2 * m.c.vh * 2 * N;
+    if (nt <= 256) k_assemble_fine<T, 256><<<nwg, nt, lds, s>>>(op, m, N, P, M);
+    else k_assemble_fine<T, 1024><<<nwg, nt, lds, s>>>(op, m, N, P, M);
 }
 
 // ---------------------------------------------------------------------------
