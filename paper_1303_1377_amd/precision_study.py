@@ -63,6 +63,7 @@ def run(dims, m0, precisions=(64, 32, 16), solves=2, tol=1e-10, seed=0, ape=2, n
         torch.cuda.synchronize()
         setup_s = time.time() - t0
         s.autotune(reps=3)
+        s.autotune_coarse(reps=1)
         xs, sts, times = [], [], []
         for b in B:
             torch.cuda.synchronize()

@@ -586,18 +586,19 @@ def test_multi_rhs_coarse_solve_and_vcycle():
         assert rel(Z[q].reshape(-1), p.o.vcycle(0, R[q]).reshape(-1)) < 1e-4
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("precision", [32, 64])
+def test_graph_replay_matches_eager(precision):
     """Coarsest-level Arnoldi steps replayed from captured HIP graphs give
     the same bits as the eagerly launched kernels, on the first capture and
     on later replays (solves of several right-hand sides, single and batched,
-    with host work and synchronisation in between)."""
-    say("case: graph replay 8^4")
+    with host work and synchronisation in between), in FP32 and FP64."""
+    say("case: graph replay 8^4, precision", precision)
     import paper_1303_1377_amd as G
 
     dims = (8, 8, 8, 8)
     p = Pair(dims, eps=0.3, seed=3, m0=-0.25, csw=1.0)
     kw = dict(levels=2, n_tv=[8], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4], n_inv=2, outer_restart=20,
-              max_rhs=3, precision=32)
+              max_rhs=3, precision=precision)
     p.g.setup(params=G.default_params(**kw))
     base = p.g.get_schedule()
     assert base & 16, "graphs are part of the default schedule"
