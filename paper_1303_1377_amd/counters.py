@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CLASSES = {
     "sap": ("void dd::k_sap_fine<double, double, 1>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
     "dirac64": ("void dd::k_dirac<double, double>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
-    "restrict": ("void dd::k_restrict_fine<double, double>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
+    "restrict": ("void dd::k_restrict_fine<double, double, 256>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
     "prolong": ("void dd::k_prolong_fine<double, double>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
 }
 

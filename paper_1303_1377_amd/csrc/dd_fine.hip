@@ -1059,9 +1059,12 @@ __device__ __forceinline__ void coarse_of(const AggMap& m, const int x[4], int x
 
 // sum of per-wave partials: lane 0 of each wave stores; after a sync thread 0..n-1 adds them up
 // out[k] for k < n: P^H in, 2N unknowns per coarse site (index h*N + k)
-template <class T, class S>
-__global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
-                                cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
+// NT: the largest workgroup the build allows (one thread per aggregate site);
+// the 256-thread form keeps two test vectors' loads in flight without spilling
+template <class T, class S, int NT>
+__global__ void __launch_bounds__(NT) k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P,
+                                                      const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long ldi,
+                                                      long ldo, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     in += blockIdx.y * ldi;
     out += blockIdx.y * ldo;
@@ -1075,6 +1078,8 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, co
     const bool act = t < m.asz;
     int p = 0, i = 0;
     cx<T> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) v[c] = czero<T>();   // lanes past the aggregate add zeros
     if (act) {
         int x[4];
         agg_site(m, xc, t, x);
@@ -1087,19 +1092,28 @@ __global__ void k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, co
     // when there are few coarse sites, so that enough workgroups stream P)
     const int kper = (N + gridDim.z - 1) / gridDim.z;
     const int k0 = blockIdx.z * kper, k1 = min(N, k0 + kper);
-    for (int k = k0; k < k1; k++) {
-        cx<double> d0 = czero<double>(), d1 = czero<double>();
-        if (act) {
-            cx<T> q[12];
-            load_spinor(P + (size_t)k * 24 * vh, vh, p, i, q);
+    // two test vectors at a time: both loads in flight before the reductions
+    for (int k = k0; k < k1; k += 2) {
+        const bool two = k + 1 < k1;
+        cx<T> q[2][12];
 #pragma unroll
-            for (int c = 0; c < 6; c++) d0 += ccast<double>(cmulc(q[c], v[c]));
+        for (int u = 0; u < 2; u++) {
+            if (act && (u == 0 || two)) load_spinor(P + (size_t)(k + u) * 24 * vh, vh, p, i, q[u]);
+            else
 #pragma unroll
-            for (int c = 6; c < 12; c++) d1 += ccast<double>(cmulc(q[c], v[c]));
+                for (int c = 0; c < 12; c++) q[u][c] = czero<T>();
         }
-        d0.re = wave_sum(d0.re); d0.im = wave_sum(d0.im);
-        d1.re = wave_sum(d1.re); d1.im = wave_sum(d1.im);
-        if (lane == 0) { red[w * 2 * N + k] = d0; red[w * 2 * N + N + k] = d1; }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            cx<double> d0 = czero<double>(), d1 = czero<double>();
+#pragma unroll
+            for (int c = 0; c < 6; c++) d0 += ccast<double>(cmulc(q[u][c], v[c]));
+#pragma unroll
+            for (int c = 6; c < 12; c++) d1 += ccast<double>(cmulc(q[u][c], v[c]));
+            d0.re = wave_sum(d0.re); d0.im = wave_sum(d0.im);
+            d1.re = wave_sum(d1.re); d1.im = wave_sum(d1.im);
+            if (lane == 0 && (u == 0 || two)) { red[w * 2 * N + k + u] = d0; red[w * 2 * N + N + k + u] = d1; }
+        }
     }
     __syncthreads();
     const int kn = max(0, k1 - k0);
@@ -1148,7 +1162,8 @@ void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T
     // split the test vectors over workgroups until about 1024 stream P
     const int ks = std::max(1, std::min(N, (1024 + 2 * m.c.vh - 1) / (2 * m.c.vh)));
     dim3 grid(2 * m.c.vh, nr, ks);
-    k_restrict_fine<T, S><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    if (nt <= 256) k_restrict_fine<T, S, 256><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    else k_restrict_fine<T, S, 1024><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
 }
 template <class T, class S>
 void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
