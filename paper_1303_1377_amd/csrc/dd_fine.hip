@@ -650,35 +650,26 @@ __device__ __forceinline__ void su3_rebuild(cx<T> u[9]) {
 }
 
 template <class T>
-__device__ __forceinline__ void lds_load(const cx<T>* buf, int bvh, int l, cx<T> v[12]) {
-#pragma unroll
-    for (int c = 0; c < 12; c++) v[c] = buf[c * bvh + l];
-}
-template <class T>
 __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T> v[12]) {
 #pragma unroll
     for (int c = 0; c < 12; c++) buf[c * bvh + l] = v[c];
 }
 
-// hop k of the site (p, i) owned by thread t.  tab[k][t] packs, for a hop
-// inside the block, the LDS slot of the link (<< 8) and the neighbour's local
-// index; -1 marks a hop that leaves the block.  INTERNAL_ONLY: only internal
-// hops, neighbour field from the LDS array `buf`; otherwise all hops with the
-// neighbour field from global memory `psi`.
-template <class T, class S, bool INTERNAL_ONLY>
+// hop k of the lane's own site (p, i) for the block residual.  tab[k][t]
+// packs, for a hop inside the block, the LDS slot of the link (<< 8) and the
+// neighbour's local index; -1 marks a hop that leaves the block (its link is
+// read from memory).  The neighbour spinor comes from global memory psi.
+template <class T, class S>
 __device__ __forceinline__ void sap_hop(const FineOp<T, S>& op, int ltot, const cx<T>* __restrict__ L,
                                         const int* __restrict__ tab, int ntab, int k, int t, int p, int i,
-                                        const int x[4], int base, const cx<T>* buf, const cx<T>* __restrict__ psi,
-                                        cx<T> acc[12]) {
+                                        const int x[4], int base, const cx<T>* __restrict__ psi, cx<T> acc[12]) {
     const Geom& g = op.g;
     const int code = tab[k * ntab + t];
-    if (INTERNAL_ONLY && code < 0) return;
     const int mu = k & 3;
     const bool fwd = k < 4;
     const int j = (code >= 0) ? base + (code & 255) : nb_index_sel(g, x, k);
     cx<T> v[12], u[9], h[6], gg[6];
-    if (INTERNAL_ONLY) lds_load(buf, g.bvh, j - base, v);
-    else load_spinor(psi, g.vh, 1 - p, j, v);
+    load_spinor(psi, g.vh, 1 - p, j, v);
     if (code >= 0) {
         const int li = code >> 8;
 #pragma unroll
@@ -900,7 +891,7 @@ __global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const i
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = czero<T>();
 #pragma unroll 1
-        for (int k = 0; k < 8; k++) sap_hop<T, S, false>(op, ltot, L, tab, ntab, k, sidx, h, i, x, base, nullptr, z, acc);
+        for (int k = 0; k < 8; k++) sap_hop<T, S>(op, ltot, L, tab, ntab, k, sidx, h, i, x, base, z, acc);
         load_spinor(b, g.vh, h, i, v);
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] += T(0.5) * acc[c];
