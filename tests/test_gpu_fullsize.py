@@ -4,7 +4,7 @@ parameters (two levels, aggregates and SAP blocks 4^4, N = 20, 3 MR steps,
 FP64) and the launch schedule the benchmark's autotuner picks.  At this size
 the FP64 oracle still computes every output in seconds, so the comparisons
 are element by element over the whole lattice, at the bars of the small
-cases: linear operator applies 1e-13 (FP64) / 2e-6 (FP32), SAP 1e-12, coarse
+cases: linear operator applies 1e-13 (FP64) / 2e-6 (FP32), SAP 1e-12 (FP32: 1e-5), coarse
 GMRES with a fixed iteration count 1e-10; the full solve is checked by its
 true residual under the oracle's operator (<= 1e-10)."""
 import json
@@ -77,6 +77,15 @@ def test_fullsize_sap(full):
     b = F.gaussian_spinor(full.dims, 32)
     z, _ = full.g.apply("SAP", 0, b, arg=2)
     assert rel(to_np(z), full.o.sap(0, b, 2)) < 1e-12
+
+
+def test_fullsize_sap_fp32(full):
+    """The FP32 SAP kernel (two waves per SIMD, 4^4 blocks) at full size, at
+    the FP32 SAP bar of the small cases."""
+    full.configure(precision=32)
+    b = F.gaussian_spinor(full.dims, 36)
+    z, _ = full.g.apply("SAP", 0, b, arg=2)
+    assert rel(to_np(z), full.o.sap(0, b, 2)) < 1e-5
 
 
 def test_fullsize_transfer_and_coarse(full):
