@@ -436,37 +436,40 @@ void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s) { k_gm_gather<<
 void gm_solve(GmDev* st, int nr, hipStream_t s) { k_gm_solve<<<nr, 64, 0, s>>>(st); }
 
 template <class T>
-__global__ void k_scale_dev(long n, const GmDev* st0, cx<T>* __restrict__ x, int ignore_stop, long ld) {
+__global__ void k_scale_dev(long n, const GmDev* st0, cx<T>* __restrict__ x, const cx<T>* src, int ignore_stop,
+                            long ld) {
     const GmDev* st = st0 + blockIdx.y;
     if (!ignore_stop && st->stop) return;
     x += blockIdx.y * ld;
+    const cx<T>* in = src ? src + blockIdx.y * ld : x;
     const T sc = T(st->scale);
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) x[e] = sc * x[e];
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) x[e] = sc * in[e];
 }
 template <class T>
-void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr, long ld) {
+void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr, long ld,
+                   const cx<T>* src) {
     dim3 grid(grid_for(n), nr);
-    k_scale_dev<T><<<grid, 256, 0, s>>>(n, st, x, ignore_stop ? 1 : 0, ld);
+    k_scale_dev<T><<<grid, 256, 0, s>>>(n, st, x, src, ignore_stop ? 1 : 0, ld);
 }
 
 template <class T>
 __global__ void k_lincomb_dev(long n, const cx<T>* __restrict__ V, long ldv, const GmDev* st0, cx<T>* __restrict__ x,
-                              long ldr, long ldx) {
+                              long ldr, long ldx, int assign) {
     const GmDev* st = st0 + blockIdx.y;
     const int m = st->j;
     V += blockIdx.y * ldr;
     x += blockIdx.y * ldx;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        cx<double> sacc = ccast<double>(x[e]);
+        cx<double> sacc = assign ? czero<double>() : ccast<double>(x[e]);
         for (int i = 0; i < m; i++) sacc += st->y[i] * (st->sc[i] * ccast<double>(V[(size_t)i * ldv + e]));
         x[e] = ccast<T>(sacc);
     }
 }
 template <class T>
 void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s, int nr, long ldr,
-                     long ldx) {
+                     long ldx, bool assign) {
     dim3 grid(grid_for(n), nr);
-    k_lincomb_dev<T><<<grid, 256, 0, s>>>(n, V, ldv, st, x, ldr, ldx);
+    k_lincomb_dev<T><<<grid, 256, 0, s>>>(n, V, ldv, st, x, ldr, ldx, assign ? 1 : 0);
 }
 
 template <class T>
@@ -580,8 +583,9 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template void vec_finite_check<T>(long, const cx<T>*, int*, hipStream_t);                                     \
     template void bvec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, long, int, Mask, hipStream_t);            \
     template void bvec_scale<T>(long, const Coefs&, cx<T>*, long, int, Mask, hipStream_t);                         \
-    template void vec_scale_dev<T>(long, const GmDev*, cx<T>*, hipStream_t, bool, int, long);                      \
-    template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t, int, long, long); \
+    template void vec_scale_dev<T>(long, const GmDev*, cx<T>*, hipStream_t, bool, int, long, const cx<T>*);        \
+    template void vec_lincomb_dev<T>(long, const cx<T>*, long, const GmDev*, cx<T>*, hipStream_t, int, long, long,  \
+                                     bool);                                                                         \
     template void vec_multidot_skip<T>(long, int, const cx<T>*, long, const cx<T>*, void*, hipStream_t, RedBatch);  \
     template void vec_update_norm_givens<T>(long, int, const cx<T>*, long, cx<T>*, cx<double>*, void*, hipStream_t, \
                                             RedBatch, GmDev*, int, int*, bool);

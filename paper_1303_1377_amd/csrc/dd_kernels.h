@@ -251,13 +251,15 @@ void gm_start(GmDev* st, const cx<double>* res, int rstride, double tol, int fir
 void gm_gather(const GmDev* st, int nr, int* out, hipStream_t s);
 // y = R^{-1} g for the st->j columns of the cycle
 void gm_solve(GmDev* st, int nr, hipStream_t s);
-// x_r *= st[r].scale (skipped once st[r].stop unless ignore_stop)
+// x_r = st[r].scale * (src_r, or x_r itself when src is null) (skipped once
+// st[r].stop unless ignore_stop)
 template <class T>
-void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr = 1, long ld = 0);
-// x_r += sum_{i < st[r].j} y_i sc_i V_i
+void vec_scale_dev(long n, const GmDev* st, cx<T>* x, hipStream_t s, bool ignore_stop, int nr = 1, long ld = 0,
+                   const cx<T>* src = nullptr);
+// x_r += sum_{i < st[r].j} y_i sc_i V_i (x_r = the sum when assign)
 template <class T>
 void vec_lincomb_dev(long n, const cx<T>* V, long ldv, const GmDev* st, cx<T>* x, hipStream_t s, int nr = 1,
-                     long ldr = 0, long ldx = 0);
+                     long ldr = 0, long ldx = 0, bool assign = false);
 // Arnoldi reductions of the device-resident GMRES (RHS with st[r].stop skip)
 template <class T>
 void vec_multidot_skip(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, void* work, hipStream_t s,

@@ -729,12 +729,14 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
             coarse_apply(op, 1, CS_IDENT, r, -1, t, false, f, C->s, in, nr, nfull);
         });
     }
-    HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull * nr, C->s));
-    HIPX(hipMemcpyAsync(V, f, sizeof(cx<T>) * nfull * nr, hipMemcpyDeviceToDevice, C->s));
+    // V_0 = f_o / ||f_o||.  The first correction is assigned, so e needs no
+    // clearing unless right-hand sides outside the batch's mask keep theirs
+    if (k < nr) HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull * nr, C->s));
     RedBatch rb0{nr, nfull, nfull, RS, in};
-    vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, nullptr, C->s, rb0);
+    vec_multidot<T>(nh, 1, odd(f), 0, odd(f), C->dred, C->dwork, nullptr, C->s, rb0);
     gm_start(st, C->dred, RS, p.coarse_tol, 1, m, p.coarse_maxit, p.coarse_fixed, nr, C->s, in);
-    vec_scale_dev<T>(nh, st, odd(V), C->s, true, nr, nfull);
+    vec_scale_dev<T>(nh, st, odd(V), C->s, true, nr, nfull, odd(f));
+    bool first_cycle = true;
     int* hs = C->hint + DI_GATHER;
     auto read_state = [&]() {
         gm_gather(st, nr, C->dflags + DI_GATHER, C->s);
@@ -844,7 +846,8 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
             chunk = 4;
         }
         gm_solve(st, nr, C->s);
-        vec_lincomb_dev<T>(nh, odd(V), ldv, st, odd(e), C->s, nr, nfull, nfull);
+        vec_lincomb_dev<T>(nh, odd(V), ldv, st, odd(e), C->s, nr, nfull, nfull, first_cycle);
+        first_cycle = false;
         if (all_stop) break;
         // restart the running RHS from their true Schur residual
         schur(l, e, V, live, nr, k);
