@@ -78,6 +78,7 @@ def main():
         torch.cuda.synchronize()
         st = time.time() - t
         s.autotune(reps=2)
+        s.autotune_coarse(reps=1)
         return s, st
 
     # n_inv scan
