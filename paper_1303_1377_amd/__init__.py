@@ -160,8 +160,23 @@ def _dev(t):
     return t.to(device="cuda", dtype=torch.complex128).contiguous()
 
 
+def _order_after_current(stream):
+    """Make `stream` wait for the work torch queued on its current stream (the
+    conversions and copies that produced the input tensors), so the library,
+    which enqueues on `stream`, reads them only after they are written."""
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    if stream is not None and stream != cur:
+        stream.wait_stream(cur)
+
+
 class Solver:
-    """One gauge field, one hierarchy (see include/ddamg.h for the semantics)."""
+    """One gauge field, one hierarchy (see include/ddamg.h for the semantics).
+
+    Inputs are prepared on torch's current stream and the library runs on
+    `self.stream`; every call that reads caller data first orders the solver's
+    stream after the current one.  Calls return after their work has finished
+    (the C-ABI synchronises its stream), so outputs are ready on return."""
 
     def __init__(self, dims, gauge, m0, csw, clover=None, stream=None):
         torch = _torch()
@@ -171,6 +186,7 @@ class Solver:
         g = _dev(gauge).reshape(self.vol, 4, 3, 3)
         cl = None if clover is None else _dev(clover).reshape(self.vol, 2, 6, 6)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _order_after_current(self.stream)
         h = C.c_void_p()
         rc = L.dd_create(C.byref(h), (C.c_int * 4)(*self.dims), C.c_void_p(g.data_ptr()),
                          None if cl is None else C.c_void_p(cl.data_ptr()), float(m0), float(csw),
@@ -228,6 +244,7 @@ class Solver:
         bb = _dev(b).reshape(self.vol, 4, 3)
         x = torch.empty_like(bb)
         st = Stats()
+        _order_after_current(self.stream)
         rc = library().dd_solve(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), C.byref(st))
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, st.as_dict()
@@ -239,6 +256,7 @@ class Solver:
         k = bb.shape[0]
         x = torch.empty_like(bb)
         st = (Stats * max(k, 1))()
+        _order_after_current(self.stream)
         rc = library().dd_solve_batch(self.h, k, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), st)
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, [s.as_dict() for s in st[:k]]
@@ -301,6 +319,7 @@ class Solver:
     def set_test_vectors(self, level, v):
         vv = _dev(v)
         n = int(vv.shape[0])
+        _order_after_current(self.stream)
         self._check(library().dd_set_test_vectors(self.h, level, n, C.c_void_p(vv.data_ptr())))
 
     def get_test_vectors(self, level):
@@ -352,6 +371,7 @@ class Solver:
         else:
             out = torch.empty_like(vin)
         its = C.c_long(0)
+        _order_after_current(self.stream)
         self._check(library().dd_apply(self.h, code, level, int(arg), C.c_void_p(vin.data_ptr()),
                                        C.c_void_p(out.data_ptr()), C.byref(its)))
         return out, its.value
@@ -373,6 +393,7 @@ class Solver:
             vol, nd = self.level_size(level)
             out = torch.empty((k, vol, nd), dtype=torch.complex128, device="cuda")
         its = (C.c_long * k)()
+        _order_after_current(self.stream)
         self._check(library().dd_apply_batch(self.h, code, level, int(arg), int(k), C.c_void_p(vin.data_ptr()),
                                              C.c_void_p(out.data_ptr()), its))
         return out, list(its)
