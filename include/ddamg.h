@@ -213,6 +213,20 @@ dd_status dd_apply(dd_ctx *ctx, int op, int level, int arg, const double *in, do
 dd_status dd_apply_batch(dd_ctx *ctx, int op, int level, int arg, int k, const double *in, double *out,
                          long *iters);
 
+/* Allocation-free form of dd_apply(ctx, DD_OP_D, 0, 0, in, out, NULL): out = D in
+ * on the fine level in FP64, computed by the same kernels, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The call allocates nothing: the two
+ * internal-layout staging spinors live in a fixed 24 MiB device array that
+ * each GPU the library runs on holds until the process ends.
+ *   in, out  device complex128 fine spinors [vol][4][3] (the caller allocates)
+ * Limit: vol <= 65,536 sites (a 16^4 lattice); larger lattices -> DD_EINVAL.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two threads, or two contexts on different streams) race and must be
+ * serialised by the caller.  Works on configured and unconfigured contexts.
+ * Errors: DD_EINVAL (NULL pointer, lattice above the limit), DD_EDEVICE. */
+dd_status dd_apply_D_noalloc(dd_ctx *ctx, const double *in, double *out);
+
 /* Lattice dims and unknowns per site of a level (level 0: the fine lattice). */
 dd_status dd_level_info(const dd_ctx *ctx, int level, int dims[4], int *nd);
 

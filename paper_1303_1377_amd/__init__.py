@@ -103,6 +103,7 @@ def library():
         L.dd_get_clover.argtypes = [vp, vp, vp]
         L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
+        L.dd_apply_D_noalloc.argtypes = [vp, vp, vp]
         L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
         L.dd_profile.argtypes = [vp, C.c_int]
         L.dd_profile_classes.argtypes = [vp, C.c_uint]
@@ -118,7 +119,7 @@ def library():
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
-                     "dd_profile_classes",
+                     "dd_profile_classes", "dd_apply_D_noalloc",
                      "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -375,6 +376,17 @@ class Solver:
         self._check(library().dd_apply(self.h, code, level, int(arg), C.c_void_p(vin.data_ptr()),
                                        C.c_void_p(out.data_ptr()), C.byref(its)))
         return out, its.value
+
+    def apply_D_noalloc(self, v, out=None):
+        """out = D v (fine level, FP64) through the allocation-free entry point;
+        `out` may be a preallocated complex128 device tensor of v's shape."""
+        torch = _torch()
+        vin = _dev(v)
+        if out is None:
+            out = torch.empty_like(vin)
+        _order_after_current(self.stream)
+        self._check(library().dd_apply_D_noalloc(self.h, C.c_void_p(vin.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
 
     def apply_batch(self, op, level, vs, arg=0):
         """One component on k vectors at once ([k][vol_level][nd_level]); returns (out, [iters])."""

@@ -220,6 +220,8 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
+    void* scratch = nullptr;     // device address of this GPU's `scratch` array (dd_apply_D_noalloc)
+    std::string scratch_err;     // why it is unavailable, if it is
     int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
     int coop_cap = 32;           // workgroups of the cooperative coarse GMRES (autotuned)
     ~dd_ctx();
@@ -1202,6 +1204,39 @@ static void outer_fgmres(dd_ctx* C, Hier<T>& H, int nr, double tol, long fixed, 
 
 
 // ---------------------------------------------------------------------------
+// Fixed staging memory of the allocation-free stencil entry point
+// (dd_apply_D_noalloc): the two internal-layout FP64 spinors that dd_apply
+// allocates per call live here instead.  Every GPU the library runs on holds
+// its own copy until the process ends; host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+// ---------------------------------------------------------------------------
+static const size_t NOALLOC_SITES = 65536;                        // a 16^4 lattice
+static const size_t NOALLOC_BYTES = NOALLOC_SITES * 2 * 12 * 16;  // two FP64 spinors: 24 MiB
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+static const int NOALLOC_MAXDEV = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAXDEV];
+
+// address of `scratch` on the current device, looked up once per device
+static void* scratch_for_current_device() {
+    int dev = -1;
+    HIPX(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAXDEV) fail(DD_EDEVICE, "device index " + std::to_string(dev) + " out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(DD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
 static std::string g_create_error;
@@ -1284,6 +1319,11 @@ dd_status dd_create(dd_ctx** out, const int dims[4], const double* gauge, const 
         if (!valid_layout(dims, b, true)) fail(DD_EINVAL, "lattice extents admit no 2-colourable block layout");
         layout_fields(C, b, gauge, clover);
         dd_default_params(&C->p);
+        try {
+            C->scratch = scratch_for_current_device();
+        } catch (const DdError& e) {
+            C->scratch_err = e.msg;   // only dd_apply_D_noalloc needs it; it reports this
+        }
     } catch (const DdError& e) {
         g_create_error = e.msg;
         delete C;
@@ -1835,6 +1875,27 @@ dd_status dd_apply(dd_ctx* ctx, int op, int level, int arg, const double* in, do
 }
 
 
+
+dd_status dd_apply_D_noalloc(dd_ctx* ctx, const double* in, double* out) {
+    ABI_TRY(ctx)
+    if (!in || !out) fail(DD_EINVAL, "NULL vector");
+    if ((size_t)ctx->vol > NOALLOC_SITES)
+        fail(DD_EINVAL, "lattice of " + std::to_string(ctx->vol) + " sites exceeds the allocation-free limit of " +
+                            std::to_string(NOALLOC_SITES) + " sites");
+    if (!ctx->scratch) fail(DD_EDEVICE, "scratch array unavailable: " + ctx->scratch_err);
+    const long n = 24L * ctx->g0.vh;   // complex entries of one fine spinor
+    cx<double>* a = reinterpret_cast<cx<double>*>(ctx->scratch);
+    cx<double>* b = a + n;
+    // the import writes every entry of a and the stencil every entry of b:
+    // nothing has to start at zero
+    fine_import_spinor<double>(ctx->g0, in, a, ctx->s);
+    fine_dirac<double>(fine_op<double>(ctx), a, b, ctx->s);
+    fine_export_spinor<double>(ctx->g0, b, out, ctx->s);
+    HIPX(hipGetLastError());
+    HIPX(hipStreamSynchronize(ctx->s));
+    return DD_OK;
+    ABI_END(ctx)
+}
 
 static void set_sched(dd_ctx* C, int sched) {
     C->sched = sched;
