@@ -146,6 +146,8 @@ def lib():
         L.or_coarse_solve.argtypes = [vp, C.c_int, cp, cp]
         L.or_schur.argtypes = [vp, C.c_int, cp, cp]
         L.or_vcycle.argtypes = [vp, C.c_int, C.c_int, cp, cp]
+        L.or_fgmres_level.restype = C.c_long
+        L.or_fgmres_level.argtypes = [vp, C.c_int, cp, cp]
         L.or_setup_level.argtypes = [vp, C.c_int]
         L.or_setup.argtypes = [vp, C.POINTER(C.c_void_p)]
         L.or_solve.argtypes = [vp, cp, cp, dp, C.c_long, C.POINTER(Stats)]
@@ -332,6 +334,14 @@ class Oracle:
         z = np.zeros_like(rr)
         lib().or_vcycle(self.h, l, bottom, _ptr(rr), _ptr(z))
         return z.reshape(np.shape(r))
+
+    def fgmres_level(self, l, r):
+        """Intermediate-level FGMRES (3+ levels) on level l: (solution, iterations)."""
+        vol, nd = self.level_size(l)
+        rr = _c(r).reshape(vol * nd)
+        x = np.zeros_like(rr)
+        its = lib().or_fgmres_level(self.h, l, _ptr(rr), _ptr(x))
+        return x.reshape(np.shape(r)), its
 
     def setup_level(self, l):
         if lib().or_setup_level(self.h, l):

@@ -1270,6 +1270,15 @@ void or_schur(void *p, int l, const cplx *in, cplx *out) {
 
 void or_vcycle(void *p, int l, int bottom, const cplx *r, cplx *z) { vcycle((octx *)p, l, bottom, r, z); }
 
+/* The intermediate-level solve of a V-cycle on level l (1 <= l < levels-1):
+ * FGMRES preconditioned by the level-l V-cycle, with the intermediate-level
+ * tolerance, restart and iteration counts; returns the iteration count. */
+long or_fgmres_level(void *p, int l, const cplx *rhs, cplx *x) {
+    octx *X = (octx *)p;
+    return fgmres(X, l, X->nlev - 1, rhs, x, X->p.mid_tol, X->p.mid_restart, X->p.mid_maxit, X->p.mid_fixed,
+                  NULL, NULL);
+}
+
 /* Algorithm 2 (DD-alpha-AMG-setup(n_inv, nu)) on level l with the test vectors
  * already installed by or_set_vectors.  The V-cycles inside use level l+1 as
  * the coarsest level.  Readings: the vectors are normalised after each of the

@@ -8,8 +8,10 @@ of a solver does, and raises if the library was not built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 __all__ = ["Solver", "Params", "Stats", "default_params", "library", "DDError", "OPS", "KERNEL_CLASSES"]
 
@@ -161,6 +163,22 @@ def _dev(t):
     return t.to(device="cuda", dtype=torch.complex128).contiguous()
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_solvers():
+    """Release every context still open when the interpreter exits, while the
+    HIP runtime (and any profiler attached to it) is still fully alive; left
+    to garbage collection the contexts would be destroyed during the runtime's
+    own teardown."""
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
 def _order_after_current(stream):
     """Make `stream` wait for the work torch queued on its current stream (the
     conversions and copies that produced the input tensors), so the library,
@@ -197,6 +215,7 @@ class Solver:
         self.h = h
         self.m0, self.csw = float(m0), float(csw)
         self.params = None
+        _live.add(self)
 
     # ---- plumbing ----------------------------------------------------------
     def _check(self, rc, ok=(0,)):

@@ -6,7 +6,9 @@ the FP64 oracle still computes every output in seconds, so the comparisons
 are element by element over the whole lattice, at the bars of the small
 cases: linear operator applies 1e-13 (FP64) / 2e-6 (FP32), SAP 1e-12 (FP32: 1e-5), coarse
 GMRES with a fixed iteration count 1e-10; the full solve is checked by its
-true residual under the oracle's operator (<= 1e-10)."""
+true residual under the oracle's operator (<= 1e-10) and its solution against
+the oracle's own solution (its own setup, tolerance 1e-12): two solutions that
+meet the true residual agree to about kappa * tol (reading A33: <= 1e-8)."""
 import json
 import os
 
@@ -127,3 +129,20 @@ def test_fullsize_solve_true_residual(full):
     relres = float(np.linalg.norm(r) / np.linalg.norm(b))
     assert relres <= 1e-10
     assert abs(relres - st["true_relres"]) <= 1e-3 * relres + 1e-14
+
+
+def test_fullsize_solution_matches_oracle_solution(full):
+    """x of the benchmarked solve against the oracle's x for the same b."""
+    full.configure()
+    full.g.setup(params=full.G.default_params(precision=64, **PARAMS))
+    b = F.gaussian_spinor(full.dims, 35)
+    x, st = full.g.solve(b, 1e-10)
+    okw = dict(PARAMS, n_inv=2)
+    full.o.configure(**okw)
+    full.o.setup([F.random_vectors(int(np.prod(full.dims)), 12, 20, 123)])
+    xo, sto = full.o.solve(b, 1e-12)
+    assert sto["converged"]
+    diff = float(np.linalg.norm(to_np(x) - xo) / np.linalg.norm(xo))
+    say("full size: |x - x_oracle| / |x_oracle| = %.3e (gpu its %d, oracle its %d)" %
+        (diff, st["outer_iters"], sto["outer_iters"]))
+    assert st["converged"] and diff <= 1e-8

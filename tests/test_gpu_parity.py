@@ -230,7 +230,10 @@ def test_three_level_components():
     rc, _ = p.g.apply("RESTRICT", 1, v1)
     assert rel(to_np(rc), p.o.restrict(1, v1)) < 1e-13
     e, its = p.g.apply("FGMRES", 1, v1)
-    # oracle: intermediate FGMRES = V-cycle of level 1 inside FGMRES; compare via the V-cycle
+    eo, itso = p.o.fgmres_level(1, v1)
+    say("intermediate FGMRES its", its, itso)
+    assert its == itso == 3
+    assert rel(to_np(e), eo) < 1e-10
     zv, _ = p.g.apply("VCYCLE", 1, v1)
     assert rel(to_np(zv), p.o.vcycle(1, v1)) < 1e-10
     r = F.gaussian_spinor(dims, 4)
