@@ -168,3 +168,22 @@ def test_enoconv_returns_last_iterate():
     assert not st["converged"] and st["outer_iters"] == 1
     assert relres < 1.0 and relres > 1e-10
     assert abs(relres - st["true_relres"]) <= 1e-6 * relres
+
+
+def test_mcrit_krylov_schur_on_the_library_matches_oracle_arpack():
+    """The critical mass the workloads' masses are fixed from, computed by the
+    Krylov-Schur routine on the library's FP64 D at 16^4, against the CPU
+    oracle's ARPACK value stored in tests/golden/mcrit.json."""
+    import json
+    import os
+
+    from paper_1303_1377_amd.mcrit import m_crit
+
+    say("case: m_crit of the 16^4 field on the device")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "tests", "golden", "mcrit.json")) as f:
+        info = json.load(f)["lat16x4_ape2_seed0"]
+    U = F.make_gauge(tuple(info["dims"]), info["eps"], info["seed"], ape_steps=info["ape"], ape_alpha=0.5)
+    r = m_crit(info["dims"], U, info["csw"], tol=1e-4)
+    say("  device %.10f oracle ARPACK %.10f" % (r["m_crit"], info["m_crit"]))
+    assert abs(r["m_crit"] - info["m_crit"]) < 1e-7
