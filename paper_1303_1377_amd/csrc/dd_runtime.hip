@@ -400,17 +400,24 @@ struct Hier {
 
     long nlv(int l) const { return 2L * g[l].vh * nd[l]; }   // complex entries of a level vector
 
-    // algorithmic bytes of one launch for k right-hand sides (model documented
-    // with the kernels): operator data once, vector data once per RHS
-    double by_dirac(int k) const { return 2.0 * g[0].vh * (144 + 48.0 * k) * sizeof(T); }
-    double by_sap_half(int k) const { return 1.0 * g[0].vh * (144 + 72.0 * k) * sizeof(T); }
+    // algorithmic bytes of one launch for k right-hand sides: operator data
+    // once, vector data once per RHS, every datum counted once.  Per fine site:
+    // stencil 144 operator reals (links 72, clover 72) + 48 per RHS (in, out);
+    // SAP half sweep, per site of the active colour, 144 operator reals + 144
+    // per RHS (b, z read and written, the residual, the face values of the
+    // neighbouring blocks): 288 reals for one RHS.  Operators stored in FP16
+    // (precision 16) count 2 bytes per real, vectors sizeof(T).
+    double osz() const { return half ? 2.0 : (double)sizeof(T); }
+    double by_dirac(int k) const { return 2.0 * g[0].vh * (144 * osz() + 48.0 * k * sizeof(T)); }
+    double by_sap_half(int k) const { return 1.0 * g[0].vh * (144 * osz() + 144.0 * k * sizeof(T)); }
     double by_coarse(int l, int nblk_per_site, int nvec_per_site, bool all_sites, int k) const {
         double sites = all_sites ? 2.0 * g[l].vh : 1.0 * g[l].vh;
-        return sites * ((double)nblk_per_site * nd[l] * nd[l] + (double)k * nvec_per_site * nd[l]) * 2 * sizeof(T);
+        return sites * ((double)nblk_per_site * nd[l] * nd[l] * 2 * osz() + (double)k * nvec_per_site * nd[l] * 2 * sizeof(T));
     }
     double by_transfer(int l, int k) const {
         // P (N vectors) + fine vector + coarse vector per RHS
-        return (double)nlv(l) * (N[l] + k) * 2 * sizeof(T) + (double)k * nlv(l + 1) * 2 * sizeof(T);
+        return (double)nlv(l) * N[l] * 2 * osz() + (double)k * nlv(l) * 2 * sizeof(T) +
+               (double)k * nlv(l + 1) * 2 * sizeof(T);
     }
     double by_reduce(long n, int m, int k) const { return (double)k * n * (m + 1) * 2 * sizeof(T); }
 
