@@ -1031,10 +1031,11 @@ __device__ __forceinline__ cx<T> row_apply(const cx<S>* __restrict__ A, int nd, 
     return s;
 }
 
+// One right-hand side per workgroup (grid.y = RHS).
 // NTMAX: the workgroup size the kernel is compiled for (wider batches of
 // loads where fewer threads leave more registers per thread)
 template <class T, class S, int NTMAX>
-__global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+__global__ void __launch_bounds__(NTMAX) k_coarse_sap1(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
                              cx<T>* __restrict__ z, int mr_steps, long ld, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
     b += blockIdx.y * ld;
@@ -1138,15 +1139,245 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
     }
 }
 
+// KR right-hand sides at once: every block entry loaded is applied to the KR
+// vectors v + vo[q] (q < KR), accumulated into s[q] in the same column order
+// as row_apply (so a RHS gets the same sums alone and in a group)
+template <class T, class S, int KR, int RA_BATCH>
+__device__ __forceinline__ void row_apply_k(const cx<S>* __restrict__ A, int nd, int r, const cx<T>* v,
+                                            const size_t (&vo)[KR], cx<T> (&s)[KR]) {
+    using W = cx_word<S>;
+    const W* Aw = reinterpret_cast<const W*>(A);
+#pragma unroll
+    for (int q = 0; q < KR; q++) s[q] = czero<T>();
+    for (int c0 = 0; c0 < nd; c0 += RA_BATCH) {
+        W a[RA_BATCH];
+#pragma unroll
+        for (int u = 0; u < RA_BATCH; u++) a[u] = (c0 + u < nd) ? Aw[(size_t)(c0 + u) * nd + r] : W{};
+#pragma unroll
+        for (int q = 0; q < KR; q++) {
+            cx<T> x[RA_BATCH];
+#pragma unroll
+            for (int u = 0; u < RA_BATCH; u++) x[u] = (c0 + u < nd) ? v[vo[q] + c0 + u] : czero<T>();
+#pragma unroll
+            for (int u = 0; u < RA_BATCH; u++)
+                if (c0 + u < nd) s[q] += ccast<T>(__builtin_bit_cast(cx<S>, a[u])) * x[u];
+        }
+    }
+}
+
+// Coarse SAP half sweep for KR right-hand sides per workgroup: workgroup =
+// (block, group of KR RHS), thread = (local site l, row r) for both parities;
+// each block entry is loaded once per use for the whole group.  The fields of
+// the group live in LDS as [q][bvh][nd].  Right-hand sides beyond nr or masked
+// off take no part (their z is not touched).  NTMAX: the workgroup size the
+// kernel is compiled for (wider batches of loads where fewer threads leave
+// more registers per thread).
+template <class T, class S, int NTMAX, int KR>
+__global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+                             cx<T>* __restrict__ z, int mr_steps, long ld, int nr, Mask mk) {
+    const int q0 = blockIdx.y * KR;
+    bool on[KR];
+    bool any = false;
+    size_t go_[KR], lo_[KR];   // offsets of member q in the global vector sets and in the LDS fields
+#pragma unroll
+    for (int q = 0; q < KR; q++) {
+        on[q] = (q0 + q < nr) && mk.on(q0 + q);
+        any |= on[q];
+        // members past the batch read the first member's data (never written)
+        go_[q] = (size_t)((q0 + q < nr) ? q : 0) * ld;
+    }
+    if (!any) return;
+    b += (size_t)q0 * ld;
+    z += (size_t)q0 * ld;
+    extern __shared__ char smem_raw[];
+    const Geom g = op.g;
+    const int nd = op.nd, bvh = g.bvh;
+    const size_t nn = (size_t)nd * nd;
+    const size_t fs = (size_t)bvh * nd;               // one field of the block
+#pragma unroll
+    for (int q = 0; q < KR; q++) lo_[q] = q * fs;
+    constexpr int RB = sizeof(T) == 8 ? (NTMAX <= 512 ? 4 : 2) : (NTMAX <= 512 ? 10 : 5);
+    cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // [KR][bvh][nd] odd-site fields
+    cx<T>* se = so + KR * fs;                         // even-site fields
+    cx<T>* tm = se + KR * fs;                         // temporaries (even)
+    double* red = reinterpret_cast<double*>(tm + KR * fs);
+    const int blk = blocks[blockIdx.x];
+    const int base = blk << g.lbvh;
+    const int t = threadIdx.x;
+    const bool act = t < bvh * nd;
+    const int l = act ? t / nd : 0, r = act ? t % nd : 0;
+    const int i = base + l;
+    int xe[4], xo[4], nbe[8], nbo[8];
+    cb_coords(g, 0, i, xe);
+    cb_coords(g, 1, i, xo);
+    for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, xe, k, y);
+        nbe[k] = cb_index(g, y);
+        nb_coords(g, xo, k, y);
+        nbo[k] = cb_index(g, y);
+    }
+    const size_t ge = i, go = (size_t)g.vh + i;
+    // sum over the 8 hops of site gs (parity p) applied to the global vectors
+    auto hop_glob = [&](size_t gs, int p, const int* nbj, cx<T> (&h)[KR]) {
+#pragma unroll
+        for (int q = 0; q < KR; q++) h[q] = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            size_t gy = (size_t)(1 - p) * g.vh + nbj[k];
+            cx<T> u[KR];
+            row_apply_k<T, S, KR, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, z + gy * nd, go_, u);
+#pragma unroll
+            for (int q = 0; q < KR; q++) h[q] += u[q];
+        }
+    };
+    // sum over the hops that stay inside the block, applied to LDS fields
+    auto hop_int = [&](size_t gs, const int* nbj, const cx<T>* buf, cx<T> (&h)[KR]) {
+#pragma unroll
+        for (int q = 0; q < KR; q++) h[q] = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            if ((nbj[k] >> g.lbvh) != blk) continue;
+            cx<T> u[KR];
+            row_apply_k<T, S, KR, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (nbj[k] - base) * nd, lo_, u);
+#pragma unroll
+            for (int q = 0; q < KR; q++) h[q] += u[q];
+        }
+    };
+    const int me = l * nd + r;
+    cx<T> t0[KR], rho[KR], eo[KR], sv[KR], h[KR], u[KR];
+#pragma unroll
+    for (int q = 0; q < KR; q++) { t0[q] = rho[q] = eo[q] = sv[q] = czero<T>(); }
+    // t0_e = Minv (b_e - H z) - z_e
+    if (act) {
+        hop_glob(ge, 0, nbe, h);
+#pragma unroll
+        for (int q = 0; q < KR; q++) tm[q * fs + me] = b[go_[q] + ge * nd + r] - h[q];
+    }
+    __syncthreads();
+    if (act) {
+        row_apply_k<T, S, KR, RB>(op.Minv + ge * nn, nd, r, tm + l * nd, lo_, u);
+#pragma unroll
+        for (int q = 0; q < KR; q++) {
+            t0[q] = u[q] - z[go_[q] + ge * nd + r];
+            se[q * fs + me] = t0[q];
+            so[q * fs + me] = z[go_[q] + go * nd + r];
+        }
+    }
+    __syncthreads();
+    // f_o = b_o - M0 z_o - H z - H_int t0
+    if (act) {
+        cx<T> hg[KR], hi[KR];
+        row_apply_k<T, S, KR, RB>(op.M + go * 9 * nn, nd, r, so + l * nd, lo_, u);
+        hop_glob(go, 1, nbo, hg);
+        hop_int(go, nbo, se, hi);
+#pragma unroll
+        for (int q = 0; q < KR; q++) rho[q] = b[go_[q] + go * nd + r] - u[q] - hg[q] - hi[q];
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int q = 0; q < KR; q++) so[q * fs + me] = rho[q];
+    __syncthreads();
+    const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int it = 0; it < mr_steps; it++) {
+        if (act) {
+            hop_int(ge, nbe, so, h);
+#pragma unroll
+            for (int q = 0; q < KR; q++) tm[q * fs + me] = h[q];
+        }
+        __syncthreads();
+        if (act) row_apply_k<T, S, KR, RB>(op.Minv + ge * nn, nd, r, tm + l * nd, lo_, u);
+        __syncthreads();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < KR; q++) se[q * fs + me] = u[q];
+        __syncthreads();
+        double sr[KR], si[KR], ss[KR];
+        if (act) {
+            row_apply_k<T, S, KR, RB>(op.M + go * 9 * nn, nd, r, so + l * nd, lo_, u);
+            hop_int(go, nbo, se, h);
+        }
+#pragma unroll
+        for (int q = 0; q < KR; q++) {
+            sr[q] = si[q] = ss[q] = 0;
+            if (act) {
+                sv[q] = u[q] - h[q];
+                cx<T> d = cmulc(sv[q], rho[q]);
+                sr[q] = d.re; si[q] = d.im; ss[q] = norm2(sv[q]);
+            }
+            sr[q] = wave_sum(sr[q]); si[q] = wave_sum(si[q]); ss[q] = wave_sum(ss[q]);
+            if (lane == 0) { red[(q * nw + w) * 3] = sr[q]; red[(q * nw + w) * 3 + 1] = si[q]; red[(q * nw + w) * 3 + 2] = ss[q]; }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KR; q++) {
+            double a0 = 0, a1 = 0, a2 = 0;
+            for (int v = 0; v < nw; v++) { a0 += red[(q * nw + v) * 3]; a1 += red[(q * nw + v) * 3 + 1]; a2 += red[(q * nw + v) * 3 + 2]; }
+            if (a2 > 0 && act) {
+                cx<T> alpha = {T(a0 / a2), T(a1 / a2)};
+                eo[q] += alpha * rho[q];
+                rho[q] -= alpha * sv[q];
+            }
+        }
+        __syncthreads();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < KR; q++) so[q * fs + me] = (it + 1 < mr_steps) ? rho[q] : eo[q];
+        __syncthreads();
+    }
+    if (mr_steps == 0) {
+        if (act)
+#pragma unroll
+            for (int q = 0; q < KR; q++) so[q * fs + me] = eo[q];
+        __syncthreads();
+    }
+    if (act) {
+        hop_int(ge, nbe, so, h);
+#pragma unroll
+        for (int q = 0; q < KR; q++) tm[q * fs + me] = h[q];
+    }
+    __syncthreads();
+    if (act) {
+        row_apply_k<T, S, KR, RB>(op.Minv + ge * nn, nd, r, tm + l * nd, lo_, u);
+#pragma unroll
+        for (int q = 0; q < KR; q++) {
+            if (!on[q]) continue;
+            z[q * ld + ge * nd + r] += t0[q] - u[q];
+            z[q * ld + go * nd + r] += eo[q];
+        }
+    }
+}
+
+template <class T, class S, int KR>
+static void coarse_sap_launch(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z,
+                              int mr_steps, hipStream_t s, int nr, long ld, Mask mk) {
+    const int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
+    if constexpr (KR == 1) {
+        const size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
+        dim3 grid(nblocks, nr);
+        if (nt <= 512) k_coarse_sap1<T, S, 512><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+        else k_coarse_sap1<T, S, 1024><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+    } else {
+        const size_t lds = 3 * KR * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * KR * sizeof(double) * (nt / 64);
+        dim3 grid(nblocks, (nr + KR - 1) / KR);
+        if (nt <= 512) k_coarse_sap<T, S, 512, KR><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, nr, mk);
+        else k_coarse_sap<T, S, 1024, KR><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, nr, mk);
+    }
+}
+
+// Right-hand sides are taken in groups of four (two for a batch of two), so a
+// block entry read from memory serves the whole group; a single RHS runs the
+// one-RHS kernel.  Both compute the same sums in the same order.
 template <class T, class S>
 void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
                      hipStream_t s, int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
-    int nt = ((op.g.bvh * op.nd + 63) / 64) * 64;
-    size_t lds = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * (nt / 64);
-    dim3 grid(nblocks, nr);
-    if (nt <= 512) k_coarse_sap<T, S, 512><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
-    else k_coarse_sap<T, S, 1024><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
+    // LDS of a group: three block fields per member (kept within the 64 KB
+    // a workgroup gets without an opt-in)
+    const int nw = (op.g.bvh * op.nd + 63) / 64;
+    const size_t member = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * nw;
+    if (nr >= 3 && 4 * member <= 65536) coarse_sap_launch<T, S, 4>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
+    else if (nr >= 2 && 2 * member <= 65536) coarse_sap_launch<T, S, 2>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
+    else coarse_sap_launch<T, S, 1>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
