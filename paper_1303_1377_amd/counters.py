@@ -1,8 +1,15 @@
-"""Reduce rocprofv3 counter-collection CSVs to per-kernel means and write the
-counter record bench.py reads for its roofline `traffic` figure.
+"""Reduce rocprofv3 output: counter-collection CSVs to the counter record
+bench.py reads for its roofline `traffic` figure, and kernel traces to
+per-kernel statistics.
 
     python -m paper_1303_1377_amd.counters --fetch DIR_FETCH --write DIR_WRITE \\
         --out profiles/counters_16x4_fp64_solve.json --command "..."
+    python -m paper_1303_1377_amd.counters --stats RESULTS.db [--last-seconds T] [--top 20]
+
+--stats reads the SQLite results database of `rocprofv3 --kernel-trace` and
+prints calls, total, mean and share per kernel; --last-seconds keeps only the
+dispatches that start in the last T seconds of GPU activity (the timed region
+of a benchmark that ends with it).
 
 Each DIR holds the *_counter_collection.csv of one `rocprofv3 --pmc` run
 (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch).  Kernels are matched by
@@ -43,13 +50,43 @@ def per_kernel(d):
     return vals
 
 
+def kernel_stats(db, last_seconds=None, top=20):
+    """Per-kernel (calls, total us, mean us, share) from a rocprofv3 SQLite results file."""
+    import sqlite3
+
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, start, end from kernels"))
+    if last_seconds:
+        t_end = max(r[2] for r in rows)
+        rows = [r for r in rows if r[1] >= t_end - last_seconds * 1e9]
+    agg = {}
+    for name, t0, t1 in rows:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += (t1 - t0) / 1e3
+    tot = sum(v[1] for v in agg.values())
+    out = sorted(((n, v[0], v[1], v[1] / v[0], 100.0 * v[1] / tot) for n, v in agg.items()), key=lambda r: -r[2])
+    return out[:top], tot, len(rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--out")
     ap.add_argument("--command", default="")
+    ap.add_argument("--stats")
+    ap.add_argument("--last-seconds", type=float, default=None)
+    ap.add_argument("--top", type=int, default=20)
     a = ap.parse_args()
+    if a.stats:
+        rows, tot, n = kernel_stats(a.stats, a.last_seconds, a.top)
+        print("%d dispatches, %.1f us of kernel time" % (n, tot))
+        print("| kernel | calls | total (us) | average (us) | % |")
+        print("|---|---|---|---|---|")
+        for name, calls, t, avg, pct in rows:
+            print("| `%s` | %d | %.1f | %.2f | %.2f |" % (name[:100] + ("..." if len(name) > 100 else ""), calls, t, avg, pct))
+        return
     fe, wr = per_kernel(a.fetch), per_kernel(a.write)
     rec = dict(fetch_scale=2.0, write_scale=1.0, command=a.command, kernels={})
     for cls, (prefix, src) in CLASSES.items():

@@ -1145,22 +1145,173 @@ __global__ void k_prolong_fine(AggMap m, int N, const cx<S>* __restrict__ P, con
     store_spinor(out, vh, p, i, acc);
 }
 
+// Restriction and prolongation for a group of KR right-hand sides: every
+// entry of P loaded from memory serves the whole group (P, N fine vectors, is
+// the bulk of the traffic).  Per RHS the sums are formed in the same order as
+// in the one-RHS kernels above.  Members of the group past the batch read the
+// first member's data and are never stored.
+template <class T, class S, int NT, int KR>
+__global__ void __launch_bounds__(NT) k_restrict_fine_k(AggMap m, int N, const cx<S>* __restrict__ P,
+                                                        const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                        long ldi, long ldo, int nr, Mask mk) {
+    const int q0 = blockIdx.y * KR;
+    bool on[KR];
+    bool any = false;
+    size_t io[KR];
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+        on[r] = (q0 + r < nr) && mk.on(q0 + r);
+        any |= on[r];
+        io[r] = (size_t)(q0 + ((q0 + r < nr) ? r : 0)) * ldi;
+    }
+    if (!any) return;
+    extern __shared__ char smem_raw[];
+    cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][KR][2N]
+    const int gc = blockIdx.x;
+    const int pc = gc >= m.c.vh, ic = gc - pc * m.c.vh;
+    int xc[4];
+    cb_coords(m.c, pc, ic, xc);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool act = t < m.asz;
+    int p = 0, i = 0;
+    cx<T> v[KR][12];
+#pragma unroll
+    for (int r = 0; r < KR; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[r][c] = czero<T>();
+    if (act) {
+        int x[4];
+        agg_site(m, xc, t, x);
+        p = site_parity(x);
+        i = cb_index(m.f, x);
+#pragma unroll
+        for (int r = 0; r < KR; r++) load_spinor(in + io[r], m.f.vh, p, i, v[r]);
+    }
+    const int vh = m.f.vh;
+    const int kper = (N + gridDim.z - 1) / gridDim.z;
+    const int k0 = blockIdx.z * kper, k1 = min(N, k0 + kper);
+    const int W = KR * 2 * N;   // reduction slots per wave
+    for (int k = k0; k < k1; k++) {
+        cx<T> q[12];
+        if (act) load_spinor(P + (size_t)k * 24 * vh, vh, p, i, q);
+        else
+#pragma unroll
+            for (int c = 0; c < 12; c++) q[c] = czero<T>();
+#pragma unroll
+        for (int r = 0; r < KR; r++) {
+            cx<double> d0 = czero<double>(), d1 = czero<double>();
+#pragma unroll
+            for (int c = 0; c < 6; c++) d0 += ccast<double>(cmulc(q[c], v[r][c]));
+#pragma unroll
+            for (int c = 6; c < 12; c++) d1 += ccast<double>(cmulc(q[c], v[r][c]));
+            d0.re = wave_sum(d0.re); d0.im = wave_sum(d0.im);
+            d1.re = wave_sum(d1.re); d1.im = wave_sum(d1.im);
+            if (lane == 0) { red[w * W + r * 2 * N + k] = d0; red[w * W + r * 2 * N + N + k] = d1; }
+        }
+    }
+    __syncthreads();
+    const int kn = max(0, k1 - k0);
+    for (int e = t; e < KR * 2 * kn; e += blockDim.x) {
+        const int r = e / (2 * kn), e2 = e % (2 * kn);
+        if (!on[r]) continue;
+        const int q = (e2 < kn) ? k0 + e2 : N + k0 + (e2 - kn);
+        cx<double> sum = czero<double>();
+        for (int ww = 0; ww < nw; ww++) sum += red[ww * W + r * 2 * N + q];
+        out[(size_t)(q0 + r) * ldo + (size_t)gc * 2 * N + q] = ccast<T>(sum);
+    }
+}
+
+template <class T, class S, int KR>
+__global__ void __launch_bounds__(256) k_prolong_fine_k(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
+                                 cx<T>* __restrict__ out, long ldi, long ldo, int nr, Mask mk) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int vh = m.f.vh;
+    if (gid >= 2 * vh) return;
+    const int q0 = blockIdx.y * KR;
+    bool on[KR];
+    bool any = false;
+    size_t io[KR];
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+        on[r] = (q0 + r < nr) && mk.on(q0 + r);
+        any |= on[r];
+        io[r] = (size_t)(q0 + ((q0 + r < nr) ? r : 0)) * ldi;
+    }
+    if (!any) return;
+    int p = gid >= vh, i = gid - p * vh;
+    int x[4], xc[4];
+    cb_coords(m.f, p, i, x);
+    coarse_of(m, x, xc);
+    int pc = site_parity(xc), ic = cb_index(m.c, xc);
+    const size_t eo = ((size_t)pc * m.c.vh + ic) * 2 * N;
+    cx<T> acc[KR][12];
+#pragma unroll
+    for (int r = 0; r < KR; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[r][c] = czero<T>();
+    for (int k = 0; k < N; k++) {
+        cx<T> q[12];
+        load_spinor(P + (size_t)k * 24 * vh, vh, p, i, q);
+#pragma unroll
+        for (int r = 0; r < KR; r++) {
+            const cx<T> e0 = in[io[r] + eo + k], e1 = in[io[r] + eo + N + k];
+#pragma unroll
+            for (int c = 0; c < 6; c++) acc[r][c] += q[c] * e0;
+#pragma unroll
+            for (int c = 6; c < 12; c++) acc[r][c] += q[c] * e1;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KR; r++)
+        if (on[r]) store_spinor(out + (size_t)(q0 + r) * ldo, vh, p, i, acc[r]);
+}
+
+// group size for a batch of nr right-hand sides (FP64 fields hold twice the
+// registers, so their groups are half as large)
+template <class T> static int transfer_group(int nr) {
+    const int cap = sizeof(T) == 8 ? 2 : 4;
+    return nr >= cap ? cap : (nr >= 2 ? 2 : 1);
+}
+
 template <class T, class S>
 void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
                    long ldi, long ldo, Mask mk) {
     int nt = ((m.asz + 63) / 64) * 64;
-    size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
     // split the test vectors over workgroups until about 1024 stream P
     const int ks = std::max(1, std::min(N, (1024 + 2 * m.c.vh - 1) / (2 * m.c.vh)));
-    dim3 grid(2 * m.c.vh, nr, ks);
-    if (nt <= 256) k_restrict_fine<T, S, 256><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
-    else k_restrict_fine<T, S, 1024><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    const int kr = transfer_group<T>(nr);
+    if (kr == 1 || nt > 256) {
+        size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
+        dim3 grid(2 * m.c.vh, nr, ks);
+        if (nt <= 256) k_restrict_fine<T, S, 256><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        else k_restrict_fine<T, S, 1024><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        return;
+    }
+    size_t lds = sizeof(cx<double>) * kr * 2 * N * (nt / 64);
+    dim3 grid(2 * m.c.vh, (nr + kr - 1) / kr, ks);
+    if constexpr (sizeof(T) == 4)
+        if (kr == 4) {
+            k_restrict_fine_k<T, S, 256, 4><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+            return;
+        }
+    k_restrict_fine_k<T, S, 256, 2><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
 }
 template <class T, class S>
 void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
                   long ldi, long ldo, Mask mk) {
-    dim3 grid(nblk_of(2L * m.f.vh, 256), nr);
-    k_prolong_fine<T, S><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
+    const int kr = transfer_group<T>(nr);
+    if (kr == 1) {
+        dim3 grid(nblk_of(2L * m.f.vh, 256), nr);
+        k_prolong_fine<T, S><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        return;
+    }
+    dim3 grid(nblk_of(2L * m.f.vh, 256), (nr + kr - 1) / kr);
+    if constexpr (sizeof(T) == 4)
+        if (kr == 4) {
+            k_prolong_fine_k<T, S, 4><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+            return;
+        }
+    k_prolong_fine_k<T, S, 2><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
 }
 
 // ---------------------------------------------------------------------------
