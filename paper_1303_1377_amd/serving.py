@@ -139,6 +139,7 @@ class Server:
         self._fields = {}
         self._resident = collections.OrderedDict()   # field_id -> solver (LRU order)
         self._resident_bytes = {}
+        self._reserved = {}    # field_id -> bytes held for a setup that is being built
         self._busy = set()
         self._pending = collections.deque()
         self._cv = threading.Condition()
@@ -200,6 +201,7 @@ class Server:
                         solves_per_s=(self._solved / span) if span > 0 else 0.0,
                         requests_per_s=(len(self._latency) / span) if span > 0 else 0.0,
                         resident=list(self._resident.keys()), resident_bytes=sum(self._resident_bytes.values()),
+                        reserved_bytes=sum(self._reserved.values()),
                         admitted=self.admitted, evicted=self.evicted)
 
     def close(self):
@@ -234,12 +236,19 @@ class Server:
             close()
         self.evicted += 1
 
+    def _held(self):
+        """Bytes of resident setups plus the reservations of setups being built."""
+        return sum(self._resident_bytes.values()) + sum(self._reserved.values())
+
     def _admit(self, fid):
         """Make room for field `fid` (caller holds the lock).  True when the
-        field may be set up now."""
+        field may be set up now; its estimate is then reserved until the setup
+        is resident (or has failed), so setups admitted together never exceed
+        the budget."""
         need = self._fields[fid].est_bytes
-        used = sum(self._resident_bytes.values())
+        used = self._held()
         if used + need <= self.budget:
+            self._reserved[fid] = need
             return True
         pending_fields = {r.field_id for r in self._pending}
         for old in list(self._resident):
@@ -249,14 +258,17 @@ class Server:
                 continue
             used -= self._resident_bytes.get(old, 0)
             self._evict(old)
-        return used + need <= self.budget
+        if used + need <= self.budget:
+            self._reserved[fid] = need
+            return True
+        return False
 
     def _trim(self, keep):
         """Evict idle setups (least recently used first) while the resident
         bytes exceed the budget (caller holds the lock)."""
         pending_fields = {r.field_id for r in self._pending}
         for old in list(self._resident):
-            if sum(self._resident_bytes.values()) <= self.budget:
+            if self._held() <= self.budget:
                 break
             if old == keep or old in self._busy or old in pending_fields:
                 continue
@@ -288,6 +300,7 @@ class Server:
                     if self._closed and not self._pending:
                         return
                     self._cv.wait(timeout=0.05)
+                started = 0
                 for fid in self._runnable():
                     if fid not in self._resident and not self._admit(fid):
                         continue
@@ -295,6 +308,11 @@ class Server:
                     w = threading.Thread(target=self._work, args=(fid,), name="dd-field-%s" % (fid,), daemon=True)
                     self._workers[fid] = w
                     w.start()
+                    started += 1
+                if not started:
+                    # every runnable field waits for memory: sleep until a worker
+                    # finishes (it notifies) instead of polling
+                    self._cv.wait(timeout=0.05)
 
     def _runnable(self):
         out = []
@@ -312,11 +330,17 @@ class Server:
             with self._cv:
                 solver = self._resident.get(fid)
             if solver is None:
-                solver = self._factory(self._fields[fid])
+                try:
+                    solver = self._factory(self._fields[fid])
+                except BaseException:
+                    with self._cv:
+                        self._reserved.pop(fid, None)
+                    raise
                 # account what the setup really holds once it is known
                 used = getattr(solver, "device_bytes", None)
                 held = max(self._fields[fid].est_bytes, int(used()) if callable(used) else 0)
                 with self._cv:
+                    self._reserved.pop(fid, None)
                     self._resident[fid] = solver
                     self._resident_bytes[fid] = held
                     self.admitted += 1

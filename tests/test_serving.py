@@ -99,6 +99,46 @@ def test_budget_admission_and_lru_eviction():
     srv.close()
 
 
+def test_setups_in_flight_respect_the_budget():
+    """Setups being built hold their estimate: with room for 1.5 setups and a
+    slow setup, three fields are never set up at once, and the bytes held
+    (resident plus reserved) never exceed the budget."""
+    dims = (4, 4, 4, 4)
+    one = estimate_bytes(dims, None, 4)
+    budget = int(one * 1.5)
+    live = [0]
+    peak = [0]
+    lock = threading.Lock()
+    srv_ref = []
+
+    def factory(spec):
+        with lock:
+            live[0] += 1
+            peak[0] = max(peak[0], live[0])
+        st = srv_ref[0].stats()
+        assert st["resident_bytes"] + st["reserved_bytes"] <= budget
+        time.sleep(0.2)
+        with lock:
+            live[0] -= 1
+        return FakeSolver(spec, delay=0.01)
+
+    srv = Server(budget_bytes=budget, max_rhs=4, solver_factory=factory)
+    srv_ref.append(srv)
+    for f in ("a", "b", "c"):
+        srv.add_field(f, dims, None, -0.4, 1.0)
+    futs = [srv.submit(f, _rhs(dims, 2, i)) for i, f in enumerate(("a", "b", "c"))]
+    samples = []
+    while not all(f.done() for f in futs):
+        st = srv.stats()
+        samples.append(st["resident_bytes"] + st["reserved_bytes"])
+        time.sleep(0.005)
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+    assert peak[0] == 1
+    assert max(samples) <= budget
+
+
 def test_field_above_budget_is_refused():
     srv = _server(1e6)
     with pytest.raises(ValueError):
