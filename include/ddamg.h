@@ -145,6 +145,30 @@ dd_status dd_solve(dd_ctx *ctx, const double *b, double *x, double tol, dd_stats
  *   stats array of k records or NULL */
 dd_status dd_solve_batch(dd_ctx *ctx, int k, const double *b, double *x, double tol, dd_stats *stats);
 
+/* Continuous batching on the resident setup.  The max_rhs right-hand-side
+ * slots of the outer FGMRES are filled, advanced and emptied independently:
+ * a slot whose solve has finished is read out and refilled with a new
+ * right-hand side between two restart cycles while the other slots keep their
+ * Krylov state (the FGMRES of Sec. 4.2 with its restart length n_kv).  Each
+ * slot's iterates are those of a single dd_solve of its right-hand side.
+ *
+ * dd_stream_load: put b (device complex128 [vol][4][3]) with tolerance tol
+ *   into a free slot (x0 = 0).  DD_ESTATE before dd_setup or if the slot is in
+ *   use; DD_EINVAL for a bad slot, tol or NULL b; DD_ENUMERIC for NaN/Inf in b.
+ * dd_stream_cycle: run one restart cycle of every running slot (at most
+ *   n_kv Arnoldi steps and the true-residual check).  state (may be NULL):
+ *   max_rhs DD_SLOT_* values afterwards; st (may be NULL): max_rhs records.
+ * dd_stream_take: copy the solution of a finished slot to x (device
+ *   complex128 [vol][4][3]) and free the slot; st may be NULL.  DD_ESTATE if
+ *   the slot is not finished; DD_ENOCONV (x still written) if it stopped at
+ *   outer_maxit.
+ * While any slot is in use dd_solve / dd_solve_batch return DD_ESTATE, and
+ * dd_set_mass does while a slot runs; dd_setup / dd_configure free all slots. */
+enum { DD_SLOT_FREE = 0, DD_SLOT_RUNNING = 1, DD_SLOT_CONVERGED = 2, DD_SLOT_STOPPED = 3 };
+dd_status dd_stream_load(dd_ctx *ctx, int slot, const double *b, double tol);
+dd_status dd_stream_cycle(dd_ctx *ctx, int *state, dd_stats *st);
+dd_status dd_stream_take(dd_ctx *ctx, int slot, double *x, dd_stats *st);
+
 /* Change m0 on a context that keeps its setup: A(x) -> A(x) + (m0' - m0) I and,
  * because P^H P = I, D_c -> D_c + (m0' - m0) I on every coarse level
  * (Sec. 6, mass scaling with one setup). */

@@ -106,6 +106,9 @@ def library():
         L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_D_noalloc.argtypes = [vp, vp, vp]
+        L.dd_stream_load.argtypes = [vp, C.c_int, vp, dp]
+        L.dd_stream_cycle.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(Stats)]
+        L.dd_stream_take.argtypes = [vp, C.c_int, vp, C.POINTER(Stats)]
         L.dd_level_info.argtypes = [vp, C.c_int, ip, ip]
         L.dd_profile.argtypes = [vp, C.c_int]
         L.dd_profile_classes.argtypes = [vp, C.c_uint]
@@ -121,7 +124,7 @@ def library():
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
-                     "dd_profile_classes", "dd_apply_D_noalloc",
+                     "dd_profile_classes", "dd_apply_D_noalloc", "dd_stream_load", "dd_stream_cycle", "dd_stream_take",
                      "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -280,6 +283,32 @@ class Solver:
         rc = library().dd_solve_batch(self.h, k, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), st)
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, [s.as_dict() for s in st[:k]]
+
+    # ---- continuous batching ---------------------------------------------------
+    SLOT_FREE, SLOT_RUNNING, SLOT_CONVERGED, SLOT_STOPPED = 0, 1, 2, 3
+
+    def stream_load(self, slot, b, tol=1e-10):
+        """Put one right-hand side [vol][4][3] into a free slot of the outer FGMRES."""
+        bb = _dev(b).reshape(self.vol, 4, 3)
+        _order_after_current(self.stream)
+        self._check(library().dd_stream_load(self.h, int(slot), C.c_void_p(bb.data_ptr()), float(tol)))
+
+    def stream_cycle(self):
+        """One restart cycle of every running slot; returns ([slot states], [stats dicts])."""
+        R = int(self.params.max_rhs)
+        state = (C.c_int * R)()
+        st = (Stats * R)()
+        self._check(library().dd_stream_cycle(self.h, state, st))
+        return list(state), [s.as_dict() for s in st]
+
+    def stream_take(self, slot, allow_noconv=False):
+        """Solution and stats of a finished slot; frees the slot."""
+        torch = _torch()
+        x = torch.empty((self.vol, 4, 3), dtype=torch.complex128, device="cuda")
+        st = Stats()
+        rc = library().dd_stream_take(self.h, int(slot), C.c_void_p(x.data_ptr()), C.byref(st))
+        self._check(rc, ok=(0, -3) if allow_noconv else (0,))
+        return x, st.as_dict()
 
     def set_mass(self, m0):
         self._check(library().dd_set_mass(self.h, float(m0)))

@@ -220,6 +220,20 @@ struct dd_ctx {
     cx<double>* ob = nullptr;  // R right-hand sides
     cx<double>* ox = nullptr;  // R solutions
     cx<double>* ot = nullptr;  // 2R temporaries
+    // continuous batching (dd_stream_*): per-slot state of the outer FGMRES
+    // between restart cycles; slot r uses the r-th vector of every outer set
+    struct StreamSlots {
+        int state[MAX_RHS] = {0};   // DD_SLOT_* of include/ddamg.h
+        double tol[MAX_RHS] = {0}, beta[MAX_RHS] = {0}, bnorm[MAX_RHS] = {0};
+        long its[MAX_RHS] = {0};
+        int restarts[MAX_RHS] = {0};
+        std::vector<Hess> hs;
+        bool any() const {
+            for (int r = 0; r < MAX_RHS; r++)
+                if (state[r]) return true;
+            return false;
+        }
+    } stream;
     void* scratch = nullptr;     // device address of this GPU's `scratch` array (dd_apply_D_noalloc)
     std::string scratch_err;     // why it is unavailable, if it is
     int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
@@ -898,14 +912,95 @@ struct KrylovResult {
 
 // Ops supplies, for a batch: precond(j, V_j, Z_j, batch), matvec(Z_j -> w),
 // residual(x -> V_0 := r - A x over the batch) and the vector sets.
+//
+// One restart cycle of the right-hand sides in `cyc`: V_0 of each holds its
+// current residual, of norm beta[r] > 0.  Up to m Arnoldi steps (a RHS leaves
+// when its estimate reaches tol[r] * bnorm[r], at maxit or at `fixed`
+// iterations), x += Z y, then the true residual replaces V_0 and beta[r].
+// its[r] counts the iterations of RHS r over all cycles.
+template <class VS, class ZS, class Ops>
+static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const double* tol, int maxit, long fixed,
+                         const Batch& in, int word, unsigned cyc, std::vector<Hess>& hs, double* beta,
+                         const double* bnorm, long* its) {
+    const int nr = in.nr;
+    cx<VS>* V = ops.V();
+    cx<ZS>* Z = ops.Z();
+    Batch bc = with_mask(C, in, word, cyc);
+    Coefs sc{};
+    for (int r = 0; r < nr; r++)
+        if ((cyc >> r) & 1u) { hs[r].reset(beta[r]); sc.v[r] = 1.0 / beta[r]; }
+    bvec_scale<VS>(n, sc, V, n, nr, bc.mask(), C->s);
+    Batch cur = with_mask(C, in, word + MAX_RHS, cyc);
+    int jend[MAX_RHS] = {0};
+    int jmax = 0;
+    for (int j = 0; j < m && cur.h; j++) {
+        cx<VS>* vj = V + (size_t)j * ldv;
+        cx<VS>* w = V + (size_t)(j + 1) * ldv;
+        cx<ZS>* zj = Z + (size_t)j * ldv;
+        ops.precond(vj, zj, cur);
+        ops.matvec(zj, w, cur);
+        {
+            RedBatch rb{nr, n, n, RS, cur.mask()};
+            Prof pr(C, DD_K_REDUCE, 4.0 * cur.count() * n * (j + 2) * sizeof(cx<VS>));
+            vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred, C->dwork, nullptr, C->s, rb);
+            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
+            vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
+            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb);
+        }
+        read_red(C, nr, 68);
+        unsigned next = cur.h;
+        Coefs wn{};
+        for (int r = 0; r < nr; r++) {
+            if (!cur.on(r)) continue;
+            const cx<double>* h = C->hred + (size_t)r * RS;
+            Hess& H = hs[r];
+            for (int i = 0; i <= j; i++) H.h(i, j) = zc(h[i].re + h[34 + i].re, h[i].im + h[34 + i].im);
+            double hn = std::sqrt(h[67].re);
+            if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
+            H.h(j + 1, j) = hn;
+            double res = H.rotate(j);
+            its[r]++;
+            jend[r] = j + 1;
+            jmax = std::max(jmax, j + 1);
+            bool stop;
+            if (fixed > 0) stop = its[r] >= fixed;
+            else stop = res <= tol[r] * bnorm[r] || its[r] >= maxit;
+            if (hn == 0) stop = true;
+            if (stop) next &= ~(1u << r);
+            else wn.v[r] = 1.0 / hn;
+        }
+        if (next != cur.h) cur = with_mask(C, in, word + MAX_RHS, next);
+        if (next) bvec_scale<VS>(n, wn, w, n, nr, cur.mask(), C->s);
+    }
+    // x += Z y per RHS over the columns of its own cycle
+    for (int r = 0; r < nr; r++) {
+        cx<double>* y = C->hy + (size_t)r * 32;
+        if (!bc.on(r)) continue;
+        hs[r].solve(jend[r]);
+        for (int i = 0; i < jend[r]; i++) y[i] = cx<double>{hs[r].y[i].real(), hs[r].y[i].imag()};
+    }
+    HIPX(hipMemcpyAsync(C->dy, C->hy, sizeof(cx<double>) * 32 * nr, hipMemcpyHostToDevice, C->s));
+    Counts jc{};
+    for (int r = 0; r < nr; r++) jc.v[r] = jend[r];
+    ops.update(jmax, Z, ldv, C->dy, bc, jc);
+    // true residual of the cycle's RHS: restart vector and convergence test
+    ops.residual(bc);
+    std::vector<double> nb = ops.norms(V, bc);
+    for (int r = 0; r < nr; r++) {
+        if (!bc.on(r)) continue;
+        beta[r] = nb[r];
+        if (!std::isfinite(beta[r])) fail(DD_ENUMERIC, "non-finite residual");
+    }
+}
+
+// Restart cycles until every RHS of the batch converged or reached its limit.
 template <class VS, class ZS, class Ops>
 static void fgmres_batch(dd_ctx* C, Ops& ops, long n, long ldv, int m, double tol, int maxit, long fixed,
                          const Batch& in, int word, const std::vector<double>& bnorm, KrylovResult& out) {
     const int nr = in.nr;
-    cx<VS>* V = ops.V();
-    cx<ZS>* Z = ops.Z();
     std::vector<Hess> hs(nr, Hess(m));
     std::vector<double> beta(bnorm);
+    std::vector<double> tols(nr, tol);
     unsigned alive = 0;
     for (int r = 0; r < nr; r++) {
         out.its[r] = 0;
@@ -926,72 +1021,11 @@ static void fgmres_batch(dd_ctx* C, Ops& ops, long n, long ldv, int m, double to
         }
         alive = cyc;
         if (!cyc) break;
-        Batch bc = with_mask(C, in, word, cyc);
-        Coefs sc{};
-        for (int r = 0; r < nr; r++)
-            if ((cyc >> r) & 1u) { hs[r].reset(beta[r]); sc.v[r] = 1.0 / beta[r]; }
-        bvec_scale<VS>(n, sc, V, n, nr, bc.mask(), C->s);
-        Batch cur = with_mask(C, in, word + MAX_RHS, cyc);
-        int jend[MAX_RHS] = {0};
-        int jmax = 0;
-        for (int j = 0; j < m && cur.h; j++) {
-            cx<VS>* vj = V + (size_t)j * ldv;
-            cx<VS>* w = V + (size_t)(j + 1) * ldv;
-            cx<ZS>* zj = Z + (size_t)j * ldv;
-            ops.precond(vj, zj, cur);
-            ops.matvec(zj, w, cur);
-            {
-                RedBatch rb{nr, n, n, RS, cur.mask()};
-                Prof pr(C, DD_K_REDUCE, 4.0 * cur.count() * n * (j + 2) * sizeof(cx<VS>));
-                vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred, C->dwork, nullptr, C->s, rb);
-                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
-                vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
-                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb);
-            }
-            read_red(C, nr, 68);
-            unsigned next = cur.h;
-            Coefs wn{};
-            for (int r = 0; r < nr; r++) {
-                if (!cur.on(r)) continue;
-                const cx<double>* h = C->hred + (size_t)r * RS;
-                Hess& H = hs[r];
-                for (int i = 0; i <= j; i++) H.h(i, j) = zc(h[i].re + h[34 + i].re, h[i].im + h[34 + i].im);
-                double hn = std::sqrt(h[67].re);
-                if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
-                H.h(j + 1, j) = hn;
-                double res = H.rotate(j);
-                out.its[r]++;
-                jend[r] = j + 1;
-                jmax = std::max(jmax, j + 1);
-                bool stop;
-                if (fixed > 0) stop = out.its[r] >= fixed;
-                else stop = res <= tol * bnorm[r] || out.its[r] >= maxit;
-                if (hn == 0) stop = true;
-                if (stop) next &= ~(1u << r);
-                else wn.v[r] = 1.0 / hn;
-            }
-            if (next != cur.h) cur = with_mask(C, in, word + MAX_RHS, next);
-            if (next) bvec_scale<VS>(n, wn, w, n, nr, cur.mask(), C->s);
-        }
-        // x += Z y per RHS over the columns of its own cycle
+        fgmres_cycle<VS, ZS>(C, ops, n, ldv, m, tols.data(), maxit, fixed, in, word, cyc, hs, beta.data(),
+                             bnorm.data(), out.its);
         for (int r = 0; r < nr; r++) {
-            cx<double>* y = C->hy + (size_t)r * 32;
-            if (!bc.on(r)) continue;
-            hs[r].solve(jend[r]);
-            for (int i = 0; i < jend[r]; i++) y[i] = cx<double>{hs[r].y[i].real(), hs[r].y[i].imag()};
-        }
-        HIPX(hipMemcpyAsync(C->dy, C->hy, sizeof(cx<double>) * 32 * nr, hipMemcpyHostToDevice, C->s));
-        Counts jc{};
-        for (int r = 0; r < nr; r++) jc.v[r] = jend[r];
-        ops.update(jmax, Z, ldv, C->dy, bc, jc);
-        // true residual of the cycle's RHS: restart vector and convergence test
-        ops.residual(bc);
-        std::vector<double> nb = ops.norms(V, bc);
-        for (int r = 0; r < nr; r++) {
-            if (!bc.on(r)) continue;
-            beta[r] = nb[r];
+            if (!((cyc >> r) & 1u)) continue;
             out.relres[r] = beta[r] / bnorm[r];
-            if (!std::isfinite(beta[r])) fail(DD_ENUMERIC, "non-finite residual");
             if (fixed > 0 && out.its[r] >= fixed) {
                 out.conv[r] = beta[r] <= tol * bnorm[r];
                 alive &= ~(1u << r);
@@ -1359,6 +1393,7 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
     C->levels.release();
     C->configured = false;
     C->have_setup = false;
+    C->stream = dd_ctx::StreamSlots{};
     C->p = p;
     // re-layout the fine fields if the SAP blocks differ from the current layout
     bool same = true;
@@ -1470,6 +1505,7 @@ static dd_status solve_impl(dd_ctx* C, Hier<T>& H, int k, const double* b, doubl
 dd_status dd_solve(dd_ctx* ctx, const double* b, double* x, double tol, dd_stats* st) {
     ABI_TRY(ctx)
     if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve before dd_setup");
+    if (ctx->stream.any()) fail(DD_ESTATE, "dd_solve while continuous-batching slots are in use");
     if (!b || !x) fail(DD_EINVAL, "NULL vector");
     if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
     dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, 1, b, x, tol, st) : solve_impl(ctx, *ctx->H32, 1, b, x, tol, st);
@@ -1483,6 +1519,7 @@ dd_status dd_solve_batch(dd_ctx* ctx, int k, const double* b, double* x, double 
     if (k < 0) fail(DD_EINVAL, "k < 0");
     if (k == 0) return DD_OK;
     if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve_batch before dd_setup");
+    if (ctx->stream.any()) fail(DD_ESTATE, "dd_solve_batch while continuous-batching slots are in use");
     if (!b || !x) fail(DD_EINVAL, "NULL vector");
     if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
     dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, k, b, x, tol, st) : solve_impl(ctx, *ctx->H32, k, b, x, tol, st);
@@ -1491,8 +1528,126 @@ dd_status dd_solve_batch(dd_ctx* ctx, int k, const double* b, double* x, double 
     ABI_END(ctx)
 }
 
+// ---------------------------------------------------------------------------
+// continuous batching: slots of the outer FGMRES loaded, cycled and read out
+// one restart cycle at a time
+// ---------------------------------------------------------------------------
+template <class T>
+static void stream_load_impl(dd_ctx* C, Hier<T>& H, int slot, const double* b, double tol) {
+    auto& S = C->stream;
+    const long n = 24L * C->g0.vh;
+    if ((int)S.hs.size() != C->R) S.hs.assign(C->R, Hess(C->p.outer_restart));
+    fine_import_vectors<double>(C->g0, 1, b, C->ob + (size_t)slot * n, C->s);
+    clear_flag(C, DI_BAD);
+    vec_finite_check<double>(n, C->ob + (size_t)slot * n, C->dflags + DI_BAD, C->s);
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "NaN/Inf in the right-hand side");
+    HIPX(hipMemsetAsync(C->ox + (size_t)slot * n, 0, sizeof(cx<double>) * n, C->s));
+    HIPX(hipMemcpyAsync(C->oV + (size_t)slot * n, C->ob + (size_t)slot * n, sizeof(cx<double>) * n,
+                        hipMemcpyDeviceToDevice, C->s));
+    // no cycle is running: the outer FGMRES's own mask words carry this slot
+    Batch all{C->R, C->dflags + DI_ONES, (C->R >= 32) ? ~0u : ((1u << C->R) - 1)};
+    Batch one = with_mask(C, all, 0, 1u << slot);
+    std::vector<double> nb = OuterOps<T>::norms64(C, n, C->ob, one);
+    S.bnorm[slot] = S.beta[slot] = nb[slot];
+    S.tol[slot] = tol;
+    S.its[slot] = 0;
+    S.restarts[slot] = 0;
+    for (int l = 0; l < DD_MAXLEV; l++) H.coarse_count[l][slot] = 0;
+    S.state[slot] = (nb[slot] == 0) ? DD_SLOT_CONVERGED : DD_SLOT_RUNNING;
+}
+
+static void stream_stats(dd_ctx* C, int r, dd_stats* st, const long (*cc)[MAX_RHS]) {
+    auto& S = C->stream;
+    memset(st, 0, sizeof *st);
+    st->outer_iters = (int)S.its[r];
+    st->restarts = S.restarts[r];
+    for (int l = 0; l < DD_MAXLEV; l++) st->coarse_iters[l] = cc[l][r];
+    st->true_relres = S.bnorm[r] > 0 ? S.beta[r] / S.bnorm[r] : 0.0;
+    st->converged = S.state[r] == DD_SLOT_CONVERGED;
+    st->setup_s = C->last_setup_s;
+}
+
+template <class T>
+static void stream_cycle_impl(dd_ctx* C, Hier<T>& H, int* state, dd_stats* st) {
+    auto& S = C->stream;
+    const dd_params& p = C->p;
+    const int m = p.outer_restart, R = C->R;
+    const long n = 24L * C->g0.vh, ldv = (long)R * n;
+    unsigned cyc = 0;
+    for (int r = 0; r < R; r++) {
+        if (S.state[r] != DD_SLOT_RUNNING) continue;
+        if (S.beta[r] <= S.tol[r] * S.bnorm[r]) S.state[r] = DD_SLOT_CONVERGED;
+        else if (S.its[r] >= p.outer_maxit) S.state[r] = DD_SLOT_STOPPED;
+        else cyc |= 1u << r;
+    }
+    if (cyc) {
+        const double t0 = now_s();
+        Batch all{R, C->dflags + DI_ONES, (R >= 32) ? ~0u : ((1u << R) - 1)};
+        OuterOps<T> ops{C, &H, C->ob, C->ox, n, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
+        fgmres_cycle<double, T>(C, ops, n, ldv, m, S.tol, p.outer_maxit, 0, all, 0, cyc, S.hs, S.beta, S.bnorm,
+                                S.its);
+        sync(C);
+        (void)t0;
+        for (int r = 0; r < R; r++) {
+            if (!((cyc >> r) & 1u)) continue;
+            if (S.beta[r] <= S.tol[r] * S.bnorm[r]) S.state[r] = DD_SLOT_CONVERGED;
+            else if (S.its[r] >= p.outer_maxit) S.state[r] = DD_SLOT_STOPPED;
+            else S.restarts[r]++;
+        }
+    }
+    for (int r = 0; r < R; r++) {
+        if (state) state[r] = S.state[r];
+        if (st) stream_stats(C, r, st + r, H.coarse_count);
+    }
+}
+
+dd_status dd_stream_load(dd_ctx* ctx, int slot, const double* b, double tol) {
+    ABI_TRY(ctx)
+    if (!ctx->have_setup) fail(DD_ESTATE, "dd_stream_load before dd_setup");
+    if (slot < 0 || slot >= ctx->R) fail(DD_EINVAL, "slot out of range 0..max_rhs-1");
+    if (ctx->stream.state[slot] != DD_SLOT_FREE) fail(DD_ESTATE, "slot in use");
+    if (!b) fail(DD_EINVAL, "NULL vector");
+    if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
+    if (ctx->H64) stream_load_impl(ctx, *ctx->H64, slot, b, tol);
+    else stream_load_impl(ctx, *ctx->H32, slot, b, tol);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_stream_cycle(dd_ctx* ctx, int* state, dd_stats* st) {
+    ABI_TRY(ctx)
+    if (!ctx->have_setup) fail(DD_ESTATE, "dd_stream_cycle before dd_setup");
+    if (ctx->H64) stream_cycle_impl(ctx, *ctx->H64, state, st);
+    else stream_cycle_impl(ctx, *ctx->H32, state, st);
+    return DD_OK;
+    ABI_END(ctx)
+}
+
+dd_status dd_stream_take(dd_ctx* ctx, int slot, double* x, dd_stats* st) {
+    ABI_TRY(ctx)
+    if (slot < 0 || slot >= ctx->R) fail(DD_EINVAL, "slot out of range 0..max_rhs-1");
+    auto& S = ctx->stream;
+    if (S.state[slot] != DD_SLOT_CONVERGED && S.state[slot] != DD_SLOT_STOPPED) fail(DD_ESTATE, "slot not finished");
+    if (!x) fail(DD_EINVAL, "NULL vector");
+    const long n = 24L * ctx->g0.vh;
+    fine_export_vectors<double>(ctx->g0, 1, ctx->ox + (size_t)slot * n, x, ctx->s);
+    HIPX(hipGetLastError());
+    sync(ctx);
+    if (st) {
+        if (ctx->H64) stream_stats(ctx, slot, st, ctx->H64->coarse_count);
+        else stream_stats(ctx, slot, st, ctx->H32->coarse_count);
+    }
+    const bool ok = S.state[slot] == DD_SLOT_CONVERGED;
+    S.state[slot] = DD_SLOT_FREE;
+    if (!ok) fail(DD_ENOCONV, "the right-hand side of this slot reached outer_maxit");
+    return DD_OK;
+    ABI_END(ctx)
+}
+
 dd_status dd_set_mass(dd_ctx* ctx, double m0) {
     ABI_TRY(ctx)
+    for (int r = 0; r < MAX_RHS; r++)
+        if (ctx->stream.state[r] == DD_SLOT_RUNNING) fail(DD_ESTATE, "dd_set_mass while continuous-batching slots run");
     double dm = m0 - ctx->m0;
     clear_flag(ctx, DI_BAD);
     fine_clover_shift(ctx->g0, dm, ctx->clov64, ctx->clovinv64, ctx->dflags + DI_BAD, ctx->s);

@@ -7,9 +7,12 @@ time.  The server
     context) resident on the device, admitted against an HBM budget and
     evicted least-recently-used when a new field needs room and the old one
     is idle;
-  * batches right-hand sides that share a field and tolerance: RHS of
-    different requests join one dd_solve_batch call as slots free up, and a
-    large request is spread over several batches;
+  * batches right-hand sides that share a field: with a backend that offers
+    continuous batching (dd_stream_*: the default solver) every slot of the
+    outer FGMRES that finishes is refilled with the next queued RHS of the
+    field between two restart cycles, while the other slots keep running; a
+    backend with only solve_batch runs whole batches of one tolerance, RHS of
+    different requests joining as batches start;
   * runs the batches of different fields concurrently, each field's context
     on its own HIP stream driven by its own worker thread, so their kernels
     overlap on the device;
@@ -322,10 +325,79 @@ class Server:
                 out.append(fid)
         return out
 
+    def _deliver(self, req, q, x, st, t):
+        """Record the result of RHS q of req (caller holds the lock)."""
+        req.x[q] = x.cpu() if (self.results_on_host and hasattr(x, "cpu")) else x
+        req.stats[q] = st
+        req.done += 1
+        self._solved += 1
+        if req.done == req.k:
+            self._pending.remove(req)
+            self._latency.append(t - req.t_submit)
+            self._t_last = t
+            xs, req.x = _stack(req.x), None
+            req.rhs = None
+            req.future.set_result((xs, req.stats))
+
+    def _next_rhs(self, fid, m0):
+        """The next queued RHS of field `fid` at mass m0 (any mass if None), in
+        arrival order (caller holds the lock)."""
+        for req in self._pending:
+            if req.field_id != fid or req.next_rhs >= req.k:
+                continue
+            if m0 is not None and req.m0 != m0:
+                continue
+            q = req.next_rhs
+            req.next_rhs += 1
+            return req, q
+        return None
+
+    def _work_stream(self, fid, solver):
+        """Continuous batching: refill every finished slot between restart
+        cycles with the next queued RHS of this field (one mass at a time:
+        the mass may change only when no slot runs)."""
+        slots = [None] * self.max_rhs
+        mass = None
+        while True:
+            with self._cv:
+                self._resident.move_to_end(fid)
+                running = any(sl is not None for sl in slots)
+                if not running:
+                    mass = None
+                new = []
+                for i in range(self.max_rhs):
+                    if slots[i] is not None:
+                        continue
+                    nxt = self._next_rhs(fid, mass)
+                    if nxt is None:
+                        break
+                    slots[i] = nxt
+                    mass = nxt[0].m0
+                    new.append(i)
+            if not running and not new:
+                return
+            if new and not running and mass is not None and getattr(solver, "m0", mass) != mass:
+                solver.set_mass(mass)
+            for i in new:
+                req, q = slots[i]
+                solver.stream_load(i, req.rhs[q], req.tol)
+            states, _ = solver.stream_cycle()
+            done = []
+            for i, stt in enumerate(states):
+                if slots[i] is not None and stt in (solver.SLOT_CONVERGED, solver.SLOT_STOPPED):
+                    x, st = solver.stream_take(i, allow_noconv=True)
+                    done.append((slots[i], x, st))
+                    slots[i] = None
+            if done:
+                t = self.clock()
+                with self._cv:
+                    for (req, q), x, st in done:
+                        self._deliver(req, q, x, st, t)
+
     def _work(self, fid):
-        """Worker of one field: set up if needed, then solve batches of this
-        field until none is left (solve_batch returns after its stream has
-        finished)."""
+        """Worker of one field: set up if needed, then solve the field's queued
+        RHS until none is left (continuous batching when the backend offers it,
+        else whole batches; both return after their stream has finished)."""
         try:
             with self._cv:
                 solver = self._resident.get(fid)
@@ -345,6 +417,9 @@ class Server:
                     self._resident_bytes[fid] = held
                     self.admitted += 1
                     self._trim(keep=fid)
+            if hasattr(solver, "stream_cycle"):
+                self._work_stream(fid, solver)
+                return
             while True:
                 with self._cv:
                     self._resident.move_to_end(fid)
@@ -358,17 +433,7 @@ class Server:
                 t = self.clock()
                 with self._cv:
                     for i, (req, q) in enumerate(batch):
-                        req.x[q] = X[i].cpu() if (self.results_on_host and hasattr(X[i], "cpu")) else X[i]
-                        req.stats[q] = st[i]
-                        req.done += 1
-                        self._solved += 1
-                        if req.done == req.k:
-                            self._pending.remove(req)
-                            self._latency.append(t - req.t_submit)
-                            self._t_last = t
-                            x, req.x = _stack(req.x), None
-                            req.rhs = None
-                            req.future.set_result((x, req.stats))
+                        self._deliver(req, q, X[i], st[i], t)
         except BaseException as e:  # fail the requests of this field, keep serving others
             with self._cv:
                 for req in [r for r in self._pending if r.field_id == fid]:

@@ -218,6 +218,98 @@ def test_masses_are_not_mixed_in_a_batch():
     assert len(made[0].calls) <= len(masses)
 
 
+class FakeStreamSolver:
+    """Continuous-batching backend: a RHS b needs 1 + round(|b[0,0,0]| * 4)
+    restart cycles (capped at 6) and its solution is 2 b; records how many
+    slots run in each cycle and the order in which RHS finish."""
+
+    SLOT_FREE, SLOT_RUNNING, SLOT_CONVERGED, SLOT_STOPPED = 0, 1, 2, 3
+
+    def __init__(self, spec, max_rhs):
+        self.spec = spec
+        self.m0 = spec.m0
+        self.slots = [None] * max_rhs     # [b, cycles left]
+        self.state = [0] * max_rhs
+        self.occupancy = []
+        self.finished = []
+
+    def stream_load(self, i, b, tol):
+        assert self.state[i] == 0
+        b = np.asarray(b)
+        self.slots[i] = [b, 1 + min(5, int(round(abs(b.reshape(-1)[0]) * 4)))]
+        self.state[i] = 1
+
+    def stream_cycle(self):
+        self.occupancy.append(sum(1 for st in self.state if st == 1))
+        time.sleep(0.002)
+        for i, sl in enumerate(self.slots):
+            if self.state[i] == 1:
+                sl[1] -= 1
+                if sl[1] == 0:
+                    self.state[i] = 2
+        return list(self.state), [dict(converged=st == 2) for st in self.state]
+
+    def stream_take(self, i, allow_noconv=False):
+        assert self.state[i] in (2, 3)
+        b = self.slots[i][0]
+        self.finished.append(float(b.reshape(-1)[0]))
+        self.slots[i] = None
+        self.state[i] = 0
+        return 2 * b, dict(converged=True)
+
+    def set_mass(self, m0):
+        assert all(st != 1 for st in self.state), "mass changed while slots run"
+        self.m0 = m0
+
+    def close(self):
+        pass
+
+
+def test_continuous_batching_refills_finished_slots():
+    """A slot whose RHS finished takes the next queued RHS at the following
+    restart cycle, while the other slots keep running: short solves queued
+    behind a long one finish before it, every cycle with queued work keeps
+    all slots busy, and each result is the RHS's own."""
+    made = []
+
+    def factory(spec):
+        s = FakeStreamSolver(spec, 4)
+        made.append(s)
+        return s
+
+    srv = Server(budget_bytes=1e12, max_rhs=4, solver_factory=factory)
+    dims = (4, 4, 4, 4)
+    srv.add_field("f", dims, None, -0.4, 1.0)
+    long_b = np.full((1, 256, 4, 3), 1.25)          # 6 cycles
+    short = [np.full((1, 256, 4, 3), 0.01 * (i + 1)) for i in range(9)]   # 1 cycle each
+    futs = [srv.submit("f", long_b)] + [srv.submit("f", b) for b in short]
+    res = [f.result(timeout=10) for f in futs]
+    srv.close()
+    assert np.array_equal(res[0][0], 2 * long_b)
+    for b, (x, _) in zip(short, res[1:]):
+        assert np.array_equal(x, 2 * b)
+    s = made[0]
+    assert s.finished[-1] == 1.25            # the long solve ends last
+    # 10 RHS in 4 slots: the short ones stream through the three slots the long one leaves
+    assert len(s.occupancy) <= 6 and max(s.occupancy) == 4
+
+
+def test_continuous_batching_keeps_one_mass_per_cycle():
+    made = []
+
+    def factory(spec):
+        s = FakeStreamSolver(spec, 4)
+        made.append(s)
+        return s
+
+    srv = Server(budget_bytes=1e12, max_rhs=4, solver_factory=factory)
+    srv.add_field("f", (4, 4, 4, 4), None, -0.4, 1.0)
+    futs = [srv.submit("f", np.full((2, 256, 4, 3), 0.3), m0=(-0.4 if i % 2 == 0 else -0.3)) for i in range(6)]
+    res = [f.result(timeout=10) for f in futs]
+    srv.close()
+    assert all(np.allclose(x, 0.6) for x, _ in res)
+
+
 @pytest.mark.gpu
 def test_served_results_equal_solo_solves():
     """Two resident fields of different sizes, requests of 1..5 RHS arriving
@@ -303,4 +395,56 @@ def test_served_masses_meet_their_residuals():
             xs, _ = solo.solve(b[q], 1e-10)
             xs = xs.cpu().numpy()
             assert np.linalg.norm(x[q] - xs) <= 1e-12 * np.linalg.norm(xs)
+    solo.close()
+
+
+@pytest.mark.gpu
+def test_stream_slots_refilled_match_solo_solves():
+    """dd_stream_*: six right-hand sides through three slots, each finished
+    slot refilled with the next RHS between restart cycles; every result
+    equals the single solve of its RHS (1e-12) and meets its true residual,
+    and dd_solve is refused while slots are in use."""
+    import oracle as O
+    import paper_1303_1377_amd as G
+
+    dims = (8, 8, 8, 8)
+    U = F.make_gauge(dims, 0.3, 4)
+    kw = dict(levels=2, n_tv=[8], agg=[(2, 2, 2, 2)], sap=[(2, 2, 2, 2)], mr_steps=[4], n_inv=2, outer_restart=5)
+    s = G.Solver(dims, U, -0.25, 1.0)
+    s.setup(params=G.default_params(max_rhs=3, **kw))
+    solo = G.Solver(dims, U, -0.25, 1.0)
+    solo.setup(params=G.default_params(max_rhs=3, **kw))
+    orc = O.Oracle(dims, U, -0.25, 1.0)
+    bs = [F.gaussian_spinor(dims, 900 + i) * (10.0 ** (-(i % 3))) for i in range(6)]
+    queue = list(range(6))
+    slot_of = [None] * 3
+    results = {}
+    cycles = 0
+    while queue or any(v is not None for v in slot_of):
+        for i in range(3):
+            if slot_of[i] is None and queue:
+                q = queue.pop(0)
+                s.stream_load(i, bs[q], 1e-10)
+                slot_of[i] = q
+        if cycles == 0:
+            with pytest.raises(G.DDError) as ei:
+                s.solve(bs[0], 1e-10)
+            assert ei.value.code == -5
+        states, _ = s.stream_cycle()
+        cycles += 1
+        for i, stt in enumerate(states):
+            if slot_of[i] is not None and stt in (s.SLOT_CONVERGED, s.SLOT_STOPPED):
+                x, st = s.stream_take(i)
+                results[slot_of[i]] = (x.cpu().numpy(), st)
+                slot_of[i] = None
+        assert cycles < 200
+    for q, b in enumerate(bs):
+        x, st = results[q]
+        xs, sts = solo.solve(b, 1e-10)
+        xs = xs.cpu().numpy()
+        assert st["converged"] and st["outer_iters"] == sts["outer_iters"]
+        assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+        r = b - orc.apply(x)
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
+    s.close()
     solo.close()
