@@ -145,6 +145,18 @@ dd_status dd_solve(dd_ctx *ctx, const double *b, double *x, double tol, dd_stats
  *   stats array of k records or NULL */
 dd_status dd_solve_batch(dd_ctx *ctx, int k, const double *b, double *x, double tol, dd_stats *stats);
 
+/* Comparison solver of Sec. 6 (Table 3 and its footnote): FGMRES(outer_restart)
+ * in FP64 right-preconditioned by `steps` BiCGStab steps (zero start) on the
+ * odd-even reduced system S x_o = b_o - D_oe A_ee^{-1} b_e,
+ * S = A_oo - D_oe A_ee^{-1} D_eo, and the even-site back-substitution, in
+ * `precision` 32 (the paper's mixed-precision form) or 64.  Needs
+ * dd_configure (the outer Krylov workspace; no multigrid setup is used).
+ *   b, x  device complex128 fine spinors; x output only (x0 = 0)
+ * stats: outer_iters, restarts, true_relres, converged; coarse_iters[0] counts
+ * the BiCGStab steps.  Errors as dd_solve (DD_ESTATE without dd_configure). */
+dd_status dd_solve_bicgstab(dd_ctx *ctx, const double *b, double *x, double tol, int steps, int precision,
+                            dd_stats *stats);
+
 /* Continuous batching on the resident setup.  The max_rhs right-hand-side
  * slots of the outer FGMRES are filled, advanced and emptied independently:
  * a slot whose solve has finished is read out and refilled with a new
@@ -221,7 +233,11 @@ typedef enum {
     DD_OP_COARSE_SOLVE = 6, /* out = coarsest-level odd-even GMRES solution for in     */
     DD_OP_SCHUR = 7,        /* out = S in, S = A_oo - D_oe A_ee^-1 D_eo on `level`;
                                in and out are full vectors, zero on even sites        */
-    DD_OP_FGMRES = 8        /* intermediate-level FGMRES (3+ levels) on `level`         */
+    DD_OP_FGMRES = 8,       /* intermediate-level FGMRES (3+ levels) on `level`         */
+    DD_OP_BICGSTAB = 9      /* level 0: `arg` BiCGStab steps on the odd-even reduced
+                               system from zero, then the even-site back-substitution
+                               (the preconditioner of dd_solve_bicgstab), in the
+                               preconditioner precision                              */
 } dd_op;
 
 /* Apply one component.  in/out are device complex128 vectors of the level in

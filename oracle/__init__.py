@@ -146,6 +146,9 @@ def lib():
         L.or_coarse_solve.argtypes = [vp, C.c_int, cp, cp]
         L.or_schur.argtypes = [vp, C.c_int, cp, cp]
         L.or_vcycle.argtypes = [vp, C.c_int, C.c_int, cp, cp]
+        L.or_bicgstab.restype = C.c_long
+        L.or_bicgstab.argtypes = [vp, cp, cp, C.c_int]
+        L.or_solve_bicgstab.argtypes = [vp, cp, cp, dp, C.c_int, C.POINTER(Stats)]
         L.or_fgmres_level.restype = C.c_long
         L.or_fgmres_level.argtypes = [vp, C.c_int, cp, cp]
         L.or_setup_level.argtypes = [vp, C.c_int]
@@ -352,6 +355,22 @@ class Oracle:
         ptrs = (C.c_void_p * MAXLEV)(*([a.ctypes.data for a in arrs] + [None] * (MAXLEV - len(arrs))))
         if lib().or_setup(self.h, ptrs):
             raise RuntimeError("oracle setup: " + lib().or_error(self.h).decode())
+
+    def bicgstab(self, b, steps):
+        """Odd-even BiCGStab (steps from zero) + back-substitution: ~D^{-1} b."""
+        bb = _c(b).reshape(self.vol * 12)
+        x = np.zeros_like(bb)
+        its = lib().or_bicgstab(self.h, _ptr(bb), _ptr(x), int(steps))
+        return x.reshape(np.shape(b)), its
+
+    def solve_bicgstab(self, b, tol=1e-10, steps=50):
+        """FGMRES(outer_restart) preconditioned by `steps` odd-even BiCGStab steps."""
+        bb = _c(b).reshape(self.vol * 12)
+        x = np.zeros_like(bb)
+        st = Stats()
+        rc = lib().or_solve_bicgstab(self.h, _ptr(bb), _ptr(x), float(tol), int(steps), C.byref(st))
+        return x.reshape(np.shape(b)), dict(rc=rc, outer_iters=st.outer_iters, restarts=st.restarts,
+                                            true_relres=st.true_relres, converged=bool(st.converged))
 
     def mark_setup(self):
         lib().or_mark_setup(self.h)

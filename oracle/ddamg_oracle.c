@@ -24,6 +24,7 @@
  *   outer solver ........ Sec. 4.2/5    FGMRES right-preconditioned by one V-cycle
  *   setup ............... Alg. 2        DD-alpha-AMG-setup(n_inv, nu) built on Alg. 1
  *   multilevel .......... Sec. 3, 5     recursive application on D_c
+ *   comparison solver ... Sec. 6        FGMRES preconditioned by odd-even BiCGStab
  *
  * Readings of points the paper leaves open are listed in the design notes of
  * the repository and repeated at the routine that takes them.
@@ -289,6 +290,8 @@ typedef struct {
     int have_params;
     int have_setup;
     long coarse_count[OR_MAXLEV];
+    int pre_bicg;    /* > 0: the outer FGMRES is preconditioned by this many
+                        odd-even BiCGStab steps instead of the V-cycle       */
     char err[256];
 } octx;
 
@@ -931,6 +934,73 @@ static long coarse_solve(const level *C, const or_params *p, const cplx *r, cplx
 }
 
 /* ------------------------------------------------------------------------ */
+/* comparison solver of Sec. 6: odd-even preconditioned BiCGStab            */
+/* ------------------------------------------------------------------------ */
+
+/* x = approximate D^{-1} b on level L by the odd-even reduction (Sec. 6):
+ * f_o = b_o - D_oe A_ee^{-1} b_e, `steps` steps of BiCGStab (van der Vorst,
+ * SIAM J. Sci. Stat. Comput. 13 (1992)) from zero on S x_o = f_o with
+ * S = A_oo - D_oe A_ee^{-1} D_eo, then x_e = A_ee^{-1} (b_e - D_eo x_o).
+ * The reduced vectors are full-length with zero even entries.  Returns the
+ * steps taken (fewer on an exact breakdown). */
+static long bicgstab_oe(const level *L, const cplx *b, cplx *x, int steps) {
+    const int nd = L->nd;
+    const long n = L->g.vol * nd;
+    const long *nb = L->g.nb;
+    cplx *t = cvalloc(n), *r = cvalloc(n), *rh = cvalloc(n), *p = cvalloc(n), *v = cvalloc(n);
+    cplx *s = cvalloc(n), *tt = cvalloc(n), *xo = cvalloc(n), *w = cvalloc(n);
+    /* t_e = A_ee^{-1} b_e ; r_o = b_o - D_oe t_e ; even entries of r stay 0 */
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < L->g.vol; y++)
+        if (L->g.par[y] == 0) site_self_inv(L, y, b + y * nd, t + y * nd);
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < L->g.vol; y++) {
+        if (L->g.par[y] != 1) continue;
+        cplx u[128];
+        for (int c = 0; c < nd; c++) u[c] = 0;
+        for (int k = 0; k < 8; k++) site_hop_acc(L, y, k, t + nb[y * 8 + k] * nd, u);
+        for (int c = 0; c < nd; c++) r[y * nd + c] = b[y * nd + c] - u[c];
+    }
+    vcopy(n, r, rh);
+    cplx rho_old = 1, alpha = 1, omega = 1;
+    long it = 0;
+    for (; it < steps; it++) {
+        cplx rho = vdot(n, rh, r);
+        if (rho == 0) break;
+        cplx beta = (rho / rho_old) * (alpha / omega);
+        for (long i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        schur_apply(L, p, v, w);
+        cplx rv = vdot(n, rh, v);
+        if (rv == 0) break;
+        alpha = rho / rv;
+        for (long i = 0; i < n; i++) s[i] = r[i] - alpha * v[i];
+        schur_apply(L, s, tt, w);
+        double tn = creal(vdot(n, tt, tt));
+        vaxpy(n, alpha, p, xo);
+        if (tn == 0) { it++; break; }
+        omega = vdot(n, tt, s) / tn;
+        vaxpy(n, omega, s, xo);
+        for (long i = 0; i < n; i++) r[i] = s[i] - omega * tt[i];
+        rho_old = rho;
+    }
+    /* x_e = A_ee^{-1} (b_e - D_eo x_o) ; x_o as solved */
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < L->g.vol; y++) {
+        if (L->g.par[y] == 0) {
+            cplx u[128], q[128];
+            for (int c = 0; c < nd; c++) u[c] = 0;
+            for (int k = 0; k < 8; k++) site_hop_acc(L, y, k, xo + nb[y * 8 + k] * nd, u);
+            for (int c = 0; c < nd; c++) q[c] = b[y * nd + c] - u[c];
+            site_self_inv(L, y, q, x + y * nd);
+        } else {
+            for (int c = 0; c < nd; c++) x[y * nd + c] = xo[y * nd + c];
+        }
+    }
+    free(t); free(r); free(rh); free(p); free(v); free(s); free(tt); free(xo); free(w);
+    return it;
+}
+
+/* ------------------------------------------------------------------------ */
 /* V-cycle and FGMRES                                                        */
 /* ------------------------------------------------------------------------ */
 static void vcycle(octx *X, int l, int bottom, const cplx *r, cplx *z);
@@ -969,7 +1039,8 @@ static long fgmres(octx *X, int l, int bottom, const cplx *rhs, cplx *x, double 
         vscale(n, 1.0 / beta, V[0]);
         int jend = 0;
         for (int j = 0; j < m; j++) {
-            vcycle(X, l, bottom, V[j], Z[j]);
+            if (X->pre_bicg > 0 && l == 0) bicgstab_oe(L, V[j], Z[j], X->pre_bicg);
+            else vcycle(X, l, bottom, V[j], Z[j]);
             apply_full(L, Z[j], w);
             for (int pass = 0; pass < 2; pass++)
                 for (int i = 0; i <= j; i++) {
@@ -1350,6 +1421,38 @@ int or_solve(void *p, const cplx *b, cplx *x, double tol, long fixed, or_stats *
         st->restarts = restarts;
         st->converged = conv;
         for (int l = 0; l < OR_MAXLEV; l++) st->coarse_iters[l] = X->coarse_count[l];
+    }
+    return conv ? 0 : -3;
+}
+
+/* x = BiCGStab preconditioner (odd-even, `steps` steps from zero) applied to b
+ * on the fine level. */
+long or_bicgstab(void *p, const cplx *b, cplx *x, int steps) {
+    return bicgstab_oe(&((octx *)p)->L[0], b, x, steps);
+}
+
+/* The comparison solver: FGMRES(outer_restart) on the fine level,
+ * right-preconditioned by `steps` odd-even BiCGStab steps (needs
+ * or_configure for the outer parameters; no multigrid setup is used). */
+int or_solve_bicgstab(void *p, const cplx *b, cplx *x, double tol, int steps, or_stats *st) {
+    octx *X = (octx *)p;
+    if (!X->have_params) return -5;
+    X->pre_bicg = steps;
+    int restarts = 0, conv = 0;
+    long its = fgmres(X, 0, 0, b, x, tol, X->p.outer_restart, X->p.outer_maxit, 0, &restarts, &conv);
+    X->pre_bicg = 0;
+    if (st) {
+        level *L = &X->L[0];
+        long n = L->g.vol * L->nd;
+        cplx *r = cvalloc(n);
+        apply_full(L, x, r);
+        for (long i = 0; i < n; i++) r[i] = b[i] - r[i];
+        st->true_relres = vnorm(n, r) / vnorm(n, b);
+        free(r);
+        st->outer_iters = (int)its;
+        st->restarts = restarts;
+        st->converged = conv;
+        memset(st->coarse_iters, 0, sizeof st->coarse_iters);
     }
     return conv ? 0 : -3;
 }

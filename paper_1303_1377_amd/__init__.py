@@ -21,7 +21,7 @@ MAXLEV = 4
 
 KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse", "coarse_sap", "reduce", "blas",
                   "coarse_step"]
-OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8)
+OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8, BICGSTAB=9)
 STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
           -6: "DD_ENUMERIC"}
 
@@ -106,6 +106,7 @@ def library():
         L.dd_apply.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_D_noalloc.argtypes = [vp, vp, vp]
+        L.dd_solve_bicgstab.argtypes = [vp, vp, vp, dp, C.c_int, C.c_int, C.POINTER(Stats)]
         L.dd_stream_load.argtypes = [vp, C.c_int, vp, dp]
         L.dd_stream_cycle.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(Stats)]
         L.dd_stream_take.argtypes = [vp, C.c_int, vp, C.POINTER(Stats)]
@@ -125,6 +126,7 @@ def library():
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
                      "dd_profile_classes", "dd_apply_D_noalloc", "dd_stream_load", "dd_stream_cycle", "dd_stream_take",
+                     "dd_solve_bicgstab",
                      "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -307,6 +309,19 @@ class Solver:
         x = torch.empty((self.vol, 4, 3), dtype=torch.complex128, device="cuda")
         st = Stats()
         rc = library().dd_stream_take(self.h, int(slot), C.c_void_p(x.data_ptr()), C.byref(st))
+        self._check(rc, ok=(0, -3) if allow_noconv else (0,))
+        return x, st.as_dict()
+
+    def solve_bicgstab(self, b, tol=1e-10, steps=50, precision=32, allow_noconv=False):
+        """The comparison solver: FP64 FGMRES preconditioned by `steps` odd-even
+        BiCGStab steps in `precision` (needs configure())."""
+        torch = _torch()
+        bb = _dev(b).reshape(self.vol, 4, 3)
+        x = torch.empty_like(bb)
+        st = Stats()
+        _order_after_current(self.stream)
+        rc = library().dd_solve_bicgstab(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
+                                         int(steps), int(precision), C.byref(st))
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, st.as_dict()
 

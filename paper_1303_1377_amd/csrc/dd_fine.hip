@@ -448,6 +448,75 @@ __global__ void __launch_bounds__(256) k_dirac(FineOp<T, S> op, const cx<T>* __r
 }
 
 // ---------------------------------------------------------------------------
+// One parity of the odd-even reduced operator (the odd-even preconditioned
+// BiCGStab of the comparison solver, Sec. 6): with p the parity written,
+// q = 1 - p, D_pq = -1/2 H_pq the hopping between the parities and A_pp the
+// clover blocks,
+//   out_p = M ( s * P self_p + c * D_pq in_q ),
+// P = A_pp when PRE_A else I, M = A_pp^{-1} when POST_INV else I.  The hops
+// run in the order of the full stencil.  One thread per site of parity p.
+// ---------------------------------------------------------------------------
+template <class T, class S, bool PRE_A, bool POST_INV>
+__global__ void __launch_bounds__(256) k_oe_hop(FineOp<T, S> op, int p, const cx<T>* __restrict__ self,
+                                                const cx<T>* __restrict__ in, cx<T>* __restrict__ out, T sc, T cc) {
+    const Geom g = op.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.vh) return;
+    int x[4];
+    cb_coords(g, p, i, x);
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = czero<T>();
+    if (cc != T(0)) {
+#pragma unroll
+        for (int kk = 0; kk < 8; kk++) {
+            const int k = (kk >> 1) + ((kk & 1) << 2);
+            int y[4];
+            nb_coords(g, x, k, y);
+            const int j = cb_index(g, y);
+            cx<T> v[12];
+            load_spinor(in, g.vh, 1 - p, j, v);
+            hop_accum(op, k, p, i, j, v, acc);
+        }
+    }
+    cx<T> a[12];
+    if (sc != T(0)) {
+        cx<T> v[12];
+        load_spinor(self, g.vh, p, i, v);
+        if (PRE_A) clover_apply(op.clov, g.vh, p, i, v, a);
+        else
+#pragma unroll
+            for (int c = 0; c < 12; c++) a[c] = v[c];
+#pragma unroll
+        for (int c = 0; c < 12; c++) a[c] = sc * a[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) a[c] = czero<T>();
+    }
+    const T hc = T(-0.5) * cc;
+#pragma unroll
+    for (int c = 0; c < 12; c++) a[c] += hc * acc[c];
+    if (POST_INV) {
+        cx<T> b[12];
+        clover_apply(op.clovinv, g.vh, p, i, a, b);
+        store_spinor(out, g.vh, p, i, b);
+    } else {
+        store_spinor(out, g.vh, p, i, a);
+    }
+}
+
+template <class T, class S>
+void fine_oe_hop(const FineOp<T, S>& op, int p, bool pre_a, bool post_inv, double sc, double cc, const cx<T>* self,
+                 const cx<T>* in, cx<T>* out, hipStream_t s) {
+    const int nb = nblk_of(op.g.vh, 256);
+    const T a = T(sc), b = T(cc);
+    if (pre_a && post_inv) k_oe_hop<T, S, true, true><<<nb, 256, 0, s>>>(op, p, self, in, out, a, b);
+    else if (pre_a) k_oe_hop<T, S, true, false><<<nb, 256, 0, s>>>(op, p, self, in, out, a, b);
+    else if (post_inv) k_oe_hop<T, S, false, true><<<nb, 256, 0, s>>>(op, p, self, in, out, a, b);
+    else k_oe_hop<T, S, false, false><<<nb, 256, 0, s>>>(op, p, self, in, out, a, b);
+}
+
+// ---------------------------------------------------------------------------
 // Stencil with the layout block staged in LDS (SCHED_LDS).  One workgroup per
 // layout block, one thread per site (threads [0, bvh) even, [bvh, 2 bvh) odd).
 //   1. every thread copies its spinor into SP (coalesced; each spinor is read
@@ -1576,6 +1645,8 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
 // operator kernels for compute type T and storage type S
 #define DD_FINE_OP_INST(T, S)                                                                                 \
     template void fine_dirac<T, S>(const FineOp<T, S>&, const cx<T>*, cx<T>*, hipStream_t, int, long, Mask);  \
+    template void fine_oe_hop<T, S>(const FineOp<T, S>&, int, bool, bool, double, double, const cx<T>*,         \
+                                    const cx<T>*, cx<T>*, hipStream_t);                                       \
     template void fine_sap_half<T, S>(const FineOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
                                       int, long, Mask);                                                       \
     template void fine_restrict<T, S>(const AggMap&, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int,   \

@@ -116,6 +116,12 @@ void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* b
 template <class T>
 void fine_assemble(const FineOp<T>& op, const AggMap& m, int N, const cx<T>* P, cx<T>* M, hipStream_t s);
 template <class T> void fine_export_vectors(const Geom& g, int n, const cx<T>* in, double* canon, hipStream_t s);
+// one parity p of the odd-even reduced operator:
+//   out_p = M (sc * P self_p + cc * D_pq in_q),  P = A_pp if pre_a else I,
+//   M = A_pp^{-1} if post_inv else I, D_pq the hopping term of D between the parities
+template <class T, class S>
+void fine_oe_hop(const FineOp<T, S>& op, int p, bool pre_a, bool post_inv, double sc, double cc, const cx<T>* self,
+                 const cx<T>* in, cx<T>* out, hipStream_t s);
 template <class T> void fine_import_vectors(const Geom& g, int n, const double* canon, cx<T>* out, hipStream_t s);
 // draw n complex N(0,1) fine spinors from the counter-based generator
 template <class T> void fine_random(const Geom& g, int n, unsigned long long seed, int stream_id, cx<T>* out, hipStream_t s);

@@ -234,6 +234,8 @@ struct dd_ctx {
             return false;
         }
     } stream;
+    void* bicg_ws = nullptr;     // odd-even BiCGStab vectors (levels arena; cleared with it)
+    int bicg_prec = 0;
     void* scratch = nullptr;     // device address of this GPU's `scratch` array (dd_apply_D_noalloc)
     std::string scratch_err;     // why it is unavailable, if it is
     int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
@@ -1245,6 +1247,167 @@ static void outer_fgmres(dd_ctx* C, Hier<T>& H, int nr, double tol, long fixed, 
 
 
 // ---------------------------------------------------------------------------
+// Comparison solver of Sec. 6 (Table 3): FGMRES(n_kv) in FP64 right-
+// preconditioned by a fixed number of BiCGStab steps (van der Vorst's
+// recurrence, zero start) on the odd-even reduced system
+//   S x_o = f_o,  S = A_oo - D_oe A_ee^{-1} D_eo,  f_o = b_o - D_oe A_ee^{-1} b_e,
+// followed by x_e = A_ee^{-1} (b_e - D_eo x_o), in precision T (FP32 in the
+// paper's mixed-precision form).  Vectors are fine spinors in the layout of
+// the context; the odd half of a vector is its second half.
+// ---------------------------------------------------------------------------
+template <class T>
+struct OeBicg {
+    dd_ctx* C;
+    FineOp<T> op;
+    long n, no;          // complex entries of a fine vector and of its odd half
+    cx<T>* r; cx<T>* rh; cx<T>* p; cx<T>* v; cx<T>* sv; cx<T>* t; cx<T>* tmp;
+    static OeBicg make(dd_ctx* C) {
+        OeBicg b;
+        b.C = C;
+        b.op = fine_op<T>(C);
+        b.n = 24L * C->g0.vh;
+        b.no = 12L * C->g0.vh;
+        const int prec = sizeof(T) == 8 ? 64 : 32;
+        if (!C->bicg_ws || C->bicg_prec != prec) {
+            C->bicg_ws = C->levels.alloc(sizeof(cx<T>) * 7 * (size_t)b.n);
+            C->bicg_prec = prec;
+        }
+        cx<T>* w = reinterpret_cast<cx<T>*>(C->bicg_ws);
+        cx<T>** slot[7] = {&b.r, &b.rh, &b.p, &b.v, &b.sv, &b.t, &b.tmp};
+        for (int k = 0; k < 7; k++) *slot[k] = w + (size_t)k * b.n;
+        return b;
+    }
+    cx<T>* odd(cx<T>* a) const { return a + no; }
+    // out_o = S x_o  (x, out full vectors; the even half of tmp is used)
+    void schur(const cx<T>* x, cx<T>* out) {
+        fine_oe_hop<T, T>(op, 0, false, true, 0.0, 1.0, x, x, tmp, C->s);     // tmp_e = A_ee^{-1} D_eo x_o
+        fine_oe_hop<T, T>(op, 1, true, false, 1.0, -1.0, x, tmp, out, C->s);  // out_o = A_oo x_o - D_oe tmp_e
+    }
+    cx<double> dot(const cx<T>* a, const cx<T>* b, int slot) {   // a_o^H b_o into dred[slot]
+        vec_multidot<T>(no, 1, a + no, 0, b + no, C->dred + slot, C->dwork, nullptr, C->s);
+        return cx<double>{0, 0};
+    }
+    cx<double> read(int slot) { return C->hred[slot]; }
+    // z = (odd-even BiCGStab with `steps` steps) applied to b; returns the steps taken
+    int apply(const cx<T>* b, cx<T>* z, int steps) {
+        const size_t hb = sizeof(cx<T>) * no;
+        // f_o = b_o - D_oe A_ee^{-1} b_e
+        fine_oe_hop<T, T>(op, 0, false, true, 1.0, 0.0, b, b, tmp, C->s);       // tmp_e = A_ee^{-1} b_e
+        fine_oe_hop<T, T>(op, 1, false, false, 1.0, -1.0, b, tmp, r, C->s);     // r_o = b_o - D_oe tmp_e
+        HIPX(hipMemcpyAsync(odd(rh), odd(r), hb, hipMemcpyDeviceToDevice, C->s));
+        HIPX(hipMemsetAsync(odd(z), 0, hb, C->s));
+        HIPX(hipMemsetAsync(odd(p), 0, hb, C->s));
+        HIPX(hipMemsetAsync(odd(v), 0, hb, C->s));
+        zc rho_old(1, 0), alpha(1, 0), omega(1, 0);
+        int it = 0;
+        for (; it < steps; it++) {
+            dot(rh, r, 0);
+            read_red(C, 1, 1);
+            const zc rho(C->hred[0].re, C->hred[0].im);
+            if (std::abs(rho) == 0.0) break;
+            const zc beta = (rho / rho_old) * (alpha / omega);
+            // p = r + beta (p - omega v)
+            vec_axpy<T>(no, cx<double>{-omega.real(), -omega.imag()}, odd(v), odd(p), C->s);
+            vec_xpay<T>(no, odd(r), cx<double>{beta.real(), beta.imag()}, odd(p), C->s);
+            schur(p, v);
+            dot(rh, v, 0);
+            read_red(C, 1, 1);
+            const zc rv(C->hred[0].re, C->hred[0].im);
+            if (std::abs(rv) == 0.0) break;
+            alpha = rho / rv;
+            // s = r - alpha v
+            HIPX(hipMemcpyAsync(odd(sv), odd(r), hb, hipMemcpyDeviceToDevice, C->s));
+            vec_axpy<T>(no, cx<double>{-alpha.real(), -alpha.imag()}, odd(v), odd(sv), C->s);
+            schur(sv, t);
+            dot(t, sv, 0);
+            dot(t, t, 1);
+            read_red(C, 1, 2);
+            const zc ts(C->hred[0].re, C->hred[0].im);
+            const double tt = C->hred[1].re;
+            // x += alpha p (+ omega s)
+            vec_axpy<T>(no, cx<double>{alpha.real(), alpha.imag()}, odd(p), odd(z), C->s);
+            if (tt == 0.0) { it++; break; }   // s = 0: x is exact
+            omega = ts / tt;
+            vec_axpy<T>(no, cx<double>{omega.real(), omega.imag()}, odd(sv), odd(z), C->s);
+            // r = s - omega t
+            HIPX(hipMemcpyAsync(odd(r), odd(sv), hb, hipMemcpyDeviceToDevice, C->s));
+            vec_axpy<T>(no, cx<double>{-omega.real(), -omega.imag()}, odd(t), odd(r), C->s);
+            rho_old = rho;
+        }
+        // z_e = A_ee^{-1} (b_e - D_eo z_o)
+        fine_oe_hop<T, T>(op, 0, false, true, 1.0, -1.0, b, z, z, C->s);
+        return it;
+    }
+};
+
+template <class T>
+struct BicgOps {
+    dd_ctx* C;
+    OeBicg<T>* B;
+    const cx<double>* b;
+    cx<double>* x;
+    long n;
+    int steps;
+    cx<T>* Zb;
+    cx<double>* V() { return C->oV; }
+    cx<T>* Z() { return Zb; }
+    cx<T>* vT() { return reinterpret_cast<cx<T>*>(C->ot); }
+    cx<double>* t64() { return C->ot + (size_t)C->R * n; }
+    void precond(const cx<double>* v, cx<T>* z, const Batch& bt) {
+        bvec_convert<T, double>(n, v, vT(), n, bt.nr, bt.mask(), C->s);
+        B->apply(vT(), z, steps);
+    }
+    void matvec(const cx<T>* z, cx<double>* w, const Batch& bt) {
+        bvec_convert<double, T>(n, z, t64(), n, bt.nr, bt.mask(), C->s);
+        Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
+        fine_dirac<double>(fine_op<double>(C), t64(), w, C->s, bt.nr, n, bt.mask());
+    }
+    void update(int m, const cx<T>* Z, long ldz, const cx<double>* y, const Batch& bt, const Counts& jc) {
+        vec_lincomb<T, double>(n, m, Z, ldz, y, x, C->s, bt.nr, n, 32, n, bt.mask(), &jc);
+    }
+    void residual(const Batch& bt) {
+        fine_dirac<double>(fine_op<double>(C), x, t64(), C->s, bt.nr, n, bt.mask());
+        bvec_sub<double>(n, b, t64(), C->oV, n, bt.nr, bt.mask(), C->s);
+    }
+    std::vector<double> norms(const cx<double>* v, const Batch& bt) { return OuterOps<T>::norms64(C, n, v, bt); }
+};
+
+template <class T>
+static dd_status bicg_solve_impl(dd_ctx* C, const double* bin, double* xout, double tol, int steps, dd_stats* st) {
+    const dd_params& p = C->p;
+    const int m = p.outer_restart;
+    const long n = 24L * C->g0.vh;
+    const long ldv = (long)C->R * n;
+    const double t0 = now_s();
+    OeBicg<T> B = OeBicg<T>::make(C);
+    fine_import_vectors<double>(C->g0, 1, bin, C->ob, C->s);
+    HIPX(hipMemsetAsync(C->ox, 0, sizeof(cx<double>) * n, C->s));
+    clear_flag(C, DI_BAD);
+    vec_finite_check<double>(n, C->ob, C->dflags + DI_BAD, C->s);
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "NaN/Inf in the right-hand side");
+    Batch one{1, C->dflags + DI_ONES, 1u};
+    std::vector<double> bn = OuterOps<T>::norms64(C, n, C->ob, one);
+    HIPX(hipMemcpyAsync(C->oV, C->ob, sizeof(cx<double>) * n, hipMemcpyDeviceToDevice, C->s));
+    BicgOps<T> ops{C, &B, C->ob, C->ox, n, steps, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
+    KrylovResult res;
+    fgmres_batch<double, T>(C, ops, n, ldv, m, tol, p.outer_maxit, 0, one, 0, bn, res);
+    fine_export_vectors<double>(C->g0, 1, C->ox, xout, C->s);
+    HIPX(hipGetLastError());
+    sync(C);
+    if (st) {
+        memset(st, 0, sizeof *st);
+        st->outer_iters = (int)res.its[0];
+        st->restarts = res.restarts[0];
+        st->coarse_iters[0] = (long)res.its[0] * steps;   // BiCGStab steps (each two S applies)
+        st->true_relres = res.relres[0];
+        st->converged = res.conv[0] ? 1 : 0;
+        st->solve_s = now_s() - t0;
+    }
+    return res.conv[0] ? DD_OK : DD_ENOCONV;
+}
+
+
+// ---------------------------------------------------------------------------
 // Fixed staging memory of the allocation-free stencil entry point
 // (dd_apply_D_noalloc): the two internal-layout FP64 spinors that dd_apply
 // allocates per call live here instead.  Every GPU the library runs on holds
@@ -1394,6 +1557,8 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
     C->configured = false;
     C->have_setup = false;
     C->stream = dd_ctx::StreamSlots{};
+    C->bicg_ws = nullptr;
+    C->bicg_prec = 0;
     C->p = p;
     // re-layout the fine fields if the SAP blocks differ from the current layout
     bool same = true;
@@ -1524,6 +1689,21 @@ dd_status dd_solve_batch(dd_ctx* ctx, int k, const double* b, double* x, double 
     if (!(tol > 0)) fail(DD_EINVAL, "tol must be positive");
     dd_status rc = ctx->H64 ? solve_impl(ctx, *ctx->H64, k, b, x, tol, st) : solve_impl(ctx, *ctx->H32, k, b, x, tol, st);
     if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit for at least one right-hand side";
+    return rc;
+    ABI_END(ctx)
+}
+
+dd_status dd_solve_bicgstab(dd_ctx* ctx, const double* b, double* x, double tol, int steps, int precision,
+                            dd_stats* st) {
+    ABI_TRY(ctx)
+    if (!ctx->configured) fail(DD_ESTATE, "dd_solve_bicgstab needs dd_configure (outer workspace)");
+    if (ctx->stream.any()) fail(DD_ESTATE, "dd_solve_bicgstab while continuous-batching slots are in use");
+    if (!b || !x) fail(DD_EINVAL, "NULL vector");
+    if (!(tol > 0) || steps < 1) fail(DD_EINVAL, "tol must be positive and steps >= 1");
+    if (precision != 32 && precision != 64) fail(DD_EINVAL, "precision must be 32 or 64");
+    dd_status rc = (precision == 64) ? bicg_solve_impl<double>(ctx, b, x, tol, steps, st)
+                                     : bicg_solve_impl<float>(ctx, b, x, tol, steps, st);
+    if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit";
     return rc;
     ABI_END(ctx)
 }
@@ -1985,6 +2165,15 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
                 HIPX(hipMemsetAsync(H.wb[l] + (size_t)r * H.nlv(l), 0, sizeof(cx<T>) * (size_t)H.g[l].vh * H.nd[l], C->s));
             exp_(l, H.wb[l], out);
             break;
+        case DD_OP_BICGSTAB: {
+            if (l != 0 || k != 1) fail(DD_EINVAL, "odd-even BiCGStab acts on one fine vector (level 0)");
+            if (arg < 1) fail(DD_EINVAL, "BiCGStab needs arg >= 1 steps");
+            OeBicg<T> B = OeBicg<T>::make(C);
+            imp(0, in, H.wa[0]);
+            its[0] = B.apply(H.wa[0], H.wb[0], arg);
+            exp_(0, H.wb[0], out);
+            break;
+        }
         case DD_OP_FGMRES:
             if (l < 1 || l >= bottom) fail(DD_EINVAL, "middle-level FGMRES needs 1 <= level < levels-1");
             imp(l, in, H.rc[l]);
