@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES) k_coarse_apply(CoarseOp<T, S> o
     if (hop_sign != 0 && threadIdx.x < 8) {
         int x[4];
         cb_coords(g, p, i, x);
-        vin[nself + threadIdx.x] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, threadIdx.x)) * nd;
+        vin[nself + threadIdx.x] = in2 + nb_global(g, p, x, threadIdx.x) * nd;
     }
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
     const int Q = ns * nd;
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
         int x[4];
         cb_coords(g, p, i, x);
         mat[nself + t] = op.M + (gs * 9 + 1 + t) * nn;
-        vin[nself + t] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, t)) * nd;
+        vin[nself + t] = in2 + nb_global(g, p, x, t) * nd;
     }
     __syncthreads();
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_coarse_rows(CoarseOp<T, S> op, int par,
     if (hop_sign != 0 && threadIdx.x < 8) {
         int x[4];
         cb_coords(g, p, i, x);
-        vin[nself + threadIdx.x] = in2 + ((size_t)(1 - p) * g.vh + nb_index_sel(g, x, threadIdx.x)) * nd;
+        vin[nself + threadIdx.x] = in2 + nb_global(g, p, x, threadIdx.x) * nd;
     }
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
     const int Q = ns * nd;
@@ -930,7 +930,7 @@ __global__ void k_coarse_import(Geom g, int nd, int n, const double* __restrict_
     int c = (int)(e % nd);
     int x[4];
     canon_coords(g.d, s, x);
-    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    size_t gs = lay_global(g, x);
     const cx<double>* src = reinterpret_cast<const cx<double>*>(canon);
     for (int v = 0; v < n; v++) out[(size_t)v * vol * nd + gs * nd + c] = ccast<T>(src[(size_t)v * vol * nd + s * nd + c]);
 }
@@ -944,7 +944,7 @@ __global__ void k_coarse_export(Geom g, int nd, int n, const cx<T>* __restrict__
     int c = (int)(e % nd);
     int x[4];
     canon_coords(g.d, s, x);
-    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    size_t gs = lay_global(g, x);
     cx<double>* dst = reinterpret_cast<cx<double>*>(canon);
     for (int v = 0; v < n; v++) dst[(size_t)v * vol * nd + s * nd + c] = ccast<double>(in[(size_t)v * vol * nd + gs * nd + c]);
 }
@@ -963,7 +963,7 @@ __global__ void k_coarse_export_blocks(Geom g, int nd, int nslot, const cx<T>* _
     int r = q / nd, c = q % nd;
     int x[4];
     canon_coords(g.d, s, x);
-    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    size_t gs = lay_global(g, x);
     cx<double>* dst = reinterpret_cast<cx<double>*>(canon);
     dst[e] = ccast<double>(in[(gs * nslot + slot) * nn + (size_t)c * nd + r]);
 }
@@ -1137,6 +1137,169 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap1(CoarseOp<T, S> op, const 
         z[ge * nd + r] += ee;
         z[go * nd + r] += eo;
     }
+}
+
+// Coarse SAP half sweep on SAP blocks that are not the level's layout blocks
+// (any extents with two colours, e.g. 2 x 3^3 on a 12 x 6^3 level): the block's
+// sites come from tables (SapTab).  One workgroup per (block, RHS); thread
+// (site l, row group rr) holds NR rows rr + q nd/NR of the even site l and the
+// odd site l of the block (NR = 2 when bv * nd exceeds a workgroup).  Same
+// algebra and summation order as k_coarse_sap1.
+template <class T, class S, int NTMAX, int NR>
+__global__ void __launch_bounds__(NTMAX) k_coarse_sap_t(CoarseOp<T, S> op, const int* __restrict__ blocks, SapTab tab,
+                                                        const cx<T>* __restrict__ b, cx<T>* __restrict__ z,
+                                                        int mr_steps, long ld, Mask mk) {
+    if (!mk.on(blockIdx.y)) return;
+    b += blockIdx.y * ld;
+    z += blockIdx.y * ld;
+    extern __shared__ char smem_raw[];
+    const Geom g = op.g;
+    const int nd = op.nd, bv = tab.bv, ndr = nd / NR;
+    const size_t nn = (size_t)nd * nd;
+    constexpr int RB = 8;
+    cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // [bv][nd] odd-site field
+    cx<T>* se = so + bv * nd;                         // even-site field
+    cx<T>* tm = se + bv * nd;                         // temporary (even)
+    double* red = reinterpret_cast<double*>(tm + bv * nd);
+    const int blk = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    const bool act = t < bv * ndr;
+    const int l = act ? t / ndr : 0, rr = act ? t % ndr : 0;
+    const int ie = tab.sites[((size_t)blk * 2 + 0) * bv + l];
+    const int io = tab.sites[((size_t)blk * 2 + 1) * bv + l];
+    int xe[4], xo[4], nbe[8], nbo[8], lce[8], lco[8];
+    cb_coords(g, 0, ie, xe);
+    cb_coords(g, 1, io, xo);
+    for (int k = 0; k < 8; k++) {
+        int y[4];
+        nb_coords(g, xe, k, y);
+        nbe[k] = cb_index(g, y);
+        size_t gy = (size_t)g.vh + nbe[k];
+        lce[k] = (tab.of[gy] == blk) ? tab.loc[gy] : -1;
+        nb_coords(g, xo, k, y);
+        nbo[k] = cb_index(g, y);
+        gy = (size_t)nbo[k];
+        lco[k] = (tab.of[gy] == blk) ? tab.loc[gy] : -1;
+    }
+    const size_t ge = ie, go = (size_t)g.vh + io;
+    auto hop_glob = [&](size_t gs, int p, const int* nbj, const cx<T>* v, int r) {
+        cx<T> h = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            size_t gy = (size_t)(1 - p) * g.vh + nbj[k];
+            h += row_apply<T, S, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, v + gy * nd);
+        }
+        return h;
+    };
+    auto hop_int = [&](size_t gs, const int* lcj, const cx<T>* buf, int r) {
+        cx<T> h = czero<T>();
+        for (int k = 0; k < 8; k++) {
+            if (lcj[k] < 0) continue;
+            h += row_apply<T, S, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + lcj[k] * nd);
+        }
+        return h;
+    };
+    cx<T> t0[NR], rho[NR], eo[NR], sv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) t0[q] = rho[q] = eo[q] = sv[q] = czero<T>();
+    // t0_e = Minv (b_e - H z) - z_e
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            const int r = rr + q * ndr;
+            tm[l * nd + r] = b[ge * nd + r] - hop_glob(ge, 0, nbe, z, r);
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            const int r = rr + q * ndr;
+            t0[q] = row_apply<T, S, RB>(op.Minv + ge * nn, nd, r, tm + l * nd) - z[ge * nd + r];
+            se[l * nd + r] = t0[q];
+            so[l * nd + r] = z[go * nd + r];
+        }
+    __syncthreads();
+    // f_o = b_o - M0 z_o - H z - H_int t0
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            const int r = rr + q * ndr;
+            rho[q] = b[go * nd + r] - row_apply<T, S, RB>(op.M + go * 9 * nn, nd, r, so + l * nd) -
+                     hop_glob(go, 1, nbo, z, r) - hop_int(go, lco, se, r);
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) so[l * nd + rr + q * ndr] = rho[q];
+    __syncthreads();
+    const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int it = 0; it < mr_steps; it++) {
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) {
+                const int r = rr + q * ndr;
+                tm[l * nd + r] = hop_int(ge, lce, so, r);
+            }
+        __syncthreads();
+        cx<T> tv[NR];
+#pragma unroll
+        for (int q = 0; q < NR; q++) tv[q] = czero<T>();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) tv[q] = row_apply<T, S, RB>(op.Minv + ge * nn, nd, rr + q * ndr, tm + l * nd);
+        __syncthreads();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) se[l * nd + rr + q * ndr] = tv[q];
+        __syncthreads();
+        double sr = 0, si = 0, ss = 0;
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) {
+                const int r = rr + q * ndr;
+                sv[q] = row_apply<T, S, RB>(op.M + go * 9 * nn, nd, r, so + l * nd) - hop_int(go, lco, se, r);
+                cx<T> d = cmulc(sv[q], rho[q]);
+                sr += d.re; si += d.im; ss += norm2(sv[q]);
+            }
+        sr = wave_sum(sr); si = wave_sum(si); ss = wave_sum(ss);
+        if (lane == 0) { red[3 * w] = sr; red[3 * w + 1] = si; red[3 * w + 2] = ss; }
+        __syncthreads();
+        sr = si = ss = 0;
+        for (int v = 0; v < nw; v++) { sr += red[3 * v]; si += red[3 * v + 1]; ss += red[3 * v + 2]; }
+        if (ss > 0 && act) {
+            cx<T> alpha = {T(sr / ss), T(si / ss)};
+#pragma unroll
+            for (int q = 0; q < NR; q++) {
+                eo[q] += alpha * rho[q];
+                rho[q] -= alpha * sv[q];
+            }
+        }
+        __syncthreads();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) so[l * nd + rr + q * ndr] = (it + 1 < mr_steps) ? rho[q] : eo[q];
+        __syncthreads();
+    }
+    if (mr_steps == 0) {
+        if (act)
+#pragma unroll
+            for (int q = 0; q < NR; q++) so[l * nd + rr + q * ndr] = eo[q];
+        __syncthreads();
+    }
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            const int r = rr + q * ndr;
+            tm[l * nd + r] = hop_int(ge, lce, so, r);
+        }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            const int r = rr + q * ndr;
+            cx<T> ee = t0[q] - row_apply<T, S, RB>(op.Minv + ge * nn, nd, r, tm + l * nd);
+            z[ge * nd + r] += ee;
+            z[go * nd + r] += eo[q];
+        }
 }
 
 // KR right-hand sides at once: every block entry loaded is applied to the KR
@@ -1369,8 +1532,18 @@ static void coarse_sap_launch(const CoarseOp<T, S>& op, const int* blocks, int n
 // one-RHS kernel.  Both compute the same sums in the same order.
 template <class T, class S>
 void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                     hipStream_t s, int nr, long ld, Mask mk) {
+                     hipStream_t s, int nr, long ld, Mask mk, SapTab tab) {
     if (nblocks <= 0) return;
+    if (tab.bv > 0) {
+        // SAP blocks from tables: one workgroup per (block, RHS)
+        const int NR = (tab.bv * op.nd > 1024) ? 2 : 1;
+        const int nt = ((tab.bv * op.nd / NR + 63) / 64) * 64;
+        const size_t lds = 3 * sizeof(cx<T>) * tab.bv * op.nd + 3 * sizeof(double) * (nt / 64);
+        dim3 grid(nblocks, nr);
+        if (NR == 1) k_coarse_sap_t<T, S, 1024, 1><<<grid, nt, lds, s>>>(op, blocks, tab, b, z, mr_steps, ld, mk);
+        else k_coarse_sap_t<T, S, 1024, 2><<<grid, nt, lds, s>>>(op, blocks, tab, b, z, mr_steps, ld, mk);
+        return;
+    }
     // LDS of a group: three block fields per member (kept within the 64 KB
     // a workgroup gets without an opt-in)
     const int nw = (op.g.bvh * op.nd + 63) / 64;
@@ -1418,7 +1591,7 @@ __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<S>* __restr
             int s = e / ndf, d = e % ndf;
             int x[4];
             agg_site_c(m, xc, s, x);
-            size_t gf = (size_t)site_parity(x) * m.f.vh + cb_index(m.f, x);
+            size_t gf = lay_global(m.f, x);
             acc[d / h0] += ccast<double>(cmulc(ccast<T>(P[((size_t)k * volf + gf) * ndf + d]), in[gf * ndf + d]));
         }
         for (int h = 0; h < 2; h++) {
@@ -1449,7 +1622,7 @@ __global__ void k_coarse_prolong(AggMap m, int ndf, int N, const cx<S>* __restri
     int x[4], xc[4];
     cb_coords(m.f, p, i, x);
     for (int mu = 0; mu < 4; mu++) xc[mu] = x[mu] / m.a[mu];
-    size_t gc = (size_t)site_parity(xc) * m.c.vh + cb_index(m.c, xc);
+    size_t gc = lay_global(m.c, xc);
     const int h = d / (ndf / 2);
     cx<T> s = czero<T>();
     for (int k = 0; k < N; k++) s += ccast<T>(P[((size_t)k * volf + gf) * ndf + d]) * in[gc * 2 * N + h * N + k];
@@ -1490,7 +1663,7 @@ __global__ void k_coarse_gs(AggMap m, int ndf, int N, const cx<T>* __restrict__ 
         int s = t / h0, d = h * h0 + t % h0;
         int x[4];
         agg_site_c(m, xc, s, x);
-        size_t gf = (size_t)site_parity(x) * m.f.vh + cb_index(m.f, x);
+        size_t gf = lay_global(m.f, x);
         off = gf * ndf + d;
     }
     for (int k = 0; k < N; k++) {
@@ -1621,7 +1794,7 @@ __global__ void k_coarse_random(Geom g, int nd, int n, unsigned long long seed, 
     int c = (int)(e % nd);
     int x[4];
     canon_coords(g.d, s, x);
-    size_t gs = (size_t)site_parity(x) * g.vh + cb_index(g, x);
+    size_t gs = lay_global(g, x);
     for (int v = 0; v < n; v++) {
         unsigned long long el = (unsigned long long)e;
         uint32_t ctr[4] = {(uint32_t)el, (uint32_t)(el >> 32), (uint32_t)v, (uint32_t)sid};
@@ -1650,7 +1823,7 @@ void coarse_random(const Geom& g, int nd, int n, unsigned long long seed, int si
     template void coarse_apply_folded<T, S>(const CoarseOp<T, S>&, const cx<T>*, int, const cx<T>*, cx<T>*,           \
                                             hipStream_t, Mask, int, long, InScale);                                 \
     template void coarse_sap_half<T, S>(const CoarseOp<T, S>&, const int*, int, const cx<T>*, cx<T>*, int, hipStream_t, \
-                                        int, long, Mask);                                                           \
+                                        int, long, Mask, SapTab);                                                   \
     template void coarse_restrict<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int, \
                                         long, long, Mask);                                                          \
     template void coarse_prolong<T, S>(const AggMap&, int, int, const cx<S>*, const cx<T>*, cx<T>*, hipStream_t, int,  \

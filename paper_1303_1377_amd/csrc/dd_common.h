@@ -63,6 +63,9 @@ template <class T> __host__ __device__ __forceinline__ void cmacc(cx<T>& acc, cx
 // coordinates, so a site's parity equals the parity of its local coordinates.
 // ---------------------------------------------------------------------------
 struct Geom {
+    int lex;      // 1: lexicographic layout (a coarsest lattice with an odd extent:
+                  //    no parity structure); halves [0, vh) and [vh, 2 vh) of the
+                  //    canonical order stand in for the two parities
     int d[4];     // lattice extents
     int b[4];     // layout block extents (powers of two, >= 2 for the fine level)
     int lb[4];    // log2 b
@@ -79,8 +82,15 @@ __host__ __device__ __forceinline__ int ilog2(int v) {
     return r;
 }
 
+__host__ __device__ __forceinline__ long canon_index(const int d[4], const int x[4]);
+__host__ __device__ __forceinline__ void canon_coords(const int d[4], long i, int x[4]);
+
 // coordinates of the site with parity p and layout index i
 __host__ __device__ __forceinline__ void cb_coords(const Geom& g, int p, int i, int x[4]) {
+    if (g.lex) {
+        canon_coords(g.d, (long)p * g.vh + i, x);
+        return;
+    }
     int blk = i >> g.lbvh;
     int loc = i & (g.bvh - 1);
     int bc3 = blk % g.nb[3]; blk /= g.nb[3];
@@ -100,8 +110,13 @@ __host__ __device__ __forceinline__ void cb_coords(const Geom& g, int p, int i, 
     x[3] = (bc3 << g.lb[3]) + 2 * l3h + q;
 }
 
-// layout index of coordinates x (parity implied by the coordinates)
+// layout index of coordinates x (parity implied by the coordinates; in the
+// lexicographic layout the index within the half that holds x)
 __host__ __device__ __forceinline__ int cb_index(const Geom& g, const int x[4]) {
+    if (g.lex) {
+        const long c = canon_index(g.d, x);
+        return (int)(c >= g.vh ? c - g.vh : c);
+    }
     int blk = (((x[0] >> g.lb[0]) * g.nb[1] + (x[1] >> g.lb[1])) * g.nb[2] + (x[2] >> g.lb[2])) * g.nb[3] + (x[3] >> g.lb[3]);
     int loc = ((((x[0] & (g.b[0] - 1)) << g.lb[1] | (x[1] & (g.b[1] - 1))) << g.lb[2] | (x[2] & (g.b[2] - 1))) << g.lb[3] |
                (x[3] & (g.b[3] - 1))) >> 1;
@@ -109,6 +124,16 @@ __host__ __device__ __forceinline__ int cb_index(const Geom& g, const int x[4]) 
 }
 
 __host__ __device__ __forceinline__ int site_parity(const int x[4]) { return (x[0] + x[1] + x[2] + x[3]) & 1; }
+
+// the half of the layout that holds x: its parity, or in the lexicographic
+// layout the half of the canonical order
+__host__ __device__ __forceinline__ int lay_parity(const Geom& g, const int x[4]) {
+    return g.lex ? (canon_index(g.d, x) >= g.vh ? 1 : 0) : site_parity(x);
+}
+// index of x in the whole layout (both halves)
+__host__ __device__ __forceinline__ size_t lay_global(const Geom& g, const int x[4]) {
+    return (size_t)lay_parity(g, x) * g.vh + cb_index(g, x);
+}
 
 __host__ __device__ __forceinline__ long canon_index(const int d[4], const int x[4]) {
     return (((long)x[0] * d[1] + x[1]) * d[2] + x[2]) * d[3] + x[3];
@@ -142,6 +167,17 @@ __device__ __forceinline__ int nb_index_sel(const Geom& g, const int x[4], int k
         y[nu] = (nu == mu) ? stepped : c;
     }
     return cb_index(g, y);
+}
+
+// whole-layout index of neighbour k of x, where x lies in half p (the other
+// parity in the parity layout; looked up in the lexicographic one)
+__device__ __forceinline__ size_t nb_global(const Geom& g, int p, const int x[4], int k) {
+    if (g.lex) {
+        int y[4];
+        nb_coords(g, x, k, y);
+        return (size_t)canon_index(g.d, y);
+    }
+    return (size_t)(1 - p) * g.vh + nb_index_sel(g, x, k);
 }
 
 // ---------------------------------------------------------------------------

@@ -1197,7 +1197,7 @@ __global__ void k_prolong_fine(AggMap m, int N, const cx<S>* __restrict__ P, con
     int x[4], xc[4];
     cb_coords(m.f, p, i, x);
     coarse_of(m, x, xc);
-    int pc = site_parity(xc), ic = cb_index(m.c, xc);
+    int pc = lay_parity(m.c, xc), ic = cb_index(m.c, xc);
     const cx<T>* e = in + ((size_t)pc * m.c.vh + ic) * 2 * N;
     cx<T> acc[12];
 #pragma unroll
@@ -1311,7 +1311,7 @@ __global__ void __launch_bounds__(256) k_prolong_fine_k(AggMap m, int N, const c
     int x[4], xc[4];
     cb_coords(m.f, p, i, x);
     coarse_of(m, x, xc);
-    int pc = site_parity(xc), ic = cb_index(m.c, xc);
+    int pc = lay_parity(m.c, xc), ic = cb_index(m.c, xc);
     const size_t eo = ((size_t)pc * m.c.vh + ic) * 2 * N;
     cx<T> acc[KR][12];
 #pragma unroll

@@ -73,6 +73,18 @@ struct Counts {
 };
 
 // aggregation of a fine (or finer coarse) level onto the next coarser level
+// SAP blocks of a coarse level that are not its layout blocks (bv > 0): for
+// block B the layout indices of its even sites at sites[(2 B) bv ..] and of its
+// odd sites at sites[(2 B + 1) bv ..] (bv of each); for every site (whole-layout
+// index) its block in `of` and its position in its block's list in `loc`.
+// bv = 0: the SAP blocks are the layout blocks.
+struct SapTab {
+    const int* sites = nullptr;
+    const int* of = nullptr;
+    const int* loc = nullptr;
+    int bv = 0;
+};
+
 struct AggMap {
     Geom f;        // finer level layout
     Geom c;        // coarser level layout
@@ -172,7 +184,7 @@ template <class T> void coarse_export_blocks(const Geom& g, int nd, int nslot, c
 template <class T> void coarse_shift_diag(const Geom& g, int nd, double dm, cx<T>* M, hipStream_t s);
 template <class T, class S>
 void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                     hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs());
+                     hipStream_t s, int nr = 1, long ld = 0, Mask mk = all_rhs(), SapTab tab = SapTab{});
 template <class T, class S>
 void coarse_restrict(const AggMap& m, int ndf, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s,
                      int nr = 1, long ldi = 0, long ldo = 0, Mask mk = all_rhs());

@@ -82,6 +82,7 @@ static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 static Geom make_geom(const int d[4], const int b[4]) {
     Geom g;
+    g.lex = 0;
     long vol = 1, bvol = 1;
     for (int mu = 0; mu < 4; mu++) {
         g.d[mu] = d[mu];
@@ -96,6 +97,37 @@ static Geom make_geom(const int d[4], const int b[4]) {
     g.vh = (int)(vol / 2);
     g.nblk = g.nb[0] * g.nb[1] * g.nb[2] * g.nb[3];
     return g;
+}
+
+// lexicographic layout of a coarsest lattice with an odd extent (no parity
+// structure; the two halves of the canonical order stand in for the parities)
+static Geom make_geom_lex(const int d[4]) {
+    Geom g;
+    g.lex = 1;
+    long vol = 1;
+    for (int mu = 0; mu < 4; mu++) {
+        g.d[mu] = d[mu];
+        g.b[mu] = d[mu];
+        g.lb[mu] = ilog2(d[mu]);
+        g.nb[mu] = 1;
+        vol *= d[mu];
+    }
+    g.vh = (int)(vol / 2);
+    g.bvh = g.vh;
+    g.lbvh = ilog2(g.vh);
+    g.nblk = 1;
+    return g;
+}
+
+// SAP block validity: extents dividing the lattice with an even block count
+// (or one block) per dimension, so that two colours suffice (Sec. 2.3)
+static bool valid_sap_blocks(const int d[4], const int b[4]) {
+    for (int mu = 0; mu < 4; mu++) {
+        if (b[mu] < 1 || d[mu] % b[mu]) return false;
+        int n = d[mu] / b[mu];
+        if (n != 1 && (n & 1)) return false;
+    }
+    return true;
 }
 
 // layout block validity: powers of two >= 2 dividing the extents; blocks
@@ -389,6 +421,9 @@ struct Hier {
     void fold(int l);
     int* blocks[DD_MAXLEV][2];
     int nblocks[DD_MAXLEV][2];
+    SapTab stab[DD_MAXLEV];        // SAP blocks that are not layout blocks (bv = 0: they are)
+    bool lexl[DD_MAXLEV];          // coarsest level in the lexicographic layout (odd extent):
+                                   // plain GMRES on D_c instead of the odd-even form
     AggMap amap[DD_MAXLEV];
     int N[DD_MAXLEV];
     cx<T>* tv[DD_MAXLEV];
@@ -452,7 +487,11 @@ struct Hier {
         memset(Ph, 0, sizeof Ph);
         memset(Mh, 0, sizeof Mh);
         memset(Minvh, 0, sizeof Minvh);
-        for (int l = 0; l < DD_MAXLEV; l++) last_its[l] = 8;
+        memset(lexl, 0, sizeof lexl);
+        for (int l = 0; l < DD_MAXLEV; l++) {
+            last_its[l] = 8;
+            stab[l] = SapTab{};
+        }
     }
 
     void build_geometry();
@@ -573,18 +612,35 @@ void Hier<T>::build_geometry() {
     int d[4];
     memcpy(d, C->dims, sizeof d);
     for (int l = 0; l < nlev; l++) {
+        bool sap_tables = false;
         if (l > 0) {
             int b[4];
             bool has_sap = (l < nlev - 1);
-            for (int mu = 0; mu < 4; mu++) b[mu] = has_sap ? p.sap[l][mu] : 2;
-            if (!valid_layout(d, b, has_sap))
-                fail(DD_EINVAL, "level " + std::to_string(l) + ": lattice/blocks not supported (coarse extents must be even, "
-                                "SAP blocks powers of two with an even block count per dimension)");
-            g[l] = make_geom(d, b);
+            bool all_even = true;
+            for (int mu = 0; mu < 4; mu++) all_even = all_even && !(d[mu] & 1);
+            if (!has_sap && !all_even) {
+                // coarsest lattice with an odd extent: lexicographic layout, plain GMRES
+                if (((long)d[0] * d[1] * d[2] * d[3]) & 1)
+                    fail(DD_EINVAL, "level " + std::to_string(l) + ": the coarsest lattice needs an even volume");
+                g[l] = make_geom_lex(d);
+                lexl[l] = true;
+            } else {
+                for (int mu = 0; mu < 4; mu++) b[mu] = has_sap ? p.sap[l][mu] : 2;
+                if (has_sap && !valid_layout(d, b, true) && valid_sap_blocks(d, b) && all_even) {
+                    // SAP blocks that are no layout blocks (e.g. 2 x 3^3): layout blocks 2^4, SAP from tables
+                    for (int mu = 0; mu < 4; mu++) b[mu] = 2;
+                    sap_tables = true;
+                }
+                if (!valid_layout(d, b, has_sap && !sap_tables))
+                    fail(DD_EINVAL, "level " + std::to_string(l) + ": lattice/blocks not supported (SAP blocks must divide "
+                                    "the lattice with an even block count per dimension, and a level with SAP needs "
+                                    "even extents)");
+                g[l] = make_geom(d, b);
+            }
             nd[l] = 2 * p.n_tv[l - 1];
             M[l] = A.get<cx<T>>((size_t)2 * g[l].vh * 9 * nd[l] * nd[l]);
             Minv[l] = A.get<cx<T>>((size_t)2 * g[l].vh * nd[l] * nd[l]);
-            const bool coarsest = (l == nlev - 1) && nd[l] <= 64;
+            const bool coarsest = (l == nlev - 1) && nd[l] <= 64 && !lexl[l];
             if (coarsest) B[l] = A.get<cx<T>>((size_t)g[l].vh * 8 * nd[l] * nd[l]);
             cop[l] = CoarseOp<T>{g[l], nd[l], M[l], Minv[l], (C->sched & SCHED_NO_MFMA) ? 0 : 1, B[l]};
             if (half) {
@@ -603,11 +659,58 @@ void Hier<T>::build_geometry() {
             // SAP block lists by colour (red = even sum of block coordinates)
             std::vector<int> lists[2];
             const Geom& G = g[l];
-            for (int bi = 0; bi < G.nblk; bi++) {
-                int r = bi, bc3 = r % G.nb[3]; r /= G.nb[3];
-                int bc2 = r % G.nb[2]; r /= G.nb[2];
-                int bc1 = r % G.nb[1], bc0 = r / G.nb[1];
-                lists[(bc0 + bc1 + bc2 + bc3) & 1].push_back(bi);
+            if (sap_tables) {
+                // blocks p.sap[l]: per block the layout indices of its even and odd
+                // sites (canonical order), per site its block and position
+                const int* sb = p.sap[l];
+                int nbk[4];
+                for (int mu = 0; mu < 4; mu++) nbk[mu] = d[mu] / sb[mu];
+                const int nsb = nbk[0] * nbk[1] * nbk[2] * nbk[3];
+                std::vector<std::vector<int>> sl(2 * (size_t)nsb);
+                const long vol = 2L * G.vh;
+                std::vector<int> of(vol), loc(vol);
+                for (long c = 0; c < vol; c++) {
+                    int x[4];
+                    canon_coords(d, c, x);
+                    int bc[4];
+                    for (int mu = 0; mu < 4; mu++) bc[mu] = x[mu] / sb[mu];
+                    const int B = ((bc[0] * nbk[1] + bc[1]) * nbk[2] + bc[2]) * nbk[3] + bc[3];
+                    const int par = site_parity(x);
+                    const int i = cb_index(G, x);
+                    loc[(size_t)par * G.vh + i] = (int)sl[2 * (size_t)B + par].size();
+                    of[(size_t)par * G.vh + i] = B;
+                    sl[2 * (size_t)B + par].push_back(i);
+                }
+                const int bv = (int)sl[0].size();
+                for (auto& v : sl)
+                    if ((int)v.size() != bv)
+                        fail(DD_EINVAL, "level " + std::to_string(l) + ": SAP blocks need as many even as odd sites");
+                if (bv * nd[l] > 2048) fail(DD_EINVAL, "coarse SAP block too large for one workgroup");
+                std::vector<int> sites((size_t)nsb * 2 * bv);
+                for (int B = 0; B < nsb; B++)
+                    for (int par = 0; par < 2; par++)
+                        for (int q = 0; q < bv; q++) sites[((size_t)B * 2 + par) * bv + q] = sl[2 * (size_t)B + par][q];
+                int* dsites = A.get<int>(sites.size());
+                int* dof = A.get<int>(vol);
+                int* dloc = A.get<int>(vol);
+                HIPX(hipMemcpyAsync(dsites, sites.data(), sizeof(int) * sites.size(), hipMemcpyHostToDevice, C->s));
+                HIPX(hipMemcpyAsync(dof, of.data(), sizeof(int) * vol, hipMemcpyHostToDevice, C->s));
+                HIPX(hipMemcpyAsync(dloc, loc.data(), sizeof(int) * vol, hipMemcpyHostToDevice, C->s));
+                HIPX(hipStreamSynchronize(C->s));
+                stab[l] = SapTab{dsites, dof, dloc, bv};
+                for (int B = 0; B < nsb; B++) {
+                    int r = B, bc3 = r % nbk[3]; r /= nbk[3];
+                    int bc2 = r % nbk[2]; r /= nbk[2];
+                    int bc1 = r % nbk[1], bc0 = r / nbk[1];
+                    lists[(bc0 + bc1 + bc2 + bc3) & 1].push_back(B);
+                }
+            } else {
+                for (int bi = 0; bi < G.nblk; bi++) {
+                    int r = bi, bc3 = r % G.nb[3]; r /= G.nb[3];
+                    int bc2 = r % G.nb[2]; r /= G.nb[2];
+                    int bc1 = r % G.nb[1], bc0 = r / G.nb[1];
+                    lists[(bc0 + bc1 + bc2 + bc3) & 1].push_back(bi);
+                }
             }
             for (int c = 0; c < 2; c++) {
                 nblocks[l][c] = (int)lists[c].size();
@@ -615,14 +718,17 @@ void Hier<T>::build_geometry() {
                 if (!lists[c].empty())
                     HIPX(hipMemcpyAsync(blocks[l][c], lists[c].data(), sizeof(int) * lists[c].size(), hipMemcpyHostToDevice, C->s));
             }
-            if (l > 0 && g[l].bvh * nd[l] > 1024) fail(DD_EINVAL, "coarse SAP block too large for one workgroup");
+            if (l > 0 && !sap_tables && g[l].bvh * nd[l] > 1024) fail(DD_EINVAL, "coarse SAP block too large for one workgroup");
             // aggregation onto level l+1
             int a[4], dc[4];
             for (int mu = 0; mu < 4; mu++) {
                 a[mu] = p.agg[l][mu];
                 if (a[mu] <= 0 || d[mu] % a[mu]) fail(DD_EINVAL, "aggregates do not divide level " + std::to_string(l));
                 dc[mu] = d[mu] / a[mu];
-                if (dc[mu] < 2 || (dc[mu] & 1)) fail(DD_EINVAL, "coarse lattice extents must be even (level " + std::to_string(l + 1) + ")");
+                // odd extents only on the coarsest level (lexicographic layout, plain GMRES)
+                if (dc[mu] < 1 || ((dc[mu] & 1) && l + 1 < nlev - 1))
+                    fail(DD_EINVAL, "coarse lattice extents must be even below the coarsest level (level " +
+                                        std::to_string(l + 1) + ")");
             }
             N[l] = p.n_tv[l];
             if (N[l] < 1 || N[l] > 32) fail(DD_EINVAL, "n_tv must be in 1..32");
@@ -686,7 +792,8 @@ void Hier<T>::sap(int l, const cx<T>* b, cx<T>* z, int nsweeps, bool zero_start,
                 });
             else
                 with_coarse(l, [&](auto& op) {
-                    coarse_sap_half(op, blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s, bt.nr, nlv(l), bt.mask());
+                    coarse_sap_half(op, blocks[l][c], nblocks[l][c], b, z, C->p.mr_steps[l], C->s, bt.nr, nlv(l), bt.mask(),
+                                    stab[l]);
                 });
         }
 }
@@ -742,12 +849,18 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     GmDev* st = gmst[l];
     const Mask live{&st->stop, (int)(sizeof(GmDev) / sizeof(int)), 1};
     const Mask in = bt.mask();
-    auto odd = [&](cx<T>* v) { return v + nh; };
+    // a coarsest lattice with an odd extent has no odd-even structure: plain
+    // GMRES on D_c (Krylov vectors of the full length, no reduction)
+    const bool full = lexl[l];
+    const long nred = full ? nfull : nh;
+    auto odd = [&](cx<T>* v) { return full ? v : v + nh; };
     // A_ee^{-1} D_eo in one pass with the folded blocks (vector-unit forms)
     bool folded = false;
-    with_coarse(l, [&](auto& op) { folded = op.B && !coarse_uses_mfma(op, nr); });
-    // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
-    {
+    with_coarse(l, [&](auto& op) { folded = !full && op.B && !coarse_uses_mfma(op, nr); });
+    if (full) {
+        HIPX(hipMemcpyAsync(f, r, sizeof(cx<T>) * nfull * nr, hipMemcpyDeviceToDevice, C->s));
+    } else {
+        // t_e = A_ee^{-1} r_e ; f_o = r_o - D_oe t_e
         Prof pr(C, DD_K_COARSE, by_coarse(l, 1, 2, false, k) + by_coarse(l, 8, 3, false, k));
         with_coarse(l, [&](auto& op) {
             coarse_apply(op, 0, CS_SELFINV, r, 0, (const cx<T>*)nullptr, false, t, C->s, in, nr, nfull);
@@ -758,9 +871,9 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
     // clearing unless right-hand sides outside the batch's mask keep theirs
     if (k < nr) HIPX(hipMemsetAsync(e, 0, sizeof(cx<T>) * nfull * nr, C->s));
     RedBatch rb0{nr, nfull, nfull, RS, in};
-    vec_multidot<T>(nh, 1, odd(f), 0, odd(f), C->dred, C->dwork, nullptr, C->s, rb0);
+    vec_multidot<T>(nred, 1, odd(f), 0, odd(f), C->dred, C->dwork, nullptr, C->s, rb0);
     gm_start(st, C->dred, RS, p.coarse_tol, 1, m, p.coarse_maxit, p.coarse_fixed, nr, C->s, in);
-    vec_scale_dev<T>(nh, st, odd(V), C->s, true, nr, nfull, odd(f));
+    vec_scale_dev<T>(nred, st, odd(V), C->s, true, nr, nfull, odd(f));
     bool first_cycle = true;
     int* hs = C->hint + DI_GATHER;
     auto read_state = [&]() {
@@ -782,7 +895,9 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
             with_coarse(l, [&](auto& op) {
                 // vector-unit forms: basis vectors stay unnormalised, their factors
                 // scale the stencil's inputs (no pass over w to normalise it)
-                if (folded) {
+                if (full) {
+                    coarse_apply(op, -1, CS_SELF, vj, 1, vj, false, w, sq, live, nr, nfull);
+                } else if (folded) {
                     coarse_apply_folded(op, (const cx<T>*)nullptr, 1, vj, wc[l], sq, live, nr, nfull, InScale{st, j, 2});
                     coarse_apply(op, 1, CS_SELF, vj, -1, wc[l], false, w, sq, live, nr, nfull, InScale{st, j, 1});
                 } else {
@@ -791,16 +906,16 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
                 }
             });
         }
-        Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nh, j + 1, k));
-        vec_multidot_skip<T>(nh, j + 1, odd(V), ldv, odd(w), C->dwork, sq, rb);
-        vec_update_norm_givens<T>(nh, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb, st, j, C->dflags + DI_DONE,
+        Prof pr(C, DD_K_REDUCE, 2 * by_reduce(nred, j + 1, k));
+        vec_multidot_skip<T>(nred, j + 1, odd(V), ldv, odd(w), C->dwork, sq, rb);
+        vec_update_norm_givens<T>(nred, j + 1, odd(V), ldv, odd(w), C->dred, C->dwork, sq, rb, st, j, C->dflags + DI_DONE,
                                   !folded);
     };
     // graphs need a capture stream; live kernel timing brackets single launches
     const bool use_graphs = (C->sched & SCHED_GRAPH) && C->cap;
     // one cooperative launch per restart cycle when the device admits the grid
     int coop_grid = 0;
-    if ((C->sched & SCHED_COOP) && !coop_off && nd[l] <= 64 && nr <= 16 && m <= 32) {
+    if ((C->sched & SCHED_COOP) && !coop_off && !full && nd[l] <= 64 && nr <= 16 && m <= 32) {
         int mx = 0;
         with_coarse(l, [&](auto& op) {
             using OpT = typename std::remove_reference<decltype(op)>::type;
@@ -860,7 +975,7 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
                     it = graphs.emplace(key, ex).first;
                 }
                 double by = 0;
-                for (int q = j; q < jend; q++) by += 2 * by_coarse(l, 9, 2, false, k) + 2 * by_reduce(nh, q + 1, k);
+                for (int q = j; q < jend; q++) by += 2 * by_coarse(l, 9, 2, false, k) + 2 * by_reduce(nred, q + 1, k);
                 Prof pr(C, DD_K_COARSE_STEP, by);
                 HIPX(hipGraphLaunch(it->second, C->s));
                 j = jend;
@@ -871,20 +986,25 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
             chunk = 4;
         }
         gm_solve(st, nr, C->s);
-        vec_lincomb_dev<T>(nh, odd(V), ldv, st, odd(e), C->s, nr, nfull, nfull, first_cycle);
+        vec_lincomb_dev<T>(nred, odd(V), ldv, st, odd(e), C->s, nr, nfull, nfull, first_cycle);
         first_cycle = false;
         if (all_stop) break;
-        // restart the running RHS from their true Schur residual
-        schur(l, e, V, live, nr, k);
-        bvec_sub<T>(nh, odd(f), odd(V), odd(V), nfull, nr, live, C->s);
-        vec_multidot<T>(nh, 1, odd(V), 0, odd(V), C->dred, C->dwork, nullptr, C->s, rb);
+        // restart the running RHS from their true (Schur) residual
+        if (full) {
+            Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, true, k));
+            with_coarse(l, [&](auto& op) { coarse_apply(op, -1, CS_SELF, e, 1, e, false, V, C->s, live, nr, nfull); });
+        } else {
+            schur(l, e, V, live, nr, k);
+        }
+        bvec_sub<T>(nred, odd(f), odd(V), odd(V), nfull, nr, live, C->s);
+        vec_multidot<T>(nred, 1, odd(V), 0, odd(V), C->dred, C->dwork, nullptr, C->s, rb);
         gm_start(st, C->dred, RS, p.coarse_tol, 0, m, p.coarse_maxit, p.coarse_fixed, nr, C->s);
-        vec_scale_dev<T>(nh, st, odd(V), C->s, false, nr, nfull);
+        vec_scale_dev<T>(nred, st, odd(V), C->s, false, nr, nfull);
         if (read_state()) break;
         chunk = 4;
     }
     // e_e = A_ee^{-1} (r_e - D_eo e_o)  (= t_e - B e_o with the folded blocks)
-    {
+    if (!full) {
         Prof pr(C, DD_K_COARSE, by_coarse(l, 9, 2, false, k));
         with_coarse(l, [&](auto& op) {
             if (folded) coarse_apply_folded(op, (const cx<T>*)t, -1, e, e, C->s, in, nr, nfull);
@@ -2159,6 +2279,7 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
             break;
         case DD_OP_SCHUR:
             if (l < 1) fail(DD_EINVAL, "Schur complement needs level >= 1");
+            if (H.lexl[l]) fail(DD_EINVAL, "no odd-even Schur complement on a lattice with an odd extent");
             imp(l, in, H.wa[l]);
             H.schur(l, H.wa[l], H.wb[l], bt.mask(), k, k);
             for (int r = 0; r < k; r++)
