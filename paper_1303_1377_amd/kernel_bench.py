@@ -2,7 +2,7 @@
 
     python -m paper_1303_1377_amd.kernel_bench [--dims 64,32,32,32]
         [--kernels copy,dirac64,dirac32,sap32,sap64] [--reps 20] [--mr 4]
-        [--sched 0,1,2,3]
+        [--sched 0,1,2,3] [--device-field]
 
 Each kernel is launched `reps` times back to back between two HIP events on
 internal random data (dd_time_kernel); one JSON line reports the mean launch
@@ -12,7 +12,8 @@ kernel trace and the memory counters of exactly these launches.
 
 Byte model per lattice site (reals of the storage precision):
   stencil   192 = links 72 + clover 72 + spinor in 24 + spinor out 24
-  SAP sweep 216 = links 72 + clover 72 + b 24 + z read 24 + z write 24 (each
+  SAP sweep 288 = links 72 + clover 72 + b 24 + z read 24 + z write 24 + the
+            residual 24 + the face values of the neighbouring blocks 48 (each
             site is solved once per sweep, in the half sweep of its colour)
   copy      one FP64 spinor read and written: 2 x 24 reals of 8 bytes
   coarse    per coarse site: 9 blocks of nd x nd complex (storage precision)
@@ -32,7 +33,7 @@ def _log(*a):
 
 
 def run(dims=(64, 32, 32, 32), kernels=("copy", "dirac64", "dirac32", "sap32", "sap64"), reps=20, mr=4, seed=0,
-        scheds=(3,)):
+        scheds=(3,), device_field=False):
     import numpy as np
 
     import paper_1303_1377_amd as G
@@ -40,7 +41,7 @@ def run(dims=(64, 32, 32, 32), kernels=("copy", "dirac64", "dirac32", "sap32", "
 
     vol = int(np.prod(dims))
     t = time.time()
-    U = F.make_gauge(dims, 0.4, seed)
+    U = F.make_gauge_device(dims, 0.4, seed) if device_field else F.make_gauge(dims, 0.4, seed)
     _log("kernel_bench: %s links in %.1fs" % ("x".join(map(str, dims)), time.time() - t))
     s = G.Solver(dims, U, -0.05, 1.0)
     del U
@@ -83,7 +84,7 @@ def run(dims=(64, 32, 32, 32), kernels=("copy", "dirac64", "dirac32", "sap32", "
                 by = vol * 192 * sz
             else:
                 ms = s.time_kernel("sap", reps=reps)
-                by = vol * 216 * sz
+                by = vol * 288 * sz
         key = k if sc is None or len(scheds) == 1 else "%s_sched%d" % (k, sc)
         out[key] = dict(ms=ms, GBs=by / (ms * 1e-3) / 1e9, bytes=by, sched=sc)
         _log("kernel_bench: %s %.4f ms %.0f GB/s" % (key, ms, out[key]["GBs"]))
@@ -98,9 +99,11 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--mr", type=int, default=4)
     ap.add_argument("--sched", default="3", help="comma-separated launch schedules (DD_SCHED_* flag sets)")
+    ap.add_argument("--device-field", action="store_true", help="draw the links on the GPU (large lattices)")
     a = ap.parse_args()
     dims = tuple(int(v) for v in a.dims.split(","))
-    res = run(dims, tuple(a.kernels.split(",")), a.reps, a.mr, scheds=tuple(int(v) for v in a.sched.split(",")))
+    res = run(dims, tuple(a.kernels.split(",")), a.reps, a.mr, scheds=tuple(int(v) for v in a.sched.split(",")),
+              device_field=a.device_field)
     print(json.dumps(dict(dims=list(dims), reps=a.reps, mr_steps=a.mr, kernels=res)), flush=True)
 
 
