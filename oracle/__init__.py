@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("mid_fixed", C.c_int),
         ("outer_restart", C.c_int),
         ("outer_maxit", C.c_int),
+        ("id_setup", C.c_int),
     ]
 
 
@@ -83,6 +84,7 @@ DEFAULTS = dict(
     mid_fixed=0,
     outer_restart=25,
     outer_maxit=2000,
+    id_setup=0,
 )
 
 
@@ -101,7 +103,7 @@ def make_params(**kw) -> Params:
             p.agg[l][mu] = d["agg"][l][mu] if l < len(d["agg"]) else 2
             p.sap[l][mu] = d["sap"][l][mu] if l < len(d["sap"]) else 2
     for k in ("nu", "n_inv", "coarse_restart", "coarse_maxit", "coarse_fixed",
-              "mid_restart", "mid_maxit", "mid_fixed", "outer_restart", "outer_maxit"):
+              "mid_restart", "mid_maxit", "mid_fixed", "outer_restart", "outer_maxit", "id_setup"):
         setattr(p, k, int(d[k]))
     p.coarse_tol = float(d["coarse_tol"])
     p.mid_tol = float(d["mid_tol"])
@@ -149,6 +151,8 @@ def lib():
         L.or_bicgstab.restype = C.c_long
         L.or_bicgstab.argtypes = [vp, cp, cp, C.c_int]
         L.or_solve_bicgstab.argtypes = [vp, cp, cp, dp, C.c_int, C.POINTER(Stats)]
+        L.or_solve_id.argtypes = [vp, cp, cp, dp, C.c_int, C.POINTER(Stats)]
+        L.or_apply_deflated.argtypes = [vp, cp, cp]
         L.or_fgmres_level.restype = C.c_long
         L.or_fgmres_level.argtypes = [vp, C.c_int, cp, cp]
         L.or_setup_level.argtypes = [vp, C.c_int]
@@ -371,6 +375,24 @@ class Oracle:
         rc = lib().or_solve_bicgstab(self.h, _ptr(bb), _ptr(x), float(tol), int(steps), C.byref(st))
         return x.reshape(np.shape(b)), dict(rc=rc, outer_iters=st.outer_iters, restarts=st.restarts,
                                             true_relres=st.true_relres, converged=bool(st.converged))
+
+    def solve_id(self, b, tol=1e-10, nu=5):
+        """Inexact deflation (two-level hierarchy as built): FGMRES on D pi_R with
+        nu SAP iterations as preconditioner; returns (x, stats)."""
+        bb = _c(b).reshape(self.vol * 12)
+        x = np.zeros_like(bb)
+        st = Stats()
+        rc = lib().or_solve_id(self.h, _ptr(bb), _ptr(x), float(tol), int(nu), C.byref(st))
+        return x.reshape(np.shape(b)), dict(rc=rc, outer_iters=st.outer_iters, restarts=st.restarts,
+                                            coarse_iters=list(st.coarse_iters), true_relres=st.true_relres,
+                                            converged=bool(st.converged))
+
+    def apply_deflated(self, v):
+        """D pi_R v (inexact-deflation operator; coarse solves to the parameters' tolerance)."""
+        a = _c(v).reshape(self.vol * 12)
+        out = np.zeros_like(a)
+        lib().or_apply_deflated(self.h, _ptr(a), _ptr(out))
+        return out.reshape(np.shape(v))
 
     def mark_setup(self):
         lib().or_mark_setup(self.h)

@@ -24,7 +24,8 @@
  *   outer solver ........ Sec. 4.2/5    FGMRES right-preconditioned by one V-cycle
  *   setup ............... Alg. 2        DD-alpha-AMG-setup(n_inv, nu) built on Alg. 1
  *   multilevel .......... Sec. 3, 5     recursive application on D_c
- *   comparison solver ... Sec. 6        FGMRES preconditioned by odd-even BiCGStab
+ *   comparison solvers .. Sec. 6        FGMRES preconditioned by odd-even BiCGStab;
+ *                        Sec. 4.1      inexact deflation (FGMRES on D pi_R with SAP)
  *
  * Readings of points the paper leaves open are listed in the design notes of
  * the repository and repeated at the routine that takes them.
@@ -63,6 +64,7 @@ typedef struct {
     int mid_fixed;            /* >0: exactly this many intermediate iterations     */
     int outer_restart;
     int outer_maxit;
+    int id_setup;             /* 1: the setup is IDsetup (Sec. 4.3), not Alg. 2    */
 } or_params;
 
 typedef struct {
@@ -292,6 +294,8 @@ typedef struct {
     long coarse_count[OR_MAXLEV];
     int pre_bicg;    /* > 0: the outer FGMRES is preconditioned by this many
                         odd-even BiCGStab steps instead of the V-cycle       */
+    int pre_sap;     /* > 0: ... by this many SAP iterations (M_SAP^(nu))    */
+    int deflated;    /* 1: the outer FGMRES runs on D pi_R (inexact deflation) */
     char err[256];
 } octx;
 
@@ -1005,6 +1009,41 @@ static long bicgstab_oe(const level *L, const cplx *b, cplx *x, int steps) {
 /* ------------------------------------------------------------------------ */
 static void vcycle(octx *X, int l, int bottom, const cplx *r, cplx *z);
 
+/* Inexact deflation (Sec. 4.1): out = pi_R in = in - P D_c^{-1} P^H D in with the
+ * coarse system solved by the coarsest solver of level 1 (to the tolerance of
+ * the parameters: high accuracy for this method). */
+static void pi_R(octx *X, const cplx *in, cplx *out) {
+    level *F = &X->L[0], *C = &X->L[1];
+    const long n = F->g.vol * F->nd, nc = C->g.vol * C->nd;
+    cplx *t = cvalloc(n), *rc = cvalloc(nc), *ec = cvalloc(nc);
+    apply_full(F, in, t);
+    restrict_to(F, C, t, rc);
+    X->coarse_count[1] += coarse_solve(C, &X->p, rc, ec);
+    prolong_from(F, C, ec, t);
+    for (long i = 0; i < n; i++) out[i] = in[i] - t[i];
+    free(t); free(rc); free(ec);
+}
+
+/* The operator of the outer FGMRES on level 0: D, or D pi_R for inexact deflation. */
+static void outer_op(octx *X, int l, const cplx *in, cplx *out) {
+    const level *L = &X->L[l];
+    if (l == 0 && X->deflated) {
+        cplx *t = cvalloc(L->g.vol * L->nd);
+        pi_R(X, in, t);
+        apply_full(L, t, out);
+        free(t);
+    } else {
+        apply_full(L, in, out);
+    }
+}
+
+static void outer_op_deflated(octx *X, const cplx *in, cplx *out) {
+    int d = X->deflated;
+    X->deflated = 1;
+    outer_op(X, 0, in, out);
+    X->deflated = d;
+}
+
 /* Flexible GMRES(m) on level l, right-preconditioned by one V-cycle of level l
  * whose coarsest level is `bottom`.  Arnoldi by modified Gram-Schmidt with one
  * re-orthogonalisation pass.  Convergence is decided on the true residual
@@ -1040,8 +1079,9 @@ static long fgmres(octx *X, int l, int bottom, const cplx *rhs, cplx *x, double 
         int jend = 0;
         for (int j = 0; j < m; j++) {
             if (X->pre_bicg > 0 && l == 0) bicgstab_oe(L, V[j], Z[j], X->pre_bicg);
+            else if (X->pre_sap > 0 && l == 0) { vzero(n, Z[j]); sap_sweeps(L, V[j], Z[j], X->pre_sap); }
             else vcycle(X, l, bottom, V[j], Z[j]);
-            apply_full(L, Z[j], w);
+            outer_op(X, l, Z[j], w);
             for (int pass = 0; pass < 2; pass++)
                 for (int i = 0; i <= j; i++) {
                     cplx h = vdot(n, V[i], w);
@@ -1076,7 +1116,7 @@ static long fgmres(octx *X, int l, int bottom, const cplx *rhs, cplx *x, double 
             y[i] = s / H[i * m + i];
         }
         for (int i = 0; i < jend; i++) vaxpy(n, y[i], Z[i], x);
-        apply_full(L, x, w);
+        outer_op(X, l, x, w);
 #pragma omp parallel for schedule(static)
         for (long i = 0; i < n; i++) w[i] = rhs[i] - w[i];
         if (fixed > 0 && its >= fixed) { conv = vnorm(n, w) <= tol * bnorm; break; }
@@ -1351,7 +1391,9 @@ long or_fgmres_level(void *p, int l, const cplx *rhs, cplx *x) {
 }
 
 /* Algorithm 2 (DD-alpha-AMG-setup(n_inv, nu)) on level l with the test vectors
- * already installed by or_set_vectors.  The V-cycles inside use level l+1 as
+ * already installed by or_set_vectors; with id_setup, the inexact-deflation
+ * setup of Sec. 4.3 instead, which differs only in the update of the second
+ * half (the V-cycle applied to v_j from a zero start replaces v_j).  The V-cycles inside use level l+1 as
  * the coarsest level.  Readings: the vectors are normalised after each of the
  * three initial SAP passes (the passes are homogeneous, so only the scale
  * changes), and P, D_c are rebuilt once more from the final vectors. */
@@ -1374,11 +1416,17 @@ int or_setup_level(void *p, int l) {
         if ((rc = or_build(p, l))) goto out;
         for (int j = 0; j < F->nv; j++) {
             cplx *v = F->tv + (long)j * n;
-            apply_full(F, v, r);
+            if (X->p.id_setup) {
+                /* IDsetup: v_j <- (M_SAP^(nu) pi_L + P D_c^{-1} P^H) v_j, the V-cycle from zero */
+                vcycle(X, l, l + 1, v, c);
+                vcopy(n, c, v);
+            } else {
+                apply_full(F, v, r);
 #pragma omp parallel for schedule(static)
-            for (long i = 0; i < n; i++) r[i] = v[i] - r[i];
-            vcycle(X, l, l + 1, r, c);
-            vaxpy(n, 1.0, c, v);
+                for (long i = 0; i < n; i++) r[i] = v[i] - r[i];
+                vcycle(X, l, l + 1, r, c);
+                vaxpy(n, 1.0, c, v);
+            }
             vscale(n, 1.0 / vnorm(n, v), v);
         }
     }
@@ -1456,6 +1504,51 @@ int or_solve_bicgstab(void *p, const cplx *b, cplx *x, double tol, int steps, or
     }
     return conv ? 0 : -3;
 }
+
+/* Inexact deflation (Sec. 4.1), the other comparison solver: with the two-level
+ * hierarchy as built (P, D_c), chi' = P D_c^{-1} P^H b, then FGMRES(outer_restart)
+ * on D pi_R chi = pi_L b = b - D chi' right-preconditioned by nu SAP iterations
+ * M_SAP^(nu) (the paper uses GCR, the same minimal-residual iterates), and
+ * z = pi_R chi + chi'.  The coarse systems are solved to the coarsest solver's
+ * tolerance of the parameters, which this method needs small.  tol applies to
+ * the deflated system; the true residual of z is reported. */
+int or_solve_id(void *p, const cplx *b, cplx *x, double tol, int nu, or_stats *st) {
+    octx *X = (octx *)p;
+    if (!X->have_setup || X->nlev != 2) return -5;
+    level *F = &X->L[0], *C = &X->L[1];
+    const long n = F->g.vol * F->nd, nc = C->g.vol * C->nd;
+    memset(X->coarse_count, 0, sizeof X->coarse_count);
+    cplx *rc = cvalloc(nc), *ec = cvalloc(nc), *chi1 = cvalloc(n), *bd = cvalloc(n), *chi = cvalloc(n);
+    restrict_to(F, C, b, rc);
+    X->coarse_count[1] += coarse_solve(C, &X->p, rc, ec);
+    prolong_from(F, C, ec, chi1);
+    apply_full(F, chi1, bd);
+    for (long i = 0; i < n; i++) bd[i] = b[i] - bd[i];
+    X->deflated = 1;
+    X->pre_sap = nu;
+    int restarts = 0, conv = 0;
+    long its = fgmres(X, 0, 1, bd, chi, tol, X->p.outer_restart, X->p.outer_maxit, 0, &restarts, &conv);
+    X->deflated = 0;
+    X->pre_sap = 0;
+    pi_R(X, chi, x);
+    vaxpy(n, 1.0, chi1, x);
+    if (st) {
+        cplx *r = cvalloc(n);
+        apply_full(F, x, r);
+        for (long i = 0; i < n; i++) r[i] = b[i] - r[i];
+        st->true_relres = vnorm(n, r) / vnorm(n, b);
+        free(r);
+        st->outer_iters = (int)its;
+        st->restarts = restarts;
+        st->converged = conv;
+        for (int l = 0; l < OR_MAXLEV; l++) st->coarse_iters[l] = X->coarse_count[l];
+    }
+    free(rc); free(ec); free(chi1); free(bd); free(chi);
+    return conv ? 0 : -3;
+}
+
+/* out = D pi_R in on level 0 (the inexact-deflation operator). */
+void or_apply_deflated(void *p, const cplx *in, cplx *out) { outer_op_deflated((octx *)p, in, out); }
 
 /* Mark the hierarchy as complete after components were installed piecewise. */
 void or_mark_setup(void *p) { ((octx *)p)->have_setup = 1; }
