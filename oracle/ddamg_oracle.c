@@ -983,6 +983,7 @@ static long bicgstab_oe(const level *L, const cplx *b, cplx *x, int steps) {
         vaxpy(n, alpha, p, xo);
         if (tn == 0) { it++; break; }
         omega = vdot(n, tt, s) / tn;
+        if (omega == 0) { it++; break; }   /* breakdown: the next beta would divide by omega */
         vaxpy(n, omega, s, xo);
         for (long i = 0; i < n; i++) r[i] = s[i] - omega * tt[i];
         rho_old = rho;
