@@ -80,6 +80,9 @@ typedef struct {
     unsigned long long seed;     /* counter-based RNG key for the initial test vectors     */
     int max_rhs;                 /* right-hand sides one dd_solve_batch call can carry in
                                     one batch (1..16); sizes the Krylov workspace          */
+    int id_setup;                /* 1: the setup of inexact deflation (Sec. 4.3): in the
+                                    n_inv rounds v_j <- C^(nu) v_j (V-cycle from a zero
+                                    start) replaces v_j <- v_j + C^(nu)(v_j - D v_j)       */
 } dd_params;
 
 typedef struct {
@@ -156,6 +159,25 @@ dd_status dd_solve_batch(dd_ctx *ctx, int k, const double *b, double *x, double 
  * the BiCGStab steps.  Errors as dd_solve (DD_ESTATE without dd_configure). */
 dd_status dd_solve_bicgstab(dd_ctx *ctx, const double *b, double *x, double tol, int steps, int precision,
                             dd_stats *stats);
+
+/* Comparison solver of Sec. 4.1 (inexact deflation, Tables 8 and 9), in FP64 on
+ * a two-level setup (levels = 2, precision 64; dd_setup with id_setup = 1 gives
+ * the setup of Sec. 4.3, any other setup is accepted too):
+ *   chi' = P D_c^{-1} P^H b,
+ *   FGMRES(outer_restart) on D pi_R chi = pi_L b = b - D chi', right-
+ *   preconditioned by `nu` SAP iterations M_SAP^(nu) from zero,
+ *   x = pi_R chi + chi',   pi_R = I - P D_c^{-1} P^H D.
+ * Every D_c^{-1} is the coarsest odd-even GMRES run to relative residual
+ * `coarse_tol` (the method needs it near the solve tolerance, Sec. 4.2; the
+ * paper's comparison uses 1e-12).  tol applies to the deflated system; the
+ * returned true_relres is ||b - D x|| / ||b|| of the final x.
+ *   b, x  device complex128 fine spinors; x output only
+ * stats: outer_iters, restarts, coarse_iters[1] = summed coarse GMRES
+ * iterations, true_relres, converged.  Errors: DD_ESTATE before dd_setup or on
+ * a setup that is not FP64 two-level, DD_EINVAL on nu < 1 or tolerances <= 0,
+ * otherwise as dd_solve. */
+dd_status dd_solve_id(dd_ctx *ctx, const double *b, double *x, double tol, int nu, double coarse_tol,
+                      dd_stats *stats);
 
 /* Continuous batching on the resident setup.  The max_rhs right-hand-side
  * slots of the outer FGMRES are filled, advanced and emptied independently:
@@ -234,10 +256,13 @@ typedef enum {
     DD_OP_SCHUR = 7,        /* out = S in, S = A_oo - D_oe A_ee^-1 D_eo on `level`;
                                in and out are full vectors, zero on even sites        */
     DD_OP_FGMRES = 8,       /* intermediate-level FGMRES (3+ levels) on `level`         */
-    DD_OP_BICGSTAB = 9      /* level 0: `arg` BiCGStab steps on the odd-even reduced
+    DD_OP_BICGSTAB = 9,     /* level 0: `arg` BiCGStab steps on the odd-even reduced
                                system from zero, then the even-site back-substitution
                                (the preconditioner of dd_solve_bicgstab), in the
                                preconditioner precision                              */
+    DD_OP_DEFLATED = 10     /* level 0, FP64 two-level setup: out = D pi_R in, the
+                               operator of dd_solve_id, with the coarse system
+                               solved to the parameters' coarse_tol                   */
 } dd_op;
 
 /* Apply one component.  in/out are device complex128 vectors of the level in

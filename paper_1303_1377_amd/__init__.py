@@ -21,7 +21,8 @@ MAXLEV = 4
 
 KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse", "coarse_sap", "reduce", "blas",
                   "coarse_step"]
-OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8, BICGSTAB=9)
+OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8, BICGSTAB=9,
+           DEFLATED=10)
 STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
           -6: "DD_ENUMERIC"}
 
@@ -55,6 +56,7 @@ class Params(C.Structure):
         ("given_vectors", C.c_int),
         ("seed", C.c_ulonglong),
         ("max_rhs", C.c_int),
+        ("id_setup", C.c_int),
     ]
 
 
@@ -107,6 +109,7 @@ def library():
         L.dd_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_long)]
         L.dd_apply_D_noalloc.argtypes = [vp, vp, vp]
         L.dd_solve_bicgstab.argtypes = [vp, vp, vp, dp, C.c_int, C.c_int, C.POINTER(Stats)]
+        L.dd_solve_id.argtypes = [vp, vp, vp, dp, C.c_int, dp, C.POINTER(Stats)]
         L.dd_stream_load.argtypes = [vp, C.c_int, vp, dp]
         L.dd_stream_cycle.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(Stats)]
         L.dd_stream_take.argtypes = [vp, C.c_int, vp, C.POINTER(Stats)]
@@ -322,6 +325,20 @@ class Solver:
         _order_after_current(self.stream)
         rc = library().dd_solve_bicgstab(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
                                          int(steps), int(precision), C.byref(st))
+        self._check(rc, ok=(0, -3) if allow_noconv else (0,))
+        return x, st.as_dict()
+
+    def solve_id(self, b, tol=1e-10, nu=5, coarse_tol=1e-12, allow_noconv=False):
+        """The second comparison solver, inexact deflation (FP64, two-level
+        setup): FGMRES on D pi_R preconditioned by nu SAP iterations, coarse
+        systems solved to coarse_tol."""
+        torch = _torch()
+        bb = _dev(b).reshape(self.vol, 4, 3)
+        x = torch.empty_like(bb)
+        st = Stats()
+        _order_after_current(self.stream)
+        rc = library().dd_solve_id(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), float(tol), int(nu),
+                                   float(coarse_tol), C.byref(st))
         self._check(rc, ok=(0, -3) if allow_noconv else (0,))
         return x, st.as_dict()
 

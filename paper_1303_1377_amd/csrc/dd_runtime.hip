@@ -268,6 +268,7 @@ struct dd_ctx {
     } stream;
     void* bicg_ws = nullptr;     // odd-even BiCGStab vectors (levels arena; cleared with it)
     int bicg_prec = 0;
+    void* id_ws = nullptr;       // inexact-deflation vectors (levels arena; cleared with it)
     void* scratch = nullptr;     // device address of this GPU's `scratch` array (dd_apply_D_noalloc)
     std::string scratch_err;     // why it is unavailable, if it is
     int sched = SCHED_LDS | SCHED_XCD | SCHED_GRAPH;   // launch schedule (SCHED_* flags)
@@ -1251,9 +1252,10 @@ void Hier<T>::refresh_half(int l) {
     (void)l;
 }
 
-// Algorithm 2 on level l with level l+1 as the coarsest level of its V-cycles.
-// Readings: vectors normalised after each of the three initial SAP passes; P
-// and D_c rebuilt from the final vectors.
+// Algorithm 2 on level l with level l+1 as the coarsest level of its V-cycles
+// (with id_setup, the inexact-deflation setup of Sec. 4.3, which replaces the
+// update of the second half).  Readings: vectors normalised after each of the
+// three initial SAP passes; P and D_c rebuilt from the final vectors.
 template <class T>
 void Hier<T>::setup_level(int l, bool given) {
     const long n = nlv(l);
@@ -1275,10 +1277,16 @@ void Hier<T>::setup_level(int l, bool given) {
         build(l);
         for (int j = 0; j < N[l]; j++) {
             cx<T>* v = tv[l] + (size_t)j * n;
-            apply_D(l, v, wa[l], one);
-            vec_sub<T>(n, v, wa[l], wa[l], C->s);
-            vcycle(l, l + 1, wa[l], wb[l], one);
-            vec_axpy<T>(n, cx<double>{1.0, 0.0}, wb[l], v, C->s);
+            if (C->p.id_setup) {
+                // inexact-deflation setup (Sec. 4.3): v_j <- C^(nu) v_j from a zero start
+                vcycle(l, l + 1, v, wb[l], one);
+                HIPX(hipMemcpyAsync(v, wb[l], sizeof(cx<T>) * n, hipMemcpyDeviceToDevice, C->s));
+            } else {
+                apply_D(l, v, wa[l], one);
+                vec_sub<T>(n, v, wa[l], wa[l], C->s);
+                vcycle(l, l + 1, wa[l], wb[l], one);
+                vec_axpy<T>(n, cx<double>{1.0, 0.0}, wb[l], v, C->s);
+            }
             double nv = norm1(n, v);
             if (!(nv > 0) || !std::isfinite(nv)) fail(DD_ENUMERIC, "setup: vanishing or non-finite test vector");
             vec_scale<T>(n, cx<double>{1.0 / nv, 0.0}, v, C->s);
@@ -1448,6 +1456,7 @@ struct OeBicg {
             vec_axpy<T>(no, cx<double>{alpha.real(), alpha.imag()}, odd(p), odd(z), C->s);
             if (tt == 0.0) { it++; break; }   // s = 0: x is exact
             omega = ts / tt;
+            if (std::abs(omega) == 0.0) { it++; break; }   // breakdown: the next beta would divide by omega
             vec_axpy<T>(no, cx<double>{omega.real(), omega.imag()}, odd(sv), odd(z), C->s);
             // r = s - omega t
             HIPX(hipMemcpyAsync(odd(r), odd(sv), hb, hipMemcpyDeviceToDevice, C->s));
@@ -1526,6 +1535,131 @@ static dd_status bicg_solve_impl(dd_ctx* C, const double* bin, double* xout, dou
     return res.conv[0] ? DD_OK : DD_ENOCONV;
 }
 
+
+// ---------------------------------------------------------------------------
+// Comparison solver of Sec. 4.1: inexact deflation, FP64, two levels.
+//   pi_R v = v - P D_c^{-1} P^H D v, every D_c^{-1} the coarsest odd-even GMRES
+//   run to relative residual ctol;
+//   chi' = P D_c^{-1} P^H b;  FGMRES on D pi_R chi = b - D chi' right-
+//   preconditioned by nu SAP iterations from zero;  x = pi_R chi + chi'.
+// ---------------------------------------------------------------------------
+struct IdDefl {
+    dd_ctx* C;
+    Hier<double>* H;
+    long n;
+    double ctol;
+    cx<double>* b0; cx<double>* chi1; cx<double>* t1; cx<double>* t2; cx<double>* t3;
+    static IdDefl make(dd_ctx* C, Hier<double>* H, double ctol) {
+        IdDefl d;
+        d.C = C;
+        d.H = H;
+        d.n = 24L * C->g0.vh;
+        d.ctol = ctol;
+        if (!C->id_ws) C->id_ws = C->levels.alloc(sizeof(cx<double>) * 5 * (size_t)d.n);
+        cx<double>* w = reinterpret_cast<cx<double>*>(C->id_ws);
+        cx<double>** slot[5] = {&d.b0, &d.chi1, &d.t1, &d.t2, &d.t3};
+        for (int k = 0; k < 5; k++) *slot[k] = w + (size_t)k * d.n;
+        return d;
+    }
+    // out = P D_c^{-1} P^H in
+    void coarse_correction(const cx<double>* in, cx<double>* out, const Batch& bt) {
+        H->restrict_(0, in, H->rc[1], bt);
+        const double keep = C->p.coarse_tol;
+        C->p.coarse_tol = ctol;
+        try {
+            H->gmres_oe(1, H->rc[1], H->ec[1], bt);
+        } catch (...) {
+            C->p.coarse_tol = keep;
+            throw;
+        }
+        C->p.coarse_tol = keep;
+        H->prolong(0, H->ec[1], out, bt);
+    }
+    void dirac(const cx<double>* in, cx<double>* out, const Batch& bt) {
+        Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
+        fine_dirac<double>(fine_op<double>(C), in, out, C->s, bt.nr, n, bt.mask());
+    }
+    // out = pi_R in (out distinct from in; t1, t2 are used)
+    void pi_R(const cx<double>* in, cx<double>* out, const Batch& bt) {
+        dirac(in, t1, bt);
+        coarse_correction(t1, t2, bt);
+        bvec_sub<double>(n, in, t2, out, n, bt.nr, bt.mask(), C->s);
+    }
+    // out = D pi_R in (t1, t2, t3 are used)
+    void deflated(const cx<double>* in, cx<double>* out, const Batch& bt) {
+        pi_R(in, t3, bt);
+        dirac(t3, out, bt);
+    }
+};
+
+struct IdOps {
+    dd_ctx* C;
+    IdDefl* Dp;
+    const cx<double>* b;
+    cx<double>* x;
+    long n;
+    int nu;
+    cx<double>* Zb;
+    cx<double>* V() { return C->oV; }
+    cx<double>* Z() { return Zb; }
+    void precond(const cx<double>* v, cx<double>* z, const Batch& bt) { Dp->H->sap(0, v, z, nu, true, bt); }
+    void matvec(const cx<double>* z, cx<double>* w, const Batch& bt) { Dp->deflated(z, w, bt); }
+    void update(int m, const cx<double>* Z, long ldz, const cx<double>* y, const Batch& bt, const Counts& jc) {
+        vec_lincomb<double, double>(n, m, Z, ldz, y, x, C->s, bt.nr, n, 32, n, bt.mask(), &jc);
+    }
+    void residual(const Batch& bt) {
+        Dp->deflated(x, Dp->t1, bt);
+        bvec_sub<double>(n, b, Dp->t1, C->oV, n, bt.nr, bt.mask(), C->s);
+    }
+    std::vector<double> norms(const cx<double>* v, const Batch& bt) { return OuterOps<double>::norms64(C, n, v, bt); }
+};
+
+static dd_status id_solve_impl(dd_ctx* C, Hier<double>& H, const double* bin, double* xout, double tol, int nu,
+                               double ctol, dd_stats* st) {
+    const dd_params& p = C->p;
+    const int m = p.outer_restart;
+    const long n = 24L * C->g0.vh;
+    const long ldv = (long)C->R * n;
+    const double t0 = now_s();
+    IdDefl Dp = IdDefl::make(C, &H, ctol);
+    Batch one{1, C->dflags + DI_ONES, 1u};
+    fine_import_vectors<double>(C->g0, 1, bin, Dp.b0, C->s);
+    clear_flag(C, DI_BAD);
+    vec_finite_check<double>(n, Dp.b0, C->dflags + DI_BAD, C->s);
+    if (read_flag(C, DI_BAD)) fail(DD_ENUMERIC, "NaN/Inf in the right-hand side");
+    memset(H.coarse_count, 0, sizeof H.coarse_count);
+    // chi' = P D_c^{-1} P^H b and the deflated right-hand side pi_L b = b - D chi'
+    Dp.coarse_correction(Dp.b0, Dp.chi1, one);
+    Dp.dirac(Dp.chi1, Dp.t1, one);
+    bvec_sub<double>(n, Dp.b0, Dp.t1, C->ob, n, 1, one.mask(), C->s);
+    HIPX(hipMemsetAsync(C->ox, 0, sizeof(cx<double>) * n, C->s));
+    std::vector<double> bn = OuterOps<double>::norms64(C, n, C->ob, one);
+    HIPX(hipMemcpyAsync(C->oV, C->ob, sizeof(cx<double>) * n, hipMemcpyDeviceToDevice, C->s));
+    IdOps ops{C, &Dp, C->ob, C->ox, n, nu, C->oV + (size_t)(m + 1) * ldv};
+    KrylovResult res;
+    fgmres_batch<double, double>(C, ops, n, ldv, m, tol, p.outer_maxit, 0, one, 0, bn, res);
+    // x = pi_R chi + chi'
+    Dp.pi_R(C->ox, Dp.t3, one);
+    vec_axpy<double>(n, cx<double>{1.0, 0.0}, Dp.chi1, Dp.t3, C->s);
+    // its true residual
+    Dp.dirac(Dp.t3, Dp.t1, one);
+    bvec_sub<double>(n, Dp.b0, Dp.t1, Dp.t2, n, 1, one.mask(), C->s);
+    const double rn = OuterOps<double>::norms64(C, n, Dp.t2, one)[0];
+    const double b0n = OuterOps<double>::norms64(C, n, Dp.b0, one)[0];
+    fine_export_vectors<double>(C->g0, 1, Dp.t3, xout, C->s);
+    HIPX(hipGetLastError());
+    sync(C);
+    if (st) {
+        memset(st, 0, sizeof *st);
+        st->outer_iters = (int)res.its[0];
+        st->restarts = res.restarts[0];
+        st->coarse_iters[1] = H.coarse_count[1][0];
+        st->true_relres = b0n > 0 ? rn / b0n : 0.0;
+        st->converged = res.conv[0] ? 1 : 0;
+        st->solve_s = now_s() - t0;
+    }
+    return res.conv[0] ? DD_OK : DD_ENOCONV;
+}
 
 // ---------------------------------------------------------------------------
 // Fixed staging memory of the allocation-free stencil entry point
@@ -1679,6 +1813,7 @@ static void configure_impl(dd_ctx* C, const dd_params* pin) {
     C->stream = dd_ctx::StreamSlots{};
     C->bicg_ws = nullptr;
     C->bicg_prec = 0;
+    C->id_ws = nullptr;
     C->p = p;
     // re-layout the fine fields if the SAP blocks differ from the current layout
     bool same = true;
@@ -1823,6 +1958,19 @@ dd_status dd_solve_bicgstab(dd_ctx* ctx, const double* b, double* x, double tol,
     if (precision != 32 && precision != 64) fail(DD_EINVAL, "precision must be 32 or 64");
     dd_status rc = (precision == 64) ? bicg_solve_impl<double>(ctx, b, x, tol, steps, st)
                                      : bicg_solve_impl<float>(ctx, b, x, tol, steps, st);
+    if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit";
+    return rc;
+    ABI_END(ctx)
+}
+
+dd_status dd_solve_id(dd_ctx* ctx, const double* b, double* x, double tol, int nu, double coarse_tol, dd_stats* st) {
+    ABI_TRY(ctx)
+    if (!ctx->have_setup) fail(DD_ESTATE, "dd_solve_id before dd_setup");
+    if (!ctx->H64 || ctx->H64->nlev != 2) fail(DD_ESTATE, "inexact deflation runs on an FP64 two-level setup");
+    if (ctx->stream.any()) fail(DD_ESTATE, "dd_solve_id while continuous-batching slots are in use");
+    if (!b || !x) fail(DD_EINVAL, "NULL vector");
+    if (!(tol > 0) || !(coarse_tol > 0) || nu < 1) fail(DD_EINVAL, "tolerances must be positive and nu >= 1");
+    dd_status rc = id_solve_impl(ctx, *ctx->H64, b, x, tol, nu, coarse_tol, st);
     if (rc == DD_ENOCONV) ctx->err = "outer FGMRES reached outer_maxit";
     return rc;
     ABI_END(ctx)
@@ -2295,6 +2443,20 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
             exp_(0, H.wb[0], out);
             break;
         }
+        case DD_OP_DEFLATED:
+            if constexpr (std::is_same<T, double>::value) {
+                if (l != 0 || k != 1) fail(DD_EINVAL, "the deflated operator acts on one fine vector (level 0)");
+                if (H.nlev != 2 || !C->have_setup) fail(DD_ESTATE, "the deflated operator needs a built two-level setup");
+                IdDefl Dp = IdDefl::make(C, &H, C->p.coarse_tol);
+                memset(H.coarse_count, 0, sizeof H.coarse_count);
+                fine_import_vectors<double>(C->g0, 1, in, Dp.b0, C->s);
+                Dp.deflated(Dp.b0, Dp.chi1, bt);
+                counts(1);
+                fine_export_vectors<double>(C->g0, 1, Dp.chi1, out, C->s);
+            } else {
+                fail(DD_ESTATE, "the deflated operator runs on an FP64 setup");
+            }
+            break;
         case DD_OP_FGMRES:
             if (l < 1 || l >= bottom) fail(DD_EINVAL, "middle-level FGMRES needs 1 <= level < levels-1");
             imp(l, in, H.rc[l]);

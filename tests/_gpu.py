@@ -27,7 +27,8 @@ def to_np(t):
 
 
 COMMON = ("levels", "n_tv", "agg", "sap", "mr_steps", "nu", "n_inv", "coarse_tol", "coarse_restart", "coarse_maxit",
-          "coarse_fixed", "mid_tol", "mid_restart", "mid_maxit", "mid_fixed", "outer_restart", "outer_maxit")
+          "coarse_fixed", "mid_tol", "mid_restart", "mid_maxit", "mid_fixed", "outer_restart", "outer_maxit",
+          "id_setup")
 
 
 class Pair:
