@@ -53,6 +53,19 @@ template <class T> __host__ __device__ __forceinline__ void cmacc(cx<T>& acc, cx
     acc.im = fmadd(-a.im, b.re, acc.im);
 }
 
+// FP16 storage of fine-level spinors with one FP32 scale per (parity,
+// chirality half, site): entry c (c < 6) of chirality half h (spins 2h, 2h+1)
+// at the site (p, i) is s[(2p + h) vh + i] * d[(12p + 6h + c) vh + i], the
+// layout of a cx<T> spinor set for d.  The scale is the largest modulus of
+// the half's 12 reals, so the stored values lie in [-1, 1].  An offset of
+// `off` complex entries (a multiple of 6 vh, e.g. one vector of 24 vh)
+// moves d by off and s by off / 6.
+struct hspin {
+    cx<_Float16>* d;
+    float* s;
+    __host__ __device__ __forceinline__ hspin operator+(long off) const { return hspin{d + off, s + off / 6}; }
+};
+
 // ---------------------------------------------------------------------------
 // lattice layout
 //

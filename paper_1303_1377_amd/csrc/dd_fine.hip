@@ -364,6 +364,42 @@ __device__ __forceinline__ void store_spinor(cx<T>* psi, int vh, int p, int i, c
     for (int c = 0; c < 12; c++) base[(size_t)c * vh] = v[c];
 }
 
+// chirality half h of the site (p, i) of an FP16 spinor set (see hspin)
+template <class T>
+__device__ __forceinline__ void half_load(const hspin& psi, int vh, int p, int h, int i, cx<T> v[6]) {
+    const float sc = psi.s[(size_t)(2 * p + h) * vh + i];
+    const cx<_Float16>* base = psi.d + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const cx<_Float16> q = base[(size_t)c * vh];
+        v[c] = {T((float)q.re * sc), T((float)q.im * sc)};
+    }
+}
+template <class T>
+__device__ __forceinline__ void half_store(const hspin& psi, int vh, int p, int h, int i, const cx<T> v[6]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) m = fmaxf(m, fmaxf(fabsf((float)v[c].re), fabsf((float)v[c].im)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    psi.s[(size_t)(2 * p + h) * vh + i] = m;
+    cx<_Float16>* base = psi.d + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+    for (int c = 0; c < 6; c++) base[(size_t)c * vh] = {(_Float16)((float)v[c].re * inv), (_Float16)((float)v[c].im * inv)};
+}
+template <class T>
+__device__ __forceinline__ void load_spinor(const hspin& psi, int vh, int p, int i, cx<T> v[12]) {
+    half_load(psi, vh, p, 0, i, v);
+    half_load(psi, vh, p, 1, i, v + 6);
+}
+template <class T>
+__device__ __forceinline__ void store_spinor(const hspin& psi, int vh, int p, int i, const cx<T> v[12]) {
+    half_store(psi, vh, p, 0, i, v);
+    half_store(psi, vh, p, 1, i, v + 6);
+}
+// a vector pointer with __restrict__ for plain spinor sets (FP16 sets are a struct)
+template <class VP> struct vrestrict { using type = VP; };
+template <class T> struct vrestrict<cx<T>*> { using type = cx<T>* __restrict__; };
+
 // out = A v with the packed clover blocks at (p, i) of array `cl`
 template <class T, class S>
 __device__ __forceinline__ void clover_apply(const S* __restrict__ cl, int vh, int p, int i, const cx<T> v[12], cx<T> out[12]) {
@@ -728,10 +764,10 @@ __device__ __forceinline__ void lds_store(cx<T>* buf, int bvh, int l, const cx<T
 // packs, for a hop inside the block, the LDS slot of the link (<< 8) and the
 // neighbour's local index; -1 marks a hop that leaves the block (its link is
 // read from memory).  The neighbour spinor comes from global memory psi.
-template <class T, class S>
+template <class T, class S, class VP>
 __device__ __forceinline__ void sap_hop(const FineOp<T, S>& op, int ltot, const cx<T>* __restrict__ L,
                                         const int* __restrict__ tab, int ntab, int k, int t, int p, int i,
-                                        const int x[4], int base, const cx<T>* __restrict__ psi, cx<T> acc[12]) {
+                                        const int x[4], int base, const VP& psi, cx<T> acc[12]) {
     const Geom& g = op.g;
     const int code = tab[k * ntab + t];
     const int mu = k & 3;
@@ -853,10 +889,9 @@ __device__ __forceinline__ void pair_hop(const cx<T>* __restrict__ L, int ltot, 
 
 // MINW: waves per SIMD the register allocation must allow (2 for FP32 fields,
 // so that two workgroups share a CU; FP64 needs the whole register file)
-template <class T, class S, int MINW = (sizeof(T) > 4 ? 1 : 2)>
-__global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const int* __restrict__ blocks,
-                                                  const cx<T>* __restrict__ b0, cx<T>* __restrict__ z0, int mr_steps,
-                                                  int nr, long ld, Mask mk) {
+template <class T, class S, class VP, int MINW = (sizeof(T) > 4 ? 1 : 2)>
+__global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const int* __restrict__ blocks, VP b0, VP z0,
+                                                  int mr_steps, int nr, long ld, Mask mk) {
     extern __shared__ char smem_raw[];
     const Geom g = op.g;
     const int bvh = g.bvh;
@@ -950,8 +985,8 @@ __global__ void __launch_bounds__(256, MINW) k_sap_fine(FineOp<T, S> op, const i
     };
     for (int rhs = 0; rhs < nr; rhs++) {
     if (!mk.on(rhs)) continue;
-    const cx<T>* __restrict__ b = b0 + rhs * ld;
-    cx<T>* __restrict__ z = z0 + rhs * ld;
+    const typename vrestrict<VP>::type b = b0 + rhs * ld;
+    const typename vrestrict<VP>::type z = z0 + rhs * ld;
     // half h of: e_o, rho (the odd MR residual), w, R
     cx<T> eo[6], rho[6], w[6], R[6];
     // ---- residual on the block, b - H z with all 8 hops of the lane's own site ----
@@ -1081,9 +1116,9 @@ size_t fine_sap_lds_bytes(const Geom& g) {
            3 * sizeof(double) * (nt / 64);
 }
 
-template <class T, class S>
-void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
-                   hipStream_t s, int nr, long ld, Mask mk) {
+template <class T, class S, class VP>
+static void sap_launch(const FineOp<T, S>& op, const int* blocks, int nblocks, VP b, VP z, int mr_steps, hipStream_t s,
+                       int nr, long ld, Mask mk) {
     if (nblocks <= 0) return;
     int nt = ((2 * op.g.bvh + 63) / 64) * 64;
     size_t lds = fine_sap_lds_bytes<T>(op.g);
@@ -1091,12 +1126,25 @@ void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const
     static size_t configured = 0;
     {
         std::lock_guard<std::mutex> lock(mu);
-        if (lds > 65536 && lds > configured) {
-            (void)hipFuncSetAttribute((const void*)k_sap_fine<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // a refusal leaves its error for the launch below to report
+        if (lds > 65536 && lds > configured &&
+            hipFuncSetAttribute((const void*)k_sap_fine<T, S, VP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) == hipSuccess)
             configured = lds;
-        }
     }
-    k_sap_fine<T, S><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
+    k_sap_fine<T, S, VP><<<nblocks, nt, lds, s>>>(op, blocks, b, z, mr_steps, nr, ld, mk);
+}
+
+template <class T, class S>
+void fine_sap_half(const FineOp<T, S>& op, const int* blocks, int nblocks, const cx<T>* b, cx<T>* z, int mr_steps,
+                   hipStream_t s, int nr, long ld, Mask mk) {
+    sap_launch<T, S, cx<T>*>(op, blocks, nblocks, const_cast<cx<T>*>(b), z, mr_steps, s, nr, ld, mk);
+}
+
+template <class S>
+void fine_sap_half_h(const FineOp<float, S>& op, const int* blocks, int nblocks, hspin b, hspin z, int mr_steps,
+                     hipStream_t s, int nr, long ld, Mask mk) {
+    sap_launch<float, S, hspin>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1121,12 +1169,11 @@ __device__ __forceinline__ void coarse_of(const AggMap& m, const int x[4], int x
 // out[k] for k < n: P^H in, 2N unknowns per coarse site (index h*N + k)
 // NT: the largest workgroup the build allows (one thread per aggregate site);
 // the 256-thread form keeps two test vectors' loads in flight without spilling
-template <class T, class S, int NT>
-__global__ void __launch_bounds__(NT) k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P,
-                                                      const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long ldi,
-                                                      long ldo, Mask mk) {
+template <class T, class S, int NT, class VI>
+__global__ void __launch_bounds__(NT) k_restrict_fine(AggMap m, int N, const cx<S>* __restrict__ P, VI in0,
+                                                      cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
     if (!mk.on(blockIdx.y)) return;
-    in += blockIdx.y * ldi;
+    const VI in = in0 + blockIdx.y * ldi;
     out += blockIdx.y * ldo;
     extern __shared__ char smem_raw[];
     cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);  // [nw][2N]
@@ -1185,14 +1232,14 @@ __global__ void __launch_bounds__(NT) k_restrict_fine(AggMap m, int N, const cx<
     }
 }
 
-template <class T, class S>
+template <class T, class S, class VO>
 __global__ void k_prolong_fine(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
-                               cx<T>* __restrict__ out, long ldi, long ldo, Mask mk) {
+                               VO out0, long ldi, long ldo, Mask mk) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int vh = m.f.vh;
     if (gid >= 2 * vh || !mk.on(blockIdx.y)) return;
     in += blockIdx.y * ldi;
-    out += blockIdx.y * ldo;
+    const VO out = out0 + blockIdx.y * ldo;
     int p = gid >= vh, i = gid - p * vh;
     int x[4], xc[4];
     cb_coords(m.f, p, i, x);
@@ -1219,10 +1266,9 @@ __global__ void k_prolong_fine(AggMap m, int N, const cx<S>* __restrict__ P, con
 // the bulk of the traffic).  Per RHS the sums are formed in the same order as
 // in the one-RHS kernels above.  Members of the group past the batch read the
 // first member's data and are never stored.
-template <class T, class S, int NT, int KR>
-__global__ void __launch_bounds__(NT) k_restrict_fine_k(AggMap m, int N, const cx<S>* __restrict__ P,
-                                                        const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                        long ldi, long ldo, int nr, Mask mk) {
+template <class T, class S, int NT, int KR, class VI>
+__global__ void __launch_bounds__(NT) k_restrict_fine_k(AggMap m, int N, const cx<S>* __restrict__ P, VI in,
+                                                        cx<T>* __restrict__ out, long ldi, long ldo, int nr, Mask mk) {
     const int q0 = blockIdx.y * KR;
     bool on[KR];
     bool any = false;
@@ -1290,9 +1336,9 @@ __global__ void __launch_bounds__(NT) k_restrict_fine_k(AggMap m, int N, const c
     }
 }
 
-template <class T, class S, int KR>
+template <class T, class S, int KR, class VO>
 __global__ void __launch_bounds__(256) k_prolong_fine_k(AggMap m, int N, const cx<S>* __restrict__ P, const cx<T>* __restrict__ in,
-                                 cx<T>* __restrict__ out, long ldi, long ldo, int nr, Mask mk) {
+                                 VO out, long ldi, long ldo, int nr, Mask mk) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int vh = m.f.vh;
     if (gid >= 2 * vh) return;
@@ -1342,9 +1388,9 @@ template <class T> static int transfer_group(int nr) {
     return nr >= cap ? cap : (nr >= 2 ? 2 : 1);
 }
 
-template <class T, class S>
-void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
-                   long ldi, long ldo, Mask mk) {
+template <class T, class S, class VI>
+static void restrict_launch(const AggMap& m, int N, const cx<S>* P, VI in, cx<T>* out, hipStream_t s, int nr,
+                            long ldi, long ldo, Mask mk) {
     int nt = ((m.asz + 63) / 64) * 64;
     // split the test vectors over workgroups until about 1024 stream P
     const int ks = std::max(1, std::min(N, (1024 + 2 * m.c.vh - 1) / (2 * m.c.vh)));
@@ -1352,35 +1398,127 @@ void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T
     if (kr == 1 || nt > 256) {
         size_t lds = sizeof(cx<double>) * 2 * N * (nt / 64);
         dim3 grid(2 * m.c.vh, nr, ks);
-        if (nt <= 256) k_restrict_fine<T, S, 256><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
-        else k_restrict_fine<T, S, 1024><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        if (nt <= 256) k_restrict_fine<T, S, 256, VI><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        else k_restrict_fine<T, S, 1024, VI><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, mk);
         return;
     }
     size_t lds = sizeof(cx<double>) * kr * 2 * N * (nt / 64);
     dim3 grid(2 * m.c.vh, (nr + kr - 1) / kr, ks);
     if constexpr (sizeof(T) == 4)
         if (kr == 4) {
-            k_restrict_fine_k<T, S, 256, 4><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+            k_restrict_fine_k<T, S, 256, 4, VI><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
             return;
         }
-    k_restrict_fine_k<T, S, 256, 2><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+    k_restrict_fine_k<T, S, 256, 2, VI><<<grid, nt, lds, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
 }
-template <class T, class S>
-void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
-                  long ldi, long ldo, Mask mk) {
+template <class T, class S, class VO>
+static void prolong_launch(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, VO out, hipStream_t s, int nr,
+                           long ldi, long ldo, Mask mk) {
     const int kr = transfer_group<T>(nr);
     if (kr == 1) {
         dim3 grid(nblk_of(2L * m.f.vh, 256), nr);
-        k_prolong_fine<T, S><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
+        k_prolong_fine<T, S, VO><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, mk);
         return;
     }
     dim3 grid(nblk_of(2L * m.f.vh, 256), (nr + kr - 1) / kr);
     if constexpr (sizeof(T) == 4)
         if (kr == 4) {
-            k_prolong_fine_k<T, S, 4><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+            k_prolong_fine_k<T, S, 4, VO><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
             return;
         }
-    k_prolong_fine_k<T, S, 2><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+    k_prolong_fine_k<T, S, 2, VO><<<grid, 256, 0, s>>>(m, N, P, in, out, ldi, ldo, nr, mk);
+}
+
+template <class T, class S>
+void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+                   long ldi, long ldo, Mask mk) {
+    restrict_launch<T, S, const cx<T>*>(m, N, P, in, out, s, nr, ldi, ldo, mk);
+}
+template <class T, class S>
+void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr,
+                  long ldi, long ldo, Mask mk) {
+    prolong_launch<T, S, cx<T>*>(m, N, P, in, out, s, nr, ldi, ldo, mk);
+}
+template <class S>
+void fine_restrict_h(const AggMap& m, int N, const cx<S>* P, hspin in, cx<float>* out, hipStream_t s, int nr, long ldi,
+                     long ldo, Mask mk) {
+    restrict_launch<float, S, hspin>(m, N, P, in, out, s, nr, ldi, ldo, mk);
+}
+template <class S>
+void fine_prolong_h(const AggMap& m, int N, const cx<S>* P, const cx<float>* in, hspin out, hipStream_t s, int nr,
+                    long ldi, long ldo, Mask mk) {
+    prolong_launch<float, S, hspin>(m, N, P, in, out, s, nr, ldi, ldo, mk);
+}
+
+// ---------------------------------------------------------------------------
+// FP16 spinor sets (hspin): conversion from and to FP64 / FP32 sets and the
+// FGMRES update x += sum_j y_j Z_j, one thread per (parity, chirality half,
+// site) -- the thread index is the scale's index
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void k_hpack(int vh, const cx<S>* __restrict__ in, hspin out, long ld, Mask mk) {
+    const long gid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (gid >= 4L * vh || !mk.on(blockIdx.y)) return;
+    const int ph = (int)(gid / vh), i = (int)(gid - (long)ph * vh);
+    const int p = ph >> 1, h = ph & 1;
+    const cx<S>* src = in + blockIdx.y * ld + (size_t)(p * 12 + 6 * h) * vh + i;
+    cx<float> v[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) v[c] = ccast<float>(src[(size_t)c * vh]);
+    half_store(out + blockIdx.y * ld, vh, p, h, i, v);
+}
+template <class D>
+__global__ void k_hunpack(int vh, hspin in, cx<D>* __restrict__ out, long ld, Mask mk) {
+    const long gid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (gid >= 4L * vh || !mk.on(blockIdx.y)) return;
+    const int ph = (int)(gid / vh), i = (int)(gid - (long)ph * vh);
+    const int p = ph >> 1, h = ph & 1;
+    cx<float> v[6];
+    half_load(in + blockIdx.y * ld, vh, p, h, i, v);
+    cx<D>* dst = out + blockIdx.y * ld + (size_t)(p * 12 + 6 * h) * vh + i;
+#pragma unroll
+    for (int c = 0; c < 6; c++) dst[(size_t)c * vh] = ccast<D>(v[c]);
+}
+__global__ void k_hlincomb(int vh, Counts mc, hspin Z, long ldz, const cx<double>* __restrict__ y,
+                           cx<double>* __restrict__ x, long ldzr, int ystride, long ldx, Mask mk) {
+    const long gid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (gid >= 4L * vh || !mk.on(blockIdx.y)) return;
+    const int ph = (int)(gid / vh), i = (int)(gid - (long)ph * vh);
+    const int p = ph >> 1, h = ph & 1;
+    const int m = mc.v[blockIdx.y];
+    const hspin z = Z + blockIdx.y * ldzr;
+    y += (size_t)blockIdx.y * ystride;
+    cx<double>* xp = x + blockIdx.y * ldx + (size_t)(p * 12 + 6 * h) * vh + i;
+    cx<double> acc[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) acc[c] = xp[(size_t)c * vh];
+    for (int j = 0; j < m; j++) {
+        cx<float> v[6];
+        half_load(z + (long)j * ldz, vh, p, h, i, v);
+        const cx<double> yj = y[j];
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[c] += yj * ccast<double>(v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) xp[(size_t)c * vh] = acc[c];
+}
+
+template <class S>
+void fine_hpack(int vh, const cx<S>* in, hspin out, long ld, int nr, Mask mk, hipStream_t s) {
+    dim3 grid(nblk_of(4L * vh, 256), nr);
+    k_hpack<S><<<grid, 256, 0, s>>>(vh, in, out, ld, mk);
+}
+template <class D>
+void fine_hunpack(int vh, hspin in, cx<D>* out, long ld, int nr, Mask mk, hipStream_t s) {
+    dim3 grid(nblk_of(4L * vh, 256), nr);
+    k_hunpack<D><<<grid, 256, 0, s>>>(vh, in, out, ld, mk);
+}
+void fine_hlincomb(int vh, int m, hspin Z, long ldz, const cx<double>* y, cx<double>* x, hipStream_t s, int nr,
+                   long ldzr, int ystride, long ldx, Mask mk, const Counts* per) {
+    Counts mc;
+    for (int r = 0; r < MAX_RHS; r++) mc.v[r] = (per && r < nr) ? std::min(per->v[r], m) : m;
+    dim3 grid(nblk_of(4L * vh, 256), nr);
+    k_hlincomb<<<grid, 256, 0, s>>>(vh, mc, Z, ldz, y, x, ldzr, ystride, ldx, mk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1669,5 +1807,20 @@ void fine_random(const Geom& g, int n, unsigned long long seed, int sid, cx<T>* 
 DD_FINE_INST(double)
 DD_FINE_INST(float)
 DD_FINE_OP_INST(float, _Float16)
+
+// FP16 spinor sets (FP32 arithmetic) with FP32 or FP16 operator storage
+#define DD_FINE_H_INST(S)                                                                                     \
+    template void fine_sap_half_h<S>(const FineOp<float, S>&, const int*, int, hspin, hspin, int, hipStream_t, \
+                                     int, long, Mask);                                                        \
+    template void fine_restrict_h<S>(const AggMap&, int, const cx<S>*, hspin, cx<float>*, hipStream_t, int, long, \
+                                     long, Mask);                                                             \
+    template void fine_prolong_h<S>(const AggMap&, int, const cx<S>*, const cx<float>*, hspin, hipStream_t, int, \
+                                    long, long, Mask);
+DD_FINE_H_INST(float)
+DD_FINE_H_INST(_Float16)
+template void fine_hpack<double>(int, const cx<double>*, hspin, long, int, Mask, hipStream_t);
+template void fine_hpack<float>(int, const cx<float>*, hspin, long, int, Mask, hipStream_t);
+template void fine_hunpack<double>(int, hspin, cx<double>*, long, int, Mask, hipStream_t);
+template void fine_hunpack<float>(int, hspin, cx<float>*, long, int, Mask, hipStream_t);
 
 }  // namespace dd

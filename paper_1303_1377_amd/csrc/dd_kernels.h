@@ -123,6 +123,22 @@ void fine_restrict(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T
 template <class T, class S>
 void fine_prolong(const AggMap& m, int N, const cx<S>* P, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1,
                   long ldi = 0, long ldo = 0, Mask mk = all_rhs());
+// the same three on FP16 spinor sets (hspin; offsets as for cx<T> sets)
+template <class S>
+void fine_sap_half_h(const FineOp<float, S>& op, const int* blocks, int nblocks, hspin b, hspin z, int mr_steps,
+                     hipStream_t s, int nr, long ld, Mask mk);
+template <class S>
+void fine_restrict_h(const AggMap& m, int N, const cx<S>* P, hspin in, cx<float>* out, hipStream_t s, int nr, long ldi,
+                     long ldo, Mask mk);
+template <class S>
+void fine_prolong_h(const AggMap& m, int N, const cx<S>* P, const cx<float>* in, hspin out, hipStream_t s, int nr,
+                    long ldi, long ldo, Mask mk);
+// FP16 spinor sets to and from FP64 / FP32 sets (nr vectors at stride ld) and
+// x += sum_{j < m_r} y_r[j] Z_j for RHS r (Z_j of RHS r at Z + j ldz + r ldzr)
+template <class S> void fine_hpack(int vh, const cx<S>* in, hspin out, long ld, int nr, Mask mk, hipStream_t s);
+template <class D> void fine_hunpack(int vh, hspin in, cx<D>* out, long ld, int nr, Mask mk, hipStream_t s);
+void fine_hlincomb(int vh, int m, hspin Z, long ldz, const cx<double>* y, cx<double>* x, hipStream_t s, int nr,
+                   long ldzr, int ystride, long ldx, Mask mk, const Counts* per);
 template <class T>
 void fine_gram_schmidt(const AggMap& m, int N, const cx<T>* tv, cx<T>* P, int* bad, hipStream_t s);
 template <class T>

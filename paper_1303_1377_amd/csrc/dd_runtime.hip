@@ -462,6 +462,12 @@ struct Hier {
     double osz() const { return half ? 2.0 : (double)sizeof(T); }
     double by_dirac(int k) const { return 2.0 * g[0].vh * (144 * osz() + 48.0 * k * sizeof(T)); }
     double by_sap_half(int k) const { return 1.0 * g[0].vh * (144 * osz() + 144.0 * k * sizeof(T)); }
+    // FP16 spinor sets: 2 bytes per real and one 4-byte scale per 12 reals
+    static constexpr double HSZ = 2.0 + 4.0 / 12.0;
+    double by_sap_half_h(int k) const { return 1.0 * g[0].vh * (144 * osz() + 144.0 * k * HSZ); }
+    double by_transfer_h(int k) const {
+        return (double)nlv(0) * N[0] * 2 * osz() + (double)k * nlv(0) * 2 * HSZ + (double)k * nlv(1) * 2 * sizeof(T);
+    }
     double by_coarse(int l, int nblk_per_site, int nvec_per_site, bool all_sites, int k) const {
         double sites = all_sites ? 2.0 * g[l].vh : 1.0 * g[l].vh;
         return sites * ((double)nblk_per_site * nd[l] * nd[l] * 2 * osz() + (double)k * nvec_per_site * nd[l] * 2 * sizeof(T));
@@ -505,6 +511,16 @@ struct Hier {
     void gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt);
     void fgmres_mid(int l, int bottom, const cx<T>* r, cx<T>* e, const Batch& bt);
     void vcycle(int l, int bottom, const cx<T>* r, cx<T>* z, const Batch& bt);
+    // the fine level of the V-cycle on FP16 spinor sets (precision 16)
+    void sap(int l, hspin b, hspin z, int nsweeps, bool zero_start, const Batch& bt);
+    void restrict_(int l, hspin in, cx<T>* out, const Batch& bt);
+    void prolong(int l, const cx<T>* in, hspin out, const Batch& bt);
+    void vcycle(int l, int bottom, hspin r, hspin z, const Batch& bt);
+    // an FP16 spinor set of R fine vectors in the memory of a level-0 scratch set
+    hspin as_h(cx<T>* buf) const {
+        cx<_Float16>* d = reinterpret_cast<cx<_Float16>*>(buf);
+        return hspin{d, reinterpret_cast<float*>(d + (size_t)R * nlv(0))};
+    }
     void build(int l);
     void setup_level(int l, bool given);
     double norm1(long n, const cx<T>* v) { return norms(n, v, 0, single(C))[0]; }
@@ -1211,6 +1227,64 @@ void Hier<T>::vcycle(int l, int bottom, const cx<T>* r, cx<T>* z, const Batch& b
 }
 
 // ---------------------------------------------------------------------------
+// the fine level on FP16 spinor sets (precision 16): the vectors the V-cycle
+// reads and writes there (its input r, the interpolated and smoothed z) are
+// stored in FP16 with a scale per site and chirality half; arithmetic stays
+// FP32 and the coarse levels keep FP32 vectors
+// ---------------------------------------------------------------------------
+template <class T>
+void Hier<T>::sap(int l, hspin b, hspin z, int nsweeps, bool zero_start, const Batch& bt) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (l != 0 || !half) fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+        if (zero_start) {
+            HIPX(hipMemsetAsync(z.d, 0, sizeof(cx<_Float16>) * nlv(0) * bt.nr, C->s));
+            HIPX(hipMemsetAsync(z.s, 0, sizeof(float) * nlv(0) / 6 * bt.nr, C->s));
+        }
+        for (int sw = 0; sw < nsweeps; sw++)
+            for (int c = 0; c < 2; c++) {
+                Prof pr(C, DD_K_SAP, by_sap_half_h(bt.count()));
+                with_fine([&](auto& op) {
+                    fine_sap_half_h(op, blocks[0][c], nblocks[0][c], b, z, C->p.mr_steps[0], C->s, bt.nr, nlv(0),
+                                    bt.mask());
+                });
+            }
+    } else {
+        fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+    }
+}
+
+template <class T>
+void Hier<T>::restrict_(int l, hspin in, cx<T>* out, const Batch& bt) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (l != 0 || !half) fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+        Prof pr(C, DD_K_RESTRICT, by_transfer_h(bt.count()));
+        with_P(0, [&](auto* Pl) { fine_restrict_h(amap[0], N[0], Pl, in, out, C->s, bt.nr, nlv(0), nlv(1), bt.mask()); });
+    } else {
+        fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+    }
+}
+
+template <class T>
+void Hier<T>::prolong(int l, const cx<T>* in, hspin out, const Batch& bt) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (l != 0 || !half) fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+        Prof pr(C, DD_K_PROLONG, by_transfer_h(bt.count()));
+        with_P(0, [&](auto* Pl) { fine_prolong_h(amap[0], N[0], Pl, in, out, C->s, bt.nr, nlv(1), nlv(0), bt.mask()); });
+    } else {
+        fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
+    }
+}
+
+template <class T>
+void Hier<T>::vcycle(int l, int bottom, hspin r, hspin z, const Batch& bt) {
+    restrict_(l, r, rc[l + 1], bt);
+    if (l + 1 == bottom) gmres_oe(l + 1, rc[l + 1], ec[l + 1], bt);
+    else fgmres_mid(l + 1, bottom, rc[l + 1], ec[l + 1], bt);
+    prolong(l, ec[l + 1], z, bt);
+    sap(l, r, z, C->p.nu, false, bt);
+}
+
+// ---------------------------------------------------------------------------
 // P, D_c and self-block inverses from the current test vectors of level l
 // ---------------------------------------------------------------------------
 template <class T>
@@ -1344,6 +1418,71 @@ struct OuterOps {
     }
 };
 
+// The outer FGMRES of precision 16: its preconditioned vectors Z and the
+// V-cycle's input are FP16 spinor sets.  Z's data fill the first 4 m ldv
+// bytes of the Z area of the workspace and its scales follow; the input
+// lives in the first half of C->ot.
+struct OuterOpsH {
+    dd_ctx* C;
+    Hier<float>* H;
+    const cx<double>* b;
+    cx<double>* x;
+    long n;
+    int m;
+    cx<_Float16>* Zb;
+    float* Zs;
+    cx<double>* V() { return C->oV; }
+    cx<_Float16>* Z() { return Zb; }
+    hspin zh(const cx<_Float16>* z) const { return hspin{const_cast<cx<_Float16>*>(z), Zs + (z - Zb) / 6}; }
+    hspin vT() {
+        cx<_Float16>* d = reinterpret_cast<cx<_Float16>*>(C->ot);
+        return hspin{d, reinterpret_cast<float*>(d + (size_t)C->R * n)};
+    }
+    cx<double>* t64() { return C->ot + (size_t)C->R * n; }
+    int vh() const { return (int)(n / 24); }
+    void precond(const cx<double>* v, cx<_Float16>* z, const Batch& bt) {
+        {
+            Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * Hier<float>::HSZ));
+            fine_hpack<double>(vh(), v, vT(), n, bt.nr, bt.mask(), C->s);
+        }
+        H->vcycle(0, H->nlev - 1, vT(), zh(z), bt);
+    }
+    void matvec(const cx<_Float16>* z, cx<double>* w, const Batch& bt) {
+        {
+            Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * Hier<float>::HSZ));
+            fine_hunpack<double>(vh(), zh(z), t64(), n, bt.nr, bt.mask(), C->s);
+        }
+        Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
+        fine_dirac<double>(fine_op<double>(C), t64(), w, C->s, bt.nr, n, bt.mask());
+    }
+    void update(int mm, const cx<_Float16>* Z, long ldz, const cx<double>* y, const Batch& bt, const Counts& jc) {
+        fine_hlincomb(vh(), mm, zh(Z), ldz, y, x, C->s, bt.nr, n, 32, n, bt.mask(), &jc);
+    }
+    void residual(const Batch& bt) {
+        fine_dirac<double>(fine_op<double>(C), x, t64(), C->s, bt.nr, n, bt.mask());
+        bvec_sub<double>(n, b, t64(), C->oV, n, bt.nr, bt.mask(), C->s);
+    }
+    std::vector<double> norms(const cx<double>* v, const Batch& bt) { return OuterOps<float>::norms64(C, n, v, bt); }
+};
+
+// run f(ops, ZS*) with the outer FGMRES operations of the hierarchy (ZS: the
+// element type of the preconditioned vectors)
+template <class T, class F>
+static void with_outer_ops(dd_ctx* C, Hier<T>& H, F&& f) {
+    const int m = C->p.outer_restart;
+    const long n = 24L * C->g0.vh, ldv = (long)C->R * n;
+    if constexpr (std::is_same<T, float>::value) {
+        if (H.half) {
+            cx<_Float16>* Zb = reinterpret_cast<cx<_Float16>*>(C->oV + (size_t)(m + 1) * ldv);
+            OuterOpsH ops{C, &H, C->ob, C->ox, n, m, Zb, reinterpret_cast<float*>(Zb + (size_t)m * ldv)};
+            f(ops, (_Float16*)nullptr);
+            return;
+        }
+    }
+    OuterOps<T> ops{C, &H, C->ob, C->ox, n, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
+    f(ops, (T*)nullptr);
+}
+
 // Solve the nr right-hand sides at C->ob into C->ox.
 template <class T>
 static void outer_fgmres(dd_ctx* C, Hier<T>& H, int nr, double tol, long fixed, dd_stats* st, dd_status* rc) {
@@ -1359,9 +1498,11 @@ static void outer_fgmres(dd_ctx* C, Hier<T>& H, int nr, double tol, long fixed, 
     Batch all{nr, C->dflags + DI_ONES, (nr >= 32) ? ~0u : ((1u << nr) - 1)};
     std::vector<double> bn = OuterOps<T>::norms64(C, n, C->ob, all);
     HIPX(hipMemcpyAsync(C->oV, C->ob, sizeof(cx<double>) * n * nr, hipMemcpyDeviceToDevice, C->s));
-    OuterOps<T> ops{C, &H, C->ob, C->ox, n, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
     KrylovResult res;
-    fgmres_batch<double, T>(C, ops, n, ldv, m, tol, p.outer_maxit, fixed, all, 0, bn, res);
+    with_outer_ops(C, H, [&](auto& ops, auto* zs) {
+        using ZS = std::remove_pointer_t<decltype(zs)>;
+        fgmres_batch<double, ZS>(C, ops, n, ldv, m, tol, p.outer_maxit, fixed, all, 0, bn, res);
+    });
     for (int r = 0; r < nr; r++) {
         rc[r] = res.conv[r] ? DD_OK : DD_ENOCONV;
         if (!st) continue;
@@ -2031,9 +2172,11 @@ static void stream_cycle_impl(dd_ctx* C, Hier<T>& H, int* state, dd_stats* st) {
     if (cyc) {
         const double t0 = now_s();
         Batch all{R, C->dflags + DI_ONES, (R >= 32) ? ~0u : ((1u << R) - 1)};
-        OuterOps<T> ops{C, &H, C->ob, C->ox, n, reinterpret_cast<cx<T>*>(C->oV + (size_t)(m + 1) * ldv)};
-        fgmres_cycle<double, T>(C, ops, n, ldv, m, S.tol, p.outer_maxit, 0, all, 0, cyc, S.hs, S.beta, S.bnorm,
-                                S.its);
+        with_outer_ops(C, H, [&](auto& ops, auto* zs) {
+            using ZS = std::remove_pointer_t<decltype(zs)>;
+            fgmres_cycle<double, ZS>(C, ops, n, ldv, m, S.tol, p.outer_maxit, 0, all, 0, cyc, S.hs, S.beta, S.bnorm,
+                                     S.its);
+        });
         sync(C);
         (void)t0;
         for (int r = 0; r < R; r++) {
@@ -2370,6 +2513,11 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
     };
     const int bottom = H.nlev - 1;
     const Batch bt{k, C->dflags + DI_ONES, (1u << k) - 1};
+    // precision 16: the fine-level V-cycle components run on FP16 spinor sets,
+    // as in the solve (packed from and unpacked to the FP32 staging sets)
+    const bool h16 = H.half && l == 0;
+    auto pack = [&](const cx<T>* src, hspin dst) { fine_hpack<T>(H.g[0].vh, src, dst, H.nlv(0), k, bt.mask(), C->s); };
+    auto unpack = [&](hspin src, cx<T>* dst) { fine_hunpack<T>(H.g[0].vh, src, dst, H.nlv(0), k, bt.mask(), C->s); };
     switch (op) {
         case DD_OP_D:
             if (l == 0) {
@@ -2393,7 +2541,13 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
         case DD_OP_SAP:
             if (l >= bottom) fail(DD_EINVAL, "no SAP on the coarsest level");
             imp(l, in, H.wa[l]);
-            H.sap(l, H.wa[l], H.wb[l], arg, true, bt);
+            if (h16) {
+                pack(H.wa[0], H.as_h(H.wb[0]));
+                H.sap(0, H.as_h(H.wb[0]), H.as_h(H.wc[0]), arg, true, bt);
+                unpack(H.as_h(H.wc[0]), H.wb[0]);
+            } else {
+                H.sap(l, H.wa[l], H.wb[l], arg, true, bt);
+            }
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_VCYCLE:
@@ -2401,20 +2555,36 @@ static void apply_impl(dd_ctx* C, Hier<T>& H, int op, int l, int arg, int k, con
             if (!C->have_setup) fail(DD_ESTATE, "hierarchy not built");
             imp(l, in, H.wa[l]);
             memset(H.coarse_count, 0, sizeof H.coarse_count);
-            H.vcycle(l, bottom, H.wa[l], H.wb[l], bt);
+            if (h16) {
+                pack(H.wa[0], H.as_h(H.wb[0]));
+                H.vcycle(0, bottom, H.as_h(H.wb[0]), H.as_h(H.wc[0]), bt);
+                unpack(H.as_h(H.wc[0]), H.wb[0]);
+            } else {
+                H.vcycle(l, bottom, H.wa[l], H.wb[l], bt);
+            }
             counts(l + 1);
             exp_(l, H.wb[l], out);
             break;
         case DD_OP_RESTRICT:
             if (l >= bottom) fail(DD_EINVAL, "no restriction from the coarsest level");
             imp(l, in, H.wa[l]);
-            H.restrict_(l, H.wa[l], H.wa[l + 1], bt);
+            if (h16) {
+                pack(H.wa[0], H.as_h(H.wb[0]));
+                H.restrict_(0, H.as_h(H.wb[0]), H.wa[1], bt);
+            } else {
+                H.restrict_(l, H.wa[l], H.wa[l + 1], bt);
+            }
             exp_(l + 1, H.wa[l + 1], out);
             break;
         case DD_OP_PROLONG:
             if (l >= bottom) fail(DD_EINVAL, "no prolongation to the coarsest level");
             imp(l + 1, in, H.wa[l + 1]);
-            H.prolong(l, H.wa[l + 1], H.wa[l], bt);
+            if (h16) {
+                H.prolong(0, H.wa[1], H.as_h(H.wc[0]), bt);
+                unpack(H.as_h(H.wc[0]), H.wa[0]);
+            } else {
+                H.prolong(l, H.wa[l + 1], H.wa[l], bt);
+            }
             exp_(l, H.wa[l], out);
             break;
         case DD_OP_COARSE_SOLVE:
