@@ -260,14 +260,44 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     }
     __syncthreads();
     const int ns = nself + (hop_sign != 0 ? 8 : 0);
-    // stage X_s: entry (s, c, j), c fastest so each RHS column is read contiguously
-    for (int e = t; e < ns * 16 * ndk; e += nt) {
-        const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
-        const int j = rem / ndk, c = rem - j * ndk;
-        cx<float> v = czero<float>();
-        if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
-        Xre[(sl * ndk + c) * 16 + j] = S(v.re);
-        Xim[(sl * ndk + c) * 16 + j] = S(v.im);
+    // stage X_s: entry (s, c, j), c fastest so each RHS column is read contiguously.
+    // FP16 form: column j of every X_s is divided by sc[j], the largest modulus
+    // of the column's reals over the 9 slots (a first pass over the inputs
+    // finds it), so that the rounded inputs lie in [-1, 1] whatever the
+    // vector's magnitude; the products are scaled back in FP32.
+    constexpr bool F16 = std::is_same<S, _Float16>::value;
+    __shared__ float sc[16];
+    if constexpr (F16) {
+        if (t < 16) sc[t] = 0.f;
+        __syncthreads();
+        for (int e = t; e < ns * 16 * ndk; e += nt) {
+            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+            const int j = rem / ndk, c = rem - j * ndk;
+            if (c < nd && j < nr && mk.on(j)) {
+                const cx<float> v = vin[sl][(size_t)j * ld + c];
+                const float m = fmaxf(fabsf(v.re), fabsf(v.im));
+                if (m > 0.f) atomicMax(reinterpret_cast<int*>(sc) + j, __float_as_int(m));
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < ns * 16 * ndk; e += nt) {
+            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+            const int j = rem / ndk, c = rem - j * ndk;
+            cx<float> v = czero<float>();
+            if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
+            const float inv = sc[j] > 0.f ? 1.f / sc[j] : 0.f;
+            Xre[(sl * ndk + c) * 16 + j] = S(v.re * inv);
+            Xim[(sl * ndk + c) * 16 + j] = S(v.im * inv);
+        }
+    } else {
+        for (int e = t; e < ns * 16 * ndk; e += nt) {
+            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+            const int j = rem / ndk, c = rem - j * ndk;
+            cx<float> v = czero<float>();
+            if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
+            Xre[(sl * ndk + c) * 16 + j] = S(v.re);
+            Xim[(sl * ndk + c) * 16 + j] = S(v.im);
+        }
     }
     __syncthreads();
     const int w = t >> 6, lane = t & 63;
@@ -283,6 +313,13 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     // result rows 16w + 4q + v, column j
     const int q = lane >> 4, j = lane & 15;
     const bool jon = j < nr && mk.on(j);
+    if constexpr (F16) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            cre[v] *= sc[j];
+            cim[v] *= sc[j];
+        }
+    }
     if (self_mode == CS_IDENT && w < ntile && jon) {
 #pragma unroll
         for (int v = 0; v < 4; v++) {
@@ -305,19 +342,33 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
         return;
     }
     // post multiplication by the self-block inverse: stage the result as a new X
+    // (FP16 form: scaled per column as above)
     __syncthreads();
     for (int e = t; e < ndk * 16; e += nt) {   // clear (padding rows stay zero)
         Xre[e] = S(0.f);
         Xim[e] = S(0.f);
     }
+    if constexpr (F16) {
+        if (t < 16) sc[t] = 0.f;
+        __syncthreads();
+        if (w < ntile) {
+            float m = 0.f;
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                if (16 * w + 4 * q + v < nd) m = fmaxf(m, fmaxf(fabsf(cre[v]), fabsf(cim[v])));
+            if (m > 0.f) atomicMax(reinterpret_cast<int*>(sc) + j, __float_as_int(m));
+        }
+    }
     __syncthreads();
+    float inv = 1.f;
+    if constexpr (F16) inv = sc[j] > 0.f ? 1.f / sc[j] : 0.f;
     if (w < ntile) {
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int row = 16 * w + 4 * q + v;
             if (row < nd) {
-                Xre[row * 16 + j] = S(cre[v]);
-                Xim[row * 16 + j] = S(cim[v]);
+                Xre[row * 16 + j] = S(cre[v] * inv);
+                Xim[row * 16 + j] = S(cim[v] * inv);
             }
         }
     }
@@ -325,6 +376,13 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     if (w < ntile) {
         f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
         tile_mma<S>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, dre, dim);
+        if constexpr (F16) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                dre[v] *= sc[j];
+                dim[v] *= sc[j];
+            }
+        }
         if (jon) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {

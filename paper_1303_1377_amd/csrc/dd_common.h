@@ -53,18 +53,20 @@ template <class T> __host__ __device__ __forceinline__ void cmacc(cx<T>& acc, cx
     acc.im = fmadd(-a.im, b.re, acc.im);
 }
 
-// FP16 storage of fine-level spinors with one FP32 scale per (parity,
-// chirality half, site): entry c (c < 6) of chirality half h (spins 2h, 2h+1)
-// at the site (p, i) is s[(2p + h) vh + i] * d[(12p + 6h + c) vh + i], the
-// layout of a cx<T> spinor set for d.  The scale is the largest modulus of
-// the half's 12 reals, so the stored values lie in [-1, 1].  An offset of
-// `off` complex entries (a multiple of 6 vh, e.g. one vector of 24 vh)
-// moves d by off and s by off / 6.
+// FP16 storage of fine-level spinor sets with one FP32 scale per (parity,
+// chirality half, site).  Per site and half (p, h) seven 4-byte slots at
+// d[((2p + h) 7 + c) vh + i]: for c < 6 the entry 6h + c of the spinor
+// (real and imaginary part in FP16, divided by the scale), for c = 6 the
+// scale itself (FP32 bits: the largest modulus of the half's 12 reals, so the
+// stored values lie in [-1, 1]).  A set of n = 24 vh complex entries takes
+// 28 vh slots; an offset of `off` complex entries (a multiple of 6 vh, e.g.
+// one vector) is 7 off / 6 slots.
+typedef _Float16 hpair __attribute__((ext_vector_type(2)));
 struct hspin {
-    cx<_Float16>* d;
-    float* s;
-    __host__ __device__ __forceinline__ hspin operator+(long off) const { return hspin{d + off, s + off / 6}; }
+    hpair* d;
+    __host__ __device__ __forceinline__ hspin operator+(long off) const { return hspin{d + off / 6 * 7}; }
 };
+
 
 // ---------------------------------------------------------------------------
 // lattice layout

@@ -367,12 +367,12 @@ __device__ __forceinline__ void store_spinor(cx<T>* psi, int vh, int p, int i, c
 // chirality half h of the site (p, i) of an FP16 spinor set (see hspin)
 template <class T>
 __device__ __forceinline__ void half_load(const hspin& psi, int vh, int p, int h, int i, cx<T> v[6]) {
-    const float sc = psi.s[(size_t)(2 * p + h) * vh + i];
-    const cx<_Float16>* base = psi.d + (size_t)(p * 12 + 6 * h) * vh + i;
+    const hpair* base = psi.d + (size_t)((2 * p + h) * 7) * vh + i;
+    const float sc = __builtin_bit_cast(float, base[(size_t)6 * vh]);
 #pragma unroll
     for (int c = 0; c < 6; c++) {
-        const cx<_Float16> q = base[(size_t)c * vh];
-        v[c] = {T((float)q.re * sc), T((float)q.im * sc)};
+        const hpair q = base[(size_t)c * vh];
+        v[c] = {T((float)q.x * sc), T((float)q.y * sc)};
     }
 }
 template <class T>
@@ -381,10 +381,15 @@ __device__ __forceinline__ void half_store(const hspin& psi, int vh, int p, int 
 #pragma unroll
     for (int c = 0; c < 6; c++) m = fmaxf(m, fmaxf(fabsf((float)v[c].re), fabsf((float)v[c].im)));
     const float inv = m > 0.f ? 1.f / m : 0.f;
-    psi.s[(size_t)(2 * p + h) * vh + i] = m;
-    cx<_Float16>* base = psi.d + (size_t)(p * 12 + 6 * h) * vh + i;
+    hpair* base = psi.d + (size_t)((2 * p + h) * 7) * vh + i;
 #pragma unroll
-    for (int c = 0; c < 6; c++) base[(size_t)c * vh] = {(_Float16)((float)v[c].re * inv), (_Float16)((float)v[c].im * inv)};
+    for (int c = 0; c < 6; c++) {
+        hpair q;
+        q.x = (_Float16)((float)v[c].re * inv);
+        q.y = (_Float16)((float)v[c].im * inv);
+        base[(size_t)c * vh] = q;
+    }
+    base[(size_t)6 * vh] = __builtin_bit_cast(hpair, m);
 }
 template <class T>
 __device__ __forceinline__ void load_spinor(const hspin& psi, int vh, int p, int i, cx<T> v[12]) {

@@ -517,10 +517,8 @@ struct Hier {
     void prolong(int l, const cx<T>* in, hspin out, const Batch& bt);
     void vcycle(int l, int bottom, hspin r, hspin z, const Batch& bt);
     // an FP16 spinor set of R fine vectors in the memory of a level-0 scratch set
-    hspin as_h(cx<T>* buf) const {
-        cx<_Float16>* d = reinterpret_cast<cx<_Float16>*>(buf);
-        return hspin{d, reinterpret_cast<float*>(d + (size_t)R * nlv(0))};
-    }
+    // (R sets of 28 vh four-byte slots: 7/12 of the set's bytes)
+    hspin as_h(cx<T>* buf) const { return hspin{reinterpret_cast<hpair*>(buf)}; }
     void build(int l);
     void setup_level(int l, bool given);
     double norm1(long n, const cx<T>* v) { return norms(n, v, 0, single(C))[0]; }
@@ -1236,10 +1234,7 @@ template <class T>
 void Hier<T>::sap(int l, hspin b, hspin z, int nsweeps, bool zero_start, const Batch& bt) {
     if constexpr (std::is_same<T, float>::value) {
         if (l != 0 || !half) fail(DD_EINVAL, "FP16 spinor sets on the fine level of precision 16 only");
-        if (zero_start) {
-            HIPX(hipMemsetAsync(z.d, 0, sizeof(cx<_Float16>) * nlv(0) * bt.nr, C->s));
-            HIPX(hipMemsetAsync(z.s, 0, sizeof(float) * nlv(0) / 6 * bt.nr, C->s));
-        }
+        if (zero_start) HIPX(hipMemsetAsync(z.d, 0, sizeof(hpair) * (nlv(0) / 6 * 7) * bt.nr, C->s));
         for (int sw = 0; sw < nsweeps; sw++)
             for (int c = 0; c < 2; c++) {
                 Prof pr(C, DD_K_SAP, by_sap_half_h(bt.count()));
@@ -1419,9 +1414,10 @@ struct OuterOps {
 };
 
 // The outer FGMRES of precision 16: its preconditioned vectors Z and the
-// V-cycle's input are FP16 spinor sets.  Z's data fill the first 4 m ldv
-// bytes of the Z area of the workspace and its scales follow; the input
-// lives in the first half of C->ot.
+// V-cycle's input are FP16 spinor sets.  The Krylov loop addresses Z_j as
+// Zb + j ldv in units of cx<_Float16>; zh() turns such an address into the
+// FP16 set at the same logical offset (7/12 of the Z area's bytes are used).
+// The input lives at the start of C->ot.
 struct OuterOpsH {
     dd_ctx* C;
     Hier<float>* H;
@@ -1430,14 +1426,10 @@ struct OuterOpsH {
     long n;
     int m;
     cx<_Float16>* Zb;
-    float* Zs;
     cx<double>* V() { return C->oV; }
     cx<_Float16>* Z() { return Zb; }
-    hspin zh(const cx<_Float16>* z) const { return hspin{const_cast<cx<_Float16>*>(z), Zs + (z - Zb) / 6}; }
-    hspin vT() {
-        cx<_Float16>* d = reinterpret_cast<cx<_Float16>*>(C->ot);
-        return hspin{d, reinterpret_cast<float*>(d + (size_t)C->R * n)};
-    }
+    hspin zh(const cx<_Float16>* z) const { return hspin{reinterpret_cast<hpair*>(Zb)} + (long)(z - Zb); }
+    hspin vT() { return hspin{reinterpret_cast<hpair*>(C->ot)}; }
     cx<double>* t64() { return C->ot + (size_t)C->R * n; }
     int vh() const { return (int)(n / 24); }
     void precond(const cx<double>* v, cx<_Float16>* z, const Batch& bt) {
@@ -1474,7 +1466,7 @@ static void with_outer_ops(dd_ctx* C, Hier<T>& H, F&& f) {
     if constexpr (std::is_same<T, float>::value) {
         if (H.half) {
             cx<_Float16>* Zb = reinterpret_cast<cx<_Float16>*>(C->oV + (size_t)(m + 1) * ldv);
-            OuterOpsH ops{C, &H, C->ob, C->ox, n, m, Zb, reinterpret_cast<float*>(Zb + (size_t)m * ldv)};
+            OuterOpsH ops{C, &H, C->ob, C->ox, n, m, Zb};
             f(ops, (_Float16*)nullptr);
             return;
         }

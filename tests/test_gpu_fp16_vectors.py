@@ -85,3 +85,39 @@ def test_fp16_vectors_are_scale_invariant():
         say("  scale %g: its %d relres %.2e" % (sc, st["outer_iters"], relres))
         assert st["converged"] and relres <= 1e-10
     assert abs(its[1e-8] - its[1.0]) <= 1 and abs(its[1e12] - its[1.0]) <= 1
+
+
+def test_fp16_coarse_stencil_is_scale_invariant():
+    """The matrix-core coarse stencil of precision 16 divides each right-hand
+    side's inputs by their largest modulus over the site's 9-block stencil
+    before rounding them to FP16: twelve vectors (nd = 40) scaled by 1e-9 and
+    1e6, whose entries unscaled would fall below FP16's subnormals or above its
+    range, give D_c and the Schur complement within the FP16-storage bound
+    (4e-3) of the oracle's scaled result, as the unscaled vectors do."""
+    say("case: precision-16 multi-RHS coarse stencil on vectors scaled by 1e-9 and 1e6")
+    import paper_1303_1377_amd as G
+
+    p = Pair(DIMS, eps=0.3, seed=8, m0=-0.25, csw=1.0)
+    kw = dict(levels=2, n_tv=[20], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], mr_steps=[4], coarse_fixed=6)
+    p.o.configure(**kw)
+    p.g.configure(G.default_params(precision=16, max_rhs=12, **kw))
+    tv = p.vectors(0, 20, 12)
+    p.o.set_vectors(0, tv)
+    p.o.build(0)
+    p.g.set_test_vectors(0, tv)
+    p.g.build_level(0)
+    p.g.mark_setup()
+    p.o.mark_setup()
+    vol_c, ndc = p.o.level_size(1)
+    rng = np.random.default_rng(31)
+    V = rng.standard_normal((12, vol_c, ndc)) + 1j * rng.standard_normal((12, vol_c, ndc))
+    refD = [p.o.apply(V[q], level=1) for q in range(12)]
+    refS = [p.o.schur(1, V[q]) for q in range(12)]
+    for f in (1.0, 1e-9, 1e6):
+        D, _ = p.g.apply_batch("D", 1, f * V)
+        S, _ = p.g.apply_batch("SCHUR", 1, f * V)
+        D, S = to_np(D), to_np(S)
+        ed = max(rel(D[q], f * refD[q]) for q in range(12))
+        es = max(rel(S[q], f * refS[q]) for q in range(12))
+        say("  scale %g: D_c error %.2e, Schur error %.2e" % (f, ed, es))
+        assert ed < 4e-3 and es < 4e-3
