@@ -403,6 +403,20 @@ dd_status dd_autotune(dd_ctx *ctx, int reps, int *chosen, double *times_ms);
  * cooperative form won). */
 dd_status dd_autotune_coarse(dd_ctx *ctx, int reps, int *chosen_grid, double *times_ms);
 
+/* Persistent autotuning (after dd_setup).  `path` names a text file with one
+ * line per tuned problem shape: a key (device architecture and compute-unit
+ * count, lattice, precision, max_rhs, levels, and per level the test vectors,
+ * aggregate and SAP block dims and MR steps, plus nu), a tab, the schedule
+ * flags and the cooperative workgroup count.  On a hit the stored schedule is
+ * applied without timing; on a miss dd_autotune and dd_autotune_coarse run
+ * with `reps` and their choice is appended.  The choices are launch forms
+ * whose results agree to rounding, so one entry serves every field and mass of
+ * its shape.  sched, grid, hit (each may be NULL) receive the schedule in use,
+ * the cooperative workgroups (0: step-by-step) and 1 for a cache hit.
+ * Errors: DD_EINVAL for a NULL path, reps < 1 or a file that cannot be
+ * appended to (the tuned forms stay in use); DD_ESTATE before dd_setup. */
+dd_status dd_autotune_cached(dd_ctx *ctx, const char *path, int reps, int *sched, int *grid, int *hit);
+
 #ifdef __cplusplus
 }
 #endif

@@ -125,11 +125,12 @@ def library():
         L.dd_get_schedule.restype = C.c_int
         L.dd_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.dd_autotune_coarse.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.dd_autotune_cached.argtypes = [vp, C.c_char_p, C.c_int, ip, ip, ip]
         for name in ("dd_create", "dd_setup", "dd_solve", "dd_solve_batch", "dd_set_mass", "dd_configure",
                      "dd_set_test_vectors", "dd_get_test_vectors", "dd_build_level", "dd_mark_setup", "dd_get_P",
                      "dd_get_coarse", "dd_get_clover", "dd_apply", "dd_level_info", "dd_profile", "dd_profile_read",
                      "dd_profile_classes", "dd_apply_D_noalloc", "dd_stream_load", "dd_stream_cycle", "dd_stream_take",
-                     "dd_solve_bicgstab",
+                     "dd_solve_bicgstab", "dd_solve_id", "dd_autotune_cached",
                      "dd_time_kernel", "dd_set_schedule", "dd_autotune", "dd_apply_batch", "dd_autotune_coarse"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -389,6 +390,21 @@ class Solver:
         t = (C.c_double * 8)()
         self._check(library().dd_autotune_coarse(self.h, int(reps), C.byref(ch), t))
         return ch.value, list(t)
+
+    def autotune_cached(self, path=None, reps=3):
+        """Apply the launch forms stored for this problem shape in the text cache
+        at `path` (default: $DD_TUNE_CACHE, else ~/.cache/ddamg/autotune.txt), or
+        tune them (autotune, then autotune_coarse) and store them; returns
+        (schedule, cooperative grid, hit)."""
+        if path is None:
+            path = os.environ.get("DD_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "ddamg",
+                                                                   "autotune.txt")
+        d = os.path.dirname(os.path.abspath(path))
+        os.makedirs(d, exist_ok=True)
+        sc, gr, hit = C.c_int(), C.c_int(), C.c_int()
+        self._check(library().dd_autotune_cached(self.h, os.fsencode(path), int(reps), C.byref(sc), C.byref(gr),
+                                                 C.byref(hit)))
+        return sc.value, gr.value, bool(hit.value)
 
     def time_kernel(self, name, reps=20):
         """Mean duration (ms) of one standalone launch: dirac64, dirac_prec or sap (full sweep)."""

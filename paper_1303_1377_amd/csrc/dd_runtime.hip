@@ -2820,3 +2820,76 @@ dd_status dd_autotune_coarse(dd_ctx* ctx, int reps, int* chosen_grid, double* ti
     return DD_OK;
     ABI_END(ctx)
 }
+
+
+// ---------------------------------------------------------------------------
+// Persistent autotuning cache: one text line per tuned problem shape,
+//   <key> TAB <schedule flags> <cooperative workgroups>
+// The key names the device (architecture, compute units) and everything the
+// launch forms' costs depend on: lattice, precision, max_rhs, levels, test
+// vectors, aggregates and SAP blocks per level, MR steps and nu.  The choices
+// are launch forms whose results agree to rounding, so a stored choice serves
+// every field and mass of the same shape.
+// ---------------------------------------------------------------------------
+static std::string tune_key(dd_ctx* C) {
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPX(hipGetDeviceProperties(&prop, dev));
+    const dd_params& p = C->p;
+    std::string k = std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount) + "cu";
+    k += " dims=" + std::to_string(C->dims[0]) + "x" + std::to_string(C->dims[1]) + "x" + std::to_string(C->dims[2]) +
+         "x" + std::to_string(C->dims[3]);
+    k += " prec=" + std::to_string(p.precision) + " rhs=" + std::to_string(p.max_rhs) + " lev=" +
+         std::to_string(p.levels) + " nu=" + std::to_string(p.nu);
+    for (int l = 0; l + 1 < p.levels; l++) {
+        k += " L" + std::to_string(l) + "=n" + std::to_string(p.n_tv[l]) + ",a" + std::to_string(p.agg[l][0]);
+        for (int mu = 1; mu < 4; mu++) k += "x" + std::to_string(p.agg[l][mu]);
+        k += ",s" + std::to_string(p.sap[l][0]);
+        for (int mu = 1; mu < 4; mu++) k += "x" + std::to_string(p.sap[l][mu]);
+        k += ",mr" + std::to_string(p.mr_steps[l]);
+    }
+    return k;
+}
+
+dd_status dd_autotune_cached(dd_ctx* ctx, const char* path, int reps, int* sched, int* grid, int* hit) {
+    ABI_TRY(ctx)
+    if (!path || !*path) fail(DD_EINVAL, "NULL cache path");
+    if (reps < 1) fail(DD_EINVAL, "reps >= 1");
+    if (!ctx->have_setup) fail(DD_ESTATE, "the launch forms are tuned after dd_setup");
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    const std::string key = tune_key(ctx);
+    int fs = -1, fg = -1;
+    if (FILE* f = fopen(path, "r")) {
+        char line[1024];
+        while (fgets(line, sizeof line, f)) {
+            char* tab = strchr(line, '\t');
+            if (!tab) continue;
+            *tab = 0;
+            int a = -1, b = -1;
+            if (key == line && sscanf(tab + 1, "%d %d", &a, &b) == 2 && a >= 0 && b >= 0) { fs = a; fg = b; }
+        }
+        fclose(f);
+    }
+    const bool found = fs >= 0;
+    if (found) {
+        set_sched(ctx, fs);
+        if (fg > 0) ctx->coop_cap = fg;
+    } else {
+        dd_status rc = dd_autotune(ctx, reps, nullptr, nullptr);
+        if (rc != DD_OK) return rc;
+        rc = dd_autotune_coarse(ctx, reps, &fg, nullptr);
+        if (rc != DD_OK) return rc;
+        fs = ctx->sched;
+        FILE* f = fopen(path, "a");
+        if (!f) fail(DD_EINVAL, std::string("cannot append to the autotuning cache ") + path + " (the tuned forms are in use)");
+        fprintf(f, "%s\t%d %d\n", key.c_str(), fs, fg);
+        fclose(f);
+    }
+    if (sched) *sched = ctx->sched;
+    if (grid) *grid = fg;
+    if (hit) *hit = found ? 1 : 0;
+    return DD_OK;
+    ABI_END(ctx)
+}

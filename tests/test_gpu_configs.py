@@ -187,3 +187,36 @@ def test_mcrit_krylov_schur_on_the_library_matches_oracle_arpack():
     r = m_crit(info["dims"], U, info["csw"], tol=1e-4)
     say("  device %.10f oracle ARPACK %.10f" % (r["m_crit"], info["m_crit"]))
     assert abs(r["m_crit"] - info["m_crit"]) < 1e-7
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """dd_autotune_cached: a miss tunes and appends one line; the same shape then
+    hits and applies the stored schedule without timing; another precision
+    misses again.  Solves after a hit meet the residual."""
+    import paper_1303_1377_amd as G
+
+    say("case: persistent autotuning cache")
+    path = str(tmp_path / "tune.txt")
+    dims = (8, 8, 8, 8)
+    p = Pair(dims, eps=0.3, seed=3, m0=-0.25, csw=1.0)
+    kw = dict(levels=2, n_tv=[8], agg=[(4, 4, 4, 4)], sap=[(4, 4, 4, 4)], n_inv=2)
+    p.g.setup(params=G.default_params(precision=32, **kw))
+    s1, g1, hit1 = p.g.autotune_cached(path, reps=1)
+    assert not hit1
+    with open(path) as f:
+        lines = f.read().splitlines()
+    assert len(lines) == 1 and "prec=32" in lines[0] and "dims=8x8x8x8" in lines[0]
+    p.g.set_schedule(0)
+    s2, g2, hit2 = p.g.autotune_cached(path, reps=1)
+    assert hit2 and s2 == s1 and g2 == g1 and p.g.get_schedule() == s1
+    b = F.gaussian_spinor(dims, 5)
+    x, st = p.g.solve(b, 1e-10)
+    assert st["converged"] and st["true_relres"] <= 1e-10
+    p.g.setup(params=G.default_params(precision=64, **kw))
+    _, _, hit3 = p.g.autotune_cached(path, reps=1)
+    assert not hit3
+    with open(path) as f:
+        assert len(f.read().splitlines()) == 2
+    # a file that cannot be appended to (its directory does not exist): DD_EINVAL
+    bad = str(tmp_path / "missing_dir" / "tune.txt").encode()
+    assert G.library().dd_autotune_cached(p.g.h, bad, 1, None, None, None) == -1
