@@ -83,6 +83,18 @@ static int run(const int d[4], int levels, const int agg[2][4], const int sap[2]
     if (levels == 2) {
         or_coarse_solve(X, 1, rc1, ec1);
         or_schur(X, 1, rc1, ec1);
+        /* the comparison solvers: odd-even BiCGStab, inexact deflation and its setup */
+        or_bicgstab(X, b, y, 5);
+        rc = or_solve_bicgstab(X, b, x, 1e-8, 10, &st);
+        if (rc || st.true_relres > 1e-8) { fprintf(stderr, "bicgstab rc %d relres %g\n", rc, st.true_relres); return 1; }
+        /* inexact deflation needs its coarse systems solved accurately */
+        p.id_setup = 1;
+        p.coarse_tol = 1e-12;
+        p.coarse_maxit = 4000;
+        if (or_configure(X, &p) || or_setup(X, tv)) { fprintf(stderr, "id setup: %s\n", or_error(X)); return 1; }
+        or_apply_deflated(X, b, y);
+        rc = or_solve_id(X, b, x, 1e-8, 3, &st);
+        if (rc || st.true_relres > 1e-7) { fprintf(stderr, "id rc %d relres %g\n", rc, st.true_relres); return 1; }
     } else {
         or_fgmres_level(X, 1, rc1, ec1);
         or_sap(X, 1, rc1, ec1, 1, 1);
