@@ -226,7 +226,73 @@ __device__ __forceinline__ void tile_mma(const cx<S>* __restrict__ A, int nd, in
     }
 }
 
-template <class S>
+// The same for a compile-time padded extent NDK (the production nd = 40): all
+// A fragments of the block are loaded before the first product, so a wave has
+// NDK / K loads in flight instead of one per instruction step.
+template <class S, int NDK>
+__device__ __forceinline__ void tile_mma_fixed(const cx<S>* __restrict__ A, int nd, int r, int lane, float sgn,
+                                               const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
+    constexpr int K = MfmaK<S>::K;
+    constexpr int KL = K / 4;
+    constexpr int NS = NDK / K;
+    const int q = lane >> 4, j = lane & 15;
+    typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type are[NS], aim[NS];
+#pragma unroll
+    for (int t = 0; t < NS; t++) a_frag<S>(A, nd, r, t * K + q * KL, sgn, are[t], aim[t]);
+#pragma unroll
+    for (int t = 0; t < NS; t++) {
+        typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type bre, bim, naim;
+        b_frag<S>(Xre, Xim, t * K + q * KL, j, bre, bim);
+        naim = -aim[t];
+        cre = mma(are[t], bre, cre);
+        cre = mma(naim, bim, cre);
+        cim = mma(are[t], bim, cim);
+        cim = mma(aim[t], bre, cim);
+    }
+}
+
+// Fragments of one block for tile_mma_fixed, loaded ahead of their products
+// so that the next block's loads overlap the current block's MFMA work.
+template <class S, int NDK>
+struct TileFrags {
+    static constexpr int NS = NDK / MfmaK<S>::K;
+    typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type re[NS], im[NS];
+};
+template <class S, int NDK>
+__device__ __forceinline__ void tile_load(const cx<S>* __restrict__ A, int nd, int r, int lane, float sgn,
+                                          TileFrags<S, NDK>& f) {
+    constexpr int K = MfmaK<S>::K, KL = K / 4;
+    const int q = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < TileFrags<S, NDK>::NS; t++) a_frag<S>(A, nd, r, t * K + q * KL, sgn, f.re[t], f.im[t]);
+}
+template <class S, int NDK>
+__device__ __forceinline__ void tile_product(const TileFrags<S, NDK>& f, int lane, const S* Xre, const S* Xim,
+                                             f32x4& cre, f32x4& cim) {
+    constexpr int K = MfmaK<S>::K, KL = K / 4;
+    const int q = lane >> 4, j = lane & 15;
+#pragma unroll
+    for (int t = 0; t < TileFrags<S, NDK>::NS; t++) {
+        typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type bre, bim, naim;
+        b_frag<S>(Xre, Xim, t * K + q * KL, j, bre, bim);
+        naim = -f.im[t];
+        cre = mma(f.re[t], bre, cre);
+        cre = mma(naim, bim, cre);
+        cim = mma(f.re[t], bim, cim);
+        cim = mma(f.im[t], bre, cim);
+    }
+}
+
+// the k x ndk tile product of one block: the unrolled form where the padded
+// extent is the production one (NDK > 0), the loop otherwise
+template <class S, int NDK>
+__device__ __forceinline__ void tile_any(const cx<S>* __restrict__ A, int nd, int ndk, int r, int lane, float sgn,
+                                         const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
+    if constexpr (NDK > 0) tile_mma_fixed<S, NDK>(A, nd, r, lane, sgn, Xre, Xim, cre, cim);
+    else tile_mma<S>(A, nd, ndk, r, lane, sgn, Xre, Xim, cre, cim);
+}
+
+template <class S, int NDK = 0>
 __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op, int par, int self_mode,
                                                            const cx<float>* __restrict__ in1, int hop_sign,
                                                            const cx<float>* in2, int post_inv, cx<float>* out, Mask mk,
@@ -305,9 +371,21 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     const int r = 16 * w + (lane & 15);
     f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
     if (w < ntile) {
-        for (int sl = 0; sl < ns; sl++) {
-            const float sgn = (sl >= nself && hop_sign < 0) ? -1.f : 1.f;
-            tile_mma<S>(mat[sl], nd, ndk, r, lane, sgn, Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
+        auto sgn_of = [&](int sl) { return (sl >= nself && hop_sign < 0) ? -1.f : 1.f; };
+        if constexpr (NDK > 0) {
+            // software pipeline over the slots: block sl + 1 loads while block sl multiplies
+            TileFrags<S, NDK> fa, fb;
+            tile_load<S, NDK>(mat[0], nd, r, lane, sgn_of(0), fa);
+            for (int sl = 0; sl < ns; sl += 2) {
+                if (sl + 1 < ns) tile_load<S, NDK>(mat[sl + 1], nd, r, lane, sgn_of(sl + 1), fb);
+                tile_product<S, NDK>(fa, lane, Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
+                if (sl + 1 >= ns) break;
+                if (sl + 2 < ns) tile_load<S, NDK>(mat[sl + 2], nd, r, lane, sgn_of(sl + 2), fa);
+                tile_product<S, NDK>(fb, lane, Xre + (sl + 1) * ndk * 16, Xim + (sl + 1) * ndk * 16, cre, cim);
+            }
+        } else {
+            for (int sl = 0; sl < ns; sl++)
+                tile_mma<S>(mat[sl], nd, ndk, r, lane, sgn_of(sl), Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
         }
     }
     // result rows 16w + 4q + v, column j
@@ -375,7 +453,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     __syncthreads();
     if (w < ntile) {
         f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-        tile_mma<S>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, dre, dim);
+        tile_any<S, NDK>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, dre, dim);
         if constexpr (F16) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -553,8 +631,14 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
     if constexpr (std::is_same<T, float>::value) {
         // the matrix-core form serves FP32 arithmetic with 2..16 right-hand sides and nd <= 64
         if (op.mfma && nr >= 2 && nr <= 16 && op.nd <= 64) {
-            k_coarse_apply_mfma<S><<<nsite, 64 * ((op.nd + 15) / 16), mfma_lds_bytes<S>(op.nd), s>>>(
-                op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
+            constexpr int K = MfmaK<S>::K;
+            constexpr int NDK40 = (40 + K - 1) / K * K;
+            if (op.nd == 40)
+                k_coarse_apply_mfma<S, NDK40><<<nsite, 64 * 3, mfma_lds_bytes<S>(op.nd), s>>>(
+                    op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
+            else
+                k_coarse_apply_mfma<S><<<nsite, 64 * ((op.nd + 15) / 16), mfma_lds_bytes<S>(op.nd), s>>>(
+                    op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
             return;
         }
     }
