@@ -6,7 +6,8 @@ per-kernel statistics.
         --out profiles/counters_16x4_fp64_solve.json --command "..."
     python -m paper_1303_1377_amd.counters --stats RESULTS.db [--last-seconds T] [--top 20]
 
---stats reads the SQLite results database of `rocprofv3 --kernel-trace` and
+--last N keeps the last N dispatches of each class (the timed part of a run
+that ends with it).  --stats reads the SQLite results database of `rocprofv3 --kernel-trace` and
 prints calls, total, mean and share per kernel; --last-seconds keeps only the
 dispatches that start in the last T seconds of GPU activity (the timed region
 of a benchmark that ends with it).
@@ -31,22 +32,32 @@ import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# kernel class -> (kernel name prefix in the trace, source file)
+# kernel class -> (kernel name prefixes in the trace, source file); the
+# prefixes cover the FP64 and the FP32 forms of each class
 CLASSES = {
-    "sap": ("void dd::k_sap_fine<double, double, 1>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
-    "dirac64": ("void dd::k_dirac<double, double>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
-    "restrict": ("void dd::k_restrict_fine<double, double, 256>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
-    "prolong": ("void dd::k_prolong_fine<double, double>(", "paper_1303_1377_amd/csrc/dd_fine.hip"),
+    "sap": (("void dd::k_sap_fine<double, double, dd::cx<double>*, 1>(",
+             "void dd::k_sap_fine<float, float, dd::cx<float>*, 2>(",
+             "void dd::k_sap_fine<double, double, 1>("), "paper_1303_1377_amd/csrc/dd_fine.hip"),
+    "dirac64": (("void dd::k_dirac<double, double>(", "void dd::k_dirac_lds<double, double>("),
+                "paper_1303_1377_amd/csrc/dd_fine.hip"),
+    "restrict": (("void dd::k_restrict_fine<double, double, 256",
+                  "void dd::k_restrict_fine<float, float, 256"), "paper_1303_1377_amd/csrc/dd_fine.hip"),
+    "prolong": (("void dd::k_prolong_fine<double, double", "void dd::k_prolong_fine<float, float"),
+                "paper_1303_1377_amd/csrc/dd_fine.hip"),
 }
 
 
 def per_kernel(d):
+    """Counter values per kernel name, in dispatch order."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    vals = {}
+    rows = []
     for fn in files:
         with open(fn) as f:
             for r in csv.DictReader(f):
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    vals = {}
+    for _, name, v in sorted(rows):
+        vals.setdefault(name, []).append(v)
     return vals
 
 
@@ -78,6 +89,8 @@ def main():
     ap.add_argument("--stats")
     ap.add_argument("--last-seconds", type=float, default=None)
     ap.add_argument("--top", type=int, default=20)
+    ap.add_argument("--last", type=int, default=None,
+                    help="keep the last N dispatches of each class (the timed part of a run that ends with it)")
     a = ap.parse_args()
     if a.stats:
         rows, tot, n = kernel_stats(a.stats, a.last_seconds, a.top)
@@ -89,9 +102,14 @@ def main():
         return
     fe, wr = per_kernel(a.fetch), per_kernel(a.write)
     rec = dict(fetch_scale=2.0, write_scale=1.0, command=a.command, kernels={})
-    for cls, (prefix, src) in CLASSES.items():
+    for cls, (prefixes, src) in CLASSES.items():
+        prefix = next((p for p in prefixes if any(n.startswith(p) for n in fe)), None)
+        if prefix is None:
+            continue
         fk = [v for n, vs in fe.items() if n.startswith(prefix) for v in vs]
         wk = [v for n, vs in wr.items() if n.startswith(prefix) for v in vs]
+        if a.last:
+            fk, wk = fk[-a.last:], wk[-a.last:]
         if not fk or not wk:
             continue
         with open(os.path.join(ROOT, src), "rb") as f:
