@@ -85,13 +85,16 @@ void vec_sub(long n, const cx<T>* a, const cx<T>* b, cx<T>* out, hipStream_t s) 
 }
 
 // ---- reductions ------------------------------------------------------------
-// The vector is cut into at most RED_CHUNKS chunks.  multidot runs one
+// The vector is cut into at most RED_CHUNKS chunks of at least 1024 entries.  multidot runs one
 // workgroup per (chunk, basis vector, right-hand side) and writes the chunk's
 // partial inner product; update_norm runs one workgroup per (chunk, RHS).  A
 // small kernel then adds the partials in chunk order, so the results do not
 // depend on scheduling.
 static inline int red_chunks(long n) {
-    long c = (n + 255) / 256;
+    // at least 1024 entries per chunk: every workgroup of update_norm first adds
+    // all nc chunk partials of the inner products, a dependent chain of nc / 8
+    // loads per thread, so short vectors want few chunks
+    long c = (n + 1023) / 1024;
     if (c > RED_CHUNKS) c = RED_CHUNKS;
     if (c < 1) c = 1;
     return (int)c;
