@@ -17,7 +17,8 @@ static_assert(RED_NT % MAXM == 0, "k_update_norm splits its threads into groups 
 
 size_t reduce_work_size(int m, int nr) {
     (void)m;
-    return sizeof(cx<double>) * (size_t)RED_CHUNKS * (MAXM + 1) * (size_t)(nr < 1 ? 1 : nr);
+    // multidot partials, norm partials, and the partials of the fused update + inner products
+    return sizeof(cx<double>) * (size_t)RED_CHUNKS * (2 * MAXM + 1) * (size_t)(nr < 1 ? 1 : nr);
 }
 
 static inline int nblk_of(long n, int b) { return (int)((n + b - 1) / b); }
@@ -263,6 +264,54 @@ static inline cx<double>* hpart_of(void* work) { return (cx<double>*)work; }
 static inline cx<double>* npart_of(void* work, int nr) {
     return (cx<double>*)work + (size_t)RED_CHUNKS * MAXM * (nr < 1 ? 1 : nr);
 }
+static inline cx<double>* upart_of(void* work, int nr) {
+    return (cx<double>*)work + (size_t)RED_CHUNKS * (MAXM + 1) * (nr < 1 ? 1 : nr);
+}
+
+// The first projection of a classical Gram-Schmidt pass with its
+// reorthogonalisation's inner products in the same sweep: w -= sum_i h_i V_i,
+// then part[(r*nc + c)*m + i] = chunk c of V_i^H w (the updated w), each basis
+// entry loaded once for both (m <= UD_MAX).
+static constexpr int UD_MAX = 16;
+template <class T, int JM>
+__global__ void __launch_bounds__(RED_NT) k_update_dot(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
+                                                       long ldv, const cx<double>* __restrict__ h, int hstride,
+                                                       cx<T>* __restrict__ w, cx<double>* __restrict__ part, long ldr,
+                                                       long ldw, Mask mk) {
+    const int c = blockIdx.x, r = blockIdx.y;
+    if (!mk.on(r)) return;
+    __shared__ cx<T> hh[JM];
+    __shared__ double sh[2][RED_NT / 64];
+    if (threadIdx.x < m) hh[threadIdx.x] = ccast<T>(h[(size_t)r * hstride + threadIdx.x]);
+    __syncthreads();
+    const cx<T>* Vr = V + r * ldr;
+    cx<T>* wr = w + r * ldw;
+    const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
+    double are[JM], aim[JM];
+#pragma unroll
+    for (int i = 0; i < JM; i++) are[i] = aim[i] = 0.0;
+    for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
+        cx<T> we = wr[e];
+        cx<T> vv[JM];
+#pragma unroll
+        for (int i = 0; i < JM; i++) vv[i] = (i < m) ? Vr[(size_t)i * ldv + e] : czero<T>();
+#pragma unroll
+        for (int i = 0; i < JM; i++)
+            if (i < m) we -= hh[i] * vv[i];
+        wr[e] = we;
+#pragma unroll
+        for (int i = 0; i < JM; i++) {
+            are[i] += (double)vv[i].re * we.re + (double)vv[i].im * we.im;
+            aim[i] += (double)vv[i].re * we.im - (double)vv[i].im * we.re;
+        }
+    }
+    for (int i = 0; i < m; i++) {
+        const double a = block_sum256(are[i], sh[0]);
+        const double b = block_sum256(aim[i], sh[1]);
+        if (threadIdx.x == 0) part[((size_t)r * nc + c) * m + i] = cx<double>{a, b};
+        __syncthreads();   // sh is reused by the next pair of sums
+    }
+}
 
 template <class T>
 void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work, int* count,
@@ -278,6 +327,24 @@ void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<do
         dim3 g2(mm, rb.nr);
         k_final_sum<<<g2, RED_NT, 0, s>>>(nc, mm, hpart_of(work), out + i0, rb.ostride, rb.mk);
     }
+}
+
+template <class T>
+bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
+                    void* work, hipStream_t s, RedBatch rb) {
+    if (m > UD_MAX) return false;
+    const int nc = red_chunks(n);
+    const long chunk = (n + nc - 1) / nc;
+    dim3 grid(nc, rb.nr);
+    if (m <= 8)
+        k_update_dot<T, 8><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, h, rb.ostride, w, upart_of(work, rb.nr),
+                                                  rb.ldr, rb.ldw, rb.mk);
+    else
+        k_update_dot<T, UD_MAX><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, h, rb.ostride, w,
+                                                       upart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
+    dim3 g2(m, rb.nr);
+    k_final_sum<<<g2, RED_NT, 0, s>>>(nc, m, upart_of(work, rb.nr), out, rb.ostride, rb.mk);
+    return true;
 }
 
 template <class T>
@@ -581,6 +648,8 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template void vec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, hipStream_t);                               \
     template void vec_multidot<T>(long, int, const cx<T>*, long, const cx<T>*, cx<double>*, void*, int*, hipStream_t, \
                                   RedBatch);                                                                       \
+    template bool vec_update_dot<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*,       \
+                                    hipStream_t, RedBatch);                                                        \
     template void vec_update_norm<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*, int*, \
                                      hipStream_t, RedBatch);                                                       \
     template void vec_finite_check<T>(long, const cx<T>*, int*, hipStream_t);                                     \

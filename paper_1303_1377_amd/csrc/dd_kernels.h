@@ -240,6 +240,12 @@ void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<do
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
                      void* work, int* count, hipStream_t s, RedBatch rb = single_rhs());
+// w -= sum_i h_i V_i and out_i = V_i^H w (the updated w) in one sweep over the
+// basis: the first projection of a Gram-Schmidt pass and the inner products of
+// its reorthogonalisation.  Returns false (nothing done) for m above its limit.
+template <class T>
+bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
+                    void* work, hipStream_t s, RedBatch rb = single_rhs());
 // x += sum_i y_i Z_i (y in FP64 on the device; RHS r: Z + r*ldzr, y + r*ystride, x + r*ldx)
 // over i < m, or i < per->v[r] when per-RHS counts are given
 template <class T, class X>

@@ -1078,10 +1078,14 @@ static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const dou
         ops.matvec(zj, w, cur);
         {
             RedBatch rb{nr, n, n, RS, cur.mask()};
-            Prof pr(C, DD_K_REDUCE, 4.0 * cur.count() * n * (j + 2) * sizeof(cx<VS>));
+            Prof pr(C, DD_K_REDUCE, (j + 1 <= 16 ? 3.0 : 4.0) * cur.count() * n * (j + 2) * sizeof(cx<VS>));
+            // CGS with one reorthogonalisation; the first update and the second
+            // pass's inner products share one sweep over the basis where it fits
             vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred, C->dwork, nullptr, C->s, rb);
-            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
-            vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
+            if (!vec_update_dot<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 34, C->dwork, C->s, rb)) {
+                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
+                vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
+            }
             vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb);
         }
         read_red(C, nr, 68);
