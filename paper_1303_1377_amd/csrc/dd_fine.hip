@@ -574,16 +574,21 @@ void fine_oe_hop(const FineOp<T, S>& op, int p, bool pre_a, bool post_inv, doubl
 // ---------------------------------------------------------------------------
 template <class T, class S>
 __global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T, S> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                   long ld, Mask mk) {
+                                                   long ld, Mask mk, int nr) {
     extern __shared__ char smem_raw[];
-    if (!mk.on(blockIdx.y)) return;
+    // one workgroup per (layout block, RHS), RHS fastest in the logical order:
+    // the nr workgroups of a block run back to back on one XCD and the later
+    // ones find the block's links and clover in its L2
+    const int lw = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int rhs = lw % nr;
+    if (!mk.on(rhs)) return;
     const Geom g = op.g;
     const int bvh = g.bvh;
     cx<T>* SP = reinterpret_cast<cx<T>*>(smem_raw);  // [2][12][bvh]
     cx<T>* HB = SP + 24 * bvh;                         // [2][6][bvh]
-    in += blockIdx.y * ld;
-    out += blockIdx.y * ld;
-    const int blk = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+    in += rhs * ld;
+    out += rhs * ld;
+    const int blk = lw / nr;
     const int t = threadIdx.x;
     const int p = t >= bvh;
     const int l = t - p * bvh;
@@ -687,8 +692,7 @@ void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t
             allowed = configured;
         }
         if (lds <= allowed) {
-            dim3 grid(op.g.nblk, nr);
-            k_dirac_lds<T, S><<<grid, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk);
+            k_dirac_lds<T, S><<<op.g.nblk * nr, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk, nr);
             return;
         }
     }
