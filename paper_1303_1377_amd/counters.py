@@ -3,7 +3,7 @@ bench.py reads for its roofline `traffic` figure, and kernel traces to
 per-kernel statistics.
 
     python -m paper_1303_1377_amd.counters --fetch DIR_FETCH --write DIR_WRITE \\
-        --out profiles/counters_16x4_fp64_solve.json --command "..."
+        --out profiles/counters_48c96_fp32_batch4.json --last 52 --command "..."
     python -m paper_1303_1377_amd.counters --stats RESULTS.db [--last-seconds T] [--top 20]
 
 --last N keeps the last N dispatches of each class (the timed part of a run
