@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
                                                         long ldv, const cx<double>* __restrict__ h, int hstride,
                                                         const cx<double>* __restrict__ hpart, cx<double>* hout,
                                                         cx<T>* __restrict__ w, cx<double>* __restrict__ npart, long ldr,
-                                                        long ldw, Mask mk, GivensArgs ga) {
+                                                        long ldw, Mask mk, GivensArgs ga, const double* __restrict__ g,
+                                                        int gstride) {
     const int c = blockIdx.x, r = blockIdx.y;
     if (!mk.on(r)) return;
     const double* scv = ga.st ? ga.st[r].sc : nullptr;
@@ -199,7 +200,8 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
             hh[threadIdx.x] = ccast<T>(f * hv);
         }
     } else if (threadIdx.x < m) {
-        hh[threadIdx.x] = ccast<T>(h[(size_t)r * hstride + threadIdx.x]);
+        const double gi = g ? g[(size_t)r * gstride + threadIdx.x] : 1.0;
+        hh[threadIdx.x] = ccast<T>(gi * h[(size_t)r * hstride + threadIdx.x]);
     }
     __syncthreads();
     const cx<T>* Vr = V + r * ldr;
@@ -277,12 +279,15 @@ template <class T, int JM>
 __global__ void __launch_bounds__(RED_NT) k_update_dot(long n, long chunk, int nc, int m, const cx<T>* __restrict__ V,
                                                        long ldv, const cx<double>* __restrict__ h, int hstride,
                                                        cx<T>* __restrict__ w, cx<double>* __restrict__ part, long ldr,
-                                                       long ldw, Mask mk) {
+                                                       long ldw, Mask mk, const double* __restrict__ g, int gstride) {
     const int c = blockIdx.x, r = blockIdx.y;
     if (!mk.on(r)) return;
     __shared__ cx<T> hh[JM];
     __shared__ double sh[2][RED_NT / 64];
-    if (threadIdx.x < m) hh[threadIdx.x] = ccast<T>(h[(size_t)r * hstride + threadIdx.x]);
+    if (threadIdx.x < m) {
+        const double gi = g ? g[(size_t)r * gstride + threadIdx.x] : 1.0;
+        hh[threadIdx.x] = ccast<T>(gi * h[(size_t)r * hstride + threadIdx.x]);
+    }
     __syncthreads();
     const cx<T>* Vr = V + r * ldr;
     cx<T>* wr = w + r * ldw;
@@ -331,17 +336,17 @@ void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<do
 
 template <class T>
 bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                    void* work, hipStream_t s, RedBatch rb) {
+                    void* work, hipStream_t s, RedBatch rb, const double* g, int gstride) {
     if (m > UD_MAX) return false;
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
     dim3 grid(nc, rb.nr);
     if (m <= 8)
         k_update_dot<T, 8><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, h, rb.ostride, w, upart_of(work, rb.nr),
-                                                  rb.ldr, rb.ldw, rb.mk);
+                                                  rb.ldr, rb.ldw, rb.mk, g, gstride);
     else
         k_update_dot<T, UD_MAX><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, h, rb.ostride, w,
-                                                       upart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk);
+                                                       upart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk, g, gstride);
     dim3 g2(m, rb.nr);
     k_final_sum<<<g2, RED_NT, 0, s>>>(nc, m, upart_of(work, rb.nr), out, rb.ostride, rb.mk);
     return true;
@@ -349,7 +354,7 @@ bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h
 
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                     void* work, int* count, hipStream_t s, RedBatch rb) {
+                     void* work, int* count, hipStream_t s, RedBatch rb, const double* g, int gstride) {
     (void)count;
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
@@ -358,7 +363,8 @@ void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* 
         int mm = (m - i0 < MAXM) ? m - i0 : MAXM;
         dim3 grid(nc, rb.nr);
         k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, mm, V + (size_t)i0 * ldv, ldv, h + i0, rb.ostride, nullptr,
-                                                 nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk, GivensArgs{});
+                                                 nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk, GivensArgs{},
+                                                 g ? g + i0 : nullptr, gstride);
         i0 += mm;
     } while (i0 < m);
     dim3 g2(1, rb.nr);
@@ -559,7 +565,7 @@ void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, c
     dim3 grid(nc, rb.nr);
     k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
                                              npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk,
-                                             GivensArgs{st, j, done, normalize ? 1 : 0});
+                                             GivensArgs{st, j, done, normalize ? 1 : 0}, nullptr, 0);
 }
 
 template <class T, class X>
@@ -622,6 +628,14 @@ __global__ void k_scale_b(long n, Coefs c, cx<T>* __restrict__ x, long ld, Mask 
     const T f = T(c.v[blockIdx.y]);
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) x[e] = f * x[e];
 }
+// g[r * gstride + idx] = c.v[r] for the RHS the mask keeps
+__global__ void k_set_factor(double* g, int gstride, int idx, Coefs c, int nr, Mask mk) {
+    const int r = threadIdx.x;
+    if (r < nr && mk.on(r)) g[(size_t)r * gstride + idx] = c.v[r];
+}
+void set_factor(double* g, int gstride, int idx, const Coefs& c, int nr, Mask mk, hipStream_t s) {
+    k_set_factor<<<1, 64, 0, s>>>(g, gstride, idx, c, nr, mk);
+}
 __global__ void k_set_flags(int* d, unsigned bits, int n) {
     if ((int)threadIdx.x < n) d[threadIdx.x] = (bits >> threadIdx.x) & 1u;
 }
@@ -649,9 +663,9 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template void vec_multidot<T>(long, int, const cx<T>*, long, const cx<T>*, cx<double>*, void*, int*, hipStream_t, \
                                   RedBatch);                                                                       \
     template bool vec_update_dot<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*,       \
-                                    hipStream_t, RedBatch);                                                        \
+                                    hipStream_t, RedBatch, const double*, int);                                    \
     template void vec_update_norm<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*, int*, \
-                                     hipStream_t, RedBatch);                                                       \
+                                     hipStream_t, RedBatch, const double*, int);                                   \
     template void vec_finite_check<T>(long, const cx<T>*, int*, hipStream_t);                                     \
     template void bvec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, long, int, Mask, hipStream_t);            \
     template void bvec_scale<T>(long, const Coefs&, cx<T>*, long, int, Mask, hipStream_t);                         \

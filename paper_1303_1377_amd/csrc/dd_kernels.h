@@ -239,13 +239,18 @@ void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<do
 // out[0].re = ||w||^2
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                     void* work, int* count, hipStream_t s, RedBatch rb = single_rhs());
+                     void* work, int* count, hipStream_t s, RedBatch rb = single_rhs(), const double* g = nullptr,
+                     int gstride = 0);
 // w -= sum_i h_i V_i and out_i = V_i^H w (the updated w) in one sweep over the
 // basis: the first projection of a Gram-Schmidt pass and the inner products of
 // its reorthogonalisation.  Returns false (nothing done) for m above its limit.
 template <class T>
 bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                    void* work, hipStream_t s, RedBatch rb = single_rhs());
+                    void* work, hipStream_t s, RedBatch rb = single_rhs(), const double* g = nullptr, int gstride = 0);
+// g (may be NULL) scales the coefficients of the two updates: w -= sum_i g[r gstride + i] h_i V_i
+// (basis vectors stored with factors, V_i = f_i stored_i, take g_i = f_i^2)
+// g[r * gstride + idx] = c.v[r] for the RHS the mask keeps
+void set_factor(double* g, int gstride, int idx, const Coefs& c, int nr, Mask mk, hipStream_t s);
 // x += sum_i y_i Z_i (y in FP64 on the device; RHS r: Z + r*ldzr, y + r*ystride, x + r*ldx)
 // over i < m, or i < per->v[r] when per-RHS counts are given
 template <class T, class X>

@@ -199,6 +199,7 @@ static const int DI_WORDS = DI_DONE + MAX_RHS;
 // reduction results per right-hand side: pass-1 h (0..32), ||w||^2 (33),
 // pass-2 h (34..66), ||w||^2 (67)
 static const int RS = 136;
+static const int GSTR = 64;   // basis factors per RHS in dd_ctx::dg (a cycle holds at most 33 basis vectors)
 
 struct dd_ctx {
     hipStream_t s = nullptr;
@@ -226,6 +227,7 @@ struct dd_ctx {
     _Float16* clovinv16 = nullptr;
     int* dflags = nullptr;          // DI_WORDS device ints
     cx<double>* dred = nullptr;     // MAX_RHS * RS reduction results
+    double* dg = nullptr;           // FGMRES basis factors: [nesting level][RHS][GSTR] (squared)
     cx<double>* dy = nullptr;       // MAX_RHS * 32 least-squares solutions
     void* dwork = nullptr;          // reduction partials
     cx<double>* hred = nullptr;     // pinned mirror of dred
@@ -586,6 +588,7 @@ static void layout_fields(dd_ctx* C, const int b[4], const double* gauge_src, co
     C->U32 = U32; C->clov32 = clov32; C->clovinv32 = clovinv32;
     C->dflags = flags;
     C->dred = C->fields.get<cx<double>>((size_t)MAX_RHS * RS);
+    C->dg = C->fields.get<double>((size_t)DD_MAXLEV * MAX_RHS * GSTR);
     C->dy = C->fields.get<cx<double>>((size_t)MAX_RHS * 32);
     C->dwork = C->fields.alloc(reduce_work_size(34, MAX_RHS));
     if (bad) fail(DD_ENUMERIC, "singular clover block on " + std::to_string(bad) + " sites");
@@ -1063,10 +1066,22 @@ static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const dou
     cx<VS>* V = ops.V();
     cx<ZS>* Z = ops.Z();
     Batch bc = with_mask(C, in, word, cyc);
-    Coefs sc{};
+    // The basis is stored unnormalised: V_i = f_i * stored_i, f_i = 1 / |stored_i|
+    // (the Arnoldi vector as the Gram-Schmidt passes leave it), which saves a
+    // pass over every new vector.  The preconditioners are scale invariant, so
+    // the stored Z holds Z_i / f_i, and every coefficient is rescaled: the
+    // Hessenberg entries (host), the Gram-Schmidt updates (device factors
+    // g_i = f_i^2 in dg, one block per nesting level) and the solution update.
+    double* g = C->dg + (size_t)(word / (2 * MAX_RHS)) * MAX_RHS * GSTR;
+    std::vector<std::vector<double>> f(nr, std::vector<double>(m + 1, 0.0));
+    Coefs g0{};
     for (int r = 0; r < nr; r++)
-        if ((cyc >> r) & 1u) { hs[r].reset(beta[r]); sc.v[r] = 1.0 / beta[r]; }
-    bvec_scale<VS>(n, sc, V, n, nr, bc.mask(), C->s);
+        if ((cyc >> r) & 1u) {
+            hs[r].reset(beta[r]);
+            f[r][0] = 1.0 / beta[r];
+            g0.v[r] = f[r][0] * f[r][0];
+        }
+    set_factor(g, GSTR, 0, g0, nr, bc.mask(), C->s);
     Batch cur = with_mask(C, in, word + MAX_RHS, cyc);
     int jend[MAX_RHS] = {0};
     int jmax = 0;
@@ -1082,23 +1097,25 @@ static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const dou
             // CGS with one reorthogonalisation; the first update and the second
             // pass's inner products share one sweep over the basis where it fits
             vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred, C->dwork, nullptr, C->s, rb);
-            if (!vec_update_dot<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 34, C->dwork, C->s, rb)) {
-                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb);
+            if (!vec_update_dot<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 34, C->dwork, C->s, rb, g, GSTR)) {
+                vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb, g, GSTR);
                 vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
             }
-            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb);
+            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb, g, GSTR);
         }
         read_red(C, nr, 68);
         unsigned next = cur.h;
-        Coefs wn{};
+        Coefs gn{};
         for (int r = 0; r < nr; r++) {
             if (!cur.on(r)) continue;
             const cx<double>* h = C->hred + (size_t)r * RS;
             Hess& H = hs[r];
-            for (int i = 0; i <= j; i++) H.h(i, j) = zc(h[i].re + h[34 + i].re, h[i].im + h[34 + i].im);
+            const double fj = f[r][j];
+            for (int i = 0; i <= j; i++)
+                H.h(i, j) = (f[r][i] * fj) * zc(h[i].re + h[34 + i].re, h[i].im + h[34 + i].im);
             double hn = std::sqrt(h[67].re);
             if (!std::isfinite(hn)) fail(DD_ENUMERIC, "non-finite Arnoldi coefficient");
-            H.h(j + 1, j) = hn;
+            H.h(j + 1, j) = fj * hn;
             double res = H.rotate(j);
             its[r]++;
             jend[r] = j + 1;
@@ -1107,18 +1124,22 @@ static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const dou
             if (fixed > 0) stop = its[r] >= fixed;
             else stop = res <= tol[r] * bnorm[r] || its[r] >= maxit;
             if (hn == 0) stop = true;
-            if (stop) next &= ~(1u << r);
-            else wn.v[r] = 1.0 / hn;
+            if (stop) {
+                next &= ~(1u << r);
+            } else {
+                f[r][j + 1] = 1.0 / hn;
+                gn.v[r] = f[r][j + 1] * f[r][j + 1];
+            }
         }
         if (next != cur.h) cur = with_mask(C, in, word + MAX_RHS, next);
-        if (next) bvec_scale<VS>(n, wn, w, n, nr, cur.mask(), C->s);
+        if (next) set_factor(g, GSTR, j + 1, gn, nr, cur.mask(), C->s);
     }
-    // x += Z y per RHS over the columns of its own cycle
+    // x += Z y per RHS over the columns of its own cycle (Z_i = f_i * stored Z_i)
     for (int r = 0; r < nr; r++) {
         cx<double>* y = C->hy + (size_t)r * 32;
         if (!bc.on(r)) continue;
         hs[r].solve(jend[r]);
-        for (int i = 0; i < jend[r]; i++) y[i] = cx<double>{hs[r].y[i].real(), hs[r].y[i].imag()};
+        for (int i = 0; i < jend[r]; i++) y[i] = cx<double>{f[r][i] * hs[r].y[i].real(), f[r][i] * hs[r].y[i].imag()};
     }
     HIPX(hipMemcpyAsync(C->dy, C->hy, sizeof(cx<double>) * 32 * nr, hipMemcpyHostToDevice, C->s));
     Counts jc{};
