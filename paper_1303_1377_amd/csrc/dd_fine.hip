@@ -446,8 +446,8 @@ __device__ __forceinline__ void hop_accum(const FineOp<T, S>& op, int k, int p, 
 // and spinor is fetched from HBM about once.  Without it the grid runs all
 // even sites, then all odd ones, and each link is fetched twice.
 // ---------------------------------------------------------------------------
-template <class T, class S>
-__global__ void __launch_bounds__(256) k_dirac(FineOp<T, S> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+template <class T, class S, class TI = T>
+__global__ void __launch_bounds__(256) k_dirac(FineOp<T, S> op, const cx<TI>* __restrict__ in, cx<T>* __restrict__ out,
                                                long ld, Mask mk) {
     const Geom g = op.g;
     const int w = (op.sched & SCHED_XCD) ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -572,8 +572,8 @@ void fine_oe_hop(const FineOp<T, S>& op, int p, bool pre_a, bool post_inv, doubl
 //   3. out = A psi - acc / 2.
 // LDS: SP [2][12][bvh] + HB [2][6][bvh] complex entries.
 // ---------------------------------------------------------------------------
-template <class T, class S>
-__global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T, S> op, const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+template <class T, class S, class TI = T>
+__global__ void __launch_bounds__(256) k_dirac_lds(FineOp<T, S> op, const cx<TI>* __restrict__ in, cx<T>* __restrict__ out,
                                                    long ld, Mask mk, int nr) {
     extern __shared__ char smem_raw[];
     // one workgroup per (layout block, RHS), RHS fastest in the logical order:
@@ -670,8 +670,8 @@ size_t fine_dirac_lds_bytes(const Geom& g) {
 // the LDS stencil needs whole waves and at most 256 threads per layout block
 static inline bool dirac_lds_fits(const Geom& g) { return 2 * g.bvh >= 64 && 2 * g.bvh <= 256; }
 
-template <class T, class S>
-void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
+template <class T, class S, class TI>
+static void dirac_launch(const FineOp<T, S>& op, const cx<TI>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
     if ((op.sched & SCHED_LDS) && dirac_lds_fits(op.g)) {
         const size_t lds = fine_dirac_lds_bytes<T>(op.g);
         static std::mutex mu;
@@ -681,7 +681,7 @@ void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t
         {
             std::lock_guard<std::mutex> lock(mu);
             if (lds > configured && !refused) {
-                if (hipFuncSetAttribute((const void*)k_dirac_lds<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                if (hipFuncSetAttribute((const void*)k_dirac_lds<T, S, TI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds) == hipSuccess)
                     configured = lds;
                 else {
@@ -692,12 +692,22 @@ void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t
             allowed = configured;
         }
         if (lds <= allowed) {
-            k_dirac_lds<T, S><<<op.g.nblk * nr, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk, nr);
+            k_dirac_lds<T, S, TI><<<op.g.nblk * nr, 2 * op.g.bvh, lds, s>>>(op, in, out, ld, mk, nr);
             return;
         }
     }
     dim3 grid(nblk_of(2L * op.g.vh, 256), nr);
-    k_dirac<T, S><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
+    k_dirac<T, S, TI><<<grid, 256, 0, s>>>(op, in, out, ld, mk);
+}
+
+template <class T, class S>
+void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr, long ld, Mask mk) {
+    dirac_launch<T, S, T>(op, in, out, s, nr, ld, mk);
+}
+
+void fine_dirac_from32(const FineOp<double>& op, const cx<float>* in, cx<double>* out, hipStream_t s, int nr, long ld,
+                       Mask mk) {
+    dirac_launch<double, double, float>(op, in, out, s, nr, ld, mk);
 }
 
 // ---------------------------------------------------------------------------

@@ -109,6 +109,9 @@ void fine_clover_export(const Geom& g, const double* packed, double* canon, hipS
 template <class T, class S>
 void fine_dirac(const FineOp<T, S>& op, const cx<T>* in, cx<T>* out, hipStream_t s, int nr = 1, long ld = 0,
                 Mask mk = all_rhs());
+// the FP64 stencil applied to FP32 input vectors (converted as they are loaded)
+void fine_dirac_from32(const FineOp<double>& op, const cx<float>* in, cx<double>* out, hipStream_t s, int nr = 1,
+                       long ld = 0, Mask mk = all_rhs());
 // one SAP half sweep: blocks listed in `blocks` (all of one colour); the block
 // operator is loaded once and applied to every right-hand side of the batch
 template <class T, class S>

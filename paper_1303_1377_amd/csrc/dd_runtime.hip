@@ -1412,12 +1412,14 @@ struct OuterOps {
         H->vcycle(0, H->nlev - 1, vT(), z, bt);
     }
     void matvec(const cx<T>* z, cx<double>* w, const Batch& bt) {
-        {
-            Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * sizeof(T)));
-            bvec_convert<double, T>(n, z, t64(), n, bt.nr, bt.mask(), C->s);
+        if constexpr (std::is_same<T, float>::value) {
+            // the FP64 stencil reads the FP32 vectors directly
+            Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 * 8 + (24.0 * 4 + 24.0 * 8) * bt.count()));
+            fine_dirac_from32(fine_op<double>(C), z, w, C->s, bt.nr, n, bt.mask());
+        } else {
+            Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
+            fine_dirac<double>(fine_op<double>(C), z, w, C->s, bt.nr, n, bt.mask());
         }
-        Prof pr(C, DD_K_DIRAC64, 2.0 * C->g0.vh * (144 + 48.0 * bt.count()) * 8);
-        fine_dirac<double>(fine_op<double>(C), t64(), w, C->s, bt.nr, n, bt.mask());
     }
     void update(int m, const cx<T>* Z, long ldz, const cx<double>* y, const Batch& bt, const Counts& jc) {
         vec_lincomb<T, double>(n, m, Z, ldz, y, x, C->s, bt.nr, n, 32, n, bt.mask(), &jc);
