@@ -1477,8 +1477,12 @@ __device__ __forceinline__ void row_apply_k(const cx<S>* __restrict__ A, int nd,
 // off take no part (their z is not touched).  NTMAX: the workgroup size the
 // kernel is compiled for (wider batches of loads where fewer threads leave
 // more registers per thread).
+// Registers: the single-precision group of four is held to 128 VGPRs (four
+// waves per SIMD, three workgroups of the 2^4 blocks per CU): t0 and e_o live
+// in LDS and the column batches are shorter.  Latency, not bandwidth, bounds
+// this kernel, and one workgroup per CU left most of the wait exposed.
 template <class T, class S, int NTMAX, int KR>
-__global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
+__global__ void __launch_bounds__(NTMAX, (KR >= 4 && sizeof(T) == 4) ? 4 : 1) k_coarse_sap(CoarseOp<T, S> op, const int* __restrict__ blocks, const cx<T>* __restrict__ b,
                              cx<T>* __restrict__ z, int mr_steps, long ld, int nr, Mask mk) {
     const int q0 = blockIdx.y * KR;
     bool on[KR];
@@ -1501,34 +1505,45 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
     const size_t fs = (size_t)bvh * nd;               // one field of the block
 #pragma unroll
     for (int q = 0; q < KR; q++) lo_[q] = q * fs;
-    constexpr int RB = sizeof(T) == 8 ? (NTMAX <= 512 ? 4 : 2) : (NTMAX <= 512 ? 10 : 5);
+    constexpr int RB = sizeof(T) == 8 ? (NTMAX <= 512 ? 4 : 2) : (NTMAX <= 512 && KR < 4 ? 10 : 5);
     cx<T>* so = reinterpret_cast<cx<T>*>(smem_raw);  // [KR][bvh][nd] odd-site fields
     cx<T>* se = so + KR * fs;                         // even-site fields
     cx<T>* tm = se + KR * fs;                         // temporaries (even)
-    double* red = reinterpret_cast<double*>(tm + KR * fs);
+    cx<T>* st = tm + KR * fs;                         // t0 (even), kept for the final update
+    cx<T>* seo = st + KR * fs;                        // the odd-site correction e_o
+    const int nw = (blockDim.x + 63) >> 6;
+    double* red = reinterpret_cast<double*>(seo + KR * fs);  // [KR][nw][3]
+    int* nbl = reinterpret_cast<int*>(red + 3 * KR * nw);   // [2][8][bvh] neighbour indices
     const int blk = blocks[blockIdx.x];
     const int base = blk << g.lbvh;
     const int t = threadIdx.x;
     const bool act = t < bvh * nd;
     const int l = act ? t / nd : 0, r = act ? t % nd : 0;
     const int i = base + l;
-    int xe[4], xo[4], nbe[8], nbo[8];
-    cb_coords(g, 0, i, xe);
-    cb_coords(g, 1, i, xo);
-    for (int k = 0; k < 8; k++) {
-        int y[4];
-        nb_coords(g, xe, k, y);
-        nbe[k] = cb_index(g, y);
-        nb_coords(g, xo, k, y);
-        nbo[k] = cb_index(g, y);
+    if (act && r == 0) {
+        int xe[4], xo[4];
+        cb_coords(g, 0, i, xe);
+        cb_coords(g, 1, i, xo);
+        for (int k = 0; k < 8; k++) {
+            int y[4];
+            nb_coords(g, xe, k, y);
+            nbl[k * bvh + l] = cb_index(g, y);
+            nb_coords(g, xo, k, y);
+            nbl[(8 + k) * bvh + l] = cb_index(g, y);
+        }
     }
+    // the neighbour indices of even (odd) sites: nbe[k * bvh] (nbo[k * bvh])
+    const int* nbe = nbl + l;
+    const int* nbo = nbl + 8 * bvh + l;
+    __syncthreads();
     const size_t ge = i, go = (size_t)g.vh + i;
     // sum over the 8 hops of site gs (parity p) applied to the global vectors
     auto hop_glob = [&](size_t gs, int p, const int* nbj, cx<T> (&h)[KR]) {
 #pragma unroll
         for (int q = 0; q < KR; q++) h[q] = czero<T>();
+#pragma unroll 1
         for (int k = 0; k < 8; k++) {
-            size_t gy = (size_t)(1 - p) * g.vh + nbj[k];
+            size_t gy = (size_t)(1 - p) * g.vh + nbj[k * bvh];
             cx<T> u[KR];
             row_apply_k<T, S, KR, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, z + gy * nd, go_, u);
 #pragma unroll
@@ -1539,18 +1554,23 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
     auto hop_int = [&](size_t gs, const int* nbj, const cx<T>* buf, cx<T> (&h)[KR]) {
 #pragma unroll
         for (int q = 0; q < KR; q++) h[q] = czero<T>();
+#pragma unroll 1
         for (int k = 0; k < 8; k++) {
-            if ((nbj[k] >> g.lbvh) != blk) continue;
+            const int j = nbj[k * bvh];
+            if ((j >> g.lbvh) != blk) continue;
             cx<T> u[KR];
-            row_apply_k<T, S, KR, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (nbj[k] - base) * nd, lo_, u);
+            row_apply_k<T, S, KR, RB>(op.M + (gs * 9 + 1 + k) * nn, nd, r, buf + (j - base) * nd, lo_, u);
 #pragma unroll
             for (int q = 0; q < KR; q++) h[q] += u[q];
         }
     };
     const int me = l * nd + r;
-    cx<T> t0[KR], rho[KR], eo[KR], sv[KR], h[KR], u[KR];
+    cx<T> rho[KR], sv[KR], h[KR], u[KR];
 #pragma unroll
-    for (int q = 0; q < KR; q++) { t0[q] = rho[q] = eo[q] = sv[q] = czero<T>(); }
+    for (int q = 0; q < KR; q++) {
+        rho[q] = sv[q] = czero<T>();
+        if (act) seo[q * fs + me] = czero<T>();
+    }
     // t0_e = Minv (b_e - H z) - z_e
     if (act) {
         hop_glob(ge, 0, nbe, h);
@@ -1562,8 +1582,9 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
         row_apply_k<T, S, KR, RB>(op.Minv + ge * nn, nd, r, tm + l * nd, lo_, u);
 #pragma unroll
         for (int q = 0; q < KR; q++) {
-            t0[q] = u[q] - z[go_[q] + ge * nd + r];
-            se[q * fs + me] = t0[q];
+            const cx<T> t0 = u[q] - z[go_[q] + ge * nd + r];
+            se[q * fs + me] = t0;
+            st[q * fs + me] = t0;
             so[q * fs + me] = z[go_[q] + go * nd + r];
         }
     }
@@ -1582,7 +1603,7 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
 #pragma unroll
         for (int q = 0; q < KR; q++) so[q * fs + me] = rho[q];
     __syncthreads();
-    const int lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const int lane = t & 63, w = t >> 6;
     for (int it = 0; it < mr_steps; it++) {
         if (act) {
             hop_int(ge, nbe, so, h);
@@ -1619,20 +1640,20 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
             for (int v = 0; v < nw; v++) { a0 += red[(q * nw + v) * 3]; a1 += red[(q * nw + v) * 3 + 1]; a2 += red[(q * nw + v) * 3 + 2]; }
             if (a2 > 0 && act) {
                 cx<T> alpha = {T(a0 / a2), T(a1 / a2)};
-                eo[q] += alpha * rho[q];
+                seo[q * fs + me] += alpha * rho[q];
                 rho[q] -= alpha * sv[q];
             }
         }
         __syncthreads();
         if (act)
 #pragma unroll
-            for (int q = 0; q < KR; q++) so[q * fs + me] = (it + 1 < mr_steps) ? rho[q] : eo[q];
+            for (int q = 0; q < KR; q++) so[q * fs + me] = (it + 1 < mr_steps) ? rho[q] : seo[q * fs + me];
         __syncthreads();
     }
     if (mr_steps == 0) {
         if (act)
 #pragma unroll
-            for (int q = 0; q < KR; q++) so[q * fs + me] = eo[q];
+            for (int q = 0; q < KR; q++) so[q * fs + me] = seo[q * fs + me];
         __syncthreads();
     }
     if (act) {
@@ -1646,10 +1667,19 @@ __global__ void __launch_bounds__(NTMAX) k_coarse_sap(CoarseOp<T, S> op, const i
 #pragma unroll
         for (int q = 0; q < KR; q++) {
             if (!on[q]) continue;
-            z[q * ld + ge * nd + r] += t0[q] - u[q];
-            z[q * ld + go * nd + r] += eo[q];
+            z[q * ld + ge * nd + r] += st[q * fs + me] - u[q];
+            z[q * ld + go * nd + r] += seo[q * fs + me];
         }
     }
+}
+
+// LDS of one member of a multi-RHS group: five block fields (odd sites, even
+// sites, a temporary, t0, e_o) and the partial sums of three reductions per
+// wave
+template <class T>
+static size_t coarse_sap_member_lds(int bvh, int nd) {
+    const int nw = (bvh * nd + 63) / 64;
+    return 5 * sizeof(cx<T>) * bvh * nd + 3 * sizeof(double) * nw;
 }
 
 template <class T, class S, int KR>
@@ -1662,7 +1692,7 @@ static void coarse_sap_launch(const CoarseOp<T, S>& op, const int* blocks, int n
         if (nt <= 512) k_coarse_sap1<T, S, 512><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
         else k_coarse_sap1<T, S, 1024><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, mk);
     } else {
-        const size_t lds = 3 * KR * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * KR * sizeof(double) * (nt / 64);
+        const size_t lds = coarse_sap_member_lds<T>(op.g.bvh, op.nd) * KR + 16 * sizeof(int) * op.g.bvh;
         dim3 grid(nblocks, (nr + KR - 1) / KR);
         if (nt <= 512) k_coarse_sap<T, S, 512, KR><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, nr, mk);
         else k_coarse_sap<T, S, 1024, KR><<<grid, nt, lds, s>>>(op, blocks, b, z, mr_steps, ld, nr, mk);
@@ -1686,12 +1716,11 @@ void coarse_sap_half(const CoarseOp<T, S>& op, const int* blocks, int nblocks, c
         else k_coarse_sap_t<T, S, 1024, 2><<<grid, nt, lds, s>>>(op, blocks, tab, b, z, mr_steps, ld, mk);
         return;
     }
-    // LDS of a group: three block fields per member (kept within the 64 KB
-    // a workgroup gets without an opt-in)
-    const int nw = (op.g.bvh * op.nd + 63) / 64;
-    const size_t member = 3 * sizeof(cx<T>) * op.g.bvh * op.nd + 3 * sizeof(double) * nw;
-    if (nr >= 3 && 4 * member <= 65536) coarse_sap_launch<T, S, 4>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
-    else if (nr >= 2 && 2 * member <= 65536) coarse_sap_launch<T, S, 2>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
+    // LDS of a group: five block fields per member and the neighbour table
+    // (kept within the 64 KB a workgroup gets without an opt-in)
+    const size_t member = coarse_sap_member_lds<T>(op.g.bvh, op.nd), nbt = 16 * sizeof(int) * op.g.bvh;
+    if (nr >= 3 && 4 * member + nbt <= 65536) coarse_sap_launch<T, S, 4>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
+    else if (nr >= 2 && 2 * member + nbt <= 65536) coarse_sap_launch<T, S, 2>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
     else coarse_sap_launch<T, S, 1>(op, blocks, nblocks, b, z, mr_steps, s, nr, ld, mk);
 }
 
