@@ -38,7 +38,7 @@ CLASSES = {
     "sap": (("void dd::k_sap_fine<double, double, dd::cx<double>*, 1>(",
              "void dd::k_sap_fine<float, float, dd::cx<float>*, 2>(",
              "void dd::k_sap_fine<double, double, 1>("), "paper_1303_1377_amd/csrc/dd_fine.hip"),
-    "dirac64": (("void dd::k_dirac<double, double>(", "void dd::k_dirac_lds<double, double>("),
+    "dirac64": (("void dd::k_dirac<double, double", "void dd::k_dirac_lds<double, double"),
                 "paper_1303_1377_amd/csrc/dd_fine.hip"),
     "restrict": (("void dd::k_restrict_fine<double, double, 256",
                   "void dd::k_restrict_fine<float, float, 256"), "paper_1303_1377_amd/csrc/dd_fine.hip"),

@@ -2451,32 +2451,38 @@ static double time_prec(dd_ctx* C, Hier<T>& H, int cls, int reps) {
     return ms / reps;
 }
 
+// mean duration of the FP64 stencil applied to nr vectors at once (or of a
+// plain FP64 copy of one vector, DD_K_BLAS) on random data
+static double time_dirac64(dd_ctx* ctx, int cls, int nr, int reps) {
+    const long n = 24L * ctx->g0.vh;
+    Arena tmp;
+    cx<double>* a = tmp.get<cx<double>>(n * nr);
+    cx<double>* b = tmp.get<cx<double>>(n * nr);
+    fine_random<double>(ctx->g0, nr, 12345ULL, 7, a, ctx->s);
+    FineOp<double> op = fine_op<double>(ctx);
+    auto launch = [&]() {
+        if (cls == DD_K_BLAS) vec_convert<double, double>(n, a, b, ctx->s);
+        else fine_dirac<double>(op, a, b, ctx->s, nr, n, all_rhs());
+    };
+    launch();
+    hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
+    HIPX(hipEventRecord(e0, ctx->s));
+    for (int r = 0; r < reps; r++) launch();
+    HIPX(hipEventRecord(e1, ctx->s));
+    HIPX(hipGetLastError());
+    HIPX(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPX(hipEventElapsedTime(&ms, e0, e1));
+    ctx->ev_pool.push_back(e0);
+    ctx->ev_pool.push_back(e1);
+    return ms / reps;
+}
+
 dd_status dd_time_kernel(dd_ctx* ctx, int cls, int reps, double* avg_ms) {
     ABI_TRY(ctx)
     if (reps < 1 || !avg_ms) fail(DD_EINVAL, "reps >= 1 and avg_ms required");
     if (cls == DD_K_DIRAC64 || cls == DD_K_BLAS) {
-        const long n = 24L * ctx->g0.vh;
-        Arena tmp;
-        cx<double>* a = tmp.get<cx<double>>(n);
-        cx<double>* b = tmp.get<cx<double>>(n);
-        fine_random<double>(ctx->g0, 1, 12345ULL, 7, a, ctx->s);
-        FineOp<double> op = fine_op<double>(ctx);
-        auto launch = [&]() {
-            if (cls == DD_K_BLAS) vec_convert<double, double>(n, a, b, ctx->s);
-            else fine_dirac<double>(op, a, b, ctx->s);
-        };
-        launch();
-        hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
-        HIPX(hipEventRecord(e0, ctx->s));
-        for (int r = 0; r < reps; r++) launch();
-        HIPX(hipEventRecord(e1, ctx->s));
-        HIPX(hipGetLastError());
-        HIPX(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPX(hipEventElapsedTime(&ms, e0, e1));
-        ctx->ev_pool.push_back(e0);
-        ctx->ev_pool.push_back(e1);
-        *avg_ms = ms / reps;
+        *avg_ms = time_dirac64(ctx, cls, 1, reps);
         return DD_OK;
     }
     if (cls == DD_K_COARSE) {
@@ -2761,11 +2767,12 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     const int keep = ctx->sched & (SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP);
     double best = 0;
     int pick = ctx->sched;
+    // the outer stencil is timed at the batch width of the solves (the
+    // XCD-ordered schedules let the workgroups of one block's RHS share L2)
+    const int nr = ctx->configured ? std::max(ctx->R, 1) : 1;
     for (int sc = 0; sc < nsched; sc++) {
         set_sched(ctx, sc | keep);
-        double ms = 0, t = 0;
-        if (dd_time_kernel(ctx, DD_K_DIRAC64, reps, &t) != DD_OK) return DD_EDEVICE;
-        ms += t;
+        double ms = time_dirac64(ctx, DD_K_DIRAC64, nr, reps) / nr, t = 0;
         if (ctx->configured) {
             if (dd_time_kernel(ctx, DD_K_SAP, reps, &t) != DD_OK) return DD_EDEVICE;
             ms += std::max(ctx->p.nu, 1) * t;
