@@ -168,6 +168,11 @@ __device__ __forceinline__ f32x4 mma(f16x4 a, f16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
+// columns of X staged in LDS for a batch of nr right-hand sides (the tile
+// has 16): a batch of four needs a quarter of the LDS of sixteen, so more
+// workgroups share a CU
+__host__ __device__ __forceinline__ int mfma_cols(int nr) { return nr <= 4 ? 4 : (nr <= 8 ? 8 : 16); }
+
 // A fragment of a column-major nd x nd block: row r, columns c0 .. c0+K/4-1
 // of this lane's k-slice; zero outside the block.
 template <class S>
@@ -189,19 +194,22 @@ __device__ __forceinline__ void a_frag(const cx<S>* __restrict__ A, int nd, int 
     }
 }
 
-// B fragment from the staged X [ndk][16] (split re / im planes of type S)
+// B fragment from the staged X [ndk][xs] (split re / im planes of type S):
+// xs columns are staged (the batch rounded up to 4, 8 or 16); the lanes of
+// the tile's other columns take zeros
 template <class S>
-__device__ __forceinline__ void b_frag(const S* __restrict__ Xre, const S* __restrict__ Xim, int c0, int j,
+__device__ __forceinline__ void b_frag(const S* __restrict__ Xre, const S* __restrict__ Xim, int c0, int j, int xs,
                                        typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& re,
                                        typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type& im) {
+    const bool on = j < xs;
     if constexpr (std::is_same<S, float>::value) {
-        re = Xre[c0 * 16 + j];
-        im = Xim[c0 * 16 + j];
+        re = on ? Xre[c0 * xs + j] : 0.f;
+        im = on ? Xim[c0 * xs + j] : 0.f;
     } else {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            re[q] = Xre[(c0 + q) * 16 + j];
-            im[q] = Xim[(c0 + q) * 16 + j];
+            re[q] = on ? Xre[(c0 + q) * xs + j] : _Float16(0);
+            im[q] = on ? Xim[(c0 + q) * xs + j] : _Float16(0);
         }
     }
 }
@@ -209,7 +217,7 @@ __device__ __forceinline__ void b_frag(const S* __restrict__ Xre, const S* __res
 // C += A X over the ndk rows of X for one 16-row tile
 template <class S>
 __device__ __forceinline__ void tile_mma(const cx<S>* __restrict__ A, int nd, int ndk, int r, int lane, float sgn,
-                                         const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
+                                         const S* Xre, const S* Xim, int xs, f32x4& cre, f32x4& cim) {
     constexpr int K = MfmaK<S>::K;
     constexpr int KL = K / 4;   // k entries per lane
     const int q = lane >> 4, j = lane & 15;
@@ -217,7 +225,7 @@ __device__ __forceinline__ void tile_mma(const cx<S>* __restrict__ A, int nd, in
         const int c0 = k0 + q * KL;
         typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type are, aim, bre, bim, naim;
         a_frag<S>(A, nd, r, c0, sgn, are, aim);
-        b_frag<S>(Xre, Xim, c0, j, bre, bim);
+        b_frag<S>(Xre, Xim, c0, j, xs, bre, bim);
         naim = -aim;
         cre = mma(are, bre, cre);
         cre = mma(naim, bim, cre);
@@ -231,7 +239,7 @@ __device__ __forceinline__ void tile_mma(const cx<S>* __restrict__ A, int nd, in
 // NDK / K loads in flight instead of one per instruction step.
 template <class S, int NDK>
 __device__ __forceinline__ void tile_mma_fixed(const cx<S>* __restrict__ A, int nd, int r, int lane, float sgn,
-                                               const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
+                                               const S* Xre, const S* Xim, int xs, f32x4& cre, f32x4& cim) {
     constexpr int K = MfmaK<S>::K;
     constexpr int KL = K / 4;
     constexpr int NS = NDK / K;
@@ -242,7 +250,7 @@ __device__ __forceinline__ void tile_mma_fixed(const cx<S>* __restrict__ A, int 
 #pragma unroll
     for (int t = 0; t < NS; t++) {
         typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type bre, bim, naim;
-        b_frag<S>(Xre, Xim, t * K + q * KL, j, bre, bim);
+        b_frag<S>(Xre, Xim, t * K + q * KL, j, xs, bre, bim);
         naim = -aim[t];
         cre = mma(are[t], bre, cre);
         cre = mma(naim, bim, cre);
@@ -267,14 +275,14 @@ __device__ __forceinline__ void tile_load(const cx<S>* __restrict__ A, int nd, i
     for (int t = 0; t < TileFrags<S, NDK>::NS; t++) a_frag<S>(A, nd, r, t * K + q * KL, sgn, f.re[t], f.im[t]);
 }
 template <class S, int NDK>
-__device__ __forceinline__ void tile_product(const TileFrags<S, NDK>& f, int lane, const S* Xre, const S* Xim,
+__device__ __forceinline__ void tile_product(const TileFrags<S, NDK>& f, int lane, const S* Xre, const S* Xim, int xs,
                                              f32x4& cre, f32x4& cim) {
     constexpr int K = MfmaK<S>::K, KL = K / 4;
     const int q = lane >> 4, j = lane & 15;
 #pragma unroll
     for (int t = 0; t < TileFrags<S, NDK>::NS; t++) {
         typename std::conditional<std::is_same<S, float>::value, float, f16x4>::type bre, bim, naim;
-        b_frag<S>(Xre, Xim, t * K + q * KL, j, bre, bim);
+        b_frag<S>(Xre, Xim, t * K + q * KL, j, xs, bre, bim);
         naim = -f.im[t];
         cre = mma(f.re[t], bre, cre);
         cre = mma(naim, bim, cre);
@@ -287,9 +295,9 @@ __device__ __forceinline__ void tile_product(const TileFrags<S, NDK>& f, int lan
 // extent is the production one (NDK > 0), the loop otherwise
 template <class S, int NDK>
 __device__ __forceinline__ void tile_any(const cx<S>* __restrict__ A, int nd, int ndk, int r, int lane, float sgn,
-                                         const S* Xre, const S* Xim, f32x4& cre, f32x4& cim) {
-    if constexpr (NDK > 0) tile_mma_fixed<S, NDK>(A, nd, r, lane, sgn, Xre, Xim, cre, cim);
-    else tile_mma<S>(A, nd, ndk, r, lane, sgn, Xre, Xim, cre, cim);
+                                         const S* Xre, const S* Xim, int xs, f32x4& cre, f32x4& cim) {
+    if constexpr (NDK > 0) tile_mma_fixed<S, NDK>(A, nd, r, lane, sgn, Xre, Xim, xs, cre, cim);
+    else tile_mma<S>(A, nd, ndk, r, lane, sgn, Xre, Xim, xs, cre, cim);
 }
 
 template <class S, int NDK = 0>
@@ -304,8 +312,9 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     const Geom g = op.g;
     const int nd = op.nd;
     const int ndk = (nd + K - 1) / K * K;          // k extent padded to the instruction
-    S* Xre = reinterpret_cast<S*>(smem_raw);        // [9][ndk][16]
-    S* Xim = Xre + 9 * ndk * 16;
+    const int xs = mfma_cols(nr);                   // staged columns
+    S* Xre = reinterpret_cast<S*>(smem_raw);        // [9][ndk][xs]
+    S* Xim = Xre + 9 * ndk * xs;
     int p, i;
     if (par < 0) { p = blockIdx.x >= g.vh; i = blockIdx.x - p * g.vh; }
     else { p = par; i = blockIdx.x; }
@@ -336,8 +345,8 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     if constexpr (F16) {
         if (t < 16) sc[t] = 0.f;
         __syncthreads();
-        for (int e = t; e < ns * 16 * ndk; e += nt) {
-            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+        for (int e = t; e < ns * xs * ndk; e += nt) {
+            const int sl = e / (xs * ndk), rem = e - sl * xs * ndk;
             const int j = rem / ndk, c = rem - j * ndk;
             if (c < nd && j < nr && mk.on(j)) {
                 const cx<float> v = vin[sl][(size_t)j * ld + c];
@@ -346,23 +355,23 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
             }
         }
         __syncthreads();
-        for (int e = t; e < ns * 16 * ndk; e += nt) {
-            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+        for (int e = t; e < ns * xs * ndk; e += nt) {
+            const int sl = e / (xs * ndk), rem = e - sl * xs * ndk;
             const int j = rem / ndk, c = rem - j * ndk;
             cx<float> v = czero<float>();
             if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
             const float inv = sc[j] > 0.f ? 1.f / sc[j] : 0.f;
-            Xre[(sl * ndk + c) * 16 + j] = S(v.re * inv);
-            Xim[(sl * ndk + c) * 16 + j] = S(v.im * inv);
+            Xre[(sl * ndk + c) * xs + j] = S(v.re * inv);
+            Xim[(sl * ndk + c) * xs + j] = S(v.im * inv);
         }
     } else {
-        for (int e = t; e < ns * 16 * ndk; e += nt) {
-            const int sl = e / (16 * ndk), rem = e - sl * 16 * ndk;
+        for (int e = t; e < ns * xs * ndk; e += nt) {
+            const int sl = e / (xs * ndk), rem = e - sl * xs * ndk;
             const int j = rem / ndk, c = rem - j * ndk;
             cx<float> v = czero<float>();
             if (c < nd && j < nr && mk.on(j)) v = vin[sl][(size_t)j * ld + c];
-            Xre[(sl * ndk + c) * 16 + j] = S(v.re);
-            Xim[(sl * ndk + c) * 16 + j] = S(v.im);
+            Xre[(sl * ndk + c) * xs + j] = S(v.re);
+            Xim[(sl * ndk + c) * xs + j] = S(v.im);
         }
     }
     __syncthreads();
@@ -378,14 +387,14 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
             tile_load<S, NDK>(mat[0], nd, r, lane, sgn_of(0), fa);
             for (int sl = 0; sl < ns; sl += 2) {
                 if (sl + 1 < ns) tile_load<S, NDK>(mat[sl + 1], nd, r, lane, sgn_of(sl + 1), fb);
-                tile_product<S, NDK>(fa, lane, Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
+                tile_product<S, NDK>(fa, lane, Xre + sl * ndk * xs, Xim + sl * ndk * xs, xs, cre, cim);
                 if (sl + 1 >= ns) break;
                 if (sl + 2 < ns) tile_load<S, NDK>(mat[sl + 2], nd, r, lane, sgn_of(sl + 2), fa);
-                tile_product<S, NDK>(fb, lane, Xre + (sl + 1) * ndk * 16, Xim + (sl + 1) * ndk * 16, cre, cim);
+                tile_product<S, NDK>(fb, lane, Xre + (sl + 1) * ndk * xs, Xim + (sl + 1) * ndk * xs, xs, cre, cim);
             }
         } else {
             for (int sl = 0; sl < ns; sl++)
-                tile_mma<S>(mat[sl], nd, ndk, r, lane, sgn_of(sl), Xre + sl * ndk * 16, Xim + sl * ndk * 16, cre, cim);
+                tile_mma<S>(mat[sl], nd, ndk, r, lane, sgn_of(sl), Xre + sl * ndk * xs, Xim + sl * ndk * xs, xs, cre, cim);
         }
     }
     // result rows 16w + 4q + v, column j
@@ -422,7 +431,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
     // post multiplication by the self-block inverse: stage the result as a new X
     // (FP16 form: scaled per column as above)
     __syncthreads();
-    for (int e = t; e < ndk * 16; e += nt) {   // clear (padding rows stay zero)
+    for (int e = t; e < ndk * xs; e += nt) {   // clear (padding rows stay zero)
         Xre[e] = S(0.f);
         Xim[e] = S(0.f);
     }
@@ -444,16 +453,16 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int row = 16 * w + 4 * q + v;
-            if (row < nd) {
-                Xre[row * 16 + j] = S(cre[v] * inv);
-                Xim[row * 16 + j] = S(cim[v] * inv);
+            if (row < nd && j < xs) {
+                Xre[row * xs + j] = S(cre[v] * inv);
+                Xim[row * xs + j] = S(cim[v] * inv);
             }
         }
     }
     __syncthreads();
     if (w < ntile) {
         f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
-        tile_any<S, NDK>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, dre, dim);
+        tile_any<S, NDK>(op.Minv + gs * nn, nd, ndk, r, lane, 1.f, Xre, Xim, xs, dre, dim);
         if constexpr (F16) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -472,10 +481,10 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mfma(CoarseOp<float, S> op
 }
 
 template <class S>
-static size_t mfma_lds_bytes(int nd) {
+static size_t mfma_lds_bytes(int nd, int nr) {
     const int K = MfmaK<S>::K;
     const int ndk = (nd + K - 1) / K * K;
-    return 2 * sizeof(S) * 9 * (size_t)ndk * 16;
+    return 2 * sizeof(S) * 9 * (size_t)ndk * mfma_cols(nr);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,10 +643,10 @@ void coarse_apply(const CoarseOp<T, S>& op, int par, int self_mode, const cx<T>*
             constexpr int K = MfmaK<S>::K;
             constexpr int NDK40 = (40 + K - 1) / K * K;
             if (op.nd == 40)
-                k_coarse_apply_mfma<S, NDK40><<<nsite, 64 * 3, mfma_lds_bytes<S>(op.nd), s>>>(
+                k_coarse_apply_mfma<S, NDK40><<<nsite, 64 * 3, mfma_lds_bytes<S>(op.nd, nr), s>>>(
                     op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
             else
-                k_coarse_apply_mfma<S><<<nsite, 64 * ((op.nd + 15) / 16), mfma_lds_bytes<S>(op.nd), s>>>(
+                k_coarse_apply_mfma<S><<<nsite, 64 * ((op.nd + 15) / 16), mfma_lds_bytes<S>(op.nd, nr), s>>>(
                     op, par, self_mode, in1, hop_sign, in2, post_inv ? 1 : 0, out, mk, ld, nr);
             return;
         }
