@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
                                                         const cx<double>* __restrict__ hpart, cx<double>* hout,
                                                         cx<T>* __restrict__ w, cx<double>* __restrict__ npart, long ldr,
                                                         long ldw, Mask mk, GivensArgs ga, const double* __restrict__ g,
-                                                        int gstride) {
+                                                        int gstride, cx<float>* __restrict__ wc, long ldc) {
     const int c = blockIdx.x, r = blockIdx.y;
     if (!mk.on(r)) return;
     const double* scv = ga.st ? ga.st[r].sc : nullptr;
@@ -206,6 +206,7 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
     __syncthreads();
     const cx<T>* Vr = V + r * ldr;
     cx<T>* wr = w + r * ldw;
+    cx<float>* wcr = wc ? wc + r * ldc : nullptr;
     const long e0 = c * chunk, e1 = (e0 + chunk < n) ? e0 + chunk : n;
     double acc = 0;
     for (long e = e0 + threadIdx.x; e < e1; e += RED_NT) {
@@ -221,6 +222,7 @@ __global__ void __launch_bounds__(RED_NT) k_update_norm(long n, long chunk, int 
                 if (i0 + u < m) we -= hh[i0 + u] * vv[u];
         }
         wr[e] = we;
+        if (wcr) wcr[e] = ccast<float>(we);
         acc += (double)norm2(we);
     }
     acc = block_sum256(acc, sh);
@@ -354,7 +356,8 @@ bool vec_update_dot(long n, int m, const cx<T>* V, long ldv, const cx<double>* h
 
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
-                     void* work, int* count, hipStream_t s, RedBatch rb, const double* g, int gstride) {
+                     void* work, int* count, hipStream_t s, RedBatch rb, const double* g, int gstride, cx<float>* wc,
+                     long ldc) {
     (void)count;
     const int nc = red_chunks(n);
     const long chunk = (n + nc - 1) / nc;
@@ -362,9 +365,11 @@ void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* 
     do {
         int mm = (m - i0 < MAXM) ? m - i0 : MAXM;
         dim3 grid(nc, rb.nr);
+        // the FP32 copy is written by the launch that leaves w final
+        const bool last = i0 + mm >= m;
         k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, mm, V + (size_t)i0 * ldv, ldv, h + i0, rb.ostride, nullptr,
                                                  nullptr, w, npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk, GivensArgs{},
-                                                 g ? g + i0 : nullptr, gstride);
+                                                 g ? g + i0 : nullptr, gstride, last ? wc : nullptr, ldc);
         i0 += mm;
     } while (i0 < m);
     dim3 g2(1, rb.nr);
@@ -565,7 +570,7 @@ void vec_update_norm_givens(long n, int m, const cx<T>* V, long ldv, cx<T>* w, c
     dim3 grid(nc, rb.nr);
     k_update_norm<T><<<grid, RED_NT, 0, s>>>(n, chunk, nc, m, V, ldv, nullptr, rb.ostride, hpart_of(work), res, w,
                                              npart_of(work, rb.nr), rb.ldr, rb.ldw, rb.mk,
-                                             GivensArgs{st, j, done, normalize ? 1 : 0}, nullptr, 0);
+                                             GivensArgs{st, j, done, normalize ? 1 : 0}, nullptr, 0, nullptr, 0);
 }
 
 template <class T, class X>
@@ -665,7 +670,7 @@ void set_flags(int* d, unsigned bits, int n, hipStream_t s) { k_set_flags<<<1, 6
     template bool vec_update_dot<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*,       \
                                     hipStream_t, RedBatch, const double*, int);                                    \
     template void vec_update_norm<T>(long, int, const cx<T>*, long, const cx<double>*, cx<T>*, cx<double>*, void*, int*, \
-                                     hipStream_t, RedBatch, const double*, int);                                   \
+                                     hipStream_t, RedBatch, const double*, int, cx<float>*, long);                 \
     template void vec_finite_check<T>(long, const cx<T>*, int*, hipStream_t);                                     \
     template void bvec_sub<T>(long, const cx<T>*, const cx<T>*, cx<T>*, long, int, Mask, hipStream_t);            \
     template void bvec_scale<T>(long, const Coefs&, cx<T>*, long, int, Mask, hipStream_t);                         \

@@ -239,11 +239,12 @@ template <class T>
 void vec_multidot(long n, int m, const cx<T>* V, long ldv, const cx<T>* w, cx<double>* out, void* work, int* count,
                   hipStream_t s, RedBatch rb = single_rhs());
 // w -= sum_i h_i V_i (h in FP64 on the device, RHS r at h + r*ostride), then
-// out[0].re = ||w||^2
+// out[0].re = ||w||^2; with wc, the final w is also written in FP32 to
+// wc + r*ldc (the input of a single-precision preconditioner)
 template <class T>
 void vec_update_norm(long n, int m, const cx<T>* V, long ldv, const cx<double>* h, cx<T>* w, cx<double>* out,
                      void* work, int* count, hipStream_t s, RedBatch rb = single_rhs(), const double* g = nullptr,
-                     int gstride = 0);
+                     int gstride = 0, cx<float>* wc = nullptr, long ldc = 0);
 // w -= sum_i h_i V_i and out_i = V_i^H w (the updated w) in one sweep over the
 // basis: the first projection of a Gram-Schmidt pass and the inner products of
 // its reorthogonalisation.  Returns false (nothing done) for m above its limit.

@@ -1058,6 +1058,13 @@ struct KrylovResult {
 // when its estimate reaches tol[r] * bnorm[r], at maxit or at `fixed`
 // iterations), x += Z y, then the true residual replaces V_0 and beta[r].
 // its[r] counts the iterations of RHS r over all cycles.
+// Ops with prec_copy(w) take the next preconditioner input as an FP32 copy
+// that the last Gram-Schmidt pass writes while it leaves w final
+template <class Ops, class = void>
+struct HasPrecCopy : std::false_type {};
+template <class Ops>
+struct HasPrecCopy<Ops, std::void_t<decltype(std::declval<Ops&>().prec_copy((const void*)nullptr))>> : std::true_type {};
+
 template <class VS, class ZS, class Ops>
 static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const double* tol, int maxit, long fixed,
                          const Batch& in, int word, unsigned cyc, std::vector<Hess>& hs, double* beta,
@@ -1101,7 +1108,10 @@ static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const dou
                 vec_update_norm<VS>(n, j + 1, V, ldv, C->dred, w, C->dred + 33, C->dwork, nullptr, C->s, rb, g, GSTR);
                 vec_multidot<VS>(n, j + 1, V, ldv, w, C->dred + 34, C->dwork, nullptr, C->s, rb);
             }
-            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb, g, GSTR);
+            cx<float>* wc = nullptr;
+            if constexpr (HasPrecCopy<Ops>::value) wc = ops.prec_copy(w);
+            vec_update_norm<VS>(n, j + 1, V, ldv, C->dred + 34, w, C->dred + 67, C->dwork, nullptr, C->s, rb, g, GSTR,
+                                wc, n);
         }
         read_red(C, nr, 68);
         unsigned next = cur.h;
@@ -1404,11 +1414,22 @@ struct OuterOps {
     cx<T>* Z() { return Zb; }
     cx<T>* vT() { return reinterpret_cast<cx<T>*>(C->ot); }    // preconditioner-precision copies of v_j
     cx<double>* t64() { return C->ot + (size_t)C->R * n; }
+    // the FP32 preconditioner takes its input from the Gram-Schmidt pass that
+    // finished the vector (fgmres_cycle passes vT() to it): no conversion pass
+    const void* copied = nullptr;
+    cx<float>* prec_copy(const void* w) {
+        if constexpr (std::is_same<T, float>::value) {
+            copied = w;
+            return vT();
+        }
+        return nullptr;
+    }
     void precond(const cx<double>* v, cx<T>* z, const Batch& bt) {
-        {
+        if (v != copied) {
             Prof pr(C, DD_K_BLAS, (double)bt.count() * n * (16 + 2 * sizeof(T)));
             bvec_convert<T, double>(n, v, vT(), n, bt.nr, bt.mask(), C->s);
         }
+        copied = nullptr;
         H->vcycle(0, H->nlev - 1, vT(), z, bt);
     }
     void matvec(const cx<T>* z, cx<double>* w, const Batch& bt) {
