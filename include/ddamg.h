@@ -371,12 +371,17 @@ long long dd_device_bytes(const dd_ctx *ctx);
  *                   barriers between the phases of an Arnoldi step); falls
  *                   back to DD_SCHED_GRAPH / single launches when the device
  *                   does not admit the grid.  Results agree to rounding.
+ *   DD_SCHED_COOP_ABORT  for tests of the fallback: every cooperative cycle
+ *                   starts with its abort flag raised, so its first grid
+ *                   barrier gives up, all workgroups leave, and the coarse
+ *                   solve reruns with step launches (the results of a
+ *                   schedule without DD_SCHED_COOP)
  * The default is DD_SCHED_LDS | DD_SCHED_XCD | DD_SCHED_GRAPH with the matrix
  * cores on; dd_autotune_coarse decides about DD_SCHED_GRAPH, DD_SCHED_COOP and
  * the cooperative grid.
  * ------------------------------------------------------------------------- */
 enum { DD_SCHED_FUSED = 1, DD_SCHED_XCD = 2, DD_SCHED_LDS = 4, DD_SCHED_NO_MFMA = 8, DD_SCHED_GRAPH = 16,
-       DD_SCHED_COOP = 32 };
+       DD_SCHED_COOP = 32, DD_SCHED_COOP_ABORT = 64 };
 
 /* Select a schedule (a combination of DD_SCHED_* flags). DD_EINVAL otherwise. */
 dd_status dd_set_schedule(dd_ctx *ctx, int sched);

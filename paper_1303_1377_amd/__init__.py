@@ -23,6 +23,8 @@ KERNEL_CLASSES = ["dirac64", "dirac_prec", "sap", "restrict", "prolong", "coarse
                   "coarse_step"]
 OPS = dict(D=0, D_PREC=1, SAP=2, VCYCLE=3, RESTRICT=4, PROLONG=5, COARSE_SOLVE=6, SCHUR=7, FGMRES=8, BICGSTAB=9,
            DEFLATED=10)
+# DD_SCHED_* flags of include/ddamg.h
+SCHED = dict(FUSED=1, XCD=2, LDS=4, NO_MFMA=8, GRAPH=16, COOP=32, COOP_ABORT=64)
 STATUS = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_ENOCONV", -4: "DD_EDEVICE", -5: "DD_ESTATE",
           -6: "DD_ENUMERIC"}
 

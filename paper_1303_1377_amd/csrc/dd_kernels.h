@@ -19,6 +19,7 @@ enum FineSched {
     SCHED_NO_MFMA = 8, // multi-RHS coarse stencil on the vector units instead of the matrix cores
     SCHED_GRAPH = 16,  // coarsest-level Arnoldi steps replayed as captured HIP graphs
     SCHED_COOP = 32,   // coarsest-level GMRES cycle as one persistent cooperative launch
+    SCHED_COOP_ABORT = 64,  // test of the fallback: the cooperative cycle starts with its abort flag raised
 };
 // Fields are stored in S (T, or _Float16 for the FP16-storage preconditioner)
 // and computed on in T.

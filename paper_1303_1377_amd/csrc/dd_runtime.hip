@@ -948,6 +948,9 @@ void Hier<T>::gmres_oe(int l, const cx<T>* r, cx<T>* e, const Batch& bt) {
         if (coop_grid > 0) {
             unsigned* bar = reinterpret_cast<unsigned*>(C->dflags + DI_BAR);
             HIPX(hipMemsetAsync(C->dflags + DI_BAR, 0, 3 * sizeof(int), C->s));
+            // test of the fallback below: with the abort flag already raised the
+            // first grid barrier gives up and every workgroup leaves
+            if (C->sched & SCHED_COOP_ABORT) HIPX(hipMemsetD32Async((hipDeviceptr_t)(C->dflags + DI_BAR + 2), 1, 1, C->s));
             hipError_t herr = hipSuccess;
             {
                 Prof pr(C, DD_K_COARSE_STEP, 0.0);
@@ -2756,6 +2759,9 @@ static void set_sched(dd_ctx* C, int sched) {
     };
     if (C->H64) drop(*C->H64);
     if (C->H32) drop(*C->H32);
+    // a new schedule tries the cooperative cycle again
+    if (C->H64) C->H64->coop_off = false;
+    if (C->H32) C->H32->coop_off = false;
     const int mf = (sched & SCHED_NO_MFMA) ? 0 : 1;
     if (C->H64) {
         C->H64->op0.sched = sched;
@@ -2769,7 +2775,8 @@ static void set_sched(dd_ctx* C, int sched) {
 
 dd_status dd_set_schedule(dd_ctx* ctx, int sched) {
     ABI_TRY(ctx)
-    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP))
+    if (sched < 0 || sched > (SCHED_FUSED | SCHED_XCD | SCHED_LDS | SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP |
+                              SCHED_COOP_ABORT))
         fail(DD_EINVAL, "unknown schedule flags");
     set_sched(ctx, sched);
     return DD_OK;

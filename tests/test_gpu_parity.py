@@ -696,6 +696,34 @@ def test_cooperative_coarse_gmres_matches_step_launches(precision):
     assert rel(to_np(Ec), to_np(Es)) < (1e-9 if precision == 64 else 1e-4)
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_cooperative_fallback_when_a_barrier_gives_up(precision):
+    """The cooperative cycle's fallback, forced from the host: with its abort
+    flag raised before the launch (DD_SCHED_COOP_ABORT) the first grid barrier
+    gives up, every workgroup leaves, and the coarse solve reruns with step
+    launches, bit for bit the result of a schedule without the cooperative
+    cycle.  The context keeps working afterwards."""
+    say("case: cooperative fallback precision", precision)
+    import paper_1303_1377_amd as G
+
+    k = 3
+    p, V = _built_batch(precision, k)
+    base = p.g.get_schedule() & ~(G.SCHED["COOP"] | G.SCHED["COOP_ABORT"])
+    p.g.set_schedule(base | G.SCHED["COOP"] | G.SCHED["COOP_ABORT"])
+    Ea, ita = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    ea, ja = p.g.apply("COARSE_SOLVE", 1, V[0])
+    p.g.set_schedule(base)
+    Es, its = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    es, js = p.g.apply("COARSE_SOLVE", 1, V[0])
+    say("aborted-coop its", ita, ja, "step its", its, js)
+    assert ita == its and ja == js
+    assert np.array_equal(to_np(Ea), to_np(Es)) and np.array_equal(to_np(ea), to_np(es))
+    # the cooperative cycle runs again under a schedule without the abort flag
+    p.g.set_schedule(base | G.SCHED["COOP"])
+    Ec, itc = p.g.apply_batch("COARSE_SOLVE", 1, V)
+    assert itc == its and rel(to_np(Ec), to_np(Es)) < (1e-11 if precision == 64 else 1e-5)
+
+
 def test_coarse_autotuner_keeps_results():
     """dd_autotune_coarse picks a coarse-solver form; solves before and after agree to rounding."""
     say("case: coarse autotuner")
