@@ -1764,15 +1764,51 @@ __global__ void k_coarse_restrict(AggMap m, int ndf, int N, const cx<S>* __restr
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
     const long volf = 2L * m.f.vh;
     const int h0 = ndf / 2;
+    const int ne = m.asz * ndf;
+    // up to EPT entries per thread: their offsets, halves and input values are
+    // found once for all N test vectors (the same sums in the same order)
+    constexpr int EPT = 4;
+    const bool held = ne <= EPT * (int)blockDim.x;
+    size_t off[EPT];
+    cx<T> vin[EPT];
+    bool hi[EPT];
+    if (held) {
+#pragma unroll
+        for (int u = 0; u < EPT; u++) {
+            const int e = t + u * (int)blockDim.x;
+            off[u] = 0;
+            vin[u] = czero<T>();
+            hi[u] = false;
+            if (e < ne) {
+                const int s = e / ndf, d = e % ndf;
+                int x[4];
+                agg_site_c(m, xc, s, x);
+                off[u] = lay_global(m.f, x) * ndf + d;
+                vin[u] = in[off[u]];
+                hi[u] = d >= h0;
+            }
+        }
+    }
     cx<double> acc[2];
     for (int k = 0; k < N; k++) {
         acc[0] = acc[1] = czero<double>();
-        for (int e = t; e < m.asz * ndf; e += blockDim.x) {
-            int s = e / ndf, d = e % ndf;
-            int x[4];
-            agg_site_c(m, xc, s, x);
-            size_t gf = lay_global(m.f, x);
-            acc[d / h0] += ccast<double>(cmulc(ccast<T>(P[((size_t)k * volf + gf) * ndf + d]), in[gf * ndf + d]));
+        if (held) {
+            const cx<S>* Pk = P + (size_t)k * volf * ndf;
+#pragma unroll
+            for (int u = 0; u < EPT; u++) {
+                if (t + u * (int)blockDim.x >= ne) break;
+                const cx<double> pr = ccast<double>(cmulc(ccast<T>(Pk[off[u]]), vin[u]));
+                if (hi[u]) acc[1] += pr;
+                else acc[0] += pr;
+            }
+        } else {
+            for (int e = t; e < ne; e += blockDim.x) {
+                int s = e / ndf, d = e % ndf;
+                int x[4];
+                agg_site_c(m, xc, s, x);
+                size_t gf = lay_global(m.f, x);
+                acc[d / h0] += ccast<double>(cmulc(ccast<T>(P[((size_t)k * volf + gf) * ndf + d]), in[gf * ndf + d]));
+            }
         }
         for (int h = 0; h < 2; h++) {
             acc[h].re = wave_sum(acc[h].re);
