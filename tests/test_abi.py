@@ -43,3 +43,26 @@ def test_package_import_does_not_need_the_device():
     import paper_1303_1377_amd as G
 
     assert callable(G.Solver)
+
+
+def _enum_values(prefix):
+    src = open(os.path.join(ROOT, "include", "ddamg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b%s([A-Z0-9_]+)\s*=\s*(\d+)" % prefix, src)}
+
+
+def test_binding_constants_match_the_header():
+    """The binding passes operators, kernel classes and schedule flags as
+    plain integers: its tables must hold the header's values."""
+    import paper_1303_1377_amd as G
+
+    ops = _enum_values("DD_OP_")
+    assert ops == G.OPS
+    sched = _enum_values("DD_SCHED_")
+    assert sched == G.SCHED
+    kcls = _enum_values("DD_K_")
+    n = kcls.pop("NCLASS")
+    assert n == len(G.KERNEL_CLASSES)
+    assert sorted(kcls.values()) == list(range(n))
+    for name, v in kcls.items():
+        assert G.KERNEL_CLASSES[v] == name.lower(), (name, v)
