@@ -1053,6 +1053,13 @@ struct KrylovResult {
     bool conv[MAX_RHS];
 };
 
+// Ops with prec_copy(w) take the next preconditioner input as an FP32 copy
+// that the last Gram-Schmidt pass writes while it leaves w final
+template <class Ops, class = void>
+struct HasPrecCopy : std::false_type {};
+template <class Ops>
+struct HasPrecCopy<Ops, std::void_t<decltype(std::declval<Ops&>().prec_copy((const void*)nullptr))>> : std::true_type {};
+
 // Ops supplies, for a batch: precond(j, V_j, Z_j, batch), matvec(Z_j -> w),
 // residual(x -> V_0 := r - A x over the batch) and the vector sets.
 //
@@ -1061,13 +1068,6 @@ struct KrylovResult {
 // when its estimate reaches tol[r] * bnorm[r], at maxit or at `fixed`
 // iterations), x += Z y, then the true residual replaces V_0 and beta[r].
 // its[r] counts the iterations of RHS r over all cycles.
-// Ops with prec_copy(w) take the next preconditioner input as an FP32 copy
-// that the last Gram-Schmidt pass writes while it leaves w final
-template <class Ops, class = void>
-struct HasPrecCopy : std::false_type {};
-template <class Ops>
-struct HasPrecCopy<Ops, std::void_t<decltype(std::declval<Ops&>().prec_copy((const void*)nullptr))>> : std::true_type {};
-
 template <class VS, class ZS, class Ops>
 static void fgmres_cycle(dd_ctx* C, Ops& ops, long n, long ldv, int m, const double* tol, int maxit, long fixed,
                          const Batch& in, int word, unsigned cyc, std::vector<Hess>& hs, double* beta,
