@@ -2795,9 +2795,10 @@ dd_status dd_autotune(dd_ctx* ctx, int reps, int* chosen, double* times_ms) {
     const int keep = ctx->sched & (SCHED_NO_MFMA | SCHED_GRAPH | SCHED_COOP);
     double best = 0;
     int pick = ctx->sched;
-    // the outer stencil is timed at the batch width of the solves (the
-    // XCD-ordered schedules let the workgroups of one block's RHS share L2)
-    const int nr = ctx->configured ? std::max(ctx->R, 1) : 1;
+    // the outer stencil is timed at the batch width of the solves, up to four
+    // (the XCD-ordered schedules let the workgroups of one block's RHS share
+    // L2; four show it, and the two temporary vector sets stay small)
+    const int nr = ctx->configured ? std::min(std::max(ctx->R, 1), 4) : 1;
     for (int sc = 0; sc < nsched; sc++) {
         set_sched(ctx, sc | keep);
         double ms = time_dirac64(ctx, DD_K_DIRAC64, nr, reps) / nr, t = 0;
